@@ -1,0 +1,302 @@
+// knn_oracle.cpp -- CPU oracle for the grid KNN self-join.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the tests, the package's smoke() entry and
+// the CPU-baseline leg of the benchmark may load this library.  It shares no
+// code, header, table or constant with the HIP path and must never be used as
+// a fallback for it.
+//
+// Everything here is written to be checked against the paper by eye: plain
+// loops, fp64, no contraction (built with -ffp-contract=off, no fast-math),
+// and a library sort where the definition says "sort".
+//
+// Paper: Gowanlock, "Hybrid CPU/GPU KNN self-join" (arXiv:1810.04758).
+//   * Problem statement (Sec. 2.1): for every point of D find its K nearest
+//     neighbours, excluding the point itself, under the Euclidean distance
+//     sqrt(sum_j (x^a_j - x^b_j)^2).
+//   * Grid index (Sec. 3.1): uniform grid with cells of side eps, only
+//     non-empty cells stored, a query scans its own cell and the 3^n - 1
+//     adjacent cells.
+//   * Search-distance selection (Sec. 4.4): eps_mean from a 0.1 % sample,
+//     a distance histogram of n_bins bins of width eps_mean / n_bins built from
+//     sample points against all of D, eps_min = midpoint of the first bin whose
+//     cumulative count reaches K.
+//
+// Readings where the paper is silent (each is listed in the design notes):
+//   * ties between equal squared distances go to the lower point id;
+//   * the squared distance is summed left to right over dimensions 0..n-1 with
+//     every subtraction, product and sum rounded (no fused multiply-add), and
+//     the reported distance is the correctly rounded sqrt of it;
+//   * the point itself is excluded by id; a duplicate of it at distance 0 is a
+//     neighbour like any other;
+//   * the grid key is row-major over the per-dimension cell coordinates with the
+//     last dimension varying fastest (the paper defers the layout to its prior
+//     work);
+//   * eps_mean is the mean over unordered pairs inside the sample; the
+//     cumulative histogram count is compared with K per sample point
+//     (count >= K * n_sample); self pairs are skipped.
+//
+// Parity pins (see tests/test_oracle_*.py): brute force in exact rational
+// arithmetic on tiny dyadic inputs, the paper's figure examples, integer
+// lattice closed forms, invariants and metamorphic relations.  The eps_min
+// selection rule is pinned by a hand-built histogram; the statistical quality
+// of eps_min itself is "parity unpinned".
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <map>
+#include <utility>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// Squared Euclidean distance of Sec. 2.1, dimensions summed left to right.
+double sq_dist(const double* a, const double* b, int n) {
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double t = a[j] - b[j];
+    double t2 = t * t;
+    s = s + t2;
+  }
+  return s;
+}
+
+// Cell coordinate of one coordinate value: floor((x - lo) * inv_w).
+int64_t cell_coord(double x, double lo, double inv_w) {
+  double u = (x - lo) * inv_w;
+  return (int64_t)std::floor(u);
+}
+
+}  // namespace
+
+extern "C" {
+
+// ---------------------------------------------------------------------------
+// KNN self-join by the definition of Sec. 2.1.
+// D: row-major N x n.  rows: the query rows to answer (NULL = all N rows, in
+// order).  For output row r (query i = rows[r]) the K pairs (d^2(i,j), j) with
+// j != i that come first in lexicographic order are written to
+// out_ids[r*K + k] and out_dists[r*K + k] = sqrt(d^2).
+// Returns 0, or -1 on invalid arguments.
+// ---------------------------------------------------------------------------
+int oracle_knn(const double* D, int64_t N, int32_t n, int32_t K,
+               const int64_t* rows, int64_t nrows, int32_t* out_ids,
+               double* out_dists, int32_t nthreads) {
+  if (!D || !out_ids || !out_dists || n < 1 || K < 1 || K > N - 1) return -1;
+  if (!rows) nrows = N;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  int bad = 0;
+#pragma omp parallel
+  {
+    std::vector<std::pair<double, int64_t>> cand;
+    cand.reserve((size_t)(N - 1));
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; ++r) {
+      int64_t i = rows ? rows[r] : r;
+      if (i < 0 || i >= N) {
+        bad = 1;
+        continue;
+      }
+      cand.clear();
+      for (int64_t j = 0; j < N; ++j) {
+        if (j == i) continue;  // exclude the point itself (by id)
+        cand.push_back(std::make_pair(sq_dist(D + i * n, D + j * n, n), j));
+      }
+      // The K first pairs in (d^2, id) order; std::pair compares lexicographically.
+      std::partial_sort(cand.begin(), cand.begin() + K, cand.end());
+      for (int32_t k = 0; k < K; ++k) {
+        out_ids[r * K + k] = (int32_t)cand[k].second;
+        out_dists[r * K + k] = std::sqrt(cand[k].first);
+      }
+    }
+  }
+  return bad ? -1 : 0;
+}
+
+// Squared distance between rows a and b of D (exposed for the tests).
+double oracle_sq_dist(const double* D, int32_t n, int64_t a, int64_t b) {
+  return sq_dist(D + a * n, D + b * n, n);
+}
+
+// ---------------------------------------------------------------------------
+// Grid index of Sec. 3.1, by definition.
+// ---------------------------------------------------------------------------
+
+// Per-dimension minimum and maximum of D.
+void oracle_bounds(const double* D, int64_t N, int32_t n, double* lo, double* hi) {
+  for (int j = 0; j < n; ++j) {
+    lo[j] = D[j];
+    hi[j] = D[j];
+  }
+  for (int64_t i = 1; i < N; ++i)
+    for (int j = 0; j < n; ++j) {
+      double x = D[i * n + j];
+      if (x < lo[j]) lo[j] = x;
+      if (x > hi[j]) hi[j] = x;
+    }
+}
+
+// Number of cells per dimension: the cell coordinate of hi, plus one.
+void oracle_grid_dims(const double* lo, const double* hi, int32_t n, double inv_w,
+                      int64_t* g) {
+  for (int j = 0; j < n; ++j) g[j] = cell_coord(hi[j], lo[j], inv_w) + 1;
+}
+
+// Cell key of every point: row-major over the cell coordinates, last
+// dimension fastest.
+void oracle_cell_keys(const double* D, int64_t N, int32_t n, const double* lo,
+                      double inv_w, const int64_t* g, uint64_t* keys) {
+  for (int64_t i = 0; i < N; ++i) {
+    uint64_t key = 0;
+    for (int j = 0; j < n; ++j) {
+      uint64_t c = (uint64_t)cell_coord(D[i * n + j], lo[j], inv_w);
+      key = key * (uint64_t)g[j] + c;
+    }
+    keys[i] = key;
+  }
+}
+
+// Points ordered by cell key, stable in the point id (std::stable_sort), and
+// the table of non-empty cells: cell_keys[c], cell_start[c] (cell_start[M] =
+// N).  Returns M.  Arrays must hold N entries (cell_start N + 1).
+int64_t oracle_grid_build(const uint64_t* keys, int64_t N, uint64_t* sorted_keys,
+                          int32_t* perm, uint64_t* cell_keys, int64_t* cell_start) {
+  std::vector<int64_t> order((size_t)N);
+  for (int64_t i = 0; i < N; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return keys[a] < keys[b]; });
+  int64_t M = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    perm[i] = (int32_t)order[i];
+    sorted_keys[i] = keys[order[i]];
+    if (i == 0 || sorted_keys[i] != sorted_keys[i - 1]) {
+      cell_keys[M] = sorted_keys[i];
+      cell_start[M] = i;
+      ++M;
+    }
+  }
+  cell_start[M] = N;
+  return M;
+}
+
+// For every non-empty cell c, the points of the 3^n adjacent cells grouped into
+// 3^(n-1) row segments: for each offset (o_0..o_{n-2}) in {-1,0,1}^(n-1),
+// enumerated with o_0 varying slowest, the cells whose first n-1 coordinates
+// equal c's plus the offset and whose last coordinate is within one of c's.
+// Because the key is row-major with the last dimension fastest, the points of
+// one segment are contiguous in key order.  The segment is written as the
+// half-open range [start, end) of sorted positions; an empty segment is (0, 0).
+// ranges: M * 3^(n-1) * 2 entries.
+void oracle_neighbor_ranges(const uint64_t* cell_keys, const int64_t* cell_start,
+                            int64_t M, int32_t n, const int64_t* g, int64_t* ranges) {
+  std::map<uint64_t, int64_t> where;  // key -> cell index
+  for (int64_t c = 0; c < M; ++c) where[cell_keys[c]] = c;
+  int64_t R = 1;
+  for (int j = 0; j < n - 1; ++j) R *= 3;
+  std::vector<int64_t> coord((size_t)n), nb((size_t)n);
+  for (int64_t c = 0; c < M; ++c) {
+    // decode coordinates of cell c from its key
+    uint64_t k = cell_keys[c];
+    for (int j = n - 1; j >= 0; --j) {
+      coord[j] = (int64_t)(k % (uint64_t)g[j]);
+      k /= (uint64_t)g[j];
+    }
+    for (int64_t r = 0; r < R; ++r) {
+      // offset digits, o_0 slowest
+      int64_t rr = r;
+      bool inside = true;
+      for (int j = n - 2; j >= 0; --j) {
+        int64_t o = rr % 3 - 1;
+        rr /= 3;
+        nb[j] = coord[j] + o;
+        if (nb[j] < 0 || nb[j] >= g[j]) inside = false;
+      }
+      int64_t start = 0, end = 0;
+      bool any = false;
+      if (inside) {
+        for (int64_t o = -1; o <= 1; ++o) {
+          nb[n - 1] = coord[n - 1] + o;
+          if (nb[n - 1] < 0 || nb[n - 1] >= g[n - 1]) continue;
+          uint64_t key = 0;
+          for (int j = 0; j < n; ++j) key = key * (uint64_t)g[j] + (uint64_t)nb[j];
+          auto it = where.find(key);
+          if (it == where.end()) continue;
+          int64_t s = cell_start[it->second], e = cell_start[it->second + 1];
+          if (!any) {
+            start = s;
+            end = e;
+            any = true;
+          } else {
+            if (s < start) start = s;
+            if (e > end) end = e;
+          }
+        }
+      }
+      ranges[(c * R + r) * 2 + 0] = any ? start : 0;
+      ranges[(c * R + r) * 2 + 1] = any ? end : 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Search-distance selection of Sec. 4.4.
+// ---------------------------------------------------------------------------
+
+// eps_mean: mean Euclidean distance over the unordered pairs (a < b) of the
+// sample points.
+double oracle_sample_mean_dist(const double* D, int32_t n, const int64_t* sample,
+                               int64_t ns) {
+  double sum = 0.0;
+  int64_t pairs = 0;
+  for (int64_t a = 0; a < ns; ++a)
+    for (int64_t b = a + 1; b < ns; ++b) {
+      sum += std::sqrt(sq_dist(D + sample[a] * n, D + sample[b] * n, n));
+      ++pairs;
+    }
+  return pairs ? sum / (double)pairs : 0.0;
+}
+
+// Distance histogram: every sample point against every other point of D.
+// A distance d falls into bin floor(d * inv_bin_width); distances whose bin
+// is >= n_bins (beyond eps_mean) are not stored.
+void oracle_dist_histogram(const double* D, int64_t N, int32_t n, const int64_t* sample,
+                           int64_t ns, double inv_bin_width, int32_t n_bins,
+                           uint64_t* counts) {
+  for (int32_t b = 0; b < n_bins; ++b) counts[b] = 0;
+  for (int64_t a = 0; a < ns; ++a) {
+    int64_t s = sample[a];
+    for (int64_t j = 0; j < N; ++j) {
+      if (j == s) continue;
+      double d = std::sqrt(sq_dist(D + s * n, D + j * n, n));
+      double t = std::floor(d * inv_bin_width);
+      if (t < (double)n_bins) counts[(int64_t)t] += 1;
+    }
+  }
+}
+
+// eps_min: midpoint of the first bin d whose cumulative count reaches K per
+// sample point (B^c_{d-1} < K <= B^c_d, with counts summed over ns sample
+// points).  If no bin reaches it, the end of the last bin (eps_mean).
+double oracle_eps_min(const uint64_t* counts, int32_t n_bins, double bin_width, int64_t ns,
+                      int32_t K) {
+  uint64_t need = (uint64_t)K * (uint64_t)ns;
+  uint64_t cum = 0;
+  for (int32_t d = 0; d < n_bins; ++d) {
+    cum += counts[d];
+    if (cum >= need) {
+      double start = (double)d * bin_width;
+      double end = (double)(d + 1) * bin_width;
+      return (start + end) / 2.0;
+    }
+  }
+  return (double)n_bins * bin_width;
+}
+
+}  // extern "C"
