@@ -1,0 +1,265 @@
+/*
+ * knnjoin.h -- C ABI of libknnjoin.so, an exact grid-indexed K-nearest-
+ * neighbour self-join for one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gowanlock, "Hybrid CPU/GPU KNN self-join" (arXiv:1810.04758),
+ * GPU component only (HYBRID-GPU / GPU-Only configuration, Sec. 4.2, Alg. 1):
+ *   - points are binned into a uniform grid whose cell side is the search
+ *     distance eps (Sec. 3.1; built on the GPU, Sec. 4.6);
+ *   - each query scans its own cell and the 3^n - 1 adjacent cells, computes
+ *     the distances and keeps its K nearest (Alg. 1, GPUJoinKernel);
+ *   - queries that cannot prove their K nearest inside the scanned cells fail
+ *     and are re-run on a grid with a larger eps (Alg. 1, re-index rule;
+ *     Sec. 4.5);
+ *   - eps starts from eps_min, chosen by sampling (Sec. 4.4);
+ *   - queries are processed dense-first (work estimate of Sec. 4.5).
+ *
+ * Result (problem statement, Sec. 2.1): for every point i of D, the K points
+ * j != i with the smallest Euclidean distance.  Ties in the squared distance
+ * go to the lower point id (the paper is silent; this library's reading).
+ * Row i of the output lists them nearest first.  Distances are
+ * sqrt(sum_j (x_j - y_j)^2), the sum taken left to right over the
+ * dimensions with every operation rounded (no fused multiply-add), and the
+ * square root correctly rounded, so results are reproducible bit for bit.
+ *
+ * Conventions
+ *   - Every function returns KNN_OK (0) or a negative KNN_E* code and never
+ *     lets a C++ exception escape.  knn_last_error() returns a description of
+ *     the last failure on the calling thread.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the index's device.  Streams are hipStream_t passed as
+ *     void* (NULL = the legacy default stream).
+ *   - Point coordinates are fp64, row-major N x dims (point i occupies
+ *     D[i*dims .. i*dims+dims-1]).  2 <= dims <= 6 (the paper's range, Sec.
+ *     2.3), 2 <= N < 2^31, every coordinate finite.
+ *   - Output arrays are row-major N x K: ids int32, dists fp64.
+ */
+#ifndef KNNJOIN_H
+#define KNNJOIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KNN_OK 0
+#define KNN_EINVAL (-1)    /* invalid argument */
+#define KNN_ENOMEM (-2)    /* device or host allocation failed */
+#define KNN_EDEVICE (-3)   /* HIP runtime or kernel error */
+#define KNN_EBUSY (-4)     /* object in use / queue full */
+#define KNN_ETIMEOUT (-5)  /* wait timed out */
+#define KNN_EINTERNAL (-6) /* internal invariant violated (a bug) */
+
+#define KNN_MIN_DIMS 2
+#define KNN_MAX_DIMS 6
+#define KNN_MAX_K 1024 /* largest K the search kernel's per-query buffers hold */
+
+typedef struct knn_index knn_index;
+
+/* Options of knn_build_index*.  Zero fields take the defaults in brackets. */
+typedef struct knn_build_opts {
+  uint64_t seed;        /* seed of the sampling generator (SplitMix64) [1] */
+  int32_t n_sample;     /* sample points of the distance histogram [500], Sec. 4.4 */
+  int32_t n_bins;       /* histogram bins up to eps_mean [1000], Sec. 4.4 */
+  double mean_frac;     /* fraction of D sampled for eps_mean [0.001], Sec. 4.4 */
+  int32_t min_mean_sample; /* lower bound of the eps_mean sample size [64] */
+  int32_t device;       /* HIP device ordinal; < 0 = current device [-1] */
+} knn_build_opts;
+
+/* Per-join statistics (optional output of the join calls). */
+#define KNN_MAX_LEVELS 64
+typedef struct knn_join_stats {
+  int32_t levels;             /* grid levels searched (1 + re-indexes) */
+  double eps_min;             /* eps_min(K) from the histogram */
+  double cell_width[KNN_MAX_LEVELS];   /* cell side of each level */
+  int64_t attempted[KNN_MAX_LEVELS];   /* queries searched at each level */
+  int64_t failed[KNN_MAX_LEVELS];      /* of which failed (re-queued) */
+  int64_t cells[KNN_MAX_LEVELS];       /* non-empty cells of each level */
+  double ms_build[KNN_MAX_LEVELS];     /* index construction time per level */
+  double ms_search[KNN_MAX_LEVELS];    /* search kernel time per level */
+  double ms_total;            /* wall time of the whole join */
+  int64_t total_attempted;    /* sum of attempted */
+  int64_t total_failed;       /* sum of failed: fraction = failed/attempted */
+  int32_t lanes_per_query;    /* t used */
+} knn_join_stats;
+
+/* Options of the join calls.  Zero fields take the defaults in brackets. */
+typedef struct knn_join_opts {
+  double w_factor;        /* level-0 cell side = w_factor * eps_min(K) [autotuned or 1] */
+  double cell_width;      /* > 0: explicit level-0 cell side, overrides w_factor */
+  int32_t lanes_per_query;/* t, threads per query: 1,2,4,...,64 [autotuned] (Sec. 4.7) */
+  int32_t schedule;       /* 0 persistent kernel + device work queue, density ordered;
+                             1 one launch per batch, cell order [0] */
+  int32_t batch_queries;  /* schedule 1: queries per launch, 0 = all [0] */
+  double eps_step;        /* linear growth step, multiple of eps_min [0.5] (Alg. 1) */
+  int32_t linear_levels;  /* linear growths before geometric growth [2] */
+  double growth;          /* geometric growth factor of the cell side [2.0] */
+  int32_t use_graph;      /* capture the per-level launch sequence in a HIP graph [0] */
+  knn_join_stats* stats;  /* optional statistics output */
+} knn_join_opts;
+
+/* Fills *o with the defaults (all zero).  Always succeeds. */
+void knn_build_opts_default(knn_build_opts* o);
+void knn_join_opts_default(knn_join_opts* o);
+
+/*
+ * Builds the index of D: copies D to the device, computes per-dimension
+ * bounds, and runs the search-distance sampling of Sec. 4.4 (eps_mean and
+ * the cumulative distance histogram, which does not depend on K, so
+ * eps_min(K) becomes a lookup at join time).  Grid levels are built by the
+ * join, since their cell side depends on K.
+ *   D        host, N x dims fp64, read only; copied, the caller may free it on
+ *            return.
+ *   opts     may be NULL.
+ *   out      receives the index; owned by the caller, free with
+ *            knn_destroy_index.
+ * Errors: KNN_EINVAL (dims outside [2,6], N < 2 or N >= 2^31, a non-finite
+ * coordinate, NULL pointers), KNN_ENOMEM, KNN_EDEVICE.
+ */
+int knn_build_index(const double* D, int64_t n_points, int32_t dims,
+                    const knn_build_opts* opts, knn_index** out);
+
+/* As knn_build_index, with D already in device memory (N x dims fp64,
+ * row-major).  D is copied on `stream`; it must stay valid until the call
+ * returns (the call synchronises the stream). */
+int knn_build_index_device(const double* d_D, int64_t n_points, int32_t dims,
+                           const knn_build_opts* opts, void* stream,
+                           knn_index** out);
+
+/*
+ * KNN self-join D join_KNN D (Sec. 2.1) into host arrays.
+ *   ids, dists  host, N x K each, written completely on success; contents
+ *               unspecified on error.
+ *   K           1 <= K <= min(N-1, KNN_MAX_K).
+ *   opts        may be NULL.
+ * Blocks until done.  One join per index at a time: a concurrent call on the
+ * same index returns KNN_EBUSY.
+ */
+int knn_self_join(knn_index* idx, int32_t K, int32_t* ids, double* dists,
+                  const knn_join_opts* opts);
+
+/*
+ * As knn_self_join, with d_ids / d_dists in device memory (N x K each).
+ * Work is issued on `stream`; the call returns after the last level's
+ * failure count has been read back (the level loop needs it on the host), at
+ * which point the results are complete in device memory.
+ */
+int knn_self_join_device(knn_index* idx, int32_t K, int32_t* d_ids, double* d_dists,
+                         const knn_join_opts* opts, void* stream);
+
+/* Frees the index and its device memory.  NULL is a no-op. */
+void knn_destroy_index(knn_index* idx);
+
+/* Thread-local message of the last error ("" if none). */
+const char* knn_last_error(void);
+
+/* Basic facts about an index. */
+typedef struct knn_index_info {
+  int64_t n_points;
+  int32_t dims;
+  int32_t device;
+  double lo[KNN_MAX_DIMS];
+  double hi[KNN_MAX_DIMS];
+  double eps_mean;        /* Sec. 4.4 */
+  int32_t n_bins;
+  int32_t n_sample;
+  int64_t device_bytes;   /* device memory held by the index right now */
+} knn_index_info;
+int knn_index_info_get(const knn_index* idx, knn_index_info* out);
+
+/* eps_min(K) of Sec. 4.4 from the index's cumulative distance histogram:
+ * the midpoint of the first bin whose cumulative count reaches K per sample
+ * point, or eps_mean if none does. */
+int knn_eps_min(const knn_index* idx, int32_t K, double* eps_min);
+
+/*
+ * Builds the grid level of cell side `cell_width` (Sec. 3.1) and copies it
+ * to host arrays, for inspection and testing.  Any output pointer may be
+ * NULL.  Sizes: sorted_keys, perm: N; cell_keys: N (first *n_cells used);
+ * cell_start: N+1 (first *n_cells+1 used); ranges: N * 3^(dims-1) * 2 (first
+ * *n_cells * 3^(dims-1) * 2 used); grid_dims: dims.
+ * Layout: the key of a point is row-major over its cell coordinates
+ * floor((x_j - lo_j) * inv_w), inv_w = 1/cell_width, last dimension fastest;
+ * points are sorted by key, stably in their id; perm[p] is the id of the
+ * point at sorted position p; cell c holds sorted positions
+ * [cell_start[c], cell_start[c+1]); ranges[(c*R + r)*2 + {0,1}] is the
+ * half-open sorted range of row segment r (offsets o_0..o_{n-2} in
+ * {-1,0,1}, o_0 slowest, last coordinate within one of c's), (0,0) if empty.
+ */
+int knn_grid_export(knn_index* idx, double cell_width, uint64_t* sorted_keys,
+                    int32_t* perm, uint64_t* cell_keys, uint32_t* cell_start,
+                    uint32_t* ranges, int64_t* grid_dims, int64_t* n_cells);
+
+/*
+ * The two sampling kernels of Sec. 4.4 on caller-chosen samples, device
+ * memory throughout (used by the index build; exposed for testing).
+ *   d_D        device, N x dims fp64 row-major.
+ *   d_sample   device, ns int64 point ids (each in [0, N)).
+ * knn_sample_mean_dist: mean distance over the unordered pairs of the
+ *   sample; *mean is written to host memory (the call synchronises).
+ * knn_dist_histogram: counts, for every sample point s and every point
+ *   j != s, the distance d = sqrt(d^2(s,j)) into bin floor(d * inv_bin_width)
+ *   when that bin is < n_bins; d_counts (device, n_bins uint64) is
+ *   overwritten.  Asynchronous on `stream`.
+ */
+int knn_sample_mean_dist(const double* d_D, int64_t n_points, int32_t dims,
+                         const int64_t* d_sample, int64_t ns, double* mean,
+                         void* stream);
+int knn_dist_histogram(const double* d_D, int64_t n_points, int32_t dims,
+                       const int64_t* d_sample, int64_t ns, double inv_bin_width,
+                       int32_t n_bins, uint64_t* d_counts, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over indexes resident in device memory.
+ * Requests (dataset, K) are admitted while their device footprint fits the
+ * memory budget and fewer than max_inflight run; admitted requests run
+ * concurrently on their own streams, so work of requests that arrive while
+ * others run overlaps on the device.  Results are the same as a solo
+ * knn_self_join on the same index and K (bit for bit).
+ * ------------------------------------------------------------------------ */
+typedef struct knn_server knn_server;
+
+typedef struct knn_server_opts {
+  uint64_t mem_budget_bytes; /* device bytes for in-flight requests [8 GiB] */
+  int32_t max_inflight;      /* concurrent requests [4] */
+  int32_t max_queue;         /* pending requests before submit returns KNN_EBUSY [4096] */
+  int32_t device;            /* < 0 = current device */
+} knn_server_opts;
+
+typedef struct knn_server_stats {
+  int64_t submitted;
+  int64_t completed;
+  int64_t failed;
+  double p50_ms;           /* latency submit -> results in host memory */
+  double p99_ms;
+  double mean_ms;
+  double max_ms;
+  double queries_per_s;    /* completed queries (points) / busy wall time */
+  double requests_per_s;
+  uint64_t peak_bytes;     /* peak admitted footprint */
+  int32_t peak_inflight;
+} knn_server_stats;
+
+int knn_server_create(const knn_server_opts* opts, knn_server** out);
+/* Registers a built index (borrowed: it must outlive the server). */
+int knn_server_add_dataset(knn_server* srv, knn_index* idx, int32_t* dataset_id);
+/* Queues a self-join of dataset `dataset_id` with K neighbours into host
+ * arrays ids/dists (N x K, owned by the caller, untouched until completion).
+ * Returns KNN_EBUSY when the pending queue is full; a request that does not
+ * fit the free budget waits in the queue (it is not rejected).  A request
+ * whose footprint exceeds the whole budget is rejected with KNN_EINVAL. */
+int knn_server_submit(knn_server* srv, int32_t dataset_id, int32_t K, int32_t* ids,
+                      double* dists, int64_t* ticket);
+/* Waits for a ticket: KNN_OK when done, KNN_ETIMEOUT, or the request's own
+ * error code.  timeout_us < 0 waits forever. */
+int knn_server_wait(knn_server* srv, int64_t ticket, int64_t timeout_us);
+int knn_server_stats_get(knn_server* srv, knn_server_stats* out);
+/* Waits for all requests, then frees the server. NULL is a no-op. */
+void knn_server_destroy(knn_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KNNJOIN_H */

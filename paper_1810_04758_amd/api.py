@@ -1,0 +1,247 @@
+"""Python surface of the library (same names as the C ABI in include/knnjoin.h).
+
+PyTorch is used only for device memory and streams: device tensors are passed
+to the HIP library as raw pointers, and the library runs every step.
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (BuildOpts, IndexInfo, JoinOpts, JoinStats, ServerOpts, ServerStats,
+                   check, load)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _join_opts(w_factor=0.0, cell_width=0.0, lanes_per_query=0, schedule=0, batch_queries=0,
+               eps_step=0.0, linear_levels=0, growth=0.0, use_graph=0, stats=None):
+    o = JoinOpts()
+    load().knn_join_opts_default(ctypes.byref(o))
+    o.w_factor = w_factor
+    o.cell_width = cell_width
+    o.lanes_per_query = lanes_per_query
+    o.schedule = schedule
+    o.batch_queries = batch_queries
+    o.eps_step = eps_step
+    o.linear_levels = linear_levels
+    o.growth = growth
+    o.use_graph = use_graph
+    o.stats = ctypes.pointer(stats) if stats is not None else None
+    return o
+
+
+def _build_opts(seed=1, n_sample=0, n_bins=0, mean_frac=0.0, min_mean_sample=0, device=-1):
+    o = BuildOpts()
+    load().knn_build_opts_default(ctypes.byref(o))
+    o.seed = seed
+    o.n_sample = n_sample
+    o.n_bins = n_bins
+    o.mean_frac = mean_frac
+    o.min_mean_sample = min_mean_sample
+    o.device = device
+    return o
+
+
+class Index:
+    """A dataset resident in device memory (knn_index)."""
+
+    def __init__(self, handle, N, dims):
+        self._h = handle
+        self.N = N
+        self.dims = dims
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("index is closed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            load().knn_destroy_index(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        inf = IndexInfo()
+        check(load().knn_index_info_get(self.handle, ctypes.byref(inf)))
+        n = inf.dims
+        return dict(n_points=inf.n_points, dims=n, device=inf.device, lo=list(inf.lo[:n]),
+                    hi=list(inf.hi[:n]), eps_mean=inf.eps_mean, n_bins=inf.n_bins,
+                    n_sample=inf.n_sample, device_bytes=inf.device_bytes)
+
+    def eps_min(self, K):
+        v = ctypes.c_double()
+        check(load().knn_eps_min(self.handle, K, ctypes.byref(v)))
+        return v.value
+
+    def self_join(self, K, ids=None, dists=None, stream=None, with_stats=False, **opts):
+        """knn_self_join_device: returns (ids int32 [N,K], dists float64 [N,K]) on
+        the GPU (and the per-level statistics if with_stats)."""
+        torch = _torch()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if ids is None:
+            ids = torch.empty((self.N, K), dtype=torch.int32, device=dev)
+        if dists is None:
+            dists = torch.empty((self.N, K), dtype=torch.float64, device=dev)
+        if ids.shape != (self.N, K) or dists.shape != (self.N, K):
+            raise ValueError("output shape must be (N, K)")
+        if ids.dtype != torch.int32 or dists.dtype != torch.float64:
+            raise ValueError("outputs must be int32 / float64")
+        if not (ids.is_cuda and dists.is_cuda and ids.is_contiguous() and dists.is_contiguous()):
+            raise ValueError("outputs must be contiguous device tensors")
+        st = JoinStats() if with_stats else None
+        o = _join_opts(stats=st, **opts)
+        check(load().knn_self_join_device(self.handle, K, ctypes.c_void_p(ids.data_ptr()),
+                                          ctypes.c_void_p(dists.data_ptr()), ctypes.byref(o),
+                                          _stream_ptr(stream)))
+        if with_stats:
+            return ids, dists, st.as_dict()
+        return ids, dists
+
+    def self_join_host(self, K, with_stats=False, **opts):
+        """knn_self_join: results in host (numpy) arrays."""
+        ids = np.empty((self.N, K), dtype=np.int32)
+        dists = np.empty((self.N, K), dtype=np.float64)
+        st = JoinStats() if with_stats else None
+        o = _join_opts(stats=st, **opts)
+        check(load().knn_self_join(self.handle, K, ids.ctypes.data_as(ctypes.c_void_p),
+                                   dists.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o)))
+        if with_stats:
+            return ids, dists, st.as_dict()
+        return ids, dists
+
+    def grid_export(self, cell_width):
+        """knn_grid_export: the grid level of the given cell side, on the host."""
+        N, n = self.N, self.dims
+        R = 3 ** (n - 1)
+        sk = np.empty(N, dtype=np.uint64)
+        perm = np.empty(N, dtype=np.int32)
+        ck = np.empty(N, dtype=np.uint64)
+        cs = np.empty(N + 1, dtype=np.uint32)
+        rg = np.empty(N * R * 2, dtype=np.uint32)
+        gd = np.empty(n, dtype=np.int64)
+        M = ctypes.c_int64()
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        check(load().knn_grid_export(self.handle, cell_width, p(sk), p(perm), p(ck), p(cs),
+                                     p(rg), p(gd), ctypes.byref(M)))
+        M = M.value
+        return dict(sorted_keys=sk, perm=perm, cell_keys=ck[:M].copy(),
+                    cell_start=cs[:M + 1].astype(np.int64), g=gd,
+                    ranges=rg[:M * R * 2].reshape(M, R, 2).astype(np.int64))
+
+
+def build_index(D, seed=1, stream=None, **kw):
+    """knn_build_index / knn_build_index_device.  D: N x dims float64, either a
+    numpy array (host) or a CUDA tensor (device)."""
+    h = ctypes.c_void_p()
+    o = _build_opts(seed=seed, **kw)
+    try:
+        torch = _torch()
+        is_dev = isinstance(D, torch.Tensor) and D.is_cuda
+    except ImportError:
+        torch = None
+        is_dev = False
+    if is_dev:
+        if D.dtype != torch.float64 or D.dim() != 2 or not D.is_contiguous():
+            raise ValueError("D must be a contiguous float64 N x dims tensor")
+        N, n = D.shape
+        check(load().knn_build_index_device(ctypes.c_void_p(D.data_ptr()), N, n,
+                                            ctypes.byref(o), _stream_ptr(stream), ctypes.byref(h)))
+    else:
+        if torch is not None and isinstance(D, torch.Tensor):
+            D = D.numpy()
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        if D.ndim != 2:
+            raise ValueError("D must be N x dims")
+        N, n = D.shape
+        check(load().knn_build_index(D.ctypes.data_as(ctypes.c_void_p), N, n, ctypes.byref(o),
+                                     ctypes.byref(h)))
+    return Index(h, N, n)
+
+
+def sample_mean_dist(D, sample, stream=None):
+    """knn_sample_mean_dist on device tensors (D N x n float64, sample int64)."""
+    torch = _torch()
+    D = D.contiguous()
+    sample = sample.to(torch.int64).contiguous()
+    out = ctypes.c_double()
+    check(load().knn_sample_mean_dist(ctypes.c_void_p(D.data_ptr()), D.shape[0], D.shape[1],
+                                      ctypes.c_void_p(sample.data_ptr()), sample.numel(),
+                                      ctypes.byref(out), _stream_ptr(stream)))
+    return out.value
+
+
+def dist_histogram(D, sample, inv_bin_width, n_bins, stream=None):
+    """knn_dist_histogram on device tensors; returns a uint64 counts tensor."""
+    torch = _torch()
+    D = D.contiguous()
+    sample = sample.to(torch.int64).contiguous()
+    counts = torch.empty(n_bins, dtype=torch.int64, device=D.device)  # uint64 bits
+    check(load().knn_dist_histogram(ctypes.c_void_p(D.data_ptr()), D.shape[0], D.shape[1],
+                                    ctypes.c_void_p(sample.data_ptr()), sample.numel(),
+                                    inv_bin_width, n_bins, ctypes.c_void_p(counts.data_ptr()),
+                                    _stream_ptr(stream)))
+    return counts
+
+
+class Server:
+    """knn_server_*: continuous-batching request loop over resident indexes."""
+
+    def __init__(self, mem_budget_bytes=0, max_inflight=0, max_queue=0, device=-1):
+        o = ServerOpts(mem_budget_bytes, max_inflight, max_queue, device)
+        h = ctypes.c_void_p()
+        check(load().knn_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def add_dataset(self, index):
+        ds = ctypes.c_int32()
+        check(load().knn_server_add_dataset(self._h, index.handle, ctypes.byref(ds)))
+        return ds.value
+
+    def submit(self, dataset, K, N):
+        ids = np.empty((N, K), dtype=np.int32)
+        dists = np.empty((N, K), dtype=np.float64)
+        t = ctypes.c_int64()
+        check(load().knn_server_submit(self._h, dataset, K, ids.ctypes.data_as(ctypes.c_void_p),
+                                       dists.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t)))
+        self._keep[t.value] = (ids, dists)
+        return t.value
+
+    def wait(self, ticket, timeout_us=-1):
+        check(load().knn_server_wait(self._h, ticket, timeout_us))
+        return self._keep.pop(ticket)
+
+    def stats(self):
+        s = ServerStats()
+        check(load().knn_server_stats_get(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h is not None:
+            load().knn_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,78 @@
+// common.hpp -- shared definitions of the HIP implementation of knnjoin.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/knnjoin.h"
+
+namespace knn {
+
+// Error carrying a KNN_E* code; converted to a return code at the ABI edge.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define KNN_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      int code_ = (e_ == hipErrorOutOfMemory) ? KNN_ENOMEM : KNN_EDEVICE;      \
+      throw ::knn::Error(code_, std::string(#call) + ": " + hipGetErrorString(e_) + \
+                                    " (" + __FILE__ + ":" + std::to_string(__LINE__) + ")"); \
+    }                                                                          \
+  } while (0)
+
+#define KNN_CHECK(cond, code, msg)                                             \
+  do {                                                                         \
+    if (!(cond)) throw ::knn::Error((code), (msg));                            \
+  } while (0)
+
+// Launch-error check after a kernel launch.
+#define KNN_LAUNCHED() KNN_HIP(hipGetLastError())
+
+constexpr int kWave = 64;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Device buffer owned by RAII.
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    KNN_HIP(hipMalloc(&p, count * sizeof(T)));
+    n = count;
+  }
+  // Grow to at least `count` elements (contents not preserved).
+  void reserve(size_t count) {
+    if (count > n || p == nullptr) alloc(count);
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+}  // namespace knn

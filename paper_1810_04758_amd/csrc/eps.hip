@@ -1,0 +1,117 @@
+// eps.hip -- the two sampling kernels of the search-distance selection
+// (Sec. 4.4): the mean distance between the points of a small sample
+// (eps_mean), and the histogram of distances from sample points to every
+// point of D, binned up to eps_mean.
+#pragma clang fp contract(off)
+
+#include "kernels.hpp"
+
+namespace knn {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double sq_dist_soa(const double* __restrict__ X, int64_t N, int n,
+                                              int64_t a, const double* qa) {
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double t = __dsub_rn(X[(int64_t)j * N + a], qa[j]);
+    s = __dadd_rn(s, __dmul_rn(t, t));
+  }
+  return s;
+}
+
+// Block `a` sums the distances of sample point a to the sample points after it.
+__global__ void k_pair_sums(const double* __restrict__ X, int64_t N, int n,
+                            const int64_t* __restrict__ sample, int64_t ns,
+                            double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  for (int64_t a = blockIdx.x; a < ns; a += gridDim.x) {
+    double qa[kMaxDims];
+    const int64_t ia = sample[a];
+    for (int j = 0; j < n; ++j) qa[j] = X[(int64_t)j * N + ia];
+    double s = 0.0;
+    for (int64_t b = a + 1 + threadIdx.x; b < ns; b += blockDim.x)
+      s += sqrt(sq_dist_soa(X, N, n, sample[b], qa));
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[a] = red[0];
+    __syncthreads();
+  }
+}
+
+constexpr int kSampleChunk = 256;
+constexpr int kMaxBins = 4096;
+
+// Each thread takes points j; the sample points of a chunk sit in LDS.  The
+// per-block histogram is accumulated in LDS (uint32) and added to the global
+// uint64 counts at the end.
+__global__ void k_dist_histogram(const double* __restrict__ X, int64_t N, int n,
+                                 const int64_t* __restrict__ sample, int64_t ns, double inv_bw,
+                                 int n_bins, double skip_d2, uint64_t* __restrict__ counts) {
+  __shared__ uint32_t h[kMaxBins];
+  __shared__ double sx[kMaxDims][kSampleChunk];
+  __shared__ int64_t sid[kSampleChunk];
+  for (int b = threadIdx.x; b < n_bins; b += blockDim.x) h[b] = 0;
+  for (int64_t c0 = 0; c0 < ns; c0 += kSampleChunk) {
+    const int cn = (int)((ns - c0) < kSampleChunk ? (ns - c0) : kSampleChunk);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cn; i += blockDim.x) {
+      int64_t id = sample[c0 + i];
+      sid[i] = id;
+      for (int j = 0; j < n; ++j) sx[j][i] = X[(int64_t)j * N + id];
+    }
+    __syncthreads();
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+         p += (int64_t)gridDim.x * blockDim.x) {
+      double x[kMaxDims];
+      for (int j = 0; j < n; ++j) x[j] = X[(int64_t)j * N + p];
+      for (int i = 0; i < cn; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) {
+          double t = __dsub_rn(x[j], sx[j][i]);
+          s = __dadd_rn(s, __dmul_rn(t, t));
+        }
+        if (s > skip_d2 || p == sid[i]) continue;  // certainly beyond the last bin, or self
+        double t = floor(sqrt(s) * inv_bw);
+        if (t < (double)n_bins) atomicAdd(&h[(int)t], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < n_bins; b += blockDim.x)
+    if (h[b]) atomicAdd((unsigned long long*)&counts[b], (unsigned long long)h[b]);
+}
+
+}  // namespace
+
+int launch_sample_pair_sums(const double* X, int64_t N, int n, const int64_t* sample,
+                            int64_t ns, double* part, hipStream_t s) {
+  if (ns < 2) return 0;
+  int nb = (int)(ns < 65535 ? ns : 65535);
+  k_pair_sums<<<nb, kBlock, 0, s>>>(X, N, n, sample, ns, part);
+  KNN_LAUNCHED();
+  return (int)ns;
+}
+
+void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sample,
+                           int64_t ns, double inv_bw, int n_bins, uint64_t* counts,
+                           hipStream_t s) {
+  KNN_CHECK(n_bins >= 1 && n_bins <= kMaxBins, KNN_EINVAL, "n_bins must be in [1, 4096]");
+  KNN_HIP(hipMemsetAsync(counts, 0, n_bins * sizeof(uint64_t), s));
+  if (ns <= 0 || N <= 0) return;
+  // distances whose bin is certainly >= n_bins skip the square root
+  double lim = (double)n_bins / inv_bw;
+  double skip_d2 = lim * lim * 1.0001 + 1e-300;
+  int64_t want = ceil_div(N, kBlock);
+  int nb = (int)(want < 2048 ? want : 2048);
+  k_dist_histogram<<<nb, kBlock, 0, s>>>(X, N, n, sample, ns, inv_bw, n_bins, skip_d2, counts);
+  KNN_LAUNCHED();
+}
+
+}  // namespace knn

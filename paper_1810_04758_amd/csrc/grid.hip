@@ -1,0 +1,619 @@
+// grid.hip -- construction of one uniform-grid level on the GPU (Sec. 3.1,
+// built on the GPU as in Sec. 4.6): layout change, bounds, cell keys, LSD
+// radix sort, cell table by flag + exclusive scan, SoA gather of the sorted
+// coordinates, and the row-segment neighbour ranges of every non-empty cell.
+// Also the small helpers of the level loop (work-item keys, failure flags).
+#pragma clang fp contract(off)
+
+#include "kernels.hpp"
+
+namespace knn {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ inline int64_t cell_coord(double x, double lo, double inv_w) {
+  // floor((x - lo) * inv_w), both operations rounded (no contraction)
+  return (int64_t)floor(__dmul_rn(__dsub_rn(x, lo), inv_w));
+}
+
+// --------------------------------------------------------------------------
+// layout + bounds
+// --------------------------------------------------------------------------
+__global__ void k_aos_to_soa(const double* __restrict__ D, int64_t N, int n,
+                             double* __restrict__ X, uint32_t* bad) {
+  uint32_t nbad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = D[e];
+    int64_t i = e / n;
+    int j = (int)(e - i * n);
+    X[(int64_t)j * N + i] = v;
+    if (!isfinite(v)) ++nbad;
+  }
+  if (nbad) atomicAdd(bad, nbad);
+}
+
+__global__ void k_bounds_partial(const double* __restrict__ X, int64_t N, int n,
+                                 double* __restrict__ part) {
+  __shared__ double smin[kBlock], smax[kBlock];
+  for (int j = 0; j < n; ++j) {
+    double mn = INFINITY, mx = -INFINITY;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      double v = X[(int64_t)j * N + i];
+      mn = fmin(mn, v);
+      mx = fmax(mx, v);
+    }
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+        smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      part[(2 * j) * gridDim.x + blockIdx.x] = smin[0];
+      part[(2 * j + 1) * gridDim.x + blockIdx.x] = smax[0];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_bounds_final(const double* __restrict__ part, int nparts, int n,
+                               double* lo, double* hi) {
+  __shared__ double smin[kBlock], smax[kBlock];
+  for (int j = 0; j < n; ++j) {
+    double mn = INFINITY, mx = -INFINITY;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+      mn = fmin(mn, part[(2 * j) * nparts + i]);
+      mx = fmax(mx, part[(2 * j + 1) * nparts + i]);
+    }
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+        smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      lo[j] = smin[0];
+      hi[j] = smax[0];
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------------------
+// exclusive scan of uint32 (reduce, scan partials, apply)
+// --------------------------------------------------------------------------
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive block scan of one value per thread (blockDim == kBlock); returns
+// the exclusive prefix and writes the block total to *total.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) {
+    if (i < w) base += wsum[i];
+    tot += wsum[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - v;
+}
+
+__global__ void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                              uint32_t* __restrict__ part) {
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  uint32_t tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// Single-block exclusive scan of the partials in place; total to *total.
+__global__ void k_scan_partials(uint32_t* part, int64_t np, uint32_t* total) {
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < np; base += kBlock) {
+    int64_t i = base + threadIdx.x;
+    uint32_t v = i < np ? part[i] : 0;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(v, &tot);
+    if (i < np) part[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ void k_scan_apply(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                             int64_t n, const uint32_t* __restrict__ part) {
+  // thread t owns kScanItems consecutive elements of the tile
+  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    v[k] = i < n ? in[i] : 0;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t ex = block_excl_scan(s, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    if (i < n) out[i] = ex;
+    ex += v[k];
+  }
+}
+
+// --------------------------------------------------------------------------
+// LSD radix sort, 8-bit digits: per-tile histogram, scan, stable scatter
+// --------------------------------------------------------------------------
+constexpr int kRadixItems = 8;
+constexpr int kRadixTile = kBlock * kRadixItems;
+
+__global__ void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                             uint32_t* __restrict__ hist, int64_t nb) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kRadixTile;
+#pragma unroll
+  for (int k = 0; k < kRadixItems; ++k) {
+    int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_radix_scatter(const uint64_t* __restrict__ keys,
+                                const int32_t* __restrict__ vals, int64_t n, int shift,
+                                const uint32_t* __restrict__ offs, int64_t nb,
+                                uint64_t* __restrict__ okeys, int32_t* __restrict__ ovals) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[kBlock / 64][256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  run[t] = offs[(int64_t)t * nb + blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) wcnt[i][t] = 0;
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  for (int k = 0; k < kRadixItems; ++k) {
+    int64_t i = base + (int64_t)k * kBlock + t;
+    bool valid = i < n;
+    uint64_t key = valid ? keys[i] : 0;
+    int32_t val = valid ? vals[i] : 0;
+    uint32_t d = (uint32_t)(key >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (d >> b) & 1u;
+      uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int i2 = 0; i2 < w; ++i2) pos += wcnt[i2][d];
+      okeys[pos] = key;
+      ovals[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int i2 = 0; i2 < kBlock / 64; ++i2) {
+      add += wcnt[i2][t];
+      wcnt[i2][t] = 0;
+    }
+    run[t] += add;
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------------------
+// grid level
+// --------------------------------------------------------------------------
+struct GeomDev {
+  double lo[kMaxDims];
+  double inv_w;
+  uint64_t stride[kMaxDims];
+  int64_t g[kMaxDims];
+};
+
+GeomDev to_dev(const GridGeom& gg) {
+  GeomDev d{};
+  for (int j = 0; j < kMaxDims; ++j) {
+    d.lo[j] = gg.lo[j];
+    d.stride[j] = gg.stride[j];
+    d.g[j] = gg.g[j];
+  }
+  d.inv_w = gg.inv_w;
+  return d;
+}
+
+template <int DIM>
+__global__ void k_cell_keys(const double* __restrict__ X, int64_t N, GeomDev gd,
+                            uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t key = 0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+      key += (uint64_t)cell_coord(X[(int64_t)j * N + i], gd.lo[j], gd.inv_w) * gd.stride[j];
+    keys[i] = key;
+    vals[i] = (int32_t)i;
+  }
+}
+
+__global__ void k_mark_cells(const uint64_t* __restrict__ keys, int64_t N,
+                             uint32_t* __restrict__ flags) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x)
+    flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+// ex: exclusive scan of flags (may alias cell_of).
+__global__ void k_emit_cells(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ flags,
+                             const uint32_t* ex, int64_t N, uint32_t* cell_of,
+                             uint64_t* __restrict__ cell_key, uint32_t* __restrict__ cell_start) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t f = flags[i];
+    uint32_t c = ex[i] + f - 1u;
+    if (f) {
+      cell_key[c] = keys[i];
+      cell_start[c] = (uint32_t)i;
+    }
+    cell_of[i] = c;
+    if (i == N - 1) cell_start[c + 1] = (uint32_t)N;
+  }
+}
+
+__global__ void k_gather_soa(const double* __restrict__ X, const int32_t* __restrict__ perm,
+                             int64_t N, int n, double* __restrict__ Xs) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    int64_t src = perm[p];
+    for (int j = 0; j < n; ++j) Xs[(int64_t)j * N + p] = X[(int64_t)j * N + src];
+  }
+}
+
+__global__ void k_dense_fill(uint32_t* __restrict__ table, int64_t size) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < size;
+       i += (int64_t)gridDim.x * blockDim.x)
+    table[i] = 0xFFFFFFFFu;
+}
+
+__global__ void k_dense_scatter(const uint64_t* __restrict__ cell_key, const uint32_t* d_M,
+                                uint32_t* __restrict__ table) {
+  const uint32_t M = *d_M;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < M;
+       c += (int64_t)gridDim.x * blockDim.x)
+    table[cell_key[c]] = (uint32_t)c;
+}
+
+// Index of the first cell whose key is >= key (binary search in cell_key[0..M)).
+__device__ inline uint32_t lower_bound_key(const uint64_t* __restrict__ cell_key, uint32_t M,
+                                           uint64_t key) {
+  uint32_t lo = 0, hi = M;
+  while (lo < hi) {
+    uint32_t mid = lo + ((hi - lo) >> 1);
+    if (cell_key[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// One thread per (cell, row segment).  The cell's coordinates are recomputed
+// from its first point with the key formula, so no key decoding is needed.
+template <int DIM>
+__global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
+                                  const uint32_t* __restrict__ cell_start,
+                                  const uint64_t* __restrict__ cell_key, const uint32_t* d_M,
+                                  const uint32_t* __restrict__ dense, GeomDev gd,
+                                  uint32_t* __restrict__ ranges,
+                                  uint32_t* __restrict__ cand_count) {
+  constexpr int R = DIM == 2 ? 3 : DIM == 3 ? 9 : DIM == 4 ? 27 : DIM == 5 ? 81 : 243;
+  const uint32_t M = *d_M;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)M * R;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t c = (uint32_t)(e / R);
+    const int r = (int)(e - (int64_t)c * R);
+    const uint32_t p0 = cell_start[c];
+    int64_t cc[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) cc[j] = cell_coord(Xs[(int64_t)j * N + p0], gd.lo[j], gd.inv_w);
+    // offsets o_0..o_{DIM-2}, o_0 slowest
+    bool inside = true;
+    uint64_t prefix = 0;
+    int rr = r;
+    int64_t nb[DIM];
+#pragma unroll
+    for (int j = DIM - 2; j >= 0; --j) {
+      int o = rr % 3 - 1;
+      rr /= 3;
+      nb[j] = cc[j] + o;
+      if (nb[j] < 0 || nb[j] >= gd.g[j]) inside = false;
+    }
+    uint32_t start = 0, end = 0;
+    if (inside) {
+#pragma unroll
+      for (int j = 0; j < DIM - 1; ++j) prefix += (uint64_t)nb[j] * gd.stride[j];
+      const int64_t last = cc[DIM - 1];
+      const int64_t a = last > 0 ? last - 1 : 0;
+      const int64_t b = last + 1 < gd.g[DIM - 1] ? last + 1 : gd.g[DIM - 1] - 1;
+      if (dense) {
+        uint32_t first = 0xFFFFFFFFu, lastc = 0xFFFFFFFFu;
+        for (int64_t t = a; t <= b; ++t) {
+          uint32_t ci = dense[prefix + (uint64_t)t];
+          if (ci != 0xFFFFFFFFu) {
+            if (first == 0xFFFFFFFFu) first = ci;
+            lastc = ci;
+          }
+        }
+        if (first != 0xFFFFFFFFu) {
+          start = cell_start[first];
+          end = cell_start[lastc + 1];
+        }
+      } else {
+        const uint64_t klo = prefix + (uint64_t)a, khi = prefix + (uint64_t)b;
+        uint32_t f = lower_bound_key(cell_key, M, klo);
+        uint32_t l = f;
+        while (l < M && cell_key[l] <= khi) ++l;
+        if (l > f) {
+          start = cell_start[f];
+          end = cell_start[l];
+        }
+      }
+    }
+    ranges[2 * e] = start;
+    ranges[2 * e + 1] = end;
+    if (end > start) atomicAdd(&cand_count[c], end - start);
+  }
+}
+
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+__global__ void k_item_keys(const int32_t* __restrict__ active, int64_t n_active, int G,
+                            const uint32_t* __restrict__ cell_of,
+                            const uint32_t* __restrict__ cand_count, uint64_t* __restrict__ keys,
+                            int32_t* __restrict__ vals, int64_t n_items) {
+  for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < n_items;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t est = 0;
+    int64_t s0 = it * G, s1 = s0 + G < n_active ? s0 + G : n_active;
+    for (int64_t s = s0; s < s1; ++s) {
+      int64_t q = active ? active[s] : s;
+      est += cand_count[cell_of[q]];
+    }
+    if (est > 0xFFFFFFFFull) est = 0xFFFFFFFFull;
+    keys[it] = 0xFFFFFFFFull - est;  // ascending sort = dense first
+    vals[it] = (int32_t)it;
+  }
+}
+
+__global__ void k_mark_failed(const int32_t* __restrict__ fail_list, const int32_t* d_count,
+                              uint8_t* __restrict__ failed) {
+  const int64_t cnt = *d_count;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
+       i += (int64_t)gridDim.x * blockDim.x)
+    failed[fail_list[i]] = 1;
+}
+
+__global__ void k_failed_flags(const uint8_t* __restrict__ failed, const int32_t* __restrict__ perm,
+                               int64_t N, uint32_t* __restrict__ flags) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+       p += (int64_t)gridDim.x * blockDim.x)
+    flags[p] = failed[perm[p]] ? 1u : 0u;
+}
+
+__global__ void k_compact(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ ex,
+                          int64_t N, int32_t* __restrict__ out) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+       p += (int64_t)gridDim.x * blockDim.x)
+    if (flags[p]) out[ex[p]] = (int32_t)p;
+}
+
+int grid_for(int64_t n, int cap = 8192) {
+  int64_t b = ceil_div(n, kBlock);
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+}  // namespace
+
+void launch_aos_to_soa(const double* D, int64_t N, int n, double* X, uint32_t* bad,
+                       hipStream_t s) {
+  k_aos_to_soa<<<grid_for(N * n), kBlock, 0, s>>>(D, N, n, X, bad);
+  KNN_LAUNCHED();
+}
+
+void launch_bounds(const double* X, int64_t N, int n, double* part, double* lo, double* hi,
+                   hipStream_t s) {
+  int nb = grid_for(N, kBoundsBlocks);
+  k_bounds_partial<<<nb, kBlock, 0, s>>>(X, N, n, part);
+  KNN_LAUNCHED();
+  k_bounds_final<<<1, kBlock, 0, s>>>(part, nb, n, lo, hi);
+  KNN_LAUNCHED();
+}
+
+size_t scan_tmp_elems(int64_t n) { return (size_t)ceil_div(n, kScanTile) + 1; }
+
+void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                           uint32_t* tmp, hipStream_t s) {
+  if (n <= 0) {
+    if (total) KNN_HIP(hipMemsetAsync(total, 0, sizeof(uint32_t), s));
+    return;
+  }
+  int64_t nb = ceil_div(n, kScanTile);
+  k_scan_reduce<<<(unsigned)nb, kBlock, 0, s>>>(in, n, tmp);
+  KNN_LAUNCHED();
+  k_scan_partials<<<1, kBlock, 0, s>>>(tmp, nb, total);
+  KNN_LAUNCHED();
+  k_scan_apply<<<(unsigned)nb, kBlock, 0, s>>>(in, out, n, tmp);
+  KNN_LAUNCHED();
+}
+
+size_t radix_tmp_elems(int64_t n) {
+  int64_t nb = ceil_div(n, kRadixTile);
+  return (size_t)(256 * nb) + scan_tmp_elems(256 * nb);
+}
+
+void radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
+                      int64_t n, int bits, uint32_t* tmp, hipStream_t s) {
+  if (n <= 1 || bits <= 0) return;
+  int64_t nb = ceil_div(n, kRadixTile);
+  uint32_t* hist = tmp;
+  uint32_t* stmp = tmp + 256 * nb;
+  uint64_t* src_k = keys;
+  int32_t* src_v = vals;
+  uint64_t* dst_k = keys2;
+  int32_t* dst_v = vals2;
+  int passes = (bits + 7) / 8;
+  for (int ps = 0; ps < passes; ++ps) {
+    int shift = 8 * ps;
+    k_radix_hist<<<(unsigned)nb, kBlock, 0, s>>>(src_k, n, shift, hist, nb);
+    KNN_LAUNCHED();
+    launch_exclusive_scan(hist, hist, 256 * nb, nullptr, stmp, s);
+    k_radix_scatter<<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb, dst_k,
+                                                    dst_v);
+    KNN_LAUNCHED();
+    std::swap(src_k, dst_k);
+    std::swap(src_v, dst_v);
+  }
+  if (src_k != keys) {
+    KNN_HIP(hipMemcpyAsync(keys, src_k, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    KNN_HIP(hipMemcpyAsync(vals, src_v, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  }
+}
+
+void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* keys,
+                      int32_t* vals, hipStream_t s) {
+  GeomDev gd = to_dev(gg);
+  int nb = grid_for(N);
+  switch (gg.dims) {
+    case 2: k_cell_keys<2><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
+    case 3: k_cell_keys<3><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
+    case 4: k_cell_keys<4><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
+    case 5: k_cell_keys<5><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
+    case 6: k_cell_keys<6><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
+    default: throw Error(KNN_EINVAL, "dims out of range");
+  }
+  KNN_LAUNCHED();
+}
+
+void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags, uint32_t* cell_of,
+                      uint64_t* cell_key, uint32_t* cell_start, uint32_t* d_M, uint32_t* tmp,
+                      hipStream_t s) {
+  int nb = grid_for(N);
+  k_mark_cells<<<nb, kBlock, 0, s>>>(sorted_keys, N, flags);
+  KNN_LAUNCHED();
+  launch_exclusive_scan(flags, cell_of, N, d_M, tmp, s);
+  k_emit_cells<<<nb, kBlock, 0, s>>>(sorted_keys, flags, cell_of, N, cell_of, cell_key,
+                                     cell_start);
+  KNN_LAUNCHED();
+}
+
+void launch_gather_soa(const double* X, const int32_t* perm, int64_t N, int n, double* Xs,
+                       hipStream_t s) {
+  k_gather_soa<<<grid_for(N), kBlock, 0, s>>>(X, perm, N, n, Xs);
+  KNN_LAUNCHED();
+}
+
+void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N,
+                        uint32_t* table, int64_t table_size, hipStream_t s) {
+  k_dense_fill<<<grid_for(table_size), kBlock, 0, s>>>(table, table_size);
+  KNN_LAUNCHED();
+  k_dense_scatter<<<grid_for(N), kBlock, 0, s>>>(cell_key, d_M, table);
+  KNN_LAUNCHED();
+}
+
+void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_start,
+                            const uint64_t* cell_key, const uint32_t* d_M,
+                            const uint32_t* dense, const GridGeom& gg, uint32_t* ranges,
+                            uint32_t* cand_count, hipStream_t s) {
+  GeomDev gd = to_dev(gg);
+  k_zero_u32<<<grid_for(N), kBlock, 0, s>>>(cand_count, N);
+  KNN_LAUNCHED();
+  int64_t R = 1;
+  for (int j = 0; j < gg.dims - 1; ++j) R *= 3;
+  int nb = grid_for(N * R, 65536);
+  switch (gg.dims) {
+    case 2: k_neighbor_ranges<2><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, cand_count); break;
+    case 3: k_neighbor_ranges<3><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, cand_count); break;
+    case 4: k_neighbor_ranges<4><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, cand_count); break;
+    case 5: k_neighbor_ranges<5><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, cand_count); break;
+    case 6: k_neighbor_ranges<6><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, cand_count); break;
+    default: throw Error(KNN_EINVAL, "dims out of range");
+  }
+  KNN_LAUNCHED();
+}
+
+void launch_item_keys(const int32_t* active, int64_t n_active, int G, const uint32_t* cell_of,
+                      const uint32_t* cand_count, uint64_t* keys, int32_t* vals, int64_t n_items,
+                      hipStream_t s) {
+  k_item_keys<<<grid_for(n_items), kBlock, 0, s>>>(active, n_active, G, cell_of, cand_count,
+                                                    keys, vals, n_items);
+  KNN_LAUNCHED();
+}
+
+void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count, int64_t max_fail,
+                        uint8_t* failed, hipStream_t s) {
+  k_mark_failed<<<grid_for(max_fail), kBlock, 0, s>>>(fail_list, d_fail_count, failed);
+  KNN_LAUNCHED();
+}
+
+void launch_failed_flags(const uint8_t* failed, const int32_t* perm, int64_t N, uint32_t* flags,
+                         hipStream_t s) {
+  k_failed_flags<<<grid_for(N), kBlock, 0, s>>>(failed, perm, N, flags);
+  KNN_LAUNCHED();
+}
+
+void launch_compact_positions(const uint32_t* flags, const uint32_t* ex, int64_t N, int32_t* out,
+                              hipStream_t s) {
+  k_compact<<<grid_for(N), kBlock, 0, s>>>(flags, ex, N, out);
+  KNN_LAUNCHED();
+}
+
+}  // namespace knn

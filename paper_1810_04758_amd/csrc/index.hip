@@ -1,0 +1,728 @@
+// index.hip -- host runtime of the library: index build with the sampling of
+// Sec. 4.4, grid levels (Sec. 3.1, built on the GPU as in Sec. 4.6), the
+// GPU-only level loop of Alg. 1 (failures re-queued, cell side grown,
+// re-index), and the C ABI of knnjoin.h.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <unordered_set>
+
+#include "autotune.hpp"
+#include "index.hpp"
+
+namespace knn {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+// SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): the counter-based generator of the sampling.
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+};
+
+// `count` distinct ids in [0, N), drawn with SplitMix64 (all ids if count >= N).
+std::vector<int64_t> sample_ids(int64_t N, int64_t count, uint64_t seed) {
+  std::vector<int64_t> out;
+  if (count >= N) {
+    out.resize(N);
+    for (int64_t i = 0; i < N; ++i) out[i] = i;
+    return out;
+  }
+  SplitMix64 g{seed};
+  std::unordered_set<int64_t> seen;
+  seen.reserve((size_t)count * 2);
+  while ((int64_t)out.size() < count) {
+    int64_t id = (int64_t)(g.next() % (uint64_t)N);
+    if (seen.insert(id).second) out.push_back(id);
+  }
+  std::sort(out.begin(), out.end());
+  return out;
+}
+
+int current_device() {
+  int d = 0;
+  KNN_HIP(hipGetDevice(&d));
+  return d;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    KNN_HIP(hipGetDevice(&prev));
+    if (prev != dev) KNN_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int cu_count(int dev) {
+  int v = 0;
+  KNN_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev));
+  return v > 0 ? v : 1;
+}
+
+int64_t pow3(int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= 3;
+  return r;
+}
+
+// Geometry of the level with cell side w.  The side is enlarged if the grid
+// would not fit the 62-bit key space or 2^30 cells per dimension (a
+// performance policy only: any side gives exact results).
+GridGeom make_geom(const knn_index& idx, double& w) {
+  GridGeom gg{};
+  gg.dims = idx.n;
+  double ext = 0;
+  for (int j = 0; j < idx.n; ++j) ext = std::max(ext, idx.hi[j] - idx.lo[j]);
+  if (!(w > 0) || !std::isfinite(w)) w = ext > 0 ? ext : 1.0;
+  for (int attempt = 0; attempt < 200; ++attempt) {
+    double inv_w = 1.0 / w;
+    bool fits = std::isfinite(inv_w) && inv_w > 0;
+    long double prod = 1;
+    int64_t gmax = 1;
+    for (int j = 0; fits && j < idx.n; ++j) {
+      double u = std::floor((idx.hi[j] - idx.lo[j]) * inv_w);
+      if (!(u < (double)(1ll << 30))) {
+        fits = false;
+        break;
+      }
+      gg.g[j] = (int64_t)u + 1;
+      gmax = std::max(gmax, gg.g[j]);
+      prod *= (long double)gg.g[j];
+    }
+    if (fits && prod < (long double)(1ull << 62)) {
+      gg.inv_w = inv_w;
+      gg.g_max = gmax;
+      uint64_t st = 1;
+      for (int j = idx.n - 1; j >= 0; --j) {
+        gg.stride[j] = st;
+        st *= (uint64_t)gg.g[j];
+      }
+      for (int j = 0; j < idx.n; ++j) gg.lo[j] = idx.lo[j];
+      uint64_t maxkey = st - 1;
+      int bits = 0;
+      while (bits < 64 && (maxkey >> bits) != 0) ++bits;
+      gg.key_bits = bits;
+      return gg;
+    }
+    w *= 2;
+  }
+  throw Error(KNN_EINTERNAL, "could not choose a grid geometry");
+}
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0;
+  KNN_HIP(hipEventElapsedTime(&ms, a, b));
+  return (double)ms;
+}
+
+struct Events {
+  hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool on = false;
+  explicit Events(bool enable) : on(enable) {
+    if (on)
+      for (auto& x : e) KNN_HIP(hipEventCreate(&x));
+  }
+  ~Events() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+  void rec(int i, hipStream_t s) {
+    if (on) KNN_HIP(hipEventRecord(e[i], s));
+  }
+};
+
+}  // namespace
+
+int64_t JoinContext::device_bytes() const {
+  return (int64_t)(Xs.bytes() + perm.bytes() + cell_of.bytes() + cell_key.bytes() +
+                   cell_start.bytes() + ranges.bytes() + cand_count.bytes() + dense.bytes() +
+                   keys.bytes() + keys2.bytes() + vals2.bytes() + flags.bytes() + tmp.bytes() +
+                   scal.bytes() + iscal.bytes() + active.bytes() + fail_list.bytes() +
+                   failed.bytes() + ikeys.bytes() + ikeys2.bytes() + ivals.bytes() +
+                   ivals2.bytes() + out_ids.bytes() + out_d.bytes());
+}
+
+double eps_min_of(const knn_index& idx, int32_t K) {
+  const uint64_t need = (uint64_t)K * (uint64_t)idx.n_sample;
+  for (int d = 0; d < idx.n_bins; ++d) {
+    if (idx.cum[d] >= need) {
+      double start = (double)d * idx.bin_width;
+      double end = (double)(d + 1) * idx.bin_width;
+      return (start + end) / 2.0;
+    }
+  }
+  return (double)idx.n_bins * idx.bin_width;
+}
+
+void validate_join(const knn_index* idx, int32_t K) {
+  KNN_CHECK(idx != nullptr, KNN_EINVAL, "index is NULL");
+  KNN_CHECK(K >= 1, KNN_EINVAL, "K must be >= 1");
+  KNN_CHECK((int64_t)K <= idx->N - 1, KNN_EINVAL, "K must be <= N-1");
+  KNN_CHECK(K <= KNN_MAX_K, KNN_EINVAL, "K above KNN_MAX_K");
+}
+
+void build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s) {
+  const int64_t N = idx.N;
+  const int n = idx.n;
+  c.gg = make_geom(idx, w);
+  c.Xs.reserve((size_t)N * n);
+  c.perm.reserve(N);
+  c.cell_of.reserve(N);
+  c.cell_key.reserve(N);
+  c.cell_start.reserve(N + 1);
+  c.cand_count.reserve(N);
+  c.keys.reserve(N);
+  c.keys2.reserve(N);
+  c.vals2.reserve(N);
+  c.flags.reserve(N);
+  c.tmp.reserve(std::max(radix_tmp_elems(N), scan_tmp_elems(N)));
+  c.scal.reserve(4);
+  launch_cell_keys(idx.X.p, N, c.gg, c.keys.p, c.perm.p, s);
+  radix_sort_pairs(c.keys.p, c.perm.p, c.keys2.p, c.vals2.p, N, c.gg.key_bits, c.tmp.p, s);
+  build_cell_table(c.keys.p, N, c.flags.p, c.cell_of.p, c.cell_key.p, c.cell_start.p, c.scal.p,
+                   c.tmp.p, s);
+  launch_gather_soa(idx.X.p, c.perm.p, N, n, c.Xs.p, s);
+  uint32_t M = 0;
+  KNN_HIP(hipMemcpyAsync(&M, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  KNN_HIP(hipStreamSynchronize(s));
+  c.M = M;
+  // dense key -> cell table when the grid is small enough
+  long double cells = 1;
+  for (int j = 0; j < n; ++j) cells *= (long double)c.gg.g[j];
+  const uint32_t* dense = nullptr;
+  if (n > 2 && cells <= (long double)std::max<int64_t>(16 * N, 1 << 22)) {
+    c.dense.reserve((size_t)cells);
+    launch_dense_table(c.cell_key.p, c.scal.p, N, c.dense.p, (int64_t)cells, s);
+    dense = c.dense.p;
+  }
+  const int64_t R = pow3(n - 1);
+  c.ranges.reserve((size_t)std::max<int64_t>(M, 1) * R * 2);
+  launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, dense, c.gg,
+                         c.ranges.p, c.cand_count.p, s);
+}
+
+uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
+  const uint64_t N = (uint64_t)idx.N, n = (uint64_t)idx.n;
+  // level arrays + temporaries (ranges sized for one cell per point at worst
+  // in 2-D, per-point cells are the exception in higher dims but bounded here)
+  uint64_t R = (uint64_t)pow3(idx.n - 1);
+  uint64_t b = N * (8 * n + 4 + 4 + 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8 + 1) + N * 16 * 4 / 8 +
+               N * std::min<uint64_t>(R, 27) * 8 + (1u << 24);
+  if (host_output) b += N * (uint64_t)K * 12;
+  return b;
+}
+
+static void pick_lanes(const knn_index& idx, int32_t K, int cap, int& T) {
+  if (T > 0) return;
+  T = autotune_lanes(idx.n, K, idx.N);
+  (void)cap;
+}
+
+void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, double* d_dists,
+               const knn_join_opts& o, hipStream_t s) {
+  validate_join(&idx, K);
+  KNN_CHECK(d_ids && d_dists, KNN_EINVAL, "output pointers are NULL");
+  auto t_start = std::chrono::steady_clock::now();
+  const int64_t N = idx.N;
+  knn_join_stats* st = o.stats;
+  if (st) std::memset(st, 0, sizeof(*st));
+
+  // level-0 cell side: w = w_factor * eps_min(K) (Sec. 4.4), or explicit
+  const double eps_min = eps_min_of(idx, K);
+  double ext = 0;
+  for (int j = 0; j < idx.n; ++j) ext = std::max(ext, idx.hi[j] - idx.lo[j]);
+  double w;
+  if (o.cell_width > 0) {
+    w = o.cell_width;
+  } else {
+    double f = o.w_factor > 0 ? o.w_factor : autotune_w_factor(idx.n, K, idx.N);
+    w = f * eps_min;
+  }
+  if (!(w > 0) || !std::isfinite(w)) w = ext > 0 ? ext * 1e-6 : 1.0;
+  const double w0 = w;
+  const double step = (o.eps_step > 0 ? o.eps_step : 0.5) * w0;
+  const int linear = o.linear_levels > 0 ? o.linear_levels : (o.linear_levels < 0 ? 0 : 2);
+  const double growth = o.growth > 1.0 ? o.growth : 2.0;
+
+  int T = o.lanes_per_query;
+  const int pad = std::max(8, K / 4);
+  const int cap = K + pad;
+  pick_lanes(idx, K, cap, T);
+  KNN_CHECK(T >= 1 && T <= 64 && (T & (T - 1)) == 0, KNN_EINVAL,
+            "lanes_per_query must be a power of two in [1, 64]");
+  const int G = 64 / T;
+  if (st) {
+    st->eps_min = eps_min;
+    st->lanes_per_query = T;
+  }
+
+  c.iscal.reserve(4);
+  c.scal.reserve(4);
+  c.active.reserve(N);
+  c.fail_list.reserve(N);
+  c.failed.reserve(N);
+  const int ncu = cu_count(c.device);
+  const int waves = search_waves_per_block(T, cap);
+
+  Events ev(st != nullptr);
+  int64_t A = N;  // active queries
+  for (int level = 0;; ++level) {
+    if (level >= KNN_MAX_LEVELS - 1) w = std::max(w, 2.0 * ext + 1.0);  // everything in one block
+    ev.rec(0, s);
+    build_level(idx, c, w, s);
+    // active list of this level (cell order): level 0 = every point
+    const int32_t* active = nullptr;
+    if (level > 0) {
+      // keys2 (scratch of the level's sort) holds the exclusive scan
+      uint32_t* ex = reinterpret_cast<uint32_t*>(c.keys2.p);
+      launch_failed_flags(c.failed.p, c.perm.p, N, c.flags.p, s);
+      launch_exclusive_scan(c.flags.p, ex, N, c.scal.p + 1, c.tmp.p, s);
+      launch_compact_positions(c.flags.p, ex, N, c.active.p, s);
+      active = c.active.p;
+    }
+    // work items, densest first (Sec. 4.5 work estimate; persistent schedule)
+    const int64_t n_items = ceil_div(A, G);
+    const int32_t* order = nullptr;
+    if (o.schedule == 0 && n_items > 1) {
+      c.ikeys.reserve(n_items);
+      c.ikeys2.reserve(n_items);
+      c.ivals.reserve(n_items);
+      c.ivals2.reserve(n_items);
+      launch_item_keys(active, A, G, c.cell_of.p, c.cand_count.p, c.ikeys.p, c.ivals.p, n_items,
+                       s);
+      radix_sort_pairs(c.ikeys.p, c.ivals.p, c.ikeys2.p, c.ivals2.p, n_items, 32, c.tmp.p, s);
+      order = c.ivals.p;
+    }
+    KNN_HIP(hipMemsetAsync(c.iscal.p, 0, 4 * sizeof(int32_t), s));
+    ev.rec(1, s);
+
+    SearchArgs a{};
+    a.Xs = c.Xs.p;
+    a.N = N;
+    a.perm = c.perm.p;
+    a.cell_of = c.cell_of.p;
+    a.ranges = c.ranges.p;
+    a.active = active;
+    a.n_active = A;
+    a.order = order;
+    a.n_items = n_items;
+    a.item_base = 0;
+    a.head = c.iscal.p;
+    a.persistent = o.schedule == 0 ? 1 : 0;
+    for (int j = 0; j < kMaxDims; ++j) {
+      a.lo[j] = c.gg.lo[j];
+      a.g[j] = c.gg.g[j];
+    }
+    a.inv_w = c.gg.inv_w;
+    a.margin = (8.0 * (double)c.gg.g_max + 4.0 * idx.n + 32.0) * std::ldexp(1.0, -53);
+    a.K = K;
+    a.cap = cap;
+    a.out_ids = d_ids;
+    a.out_d = d_dists;
+    a.fail_list = c.fail_list.p;
+    a.fail_count = c.iscal.p + 1;
+    a.refine_count = c.iscal.p + 2;
+    if (o.schedule == 0) {
+      int64_t want = ceil_div(n_items, waves);
+      int blocks = (int)std::min<int64_t>(want, (int64_t)ncu * 16);
+      launch_search(a, idx.n, T, blocks, s);
+    } else {
+      // one launch per batch of queries, cell order, one item per wavefront
+      int64_t per = o.batch_queries > 0 ? ceil_div(o.batch_queries, G) : n_items;
+      for (int64_t base = 0; base < n_items; base += per) {
+        a.item_base = base;
+        a.n_items = std::min<int64_t>(n_items, base + per);
+        int64_t blocks = ceil_div(a.n_items - base, waves);
+        launch_search(a, idx.n, T, (int)blocks, s);
+      }
+    }
+    ev.rec(2, s);
+    int32_t fails = 0;
+    KNN_HIP(hipMemcpyAsync(&fails, c.iscal.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    if (st && level < KNN_MAX_LEVELS) {
+      st->levels = level + 1;
+      st->cell_width[level] = 1.0 / c.gg.inv_w;
+      st->attempted[level] = A;
+      st->failed[level] = fails;
+      st->cells[level] = c.M;
+      st->ms_build[level] = elapsed_ms(ev.e[0], ev.e[1]);
+      st->ms_search[level] = elapsed_ms(ev.e[1], ev.e[2]);
+      st->total_attempted += A;
+      st->total_failed += fails;
+    }
+    if (fails == 0) break;
+    KNN_CHECK(fails <= A, KNN_EINTERNAL, "more failures than attempted queries");
+    // failures are re-queued on a grid with a larger cell side (Alg. 1):
+    // linear growth by eps_step * w0 first, then geometric growth
+    KNN_HIP(hipMemsetAsync(c.failed.p, 0, N, s));
+    launch_mark_failed(c.fail_list.p, c.iscal.p + 1, fails, c.failed.p, s);
+    A = fails;
+    w = (1.0 / c.gg.inv_w);
+    if (level < linear)
+      w = w + step;
+    else
+      w = w * growth;
+  }
+  if (st) {
+    st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                             t_start)
+                       .count();
+  }
+}
+
+}  // namespace knn
+
+using namespace knn;
+
+namespace {
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    f();
+    set_last_error("");
+    return KNN_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return KNN_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return KNN_EINTERNAL;
+  } catch (...) {
+    set_last_error("unknown error");
+    return KNN_EINTERNAL;
+  }
+}
+
+knn_build_opts resolve(const knn_build_opts* in) {
+  knn_build_opts o{};
+  if (in) o = *in;
+  if (o.seed == 0) o.seed = 1;
+  if (o.n_sample <= 0) o.n_sample = 500;
+  if (o.n_bins <= 0) o.n_bins = 1000;
+  if (!(o.mean_frac > 0)) o.mean_frac = 0.001;
+  if (o.min_mean_sample <= 0) o.min_mean_sample = 64;
+  return o;
+}
+
+// Common part of both build entry points: D_dev is AoS on the device.
+knn_index* build_from_device(const double* D_dev, int64_t N, int n, const knn_build_opts& o,
+                             hipStream_t s) {
+  auto* idx = new knn_index();
+  try {
+    idx->N = N;
+    idx->n = n;
+    idx->device = current_device();
+    idx->X.alloc((size_t)N * n);
+    DevBuf<uint32_t> bad(1);
+    KNN_HIP(hipMemsetAsync(bad.p, 0, sizeof(uint32_t), s));
+    launch_aos_to_soa(D_dev, N, n, idx->X.p, bad.p, s);
+    uint32_t nbad = 0;
+    KNN_HIP(hipMemcpyAsync(&nbad, bad.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    KNN_CHECK(nbad == 0, KNN_EINVAL, "D holds non-finite coordinates");
+    // bounds
+    DevBuf<double> part((size_t)2 * n * kBoundsBlocks), lohi(2 * kMaxDims);
+    launch_bounds(idx->X.p, N, n, part.p, lohi.p, lohi.p + kMaxDims, s);
+    double hb[2 * kMaxDims];
+    KNN_HIP(hipMemcpyAsync(hb, lohi.p, sizeof(hb), hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < n; ++j) {
+      idx->lo[j] = hb[j];
+      idx->hi[j] = hb[kMaxDims + j];
+    }
+    // eps_mean over a sample of mean_frac * N points (Sec. 4.4)
+    int64_t nm = (int64_t)std::llround(o.mean_frac * (double)N);
+    nm = std::max<int64_t>(nm, o.min_mean_sample);
+    nm = std::min<int64_t>(nm, std::min<int64_t>(N, 20000));
+    std::vector<int64_t> sm = sample_ids(N, nm, o.seed);
+    std::vector<int64_t> sh = sample_ids(N, o.n_sample, o.seed ^ 0x5DEECE66Dull);
+    DevBuf<int64_t> d_sm(sm.size()), d_sh(sh.size());
+    KNN_HIP(hipMemcpyAsync(d_sm.p, sm.data(), sm.size() * 8, hipMemcpyHostToDevice, s));
+    KNN_HIP(hipMemcpyAsync(d_sh.p, sh.data(), sh.size() * 8, hipMemcpyHostToDevice, s));
+    DevBuf<double> psum(std::max<size_t>(sm.size(), 1));
+    int np = launch_sample_pair_sums(idx->X.p, N, n, d_sm.p, (int64_t)sm.size(), psum.p, s);
+    std::vector<double> hp(np);
+    if (np) KNN_HIP(hipMemcpyAsync(hp.data(), psum.p, np * 8, hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    double sum = 0;
+    for (double v : hp) sum += v;
+    double pairs = (double)sm.size() * (double)(sm.size() - 1) / 2.0;
+    double eps_mean = pairs > 0 ? sum / pairs : 0.0;
+    double ext = 0;
+    for (int j = 0; j < n; ++j) ext = std::max(ext, idx->hi[j] - idx->lo[j]);
+    if (!(eps_mean > 0)) eps_mean = ext > 0 ? ext : 1.0;
+    idx->eps_mean = eps_mean;
+    idx->n_bins = o.n_bins;
+    idx->n_sample = (int)sh.size();
+    idx->bin_width = eps_mean / o.n_bins;
+    DevBuf<uint64_t> counts(o.n_bins);
+    launch_dist_histogram(idx->X.p, N, n, d_sh.p, (int64_t)sh.size(), 1.0 / idx->bin_width,
+                          o.n_bins, counts.p, s);
+    std::vector<uint64_t> hc(o.n_bins);
+    KNN_HIP(hipMemcpyAsync(hc.data(), counts.p, o.n_bins * 8, hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    idx->cum.resize(o.n_bins);
+    uint64_t c = 0;
+    for (int b = 0; b < o.n_bins; ++b) {
+      c += hc[b];
+      idx->cum[b] = c;
+    }
+    return idx;
+  } catch (...) {
+    delete idx;
+    throw;
+  }
+}
+
+void check_build_args(const void* D, int64_t N, int32_t dims, knn_index** out) {
+  KNN_CHECK(D != nullptr && out != nullptr, KNN_EINVAL, "NULL pointer");
+  KNN_CHECK(dims >= KNN_MIN_DIMS && dims <= KNN_MAX_DIMS, KNN_EINVAL, "dims must be in [2, 6]");
+  KNN_CHECK(N >= 2 && N < (int64_t(1) << 31), KNN_EINVAL, "N must be in [2, 2^31)");
+}
+
+JoinContext& index_ctx(knn_index* idx) {
+  if (!idx->ctx) {
+    idx->ctx = new JoinContextHolder();
+    idx->ctx->ctx.device = idx->device;
+  }
+  return idx->ctx->ctx;
+}
+
+knn_join_opts resolve_join(const knn_join_opts* o) {
+  knn_join_opts r{};
+  if (o) r = *o;
+  return r;
+}
+
+struct BusyGuard {
+  knn_index* idx;
+  explicit BusyGuard(knn_index* i) : idx(i) {
+    int expect = 0;
+    KNN_CHECK(idx->busy.compare_exchange_strong(expect, 1), KNN_EBUSY,
+              "another join is running on this index");
+  }
+  ~BusyGuard() { idx->busy.store(0); }
+};
+
+}  // namespace
+
+extern "C" {
+
+void knn_build_opts_default(knn_build_opts* o) {
+  if (o) std::memset(o, 0, sizeof(*o)), o->device = -1;
+}
+
+void knn_join_opts_default(knn_join_opts* o) {
+  if (o) std::memset(o, 0, sizeof(*o));
+}
+
+const char* knn_last_error(void) { return g_last_error.c_str(); }
+
+int knn_build_index(const double* D, int64_t n_points, int32_t dims, const knn_build_opts* opts,
+                    knn_index** out) {
+  return guarded([&] {
+    check_build_args(D, n_points, dims, out);
+    knn_build_opts o = resolve(opts);
+    int dev = o.device >= 0 ? o.device : current_device();
+    DeviceGuard dg(dev);
+    hipStream_t s = nullptr;
+    KNN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    try {
+      DevBuf<double> dD((size_t)n_points * dims);
+      KNN_HIP(hipMemcpyAsync(dD.p, D, (size_t)n_points * dims * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      *out = build_from_device(dD.p, n_points, dims, o, s);
+      KNN_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipStreamDestroy(s);
+      throw;
+    }
+    KNN_HIP(hipStreamDestroy(s));
+  });
+}
+
+int knn_build_index_device(const double* d_D, int64_t n_points, int32_t dims,
+                           const knn_build_opts* opts, void* stream, knn_index** out) {
+  return guarded([&] {
+    check_build_args(d_D, n_points, dims, out);
+    knn_build_opts o = resolve(opts);
+    int dev = o.device >= 0 ? o.device : current_device();
+    DeviceGuard dg(dev);
+    *out = build_from_device(d_D, n_points, dims, o, (hipStream_t)stream);
+  });
+}
+
+int knn_self_join_device(knn_index* idx, int32_t K, int32_t* d_ids, double* d_dists,
+                         const knn_join_opts* opts, void* stream) {
+  return guarded([&] {
+    validate_join(idx, K);
+    BusyGuard bg(idx);
+    DeviceGuard dg(idx->device);
+    knn_join_opts o = resolve_join(opts);
+    self_join(*idx, index_ctx(idx), K, d_ids, d_dists, o, (hipStream_t)stream);
+  });
+}
+
+int knn_self_join(knn_index* idx, int32_t K, int32_t* ids, double* dists,
+                  const knn_join_opts* opts) {
+  return guarded([&] {
+    validate_join(idx, K);
+    KNN_CHECK(ids && dists, KNN_EINVAL, "output pointers are NULL");
+    BusyGuard bg(idx);
+    DeviceGuard dg(idx->device);
+    knn_join_opts o = resolve_join(opts);
+    JoinContext& c = index_ctx(idx);
+    hipStream_t s = nullptr;
+    KNN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    try {
+      const size_t NK = (size_t)idx->N * K;
+      c.out_ids.reserve(NK);
+      c.out_d.reserve(NK);
+      self_join(*idx, c, K, c.out_ids.p, c.out_d.p, o, s);
+      KNN_HIP(hipMemcpyAsync(ids, c.out_ids.p, NK * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipMemcpyAsync(dists, c.out_d.p, NK * sizeof(double), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+      throw;
+    }
+    KNN_HIP(hipStreamDestroy(s));
+  });
+}
+
+void knn_destroy_index(knn_index* idx) {
+  if (!idx) return;
+  try {
+    DeviceGuard dg(idx->device);
+    delete idx->ctx;
+    idx->ctx = nullptr;
+    delete idx;
+  } catch (...) {
+  }
+}
+
+int knn_index_info_get(const knn_index* idx, knn_index_info* out) {
+  return guarded([&] {
+    KNN_CHECK(idx && out, KNN_EINVAL, "NULL pointer");
+    std::memset(out, 0, sizeof(*out));
+    out->n_points = idx->N;
+    out->dims = idx->n;
+    out->device = idx->device;
+    for (int j = 0; j < idx->n; ++j) {
+      out->lo[j] = idx->lo[j];
+      out->hi[j] = idx->hi[j];
+    }
+    out->eps_mean = idx->eps_mean;
+    out->n_bins = idx->n_bins;
+    out->n_sample = idx->n_sample;
+    out->device_bytes = (int64_t)idx->X.bytes() + (idx->ctx ? idx->ctx->ctx.device_bytes() : 0);
+  });
+}
+
+int knn_eps_min(const knn_index* idx, int32_t K, double* eps_min) {
+  return guarded([&] {
+    KNN_CHECK(idx && eps_min, KNN_EINVAL, "NULL pointer");
+    KNN_CHECK(K >= 1, KNN_EINVAL, "K must be >= 1");
+    *eps_min = eps_min_of(*idx, K);
+  });
+}
+
+int knn_grid_export(knn_index* idx, double cell_width, uint64_t* sorted_keys, int32_t* perm,
+                    uint64_t* cell_keys, uint32_t* cell_start, uint32_t* ranges,
+                    int64_t* grid_dims, int64_t* n_cells) {
+  return guarded([&] {
+    KNN_CHECK(idx != nullptr, KNN_EINVAL, "index is NULL");
+    KNN_CHECK(cell_width > 0 && std::isfinite(cell_width), KNN_EINVAL, "cell_width must be > 0");
+    BusyGuard bg(idx);
+    DeviceGuard dg(idx->device);
+    JoinContext& c = index_ctx(idx);
+    hipStream_t s = nullptr;
+    KNN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    try {
+      build_level(*idx, c, cell_width, s);
+      const int64_t N = idx->N, M = c.M, R = pow3(idx->n - 1);
+      if (sorted_keys)
+        KNN_HIP(hipMemcpyAsync(sorted_keys, c.keys.p, N * 8, hipMemcpyDeviceToHost, s));
+      if (perm) KNN_HIP(hipMemcpyAsync(perm, c.perm.p, N * 4, hipMemcpyDeviceToHost, s));
+      if (cell_keys) KNN_HIP(hipMemcpyAsync(cell_keys, c.cell_key.p, M * 8, hipMemcpyDeviceToHost, s));
+      if (cell_start)
+        KNN_HIP(hipMemcpyAsync(cell_start, c.cell_start.p, (M + 1) * 4, hipMemcpyDeviceToHost, s));
+      if (ranges)
+        KNN_HIP(hipMemcpyAsync(ranges, c.ranges.p, M * R * 2 * 4, hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));
+      if (grid_dims)
+        for (int j = 0; j < idx->n; ++j) grid_dims[j] = c.gg.g[j];
+      if (n_cells) *n_cells = M;
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+      throw;
+    }
+    KNN_HIP(hipStreamDestroy(s));
+  });
+}
+
+int knn_sample_mean_dist(const double* d_D, int64_t n_points, int32_t dims,
+                         const int64_t* d_sample, int64_t ns, double* mean, void* stream) {
+  return guarded([&] {
+    KNN_CHECK(d_D && d_sample && mean, KNN_EINVAL, "NULL pointer");
+    KNN_CHECK(dims >= 1 && dims <= KNN_MAX_DIMS && n_points >= 1 && ns >= 0, KNN_EINVAL,
+              "bad sizes");
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<double> X((size_t)n_points * dims);
+    DevBuf<uint32_t> bad(1);
+    KNN_HIP(hipMemsetAsync(bad.p, 0, 4, s));
+    launch_aos_to_soa(d_D, n_points, dims, X.p, bad.p, s);
+    DevBuf<double> part(std::max<int64_t>(ns, 1));
+    int np = launch_sample_pair_sums(X.p, n_points, dims, d_sample, ns, part.p, s);
+    std::vector<double> hp(np);
+    if (np) KNN_HIP(hipMemcpyAsync(hp.data(), part.p, np * 8, hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    double sum = 0;
+    for (double v : hp) sum += v;
+    double pairs = (double)ns * (double)(ns - 1) / 2.0;
+    *mean = pairs > 0 ? sum / pairs : 0.0;
+  });
+}
+
+int knn_dist_histogram(const double* d_D, int64_t n_points, int32_t dims, const int64_t* d_sample,
+                       int64_t ns, double inv_bin_width, int32_t n_bins, uint64_t* d_counts,
+                       void* stream) {
+  return guarded([&] {
+    KNN_CHECK(d_D && d_sample && d_counts, KNN_EINVAL, "NULL pointer");
+    KNN_CHECK(dims >= 1 && dims <= KNN_MAX_DIMS && n_points >= 1 && ns >= 0, KNN_EINVAL,
+              "bad sizes");
+    KNN_CHECK(inv_bin_width > 0 && std::isfinite(inv_bin_width), KNN_EINVAL,
+              "inv_bin_width must be > 0");
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf<double> X((size_t)n_points * dims);
+    DevBuf<uint32_t> bad(1);
+    KNN_HIP(hipMemsetAsync(bad.p, 0, 4, s));
+    launch_aos_to_soa(d_D, n_points, dims, X.p, bad.p, s);
+    launch_dist_histogram(X.p, n_points, dims, d_sample, ns, inv_bin_width, n_bins, d_counts, s);
+    KNN_HIP(hipStreamSynchronize(s));  // X is freed on return
+  });
+}
+
+}  // extern "C"

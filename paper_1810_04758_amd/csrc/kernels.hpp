@@ -1,0 +1,125 @@
+// kernels.hpp -- host-side launchers of the HIP kernels (gfx950).
+#pragma once
+
+#include "common.hpp"
+
+namespace knn {
+
+constexpr int kMaxDims = KNN_MAX_DIMS;
+
+// Geometry of one grid level (Sec. 3.1): cell side 1/inv_w, origin lo.
+struct GridGeom {
+  int32_t dims;
+  double lo[kMaxDims];
+  double inv_w;
+  int64_t g[kMaxDims];        // cells per dimension
+  uint64_t stride[kMaxDims];  // key stride per dimension (last = 1)
+  int32_t key_bits;           // bits of the largest key
+  int64_t g_max;
+};
+
+// ---- elementwise / reductions (grid.hip) ----
+// Row-major N x n (AoS) -> SoA X[j*N + i]; counts non-finite coordinates into *bad.
+void launch_aos_to_soa(const double* D, int64_t N, int n, double* X, uint32_t* bad,
+                       hipStream_t s);
+// Per-dimension min/max of SoA X into lo[n], hi[n] (device).  part: scratch of
+// at least 2*n*kBoundsBlocks doubles.
+constexpr int kBoundsBlocks = 512;
+void launch_bounds(const double* X, int64_t N, int n, double* part, double* lo, double* hi,
+                   hipStream_t s);
+
+// ---- scan (grid.hip) ----
+// Exclusive scan of n uint32 values (out may equal in).  If total != nullptr the
+// sum of all values is written there (device).  tmp: scan_tmp_elems(n) uint32.
+size_t scan_tmp_elems(int64_t n);
+void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
+                           uint32_t* tmp, hipStream_t s);
+
+// ---- radix sort (grid.hip) ----
+// Stable LSD sort of (key, val) pairs by the low `bits` bits of the keys.
+// keys/vals hold the input and receive the output; keys2/vals2 are same-size
+// scratch; tmp: radix_tmp_elems(n) uint32.
+size_t radix_tmp_elems(int64_t n);
+void radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
+                      int64_t n, int bits, uint32_t* tmp, hipStream_t s);
+
+// ---- grid level construction (grid.hip) ----
+// keys[i] = cell key of point i (original order, SoA X); vals[i] = i.
+void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* keys,
+                      int32_t* vals, hipStream_t s);
+// From sorted keys: flags -> scan -> cell table.  cell_of (N), cell_key (N),
+// cell_start (N+1), d_M (device scalar) written.  tmp: scan tmp.
+void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags,
+                      uint32_t* cell_of, uint64_t* cell_key, uint32_t* cell_start,
+                      uint32_t* d_M, uint32_t* tmp, hipStream_t s);
+// Xs[j*N + p] = X[j*N + perm[p]]
+void launch_gather_soa(const double* X, const int32_t* perm, int64_t N, int n, double* Xs,
+                       hipStream_t s);
+// Dense key -> cell lookup table (table_size entries, set to ~0 where empty).
+void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N,
+                        uint32_t* table, int64_t table_size, hipStream_t s);
+// Row-segment neighbour ranges of every cell (3^(n-1) per cell) and the
+// candidate count per cell (sum of range lengths).
+void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_start,
+                            const uint64_t* cell_key, const uint32_t* d_M,
+                            const uint32_t* dense /*nullable*/, const GridGeom& gg,
+                            uint32_t* ranges, uint32_t* cand_count, hipStream_t s);
+
+// ---- work items (grid.hip) ----
+// est[i] = sum over the queries of item i (G consecutive active slots) of the
+// candidate count of their cell; keys for a descending stable sort.
+void launch_item_keys(const int32_t* active /*nullable: identity*/, int64_t n_active,
+                      int G, const uint32_t* cell_of, const uint32_t* cand_count,
+                      uint64_t* keys, int32_t* vals, int64_t n_items, hipStream_t s);
+// flags[p] = failed[perm[p]] for the next level's active list.
+void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count,
+                        int64_t max_fail, uint8_t* failed, hipStream_t s);
+void launch_failed_flags(const uint8_t* failed, const int32_t* perm, int64_t N,
+                         uint32_t* flags, hipStream_t s);
+void launch_compact_positions(const uint32_t* flags, const uint32_t* ex, int64_t N,
+                              int32_t* out, hipStream_t s);
+
+// ---- search-distance sampling (eps.hip) ----
+// Partial sums of pair distances inside the sample: one double per block of
+// rows; returns the number of partials written to part (host reads them).
+int launch_sample_pair_sums(const double* X, int64_t N, int n, const int64_t* sample,
+                            int64_t ns, double* part, hipStream_t s);
+void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sample,
+                           int64_t ns, double inv_bw, int n_bins, uint64_t* counts,
+                           hipStream_t s);
+
+// ---- search (search.hip) ----
+struct SearchArgs {
+  const double* Xs;        // SoA sorted coordinates, Xs[j*N + p]
+  int64_t N;
+  const int32_t* perm;     // sorted position -> point id
+  const uint32_t* cell_of; // sorted position -> cell
+  const uint32_t* ranges;  // cell*R*2 row-segment ranges
+  const int32_t* active;   // active sorted positions (nullptr: identity)
+  int64_t n_active;
+  const int32_t* order;    // item order (nullptr: identity)
+  int64_t n_items;
+  int64_t item_base;       // first item of this launch (schedule 1)
+  int32_t* head;           // persistent work-queue head (device)
+  int32_t persistent;
+  double lo[kMaxDims];
+  double inv_w;
+  int64_t g[kMaxDims];
+  double margin;           // relative shrink of the covered radius (rounding)
+  double thr_frac[4];      // count-pass thresholds as fractions of r^2
+  int32_t K;
+  int32_t cap;             // per-query survivor buffer entries (>= K)
+  int32_t* out_ids;        // N x K, row = point id
+  double* out_d;
+  int32_t* fail_list;      // point ids of failed queries
+  int32_t* fail_count;
+  int32_t* refine_count;   // diagnostics: refinement rounds executed
+};
+// Returns the number of waves per block used.
+void launch_search(const SearchArgs& a, int dims, int lanes_per_query, int grid_blocks,
+                   hipStream_t s);
+// Dynamic LDS bytes per wave for a given (lanes_per_query, cap).
+size_t search_lds_per_wave(int lanes_per_query, int cap);
+int search_waves_per_block(int lanes_per_query, int cap);
+
+}  // namespace knn

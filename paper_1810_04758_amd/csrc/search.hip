@@ -1,0 +1,412 @@
+// search.hip -- the grid KNN search kernel (GPUJoinKernel of Alg. 1, with the
+// per-query top-K selection done on the device instead of the host filter).
+//
+// One wavefront takes one work item: G = 64/T consecutive active queries (in
+// cell order), T lanes per query (the paper's t threads per point, Sec. 4.7).
+// For each query:
+//   1. Candidates are the points of the 3^n adjacent cells, read as 3^(n-1)
+//      contiguous row segments of the cell-sorted SoA coordinates.
+//   2. Count pass: every candidate's squared distance (summed left to right,
+//      every operation rounded) goes through a monotone bin function into a
+//      per-query LDS histogram of NB bins covering [0, r^2], where r is the
+//      radius that the scanned cells provably cover.  Fewer than K candidates
+//      within r^2 means the K nearest cannot be proven from these cells: the
+//      query fails and is re-queued for a larger cell side (Alg. 1,
+//      findFailedPnts / addFailuresToWorkQueue).
+//   3. The first bin whose cumulative count reaches K selects the survivors
+//      (every candidate whose bin is not above it).  Since the bin function is
+//      monotone in d^2, the survivors are exactly the candidates below some
+//      squared distance, so they contain the K nearest.  If that bin would
+//      overflow the per-query buffer (cap), an exact bisection on the key
+//      (d^2, id) narrows it first.
+//   4. Collect pass: survivors (d^2, id) go to the per-query LDS buffer.
+//   5. Rank pass: each survivor's rank among the survivors in (d^2, id) order
+//      is counted; ranks below K are written to the query's output row.
+//
+// Exactness of the success test: a point outside the scanned cells differs
+// from the query by at least 1 + m cell coordinates in some dimension
+// (m = distance of the query to its own cell's nearest face, in cells), which
+// in coordinates is at least (1 + m)/inv_w minus rounding; r^2 is that
+// radius shrunk by a margin that covers every rounding of the cell
+// coordinates and of the squared distance.  So every unscanned point has a
+// computed d^2 > r^2 and cannot precede a survivor.
+#pragma clang fp contract(off)
+
+#include <climits>
+
+#include "kernels.hpp"
+
+namespace knn {
+
+namespace {
+
+constexpr int NB = 32;  // histogram bins of the count pass
+
+template <int D>
+struct Pow3 {
+  static constexpr int v = 3 * Pow3<D - 1>::v;
+};
+template <>
+struct Pow3<0> {
+  static constexpr int v = 1;
+};
+
+template <int DIM>
+__device__ __forceinline__ double sq_dist(const double* __restrict__ Xs, int64_t N, int64_t p,
+                                          const double (&q)[DIM]) {
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    double t = __dsub_rn(Xs[(int64_t)j * N + p], q[j]);
+    s = __dadd_rn(s, __dmul_rn(t, t));
+  }
+  return s;
+}
+
+// Monotone bin of a squared distance: 0..NB-1 for d2 <= thr, NB above it.
+__device__ __forceinline__ int bin_of(double d2, double thr, double scale) {
+  double f = __dmul_rn(d2, scale);
+  f = fmin(fmax(f, 0.0), (double)(NB - 1));
+  int b = (int)f;
+  return d2 > thr ? NB : b;
+}
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int T>
+__device__ __forceinline__ int group_sum(int v) {
+#pragma unroll
+  for (int o = 1; o < T; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <int T>
+__device__ __forceinline__ double group_min(double v) {
+#pragma unroll
+  for (int o = 1; o < T; o <<= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+template <int T>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+  for (int o = 1; o < T; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int DIM, int T>
+__global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
+  constexpr int G = 64 / T;      // queries per wave
+  constexpr int R = Pow3<DIM - 1>::v;
+  extern __shared__ double smem[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int g = lane / T;
+  const int l = lane % T;
+  const int cap = a.cap;
+  const int64_t N = a.N;
+  const double* __restrict__ Xs = a.Xs;
+  const int32_t* __restrict__ perm = a.perm;
+
+  // per-wave LDS: survivors d2 [cap][G], survivor ids [cap][G], histogram [NB][G]
+  double* bd = smem + (size_t)wave * cap * G;
+  int32_t* bi = reinterpret_cast<int32_t*>(smem + (size_t)nwaves * cap * G) + (size_t)wave * cap * G;
+  uint32_t* hist = reinterpret_cast<uint32_t*>(reinterpret_cast<int32_t*>(smem + (size_t)nwaves * cap * G) +
+                                               (size_t)nwaves * cap * G) +
+                   (size_t)wave * NB * G;
+
+  const uint64_t lane_lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const uint64_t gmask = (T == 64) ? ~0ull : (((1ull << T) - 1ull) << (g * T));
+
+  bool first = true;
+  for (;;) {
+    int64_t item;
+    if (a.persistent) {
+      int v = 0;
+      if (lane == 0) v = atomicAdd(a.head, 1);
+      item = __shfl(v, 0, 64);
+    } else {
+      if (!first) break;
+      item = a.item_base + (int64_t)blockIdx.x * nwaves + wave;
+    }
+    first = false;
+    if (item >= a.n_items) break;
+    const int64_t it = a.order ? (int64_t)a.order[item] : item;
+    const int64_t slot = it * G + g;
+    const bool valid = slot < a.n_active;
+    const int64_t q = valid ? (a.active ? (int64_t)a.active[slot] : slot) : 0;
+
+    // ---- query point, covered radius ---------------------------------------
+    double qx[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) qx[j] = Xs[(int64_t)j * N + q];
+    const uint32_t cell = a.cell_of[q];
+    double mfrac = 0.5;
+    bool full = true;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      double u = __dmul_rn(__dsub_rn(qx[j], a.lo[j]), a.inv_w);
+      double fl = floor(u);
+      double fr = u - fl;  // exact
+      mfrac = fmin(mfrac, fmin(fr, 1.0 - fr));
+      int64_t c = (int64_t)fl;
+      if (c > 1 || c < a.g[j] - 2) full = false;
+    }
+    double thr, scale;
+    if (full) {
+      // the scanned cells hold every point: all candidates count
+      thr = INFINITY;
+      double w = 1.0 / a.inv_w;
+      scale = (double)NB / (9.0 * DIM * w * w);
+    } else {
+      double base = (1.0 + mfrac) / a.inv_w;
+      double r = base * (1.0 - a.margin);
+      thr = r * r;
+      scale = (double)NB / thr;
+    }
+
+    // ---- count pass ----------------------------------------------------------
+    for (int b = l; b < NB; b += T) hist[b * G + g] = 0;
+    wave_fence();
+    const uint32_t* rg = a.ranges + (size_t)cell * R * 2;
+    for (int r = 0; r < R; ++r) {
+      const uint32_t s = valid ? rg[2 * r] : 0u;
+      const uint32_t e = valid ? rg[2 * r + 1] : 0u;
+      for (uint32_t p0 = s; p0 < e; p0 += T) {
+        const uint32_t p = p0 + l;
+        if (p < e && (int64_t)p != q) {
+          double d2 = sq_dist<DIM>(Xs, N, p, qx);
+          int b = bin_of(d2, thr, scale);
+          if (b < NB) atomicAdd(&hist[b * G + g], 1u);
+        }
+      }
+    }
+    wave_fence();
+    // cumulative counts (every lane of the group reads the same bins)
+    int bsel = NB, c_lo = 0, c_hi = 0;
+    {
+      int cum = 0;
+      for (int b = 0; b < NB; ++b) {
+        int h = (int)hist[b * G + g];
+        if (bsel == NB && cum + h >= a.K) {
+          bsel = b;
+          c_lo = cum;
+          c_hi = cum + h;
+        }
+        cum += h;
+      }
+    }
+    const bool fail = valid && bsel == NB;
+    const bool ok = valid && bsel < NB;
+
+    // ---- failures: re-queue (wave-aggregated append) ----------------------------
+    {
+      const bool lf = fail && l == 0;
+      const uint64_t fm = __ballot(lf);
+      if (fm) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(a.fail_count, (int)__popcll(fm));
+        base = __shfl(base, 0, 64);
+        if (lf) a.fail_list[base + (int)__popcll(fm & lane_lt)] = perm[q];
+      }
+    }
+
+    // ---- exact refinement when the selected bin overflows the buffer -------
+    // Keys are (d2 bits, id) as 96-bit integers; [A, B] is an inclusive key
+    // interval with c_lo keys below A and c_hi keys up to B, c_lo < K <= c_hi.
+    bool refine = ok && c_hi > cap;
+    const bool refined = refine;
+    unsigned __int128 B = 0;  // final threshold when refined
+    if (__ballot(refine)) {
+      // exact value bounds of the selected bin
+      double dmin = INFINITY, dmax = -INFINITY;
+      for (int r = 0; r < R; ++r) {
+        const uint32_t s = refine ? rg[2 * r] : 0u;
+        const uint32_t e = refine ? rg[2 * r + 1] : 0u;
+        for (uint32_t p0 = s; p0 < e; p0 += T) {
+          const uint32_t p = p0 + l;
+          if (p < e && (int64_t)p != q) {
+            double d2 = sq_dist<DIM>(Xs, N, p, qx);
+            if (bin_of(d2, thr, scale) == bsel) {
+              dmin = fmin(dmin, d2);
+              dmax = fmax(dmax, d2);
+            }
+          }
+        }
+      }
+      dmin = group_min<T>(dmin);
+      dmax = group_max<T>(dmax);
+      unsigned __int128 A = 0;
+      if (refine) {
+        A = (unsigned __int128)(uint64_t)__double_as_longlong(dmin) << 32;
+        B = ((unsigned __int128)(uint64_t)__double_as_longlong(dmax) << 32) | 0xFFFFFFFFu;
+      }
+      int rounds = 0;
+      while (__ballot(refine)) {
+        ++rounds;
+        unsigned __int128 t[4] = {0, 0, 0, 0};
+        if (refine) {
+          const unsigned __int128 span = B - A + 1;
+          const unsigned __int128 step = span / 4;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (i == 3)
+              t[i] = B;
+            else if (step == 0)
+              t[i] = (A + (unsigned __int128)i < B) ? A + (unsigned __int128)i : B;
+            else
+              t[i] = A - 1 + step * (unsigned __int128)(i + 1);
+          }
+        }
+        const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
+        int cnt[4] = {0, 0, 0, 0};
+        for (int r = 0; r < R; ++r) {
+          const uint32_t s = refine ? rg[2 * r] : 0u;
+          const uint32_t e = refine ? rg[2 * r + 1] : 0u;
+          for (uint32_t p0 = s; p0 < e; p0 += T) {
+            const uint32_t p = p0 + l;
+            if (p < e && (int64_t)p != q) {
+              double d2 = sq_dist<DIM>(Xs, N, p, qx);
+              const uint64_t kh = (uint64_t)__double_as_longlong(d2);
+              if (kh >= ahi && kh <= bhi) {
+                const unsigned __int128 k = ((unsigned __int128)kh << 32) | (uint32_t)perm[p];
+                if (k >= A) {
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) cnt[i] += (k <= t[i]) ? 1 : 0;
+                }
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cnt[i] = group_sum<T>(cnt[i]);
+        if (refine) {
+          int i = 0;
+          while (i < 3 && c_lo + cnt[i] < a.K) ++i;
+          const int nchi = c_lo + cnt[i];
+          if (i > 0) {
+            A = t[i - 1] + 1;
+            c_lo = c_lo + cnt[i - 1];
+          }
+          B = t[i];
+          c_hi = nchi;
+          if (c_hi <= cap) refine = false;
+        }
+      }
+      if (l == 0 && refined && a.refine_count) atomicAdd(a.refine_count, rounds);
+    }
+    const double th_d = __longlong_as_double((long long)(uint64_t)(B >> 32));
+    const uint32_t th_id = (uint32_t)(B & 0xFFFFFFFFu);
+
+    // ---- collect pass --------------------------------------------------------
+    int nsurv = 0;
+    for (int r = 0; r < R; ++r) {
+      const uint32_t s = ok ? rg[2 * r] : 0u;
+      const uint32_t e = ok ? rg[2 * r + 1] : 0u;
+      for (uint32_t p0 = s; p0 < e; p0 += T) {
+        const uint32_t p = p0 + l;
+        bool acc = false;
+        double d2 = 0.0;
+        if (p < e && (int64_t)p != q) {
+          d2 = sq_dist<DIM>(Xs, N, p, qx);
+          if (refined)
+            acc = d2 < th_d || (d2 == th_d && (th_id == 0xFFFFFFFFu || (uint32_t)perm[p] <= th_id));
+          else
+            acc = bin_of(d2, thr, scale) <= bsel;
+        }
+        if (T == 1) {
+          if (acc) {
+            if (nsurv < cap) {
+              bd[nsurv * G + g] = d2;
+              bi[nsurv * G + g] = perm[p];
+            }
+            ++nsurv;
+          }
+        } else {
+          const uint64_t m = __ballot(acc) & gmask;
+          if (acc) {
+            int slot = nsurv + (int)__popcll(m & lane_lt);
+            if (slot < cap) {
+              bd[slot * G + g] = d2;
+              bi[slot * G + g] = perm[p];
+            }
+          }
+          nsurv += (int)__popcll(m);
+        }
+      }
+    }
+    wave_fence();
+
+    // ---- rank pass -> output row ----------------------------------------------
+    const int c = nsurv < cap ? nsurv : cap;
+    const int64_t row = ok ? (int64_t)perm[q] : 0;
+    const int K = a.K;
+    for (int a0 = 0; a0 < c; a0 += T) {
+      const int ai = a0 + l;
+      if (ai < c) {
+        const double da = bd[ai * G + g];
+        const int32_t ia = bi[ai * G + g];
+        int rank = 0;
+        for (int b2 = 0; b2 < c; ++b2) {
+          const double db = bd[b2 * G + g];
+          const int32_t ib = bi[b2 * G + g];
+          rank += (db < da || (db == da && ib < ia)) ? 1 : 0;
+        }
+        if (rank < K) {
+          a.out_ids[row * K + rank] = ia;
+          a.out_d[row * K + rank] = sqrt(da);
+        }
+      }
+    }
+    wave_fence();
+  }
+}
+
+template <int DIM>
+void launch_dim(const SearchArgs& a, int T, int blocks, int threads, size_t lds, hipStream_t s) {
+  switch (T) {
+    case 1: k_search<DIM, 1><<<blocks, threads, lds, s>>>(a); break;
+    case 2: k_search<DIM, 2><<<blocks, threads, lds, s>>>(a); break;
+    case 4: k_search<DIM, 4><<<blocks, threads, lds, s>>>(a); break;
+    case 8: k_search<DIM, 8><<<blocks, threads, lds, s>>>(a); break;
+    case 16: k_search<DIM, 16><<<blocks, threads, lds, s>>>(a); break;
+    case 32: k_search<DIM, 32><<<blocks, threads, lds, s>>>(a); break;
+    case 64: k_search<DIM, 64><<<blocks, threads, lds, s>>>(a); break;
+    default: throw Error(KNN_EINVAL, "lanes_per_query must be a power of two in [1, 64]");
+  }
+}
+
+}  // namespace
+
+size_t search_lds_per_wave(int T, int cap) {
+  const int G = 64 / T;
+  return (size_t)cap * G * (sizeof(double) + sizeof(int32_t)) + (size_t)NB * G * sizeof(uint32_t);
+}
+
+int search_waves_per_block(int T, int cap) {
+  size_t per = search_lds_per_wave(T, cap);
+  int w = (int)(65536 / per);
+  if (w > 4) w = 4;
+  if (w < 1) w = 1;
+  return w;
+}
+
+void launch_search(const SearchArgs& a, int dims, int T, int grid_blocks, hipStream_t s) {
+  const int waves = search_waves_per_block(T, a.cap);
+  const size_t lds = search_lds_per_wave(T, a.cap) * waves;
+  KNN_CHECK(lds <= 65536, KNN_EINVAL, "K too large for the per-query buffers");
+  const int threads = waves * 64;
+  switch (dims) {
+    case 2: launch_dim<2>(a, T, grid_blocks, threads, lds, s); break;
+    case 3: launch_dim<3>(a, T, grid_blocks, threads, lds, s); break;
+    case 4: launch_dim<4>(a, T, grid_blocks, threads, lds, s); break;
+    case 5: launch_dim<5>(a, T, grid_blocks, threads, lds, s); break;
+    case 6: launch_dim<6>(a, T, grid_blocks, threads, lds, s); break;
+    default: throw Error(KNN_EINVAL, "dims out of range");
+  }
+  KNN_LAUNCHED();
+}
+
+}  // namespace knn

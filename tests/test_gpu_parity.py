@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Neighbour ids must be identical and distances bit-identical (0 ulp): both
+sides sum the squared distance left to right with every operation rounded
+and take a correctly rounded square root.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1810_04758_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def knn():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_04758_amd import api
+    api.load()
+    return api
+
+
+def _check_rows(D, ids, dists, K, rows, oracle_mod):
+    ref_ids, ref_d = oracle_mod.knn(D, K, rows=rows)
+    got_ids = ids[rows]
+    got_d = dists[rows]
+    bad = np.nonzero((got_ids != ref_ids).any(axis=1) | (got_d != ref_d).any(axis=1))[0]
+    assert bad.size == 0, (f"{bad.size} rows differ; first row {rows[bad[0]]}: "
+                           f"got {got_ids[bad[0]].tolist()} {got_d[bad[0]].tolist()} "
+                           f"want {ref_ids[bad[0]].tolist()} {ref_d[bad[0]].tolist()}")
+
+
+def _join(knn, D, K, device_input=True, **opts):
+    import torch
+    if device_input:
+        idx = knn.build_index(torch.from_numpy(D).cuda())
+    else:
+        idx = knn.build_index(D)
+    ids, dists, st = idx.self_join(K, with_stats=True, **opts)
+    torch.cuda.synchronize()
+    out = ids.cpu().numpy(), dists.cpu().numpy(), st
+    idx.close()
+    return out
+
+
+CASES = [
+    # (name, generator, N, n, K)
+    ("unif2d", lambda: datagen.uniform(3001, 2, seed=21), 3001, 2, 5),
+    ("unif3d", lambda: datagen.uniform(2999, 3, seed=22), 2999, 3, 8),
+    ("expo4d", lambda: datagen.exponential(4099, 4, seed=23), 4099, 4, 16),
+    ("unif5d", lambda: datagen.uniform(2050, 5, seed=24), 2050, 5, 3),
+    ("unif6d", lambda: datagen.uniform(3000, 6, seed=25), 3000, 6, 32),
+    ("clus2d", lambda: datagen.clustered(5003, seed=26), 5003, 2, 16),
+    ("expo2d_k64", lambda: datagen.exponential(4001, 2, seed=27), 4001, 2, 64),
+    ("expo2d_k1", lambda: datagen.exponential(4001, 2, seed=28), 4001, 2, 1),
+]
+
+
+@pytest.mark.parametrize("name,gen,N,n,K", CASES, ids=[c[0] for c in CASES])
+def test_parity_full(knn, oracle_mod, name, gen, N, n, K):
+    D = gen()
+    _say(f"[parity_full] {name} N={N} n={n} K={K}")
+    ids, dists, st = _join(knn, D, K)
+    _check_rows(D, ids, dists, K, np.arange(N), oracle_mod)
+    assert st["total_failed"] <= st["total_attempted"]
+
+
+def test_parity_host_entry_point(knn, oracle_mod):
+    D = datagen.exponential(2500, 3, seed=31)
+    _say("[parity_host] knn_build_index + knn_self_join N=2500 n=3 K=7")
+    idx = knn.build_index(D)
+    ids, dists = idx.self_join_host(7)
+    idx.close()
+    _check_rows(D, ids, dists, 7, np.arange(2500), oracle_mod)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+def test_lanes_per_query(knn, oracle_mod, lanes):
+    D = datagen.exponential(3333, 2, seed=32)
+    _say(f"[lanes] T={lanes}")
+    ids, dists, _ = _join(knn, D, 12, lanes_per_query=lanes)
+    _check_rows(D, ids, dists, 12, np.arange(3333), oracle_mod)
+
+
+@pytest.mark.parametrize("wf", [0.25, 0.5, 1.0, 2.0, 4.0])
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_w_factor_and_schedule_metamorphic(knn, oracle_mod, wf, schedule):
+    # the result may not depend on the cell side or the schedule (Sec. 5,
+    # sensitivity to the initial eps, factors 0.25x..4x)
+    D = datagen.uniform(2777, 4, seed=33)
+    _say(f"[w_factor] wf={wf} schedule={schedule}")
+    ids, dists, st = _join(knn, D, 9, w_factor=wf, schedule=schedule, batch_queries=640)
+    _check_rows(D, ids, dists, 9, np.arange(2777), oracle_mod)
+    if wf <= 0.25:
+        assert st["levels"] > 1  # forced failures and re-indexing ran
+
+
+def test_figures_through_gpu(knn, oracle_mod):
+    for name in ("fig_eps_expansion.json", "fig_work_example.json"):
+        g = json.load(open(os.path.join(GOLDEN, name)))
+        panels = g["panels"].values() if "panels" in g else [g]
+        for p in panels:
+            D = np.array(p["points"], dtype=np.float64)
+            K = D.shape[0] - 1
+            _say(f"[figure] {name} N={D.shape[0]} K={K}")
+            ids, dists, _ = _join(knn, D, K)
+            _check_rows(D, ids, dists, K, np.arange(D.shape[0]), oracle_mod)
+            kk = len(p["knn_ids_of_query"])
+            assert ids[0, :kk].tolist() == p["knn_ids_of_query"]
+
+
+@pytest.mark.parametrize("case", ["dups", "all_same", "n2", "lattice", "kmax", "line"])
+def test_edge_cases(knn, oracle_mod, case):
+    if case == "dups":
+        base = datagen.uniform(300, 2, seed=40)
+        D = np.concatenate([base] * 7)  # every point 7 times
+        K = 10
+    elif case == "all_same":
+        D = np.full((500, 3), 1.25)
+        K = 17
+    elif case == "n2":
+        D = np.array([[0.0, 0.0], [1.0, 2.0]])
+        K = 1
+    elif case == "lattice":
+        D = datagen.lattice(12, 2)
+        K = 12
+    elif case == "kmax":
+        D = datagen.uniform(300, 2, seed=41)
+        K = 299
+    else:  # all points on a line (zero extent in one dimension)
+        D = np.zeros((1000, 2))
+        D[:, 0] = np.linspace(0, 1, 1000) ** 2
+        K = 6
+    _say(f"[edge] {case} N={D.shape[0]} K={K}")
+    ids, dists, _ = _join(knn, D, K)
+    _check_rows(D, ids, dists, K, np.arange(D.shape[0]), oracle_mod)
+
+
+def test_invalid_arguments(knn):
+    import torch
+    from paper_1810_04758_amd._lib import KnnError, KNN_EINVAL
+    with pytest.raises(KnnError) as e:
+        knn.build_index(np.zeros((10, 7)))
+    assert e.value.code == KNN_EINVAL
+    bad = datagen.uniform(100, 2, seed=1)
+    bad[5, 1] = np.nan
+    with pytest.raises(KnnError):
+        knn.build_index(torch.from_numpy(bad).cuda())
+    idx = knn.build_index(datagen.uniform(100, 2, seed=1))
+    with pytest.raises(KnnError):
+        idx.self_join(100)
+    with pytest.raises(KnnError):
+        idx.self_join(0)
+    with pytest.raises(KnnError):
+        idx.self_join(5, lanes_per_query=3)
+    idx.close()
+
+
+def test_grid_export_matches_oracle(knn, oracle_mod):
+    for n, gen, w in ((2, lambda: datagen.exponential(5000, 2, seed=50), 0.01),
+                      (4, lambda: datagen.uniform(4000, 4, seed=51), 17.0),
+                      (6, lambda: datagen.uniform(3000, 6, seed=52), 30.0)):
+        D = gen()
+        _say(f"[grid_export] n={n} w={w}")
+        idx = knn.build_index(D)
+        got = idx.grid_export(w)
+        idx.close()
+        ref = oracle_mod.grid(D, 1.0 / w)
+        assert (got["g"] == ref["g"]).all()
+        assert (got["sorted_keys"] == ref["sorted_keys"]).all()
+        assert (got["perm"] == ref["perm"]).all()
+        assert (got["cell_keys"] == ref["cell_keys"]).all()
+        assert (got["cell_start"] == ref["cell_start"]).all()
+        assert (got["ranges"] == ref["ranges"]).all()
+
+
+def test_sampling_kernels_match_oracle(knn, oracle_mod):
+    import torch
+    D = datagen.exponential(20000, 3, seed=60)
+    sample = datagen.sample_ids(20000, 300, seed=61)
+    Dd = torch.from_numpy(D).cuda()
+    sd = torch.from_numpy(sample).cuda()
+    _say("[sampling] mean + histogram")
+    m = knn.sample_mean_dist(Dd, sd)
+    m_ref = oracle_mod.sample_mean_dist(D, sample)
+    assert abs(m - m_ref) <= 1e-12 * m_ref
+    inv_bw = 1000.0 / m_ref
+    counts = knn.dist_histogram(Dd, sd[:50], inv_bw, 1000).cpu().numpy().astype(np.uint64)
+    ref = oracle_mod.dist_histogram(D, sample[:50], inv_bw, 1000)
+    assert (counts == ref).all()
+
+
+def test_eps_min_from_index_matches_rule(knn, oracle_mod):
+    D = datagen.uniform(20000, 2, seed=62)
+    idx = knn.build_index(D)
+    info = idx.info()
+    # eps_min(K) is non-decreasing in K and bounded by eps_mean
+    prev = 0.0
+    for K in (1, 2, 4, 8, 16, 32, 64):
+        e = idx.eps_min(K)
+        assert prev <= e <= info["eps_mean"]
+        prev = e
+    idx.close()
