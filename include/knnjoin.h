@@ -82,7 +82,10 @@ typedef struct knn_join_stats {
   double ms_total;            /* wall time of the whole join */
   int64_t total_attempted;    /* sum of attempted */
   int64_t total_failed;       /* sum of failed: fraction = failed/attempted */
-  int32_t lanes_per_query;    /* t used */
+  int32_t lanes_per_query;    /* t of level 0 */
+  int32_t lanes[KNN_MAX_LEVELS];          /* t used at each level */
+  double cand_per_query[KNN_MAX_LEVELS];  /* mean candidates per active query */
+  int64_t refine_rounds[KNN_MAX_LEVELS];  /* exact-bisection rounds (crowded bins) */
 } knn_join_stats;
 
 /* Options of the join calls.  Zero fields take the defaults in brackets. */

@@ -39,7 +39,9 @@ class JoinStats(ctypes.Structure):
                 ("ms_build", c_f64 * KNN_MAX_LEVELS),
                 ("ms_search", c_f64 * KNN_MAX_LEVELS),
                 ("ms_total", c_f64), ("total_attempted", c_i64), ("total_failed", c_i64),
-                ("lanes_per_query", c_i32)]
+                ("lanes_per_query", c_i32), ("lanes", c_i32 * KNN_MAX_LEVELS),
+                ("cand_per_query", c_f64 * KNN_MAX_LEVELS),
+                ("refine_rounds", c_i64 * KNN_MAX_LEVELS)]
 
     def as_dict(self):
         L = self.levels
@@ -48,7 +50,9 @@ class JoinStats(ctypes.Structure):
                     failed=list(self.failed[:L]), cells=list(self.cells[:L]),
                     ms_build=list(self.ms_build[:L]), ms_search=list(self.ms_search[:L]),
                     ms_total=self.ms_total, total_attempted=self.total_attempted,
-                    total_failed=self.total_failed)
+                    total_failed=self.total_failed, lanes=list(self.lanes[:L]),
+                    cand_per_query=list(self.cand_per_query[:L]),
+                    refine_rounds=list(self.refine_rounds[:L]))
 
 
 class JoinOpts(ctypes.Structure):

@@ -58,11 +58,7 @@ int autotune_lanes(int dims, int K, int64_t N) {
     auto it = g_cache.find(class_of(dims, K, N));
     if (it != g_cache.end() && it->second.lanes > 0) return it->second.lanes;
   }
-  const int cap = K + (K / 4 > 8 ? K / 4 : 8);
-  int T = 1;
-  while (T < 64 && search_lds_per_wave(T, cap) > 16384) T *= 2;
-  const int t_dim = dims <= 2 ? 1 : dims == 3 ? 2 : dims == 4 ? 4 : 8;
-  return T > t_dim ? T : t_dim;
+  return 0;  // no measurement: chosen per level from the candidate counts
 }
 
 double autotune_w_factor(int dims, int K, int64_t N) {

@@ -7,9 +7,8 @@
 
 namespace knn {
 
-// Lanes per query for (dims, K, N): cached measurement, else the smallest
-// power of two that keeps the per-wave LDS buffers within budget, at least
-// the per-dimension default.
+// Lanes per query of level 0 for (dims, K, N): cached measurement, else 0
+// (the join then picks it from the level's candidate counts).
 int autotune_lanes(int dims, int K, int64_t N);
 // Cell side as a multiple of eps_min(K): cached measurement, else 1 (the
 // paper's choice, cell side = eps_min).

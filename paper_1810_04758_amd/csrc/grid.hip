@@ -432,6 +432,25 @@ __global__ void k_item_keys(const int32_t* __restrict__ active, int64_t n_active
   }
 }
 
+__global__ void k_active_cand_sum(const int32_t* __restrict__ active, int64_t n_active,
+                                  const uint32_t* __restrict__ cell_of,
+                                  const uint32_t* __restrict__ cand_count, uint64_t* sum) {
+  __shared__ unsigned long long red[kBlock];
+  unsigned long long s = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_active;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t q = active ? active[i] : i;
+    s += cand_count[cell_of[q]];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd((unsigned long long*)sum, red[0]);
+}
+
 __global__ void k_mark_failed(const int32_t* __restrict__ fail_list, const int32_t* d_count,
                               uint8_t* __restrict__ failed) {
   const int64_t cnt = *d_count;
@@ -595,6 +614,14 @@ void launch_item_keys(const int32_t* active, int64_t n_active, int G, const uint
                       hipStream_t s) {
   k_item_keys<<<grid_for(n_items), kBlock, 0, s>>>(active, n_active, G, cell_of, cand_count,
                                                     keys, vals, n_items);
+  KNN_LAUNCHED();
+}
+
+void launch_active_cand_sum(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
+                            const uint32_t* cand_count, uint64_t* sum, hipStream_t s) {
+  KNN_HIP(hipMemsetAsync(sum, 0, sizeof(uint64_t), s));
+  k_active_cand_sum<<<grid_for(n_active, 1024), kBlock, 0, s>>>(active, n_active, cell_of,
+                                                                 cand_count, sum);
   KNN_LAUNCHED();
 }
 

@@ -227,10 +227,14 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   return b;
 }
 
-static void pick_lanes(const knn_index& idx, int32_t K, int cap, int& T) {
-  if (T > 0) return;
-  T = autotune_lanes(idx.n, K, idx.N);
-  (void)cap;
+// Lanes per query for a level whose active queries see `cand` candidates on
+// average: about 32 candidates per lane, and at least enough lanes that the
+// per-wave LDS buffers stay within 16 KiB.
+static int lanes_for(double cand, int cap) {
+  int T = 1;
+  while (T < 64 && (double)T * 32.0 < cand) T *= 2;
+  while (T < 64 && search_lds_per_wave(T, cap) > 16384) T *= 2;
+  return T;
 }
 
 void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, double* d_dists,
@@ -259,25 +263,21 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   const int linear = o.linear_levels > 0 ? o.linear_levels : (o.linear_levels < 0 ? 0 : 2);
   const double growth = o.growth > 1.0 ? o.growth : 2.0;
 
-  int T = o.lanes_per_query;
+  const int T_fixed = o.lanes_per_query;
+  KNN_CHECK(T_fixed == 0 || (T_fixed >= 1 && T_fixed <= 64 && (T_fixed & (T_fixed - 1)) == 0),
+            KNN_EINVAL, "lanes_per_query must be a power of two in [1, 64]");
+  const int T_tuned = T_fixed > 0 ? 0 : autotune_lanes(idx.n, K, idx.N);
   const int pad = std::max(8, K / 4);
   const int cap = K + pad;
-  pick_lanes(idx, K, cap, T);
-  KNN_CHECK(T >= 1 && T <= 64 && (T & (T - 1)) == 0, KNN_EINVAL,
-            "lanes_per_query must be a power of two in [1, 64]");
-  const int G = 64 / T;
-  if (st) {
-    st->eps_min = eps_min;
-    st->lanes_per_query = T;
-  }
+  if (st) st->eps_min = eps_min;
 
   c.iscal.reserve(4);
   c.scal.reserve(4);
   c.active.reserve(N);
   c.fail_list.reserve(N);
   c.failed.reserve(N);
+  DevBuf<uint64_t> d_cand(1);
   const int ncu = cu_count(c.device);
-  const int waves = search_waves_per_block(T, cap);
 
   Events ev(st != nullptr);
   int64_t A = N;  // active queries
@@ -295,6 +295,20 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       launch_compact_positions(c.flags.p, ex, N, c.active.p, s);
       active = c.active.p;
     }
+    // lanes per query from the level's mean candidate count (the paper's t,
+    // Sec. 4.7, chosen per level: the tail levels see far more candidates)
+    double cand = 0;
+    {
+      launch_active_cand_sum(active, A, c.cell_of.p, c.cand_count.p, d_cand.p, s);
+      uint64_t tot = 0;
+      KNN_HIP(hipMemcpyAsync(&tot, d_cand.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));
+      cand = (double)tot / (double)std::max<int64_t>(A, 1);
+    }
+    int T = T_fixed;
+    if (T == 0) T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(cand, cap);
+    const int G = 64 / T;
+    const int waves = search_waves_per_block(T, cap);
     // work items, densest first (Sec. 4.5 work estimate; persistent schedule)
     const int64_t n_items = ceil_div(A, G);
     const int32_t* order = nullptr;
@@ -352,10 +366,15 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       }
     }
     ev.rec(2, s);
-    int32_t fails = 0;
-    KNN_HIP(hipMemcpyAsync(&fails, c.iscal.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t sc[4] = {0, 0, 0, 0};
+    KNN_HIP(hipMemcpyAsync(sc, c.iscal.p, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     KNN_HIP(hipStreamSynchronize(s));
+    const int32_t fails = sc[1];
     if (st && level < KNN_MAX_LEVELS) {
+      if (level == 0) st->lanes_per_query = T;
+      st->lanes[level] = T;
+      st->cand_per_query[level] = cand;
+      st->refine_rounds[level] = sc[2];
       st->levels = level + 1;
       st->cell_width[level] = 1.0 / c.gg.inv_w;
       st->attempted[level] = A;

@@ -71,6 +71,10 @@ void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_st
 void launch_item_keys(const int32_t* active /*nullable: identity*/, int64_t n_active,
                       int G, const uint32_t* cell_of, const uint32_t* cand_count,
                       uint64_t* keys, int32_t* vals, int64_t n_items, hipStream_t s);
+// *sum += candidate count of the cell of every active query (uint64, device).
+void launch_active_cand_sum(const int32_t* active /*nullable*/, int64_t n_active,
+                            const uint32_t* cell_of, const uint32_t* cand_count, uint64_t* sum,
+                            hipStream_t s);
 // flags[p] = failed[perm[p]] for the next level's active list.
 void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count,
                         int64_t max_fail, uint8_t* failed, hipStream_t s);

@@ -8,8 +8,9 @@
 //      contiguous row segments of the cell-sorted SoA coordinates.
 //   2. Count pass: every candidate's squared distance (summed left to right,
 //      every operation rounded) goes through a monotone bin function into a
-//      per-query LDS histogram of NB bins covering [0, r^2], where r is the
-//      radius that the scanned cells provably cover.  Fewer than K candidates
+//      per-query LDS histogram of NB log-spaced bins (4 per octave of d^2,
+//      read off the exponent and two mantissa bits) ending at r^2, where r
+//      is the radius that the scanned cells provably cover.  Fewer than K candidates
 //      within r^2 means the K nearest cannot be proven from these cells: the
 //      query fails and is re-queued for a larger cell side (Alg. 1,
 //      findFailedPnts / addFailuresToWorkQueue).
@@ -40,7 +41,8 @@ namespace knn {
 
 namespace {
 
-constexpr int NB = 32;  // histogram bins of the count pass
+constexpr int NB = 64;         // histogram bins of the count pass: 16 octaves of d^2
+constexpr int kBinShift = 50;  // exponent + 2 mantissa bits: 4 bins per octave
 
 template <int D>
 struct Pow3 {
@@ -64,10 +66,12 @@ __device__ __forceinline__ double sq_dist(const double* __restrict__ Xs, int64_t
 }
 
 // Monotone bin of a squared distance: 0..NB-1 for d2 <= thr, NB above it.
-__device__ __forceinline__ int bin_of(double d2, double thr, double scale) {
-  double f = __dmul_rn(d2, scale);
-  f = fmin(fmax(f, 0.0), (double)(NB - 1));
-  int b = (int)f;
+// top = (bit pattern of the reference top) >> kBinShift; the bit pattern of a
+// non-negative double is monotone in its value, so the bin is monotone in d2.
+__device__ __forceinline__ int bin_of(double d2, double thr, int64_t top) {
+  const int64_t k =
+      (int64_t)((uint64_t)__double_as_longlong(d2) >> kBinShift) - top + (NB - 1);
+  const int b = k < 0 ? 0 : (k > NB - 1 ? NB - 1 : (int)k);
   return d2 > thr ? NB : b;
 }
 
@@ -154,18 +158,20 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
       int64_t c = (int64_t)fl;
       if (c > 1 || c < a.g[j] - 2) full = false;
     }
-    double thr, scale;
+    double thr, ref;
     if (full) {
-      // the scanned cells hold every point: all candidates count
+      // the scanned cells hold every point: all candidates count; the bins end
+      // at the squared diagonal of the 3^n block
       thr = INFINITY;
       double w = 1.0 / a.inv_w;
-      scale = (double)NB / (9.0 * DIM * w * w);
+      ref = 9.0 * DIM * w * w;
     } else {
       double base = (1.0 + mfrac) / a.inv_w;
       double r = base * (1.0 - a.margin);
       thr = r * r;
-      scale = (double)NB / thr;
+      ref = thr;
     }
+    const int64_t top = (int64_t)((uint64_t)__double_as_longlong(ref) >> kBinShift);
 
     // ---- count pass ----------------------------------------------------------
     for (int b = l; b < NB; b += T) hist[b * G + g] = 0;
@@ -178,7 +184,7 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
         const uint32_t p = p0 + l;
         if (p < e && (int64_t)p != q) {
           double d2 = sq_dist<DIM>(Xs, N, p, qx);
-          int b = bin_of(d2, thr, scale);
+          int b = bin_of(d2, thr, top);
           if (b < NB) atomicAdd(&hist[b * G + g], 1u);
         }
       }
@@ -229,7 +235,7 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
           const uint32_t p = p0 + l;
           if (p < e && (int64_t)p != q) {
             double d2 = sq_dist<DIM>(Xs, N, p, qx);
-            if (bin_of(d2, thr, scale) == bsel) {
+            if (bin_of(d2, thr, top) == bsel) {
               dmin = fmin(dmin, d2);
               dmax = fmax(dmax, d2);
             }
@@ -314,7 +320,7 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
           if (refined)
             acc = d2 < th_d || (d2 == th_d && (th_id == 0xFFFFFFFFu || (uint32_t)perm[p] <= th_id));
           else
-            acc = bin_of(d2, thr, scale) <= bsel;
+            acc = bin_of(d2, thr, top) <= bsel;
         }
         if (T == 1) {
           if (acc) {
