@@ -86,6 +86,9 @@ typedef struct knn_join_stats {
   int32_t lanes[KNN_MAX_LEVELS];          /* t used at each level */
   double cand_per_query[KNN_MAX_LEVELS];  /* mean candidates per active query */
   int64_t refine_rounds[KNN_MAX_LEVELS];  /* exact-bisection rounds (crowded bins) */
+  int64_t tail_queries;       /* queries finished by the brute-force tail */
+  int32_t tail_rounds;        /* its exact-bisection rounds */
+  double ms_tail;             /* its time */
 } knn_join_stats;
 
 /* Options of the join calls.  Zero fields take the defaults in brackets. */
@@ -100,6 +103,8 @@ typedef struct knn_join_opts {
   int32_t linear_levels;  /* linear growths before geometric growth [2] */
   double growth;          /* geometric growth factor of the cell side [2.0] */
   int32_t use_graph;      /* capture the per-level launch sequence in a HIP graph [0] */
+  double tail_pairs;      /* brute-force tail once (remaining queries) x N <= this
+                             [1.5e9]; < 0 disables the tail (Sec. 5.3.8 remedy) */
   knn_join_stats* stats;  /* optional statistics output */
 } knn_join_opts;
 

@@ -41,7 +41,8 @@ class JoinStats(ctypes.Structure):
                 ("ms_total", c_f64), ("total_attempted", c_i64), ("total_failed", c_i64),
                 ("lanes_per_query", c_i32), ("lanes", c_i32 * KNN_MAX_LEVELS),
                 ("cand_per_query", c_f64 * KNN_MAX_LEVELS),
-                ("refine_rounds", c_i64 * KNN_MAX_LEVELS)]
+                ("refine_rounds", c_i64 * KNN_MAX_LEVELS),
+                ("tail_queries", c_i64), ("tail_rounds", c_i32), ("ms_tail", c_f64)]
 
     def as_dict(self):
         L = self.levels
@@ -52,14 +53,16 @@ class JoinStats(ctypes.Structure):
                     ms_total=self.ms_total, total_attempted=self.total_attempted,
                     total_failed=self.total_failed, lanes=list(self.lanes[:L]),
                     cand_per_query=list(self.cand_per_query[:L]),
-                    refine_rounds=list(self.refine_rounds[:L]))
+                    refine_rounds=list(self.refine_rounds[:L]),
+                    tail_queries=self.tail_queries, tail_rounds=self.tail_rounds,
+                    ms_tail=self.ms_tail)
 
 
 class JoinOpts(ctypes.Structure):
     _fields_ = [("w_factor", c_f64), ("cell_width", c_f64), ("lanes_per_query", c_i32),
                 ("schedule", c_i32), ("batch_queries", c_i32), ("eps_step", c_f64),
                 ("linear_levels", c_i32), ("growth", c_f64), ("use_graph", c_i32),
-                ("stats", ctypes.POINTER(JoinStats))]
+                ("tail_pairs", c_f64), ("stats", ctypes.POINTER(JoinStats))]
 
 
 class IndexInfo(ctypes.Structure):

@@ -11,6 +11,7 @@
 
 #include "autotune.hpp"
 #include "index.hpp"
+#include "tail.hpp"
 
 namespace knn {
 
@@ -267,9 +268,12 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   KNN_CHECK(T_fixed == 0 || (T_fixed >= 1 && T_fixed <= 64 && (T_fixed & (T_fixed - 1)) == 0),
             KNN_EINVAL, "lanes_per_query must be a power of two in [1, 64]");
   const int T_tuned = T_fixed > 0 ? 0 : autotune_lanes(idx.n, K, idx.N);
-  const int pad = std::max(8, K / 4);
+  const int pad = std::max(16, K / 2);
   const int cap = K + pad;
   if (st) st->eps_min = eps_min;
+  const double tail_budget = o.tail_pairs > 0 ? o.tail_pairs : (o.tail_pairs < 0 ? -1.0 : 1.5e9);
+  double diag2 = 0;
+  for (int j = 0; j < idx.n; ++j) diag2 += (idx.hi[j] - idx.lo[j]) * (idx.hi[j] - idx.lo[j]);
 
   c.iscal.reserve(4);
   c.scal.reserve(4);
@@ -283,6 +287,34 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   int64_t A = N;  // active queries
   for (int level = 0;; ++level) {
     if (level >= KNN_MAX_LEVELS - 1) w = std::max(w, 2.0 * ext + 1.0);  // everything in one block
+    // brute-force tail once few queries remain (their ids are in fail_list)
+    if (level > 0 && tail_budget > 0 && A <= 65535 && (double)A * (double)N <= tail_budget) {
+      ev.rec(0, s);
+      TailArgs ta{};
+      ta.X = idx.X.p;
+      ta.N = N;
+      ta.n = idx.n;
+      ta.q_ids = c.fail_list.p;
+      ta.A = (int32_t)A;
+      const double top_ref = std::max(diag2, 1e-290);
+      uint64_t tb;
+      std::memcpy(&tb, &top_ref, 8);
+      ta.top = (int64_t)(tb >> 50);
+      ta.K = K;
+      ta.cap = cap;
+      ta.out_ids = d_ids;
+      ta.out_d = d_dists;
+      DevBuf<char> scratch(tail_state_bytes(A, cap));
+      const int rounds = tail_run(ta, scratch.p, s);
+      ev.rec(1, s);
+      KNN_HIP(hipStreamSynchronize(s));
+      if (st) {
+        st->tail_queries = A;
+        st->tail_rounds = rounds;
+        st->ms_tail = elapsed_ms(ev.e[0], ev.e[1]);
+      }
+      break;
+    }
     ev.rec(0, s);
     build_level(idx, c, w, s);
     // active list of this level (cell order): level 0 = every point

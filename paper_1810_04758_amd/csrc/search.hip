@@ -99,6 +99,28 @@ __device__ __forceinline__ double group_max(double v) {
   return v;
 }
 
+template <int T>
+__device__ __forceinline__ int group_incl_scan(int v, int l) {
+#pragma unroll
+  for (int o = 1; o < T; o <<= 1) {
+    int u = __shfl_up(v, o, T);
+    if (l >= o) v += u;
+  }
+  return v;
+}
+template <int T>
+__device__ __forceinline__ int group_min_int(int v) {
+#pragma unroll
+  for (int o = 1; o < T; o <<= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+template <int T>
+__device__ __forceinline__ int group_max_int(int v) {
+#pragma unroll
+  for (int o = 1; o < T; o <<= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 template <int DIM, int T>
 __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
   constexpr int G = 64 / T;      // queries per wave
@@ -122,7 +144,6 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
                    (size_t)wave * NB * G;
 
   const uint64_t lane_lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t gmask = (T == 64) ? ~0ull : (((1ull << T) - 1ull) << (g * T));
 
   bool first = true;
   for (;;) {
@@ -190,19 +211,33 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
       }
     }
     wave_fence();
-    // cumulative counts (every lane of the group reads the same bins)
+    // Selection: lane l of the group owns bins [l*P, (l+1)*P).  A group scan
+    // of the per-lane sums gives every bin's prefix; the first bin whose
+    // cumulative count reaches K is the selected bin, and the histogram is
+    // rewritten in place as exclusive prefixes (bucket starts of the collect).
+    constexpr int P = NB / T;
     int bsel = NB, c_lo = 0, c_hi = 0;
     {
-      int cum = 0;
-      for (int b = 0; b < NB; ++b) {
-        int h = (int)hist[b * G + g];
-        if (bsel == NB && cum + h >= a.K) {
-          bsel = b;
-          c_lo = cum;
-          c_hi = cum + h;
+      uint32_t* hb = hist + (size_t)(l * P) * G + g;
+      int local = 0;
+      for (int i = 0; i < P; ++i) local += (int)hb[i * G];
+      const int incl = group_incl_scan<T>(local, l);
+      const int excl = incl - local;
+      int mb = NB, mlo = 0, mhi = 0;
+      int cum = excl;
+      for (int i = 0; i < P; ++i) {
+        const int h = (int)hb[i * G];
+        if (mb == NB && cum + h >= a.K) {
+          mb = l * P + i;
+          mlo = cum;
+          mhi = cum + h;
         }
+        hb[i * G] = (uint32_t)cum;
         cum += h;
       }
+      bsel = group_min_int<T>(mb);
+      c_lo = group_max_int<T>(mb == bsel ? mlo : 0);
+      c_hi = group_max_int<T>(mb == bsel ? mhi : 0);
     }
     const bool fail = valid && bsel == NB;
     const bool ok = valid && bsel < NB;
@@ -306,63 +341,59 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
     const double th_d = __longlong_as_double((long long)(uint64_t)(B >> 32));
     const uint32_t th_id = (uint32_t)(B & 0xFFFFFFFFu);
 
-    // ---- collect pass --------------------------------------------------------
-    int nsurv = 0;
+    // ---- collect pass: survivors bucketed by bin (counting sort) --------------
+    wave_fence();
     for (int r = 0; r < R; ++r) {
       const uint32_t s = ok ? rg[2 * r] : 0u;
       const uint32_t e = ok ? rg[2 * r + 1] : 0u;
       for (uint32_t p0 = s; p0 < e; p0 += T) {
         const uint32_t p = p0 + l;
-        bool acc = false;
-        double d2 = 0.0;
         if (p < e && (int64_t)p != q) {
-          d2 = sq_dist<DIM>(Xs, N, p, qx);
+          const double d2 = sq_dist<DIM>(Xs, N, p, qx);
+          const int b = bin_of(d2, thr, top);
+          bool acc;
           if (refined)
             acc = d2 < th_d || (d2 == th_d && (th_id == 0xFFFFFFFFu || (uint32_t)perm[p] <= th_id));
           else
-            acc = bin_of(d2, thr, top) <= bsel;
-        }
-        if (T == 1) {
+            acc = b <= bsel;
           if (acc) {
-            if (nsurv < cap) {
-              bd[nsurv * G + g] = d2;
-              bi[nsurv * G + g] = perm[p];
-            }
-            ++nsurv;
-          }
-        } else {
-          const uint64_t m = __ballot(acc) & gmask;
-          if (acc) {
-            int slot = nsurv + (int)__popcll(m & lane_lt);
-            if (slot < cap) {
+            const uint32_t slot = atomicAdd(&hist[b * G + g], 1u);
+            if ((int)slot < cap) {
               bd[slot * G + g] = d2;
               bi[slot * G + g] = perm[p];
             }
           }
-          nsurv += (int)__popcll(m);
         }
       }
     }
     wave_fence();
 
-    // ---- rank pass -> output row ----------------------------------------------
-    const int c = nsurv < cap ? nsurv : cap;
-    const int64_t row = ok ? (int64_t)perm[q] : 0;
+    // ---- rank pass -> output row ------------------------------------------------
+    // After the collect, hist[b] is the end of bucket b, and bucket b starts at
+    // the end of bucket b-1; a survivor's rank is its bucket start plus the
+    // number of bucket mates before it in (d2, id) order.
     const int K = a.K;
+    const int c = ok ? min((int)hist[bsel * G + g], cap) : 0;
+    const int64_t row = ok ? (int64_t)perm[q] : 0;
     for (int a0 = 0; a0 < c; a0 += T) {
       const int ai = a0 + l;
       if (ai < c) {
         const double da = bd[ai * G + g];
         const int32_t ia = bi[ai * G + g];
-        int rank = 0;
-        for (int b2 = 0; b2 < c; ++b2) {
-          const double db = bd[b2 * G + g];
-          const int32_t ib = bi[b2 * G + g];
-          rank += (db < da || (db == da && ib < ia)) ? 1 : 0;
-        }
-        if (rank < K) {
-          a.out_ids[row * K + rank] = ia;
-          a.out_d[row * K + rank] = sqrt(da);
+        const int b = bin_of(da, thr, top);
+        const int start = b > 0 ? (int)hist[(b - 1) * G + g] : 0;
+        if (start < K) {
+          const int end = min((int)hist[b * G + g], cap);
+          int rank = start;
+          for (int s2 = start; s2 < end; ++s2) {
+            const double db = bd[s2 * G + g];
+            const int32_t ib = bi[s2 * G + g];
+            rank += (db < da || (db == da && ib < ia)) ? 1 : 0;
+          }
+          if (rank < K) {
+            a.out_ids[row * K + rank] = ia;
+            a.out_d[row * K + rank] = sqrt(da);
+          }
         }
       }
     }

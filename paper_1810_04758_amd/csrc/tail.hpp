@@ -1,0 +1,40 @@
+// tail.hpp -- brute-force tail of the level loop (few remaining queries
+// against every point, with the whole GPU).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace knn {
+
+struct TailState {
+  unsigned __int128 A, B;  // inclusive (d2 bits, id) key interval while refining
+  unsigned __int128 t[4];  // split points of the current round
+  int32_t bsel, c_lo, c_hi, mode, fill;
+};
+
+struct TailArgs {
+  const double* X;  // SoA coordinates in id order
+  int64_t N;
+  int32_t n;
+  const int32_t* q_ids;  // the tail queries (point ids), A of them
+  int32_t A;
+  int64_t top;  // bit pattern of the squared bounding-box diagonal >> 50
+  int32_t K;
+  int32_t cap;  // per-query survivor buffer entries (>= K)
+  int32_t* out_ids;
+  double* out_d;
+  // carved from the scratch by tail_run
+  TailState* state;
+  uint32_t* hist;
+  uint32_t* cnt;
+  int32_t* flag;
+  double* buf_d;
+  int32_t* buf_i;
+};
+
+// Device scratch bytes tail_run needs for A queries.
+size_t tail_state_bytes(int64_t A, int cap);
+// Runs the whole tail on stream s; returns the number of refinement rounds.
+int tail_run(TailArgs a, char* scratch, hipStream_t s);
+
+}  // namespace knn

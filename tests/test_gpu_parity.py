@@ -106,7 +106,38 @@ def test_w_factor_and_schedule_metamorphic(knn, oracle_mod, wf, schedule):
     ids, dists, st = _join(knn, D, 9, w_factor=wf, schedule=schedule, batch_queries=640)
     _check_rows(D, ids, dists, 9, np.arange(2777), oracle_mod)
     if wf <= 0.25:
-        assert st["levels"] > 1  # forced failures and re-indexing ran
+        assert st["total_failed"] > 0  # forced failures ran
+    # same with the brute-force tail off: failures go through re-indexing only
+    ids2, dists2, st2 = _join(knn, D, 9, w_factor=wf, schedule=schedule, tail_pairs=-1.0)
+    assert (ids2 == ids).all() and (dists2 == dists).all()
+    if wf <= 0.25:
+        assert st2["levels"] > 1 and st2["tail_queries"] == 0
+
+
+@pytest.mark.parametrize("tail", [-1.0, 1e15, 0.0])
+def test_tail_modes(knn, oracle_mod, tail):
+    # brute-force tail disabled / for every failure of level 0 / default budget:
+    # identical results (skewed data with duplicates, K large enough that the
+    # tail's per-query buffers need the exact bisection on ties)
+    base = datagen.exponential(2400, 2, seed=34)
+    D = np.concatenate([base, base[:300], base[:300]])
+    _say(f"[tail] tail_pairs={tail}")
+    ids, dists, st = _join(knn, D, 24, tail_pairs=tail, w_factor=0.5)
+    _check_rows(D, ids, dists, 24, np.arange(D.shape[0]), oracle_mod)
+    if tail == 1e15:
+        assert st["tail_queries"] > 0 and st["levels"] == 1
+    if tail < 0:
+        assert st["tail_queries"] == 0
+
+
+def test_tail_all_duplicates(knn, oracle_mod):
+    # every query in the tail sees all N-1 points at distance 0: the selection
+    # must fall back on ids (exact bisection over the id bits)
+    D = np.full((700, 4), 3.5)
+    D[:10] = datagen.uniform(10, 4, seed=35)
+    _say("[tail] all duplicates")
+    ids, dists, st = _join(knn, D, 40, tail_pairs=1e15, w_factor=0.25)
+    _check_rows(D, ids, dists, 40, np.arange(D.shape[0]), oracle_mod)
 
 
 def test_figures_through_gpu(knn, oracle_mod):
