@@ -340,26 +340,76 @@ __device__ inline uint32_t lower_bound_key(const uint64_t* __restrict__ cell_key
   return lo;
 }
 
-// One thread per (cell, row segment).  The cell's coordinates are recomputed
-// from its first point with the key formula, so no key decoding is needed.
+template <int DIM>
+__device__ inline void range_of(int r, const int64_t (&cc)[DIM],
+                                const uint32_t* __restrict__ cell_start,
+                                const uint64_t* __restrict__ cell_key, uint32_t M,
+                                const uint32_t* __restrict__ dense, const struct GeomDev& gd,
+                                uint32_t& start, uint32_t& end);
+
+// A group of S lanes per cell (S = the power of two >= 3^(n-1), at most 64):
+// lane l computes row segments r = l, l+S, ...; the non-empty ones are written
+// compacted (in r order) with their slot r, their count and the cell's total
+// candidate count.  The cell's coordinates are recomputed from its first
+// point with the key formula, so no key decoding is needed.
 template <int DIM>
 __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
                                   const uint32_t* __restrict__ cell_start,
                                   const uint64_t* __restrict__ cell_key, const uint32_t* d_M,
                                   const uint32_t* __restrict__ dense, GeomDev gd,
-                                  uint32_t* __restrict__ ranges,
+                                  uint32_t* __restrict__ ranges, uint8_t* __restrict__ rslot,
+                                  uint32_t* __restrict__ nrng,
                                   uint32_t* __restrict__ cand_count) {
   constexpr int R = DIM == 2 ? 3 : DIM == 3 ? 9 : DIM == 4 ? 27 : DIM == 5 ? 81 : 243;
+  constexpr int S = R <= 4 ? 4 : R <= 16 ? 16 : R <= 32 ? 32 : 64;
   const uint32_t M = *d_M;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)M * R;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t c = (uint32_t)(e / R);
-    const int r = (int)(e - (int64_t)c * R);
+  const int lane = threadIdx.x & 63;
+  const int l = lane % S;
+  const int sub = lane / S;
+  const uint64_t lt = l == 0 ? 0ull : (~0ull >> (64 - l));
+  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / S);
+  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x / S) + threadIdx.x / S; c < (int64_t)M;
+       c += groups) {
     const uint32_t p0 = cell_start[c];
     int64_t cc[DIM];
 #pragma unroll
     for (int j = 0; j < DIM; ++j) cc[j] = cell_coord(Xs[(int64_t)j * N + p0], gd.lo[j], gd.inv_w);
-    // offsets o_0..o_{DIM-2}, o_0 slowest
+    uint32_t count = 0, cand = 0;
+    for (int rb = 0; rb < R; rb += S) {
+      const int r = rb + l;
+      uint32_t start = 0, end = 0;
+      if (r < R) range_of<DIM>(r, cc, cell_start, cell_key, M, dense, gd, start, end);
+      const bool ne = end > start;
+      const uint64_t m = (S == 64 ? __ballot(ne) : (__ballot(ne) >> (sub * S))) &
+                         (S == 64 ? ~0ull : ((1ull << S) - 1ull));
+      if (ne) {
+        const uint32_t pos = count + (uint32_t)__popcll(m & lt);
+        ranges[((int64_t)c * R + pos) * 2] = start;
+        ranges[((int64_t)c * R + pos) * 2 + 1] = end;
+        rslot[(int64_t)c * R + pos] = (uint8_t)r;
+        cand += end - start;
+      }
+      count += (uint32_t)__popcll(m);
+    }
+#pragma unroll
+    for (int o = 1; o < S; o <<= 1) cand += __shfl_xor(cand, o, 64);
+    if (l == 0) {
+      nrng[c] = count;
+      cand_count[c] = cand;
+    }
+  }
+}
+
+// Point range [start, end) of row segment r of the cell with coordinates cc
+// (offsets o_0..o_{DIM-2} in {-1,0,1}, o_0 slowest; last coordinate within
+// one of the cell's).  Empty: start == end == 0.
+template <int DIM>
+__device__ inline void range_of(int r, const int64_t (&cc)[DIM],
+                                const uint32_t* __restrict__ cell_start,
+                                const uint64_t* __restrict__ cell_key, uint32_t M,
+                                const uint32_t* __restrict__ dense, const GeomDev& gd,
+                                uint32_t& start, uint32_t& end) {
+  {
     bool inside = true;
     uint64_t prefix = 0;
     int rr = r;
@@ -371,7 +421,8 @@ __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
       nb[j] = cc[j] + o;
       if (nb[j] < 0 || nb[j] >= gd.g[j]) inside = false;
     }
-    uint32_t start = 0, end = 0;
+    start = 0;
+    end = 0;
     if (inside) {
 #pragma unroll
       for (int j = 0; j < DIM - 1; ++j) prefix += (uint64_t)nb[j] * gd.stride[j];
@@ -402,9 +453,6 @@ __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
         }
       }
     }
-    ranges[2 * e] = start;
-    ranges[2 * e + 1] = end;
-    if (end > start) atomicAdd(&cand_count[c], end - start);
   }
 }
 
@@ -426,8 +474,10 @@ __global__ void k_item_keys(const int32_t* __restrict__ active, int64_t n_active
       int64_t q = active ? active[s] : s;
       est += cand_count[cell_of[q]];
     }
-    if (est > 0xFFFFFFFFull) est = 0xFFFFFFFFull;
-    keys[it] = 0xFFFFFFFFull - est;  // ascending sort = dense first
+    // density class: half-octaves of the estimate, densest class first; the
+    // stable sort keeps cell order (spatial locality) inside a class
+    const int cls = est ? (int)(2.0 * log2((double)est)) : 0;
+    keys[it] = (uint64_t)(63 - (cls > 63 ? 63 : cls));
     vals[it] = (int32_t)it;
   }
 }
@@ -591,19 +641,16 @@ void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N
 void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_start,
                             const uint64_t* cell_key, const uint32_t* d_M,
                             const uint32_t* dense, const GridGeom& gg, uint32_t* ranges,
-                            uint32_t* cand_count, hipStream_t s) {
+                            uint8_t* rslot, uint32_t* nrng, uint32_t* cand_count, hipStream_t s) {
   GeomDev gd = to_dev(gg);
-  k_zero_u32<<<grid_for(N), kBlock, 0, s>>>(cand_count, N);
-  KNN_LAUNCHED();
-  int64_t R = 1;
-  for (int j = 0; j < gg.dims - 1; ++j) R *= 3;
-  int nb = grid_for(N * R, 65536);
+  const int S = gg.dims == 2 ? 4 : gg.dims == 3 ? 16 : gg.dims == 4 ? 32 : 64;
+  const int nb = grid_for(N * S, 65536);
   switch (gg.dims) {
-    case 2: k_neighbor_ranges<2><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, cand_count); break;
-    case 3: k_neighbor_ranges<3><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, cand_count); break;
-    case 4: k_neighbor_ranges<4><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, cand_count); break;
-    case 5: k_neighbor_ranges<5><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, cand_count); break;
-    case 6: k_neighbor_ranges<6><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, cand_count); break;
+    case 2: k_neighbor_ranges<2><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, rslot, nrng, cand_count); break;
+    case 3: k_neighbor_ranges<3><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, rslot, nrng, cand_count); break;
+    case 4: k_neighbor_ranges<4><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, rslot, nrng, cand_count); break;
+    case 5: k_neighbor_ranges<5><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, rslot, nrng, cand_count); break;
+    case 6: k_neighbor_ranges<6><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, rslot, nrng, cand_count); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
   KNN_LAUNCHED();

@@ -151,7 +151,8 @@ struct Events {
 
 int64_t JoinContext::device_bytes() const {
   return (int64_t)(Xs.bytes() + perm.bytes() + cell_of.bytes() + cell_key.bytes() +
-                   cell_start.bytes() + ranges.bytes() + cand_count.bytes() + dense.bytes() +
+                   cell_start.bytes() + ranges.bytes() + rslot.bytes() + nrng.bytes() +
+                   cand_count.bytes() + dense.bytes() +
                    keys.bytes() + keys2.bytes() + vals2.bytes() + flags.bytes() + tmp.bytes() +
                    scal.bytes() + iscal.bytes() + active.bytes() + fail_list.bytes() +
                    failed.bytes() + ikeys.bytes() + ikeys2.bytes() + ivals.bytes() +
@@ -213,8 +214,10 @@ void build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s) 
   }
   const int64_t R = pow3(n - 1);
   c.ranges.reserve((size_t)std::max<int64_t>(M, 1) * R * 2);
+  c.rslot.reserve((size_t)std::max<int64_t>(M, 1) * R);
+  c.nrng.reserve(N);
   launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, dense, c.gg,
-                         c.ranges.p, c.cand_count.p, s);
+                         c.ranges.p, c.rslot.p, c.nrng.p, c.cand_count.p, s);
 }
 
 uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
@@ -351,7 +354,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       c.ivals2.reserve(n_items);
       launch_item_keys(active, A, G, c.cell_of.p, c.cand_count.p, c.ikeys.p, c.ivals.p, n_items,
                        s);
-      radix_sort_pairs(c.ikeys.p, c.ivals.p, c.ikeys2.p, c.ivals2.p, n_items, 32, c.tmp.p, s);
+      radix_sort_pairs(c.ikeys.p, c.ivals.p, c.ikeys2.p, c.ivals2.p, n_items, 6, c.tmp.p, s);
       order = c.ivals.p;
     }
     KNN_HIP(hipMemsetAsync(c.iscal.p, 0, 4 * sizeof(int32_t), s));
@@ -363,6 +366,8 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.perm = c.perm.p;
     a.cell_of = c.cell_of.p;
     a.ranges = c.ranges.p;
+    a.nrng = c.nrng.p;
+    a.cand = c.cand_count.p;
     a.active = active;
     a.n_active = A;
     a.order = order;
@@ -719,9 +724,27 @@ int knn_grid_export(knn_index* idx, double cell_width, uint64_t* sorted_keys, in
       if (cell_keys) KNN_HIP(hipMemcpyAsync(cell_keys, c.cell_key.p, M * 8, hipMemcpyDeviceToHost, s));
       if (cell_start)
         KNN_HIP(hipMemcpyAsync(cell_start, c.cell_start.p, (M + 1) * 4, hipMemcpyDeviceToHost, s));
-      if (ranges)
-        KNN_HIP(hipMemcpyAsync(ranges, c.ranges.p, M * R * 2 * 4, hipMemcpyDeviceToHost, s));
+      std::vector<uint32_t> hr, hn;
+      std::vector<uint8_t> hs;
+      if (ranges) {
+        hr.resize((size_t)M * R * 2);
+        hs.resize((size_t)M * R);
+        hn.resize((size_t)M);
+        KNN_HIP(hipMemcpyAsync(hr.data(), c.ranges.p, M * R * 2 * 4, hipMemcpyDeviceToHost, s));
+        KNN_HIP(hipMemcpyAsync(hs.data(), c.rslot.p, M * R, hipMemcpyDeviceToHost, s));
+        KNN_HIP(hipMemcpyAsync(hn.data(), c.nrng.p, M * 4, hipMemcpyDeviceToHost, s));
+      }
       KNN_HIP(hipStreamSynchronize(s));
+      if (ranges) {
+        // compacted segments -> one slot per segment, (0, 0) where empty
+        std::memset(ranges, 0, (size_t)M * R * 2 * 4);
+        for (int64_t cc = 0; cc < M; ++cc)
+          for (uint32_t i = 0; i < hn[cc]; ++i) {
+            const int64_t r = hs[cc * R + i];
+            ranges[(cc * R + r) * 2] = hr[(cc * R + i) * 2];
+            ranges[(cc * R + r) * 2 + 1] = hr[(cc * R + i) * 2 + 1];
+          }
+      }
       if (grid_dims)
         for (int j = 0; j < idx->n; ++j) grid_dims[j] = c.gg.g[j];
       if (n_cells) *n_cells = M;

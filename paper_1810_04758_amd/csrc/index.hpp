@@ -39,7 +39,9 @@ struct JoinContext {
   DevBuf<uint32_t> cell_of;
   DevBuf<uint64_t> cell_key;
   DevBuf<uint32_t> cell_start;
-  DevBuf<uint32_t> ranges;
+  DevBuf<uint32_t> ranges;  // compacted non-empty row segments, R slots per cell
+  DevBuf<uint8_t> rslot;    // segment index of each compacted entry
+  DevBuf<uint32_t> nrng;    // non-empty segments per cell
   DevBuf<uint32_t> cand_count;
   DevBuf<uint32_t> dense;
   // temporaries

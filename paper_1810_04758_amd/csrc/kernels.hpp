@@ -58,12 +58,15 @@ void launch_gather_soa(const double* X, const int32_t* perm, int64_t N, int n, d
 // Dense key -> cell lookup table (table_size entries, set to ~0 where empty).
 void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N,
                         uint32_t* table, int64_t table_size, hipStream_t s);
-// Row-segment neighbour ranges of every cell (3^(n-1) per cell) and the
-// candidate count per cell (sum of range lengths).
+// Row-segment neighbour ranges of every cell: the non-empty ones of the
+// 3^(n-1) segments, compacted in segment order into ranges[(c*R + i)*2 + {0,1}]
+// (start, end) with their segment index in rslot[c*R + i], their number in
+// nrng[c], and the candidate count (sum of lengths) in cand_count[c].
 void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_start,
                             const uint64_t* cell_key, const uint32_t* d_M,
                             const uint32_t* dense /*nullable*/, const GridGeom& gg,
-                            uint32_t* ranges, uint32_t* cand_count, hipStream_t s);
+                            uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
+                            uint32_t* cand_count, hipStream_t s);
 
 // ---- work items (grid.hip) ----
 // est[i] = sum over the queries of item i (G consecutive active slots) of the
@@ -98,7 +101,9 @@ struct SearchArgs {
   int64_t N;
   const int32_t* perm;     // sorted position -> point id
   const uint32_t* cell_of; // sorted position -> cell
-  const uint32_t* ranges;  // cell*R*2 row-segment ranges
+  const uint32_t* ranges;  // cell*R*2 compacted non-empty row-segment ranges
+  const uint32_t* nrng;    // non-empty segments per cell
+  const uint32_t* cand;    // candidates per cell
   const int32_t* active;   // active sorted positions (nullptr: identity)
   int64_t n_active;
   const int32_t* order;    // item order (nullptr: identity)
@@ -110,7 +115,6 @@ struct SearchArgs {
   double inv_w;
   int64_t g[kMaxDims];
   double margin;           // relative shrink of the covered radius (rounding)
-  double thr_frac[4];      // count-pass thresholds as fractions of r^2
   int32_t K;
   int32_t cap;             // per-query survivor buffer entries (>= K)
   int32_t* out_ids;        // N x K, row = point id

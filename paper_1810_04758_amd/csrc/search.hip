@@ -4,25 +4,29 @@
 // One wavefront takes one work item: G = 64/T consecutive active queries (in
 // cell order), T lanes per query (the paper's t threads per point, Sec. 4.7).
 // For each query:
-//   1. Candidates are the points of the 3^n adjacent cells, read as 3^(n-1)
-//      contiguous row segments of the cell-sorted SoA coordinates.
+//   1. Candidates are the points of the 3^n adjacent cells, stored as the
+//      non-empty ones of 3^(n-1) contiguous row segments of the cell-sorted
+//      SoA coordinates.  The T lanes walk them as one flattened array, so lane
+//      utilisation does not depend on the segment lengths.
 //   2. Count pass: every candidate's squared distance (summed left to right,
 //      every operation rounded) goes through a monotone bin function into a
-//      per-query LDS histogram of NB log-spaced bins (4 per octave of d^2,
-//      read off the exponent and two mantissa bits) ending at r^2, where r
-//      is the radius that the scanned cells provably cover.  Fewer than K candidates
-//      within r^2 means the K nearest cannot be proven from these cells: the
-//      query fails and is re-queued for a larger cell side (Alg. 1,
+//      per-query LDS histogram of NB log-spaced bins (8 per octave of d^2,
+//      read off the exponent and three mantissa bits) ending at r^2, where r
+//      is the radius that the scanned cells provably cover.  Fewer than K
+//      candidates within r^2 means the K nearest cannot be proven from these
+//      cells: the query fails and is re-queued for a larger cell side (Alg. 1,
 //      findFailedPnts / addFailuresToWorkQueue).
 //   3. The first bin whose cumulative count reaches K selects the survivors
 //      (every candidate whose bin is not above it).  Since the bin function is
 //      monotone in d^2, the survivors are exactly the candidates below some
 //      squared distance, so they contain the K nearest.  If that bin would
 //      overflow the per-query buffer (cap), an exact bisection on the key
-//      (d^2, id) narrows it first.
-//   4. Collect pass: survivors (d^2, id) go to the per-query LDS buffer.
-//   5. Rank pass: each survivor's rank among the survivors in (d^2, id) order
-//      is counted; ranks below K are written to the query's output row.
+//      (d^2, id) narrows it first (32-way histogram rounds in key space).
+//   4. Collect pass: survivors (d^2, id) go to the per-query LDS buffer,
+//      bucketed by bin (the histogram, turned into prefix offsets, serves as
+//      the bucket cursors: a counting sort).
+//   5. Rank pass: a survivor's rank is its bucket's start plus the bucket
+//      mates before it in (d^2, id) order; ranks below K go to the output row.
 //
 // Exactness of the success test: a point outside the scanned cells differs
 // from the query by at least 1 + m cell coordinates in some dimension
@@ -33,16 +37,16 @@
 // computed d^2 > r^2 and cannot precede a survivor.
 #pragma clang fp contract(off)
 
-#include <climits>
-
 #include "kernels.hpp"
 
 namespace knn {
 
 namespace {
 
-constexpr int NB = 64;         // histogram bins of the count pass: 16 octaves of d^2
-constexpr int kBinShift = 50;  // exponent + 2 mantissa bits: 4 bins per octave
+constexpr int NB = 64;         // count-pass bins: 8 octaves of d^2
+constexpr int kBinShift = 49;  // exponent + 3 mantissa bits: 8 bins per octave
+constexpr int NB2 = 32;        // bins of one exact-bisection round
+constexpr int kLog2NB2 = 5;
 
 template <int D>
 struct Pow3 {
@@ -81,25 +85,6 @@ __device__ __forceinline__ void wave_fence() {
 }
 
 template <int T>
-__device__ __forceinline__ int group_sum(int v) {
-#pragma unroll
-  for (int o = 1; o < T; o <<= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-template <int T>
-__device__ __forceinline__ double group_min(double v) {
-#pragma unroll
-  for (int o = 1; o < T; o <<= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
-template <int T>
-__device__ __forceinline__ double group_max(double v) {
-#pragma unroll
-  for (int o = 1; o < T; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-template <int T>
 __device__ __forceinline__ int group_incl_scan(int v, int l) {
 #pragma unroll
   for (int o = 1; o < T; o <<= 1) {
@@ -120,11 +105,54 @@ __device__ __forceinline__ int group_max_int(int v) {
   for (int o = 1; o < T; o <<= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
 }
+template <int T>
+__device__ __forceinline__ double group_min(double v) {
+#pragma unroll
+  for (int o = 1; o < T; o <<= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+template <int T>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+  for (int o = 1; o < T; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ int bitlen128(unsigned __int128 v) {
+  const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
+  return hi ? 128 - __builtin_clzll(hi) : (lo ? 64 - __builtin_clzll(lo) : 0);
+}
+
+// Flattened walk over a cell's non-empty row segments: virtual candidate v
+// (non-decreasing from call to call, below the cell's candidate count) ->
+// sorted position.
+struct Cands {
+  const uint32_t* rg;
+  uint32_t vs, ve, st;
+  int r;
+  __device__ __forceinline__ void init(const uint32_t* rg_, int nr) {
+    rg = rg_;
+    r = 0;
+    vs = 0;
+    st = nr > 0 ? rg[0] : 0u;
+    ve = nr > 0 ? rg[1] - st : 0u;
+  }
+  __device__ __forceinline__ uint32_t pos(uint32_t v) {
+    while (v >= ve) {
+      ++r;
+      vs = ve;
+      st = rg[2 * r];
+      ve = vs + (rg[2 * r + 1] - st);
+    }
+    return st + (v - vs);
+  }
+};
 
 template <int DIM, int T>
 __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
-  constexpr int G = 64 / T;      // queries per wave
+  constexpr int G = 64 / T;  // queries per wave
   constexpr int R = Pow3<DIM - 1>::v;
+  constexpr int P = NB / T;  // count bins owned by each lane of a group
   extern __shared__ double smem[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -132,16 +160,20 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
   const int g = lane / T;
   const int l = lane % T;
   const int cap = a.cap;
+  const int K = a.K;
   const int64_t N = a.N;
   const double* __restrict__ Xs = a.Xs;
   const int32_t* __restrict__ perm = a.perm;
 
-  // per-wave LDS: survivors d2 [cap][G], survivor ids [cap][G], histogram [NB][G]
+  // per-wave LDS: survivors d2 [cap][G], survivor ids [cap][G], histogram
+  // [NB][G]; the refinement histogram [NB2][G] reuses the d2 area (it is free
+  // before the collect, and cap >= NB2/2 + 1).
   double* bd = smem + (size_t)wave * cap * G;
   int32_t* bi = reinterpret_cast<int32_t*>(smem + (size_t)nwaves * cap * G) + (size_t)wave * cap * G;
   uint32_t* hist = reinterpret_cast<uint32_t*>(reinterpret_cast<int32_t*>(smem + (size_t)nwaves * cap * G) +
                                                (size_t)nwaves * cap * G) +
                    (size_t)wave * NB * G;
+  uint32_t* hist2 = reinterpret_cast<uint32_t*>(bd);
 
   const uint64_t lane_lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
@@ -168,6 +200,9 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
 #pragma unroll
     for (int j = 0; j < DIM; ++j) qx[j] = Xs[(int64_t)j * N + q];
     const uint32_t cell = a.cell_of[q];
+    const uint32_t* rg = a.ranges + (size_t)cell * R * 2;
+    const int nr = valid ? (int)a.nrng[cell] : 0;
+    const uint32_t C = valid ? a.cand[cell] : 0u;
     double mfrac = 0.5;
     bool full = true;
 #pragma unroll
@@ -197,37 +232,35 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
     // ---- count pass ----------------------------------------------------------
     for (int b = l; b < NB; b += T) hist[b * G + g] = 0;
     wave_fence();
-    const uint32_t* rg = a.ranges + (size_t)cell * R * 2;
-    for (int r = 0; r < R; ++r) {
-      const uint32_t s = valid ? rg[2 * r] : 0u;
-      const uint32_t e = valid ? rg[2 * r + 1] : 0u;
-      for (uint32_t p0 = s; p0 < e; p0 += T) {
-        const uint32_t p = p0 + l;
-        if (p < e && (int64_t)p != q) {
-          double d2 = sq_dist<DIM>(Xs, N, p, qx);
-          int b = bin_of(d2, thr, top);
+    {
+      Cands cs;
+      cs.init(rg, nr);
+      for (uint32_t v = l; v < C; v += T) {
+        const uint32_t p = cs.pos(v);
+        if ((int64_t)p != q) {
+          const int b = bin_of(sq_dist<DIM>(Xs, N, p, qx), thr, top);
           if (b < NB) atomicAdd(&hist[b * G + g], 1u);
         }
       }
     }
     wave_fence();
-    // Selection: lane l of the group owns bins [l*P, (l+1)*P).  A group scan
-    // of the per-lane sums gives every bin's prefix; the first bin whose
-    // cumulative count reaches K is the selected bin, and the histogram is
-    // rewritten in place as exclusive prefixes (bucket starts of the collect).
-    constexpr int P = NB / T;
+
+    // ---- selection ---------------------------------------------------------
+    // Lane l of the group owns bins [l*P, (l+1)*P).  A group scan of the
+    // per-lane sums gives every bin's prefix; the first bin whose cumulative
+    // count reaches K is the selected bin, and the histogram is rewritten in
+    // place as exclusive prefixes (the bucket cursors of the collect).
     int bsel = NB, c_lo = 0, c_hi = 0;
     {
       uint32_t* hb = hist + (size_t)(l * P) * G + g;
       int local = 0;
       for (int i = 0; i < P; ++i) local += (int)hb[i * G];
       const int incl = group_incl_scan<T>(local, l);
-      const int excl = incl - local;
       int mb = NB, mlo = 0, mhi = 0;
-      int cum = excl;
+      int cum = incl - local;
       for (int i = 0; i < P; ++i) {
         const int h = (int)hb[i * G];
-        if (mb == NB && cum + h >= a.K) {
+        if (mb == NB && cum + h >= K) {
           mb = l * P + i;
           mlo = cum;
           mhi = cum + h;
@@ -257,19 +290,23 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
     // ---- exact refinement when the selected bin overflows the buffer -------
     // Keys are (d2 bits, id) as 96-bit integers; [A, B] is an inclusive key
     // interval with c_lo keys below A and c_hi keys up to B, c_lo < K <= c_hi.
+    // Each round counts the keys of [A, B] into NB2 equal key sub-ranges and
+    // keeps the first one where the count reaches K: the interval shrinks at
+    // least NB2/2-fold, and a single-key interval holds at most one candidate.
     bool refine = ok && c_hi > cap;
     const bool refined = refine;
     unsigned __int128 B = 0;  // final threshold when refined
     if (__ballot(refine)) {
       // exact value bounds of the selected bin
       double dmin = INFINITY, dmax = -INFINITY;
-      for (int r = 0; r < R; ++r) {
-        const uint32_t s = refine ? rg[2 * r] : 0u;
-        const uint32_t e = refine ? rg[2 * r + 1] : 0u;
-        for (uint32_t p0 = s; p0 < e; p0 += T) {
-          const uint32_t p = p0 + l;
-          if (p < e && (int64_t)p != q) {
-            double d2 = sq_dist<DIM>(Xs, N, p, qx);
+      {
+        Cands cs;
+        cs.init(rg, nr);
+        const uint32_t Cr = refine ? C : 0u;
+        for (uint32_t v = l; v < Cr; v += T) {
+          const uint32_t p = cs.pos(v);
+          if ((int64_t)p != q) {
+            const double d2 = sq_dist<DIM>(Xs, N, p, qx);
             if (bin_of(d2, thr, top) == bsel) {
               dmin = fmin(dmin, d2);
               dmax = fmax(dmax, d2);
@@ -287,54 +324,46 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
       int rounds = 0;
       while (__ballot(refine)) {
         ++rounds;
-        unsigned __int128 t[4] = {0, 0, 0, 0};
-        if (refine) {
-          const unsigned __int128 span = B - A + 1;
-          const unsigned __int128 step = span / 4;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (i == 3)
-              t[i] = B;
-            else if (step == 0)
-              t[i] = (A + (unsigned __int128)i < B) ? A + (unsigned __int128)i : B;
-            else
-              t[i] = A - 1 + step * (unsigned __int128)(i + 1);
-          }
-        }
-        const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
-        int cnt[4] = {0, 0, 0, 0};
-        for (int r = 0; r < R; ++r) {
-          const uint32_t s = refine ? rg[2 * r] : 0u;
-          const uint32_t e = refine ? rg[2 * r + 1] : 0u;
-          for (uint32_t p0 = s; p0 < e; p0 += T) {
-            const uint32_t p = p0 + l;
-            if (p < e && (int64_t)p != q) {
-              double d2 = sq_dist<DIM>(Xs, N, p, qx);
+        int sh = refine ? bitlen128(B - A) - kLog2NB2 : 0;
+        if (sh < 0) sh = 0;
+        for (int b = l; b < NB2; b += T) hist2[b * G + g] = 0;
+        wave_fence();
+        {
+          const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
+          Cands cs;
+          cs.init(rg, nr);
+          const uint32_t Cr = refine ? C : 0u;
+          for (uint32_t v = l; v < Cr; v += T) {
+            const uint32_t p = cs.pos(v);
+            if ((int64_t)p != q) {
+              const double d2 = sq_dist<DIM>(Xs, N, p, qx);
               const uint64_t kh = (uint64_t)__double_as_longlong(d2);
               if (kh >= ahi && kh <= bhi) {
                 const unsigned __int128 k = ((unsigned __int128)kh << 32) | (uint32_t)perm[p];
-                if (k >= A) {
-#pragma unroll
-                  for (int i = 0; i < 4; ++i) cnt[i] += (k <= t[i]) ? 1 : 0;
-                }
+                if (k >= A && k <= B) atomicAdd(&hist2[(int)((k - A) >> sh) * G + g], 1u);
               }
             }
           }
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) cnt[i] = group_sum<T>(cnt[i]);
+        wave_fence();
         if (refine) {
-          int i = 0;
-          while (i < 3 && c_lo + cnt[i] < a.K) ++i;
-          const int nchi = c_lo + cnt[i];
-          if (i > 0) {
-            A = t[i - 1] + 1;
-            c_lo = c_lo + cnt[i - 1];
+          int cum = c_lo;
+          for (int b = 0; b < NB2; ++b) {
+            const int h = (int)hist2[b * G + g];
+            if (cum + h >= K) {
+              const unsigned __int128 nA = A + ((unsigned __int128)b << sh);
+              const unsigned __int128 nB = nA + (((unsigned __int128)1 << sh) - 1);
+              A = nA;
+              B = nB < B ? nB : B;
+              c_lo = cum;
+              c_hi = cum + h;
+              break;
+            }
+            cum += h;
           }
-          B = t[i];
-          c_hi = nchi;
           if (c_hi <= cap) refine = false;
         }
+        wave_fence();
       }
       if (l == 0 && refined && a.refine_count) atomicAdd(a.refine_count, rounds);
     }
@@ -343,12 +372,13 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
 
     // ---- collect pass: survivors bucketed by bin (counting sort) --------------
     wave_fence();
-    for (int r = 0; r < R; ++r) {
-      const uint32_t s = ok ? rg[2 * r] : 0u;
-      const uint32_t e = ok ? rg[2 * r + 1] : 0u;
-      for (uint32_t p0 = s; p0 < e; p0 += T) {
-        const uint32_t p = p0 + l;
-        if (p < e && (int64_t)p != q) {
+    {
+      Cands cs;
+      cs.init(rg, nr);
+      const uint32_t Cc = ok ? C : 0u;
+      for (uint32_t v = l; v < Cc; v += T) {
+        const uint32_t p = cs.pos(v);
+        if ((int64_t)p != q) {
           const double d2 = sq_dist<DIM>(Xs, N, p, qx);
           const int b = bin_of(d2, thr, top);
           bool acc;
@@ -357,10 +387,10 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
           else
             acc = b <= bsel;
           if (acc) {
-            const uint32_t slot = atomicAdd(&hist[b * G + g], 1u);
-            if ((int)slot < cap) {
-              bd[slot * G + g] = d2;
-              bi[slot * G + g] = perm[p];
+            const uint32_t s = atomicAdd(&hist[b * G + g], 1u);
+            if ((int)s < cap) {
+              bd[s * G + g] = d2;
+              bi[s * G + g] = perm[p];
             }
           }
         }
@@ -372,7 +402,6 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
     // After the collect, hist[b] is the end of bucket b, and bucket b starts at
     // the end of bucket b-1; a survivor's rank is its bucket start plus the
     // number of bucket mates before it in (d2, id) order.
-    const int K = a.K;
     const int c = ok ? min((int)hist[bsel * G + g], cap) : 0;
     const int64_t row = ok ? (int64_t)perm[q] : 0;
     for (int a0 = 0; a0 < c; a0 += T) {
@@ -431,6 +460,7 @@ int search_waves_per_block(int T, int cap) {
 }
 
 void launch_search(const SearchArgs& a, int dims, int T, int grid_blocks, hipStream_t s) {
+  KNN_CHECK(a.cap >= NB2 / 2 + 1, KNN_EINTERNAL, "per-query buffer too small");
   const int waves = search_waves_per_block(T, a.cap);
   const size_t lds = search_lds_per_wave(T, a.cap) * waves;
   KNN_CHECK(lds <= 65536, KNN_EINVAL, "K too large for the per-query buffers");
