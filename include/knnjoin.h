@@ -177,6 +177,10 @@ typedef struct knn_index_info {
 } knn_index_info;
 int knn_index_info_get(const knn_index* idx, knn_index_info* out);
 
+/* Upper bound of the device bytes one self-join of (idx, K) with host
+ * outputs allocates beyond the index (the serving loop's admission size). */
+int knn_join_footprint(const knn_index* idx, int32_t K, uint64_t* bytes);
+
 /* eps_min(K) of Sec. 4.4 from the index's cumulative distance histogram:
  * the midpoint of the first bin whose cumulative count reaches K per sample
  * point, or eps_mean if none does. */

@@ -99,6 +99,7 @@ SIGNATURES = {
     "knn_last_error": (ctypes.c_char_p, []),
     "knn_index_info_get": (ctypes.c_int, [c_p, ctypes.POINTER(IndexInfo)]),
     "knn_eps_min": (ctypes.c_int, [c_p, c_i32, ctypes.POINTER(c_f64)]),
+    "knn_join_footprint": (ctypes.c_int, [c_p, c_i32, ctypes.POINTER(c_u64)]),
     "knn_grid_export": (ctypes.c_int, [c_p, c_f64, c_p, c_p, c_p, c_p, c_p, c_p,
                                        ctypes.POINTER(c_i64)]),
     "knn_sample_mean_dist": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_i64,

@@ -94,6 +94,12 @@ class Index:
         check(load().knn_eps_min(self.handle, K, ctypes.byref(v)))
         return v.value
 
+    def join_footprint(self, K):
+        """knn_join_footprint: device bytes a host-output join of K allocates."""
+        v = ctypes.c_uint64()
+        check(load().knn_join_footprint(self.handle, K, ctypes.byref(v)))
+        return v.value
+
     def self_join(self, K, ids=None, dists=None, stream=None, with_stats=False, **opts):
         """knn_self_join_device: returns (ids int32 [N,K], dists float64 [N,K]) on
         the GPU (and the per-level statistics if with_stats)."""

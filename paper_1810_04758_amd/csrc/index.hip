@@ -221,12 +221,22 @@ void build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s) 
 }
 
 uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
+  // Upper bound of everything a JoinContext allocates, with the worst case of
+  // one non-empty cell per point (M = N).
   const uint64_t N = (uint64_t)idx.N, n = (uint64_t)idx.n;
-  // level arrays + temporaries (ranges sized for one cell per point at worst
-  // in 2-D, per-point cells are the exception in higher dims but bounded here)
-  uint64_t R = (uint64_t)pow3(idx.n - 1);
-  uint64_t b = N * (8 * n + 4 + 4 + 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8 + 1) + N * 16 * 4 / 8 +
-               N * std::min<uint64_t>(R, 27) * 8 + (1u << 24);
+  const uint64_t R = (uint64_t)pow3(idx.n - 1);
+  const uint64_t cap = (uint64_t)K + std::max<uint64_t>(16, (uint64_t)K / 2);
+  uint64_t b = 0;
+  b += 8 * n * N;                      // Xs
+  b += (4 + 4 + 8 + 4 + 4 + 4) * N;    // perm, cell_of, cell_key, cell_start, nrng, cand_count
+  b += 9 * R * N;                      // ranges + rslot
+  if (idx.n > 2) b += std::max<uint64_t>(64 * N, 16ull << 20);  // dense key table
+  b += (16 + 4 + 4) * N;               // keys, keys2, vals2, flags
+  b += (uint64_t)radix_tmp_elems((int64_t)N) * 4;
+  b += (4 + 4 + 1) * N;                // active, fail_list, failed
+  b += 24 * N;                         // work-item keys and order (at most one item per query)
+  b += std::min<uint64_t>(N, 65535) * (512 + cap * 12);  // brute-force tail scratch
+  b += 4096;                           // scalars
   if (host_output) b += N * (uint64_t)K * 12;
   return b;
 }
@@ -693,6 +703,14 @@ int knn_index_info_get(const knn_index* idx, knn_index_info* out) {
     out->n_bins = idx->n_bins;
     out->n_sample = idx->n_sample;
     out->device_bytes = (int64_t)idx->X.bytes() + (idx->ctx ? idx->ctx->ctx.device_bytes() : 0);
+  });
+}
+
+int knn_join_footprint(const knn_index* idx, int32_t K, uint64_t* bytes) {
+  return guarded([&] {
+    KNN_CHECK(bytes != nullptr, KNN_EINVAL, "NULL pointer");
+    validate_join(idx, K);
+    *bytes = join_footprint(*idx, K, true);
   });
 }
 
