@@ -477,7 +477,8 @@ __global__ void k_item_keys(const int32_t* __restrict__ active, int64_t n_active
     // density class: half-octaves of the estimate, densest class first; the
     // stable sort keeps cell order (spatial locality) inside a class
     const int cls = est ? (int)(2.0 * log2((double)est)) : 0;
-    keys[it] = (uint64_t)(63 - (cls > 63 ? 63 : cls));
+    const uint64_t chunk = (uint64_t)(it * kXcds / n_items);
+    keys[it] = (chunk << 6) | (uint64_t)(63 - (cls > 63 ? 63 : cls));
     vals[it] = (int32_t)it;
   }
 }

@@ -288,7 +288,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   double diag2 = 0;
   for (int j = 0; j < idx.n; ++j) diag2 += (idx.hi[j] - idx.lo[j]) * (idx.hi[j] - idx.lo[j]);
 
-  c.iscal.reserve(4);
+  c.iscal.reserve(16);  // [0..7] XCD queue heads, [8] failures, [9] refinement rounds
   c.scal.reserve(4);
   c.active.reserve(N);
   c.fail_list.reserve(N);
@@ -364,10 +364,10 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       c.ivals2.reserve(n_items);
       launch_item_keys(active, A, G, c.cell_of.p, c.cand_count.p, c.ikeys.p, c.ivals.p, n_items,
                        s);
-      radix_sort_pairs(c.ikeys.p, c.ivals.p, c.ikeys2.p, c.ivals2.p, n_items, 6, c.tmp.p, s);
+      radix_sort_pairs(c.ikeys.p, c.ivals.p, c.ikeys2.p, c.ivals2.p, n_items, 9, c.tmp.p, s);
       order = c.ivals.p;
     }
-    KNN_HIP(hipMemsetAsync(c.iscal.p, 0, 4 * sizeof(int32_t), s));
+    KNN_HIP(hipMemsetAsync(c.iscal.p, 0, 16 * sizeof(int32_t), s));
     ev.rec(1, s);
 
     SearchArgs a{};
@@ -384,6 +384,8 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.n_items = n_items;
     a.item_base = 0;
     a.head = c.iscal.p;
+    for (int x = 0; x <= kXcds; ++x)  // queue x: items of chunk x (ceil(x * n_items / 8) onwards)
+      a.qbeg[x] = (x * n_items + kXcds - 1) / kXcds;
     a.persistent = o.schedule == 0 ? 1 : 0;
     for (int j = 0; j < kMaxDims; ++j) {
       a.lo[j] = c.gg.lo[j];
@@ -396,8 +398,8 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.out_ids = d_ids;
     a.out_d = d_dists;
     a.fail_list = c.fail_list.p;
-    a.fail_count = c.iscal.p + 1;
-    a.refine_count = c.iscal.p + 2;
+    a.fail_count = c.iscal.p + 8;
+    a.refine_count = c.iscal.p + 9;
     if (o.schedule == 0) {
       int64_t want = ceil_div(n_items, waves);
       int blocks = (int)std::min<int64_t>(want, (int64_t)ncu * 16);
@@ -413,15 +415,15 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       }
     }
     ev.rec(2, s);
-    int32_t sc[4] = {0, 0, 0, 0};
-    KNN_HIP(hipMemcpyAsync(sc, c.iscal.p, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t sc[2] = {0, 0};
+    KNN_HIP(hipMemcpyAsync(sc, c.iscal.p + 8, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     KNN_HIP(hipStreamSynchronize(s));
-    const int32_t fails = sc[1];
+    const int32_t fails = sc[0];
     if (st && level < KNN_MAX_LEVELS) {
       if (level == 0) st->lanes_per_query = T;
       st->lanes[level] = T;
       st->cand_per_query[level] = cand;
-      st->refine_rounds[level] = sc[2];
+      st->refine_rounds[level] = sc[1];
       st->levels = level + 1;
       st->cell_width[level] = 1.0 / c.gg.inv_w;
       st->attempted[level] = A;
@@ -437,7 +439,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     // failures are re-queued on a grid with a larger cell side (Alg. 1):
     // linear growth by eps_step * w0 first, then geometric growth
     KNN_HIP(hipMemsetAsync(c.failed.p, 0, N, s));
-    launch_mark_failed(c.fail_list.p, c.iscal.p + 1, fails, c.failed.p, s);
+    launch_mark_failed(c.fail_list.p, c.iscal.p + 8, fails, c.failed.p, s);
     A = fails;
     w = (1.0 / c.gg.inv_w);
     if (level < linear)

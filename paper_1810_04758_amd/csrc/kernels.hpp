@@ -6,6 +6,7 @@
 namespace knn {
 
 constexpr int kMaxDims = KNN_MAX_DIMS;
+constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
 
 // Geometry of one grid level (Sec. 3.1): cell side 1/inv_w, origin lo.
 struct GridGeom {
@@ -69,8 +70,10 @@ void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_st
                             uint32_t* cand_count, hipStream_t s);
 
 // ---- work items (grid.hip) ----
-// est[i] = sum over the queries of item i (G consecutive active slots) of the
-// candidate count of their cell; keys for a descending stable sort.
+// Work item i = G consecutive active slots.  Its estimate is the sum of the
+// candidate counts of its queries' cells; its sort key is (XCD chunk, density
+// class): chunk = i*8/n_items (contiguous in cell order), class = half-octaves
+// of the estimate, densest first.  A stable sort keeps cell order inside.
 void launch_item_keys(const int32_t* active /*nullable: identity*/, int64_t n_active,
                       int G, const uint32_t* cell_of, const uint32_t* cand_count,
                       uint64_t* keys, int32_t* vals, int64_t n_items, hipStream_t s);
@@ -109,7 +112,8 @@ struct SearchArgs {
   const int32_t* order;    // item order (nullptr: identity)
   int64_t n_items;
   int64_t item_base;       // first item of this launch (schedule 1)
-  int32_t* head;           // persistent work-queue head (device)
+  int32_t* head;           // persistent work-queue heads, one per XCD (device)
+  int64_t qbeg[kXcds + 1]; // queue x = order positions [qbeg[x], qbeg[x+1])
   int32_t persistent;
   double lo[kMaxDims];
   double inv_w;

@@ -47,6 +47,7 @@ constexpr int NB = 64;         // count-pass bins: 8 octaves of d^2
 constexpr int kBinShift = 49;  // exponent + 3 mantissa bits: 8 bins per octave
 constexpr int NB2 = 32;        // bins of one exact-bisection round
 constexpr int kLog2NB2 = 5;
+constexpr int kUnroll = 4;     // candidates per lane in flight in the count/collect walks
 
 template <int D>
 struct Pow3 {
@@ -177,19 +178,37 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
 
   const uint64_t lane_lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
+  // Persistent schedule: one work queue per XCD.  Workgroups are dispatched
+  // round-robin over the 8 XCDs, so blockIdx % 8 names the XCD; queue x holds
+  // a contiguous (in cell order, so spatially local) eighth of the items,
+  // densest class first, which keeps each XCD's L2 on one region of the grid.
+  // An exhausted queue sends the wavefront on to the next XCD's queue.
+  int qx = (int)(blockIdx.x % kXcds);
+  int tried = 0;
   bool first = true;
   for (;;) {
     int64_t item;
     if (a.persistent) {
-      int v = 0;
-      if (lane == 0) v = atomicAdd(a.head, 1);
-      item = __shfl(v, 0, 64);
+      int64_t pos = -1;
+      while (tried < kXcds) {
+        int v = 0;
+        if (lane == 0) v = atomicAdd(&a.head[qx], 1);
+        v = __shfl(v, 0, 64);
+        if (a.qbeg[qx] + v < a.qbeg[qx + 1]) {
+          pos = a.qbeg[qx] + v;
+          break;
+        }
+        qx = (qx + 1) % kXcds;
+        ++tried;
+      }
+      if (pos < 0) break;
+      item = pos;
     } else {
       if (!first) break;
       item = a.item_base + (int64_t)blockIdx.x * nwaves + wave;
+      if (item >= a.n_items) break;
     }
     first = false;
-    if (item >= a.n_items) break;
     const int64_t it = a.order ? (int64_t)a.order[item] : item;
     const int64_t slot = it * G + g;
     const bool valid = slot < a.n_active;
@@ -235,11 +254,24 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
     {
       Cands cs;
       cs.init(rg, nr);
-      for (uint32_t v = l; v < C; v += T) {
-        const uint32_t p = cs.pos(v);
-        if ((int64_t)p != q) {
-          const int b = bin_of(sq_dist<DIM>(Xs, N, p, qx), thr, top);
-          if (b < NB) atomicAdd(&hist[b * G + g], 1u);
+      for (uint32_t v = l; v < C; v += T * kUnroll) {
+        // positions first, then all coordinate loads in flight together
+        uint32_t p[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const uint32_t vv = v + (uint32_t)(u * T);
+          p[u] = vv < C ? cs.pos(vv) : 0xFFFFFFFFu;
+        }
+        double d2[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          d2[u] = sq_dist<DIM>(Xs, N, p[u] != 0xFFFFFFFFu ? p[u] : 0u, qx);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (p[u] != 0xFFFFFFFFu && (int64_t)p[u] != q) {
+            const int b = bin_of(d2[u], thr, top);
+            if (b < NB) atomicAdd(&hist[b * G + g], 1u);
+          }
         }
       }
     }
@@ -376,10 +408,22 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
       Cands cs;
       cs.init(rg, nr);
       const uint32_t Cc = ok ? C : 0u;
-      for (uint32_t v = l; v < Cc; v += T) {
-        const uint32_t p = cs.pos(v);
-        if ((int64_t)p != q) {
-          const double d2 = sq_dist<DIM>(Xs, N, p, qx);
+      for (uint32_t v = l; v < Cc; v += T * kUnroll) {
+        uint32_t pp[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const uint32_t vv = v + (uint32_t)(u * T);
+          pp[u] = vv < Cc ? cs.pos(vv) : 0xFFFFFFFFu;
+        }
+        double dd[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          dd[u] = sq_dist<DIM>(Xs, N, pp[u] != 0xFFFFFFFFu ? pp[u] : 0u, qx);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const uint32_t p = pp[u];
+          if (p == 0xFFFFFFFFu || (int64_t)p == q) continue;
+          const double d2 = dd[u];
           const int b = bin_of(d2, thr, top);
           bool acc;
           if (refined)

@@ -3,8 +3,10 @@
 // search them against every point instead of growing eps further).
 //
 // The few remaining queries are searched against all N points with the whole
-// GPU: blocks cover (chunk of points) x (query).  The selection is the same as
-// in the grid kernel, but kept in global memory:
+// GPU: blocks cover (chunk of points) x (batch of QB queries); a thread keeps
+// its points' coordinates in registers and loops over the batch, so every
+// coordinate is read once per batch.  The selection is the grid kernel's, kept
+// in global memory:
 //   1. count pass: per-query histogram of log-spaced d^2 bins (16 octaves at 4
 //      bins per octave, ending at the squared bounding-box diagonal; every
 //      point is a candidate, so every query succeeds);
@@ -22,7 +24,8 @@ namespace knn {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kChunk = kBlock * 16;  // points per block
+constexpr int kChunk = kBlock * 8;      // points per block
+constexpr int QB = 32;                   // queries per block
 constexpr int TNB = 64;
 constexpr int kTailShift = 50;
 
@@ -33,37 +36,79 @@ __device__ __forceinline__ int tbin(double d2, int64_t top) {
   return k < 0 ? 0 : (k > TNB - 1 ? TNB - 1 : (int)k);
 }
 
-__device__ __forceinline__ double tail_d2(const double* __restrict__ X, int64_t N, int n,
-                                          int64_t p, const double* qx) {
+template <int DIM>
+__device__ __forceinline__ double tail_d2(const double* x, const double* qx) {
   double s = 0.0;
-  for (int j = 0; j < n; ++j) {
-    double t = __dsub_rn(X[(int64_t)j * N + p], qx[j]);
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    double t = __dsub_rn(x[j], qx[j]);
     s = __dadd_rn(s, __dmul_rn(t, t));
   }
   return s;
 }
 
-__device__ __forceinline__ void load_query(const TailArgs& a, int qi, double* qx, int64_t& qid) {
-  qid = a.q_ids[qi];
-  for (int j = 0; j < a.n; ++j) qx[j] = a.X[(int64_t)j * a.N + qid];
+// The batch's query coordinates and ids, staged in LDS.
+struct QBatch {
+  double x[QB][kMaxDims];
+  int64_t id[QB];
+  int nq;
+};
+
+__device__ __forceinline__ void load_batch(const TailArgs& a, QBatch& qb) {
+  const int q0 = blockIdx.y * QB;
+  const int nq = min(QB, a.A - q0);
+  if (threadIdx.x == 0) qb.nq = nq;
+  for (int i = threadIdx.x; i < nq; i += blockDim.x) {
+    const int64_t id = a.q_ids[q0 + i];
+    qb.id[i] = id;
+    for (int j = 0; j < a.n; ++j) qb.x[i][j] = a.X[(int64_t)j * a.N + id];
+  }
 }
 
-__global__ void k_tail_hist(const TailArgs a) {
-  __shared__ uint32_t h[TNB];
-  const int qi = blockIdx.y;
-  if (threadIdx.x < TNB) h[threadIdx.x] = 0;
+// Coordinates of this thread's points (PPT of them, strided by the block,
+// PPT * kBlock = kChunk), kept in registers.
+template <int DIM, int PPT>
+__device__ __forceinline__ void load_points(const TailArgs& a, int part, double (&px)[PPT][DIM],
+                                            int64_t (&pid)[PPT]) {
+  const int64_t p0 = (int64_t)blockIdx.x * kChunk + (int64_t)part * PPT * kBlock + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int64_t p = p0 + (int64_t)k * kBlock;
+    pid[k] = p < a.N ? p : -1;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) px[k][j] = p < a.N ? a.X[(int64_t)j * a.N + p] : 0.0;
+  }
+}
+template <int DIM>
+constexpr int ppt() { return DIM <= 3 ? 8 : 4; }
+
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_tail_hist(const TailArgs a) {
+  constexpr int PPT = ppt<DIM>();
+  __shared__ QBatch qb;
+  __shared__ uint32_t h[QB][TNB];
+  for (int i = threadIdx.x; i < QB * TNB; i += blockDim.x) h[i / TNB][i % TNB] = 0;
+  load_batch(a, qb);
   __syncthreads();
-  double qx[kMaxDims];
-  int64_t qid;
-  load_query(a, qi, qx, qid);
-  const int64_t p0 = (int64_t)blockIdx.x * kChunk;
-  const int64_t p1 = p0 + kChunk < a.N ? p0 + kChunk : a.N;
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
-    if (p == qid) continue;
-    atomicAdd(&h[tbin(tail_d2(a.X, a.N, a.n, p, qx), a.top)], 1u);
+  for (int part = 0; part < 8 / PPT; ++part) {
+    double px[PPT][DIM];
+    int64_t pid[PPT];
+    load_points<DIM, PPT>(a, part, px, pid);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      if (pid[k] < 0) continue;
+      for (int i = 0; i < qb.nq; ++i) {
+        if (pid[k] == qb.id[i]) continue;
+        atomicAdd(&h[i][tbin(tail_d2<DIM>(px[k], qb.x[i]), a.top)], 1u);
+      }
+    }
   }
   __syncthreads();
-  if (threadIdx.x < TNB && h[threadIdx.x]) atomicAdd(&a.hist[qi * TNB + threadIdx.x], h[threadIdx.x]);
+  const int q0 = blockIdx.y * QB;
+  for (int e = threadIdx.x; e < qb.nq * TNB; e += blockDim.x) {
+    const uint32_t v = h[e / TNB][e % TNB];
+    if (v) atomicAdd(&a.hist[(int64_t)(q0 + e / TNB) * TNB + e % TNB], v);
+  }
 }
 
 // One thread per query: selected bin, counts, mode and (for refinement) the
@@ -123,37 +168,52 @@ __global__ void k_tail_split(const TailArgs a) {
   }
 }
 
-__global__ void k_tail_refine_count(const TailArgs a) {
-  const int qi = blockIdx.y;
-  const TailState& st = a.state[qi];
-  if (st.mode != kRefine) return;
-  __shared__ uint32_t c4[4];
-  if (threadIdx.x < 4) c4[threadIdx.x] = 0;
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_tail_refine_count(const TailArgs a) {
+  constexpr int PPT = ppt<DIM>();
+  __shared__ QBatch qb;
+  __shared__ uint32_t c4[QB][4];
+  __shared__ int refining[QB];
+  __shared__ unsigned __int128 sA[QB], st4[QB][4];
+  __shared__ int any;
+  const int q0 = blockIdx.y * QB;
+  if (threadIdx.x == 0) any = 0;
   __syncthreads();
-  double qx[kMaxDims];
-  int64_t qid;
-  load_query(a, qi, qx, qid);
-  const unsigned __int128 A = st.A;
-  const unsigned __int128 t0 = st.t[0], t1 = st.t[1], t2 = st.t[2], t3 = st.t[3];
-  uint32_t c[4] = {0, 0, 0, 0};
-  const int64_t p0 = (int64_t)blockIdx.x * kChunk;
-  const int64_t p1 = p0 + kChunk < a.N ? p0 + kChunk : a.N;
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
-    if (p == qid) continue;
-    const double d2 = tail_d2(a.X, a.N, a.n, p, qx);
-    const unsigned __int128 k =
-        ((unsigned __int128)(uint64_t)__double_as_longlong(d2) << 32) | (uint32_t)p;
-    if (k >= A && k <= t3) {
-      c[0] += k <= t0;
-      c[1] += k <= t1;
-      c[2] += k <= t2;
-      c[3] += 1;
+  for (int i = threadIdx.x; i < QB; i += blockDim.x) {
+    const bool r = q0 + i < a.A && a.state[q0 + i].mode == kRefine;
+    refining[i] = r;
+    if (r) {
+      any = 1;
+      sA[i] = a.state[q0 + i].A;
+      for (int t = 0; t < 4; ++t) st4[i][t] = a.state[q0 + i].t[t];
+    }
+    for (int t = 0; t < 4; ++t) c4[i][t] = 0;
+  }
+  load_batch(a, qb);
+  __syncthreads();
+  if (!any) return;
+  for (int part = 0; part < 8 / PPT; ++part) {
+    double px[PPT][DIM];
+    int64_t pid[PPT];
+    load_points<DIM, PPT>(a, part, px, pid);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      if (pid[k] < 0) continue;
+      for (int i = 0; i < qb.nq; ++i) {
+        if (!refining[i] || pid[k] == qb.id[i]) continue;
+        const double d2 = tail_d2<DIM>(px[k], qb.x[i]);
+        const unsigned __int128 key =
+            ((unsigned __int128)(uint64_t)__double_as_longlong(d2) << 32) | (uint32_t)pid[k];
+        if (key >= sA[i] && key <= st4[i][3]) {
+          for (int t = 0; t < 4; ++t)
+            if (key <= st4[i][t]) atomicAdd(&c4[i][t], 1u);
+        }
+      }
     }
   }
-  for (int i = 0; i < 4; ++i)
-    if (c[i]) atomicAdd(&c4[i], c[i]);
   __syncthreads();
-  if (threadIdx.x < 4 && c4[threadIdx.x]) atomicAdd(&a.cnt[qi * 4 + threadIdx.x], c4[threadIdx.x]);
+  for (int e = threadIdx.x; e < qb.nq * 4; e += blockDim.x)
+    if (c4[e / 4][e % 4]) atomicAdd(&a.cnt[(int64_t)(q0 + e / 4) * 4 + e % 4], c4[e / 4][e % 4]);
 }
 
 __global__ void k_tail_refine_update(const TailArgs a) {
@@ -177,29 +237,46 @@ __global__ void k_tail_refine_update(const TailArgs a) {
     atomicAdd(&a.flag[0], 1);
 }
 
-__global__ void k_tail_collect(const TailArgs a) {
-  const int qi = blockIdx.y;
-  TailState& st = a.state[qi];
-  double qx[kMaxDims];
-  int64_t qid;
-  load_query(a, qi, qx, qid);
-  const int mode = st.mode, bsel = st.bsel;
-  const unsigned __int128 B = st.B;
-  const int64_t p0 = (int64_t)blockIdx.x * kChunk;
-  const int64_t p1 = p0 + kChunk < a.N ? p0 + kChunk : a.N;
-  for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock) {
-    if (p == qid) continue;
-    const double d2 = tail_d2(a.X, a.N, a.n, p, qx);
-    bool acc;
-    if (mode == kBin)
-      acc = tbin(d2, a.top) <= bsel;
-    else
-      acc = (((unsigned __int128)(uint64_t)__double_as_longlong(d2) << 32) | (uint32_t)p) <= B;
-    if (acc) {
-      const int slot = atomicAdd(&st.fill, 1);
-      if (slot < a.cap) {
-        a.buf_d[(int64_t)qi * a.cap + slot] = d2;
-        a.buf_i[(int64_t)qi * a.cap + slot] = (int32_t)p;
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_tail_collect(const TailArgs a) {
+  constexpr int PPT = ppt<DIM>();
+  __shared__ QBatch qb;
+  __shared__ int smode[QB], sbsel[QB];
+  __shared__ unsigned __int128 sB[QB];
+  const int q0 = blockIdx.y * QB;
+  for (int i = threadIdx.x; i < QB; i += blockDim.x) {
+    if (q0 + i < a.A) {
+      smode[i] = a.state[q0 + i].mode;
+      sbsel[i] = a.state[q0 + i].bsel;
+      sB[i] = a.state[q0 + i].B;
+    }
+  }
+  load_batch(a, qb);
+  __syncthreads();
+  for (int part = 0; part < 8 / PPT; ++part) {
+    double px[PPT][DIM];
+    int64_t pid[PPT];
+    load_points<DIM, PPT>(a, part, px, pid);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      if (pid[k] < 0) continue;
+      for (int i = 0; i < qb.nq; ++i) {
+        if (pid[k] == qb.id[i]) continue;
+        const double d2 = tail_d2<DIM>(px[k], qb.x[i]);
+        bool acc;
+        if (smode[i] == kBin)
+          acc = tbin(d2, a.top) <= sbsel[i];
+        else
+          acc = (((unsigned __int128)(uint64_t)__double_as_longlong(d2) << 32) |
+                 (uint32_t)pid[k]) <= sB[i];
+        if (acc) {
+          TailState& st = a.state[q0 + i];
+          const int slot = atomicAdd(&st.fill, 1);
+          if (slot < a.cap) {
+            a.buf_d[(int64_t)(q0 + i) * a.cap + slot] = d2;
+            a.buf_i[(int64_t)(q0 + i) * a.cap + slot] = (int32_t)pid[k];
+          }
+        }
       }
     }
   }
@@ -234,8 +311,20 @@ __global__ void k_tail_finish(const TailArgs a) {
 }  // namespace
 
 size_t tail_state_bytes(int64_t A, int cap) {
-  return (size_t)A * (sizeof(TailState) + TNB * 4 + 16 + (size_t)cap * 12) + 256;
+  return (size_t)A * (sizeof(TailState) + TNB * 4 + 16 + (size_t)cap * 12) + 6 * 256;
 }
+
+#define LAUNCH_DIM(kern, grid, args)                                           \
+  do {                                                                         \
+    switch ((args).n) {                                                        \
+      case 2: kern<2><<<grid, kBlock, 0, s>>>(args); break;                    \
+      case 3: kern<3><<<grid, kBlock, 0, s>>>(args); break;                    \
+      case 4: kern<4><<<grid, kBlock, 0, s>>>(args); break;                    \
+      case 5: kern<5><<<grid, kBlock, 0, s>>>(args); break;                    \
+      case 6: kern<6><<<grid, kBlock, 0, s>>>(args); break;                    \
+      default: throw Error(KNN_EINVAL, "dims out of range");                   \
+    }                                                                          \
+  } while (0)
 
 int tail_run(TailArgs a, char* scratch, hipStream_t s) {
   // carve the scratch: state, hist, cnt, flag, buffers
@@ -252,8 +341,8 @@ int tail_run(TailArgs a, char* scratch, hipStream_t s) {
   a.buf_d = reinterpret_cast<double*>(take((size_t)a.A * a.cap * 8));
   a.buf_i = reinterpret_cast<int32_t*>(take((size_t)a.A * a.cap * 4));
   KNN_HIP(hipMemsetAsync(a.hist, 0, (size_t)a.A * TNB * 4, s));
-  const dim3 grid((unsigned)ceil_div(a.N, kChunk), (unsigned)a.A);
-  k_tail_hist<<<grid, kBlock, 0, s>>>(a);
+  const dim3 grid((unsigned)ceil_div(a.N, kChunk), (unsigned)ceil_div(a.A, QB));
+  LAUNCH_DIM(k_tail_hist, grid, a);
   KNN_LAUNCHED();
   const int sb = (int)ceil_div(a.A, kBlock);
   KNN_HIP(hipMemsetAsync(a.flag, 0, 16, s));
@@ -266,7 +355,7 @@ int tail_run(TailArgs a, char* scratch, hipStream_t s) {
   while (nref > 0) {
     k_tail_split<<<sb, kBlock, 0, s>>>(a);
     KNN_LAUNCHED();
-    k_tail_refine_count<<<grid, kBlock, 0, s>>>(a);
+    LAUNCH_DIM(k_tail_refine_count, grid, a);
     KNN_LAUNCHED();
     KNN_HIP(hipMemsetAsync(a.flag, 0, 4, s));
     k_tail_refine_update<<<sb, kBlock, 0, s>>>(a);
@@ -276,7 +365,7 @@ int tail_run(TailArgs a, char* scratch, hipStream_t s) {
     ++rounds;
     KNN_CHECK(rounds < 200, KNN_EINTERNAL, "tail refinement did not converge");
   }
-  k_tail_collect<<<grid, kBlock, 0, s>>>(a);
+  LAUNCH_DIM(k_tail_collect, grid, a);
   KNN_LAUNCHED();
   k_tail_finish<<<(unsigned)ceil_div(a.A, 4), kBlock, 0, s>>>(a);
   KNN_LAUNCHED();
