@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--w-factor", type=float, default=0.0)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the (untimed) knn_autotune pass before the timed steps")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -129,6 +131,19 @@ def main():
                     record.append((name, K, st))
             idx.close()
 
+    # autotuner (untimed, like a warmup): measures the level-0 cell side and
+    # the growth of the cell side per (dims, K, N) class and caches the best
+    tuned = []
+    if not args.no_autotune and not (args.lanes or args.w_factor):
+        for name, Ks in plan:
+            idx = api.build_index(dev[name], stream=stream)
+            for K in Ks:
+                r = idx.autotune(K, stream=stream)
+                tuned.append(dict(dataset=name, K=K, w_factor=round(r["w_factor"], 3),
+                                  growth=round(r["growth"], 4),
+                                  ms_default=round(r["ms_default"], 3),
+                                  ms_tuned=round(r["ms_best"], 3)))
+            idx.close()
     for _ in range(args.warmup):
         one_step(None)
     torch.cuda.synchronize()
@@ -195,6 +210,7 @@ def main():
                      "avg_launch_ms": round(search_ms / max(1, search_launches), 4),
                      "launches": search_launches},
         "cases": cases,
+        "autotune": tuned,
     }
     if not args.no_cpu_baseline:
         flat = [(name, K) for name, Ks in plan for K in Ks]

@@ -100,8 +100,8 @@ typedef struct knn_join_opts {
                              1 one launch per batch, cell order [0] */
   int32_t batch_queries;  /* schedule 1: queries per launch, 0 = all [0] */
   double eps_step;        /* linear growth step, multiple of eps_min [0.5] (Alg. 1) */
-  int32_t linear_levels;  /* linear growths before geometric growth [2] */
-  double growth;          /* geometric growth factor of the cell side [2.0] */
+  int32_t linear_levels;  /* linear growths before geometric growth [1]; < 0: none */
+  double growth;          /* geometric growth factor of the cell side [16^(1/dims)] */
   int32_t use_graph;      /* capture the per-level launch sequence in a HIP graph [0] */
   double tail_pairs;      /* brute-force tail once (remaining queries) x N <= this
                              [1.5e9]; < 0 disables the tail (Sec. 5.3.8 remedy) */
@@ -176,6 +176,29 @@ typedef struct knn_index_info {
   int64_t device_bytes;   /* device memory held by the index right now */
 } knn_index_info;
 int knn_index_info_get(const knn_index* idx, knn_index_info* out);
+
+/* ------------------------------------------------------------------------
+ * Autotuner.  The level-0 cell side (as a multiple of eps_min(K)) and the
+ * geometric growth of the cell side between levels decide how many queries
+ * fail at each level and how many candidates the rest scan; the best
+ * setting depends on the data.  knn_autotune measures joins of (idx, K) on
+ * a grid of both, keeps the fastest in a process-wide cache keyed by the
+ * workload class (dims, K rounded to a power of two, N to a power of 4), and
+ * later joins whose options leave w_factor / growth zero use it.
+ * ------------------------------------------------------------------------ */
+typedef struct knn_autotune_result {
+  double w_factor;    /* chosen level-0 cell side / eps_min(K) */
+  double growth;      /* chosen geometric growth of the cell side */
+  double ms_best;     /* best join time measured (ms) */
+  double ms_default;  /* join time of the untuned default (ms) */
+  int32_t trials;     /* settings measured */
+} knn_autotune_result;
+/* Runs on `stream` (device scratch allocated internally); blocks. */
+int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* out);
+/* Save / load the cache as text ("dims kbucket nbucket w_factor growth
+ * lanes" per line); path NULL = $KNN_AUTOTUNE_CACHE. */
+int knn_autotune_save(const char* path);
+int knn_autotune_load(const char* path);
 
 /* Upper bound of the device bytes one self-join of (idx, K) with host
  * outputs allocates beyond the index (the serving loop's admission size). */

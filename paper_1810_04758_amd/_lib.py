@@ -72,6 +72,11 @@ class IndexInfo(ctypes.Structure):
                 ("device_bytes", c_i64)]
 
 
+class AutotuneResult(ctypes.Structure):
+    _fields_ = [("w_factor", c_f64), ("growth", c_f64), ("ms_best", c_f64),
+                ("ms_default", c_f64), ("trials", c_i32)]
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", c_u64), ("max_inflight", c_i32), ("max_queue", c_i32),
                 ("device", c_i32)]
@@ -100,6 +105,9 @@ SIGNATURES = {
     "knn_index_info_get": (ctypes.c_int, [c_p, ctypes.POINTER(IndexInfo)]),
     "knn_eps_min": (ctypes.c_int, [c_p, c_i32, ctypes.POINTER(c_f64)]),
     "knn_join_footprint": (ctypes.c_int, [c_p, c_i32, ctypes.POINTER(c_u64)]),
+    "knn_autotune": (ctypes.c_int, [c_p, c_i32, c_p, ctypes.POINTER(AutotuneResult)]),
+    "knn_autotune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "knn_autotune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "knn_grid_export": (ctypes.c_int, [c_p, c_f64, c_p, c_p, c_p, c_p, c_p, c_p,
                                        ctypes.POINTER(c_i64)]),
     "knn_sample_mean_dist": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_i64,

@@ -94,6 +94,12 @@ class Index:
         check(load().knn_eps_min(self.handle, K, ctypes.byref(v)))
         return v.value
 
+    def autotune(self, K, stream=None):
+        """knn_autotune: measure and cache the best (w_factor, growth) for K."""
+        r = _lib.AutotuneResult()
+        check(load().knn_autotune(self.handle, K, _stream_ptr(stream), ctypes.byref(r)))
+        return {f: getattr(r, f) for f, _ in _lib.AutotuneResult._fields_}
+
     def join_footprint(self, K):
         """knn_join_footprint: device bytes a host-output join of K allocates."""
         v = ctypes.c_uint64()
@@ -253,3 +259,13 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def autotune_save(path=None):
+    """knn_autotune_save: write the autotune cache (path None: $KNN_AUTOTUNE_CACHE)."""
+    check(load().knn_autotune_save(path.encode() if path else None))
+
+
+def autotune_load(path=None):
+    """knn_autotune_load: read an autotune cache file."""
+    check(load().knn_autotune_load(path.encode() if path else None))

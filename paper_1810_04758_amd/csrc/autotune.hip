@@ -1,5 +1,6 @@
-// autotune.hip -- cache of measured (cell-side factor, lanes per query)
-// settings per workload class, with fixed fallback rules.
+// autotune.hip -- cache of measured join settings per workload class, with
+// fixed fallbacks.  The measurements themselves (knn_autotune) live with the
+// join in index.hip.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -8,7 +9,6 @@
 #include <tuple>
 
 #include "autotune.hpp"
-#include "kernels.hpp"
 
 namespace knn {
 
@@ -16,13 +16,9 @@ namespace {
 
 // Workload class: dims, K bucket (power of two), N bucket (power of 4).
 using Class = std::tuple<int, int, int>;
-struct Entry {
-  double w_factor;
-  int lanes;
-};
 
 std::mutex g_mu;
-std::map<Class, Entry> g_cache;
+std::map<Class, TuneEntry> g_cache;
 bool g_loaded = false;
 
 int log2_bucket(int64_t v) {
@@ -35,44 +31,45 @@ Class class_of(int dims, int K, int64_t N) {
   return Class(dims, log2_bucket(K), log2_bucket(N) / 2);
 }
 
-void ensure_loaded() {
-  if (g_loaded) return;
-  g_loaded = true;
-  const char* p = std::getenv("KNN_AUTOTUNE_CACHE");
+void load_file_locked(const char* p) {
   if (!p || !*p) return;
   FILE* f = std::fopen(p, "r");
   if (!f) return;
   int d, kb, nb, lanes;
-  double wf;
-  while (std::fscanf(f, "%d %d %d %lf %d", &d, &kb, &nb, &wf, &lanes) == 5)
-    g_cache[Class(d, kb, nb)] = Entry{wf, lanes};
+  double wf, gr;
+  while (std::fscanf(f, "%d %d %d %lf %lf %d", &d, &kb, &nb, &wf, &gr, &lanes) == 6)
+    g_cache[Class(d, kb, nb)] = TuneEntry{wf, gr, lanes};
   std::fclose(f);
+}
+
+void ensure_loaded_locked() {
+  if (g_loaded) return;
+  g_loaded = true;
+  load_file_locked(std::getenv("KNN_AUTOTUNE_CACHE"));
 }
 
 }  // namespace
 
-int autotune_lanes(int dims, int K, int64_t N) {
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    ensure_loaded();
-    auto it = g_cache.find(class_of(dims, K, N));
-    if (it != g_cache.end() && it->second.lanes > 0) return it->second.lanes;
-  }
-  return 0;  // no measurement: chosen per level from the candidate counts
+TuneEntry autotune_get(int dims, int K, int64_t N) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  ensure_loaded_locked();
+  auto it = g_cache.find(class_of(dims, K, N));
+  return it != g_cache.end() ? it->second : TuneEntry{0.0, 0.0, 0};
 }
+
+int autotune_lanes(int dims, int K, int64_t N) { return autotune_get(dims, K, N).lanes; }
 
 double autotune_w_factor(int dims, int K, int64_t N) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  ensure_loaded();
-  auto it = g_cache.find(class_of(dims, K, N));
-  if (it != g_cache.end() && it->second.w_factor > 0) return it->second.w_factor;
-  return 1.0;
+  const double f = autotune_get(dims, K, N).w_factor;
+  return f > 0 ? f : 1.0;
 }
 
-void autotune_store(int dims, int K, int64_t N, double w_factor, int lanes) {
+double autotune_growth(int dims, int K, int64_t N) { return autotune_get(dims, K, N).growth; }
+
+void autotune_store(int dims, int K, int64_t N, const TuneEntry& e) {
   std::lock_guard<std::mutex> lk(g_mu);
-  ensure_loaded();
-  g_cache[class_of(dims, K, N)] = Entry{w_factor, lanes};
+  ensure_loaded_locked();
+  g_cache[class_of(dims, K, N)] = e;
 }
 
 int autotune_load(const char* path) {
@@ -82,11 +79,8 @@ int autotune_load(const char* path) {
   if (!p) return -1;
   FILE* f = std::fopen(p, "r");
   if (!f) return -1;
-  int d, kb, nb, lanes;
-  double wf;
-  while (std::fscanf(f, "%d %d %d %lf %d", &d, &kb, &nb, &wf, &lanes) == 5)
-    g_cache[Class(d, kb, nb)] = Entry{wf, lanes};
   std::fclose(f);
+  load_file_locked(p);
   return 0;
 }
 
@@ -97,10 +91,16 @@ int autotune_save(const char* path) {
   FILE* f = std::fopen(p, "w");
   if (!f) return -1;
   for (auto& kv : g_cache)
-    std::fprintf(f, "%d %d %d %.17g %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
-                 std::get<2>(kv.first), kv.second.w_factor, kv.second.lanes);
+    std::fprintf(f, "%d %d %d %.17g %.17g %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                 std::get<2>(kv.first), kv.second.w_factor, kv.second.growth, kv.second.lanes);
   std::fclose(f);
   return 0;
+}
+
+void autotune_clear() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache.clear();
+  g_loaded = true;
 }
 
 }  // namespace knn

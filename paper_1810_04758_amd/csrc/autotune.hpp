@@ -1,22 +1,32 @@
-// autotune.hpp -- choice of the level-0 cell-side factor and of the lanes per
-// query (the paper's t, Sec. 4.7) for a workload class, from a cache filled by
-// knn_autotune() measurements, with fixed rules as the fallback.
+// autotune.hpp -- cache of measured join settings per workload class: the
+// level-0 cell-side factor (cell side = factor * eps_min(K), Sec. 4.4), the
+// geometric growth of the cell side between levels, and the lanes per query
+// of level 0 (the paper's t, Sec. 4.7).  Filled by knn_autotune()
+// measurements; fixed rules are the fallback.
 #pragma once
 
 #include <cstdint>
 
 namespace knn {
 
-// Lanes per query of level 0 for (dims, K, N): cached measurement, else 0
-// (the join then picks it from the level's candidate counts).
+struct TuneEntry {
+  double w_factor;  // 0 = no measurement
+  double growth;    // 0 = no measurement
+  int lanes;        // 0 = chosen per level from the candidate counts
+};
+
+// Cached entry for the class of (dims, K, N), or all zeros.
+TuneEntry autotune_get(int dims, int K, int64_t N);
+// Level-0 lanes (0 if none cached), cell-side factor (1 if none cached: the
+// paper's choice, cell side = eps_min) and growth (0 if none cached).
 int autotune_lanes(int dims, int K, int64_t N);
-// Cell side as a multiple of eps_min(K): cached measurement, else 1 (the
-// paper's choice, cell side = eps_min).
 double autotune_w_factor(int dims, int K, int64_t N);
+double autotune_growth(int dims, int K, int64_t N);
 // Records a measured best setting for the class of (dims, K, N).
-void autotune_store(int dims, int K, int64_t N, double w_factor, int lanes);
+void autotune_store(int dims, int K, int64_t N, const TuneEntry& e);
 // Loads / saves the cache file (path from KNN_AUTOTUNE_CACHE when path is NULL).
 int autotune_load(const char* path);
 int autotune_save(const char* path);
+void autotune_clear();
 
 }  // namespace knn

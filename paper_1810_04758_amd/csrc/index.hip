@@ -241,12 +241,15 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   return b;
 }
 
-// Lanes per query for a level whose active queries see `cand` candidates on
-// average: about 32 candidates per lane, and at least enough lanes that the
-// per-wave LDS buffers stay within 16 KiB.
-static int lanes_for(double cand, int cap) {
-  int T = 1;
-  while (T < 64 && (double)T * 32.0 < cand) T *= 2;
+// Lanes per query for a level of A active queries that see `cand` candidates
+// on average (measured on MI355X over t in 2..64 and 2-6 dims): the power of
+// two nearest cand^0.6 / 4, raised until the level has enough lanes to fill
+// the GPU (A * t >= 2^18) and the per-wave LDS buffers stay within 16 KiB.
+static int lanes_for(double cand, int64_t A, int cap) {
+  const double want = std::pow(std::max(cand, 1.0), 0.6) / 4.0;
+  int T = 2;
+  while (T < 64 && (double)T * 1.41421356 < want) T *= 2;
+  while (T < 64 && (double)A * T < (double)(1 << 18)) T *= 2;
   while (T < 64 && search_lds_per_wave(T, cap) > 16384) T *= 2;
   return T;
 }
@@ -274,8 +277,15 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   if (!(w > 0) || !std::isfinite(w)) w = ext > 0 ? ext * 1e-6 : 1.0;
   const double w0 = w;
   const double step = (o.eps_step > 0 ? o.eps_step : 0.5) * w0;
-  const int linear = o.linear_levels > 0 ? o.linear_levels : (o.linear_levels < 0 ? 0 : 2);
-  const double growth = o.growth > 1.0 ? o.growth : 2.0;
+  // growth: the paper's linear step (eps += eps_step * eps_min) for the first
+  // `linear` re-indexes, then geometric growth whose default multiplies the
+  // scanned volume by 16 per level (the non-linear expansion Sec. 5.3.8
+  // proposes for the GPU-Only tail)
+  const int linear = o.linear_levels > 0 ? o.linear_levels : (o.linear_levels < 0 ? 0 : 1);
+  const double tuned_growth = o.growth > 1.0 ? 0.0 : autotune_growth(idx.n, K, idx.N);
+  const double growth = o.growth > 1.0 ? o.growth
+                        : tuned_growth > 1.0 ? tuned_growth
+                                             : std::pow(16.0, 1.0 / idx.n);
 
   const int T_fixed = o.lanes_per_query;
   KNN_CHECK(T_fixed == 0 || (T_fixed >= 1 && T_fixed <= 64 && (T_fixed & (T_fixed - 1)) == 0),
@@ -351,7 +361,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       cand = (double)tot / (double)std::max<int64_t>(A, 1);
     }
     int T = T_fixed;
-    if (T == 0) T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(cand, cap);
+    if (T == 0) T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(cand, A, cap);
     const int G = 64 / T;
     const int waves = search_waves_per_block(T, cap);
     // work items, densest first (Sec. 4.5 work estimate; persistent schedule)
@@ -392,6 +402,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       a.g[j] = c.gg.g[j];
     }
     a.inv_w = c.gg.inv_w;
+    a.w = 1.0 / c.gg.inv_w;
     a.margin = (8.0 * (double)c.gg.g_max + 4.0 * idx.n + 32.0) * std::ldexp(1.0, -53);
     a.K = K;
     a.cap = cap;
@@ -401,8 +412,13 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.fail_count = c.iscal.p + 8;
     a.refine_count = c.iscal.p + 9;
     if (o.schedule == 0) {
+      // persistent grid: exactly what can be resident at once
       int64_t want = ceil_div(n_items, waves);
-      int blocks = (int)std::min<int64_t>(want, (int64_t)ncu * 16);
+      int blocks = (int)std::min<int64_t>(want, (int64_t)ncu * search_blocks_per_cu(idx.n, T, cap));
+      // about four pops per wavefront and queue: few atomics, fine enough
+      // granularity for the dense-first balance at the end of each queue
+      const int64_t total_waves = (int64_t)blocks * waves;
+      a.grain = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, n_items / (total_waves * 4)));
       launch_search(a, idx.n, T, blocks, s);
     } else {
       // one launch per batch of queries, cell order, one item per wavefront
@@ -706,6 +722,63 @@ int knn_index_info_get(const knn_index* idx, knn_index_info* out) {
     out->n_sample = idx->n_sample;
     out->device_bytes = (int64_t)idx->X.bytes() + (idx->ctx ? idx->ctx->ctx.device_bytes() : 0);
   });
+}
+
+int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* out) {
+  return guarded([&] {
+    validate_join(idx, K);
+    KNN_CHECK(out != nullptr, KNN_EINVAL, "NULL pointer");
+    BusyGuard bg(idx);
+    DeviceGuard dg(idx->device);
+    hipStream_t s = (hipStream_t)stream;
+    JoinContext& c = index_ctx(idx);
+    const size_t NK = (size_t)idx->N * K;
+    c.out_ids.reserve(NK);
+    c.out_d.reserve(NK);
+    auto time_join = [&](double wf, double gr) {
+      double best = 1e300;
+      for (int rep = 0; rep < 2; ++rep) {
+        knn_join_opts o{};
+        o.w_factor = wf;
+        o.growth = gr;
+        KNN_HIP(hipStreamSynchronize(s));
+        auto t0 = std::chrono::steady_clock::now();
+        self_join(*idx, c, K, c.out_ids.p, c.out_d.p, o, s);
+        KNN_HIP(hipStreamSynchronize(s));
+        best = std::min(best, std::chrono::duration<double, std::milli>(
+                                  std::chrono::steady_clock::now() - t0).count());
+      }
+      return best;
+    };
+    const double n = (double)idx->n;
+    const double wfs[] = {0.7, 1.0, 1.4, 2.0};
+    const double grs[] = {std::pow(4.0, 1.0 / n), std::pow(16.0, 1.0 / n), std::pow(64.0, 1.0 / n)};
+    std::memset(out, 0, sizeof(*out));
+    out->ms_default = time_join(1.0, std::pow(16.0, 1.0 / n));
+    out->ms_best = out->ms_default;
+    out->w_factor = 1.0;
+    out->growth = std::pow(16.0, 1.0 / n);
+    out->trials = 1;
+    for (double wf : wfs)
+      for (double gr : grs) {
+        const double ms = time_join(wf, gr);
+        ++out->trials;
+        if (ms < out->ms_best) {
+          out->ms_best = ms;
+          out->w_factor = wf;
+          out->growth = gr;
+        }
+      }
+    autotune_store(idx->n, K, idx->N, TuneEntry{out->w_factor, out->growth, 0});
+  });
+}
+
+int knn_autotune_save(const char* path) {
+  return guarded([&] { KNN_CHECK(autotune_save(path) == 0, KNN_EINVAL, "cannot write the cache"); });
+}
+
+int knn_autotune_load(const char* path) {
+  return guarded([&] { KNN_CHECK(autotune_load(path) == 0, KNN_EINVAL, "cannot read the cache"); });
 }
 
 int knn_join_footprint(const knn_index* idx, int32_t K, uint64_t* bytes) {

@@ -114,9 +114,11 @@ struct SearchArgs {
   int64_t item_base;       // first item of this launch (schedule 1)
   int32_t* head;           // persistent work-queue heads, one per XCD (device)
   int64_t qbeg[kXcds + 1]; // queue x = order positions [qbeg[x], qbeg[x+1])
+  int32_t grain;           // items claimed per queue pop
   int32_t persistent;
   double lo[kMaxDims];
   double inv_w;
+  double w;                // fl(1 / inv_w)
   int64_t g[kMaxDims];
   double margin;           // relative shrink of the covered radius (rounding)
   int32_t K;
@@ -133,5 +135,7 @@ void launch_search(const SearchArgs& a, int dims, int lanes_per_query, int grid_
 // Dynamic LDS bytes per wave for a given (lanes_per_query, cap).
 size_t search_lds_per_wave(int lanes_per_query, int cap);
 int search_waves_per_block(int lanes_per_query, int cap);
+// Resident blocks per CU of the search kernel (occupancy API).
+int search_blocks_per_cu(int dims, int lanes_per_query, int cap);
 
 }  // namespace knn

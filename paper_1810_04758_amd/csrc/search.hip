@@ -48,6 +48,7 @@ constexpr int kBinShift = 49;  // exponent + 3 mantissa bits: 8 bins per octave
 constexpr int NB2 = 32;        // bins of one exact-bisection round
 constexpr int kLog2NB2 = 5;
 constexpr int kUnroll = 4;     // candidates per lane in flight in the count/collect walks
+constexpr int kFailBuf = 64;   // failed ids buffered per wavefront before one global append
 
 template <int D>
 struct Pow3 {
@@ -149,6 +150,16 @@ struct Cands {
   }
 };
 
+// Appends the wavefront's buffered failed ids to the global failure list.
+__device__ __forceinline__ void flush_failures(const SearchArgs& a, const int32_t* fbuf, int nfail,
+                                               int lane) {
+  int base = 0;
+  if (lane == 0) base = atomicAdd(a.fail_count, nfail);
+  base = __shfl(base, 0, 64);
+  for (int i = lane; i < nfail; i += 64) a.fail_list[base + i] = fbuf[i];
+  wave_fence();
+}
+
 template <int DIM, int T>
 __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
   constexpr int G = 64 / T;  // queries per wave
@@ -169,12 +180,15 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
   // per-wave LDS: survivors d2 [cap][G], survivor ids [cap][G], histogram
   // [NB][G]; the refinement histogram [NB2][G] reuses the d2 area (it is free
   // before the collect, and cap >= NB2/2 + 1).
+  // Layout: [d2 of all waves][ids of all waves][histograms][failure buffers].
+  int32_t* bi_base = reinterpret_cast<int32_t*>(smem + (size_t)nwaves * cap * G);
+  uint32_t* hist_base = reinterpret_cast<uint32_t*>(bi_base + (size_t)nwaves * cap * G);
+  int32_t* fbuf_base = reinterpret_cast<int32_t*>(hist_base + (size_t)nwaves * NB * G);
   double* bd = smem + (size_t)wave * cap * G;
-  int32_t* bi = reinterpret_cast<int32_t*>(smem + (size_t)nwaves * cap * G) + (size_t)wave * cap * G;
-  uint32_t* hist = reinterpret_cast<uint32_t*>(reinterpret_cast<int32_t*>(smem + (size_t)nwaves * cap * G) +
-                                               (size_t)nwaves * cap * G) +
-                   (size_t)wave * NB * G;
+  int32_t* bi = bi_base + (size_t)wave * cap * G;
+  uint32_t* hist = hist_base + (size_t)wave * NB * G;
   uint32_t* hist2 = reinterpret_cast<uint32_t*>(bd);
+  int32_t* fbuf = fbuf_base + (size_t)wave * kFailBuf;
 
   const uint64_t lane_lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
@@ -183,26 +197,37 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
   // a contiguous (in cell order, so spatially local) eighth of the items,
   // densest class first, which keeps each XCD's L2 on one region of the grid.
   // An exhausted queue sends the wavefront on to the next XCD's queue.
+  // Pops claim `grain` consecutive items at a time, so the queue heads see one
+  // atomic per grain, not per item.
   int qx = (int)(blockIdx.x % kXcds);
   int tried = 0;
+  int64_t cur = 0, end = 0;  // claimed order positions [cur, end)
   bool first = true;
+  // Failed query ids are buffered per wavefront in LDS and appended to the
+  // global list kFailBuf at a time (one atomic per flush).
+  int nfail = 0;
   for (;;) {
     int64_t item;
     if (a.persistent) {
-      int64_t pos = -1;
-      while (tried < kXcds) {
+      while (cur >= end && tried < kXcds) {
         int v = 0;
-        if (lane == 0) v = atomicAdd(&a.head[qx], 1);
-        v = __shfl(v, 0, 64);
-        if (a.qbeg[qx] + v < a.qbeg[qx + 1]) {
-          pos = a.qbeg[qx] + v;
-          break;
+        if (lane == 0) {
+          // a plain load first: drained queues cost no atomic
+          v = __hip_atomic_load(&a.head[qx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (a.qbeg[qx] + v < a.qbeg[qx + 1]) v = atomicAdd(&a.head[qx], a.grain);
         }
-        qx = (qx + 1) % kXcds;
-        ++tried;
+        v = __shfl(v, 0, 64);
+        const int64_t b = a.qbeg[qx] + v;
+        if (b < a.qbeg[qx + 1]) {
+          cur = b;
+          end = min(b + (int64_t)a.grain, a.qbeg[qx + 1]);
+        } else {
+          qx = (qx + 1) % kXcds;
+          ++tried;
+        }
       }
-      if (pos < 0) break;
-      item = pos;
+      if (cur >= end) break;
+      item = cur++;
     } else {
       if (!first) break;
       item = a.item_base + (int64_t)blockIdx.x * nwaves + wave;
@@ -238,10 +263,9 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
       // the scanned cells hold every point: all candidates count; the bins end
       // at the squared diagonal of the 3^n block
       thr = INFINITY;
-      double w = 1.0 / a.inv_w;
-      ref = 9.0 * DIM * w * w;
+      ref = 9.0 * DIM * a.w * a.w;
     } else {
-      double base = (1.0 + mfrac) / a.inv_w;
+      double base = (1.0 + mfrac) * a.w;
       double r = base * (1.0 - a.margin);
       thr = r * r;
       ref = thr;
@@ -307,15 +331,19 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
     const bool fail = valid && bsel == NB;
     const bool ok = valid && bsel < NB;
 
-    // ---- failures: re-queue (wave-aggregated append) ----------------------------
+    // ---- failures: re-queue (buffered per wavefront) ------------------------------
     {
       const bool lf = fail && l == 0;
       const uint64_t fm = __ballot(lf);
       if (fm) {
-        int base = 0;
-        if (lane == 0) base = atomicAdd(a.fail_count, (int)__popcll(fm));
-        base = __shfl(base, 0, 64);
-        if (lf) a.fail_list[base + (int)__popcll(fm & lane_lt)] = perm[q];
+        const int nf = (int)__popcll(fm);
+        if (nfail + nf > kFailBuf) {
+          flush_failures(a, fbuf, nfail, lane);
+          nfail = 0;
+        }
+        if (lf) fbuf[nfail + (int)__popcll(fm & lane_lt)] = perm[q];
+        nfail += nf;
+        wave_fence();
       }
     }
 
@@ -472,6 +500,27 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
     }
     wave_fence();
   }
+  if (nfail > 0) flush_failures(a, fbuf, nfail, lane);
+}
+
+template <int DIM, int T>
+int occupancy_of(int threads, size_t lds) {
+  int n = 0;
+  KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<DIM, T>, threads, lds));
+  return n;
+}
+
+template <int DIM>
+int occupancy_dim(int T, int threads, size_t lds) {
+  switch (T) {
+    case 1: return occupancy_of<DIM, 1>(threads, lds);
+    case 2: return occupancy_of<DIM, 2>(threads, lds);
+    case 4: return occupancy_of<DIM, 4>(threads, lds);
+    case 8: return occupancy_of<DIM, 8>(threads, lds);
+    case 16: return occupancy_of<DIM, 16>(threads, lds);
+    case 32: return occupancy_of<DIM, 32>(threads, lds);
+    default: return occupancy_of<DIM, 64>(threads, lds);
+  }
 }
 
 template <int DIM>
@@ -492,7 +541,8 @@ void launch_dim(const SearchArgs& a, int T, int blocks, int threads, size_t lds,
 
 size_t search_lds_per_wave(int T, int cap) {
   const int G = 64 / T;
-  return (size_t)cap * G * (sizeof(double) + sizeof(int32_t)) + (size_t)NB * G * sizeof(uint32_t);
+  return (size_t)cap * G * (sizeof(double) + sizeof(int32_t)) + (size_t)NB * G * sizeof(uint32_t) +
+         (size_t)kFailBuf * sizeof(int32_t);
 }
 
 int search_waves_per_block(int T, int cap) {
@@ -501,6 +551,21 @@ int search_waves_per_block(int T, int cap) {
   if (w > 4) w = 4;
   if (w < 1) w = 1;
   return w;
+}
+
+int search_blocks_per_cu(int dims, int T, int cap) {
+  const int waves = search_waves_per_block(T, cap);
+  const size_t lds = search_lds_per_wave(T, cap) * waves;
+  int n = 1;
+  switch (dims) {
+    case 2: n = occupancy_dim<2>(T, waves * 64, lds); break;
+    case 3: n = occupancy_dim<3>(T, waves * 64, lds); break;
+    case 4: n = occupancy_dim<4>(T, waves * 64, lds); break;
+    case 5: n = occupancy_dim<5>(T, waves * 64, lds); break;
+    case 6: n = occupancy_dim<6>(T, waves * 64, lds); break;
+    default: break;
+  }
+  return n > 0 ? n : 1;
 }
 
 void launch_search(const SearchArgs& a, int dims, int T, int grid_blocks, hipStream_t s) {

@@ -181,6 +181,25 @@ def test_edge_cases(knn, oracle_mod, case):
     _check_rows(D, ids, dists, K, np.arange(D.shape[0]), oracle_mod)
 
 
+def test_autotune_keeps_results_and_roundtrips(knn, oracle_mod, tmp_path):
+    import torch
+    D = datagen.exponential(6000, 3, seed=36)
+    _say("[autotune]")
+    idx = knn.build_index(torch.from_numpy(D).cuda())
+    r = idx.autotune(10)
+    assert r["trials"] == 13 and r["ms_best"] <= r["ms_default"]
+    assert r["w_factor"] > 0 and r["growth"] > 1
+    ids, dists = idx.self_join(10)  # uses the cached setting
+    torch.cuda.synchronize()
+    idx.close()
+    _check_rows(D, ids.cpu().numpy(), dists.cpu().numpy(), 10, np.arange(6000), oracle_mod)
+    path = str(tmp_path / "tune.txt")
+    knn.autotune_save(path)
+    line = open(path).read().split()
+    assert len(line) % 6 == 0 and len(line) >= 6
+    knn.autotune_load(path)
+
+
 def test_invalid_arguments(knn):
     import torch
     from paper_1810_04758_amd._lib import KnnError, KNN_EINVAL
