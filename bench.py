@@ -76,6 +76,56 @@ def cpu_baseline(datasets, cases, budget_s=12.0):
                       ", ".join(sample_desc) + f" ({done} queries, {t_total:.1f} s wall)"}
 
 
+def serving_leg(api, seconds, rate=200.0, budget_gib=96, inflight=4):
+    """The serving workload: a Poisson stream (mean `rate` requests/s for
+    `seconds`) of self-join requests over 24 resident datasets (N log-uniform
+    in [1e4, 1e7], dims in {2,3,4,6}, uniform or exponential coordinates, K in
+    {1,4,16,64}), admitted by device-memory footprint and run concurrently.
+    Latency is submit -> results ready; most requests are latency-only
+    (results discarded on the device), every 25th is copied back and compared
+    with a solo join of the same index and K."""
+    from paper_1810_04758_amd import datagen
+    t_build = time.perf_counter()
+    pool = datagen.serving_pool()
+    idxs = [api.build_index(D) for D, _ in pool]
+    t_build = time.perf_counter() - t_build
+    arrivals, ds, ks = datagen.serving_trace(seconds, rate, len(pool))
+    srv = api.Server(mem_budget_bytes=budget_gib << 30, max_inflight=inflight)
+    for ix in idxs:
+        srv.add_dataset(ix)
+    checks = []
+    tickets = []
+    t0 = time.perf_counter()
+    for i, (ta, d, k) in enumerate(zip(arrivals, ds, ks)):
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        N = pool[d][0].shape[0]
+        keep = (i % 25 == 0) and N <= 1_000_000
+        tickets.append((srv.submit(int(d), int(k), N, discard=not keep), int(d), int(k), keep))
+    for t, d, k, keep in tickets:
+        ids, dists = srv.wait(t)
+        if keep:
+            checks.append((d, k, ids, dists))
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    same = True
+    for d, k, ids, dists in checks:
+        ref_i, ref_d = idxs[d].self_join_host(k)
+        same = same and bool((ref_i == ids).all() and (ref_d == dists).all())
+    for ix in idxs:
+        ix.close()
+    return {"requests": int(st["completed"]), "trace_seconds": seconds, "rate_per_s": rate,
+            "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
+            "mean_ms": round(st["mean_ms"], 2), "queries_per_s": round(st["queries_per_s"], 1),
+            "requests_per_s": round(st["requests_per_s"], 2), "wall_s": round(wall, 2),
+            "peak_inflight": int(st["peak_inflight"]), "peak_bytes": int(st["peak_bytes"]),
+            "mix_equals_solo_checked": len(checks), "mix_equals_solo": same,
+            "index_build_s": round(t_build, 2),
+            "datasets": [desc for _, desc in pool]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +138,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the (untimed) knn_autotune pass before the timed steps")
+    ap.add_argument("--serving-seconds", type=float, default=2.0,
+                    help="length of the serving trace (0 = skip the serving leg)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -212,6 +264,8 @@ def main():
         "cases": cases,
         "autotune": tuned,
     }
+    if args.serving_seconds > 0:
+        out["serving"] = serving_leg(api, args.serving_seconds)
     if not args.no_cpu_baseline:
         flat = [(name, K) for name, Ks in plan for K in Ks]
         out["cpu_baseline"] = cpu_baseline(host, flat)

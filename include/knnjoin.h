@@ -282,6 +282,8 @@ int knn_server_create(const knn_server_opts* opts, knn_server** out);
 int knn_server_add_dataset(knn_server* srv, knn_index* idx, int32_t* dataset_id);
 /* Queues a self-join of dataset `dataset_id` with K neighbours into host
  * arrays ids/dists (N x K, owned by the caller, untouched until completion).
+ * ids and dists both NULL make a latency-only request: the join runs in full
+ * and its results are discarded on the device (load generation).
  * Returns KNN_EBUSY when the pending queue is full; a request that does not
  * fit the free budget waits in the queue (it is not rejected).  A request
  * whose footprint exceeds the whole budget is rejected with KNN_EINVAL. */

@@ -231,10 +231,15 @@ class Server:
         check(load().knn_server_add_dataset(self._h, index.handle, ctypes.byref(ds)))
         return ds.value
 
-    def submit(self, dataset, K, N):
+    def submit(self, dataset, K, N, discard=False):
+        """knn_server_submit; discard=True makes a latency-only request."""
+        t = ctypes.c_int64()
+        if discard:
+            check(load().knn_server_submit(self._h, dataset, K, None, None, ctypes.byref(t)))
+            self._keep[t.value] = (None, None)
+            return t.value
         ids = np.empty((N, K), dtype=np.int32)
         dists = np.empty((N, K), dtype=np.float64)
-        t = ctypes.c_int64()
         check(load().knn_server_submit(self._h, dataset, K, ids.ctypes.data_as(ctypes.c_void_p),
                                        dists.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t)))
         self._keep[t.value] = (ids, dists)

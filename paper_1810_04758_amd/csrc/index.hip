@@ -199,10 +199,10 @@ void build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s) 
   build_cell_table(c.keys.p, N, c.flags.p, c.cell_of.p, c.cell_key.p, c.cell_start.p, c.scal.p,
                    c.tmp.p, s);
   launch_gather_soa(idx.X.p, c.perm.p, N, n, c.Xs.p, s);
-  uint32_t M = 0;
-  KNN_HIP(hipMemcpyAsync(&M, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  KNN_HIP(hipStreamSynchronize(s));
-  c.M = M;
+  // The number of cells M stays on the device (kernels read it there), so the
+  // level is built without a host round trip; per-cell arrays are sized for
+  // the worst case M = N.
+  c.M = -1;
   // dense key -> cell table when the grid is small enough
   long double cells = 1;
   for (int j = 0; j < n; ++j) cells *= (long double)c.gg.g[j];
@@ -213,8 +213,17 @@ void build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s) 
     dense = c.dense.p;
   }
   const int64_t R = pow3(n - 1);
-  c.ranges.reserve((size_t)std::max<int64_t>(M, 1) * R * 2);
-  c.rslot.reserve((size_t)std::max<int64_t>(M, 1) * R);
+  int64_t Mcap = N;
+  if (R >= 81) {
+    // 5-6 dims: 81-243 segments per cell make the worst case large; size the
+    // segment arrays from the actual cell count (one round trip)
+    uint32_t M = 0;
+    KNN_HIP(hipMemcpyAsync(&M, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    Mcap = std::max<int64_t>(M, 1);
+  }
+  c.ranges.reserve((size_t)Mcap * R * 2);
+  c.rslot.reserve((size_t)Mcap * R);
   c.nrng.reserve(N);
   launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, dense, c.gg,
                          c.ranges.p, c.rslot.p, c.nrng.p, c.cand_count.p, s);
@@ -356,9 +365,12 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     {
       launch_active_cand_sum(active, A, c.cell_of.p, c.cand_count.p, d_cand.p, s);
       uint64_t tot = 0;
+      uint32_t M = 0;
       KNN_HIP(hipMemcpyAsync(&tot, d_cand.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-      KNN_HIP(hipStreamSynchronize(s));
+      KNN_HIP(hipMemcpyAsync(&M, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));  // the level's one round trip before the search
       cand = (double)tot / (double)std::max<int64_t>(A, 1);
+      c.M = M;
     }
     int T = T_fixed;
     if (T == 0) T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(cand, A, cap);
@@ -810,6 +822,10 @@ int knn_grid_export(knn_index* idx, double cell_width, uint64_t* sorted_keys, in
     KNN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     try {
       build_level(*idx, c, cell_width, s);
+      uint32_t M32 = 0;
+      KNN_HIP(hipMemcpyAsync(&M32, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));
+      c.M = M32;
       const int64_t N = idx->N, M = c.M, R = pow3(idx->n - 1);
       if (sorted_keys)
         KNN_HIP(hipMemcpyAsync(sorted_keys, c.keys.p, N * 8, hipMemcpyDeviceToHost, s));

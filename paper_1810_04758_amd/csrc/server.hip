@@ -105,8 +105,12 @@ void worker_main(knn_server* srv) {
       ctx.out_d.reserve(NK);
       knn_join_opts o{};
       self_join(*idx, ctx, rq->K, ctx.out_ids.p, ctx.out_d.p, o, s);
-      KNN_HIP(hipMemcpyAsync(rq->ids, ctx.out_ids.p, NK * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      KNN_HIP(hipMemcpyAsync(rq->dists, ctx.out_d.p, NK * sizeof(double), hipMemcpyDeviceToHost, s));
+      if (rq->ids) {  // NULL outputs: a latency-only request, results discarded
+        KNN_HIP(hipMemcpyAsync(rq->ids, ctx.out_ids.p, NK * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+        KNN_HIP(hipMemcpyAsync(rq->dists, ctx.out_d.p, NK * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+      }
       KNN_HIP(hipStreamSynchronize(s));
     } catch (const Error& e) {
       status = e.code;
@@ -203,7 +207,9 @@ int knn_server_add_dataset(knn_server* srv, knn_index* idx, int32_t* dataset_id)
 int knn_server_submit(knn_server* srv, int32_t dataset_id, int32_t K, int32_t* ids, double* dists,
                       int64_t* ticket) {
   return guarded([&] {
-    KNN_CHECK(srv && ids && dists && ticket, KNN_EINVAL, "NULL pointer");
+    KNN_CHECK(srv && ticket, KNN_EINVAL, "NULL pointer");
+    KNN_CHECK((ids == nullptr) == (dists == nullptr), KNN_EINVAL,
+              "ids and dists must both be given or both be NULL");
     std::unique_lock<std::mutex> lk(srv->mu);
     KNN_CHECK(dataset_id >= 0 && dataset_id < (int32_t)srv->datasets.size(), KNN_EINVAL,
               "unknown dataset");

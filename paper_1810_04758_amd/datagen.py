@@ -71,6 +71,35 @@ def sample_ids(N, count, seed):
     return np.sort(rng.choice(N, size=count, replace=False)).astype(np.int64)
 
 
+def serving_pool(count=24, seed=6, n_lo=1e4, n_hi=1e7):
+    """Resident datasets of the serving workload: N log-uniform in [n_lo, n_hi],
+    dims uniform in {2,3,4,6}, coordinates uniform [0,100) or exponential(40)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        N = int(round(10 ** rng.uniform(np.log10(n_lo), np.log10(n_hi))))
+        n = int(rng.choice([2, 3, 4, 6]))
+        if rng.uniform() < 0.5:
+            D = uniform(N, n, seed=seed * 1000 + i)
+            kind = "uniform"
+        else:
+            D = exponential(N, n, seed=seed * 1000 + i)
+            kind = "exponential"
+        out.append((D, f"{kind} {n}-D N={N}"))
+    return out
+
+
+def serving_trace(seconds, rate, n_datasets, seed=7, Ks=(1, 4, 16, 64)):
+    """Poisson arrivals (mean `rate` per second) over `seconds`: arrival
+    times, dataset indexes (uniform) and K values (uniform over Ks)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = np.cumsum(rng.exponential(1.0 / rate, size=int(seconds * rate * 2) + 16))
+    t = t[t < seconds]
+    ds = rng.integers(0, n_datasets, size=t.shape[0])
+    ks = rng.choice(np.array(Ks), size=t.shape[0])
+    return t, ds, ks
+
+
 # Workloads of the benchmark configurations (seeds fixed).
 def config_points(name):
     """Return (D, K list, description) for a named workload."""
