@@ -177,36 +177,46 @@ __global__ void k_scan_apply(const uint32_t* __restrict__ in, uint32_t* __restri
 }
 
 // --------------------------------------------------------------------------
-// LSD radix sort, 8-bit digits: per-tile histogram, scan, stable scatter
+// LSD radix sort, DB-bit digits (8 or 11): per-tile histogram, scan, stable
+// scatter.  Within a tile, a key's rank among equal digits comes from DB wave
+// ballots (lanes with the same digit) plus the counts of earlier waves and
+// earlier chunks of the tile, so equal digits keep their input order.
 // --------------------------------------------------------------------------
 constexpr int kRadixItems = 8;
 constexpr int kRadixTile = kBlock * kRadixItems;
+constexpr int kMaxDigitBits = 11;
 
+template <int DB>
 __global__ void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
                              uint32_t* __restrict__ hist, int64_t nb) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  constexpr int RB = 1 << DB;
+  __shared__ uint32_t h[RB];
+  for (int d = threadIdx.x; d < RB; d += kBlock) h[d] = 0;
   __syncthreads();
   int64_t base = (int64_t)blockIdx.x * kRadixTile;
 #pragma unroll
   for (int k = 0; k < kRadixItems; ++k) {
     int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (uint64_t)(RB - 1)], 1u);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < RB; d += kBlock) hist[(int64_t)d * nb + blockIdx.x] = h[d];
 }
 
+template <int DB>
 __global__ void k_radix_scatter(const uint64_t* __restrict__ keys,
                                 const int32_t* __restrict__ vals, int64_t n, int shift,
                                 const uint32_t* __restrict__ offs, int64_t nb,
                                 uint64_t* __restrict__ okeys, int32_t* __restrict__ ovals) {
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[kBlock / 64][256];
+  constexpr int RB = 1 << DB;
+  __shared__ uint32_t run[RB];
+  __shared__ uint32_t wcnt[kBlock / 64][RB];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  run[t] = offs[(int64_t)t * nb + blockIdx.x];
+  for (int d = t; d < RB; d += kBlock) {
+    run[d] = offs[(int64_t)d * nb + blockIdx.x];
 #pragma unroll
-  for (int i = 0; i < kBlock / 64; ++i) wcnt[i][t] = 0;
+    for (int i = 0; i < kBlock / 64; ++i) wcnt[i][d] = 0;
+  }
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   int64_t base = (int64_t)blockIdx.x * kRadixTile;
@@ -215,10 +225,10 @@ __global__ void k_radix_scatter(const uint64_t* __restrict__ keys,
     bool valid = i < n;
     uint64_t key = valid ? keys[i] : 0;
     int32_t val = valid ? vals[i] : 0;
-    uint32_t d = (uint32_t)(key >> shift) & 255u;
+    uint32_t d = (uint32_t)(key >> shift) & (uint32_t)(RB - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < DB; ++b) {
       bool bit = (d >> b) & 1u;
       uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
@@ -233,13 +243,15 @@ __global__ void k_radix_scatter(const uint64_t* __restrict__ keys,
       ovals[pos] = val;
     }
     __syncthreads();
-    uint32_t add = 0;
+    for (int dd = t; dd < RB; dd += kBlock) {
+      uint32_t add = 0;
 #pragma unroll
-    for (int i2 = 0; i2 < kBlock / 64; ++i2) {
-      add += wcnt[i2][t];
-      wcnt[i2][t] = 0;
+      for (int i2 = 0; i2 < kBlock / 64; ++i2) {
+        add += wcnt[i2][dd];
+        wcnt[i2][dd] = 0;
+      }
+      run[dd] += add;
     }
-    run[t] += add;
     __syncthreads();
   }
 }
@@ -303,12 +315,14 @@ __global__ void k_emit_cells(const uint64_t* __restrict__ keys, const uint32_t* 
   }
 }
 
-__global__ void k_gather_soa(const double* __restrict__ X, const int32_t* __restrict__ perm,
+// Xs[j*N + p] = XA[perm[p]*n + j]: the source point's coordinates are
+// adjacent in the row-major copy, so each random gather touches one line.
+__global__ void k_gather_soa(const double* __restrict__ XA, const int32_t* __restrict__ perm,
                              int64_t N, int n, double* __restrict__ Xs) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
        p += (int64_t)gridDim.x * blockDim.x) {
-    int64_t src = perm[p];
-    for (int j = 0; j < n; ++j) Xs[(int64_t)j * N + p] = X[(int64_t)j * N + src];
+    const int64_t src = perm[p];
+    for (int j = 0; j < n; ++j) Xs[(int64_t)j * N + p] = XA[src * n + j];
   }
 }
 
@@ -567,35 +581,43 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_
 
 size_t radix_tmp_elems(int64_t n) {
   int64_t nb = ceil_div(n, kRadixTile);
-  return (size_t)(256 * nb) + scan_tmp_elems(256 * nb);
+  const int64_t cnt = ((int64_t)1 << kMaxDigitBits) * nb;
+  return (size_t)cnt + scan_tmp_elems(cnt);
 }
 
-void radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
+bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
                       int64_t n, int bits, uint32_t* tmp, hipStream_t s) {
-  if (n <= 1 || bits <= 0) return;
+  if (n <= 1 || bits <= 0) return false;
   int64_t nb = ceil_div(n, kRadixTile);
+  // 11-bit digits when they save a pass, else 8-bit (smaller LDS tables)
+  const int DB = (bits + 10) / 11 < (bits + 7) / 8 ? 11 : 8;
+  const int passes = (bits + DB - 1) / DB;
+  const int64_t cnt = ((int64_t)1 << DB) * nb;
   uint32_t* hist = tmp;
-  uint32_t* stmp = tmp + 256 * nb;
+  uint32_t* stmp = tmp + cnt;
   uint64_t* src_k = keys;
   int32_t* src_v = vals;
   uint64_t* dst_k = keys2;
   int32_t* dst_v = vals2;
-  int passes = (bits + 7) / 8;
   for (int ps = 0; ps < passes; ++ps) {
-    int shift = 8 * ps;
-    k_radix_hist<<<(unsigned)nb, kBlock, 0, s>>>(src_k, n, shift, hist, nb);
+    const int shift = DB * ps;
+    if (DB == 11)
+      k_radix_hist<11><<<(unsigned)nb, kBlock, 0, s>>>(src_k, n, shift, hist, nb);
+    else
+      k_radix_hist<8><<<(unsigned)nb, kBlock, 0, s>>>(src_k, n, shift, hist, nb);
     KNN_LAUNCHED();
-    launch_exclusive_scan(hist, hist, 256 * nb, nullptr, stmp, s);
-    k_radix_scatter<<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb, dst_k,
-                                                    dst_v);
+    launch_exclusive_scan(hist, hist, cnt, nullptr, stmp, s);
+    if (DB == 11)
+      k_radix_scatter<11><<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb,
+                                                          dst_k, dst_v);
+    else
+      k_radix_scatter<8><<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb,
+                                                         dst_k, dst_v);
     KNN_LAUNCHED();
     std::swap(src_k, dst_k);
     std::swap(src_v, dst_v);
   }
-  if (src_k != keys) {
-    KNN_HIP(hipMemcpyAsync(keys, src_k, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    KNN_HIP(hipMemcpyAsync(vals, src_v, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  }
+  return src_k != keys;
 }
 
 void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* keys,

@@ -195,10 +195,13 @@ void build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s) 
   c.tmp.reserve(std::max(radix_tmp_elems(N), scan_tmp_elems(N)));
   c.scal.reserve(4);
   launch_cell_keys(idx.X.p, N, c.gg, c.keys.p, c.perm.p, s);
-  radix_sort_pairs(c.keys.p, c.perm.p, c.keys2.p, c.vals2.p, N, c.gg.key_bits, c.tmp.p, s);
+  if (radix_sort_pairs(c.keys.p, c.perm.p, c.keys2.p, c.vals2.p, N, c.gg.key_bits, c.tmp.p, s)) {
+    std::swap(c.keys, c.keys2);  // sorted output is in the scratch pair
+    std::swap(c.perm, c.vals2);
+  }
   build_cell_table(c.keys.p, N, c.flags.p, c.cell_of.p, c.cell_key.p, c.cell_start.p, c.scal.p,
                    c.tmp.p, s);
-  launch_gather_soa(idx.X.p, c.perm.p, N, n, c.Xs.p, s);
+  launch_gather_soa(idx.XA.p, c.perm.p, N, n, c.Xs.p, s);
   // The number of cells M stays on the device (kernels read it there), so the
   // level is built without a host round trip; per-cell arrays are sized for
   // the worst case M = N.
@@ -386,7 +389,10 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       c.ivals2.reserve(n_items);
       launch_item_keys(active, A, G, c.cell_of.p, c.cand_count.p, c.ikeys.p, c.ivals.p, n_items,
                        s);
-      radix_sort_pairs(c.ikeys.p, c.ivals.p, c.ikeys2.p, c.ivals2.p, n_items, 9, c.tmp.p, s);
+      if (radix_sort_pairs(c.ikeys.p, c.ivals.p, c.ikeys2.p, c.ivals2.p, n_items, 9, c.tmp.p, s)) {
+        std::swap(c.ikeys, c.ikeys2);
+        std::swap(c.ivals, c.ivals2);
+      }
       order = c.ivals.p;
     }
     KNN_HIP(hipMemsetAsync(c.iscal.p, 0, 16 * sizeof(int32_t), s));
@@ -529,6 +535,9 @@ knn_index* build_from_device(const double* D_dev, int64_t N, int n, const knn_bu
     idx->n = n;
     idx->device = current_device();
     idx->X.alloc((size_t)N * n);
+    idx->XA.alloc((size_t)N * n);
+    KNN_HIP(hipMemcpyAsync(idx->XA.p, D_dev, (size_t)N * n * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
     DevBuf<uint32_t> bad(1);
     KNN_HIP(hipMemsetAsync(bad.p, 0, sizeof(uint32_t), s));
     launch_aos_to_soa(D_dev, N, n, idx->X.p, bad.p, s);

@@ -12,7 +12,8 @@ struct knn_index {
   int64_t N = 0;
   int n = 0;
   int device = 0;
-  knn::DevBuf<double> X;  // SoA coordinates in id order, X[j*N + i]
+  knn::DevBuf<double> X;   // SoA coordinates in id order, X[j*N + i]
+  knn::DevBuf<double> XA;  // the same, row-major N x n (one point = one read in gathers)
   double lo[KNN_MAX_DIMS] = {0};
   double hi[KNN_MAX_DIMS] = {0};
   // search-distance selection (Sec. 4.4)

@@ -38,10 +38,11 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_
 
 // ---- radix sort (grid.hip) ----
 // Stable LSD sort of (key, val) pairs by the low `bits` bits of the keys.
-// keys/vals hold the input and receive the output; keys2/vals2 are same-size
-// scratch; tmp: radix_tmp_elems(n) uint32.
+// keys/vals hold the input; keys2/vals2 are same-size scratch; tmp:
+// radix_tmp_elems(n) uint32.  Returns true when the sorted output ended up in
+// keys2/vals2 (odd number of passes), false when it is in keys/vals.
 size_t radix_tmp_elems(int64_t n);
-void radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
+bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
                       int64_t n, int bits, uint32_t* tmp, hipStream_t s);
 
 // ---- grid level construction (grid.hip) ----
