@@ -54,8 +54,8 @@ void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* 
 void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags,
                       uint32_t* cell_of, uint64_t* cell_key, uint32_t* cell_start,
                       uint32_t* d_M, uint32_t* tmp, hipStream_t s);
-// Xs[j*N + p] = X[j*N + perm[p]]
-void launch_gather_soa(const double* X, const int32_t* perm, int64_t N, int n, double* Xs,
+// Xs[j*N + p] = XA[perm[p]*n + j] (XA row-major N x n)
+void launch_gather_soa(const double* XA, const int32_t* perm, int64_t N, int n, double* Xs,
                        hipStream_t s);
 // Dense key -> cell lookup table (table_size entries, set to ~0 where empty).
 void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N,
