@@ -32,6 +32,8 @@ WORKLOADS = {
 }
 
 HBM_PEAK_GBS = 8000.0
+# FP64 vector peak without FMA: 256 CUs x 64 lanes x 2.4 GHz (78.6 TFLOP/s counts an FMA as 2)
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
 def alg_bytes(stats, n, K):
@@ -43,6 +45,43 @@ def alg_bytes(stats, n, K):
     for a, f in zip(stats["attempted"], stats["failed"]):
         total += a * (8 * n + 8) + (a - f) * 12 * K + f * 4
     return total
+
+
+def alg_ops(stats, n):
+    """Algorithmic FP64 operations of the search kernel over one join: per
+    scanned candidate n subtractions, n multiplications, n-1 additions and one
+    comparison (3n), for the candidates of every attempted query."""
+    return sum(a * c * 3 * n for a, c in zip(stats["attempted"], stats["cand_per_query"]))
+
+
+def kernel_source_hash():
+    """sha256 of the search kernel's source: a traffic figure is reported only
+    for the kernel it was measured on."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1810_04758_amd", "csrc", "search.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per search launch from the committed counter summary of this
+    workload (FETCH_SIZE + WRITE_SIZE per dispatch, scaled by a copy kernel of
+    known size); None when absent or taken on another version of the kernel."""
+    path = os.path.join(ROOT, "profiles", f"k_search_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("search.hip sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(datasets, cases, budget_s=12.0):
@@ -126,6 +165,39 @@ def serving_leg(api, seconds, rate=200.0, budget_gib=96, inflight=4):
             "datasets": [desc for _, desc in pool]}
 
 
+def schedule_comparison(api, dev, plan, outs, stream, reps=3):
+    """The persistent, density-ordered schedule against the plain one: one
+    launch per level over every unsolved query in cell order, one work item
+    per wavefront, no work queue (same cell sides and lanes per query, so the
+    same candidates are scanned).  Untimed by the step clock; best of `reps`
+    joins each, search-kernel time from the join's HIP events."""
+    res = []
+    tot = {0: [0.0, 0.0], 1: [0.0, 0.0]}
+    for name, Ks in plan:
+        idx = api.build_index(dev[name], stream=stream)
+        for K in Ks:
+            ids, dists = outs[(name, K)]
+            row = dict(dataset=name, K=K)
+            for sched in (0, 1):
+                best_s = best_t = float("inf")
+                for _ in range(reps):
+                    _, _, st = idx.self_join(K, ids=ids, dists=dists, stream=stream,
+                                             with_stats=True, schedule=sched)
+                    best_s = min(best_s, sum(st["ms_search"]))
+                    best_t = min(best_t, st["ms_total"])
+                key = "persistent" if sched == 0 else "plain"
+                row[f"ms_search_{key}"] = round(best_s, 3)
+                row[f"ms_join_{key}"] = round(best_t, 3)
+                tot[sched][0] += best_s
+                tot[sched][1] += best_t
+            row["search_speedup"] = round(row["ms_search_plain"] / row["ms_search_persistent"], 3)
+            res.append(row)
+        idx.close()
+    return {"cases": res,
+            "search_speedup": round(tot[1][0] / tot[0][0], 3),
+            "join_speedup": round(tot[1][1] / tot[0][1], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +212,14 @@ def main():
                     help="skip the (untimed) knn_autotune pass before the timed steps")
     ap.add_argument("--serving-seconds", type=float, default=2.0,
                     help="length of the serving trace (0 = skip the serving leg)")
+    ap.add_argument("--no-schedule-comparison", action="store_true",
+                    help="skip the (untimed) persistent-vs-plain schedule comparison")
+    ap.add_argument("--autotune-cache", default="",
+                    help="file of autotuner choices: written after the autotune pass, "
+                         "read instead of tuning with --no-autotune")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="after the timed steps, run one plain fp64 copy kernel (y = -x) over "
+                         "this many MiB, the reference dispatch for scaling HBM counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -196,6 +276,11 @@ def main():
                                   ms_default=round(r["ms_default"], 3),
                                   ms_tuned=round(r["ms_best"], 3)))
             idx.close()
+    if args.autotune_cache:
+        if tuned:
+            api.autotune_save(args.autotune_cache)
+        elif args.no_autotune:
+            api.autotune_load(args.autotune_cache)
     for _ in range(args.warmup):
         one_step(None)
     torch.cuda.synchronize()
@@ -207,6 +292,15 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1000.0 / args.steps
+    calib = None
+    if args.calibration_copy_mib > 0:
+        x = torch.ones(args.calibration_copy_mib << 17, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        calib = {"kernel": "neg (fp64 copy)", "read_bytes": x.numel() * 8,
+                 "write_bytes": y.numel() * 8}
+        del x, y
 
     queries_per_step = sum(host[name].shape[0] * len(Ks) for name, Ks in plan)
     value = queries_per_step * args.steps / elapsed
@@ -216,12 +310,14 @@ def main():
     search_ms = 0.0
     search_launches = 0
     bytes_total = 0
+    ops_total = 0.0
     per_case = {}
     for name, K, st in records:
         n = host[name].shape[1]
         search_ms += sum(st["ms_search"])
         search_launches += st["levels"]
         bytes_total += alg_bytes(st, n, K)
+        ops_total += alg_ops(st, n)
         c = per_case.setdefault((name, K), dict(dataset=name, K=K, ms_total=[], levels=[],
                                                 fail_fraction=[], ms_search=[], ms_build=[]))
         c["ms_total"].append(st["ms_total"])
@@ -230,6 +326,20 @@ def main():
         c["ms_search"].append(sum(st["ms_search"]))
         c["ms_build"].append(sum(st["ms_build"]))
     achieved = bytes_total / (search_ms * 1e-3) / 1e9 if search_ms > 0 else 0.0
+    achieved_ops = ops_total / (search_ms * 1e-3) / 1e12 if search_ms > 0 else 0.0
+    # the binding roof is the one with the larger time at peak
+    alu_bound = ops_total / (ALU_PEAK_TOPS * 1e12) > bytes_total / (HBM_PEAK_GBS * 1e9)
+    hbm_roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    alu_roof = {"bound": "alu", "achieved": round(achieved_ops, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "TFLOP/s", "frac": round(achieved_ops / ALU_PEAK_TOPS, 4)}
+    roof = dict(alu_roof if alu_bound else hbm_roof)
+    roof.update({"traffic": measured_traffic(args.workload), "kernel": "k_search",
+                 "alg_bytes_per_launch": round(bytes_total / max(1, search_launches)),
+                 "alg_fp64_ops_per_launch": round(ops_total / max(1, search_launches)),
+                 "avg_launch_ms": round(search_ms / max(1, search_launches), 4),
+                 "launches": search_launches,
+                 "other_roof": hbm_roof if alu_bound else alu_roof})
     cases = []
     for (name, K), c in per_case.items():
         N = host[name].shape[0]
@@ -256,14 +366,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": desc,
                    "queries_per_step": queries_per_step},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_search",
-                     "avg_launch_ms": round(search_ms / max(1, search_launches), 4),
-                     "launches": search_launches},
+        "roofline": roof,
         "cases": cases,
         "autotune": tuned,
     }
+    if calib:
+        out["calibration_copy"] = calib
+    if args.schedule == 0 and not args.no_schedule_comparison:
+        out["persistent_vs_plain"] = schedule_comparison(api, dev, plan, outs, stream)
     if args.serving_seconds > 0:
         out["serving"] = serving_leg(api, args.serving_seconds)
     if not args.no_cpu_baseline:

@@ -102,7 +102,14 @@ typedef struct knn_join_opts {
   double eps_step;        /* linear growth step, multiple of eps_min [0.5] (Alg. 1) */
   int32_t linear_levels;  /* linear growths before geometric growth [1]; < 0: none */
   double growth;          /* geometric growth factor of the cell side [16^(1/dims)] */
-  int32_t use_graph;      /* capture the per-level launch sequence in a HIP graph [0] */
+  int32_t use_graph;      /* 1: the first join of (index, K, these options, these
+                             outputs) runs eagerly, recording its levels, and
+                             captures the same launch sequence in a HIP graph
+                             held by the index (with scratch of its own); later
+                             such joins launch the graph: no host round trip,
+                             asynchronous on the stream.  One graph per index
+                             (another key replaces it).  Statistics of a replay
+                             repeat the recorded counts; per-level times are 0 [0] */
   double tail_pairs;      /* brute-force tail once (remaining queries) x N <= this
                              [1.5e9]; < 0 disables the tail (Sec. 5.3.8 remedy) */
   knn_join_stats* stats;  /* optional statistics output */

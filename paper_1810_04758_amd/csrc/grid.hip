@@ -538,6 +538,17 @@ __global__ void k_compact(const uint32_t* __restrict__ flags, const uint32_t* __
     if (flags[p]) out[ex[p]] = (int32_t)p;
 }
 
+// Zero fill: `words` 32-bit words, then `tail` (< 4) trailing bytes.  A kernel
+// rather than a memset node, so the join's launch sequence can be captured in
+// a graph and replayed.
+__global__ void k_zero(uint32_t* __restrict__ p, int64_t words, uint8_t* __restrict__ tailp,
+                       int tail) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+  if (blockIdx.x == 0 && (int)threadIdx.x < tail) tailp[threadIdx.x] = 0;
+}
+
 int grid_for(int64_t n, int cap = 8192) {
   int64_t b = ceil_div(n, kBlock);
   if (b < 1) b = 1;
@@ -567,7 +578,7 @@ size_t scan_tmp_elems(int64_t n) { return (size_t)ceil_div(n, kScanTile) + 1; }
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                            uint32_t* tmp, hipStream_t s) {
   if (n <= 0) {
-    if (total) KNN_HIP(hipMemsetAsync(total, 0, sizeof(uint32_t), s));
+    if (total) launch_zero(total, sizeof(uint32_t), s);
     return;
   }
   int64_t nb = ceil_div(n, kScanTile);
@@ -689,7 +700,7 @@ void launch_item_keys(const int32_t* active, int64_t n_active, int G, const uint
 
 void launch_active_cand_sum(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
                             const uint32_t* cand_count, uint64_t* sum, hipStream_t s) {
-  KNN_HIP(hipMemsetAsync(sum, 0, sizeof(uint64_t), s));
+  launch_zero(sum, sizeof(uint64_t), s);
   k_active_cand_sum<<<grid_for(n_active, 1024), kBlock, 0, s>>>(active, n_active, cell_of,
                                                                  cand_count, sum);
   KNN_LAUNCHED();
@@ -710,6 +721,16 @@ void launch_failed_flags(const uint8_t* failed, const int32_t* perm, int64_t N, 
 void launch_compact_positions(const uint32_t* flags, const uint32_t* ex, int64_t N, int32_t* out,
                               hipStream_t s) {
   k_compact<<<grid_for(N), kBlock, 0, s>>>(flags, ex, N, out);
+  KNN_LAUNCHED();
+}
+
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  KNN_CHECK(((uintptr_t)p & 3) == 0, KNN_EINTERNAL, "zero fill needs a 4-byte aligned pointer");
+  const int64_t words = (int64_t)(bytes / 4);
+  const int tail = (int)(bytes % 4);
+  k_zero<<<grid_for(std::max<int64_t>(words, 1)), kBlock, 0, s>>>(
+      static_cast<uint32_t*>(p), words, static_cast<uint8_t*>(p) + words * 4, tail);
   KNN_LAUNCHED();
 }
 

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <unordered_set>
 
@@ -156,7 +157,8 @@ int64_t JoinContext::device_bytes() const {
                    keys.bytes() + keys2.bytes() + vals2.bytes() + flags.bytes() + tmp.bytes() +
                    scal.bytes() + iscal.bytes() + active.bytes() + fail_list.bytes() +
                    failed.bytes() + ikeys.bytes() + ikeys2.bytes() + ivals.bytes() +
-                   ivals2.bytes() + out_ids.bytes() + out_d.bytes());
+                   ivals2.bytes() + out_ids.bytes() + out_d.bytes() + tail_scratch.bytes() +
+                   cand_sum.bytes());
 }
 
 double eps_min_of(const knn_index& idx, int32_t K) {
@@ -178,7 +180,8 @@ void validate_join(const knn_index* idx, int32_t K) {
   KNN_CHECK(K <= KNN_MAX_K, KNN_EINVAL, "K above KNN_MAX_K");
 }
 
-void build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s) {
+int64_t build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s,
+                    int64_t Mcap_known) {
   const int64_t N = idx.N;
   const int n = idx.n;
   c.gg = make_geom(idx, w);
@@ -220,16 +223,21 @@ void build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s) 
   if (R >= 81) {
     // 5-6 dims: 81-243 segments per cell make the worst case large; size the
     // segment arrays from the actual cell count (one round trip)
-    uint32_t M = 0;
-    KNN_HIP(hipMemcpyAsync(&M, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    KNN_HIP(hipStreamSynchronize(s));
-    Mcap = std::max<int64_t>(M, 1);
+    if (Mcap_known > 0) {
+      Mcap = Mcap_known;
+    } else {
+      uint32_t M = 0;
+      KNN_HIP(hipMemcpyAsync(&M, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));
+      Mcap = std::max<int64_t>(M, 1);
+    }
   }
   c.ranges.reserve((size_t)Mcap * R * 2);
   c.rslot.reserve((size_t)Mcap * R);
   c.nrng.reserve(N);
   launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, dense, c.gg,
                          c.ranges.p, c.rslot.p, c.nrng.p, c.cand_count.p, s);
+  return Mcap;
 }
 
 uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
@@ -267,12 +275,14 @@ static int lanes_for(double cand, int64_t A, int cap) {
 }
 
 void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, double* d_dists,
-               const knn_join_opts& o, hipStream_t s) {
+               const knn_join_opts& o, hipStream_t s, std::vector<LevelPlan>* record,
+               const std::vector<LevelPlan>* replay) {
   validate_join(&idx, K);
   KNN_CHECK(d_ids && d_dists, KNN_EINVAL, "output pointers are NULL");
   auto t_start = std::chrono::steady_clock::now();
   const int64_t N = idx.N;
-  knn_join_stats* st = o.stats;
+  knn_join_stats* st = replay ? nullptr : o.stats;
+  if (record) record->clear();
   if (st) std::memset(st, 0, sizeof(*st));
 
   // level-0 cell side: w = w_factor * eps_min(K) (Sec. 4.4), or explicit
@@ -315,15 +325,24 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   c.active.reserve(N);
   c.fail_list.reserve(N);
   c.failed.reserve(N);
-  DevBuf<uint64_t> d_cand(1);
+  c.cand_sum.reserve(1);
   const int ncu = cu_count(c.device);
 
   Events ev(st != nullptr);
   int64_t A = N;  // active queries
   for (int level = 0;; ++level) {
     if (level >= KNN_MAX_LEVELS - 1) w = std::max(w, 2.0 * ext + 1.0);  // everything in one block
+    const LevelPlan* rp = nullptr;
+    if (replay) {
+      KNN_CHECK(level < (int)replay->size(), KNN_EINTERNAL, "replayed join ran past its plan");
+      rp = &(*replay)[level];
+    }
+    LevelPlan lp;
     // brute-force tail once few queries remain (their ids are in fail_list)
-    if (level > 0 && tail_budget > 0 && A <= 65535 && (double)A * (double)N <= tail_budget) {
+    const bool tail = rp ? rp->tail
+                         : (level > 0 && tail_budget > 0 && A <= 65535 &&
+                            (double)A * (double)N <= tail_budget);
+    if (tail) {
       ev.rec(0, s);
       TailArgs ta{};
       ta.X = idx.X.p;
@@ -339,19 +358,25 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       ta.cap = cap;
       ta.out_ids = d_ids;
       ta.out_d = d_dists;
-      DevBuf<char> scratch(tail_state_bytes(A, cap));
-      const int rounds = tail_run(ta, scratch.p, s);
+      c.tail_scratch.reserve(tail_state_bytes(A, cap));
+      const int rounds = tail_run(ta, c.tail_scratch.p, s, rp ? rp->tail_rounds : -1);
       ev.rec(1, s);
-      KNN_HIP(hipStreamSynchronize(s));
+      if (!rp) KNN_HIP(hipStreamSynchronize(s));
       if (st) {
         st->tail_queries = A;
         st->tail_rounds = rounds;
         st->ms_tail = elapsed_ms(ev.e[0], ev.e[1]);
       }
+      if (record) {
+        lp.tail = true;
+        lp.A = A;
+        lp.tail_rounds = rounds;
+        record->push_back(lp);
+      }
       break;
     }
     ev.rec(0, s);
-    build_level(idx, c, w, s);
+    lp.Mcap = build_level(idx, c, w, s, rp ? rp->Mcap : 0);
     // active list of this level (cell order): level 0 = every point
     const int32_t* active = nullptr;
     if (level > 0) {
@@ -365,18 +390,22 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     // lanes per query from the level's mean candidate count (the paper's t,
     // Sec. 4.7, chosen per level: the tail levels see far more candidates)
     double cand = 0;
-    {
-      launch_active_cand_sum(active, A, c.cell_of.p, c.cand_count.p, d_cand.p, s);
+    int T = T_fixed;
+    if (rp) {
+      cand = rp->cand;
+      c.M = rp->M;
+      T = rp->T;
+    } else {
+      launch_active_cand_sum(active, A, c.cell_of.p, c.cand_count.p, c.cand_sum.p, s);
       uint64_t tot = 0;
       uint32_t M = 0;
-      KNN_HIP(hipMemcpyAsync(&tot, d_cand.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipMemcpyAsync(&tot, c.cand_sum.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipMemcpyAsync(&M, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));  // the level's one round trip before the search
       cand = (double)tot / (double)std::max<int64_t>(A, 1);
       c.M = M;
+      if (T == 0) T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(cand, A, cap);
     }
-    int T = T_fixed;
-    if (T == 0) T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(cand, A, cap);
     const int G = 64 / T;
     const int waves = search_waves_per_block(T, cap);
     // work items, densest first (Sec. 4.5 work estimate; persistent schedule)
@@ -395,7 +424,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       }
       order = c.ivals.p;
     }
-    KNN_HIP(hipMemsetAsync(c.iscal.p, 0, 16 * sizeof(int32_t), s));
+    launch_zero(c.iscal.p, 16 * sizeof(int32_t), s);
     ev.rec(1, s);
 
     SearchArgs a{};
@@ -430,13 +459,21 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.fail_count = c.iscal.p + 8;
     a.refine_count = c.iscal.p + 9;
     if (o.schedule == 0) {
-      // persistent grid: exactly what can be resident at once
-      int64_t want = ceil_div(n_items, waves);
-      int blocks = (int)std::min<int64_t>(want, (int64_t)ncu * search_blocks_per_cu(idx.n, T, cap));
-      // about four pops per wavefront and queue: few atomics, fine enough
-      // granularity for the dense-first balance at the end of each queue
-      const int64_t total_waves = (int64_t)blocks * waves;
-      a.grain = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, n_items / (total_waves * 4)));
+      int blocks;
+      if (rp) {
+        blocks = rp->blocks;
+        a.grain = rp->grain;
+      } else {
+        // persistent grid: exactly what can be resident at once
+        int64_t want = ceil_div(n_items, waves);
+        blocks = (int)std::min<int64_t>(want, (int64_t)ncu * search_blocks_per_cu(idx.n, T, cap));
+        // about four pops per wavefront and queue: few atomics, fine enough
+        // granularity for the dense-first balance at the end of each queue
+        const int64_t total_waves = (int64_t)blocks * waves;
+        a.grain = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, n_items / (total_waves * 4)));
+      }
+      lp.blocks = blocks;
+      lp.grain = a.grain;
       launch_search(a, idx.n, T, blocks, s);
     } else {
       // one launch per batch of queries, cell order, one item per wavefront
@@ -450,9 +487,25 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     }
     ev.rec(2, s);
     int32_t sc[2] = {0, 0};
-    KNN_HIP(hipMemcpyAsync(sc, c.iscal.p + 8, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    KNN_HIP(hipStreamSynchronize(s));
+    if (rp) {
+      sc[0] = rp->fails;
+      sc[1] = rp->refine;
+    } else {
+      KNN_HIP(hipMemcpyAsync(sc, c.iscal.p + 8, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));
+    }
     const int32_t fails = sc[0];
+    if (record) {
+      lp.A = A;
+      lp.T = T;
+      lp.n_items = n_items;
+      lp.cand = cand;
+      lp.fails = fails;
+      lp.refine = sc[1];
+      lp.M = c.M;
+      lp.cell_w = 1.0 / c.gg.inv_w;
+      record->push_back(lp);
+    }
     if (st && level < KNN_MAX_LEVELS) {
       if (level == 0) st->lanes_per_query = T;
       st->lanes[level] = T;
@@ -472,7 +525,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     KNN_CHECK(fails <= A, KNN_EINTERNAL, "more failures than attempted queries");
     // failures are re-queued on a grid with a larger cell side (Alg. 1):
     // linear growth by eps_step * w0 first, then geometric growth
-    KNN_HIP(hipMemsetAsync(c.failed.p, 0, N, s));
+    launch_zero(c.failed.p, (size_t)N, s);
     launch_mark_failed(c.fail_list.p, c.iscal.p + 8, fails, c.failed.p, s);
     A = fails;
     w = (1.0 / c.gg.inv_w);
@@ -486,6 +539,110 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
                                                              t_start)
                        .count();
   }
+}
+
+bool GraphPlan::matches(int32_t K_, const knn_join_opts& o, int32_t* ids_, double* dists_) const {
+  return K == K_ && ids == ids_ && dists == dists_ && opts.w_factor == o.w_factor &&
+         opts.cell_width == o.cell_width && opts.lanes_per_query == o.lanes_per_query &&
+         opts.schedule == o.schedule && opts.batch_queries == o.batch_queries &&
+         opts.eps_step == o.eps_step && opts.linear_levels == o.linear_levels &&
+         opts.growth == o.growth && opts.tail_pairs == o.tail_pairs;
+}
+
+GraphPlan::~GraphPlan() {
+  if (done) (void)hipEventSynchronize(done);  // a replay may still use the scratch
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (done) (void)hipEventDestroy(done);
+}
+
+namespace {
+
+void stats_from_plan(const GraphPlan& gp, knn_join_stats* st) {
+  std::memset(st, 0, sizeof(*st));
+  st->eps_min = gp.eps_min;
+  int L = 0;
+  for (const LevelPlan& lp : gp.levels) {
+    if (lp.tail) {
+      st->tail_queries = lp.A;
+      st->tail_rounds = lp.tail_rounds;
+      continue;
+    }
+    if (L >= KNN_MAX_LEVELS) break;
+    if (L == 0) st->lanes_per_query = lp.T;
+    st->lanes[L] = lp.T;
+    st->cand_per_query[L] = lp.cand;
+    st->refine_rounds[L] = lp.refine;
+    st->cell_width[L] = lp.cell_w;
+    st->attempted[L] = lp.A;
+    st->failed[L] = lp.fails;
+    st->cells[L] = lp.M;
+    st->total_attempted += lp.A;
+    st->total_failed += lp.fails;
+    st->levels = ++L;
+  }
+}
+
+}  // namespace
+
+void self_join_graph(knn_index& idx, int32_t K, int32_t* d_ids, double* d_dists,
+                     const knn_join_opts& o, hipStream_t s) {
+  knn_join_stats* st = o.stats;
+  GraphPlan* gp = idx.graph;
+  if (gp && gp->matches(K, o, d_ids, d_dists)) {
+    // replay: the whole join as one graph launch, ordered after the previous
+    // replay (they share the graph's scratch)
+    Events ev(st != nullptr);
+    KNN_HIP(hipStreamWaitEvent(s, gp->done, 0));
+    ev.rec(0, s);
+    KNN_HIP(hipGraphLaunch(gp->exec, s));
+    ev.rec(1, s);
+    KNN_HIP(hipEventRecord(gp->done, s));
+    if (st) {
+      KNN_HIP(hipEventSynchronize(ev.e[1]));
+      stats_from_plan(*gp, st);
+      st->ms_total = elapsed_ms(ev.e[0], ev.e[1]);
+    }
+    return;
+  }
+  // first join of this (K, options, outputs): run it eagerly, recording its
+  // levels, then capture the same launch sequence on a private stream
+  if (gp) {
+    delete gp;
+    idx.graph = nullptr;
+  }
+  std::unique_ptr<GraphPlan> np(new GraphPlan());
+  np->K = K;
+  np->opts = o;
+  np->opts.stats = nullptr;
+  np->ids = d_ids;
+  np->dists = d_dists;
+  np->ctx.device = idx.device;
+  np->eps_min = eps_min_of(idx, K);
+  KNN_HIP(hipEventCreateWithFlags(&np->done, hipEventDisableTiming));
+  self_join(idx, np->ctx, K, d_ids, d_dists, o, s, &np->levels, nullptr);
+  hipStream_t cs = nullptr;
+  KNN_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  try {
+    KNN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+      self_join(idx, np->ctx, K, d_ids, d_dists, np->opts, cs, nullptr, &np->levels);
+    } catch (...) {
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    KNN_HIP(hipStreamEndCapture(cs, &g));
+    np->graph = g;
+    KNN_HIP(hipGraphInstantiate(&np->exec, g, nullptr, nullptr, 0));
+  } catch (...) {
+    (void)hipStreamDestroy(cs);
+    throw;
+  }
+  KNN_HIP(hipStreamDestroy(cs));
+  KNN_HIP(hipEventRecord(np->done, s));
+  idx.graph = np.release();
 }
 
 }  // namespace knn
@@ -684,7 +841,10 @@ int knn_self_join_device(knn_index* idx, int32_t K, int32_t* d_ids, double* d_di
     BusyGuard bg(idx);
     DeviceGuard dg(idx->device);
     knn_join_opts o = resolve_join(opts);
-    self_join(*idx, index_ctx(idx), K, d_ids, d_dists, o, (hipStream_t)stream);
+    if (o.use_graph)
+      self_join_graph(*idx, K, d_ids, d_dists, o, (hipStream_t)stream);
+    else
+      self_join(*idx, index_ctx(idx), K, d_ids, d_dists, o, (hipStream_t)stream);
   });
 }
 
@@ -703,7 +863,10 @@ int knn_self_join(knn_index* idx, int32_t K, int32_t* ids, double* dists,
       const size_t NK = (size_t)idx->N * K;
       c.out_ids.reserve(NK);
       c.out_d.reserve(NK);
-      self_join(*idx, c, K, c.out_ids.p, c.out_d.p, o, s);
+      if (o.use_graph)
+        self_join_graph(*idx, K, c.out_ids.p, c.out_d.p, o, s);
+      else
+        self_join(*idx, c, K, c.out_ids.p, c.out_d.p, o, s);
       KNN_HIP(hipMemcpyAsync(ids, c.out_ids.p, NK * sizeof(int32_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipMemcpyAsync(dists, c.out_d.p, NK * sizeof(double), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));
@@ -720,6 +883,8 @@ void knn_destroy_index(knn_index* idx) {
   if (!idx) return;
   try {
     DeviceGuard dg(idx->device);
+    delete idx->graph;
+    idx->graph = nullptr;
     delete idx->ctx;
     idx->ctx = nullptr;
     delete idx;
@@ -741,7 +906,9 @@ int knn_index_info_get(const knn_index* idx, knn_index_info* out) {
     out->eps_mean = idx->eps_mean;
     out->n_bins = idx->n_bins;
     out->n_sample = idx->n_sample;
-    out->device_bytes = (int64_t)idx->X.bytes() + (idx->ctx ? idx->ctx->ctx.device_bytes() : 0);
+    out->device_bytes = (int64_t)(idx->X.bytes() + idx->XA.bytes()) +
+                        (idx->ctx ? idx->ctx->ctx.device_bytes() : 0) +
+                        (idx->graph ? idx->graph->ctx.device_bytes() : 0);
   });
 }
 

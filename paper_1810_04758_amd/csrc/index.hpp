@@ -8,6 +8,10 @@
 
 #include "kernels.hpp"
 
+namespace knn {
+struct GraphPlan;
+}
+
 struct knn_index {
   int64_t N = 0;
   int n = 0;
@@ -24,6 +28,7 @@ struct knn_index {
   std::vector<uint64_t> cum;  // cumulative histogram counts
   std::atomic<int> busy{0};
   struct JoinContextHolder* ctx = nullptr;  // scratch of knn_self_join*
+  knn::GraphPlan* graph = nullptr;          // last captured join (use_graph)
 };
 
 namespace knn {
@@ -57,8 +62,48 @@ struct JoinContext {
   DevBuf<int32_t> ivals, ivals2;
   DevBuf<int32_t> out_ids;  // staging for host-destination joins
   DevBuf<double> out_d;
+  DevBuf<char> tail_scratch;
+  DevBuf<uint64_t> cand_sum;
 
   int64_t device_bytes() const;
+};
+
+// What one level of a join did, recorded by an eager run so that the same
+// launch sequence can be issued again without host round trips (a join on the
+// same index, K and options is deterministic: the same levels, active counts,
+// lanes per query and launch shapes).
+struct LevelPlan {
+  bool tail = false;
+  int64_t A = 0;        // active queries
+  int T = 0;            // lanes per query
+  int64_t n_items = 0;
+  int blocks = 0;       // persistent grid
+  int grain = 1;
+  int64_t Mcap = 0;     // cells, when the level sized its ranges by them
+  int tail_rounds = 0;
+  // statistics of the recorded run
+  double cand = 0;
+  int32_t fails = 0;
+  int32_t refine = 0;
+  int64_t M = 0;
+  double cell_w = 0;
+};
+
+// A join captured in a HIP graph with the scratch it writes (its own context,
+// so eager joins on the same index cannot reallocate memory the graph uses).
+struct GraphPlan {
+  int32_t K = 0;
+  knn_join_opts opts{};  // stats pointer cleared
+  int32_t* ids = nullptr;
+  double* dists = nullptr;
+  std::vector<LevelPlan> levels;
+  double eps_min = 0;
+  JoinContext ctx;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // end of the last replay
+  bool matches(int32_t K_, const knn_join_opts& o, int32_t* ids_, double* dists_) const;
+  ~GraphPlan();
 };
 
 struct JoinParams {
@@ -67,11 +112,22 @@ struct JoinParams {
 };
 
 // Builds the grid level of cell side w into ctx (Sec. 3.1 / 4.6).
-void build_level(const knn_index& idx, JoinContext& ctx, double w, hipStream_t s);
+// Mcap_known > 0: the cell count that sizes the 5-6 dimension range arrays
+// (no round trip); else it is read back when needed.  Returns the Mcap used.
+int64_t build_level(const knn_index& idx, JoinContext& ctx, double w, hipStream_t s,
+                    int64_t Mcap_known = 0);
 // The whole GPU-only KNN self-join (Alg. 1 with n_large = 1): level loop with
 // failures re-queued and the cell side grown until every query succeeds.
+// record: filled with the levels of this run.  replay: issue exactly these
+// levels with no host round trip (stream capture), statistics not written.
 void self_join(const knn_index& idx, JoinContext& ctx, int32_t K, int32_t* d_ids,
-               double* d_dists, const knn_join_opts& o, hipStream_t s);
+               double* d_dists, const knn_join_opts& o, hipStream_t s,
+               std::vector<LevelPlan>* record = nullptr,
+               const std::vector<LevelPlan>* replay = nullptr);
+// use_graph: the first join of (index, K, options, outputs) runs eagerly and
+// captures its launch sequence; later ones launch the graph.
+void self_join_graph(knn_index& idx, int32_t K, int32_t* d_ids, double* d_dists,
+                     const knn_join_opts& o, hipStream_t s);
 // Device bytes a join of (idx, K) needs beyond the index (admission control).
 uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output);
 double eps_min_of(const knn_index& idx, int32_t K);

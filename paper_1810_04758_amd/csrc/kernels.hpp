@@ -89,6 +89,8 @@ void launch_failed_flags(const uint8_t* failed, const int32_t* perm, int64_t N,
                          uint32_t* flags, hipStream_t s);
 void launch_compact_positions(const uint32_t* flags, const uint32_t* ex, int64_t N,
                               int32_t* out, hipStream_t s);
+// Zeroes `bytes` bytes at p (4-byte aligned) with a kernel, not a memset node.
+void launch_zero(void* p, size_t bytes, hipStream_t s);
 
 // ---- search-distance sampling (eps.hip) ----
 // Partial sums of pair distances inside the sample: one double per block of

@@ -326,7 +326,7 @@ size_t tail_state_bytes(int64_t A, int cap) {
     }                                                                          \
   } while (0)
 
-int tail_run(TailArgs a, char* scratch, hipStream_t s) {
+int tail_run(TailArgs a, char* scratch, hipStream_t s, int fixed_rounds) {
   // carve the scratch: state, hist, cnt, flag, buffers
   char* p = scratch;
   auto take = [&](size_t bytes) {
@@ -340,28 +340,35 @@ int tail_run(TailArgs a, char* scratch, hipStream_t s) {
   a.flag = reinterpret_cast<int32_t*>(take(16));
   a.buf_d = reinterpret_cast<double*>(take((size_t)a.A * a.cap * 8));
   a.buf_i = reinterpret_cast<int32_t*>(take((size_t)a.A * a.cap * 4));
-  KNN_HIP(hipMemsetAsync(a.hist, 0, (size_t)a.A * TNB * 4, s));
+  launch_zero(a.hist, (size_t)a.A * TNB * 4, s);
   const dim3 grid((unsigned)ceil_div(a.N, kChunk), (unsigned)ceil_div(a.A, QB));
   LAUNCH_DIM(k_tail_hist, grid, a);
   KNN_LAUNCHED();
   const int sb = (int)ceil_div(a.A, kBlock);
-  KNN_HIP(hipMemsetAsync(a.flag, 0, 16, s));
+  launch_zero(a.flag, 16, s);
   k_tail_select<<<sb, kBlock, 0, s>>>(a);
   KNN_LAUNCHED();
   int32_t nref = 0;
-  KNN_HIP(hipMemcpyAsync(&nref, a.flag, 4, hipMemcpyDeviceToHost, s));
-  KNN_HIP(hipStreamSynchronize(s));
+  const bool fixed = fixed_rounds >= 0;
+  if (fixed) {
+    nref = fixed_rounds;
+  } else {
+    KNN_HIP(hipMemcpyAsync(&nref, a.flag, 4, hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+  }
   int rounds = 0;
-  while (nref > 0) {
+  while (fixed ? rounds < fixed_rounds : nref > 0) {
     k_tail_split<<<sb, kBlock, 0, s>>>(a);
     KNN_LAUNCHED();
     LAUNCH_DIM(k_tail_refine_count, grid, a);
     KNN_LAUNCHED();
-    KNN_HIP(hipMemsetAsync(a.flag, 0, 4, s));
+    launch_zero(a.flag, 4, s);
     k_tail_refine_update<<<sb, kBlock, 0, s>>>(a);
     KNN_LAUNCHED();
-    KNN_HIP(hipMemcpyAsync(&nref, a.flag, 4, hipMemcpyDeviceToHost, s));
-    KNN_HIP(hipStreamSynchronize(s));
+    if (!fixed) {
+      KNN_HIP(hipMemcpyAsync(&nref, a.flag, 4, hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));
+    }
     ++rounds;
     KNN_CHECK(rounds < 200, KNN_EINTERNAL, "tail refinement did not converge");
   }

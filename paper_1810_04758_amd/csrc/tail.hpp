@@ -35,6 +35,9 @@ struct TailArgs {
 // Device scratch bytes tail_run needs for A queries.
 size_t tail_state_bytes(int64_t A, int cap);
 // Runs the whole tail on stream s; returns the number of refinement rounds.
-int tail_run(TailArgs a, char* scratch, hipStream_t s);
+// fixed_rounds >= 0: issue exactly that many refinement rounds with no host
+// round trip (a replay of a recorded run; rounds beyond a query's need leave
+// it unchanged); < 0: run until no query needs refinement.  Returns the rounds.
+int tail_run(TailArgs a, char* scratch, hipStream_t s, int fixed_rounds = -1);
 
 }  // namespace knn

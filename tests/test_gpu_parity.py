@@ -265,3 +265,52 @@ def test_eps_min_from_index_matches_rule(knn, oracle_mod):
         assert prev <= e <= info["eps_mean"]
         prev = e
     idx.close()
+
+
+GRAPH_CASES = [
+    # (name, generator, K, options): several levels, the 5-6-D range sizing
+    # and the brute-force tail all have to replay
+    ("expo2d", lambda: datagen.exponential(20011, 2, seed=31), 8, {}),
+    ("unif6d", lambda: datagen.uniform(6007, 6, seed=32), 8, {}),
+    ("expo3d_tail", lambda: datagen.exponential(12001, 3, seed=33), 16,
+     {"w_factor": 0.3, "growth": 1.3, "tail_pairs": 2e6}),
+    ("expo2d_plain", lambda: datagen.exponential(9001, 2, seed=34), 4, {"schedule": 1,
+                                                                        "batch_queries": 1000}),
+]
+
+
+@pytest.mark.parametrize("name,gen,K,opts", GRAPH_CASES, ids=[c[0] for c in GRAPH_CASES])
+def test_graph_replay(knn, oracle_mod, name, gen, K, opts):
+    """use_graph: the capturing join and every replay give the eager result
+    bit for bit, also after eager joins of another K on the same index, and
+    new output buffers trigger a new capture."""
+    import torch
+    D = gen()
+    N = D.shape[0]
+    _say(f"[graph_replay] {name} N={N} K={K} {opts}")
+    idx = knn.build_index(torch.from_numpy(D).cuda())
+    ref_i, ref_d, st_e = idx.self_join(K, with_stats=True, **opts)
+    ref_i, ref_d = ref_i.cpu().numpy(), ref_d.cpu().numpy()
+    _check_rows(D, ref_i, ref_d, K, np.arange(0, N, 7), oracle_mod)
+    gi = torch.empty((N, K), dtype=torch.int32, device="cuda")
+    gd = torch.empty((N, K), dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        gi.fill_(-1)
+        gd.fill_(float("nan"))
+        if rep == 2:  # an eager join of another K in between
+            idx.self_join(K + 1)
+        _, _, st = idx.self_join(K, ids=gi, dists=gd, with_stats=True, use_graph=1, **opts)
+        torch.cuda.synchronize()
+        assert (gi.cpu().numpy() == ref_i).all(), f"replay {rep}: ids differ"
+        assert (gd.cpu().numpy() == ref_d).all(), f"replay {rep}: distances differ"
+        assert st["levels"] == st_e["levels"]
+        assert st["attempted"] == st_e["attempted"] and st["failed"] == st_e["failed"]
+        assert st["tail_queries"] == st_e["tail_queries"]
+    # other outputs: captured again, same result
+    gi2, gd2 = idx.self_join(K, use_graph=1, **opts)
+    gi2, gd2 = idx.self_join(K, ids=gi2, dists=gd2, use_graph=1, **opts)
+    torch.cuda.synchronize()
+    assert (gi2.cpu().numpy() == ref_i).all() and (gd2.cpu().numpy() == ref_d).all()
+    if name == "expo3d_tail":
+        assert st_e["tail_queries"] > 0 and st_e["levels"] >= 2
+    idx.close()
