@@ -198,6 +198,38 @@ def schedule_comparison(api, dev, plan, outs, stream, reps=3):
             "join_speedup": round(tot[1][1] / tot[0][1], 3)}
 
 
+def graph_comparison(api, dev, plan, outs, stream, reps=3):
+    """Eager joins against replays of the join captured in a HIP graph
+    (use_graph): same index, K and outputs; wall time from submit to the
+    stream being drained, best of `reps` each."""
+    import torch
+    res = []
+    tot_e = tot_g = 0.0
+    for name, Ks in plan:
+        idx = api.build_index(dev[name], stream=stream)
+        for K in Ks:
+            ids, dists = outs[(name, K)]
+            best = {}
+            for mode in (0, 1):
+                if mode:
+                    idx.self_join(K, ids=ids, dists=dists, stream=stream, use_graph=1)  # capture
+                b = float("inf")
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    idx.self_join(K, ids=ids, dists=dists, stream=stream, use_graph=mode)
+                    torch.cuda.synchronize()
+                    b = min(b, (time.perf_counter() - t0) * 1e3)
+                best[mode] = b
+            tot_e += best[0]
+            tot_g += best[1]
+            res.append(dict(dataset=name, K=K, ms_eager=round(best[0], 3),
+                            ms_graph_replay=round(best[1], 3),
+                            speedup=round(best[0] / best[1], 3)))
+        idx.close()
+    return {"cases": res, "speedup": round(tot_e / tot_g, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +246,8 @@ def main():
                     help="length of the serving trace (0 = skip the serving leg)")
     ap.add_argument("--no-schedule-comparison", action="store_true",
                     help="skip the (untimed) persistent-vs-plain schedule comparison")
+    ap.add_argument("--no-graph-comparison", action="store_true",
+                    help="skip the (untimed) eager-vs-graph-replay comparison")
     ap.add_argument("--autotune-cache", default="",
                     help="file of autotuner choices: written after the autotune pass, "
                          "read instead of tuning with --no-autotune")
@@ -374,6 +408,8 @@ def main():
         out["calibration_copy"] = calib
     if args.schedule == 0 and not args.no_schedule_comparison:
         out["persistent_vs_plain"] = schedule_comparison(api, dev, plan, outs, stream)
+    if not args.no_graph_comparison:
+        out["graph_vs_eager"] = graph_comparison(api, dev, plan, outs, stream)
     if args.serving_seconds > 0:
         out["serving"] = serving_leg(api, args.serving_seconds)
     if not args.no_cpu_baseline:

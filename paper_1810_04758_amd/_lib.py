@@ -62,7 +62,8 @@ class JoinOpts(ctypes.Structure):
     _fields_ = [("w_factor", c_f64), ("cell_width", c_f64), ("lanes_per_query", c_i32),
                 ("schedule", c_i32), ("batch_queries", c_i32), ("eps_step", c_f64),
                 ("linear_levels", c_i32), ("growth", c_f64), ("use_graph", c_i32),
-                ("tail_pairs", c_f64), ("stats", ctypes.POINTER(JoinStats))]
+                ("tail_pairs", c_f64), ("heavy_min", ctypes.c_int64),
+                ("stats", ctypes.POINTER(JoinStats))]
 
 
 class IndexInfo(ctypes.Structure):

@@ -501,19 +501,59 @@ __global__ void k_active_cand_sum(const int32_t* __restrict__ active, int64_t n_
                                   const uint32_t* __restrict__ cell_of,
                                   const uint32_t* __restrict__ cand_count, uint64_t* sum) {
   __shared__ unsigned long long red[kBlock];
+  __shared__ unsigned int redm[kBlock];
   unsigned long long s = 0;
+  unsigned int m = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_active;
        i += (int64_t)gridDim.x * blockDim.x) {
     int64_t q = active ? active[i] : i;
-    s += cand_count[cell_of[q]];
+    const unsigned int c = cand_count[cell_of[q]];
+    s += c;
+    m = max(m, c);
   }
   red[threadIdx.x] = s;
+  redm[threadIdx.x] = m;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      redm[threadIdx.x] = max(redm[threadIdx.x], redm[threadIdx.x + w]);
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd((unsigned long long*)sum, red[0]);
+  if (threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)sum, red[0]);
+    atomicMax((unsigned long long*)(sum + 1), (unsigned long long)redm[0]);
+  }
+}
+
+// Active queries (sorted positions) whose cell has at least heavy_min
+// candidates, appended to list (one atomic per wavefront); *count ends at
+// their number.
+__global__ void k_heavy_list(const int32_t* __restrict__ active, int64_t n_active,
+                             const uint32_t* __restrict__ cell_of,
+                             const uint32_t* __restrict__ cand_count, uint32_t heavy_min,
+                             int32_t* __restrict__ list, int32_t* count) {
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < n_active;
+       base += stride) {
+    const int64_t i = base + lane;
+    int32_t q = 0;
+    bool h = false;
+    if (i < n_active) {
+      q = active ? active[i] : (int32_t)i;
+      h = cand_count[cell_of[q]] >= heavy_min;
+    }
+    const uint64_t m = __ballot(h);
+    if (m) {
+      int b = 0;
+      if (lane == 0) b = atomicAdd(count, (int)__popcll(m));
+      b = __shfl(b, 0, 64);
+      const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+      if (h) list[b + (int)__popcll(m & lt)] = q;
+    }
+  }
 }
 
 __global__ void k_mark_failed(const int32_t* __restrict__ fail_list, const int32_t* d_count,
@@ -700,9 +740,18 @@ void launch_item_keys(const int32_t* active, int64_t n_active, int G, const uint
 
 void launch_active_cand_sum(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
                             const uint32_t* cand_count, uint64_t* sum, hipStream_t s) {
-  launch_zero(sum, sizeof(uint64_t), s);
+  launch_zero(sum, 2 * sizeof(uint64_t), s);
   k_active_cand_sum<<<grid_for(n_active, 1024), kBlock, 0, s>>>(active, n_active, cell_of,
                                                                  cand_count, sum);
+  KNN_LAUNCHED();
+}
+
+void launch_heavy_list(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
+                       const uint32_t* cand_count, uint32_t heavy_min, int32_t* list,
+                       int32_t* count, hipStream_t s) {
+  launch_zero(count, sizeof(int32_t), s);
+  k_heavy_list<<<grid_for(n_active, 2048), kBlock, 0, s>>>(active, n_active, cell_of, cand_count,
+                                                            heavy_min, list, count);
   KNN_LAUNCHED();
 }
 

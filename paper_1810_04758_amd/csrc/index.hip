@@ -158,7 +158,7 @@ int64_t JoinContext::device_bytes() const {
                    scal.bytes() + iscal.bytes() + active.bytes() + fail_list.bytes() +
                    failed.bytes() + ikeys.bytes() + ikeys2.bytes() + ivals.bytes() +
                    ivals2.bytes() + out_ids.bytes() + out_d.bytes() + tail_scratch.bytes() +
-                   cand_sum.bytes());
+                   cand_sum.bytes() + heavy.bytes());
 }
 
 double eps_min_of(const knn_index& idx, int32_t K) {
@@ -325,7 +325,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   c.active.reserve(N);
   c.fail_list.reserve(N);
   c.failed.reserve(N);
-  c.cand_sum.reserve(1);
+  c.cand_sum.reserve(2);
   const int ncu = cu_count(c.device);
 
   Events ev(st != nullptr);
@@ -390,6 +390,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     // lanes per query from the level's mean candidate count (the paper's t,
     // Sec. 4.7, chosen per level: the tail levels see far more candidates)
     double cand = 0;
+    uint64_t cand_max = 0;
     int T = T_fixed;
     if (rp) {
       cand = rp->cand;
@@ -397,17 +398,35 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       T = rp->T;
     } else {
       launch_active_cand_sum(active, A, c.cell_of.p, c.cand_count.p, c.cand_sum.p, s);
-      uint64_t tot = 0;
+      uint64_t tot[2] = {0, 0};
       uint32_t M = 0;
-      KNN_HIP(hipMemcpyAsync(&tot, c.cand_sum.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipMemcpyAsync(tot, c.cand_sum.p, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipMemcpyAsync(&M, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));  // the level's one round trip before the search
-      cand = (double)tot / (double)std::max<int64_t>(A, 1);
+      cand = (double)tot[0] / (double)std::max<int64_t>(A, 1);
+      cand_max = tot[1];
       c.M = M;
       if (T == 0) T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(cand, A, cap);
     }
     const int G = 64 / T;
     const int waves = search_waves_per_block(T, cap);
+    // Heavy queries: a query on one wavefront costs about C/T lane steps, the
+    // level about A*cand/(64*W) (W resident wavefronts); a query above half of
+    // that (and above 4096 candidates) would outlast the level, so it gets a
+    // workgroup of its own (persistent schedule only).
+    uint32_t heavy_min = 0;
+    if (rp) {
+      heavy_min = rp->heavy_min;
+    } else if (o.schedule == 0 && o.heavy_min >= 0) {
+      double hm;
+      if (o.heavy_min > 0) {
+        hm = (double)o.heavy_min;
+      } else {
+        const double W = (double)ncu * search_blocks_per_cu(idx.n, T, cap) * waves;
+        hm = std::max(4096.0, (double)T * (double)A * cand / (128.0 * W));
+      }
+      if ((double)cand_max >= hm) heavy_min = (uint32_t)std::min(hm, 4294967295.0);
+    }
     // work items, densest first (Sec. 4.5 work estimate; persistent schedule)
     const int64_t n_items = ceil_div(A, G);
     const int32_t* order = nullptr;
@@ -458,6 +477,17 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.fail_list = c.fail_list.p;
     a.fail_count = c.iscal.p + 8;
     a.refine_count = c.iscal.p + 9;
+    lp.heavy_min = heavy_min;
+    if (heavy_min > 0) {
+      // heavy queries first, one workgroup each (count stays on the device)
+      c.heavy.reserve(N);
+      a.heavy_min = heavy_min;
+      a.heavy = c.heavy.p;
+      a.n_heavy = c.iscal.p + 10;
+      launch_heavy_list(active, A, c.cell_of.p, c.cand_count.p, heavy_min, c.heavy.p,
+                        c.iscal.p + 10, s);
+      launch_search_heavy(a, idx.n, ncu, s);
+    }
     if (o.schedule == 0) {
       int blocks;
       if (rp) {
@@ -546,7 +576,8 @@ bool GraphPlan::matches(int32_t K_, const knn_join_opts& o, int32_t* ids_, doubl
          opts.cell_width == o.cell_width && opts.lanes_per_query == o.lanes_per_query &&
          opts.schedule == o.schedule && opts.batch_queries == o.batch_queries &&
          opts.eps_step == o.eps_step && opts.linear_levels == o.linear_levels &&
-         opts.growth == o.growth && opts.tail_pairs == o.tail_pairs;
+         opts.growth == o.growth && opts.tail_pairs == o.tail_pairs &&
+         opts.heavy_min == o.heavy_min;
 }
 
 GraphPlan::~GraphPlan() {

@@ -63,7 +63,8 @@ struct JoinContext {
   DevBuf<int32_t> out_ids;  // staging for host-destination joins
   DevBuf<double> out_d;
   DevBuf<char> tail_scratch;
-  DevBuf<uint64_t> cand_sum;
+  DevBuf<uint64_t> cand_sum;  // [0] candidates of the active queries, [1] their maximum
+  DevBuf<int32_t> heavy;      // heavy queries of the level
 
   int64_t device_bytes() const;
 };
@@ -80,6 +81,7 @@ struct LevelPlan {
   int blocks = 0;       // persistent grid
   int grain = 1;
   int64_t Mcap = 0;     // cells, when the level sized its ranges by them
+  uint32_t heavy_min = 0;
   int tail_rounds = 0;
   // statistics of the recorded run
   double cand = 0;

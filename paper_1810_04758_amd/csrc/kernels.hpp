@@ -78,10 +78,16 @@ void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_st
 void launch_item_keys(const int32_t* active /*nullable: identity*/, int64_t n_active,
                       int G, const uint32_t* cell_of, const uint32_t* cand_count,
                       uint64_t* keys, int32_t* vals, int64_t n_items, hipStream_t s);
-// *sum += candidate count of the cell of every active query (uint64, device).
+// sum[0] = total and sum[1] = maximum of the candidate counts of the cells of
+// the active queries (uint64, device).
 void launch_active_cand_sum(const int32_t* active /*nullable*/, int64_t n_active,
                             const uint32_t* cell_of, const uint32_t* cand_count, uint64_t* sum,
                             hipStream_t s);
+// list[0 .. *count) = the active sorted positions whose cell has at least
+// heavy_min candidates (order unspecified); *count is zeroed first.
+void launch_heavy_list(const int32_t* active /*nullable*/, int64_t n_active,
+                       const uint32_t* cell_of, const uint32_t* cand_count, uint32_t heavy_min,
+                       int32_t* list, int32_t* count, hipStream_t s);
 // flags[p] = failed[perm[p]] for the next level's active list.
 void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count,
                         int64_t max_fail, uint8_t* failed, hipStream_t s);
@@ -131,10 +137,17 @@ struct SearchArgs {
   int32_t* fail_list;      // point ids of failed queries
   int32_t* fail_count;
   int32_t* refine_count;   // diagnostics: refinement rounds executed
+  uint32_t heavy_min;      // > 0: k_search leaves queries with this many candidates or more
+  const int32_t* heavy;    // to k_search_heavy: their sorted positions
+  const int32_t* n_heavy;  // and their number (device)
 };
 // Returns the number of waves per block used.
 void launch_search(const SearchArgs& a, int dims, int lanes_per_query, int grid_blocks,
                    hipStream_t s);
+// One workgroup of kHeavyThreads per query for the heavy queries a.heavy[0 ..
+// *a.n_heavy), grid-stride over them (blocks: any positive count).
+constexpr int kHeavyThreads = 1024;
+void launch_search_heavy(const SearchArgs& a, int dims, int blocks, hipStream_t s);
 // Dynamic LDS bytes per wave for a given (lanes_per_query, cap).
 size_t search_lds_per_wave(int lanes_per_query, int cap);
 int search_waves_per_block(int lanes_per_query, int cap);

@@ -236,8 +236,8 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
     first = false;
     const int64_t it = a.order ? (int64_t)a.order[item] : item;
     const int64_t slot = it * G + g;
-    const bool valid = slot < a.n_active;
-    const int64_t q = valid ? (a.active ? (int64_t)a.active[slot] : slot) : 0;
+    const bool in = slot < a.n_active;
+    const int64_t q = in ? (a.active ? (int64_t)a.active[slot] : slot) : 0;
 
     // ---- query point, covered radius ---------------------------------------
     double qx[DIM];
@@ -245,8 +245,11 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
     for (int j = 0; j < DIM; ++j) qx[j] = Xs[(int64_t)j * N + q];
     const uint32_t cell = a.cell_of[q];
     const uint32_t* rg = a.ranges + (size_t)cell * R * 2;
+    const uint32_t Cq = in ? a.cand[cell] : 0u;
+    // heavy queries are handled by k_search_heavy
+    const bool valid = in && (a.heavy_min == 0 || Cq < a.heavy_min);
     const int nr = valid ? (int)a.nrng[cell] : 0;
-    const uint32_t C = valid ? a.cand[cell] : 0u;
+    const uint32_t C = valid ? Cq : 0u;
     double mfrac = 0.5;
     bool full = true;
 #pragma unroll
@@ -503,6 +506,259 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
   if (nfail > 0) flush_failures(a, fbuf, nfail, lane);
 }
 
+
+// The same search for one query per workgroup of kHeavyThreads lanes: the
+// queries of a level whose candidate count is far above the level's mean
+// (next to dense regions after the cell side has grown), which would keep a
+// single wavefront busy long after the rest of the level is done.  Same bins,
+// selection, refinement and ranking as k_search, with workgroup barriers in
+// place of the group's lane exchanges.
+template <int DIM>
+__global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs a) {
+  constexpr int R = Pow3<DIM - 1>::v;
+  constexpr int NT = kHeavyThreads;
+  extern __shared__ double smem[];
+  __shared__ uint32_t hist[NB];
+  __shared__ uint32_t hist2[NB2];
+  __shared__ int s_bsel, s_clo, s_chi, s_refine;
+  __shared__ unsigned long long s_dmin, s_dmax;
+  __shared__ unsigned __int128 s_A, s_B;
+  const int tid = threadIdx.x;
+  const int cap = a.cap;
+  const int K = a.K;
+  const int64_t N = a.N;
+  const double* __restrict__ Xs = a.Xs;
+  const int32_t* __restrict__ perm = a.perm;
+  double* bd = smem;
+  int32_t* bi = reinterpret_cast<int32_t*>(smem + cap);
+  const int nh = *a.n_heavy;
+
+  for (int hq = blockIdx.x; hq < nh; hq += gridDim.x) {
+    const int64_t q = a.heavy[hq];
+    double qx[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) qx[j] = Xs[(int64_t)j * N + q];
+    const uint32_t cell = a.cell_of[q];
+    const uint32_t* rg = a.ranges + (size_t)cell * R * 2;
+    const int nr = (int)a.nrng[cell];
+    const uint32_t C = a.cand[cell];
+    double mfrac = 0.5;
+    bool full = true;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      double u = __dmul_rn(__dsub_rn(qx[j], a.lo[j]), a.inv_w);
+      double fl = floor(u);
+      double fr = u - fl;
+      mfrac = fmin(mfrac, fmin(fr, 1.0 - fr));
+      int64_t c = (int64_t)fl;
+      if (c > 1 || c < a.g[j] - 2) full = false;
+    }
+    double thr, ref;
+    if (full) {
+      thr = INFINITY;
+      ref = 9.0 * DIM * a.w * a.w;
+    } else {
+      double base = (1.0 + mfrac) * a.w;
+      double r = base * (1.0 - a.margin);
+      thr = r * r;
+      ref = thr;
+    }
+    const int64_t top = (int64_t)((uint64_t)__double_as_longlong(ref) >> kBinShift);
+
+    // ---- count pass
+    for (int b = tid; b < NB; b += NT) hist[b] = 0;
+    __syncthreads();
+    {
+      Cands cs;
+      cs.init(rg, nr);
+      for (uint32_t v = tid; v < C; v += NT * kUnroll) {
+        uint32_t p[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const uint32_t vv = v + (uint32_t)(u * NT);
+          p[u] = vv < C ? cs.pos(vv) : 0xFFFFFFFFu;
+        }
+        double d2[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          d2[u] = sq_dist<DIM>(Xs, N, p[u] != 0xFFFFFFFFu ? p[u] : 0u, qx);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (p[u] != 0xFFFFFFFFu && (int64_t)p[u] != q) {
+            const int b = bin_of(d2[u], thr, top);
+            if (b < NB) atomicAdd(&hist[b], 1u);
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- selection (one lane), histogram -> exclusive prefixes
+    if (tid == 0) {
+      int cum = 0, bsel = NB, clo = 0, chi = 0;
+      for (int b = 0; b < NB; ++b) {
+        const int h = (int)hist[b];
+        if (bsel == NB && cum + h >= K) {
+          bsel = b;
+          clo = cum;
+          chi = cum + h;
+        }
+        hist[b] = (uint32_t)cum;
+        cum += h;
+      }
+      s_bsel = bsel;
+      s_clo = clo;
+      s_chi = chi;
+      s_dmin = ~0ull;
+      s_dmax = 0ull;
+      if (bsel == NB) a.fail_list[atomicAdd(a.fail_count, 1)] = perm[q];
+    }
+    __syncthreads();
+    const int bsel = s_bsel;
+    if (bsel == NB) continue;  // failed: re-queued for a larger cell side
+
+    // ---- exact refinement when the selected bin overflows the buffer
+    const bool refined = s_chi > cap;
+    if (refined) {
+      {
+        unsigned long long mn = ~0ull, mx = 0ull;
+        Cands cs;
+        cs.init(rg, nr);
+        for (uint32_t v = tid; v < C; v += NT) {
+          const uint32_t p = cs.pos(v);
+          if ((int64_t)p != q) {
+            const double d2 = sq_dist<DIM>(Xs, N, p, qx);
+            if (bin_of(d2, thr, top) == bsel) {
+              const unsigned long long kb = (unsigned long long)__double_as_longlong(d2);
+              mn = min(mn, kb);
+              mx = max(mx, kb);
+            }
+          }
+        }
+        if (mn != ~0ull) atomicMin(&s_dmin, mn);
+        if (mx != 0ull) atomicMax(&s_dmax, mx);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        s_A = (unsigned __int128)(uint64_t)s_dmin << 32;
+        s_B = ((unsigned __int128)(uint64_t)s_dmax << 32) | 0xFFFFFFFFu;
+        s_refine = 1;
+      }
+      __syncthreads();
+      int rounds = 0;
+      while (s_refine) {
+        ++rounds;
+        const unsigned __int128 A = s_A, B = s_B;
+        int sh = bitlen128(B - A) - kLog2NB2;
+        if (sh < 0) sh = 0;
+        for (int b = tid; b < NB2; b += NT) hist2[b] = 0;
+        __syncthreads();
+        {
+          const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
+          Cands cs;
+          cs.init(rg, nr);
+          for (uint32_t v = tid; v < C; v += NT) {
+            const uint32_t p = cs.pos(v);
+            if ((int64_t)p != q) {
+              const double d2 = sq_dist<DIM>(Xs, N, p, qx);
+              const uint64_t kh = (uint64_t)__double_as_longlong(d2);
+              if (kh >= ahi && kh <= bhi) {
+                const unsigned __int128 k = ((unsigned __int128)kh << 32) | (uint32_t)perm[p];
+                if (k >= A && k <= B) atomicAdd(&hist2[(int)((k - A) >> sh)], 1u);
+              }
+            }
+          }
+        }
+        __syncthreads();
+        if (tid == 0) {
+          int cum = s_clo;
+          for (int b = 0; b < NB2; ++b) {
+            const int h = (int)hist2[b];
+            if (cum + h >= K) {
+              const unsigned __int128 nA = A + ((unsigned __int128)b << sh);
+              const unsigned __int128 nB = nA + (((unsigned __int128)1 << sh) - 1);
+              s_A = nA;
+              s_B = nB < B ? nB : B;
+              s_clo = cum;
+              s_chi = cum + h;
+              break;
+            }
+            cum += h;
+          }
+          if (s_chi <= cap) s_refine = 0;
+        }
+        __syncthreads();
+      }
+      if (tid == 0 && a.refine_count) atomicAdd(a.refine_count, rounds);
+    }
+    const unsigned __int128 Bf = s_B;
+    const double th_d = __longlong_as_double((long long)(uint64_t)(Bf >> 32));
+    const uint32_t th_id = (uint32_t)(Bf & 0xFFFFFFFFu);
+
+    // ---- collect pass
+    {
+      Cands cs;
+      cs.init(rg, nr);
+      for (uint32_t v = tid; v < C; v += NT * kUnroll) {
+        uint32_t pp[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const uint32_t vv = v + (uint32_t)(u * NT);
+          pp[u] = vv < C ? cs.pos(vv) : 0xFFFFFFFFu;
+        }
+        double dd[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          dd[u] = sq_dist<DIM>(Xs, N, pp[u] != 0xFFFFFFFFu ? pp[u] : 0u, qx);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const uint32_t p = pp[u];
+          if (p == 0xFFFFFFFFu || (int64_t)p == q) continue;
+          const double d2 = dd[u];
+          const int b = bin_of(d2, thr, top);
+          bool acc;
+          if (refined)
+            acc = d2 < th_d || (d2 == th_d && (th_id == 0xFFFFFFFFu || (uint32_t)perm[p] <= th_id));
+          else
+            acc = b <= bsel;
+          if (acc) {
+            const uint32_t sidx = atomicAdd(&hist[b], 1u);
+            if ((int)sidx < cap) {
+              bd[sidx] = d2;
+              bi[sidx] = perm[p];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- rank pass -> output row
+    const int c = min((int)hist[bsel], cap);
+    const int64_t row = (int64_t)perm[q];
+    for (int ai = tid; ai < c; ai += NT) {
+      const double da = bd[ai];
+      const int32_t ia = bi[ai];
+      const int b = bin_of(da, thr, top);
+      const int start = b > 0 ? (int)hist[b - 1] : 0;
+      if (start < K) {
+        const int end = min((int)hist[b], cap);
+        int rank = start;
+        for (int s2 = start; s2 < end; ++s2) {
+          const double db = bd[s2];
+          const int32_t ib = bi[s2];
+          rank += (db < da || (db == da && ib < ia)) ? 1 : 0;
+        }
+        if (rank < K) {
+          a.out_ids[row * K + rank] = ia;
+          a.out_d[row * K + rank] = sqrt(da);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int DIM, int T>
 int occupancy_of(int threads, size_t lds) {
   int n = 0;
@@ -566,6 +822,21 @@ int search_blocks_per_cu(int dims, int T, int cap) {
     default: break;
   }
   return n > 0 ? n : 1;
+}
+
+void launch_search_heavy(const SearchArgs& a, int dims, int blocks, hipStream_t s) {
+  KNN_CHECK(a.heavy && a.n_heavy && blocks > 0, KNN_EINTERNAL, "heavy-query launch without a list");
+  const size_t lds = (size_t)a.cap * (sizeof(double) + sizeof(int32_t));
+  KNN_CHECK(lds <= 49152, KNN_EINVAL, "K too large for the per-query buffers");
+  switch (dims) {
+    case 2: k_search_heavy<2><<<blocks, kHeavyThreads, lds, s>>>(a); break;
+    case 3: k_search_heavy<3><<<blocks, kHeavyThreads, lds, s>>>(a); break;
+    case 4: k_search_heavy<4><<<blocks, kHeavyThreads, lds, s>>>(a); break;
+    case 5: k_search_heavy<5><<<blocks, kHeavyThreads, lds, s>>>(a); break;
+    case 6: k_search_heavy<6><<<blocks, kHeavyThreads, lds, s>>>(a); break;
+    default: throw Error(KNN_EINVAL, "dims out of range");
+  }
+  KNN_LAUNCHED();
 }
 
 void launch_search(const SearchArgs& a, int dims, int T, int grid_blocks, hipStream_t s) {

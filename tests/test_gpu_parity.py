@@ -314,3 +314,22 @@ def test_graph_replay(knn, oracle_mod, name, gen, K, opts):
     if name == "expo3d_tail":
         assert st_e["tail_queries"] > 0 and st_e["levels"] >= 2
     idx.close()
+
+
+@pytest.mark.parametrize("heavy_min", [1, 150, -1])
+@pytest.mark.parametrize("name,gen,K", [
+    ("expo4d", lambda: datagen.exponential(15013, 4, seed=41), 24),
+    ("clus2d", lambda: datagen.clustered(20011, seed=42), 40),
+    ("unif6d", lambda: datagen.uniform(4001, 6, seed=43), 5),
+], ids=["expo4d", "clus2d", "unif6d"])
+def test_heavy_queries(knn, oracle_mod, name, gen, K, heavy_min):
+    """Queries routed to the workgroup-per-query kernel (all of them with
+    heavy_min=1, the larger cells with 150, none with -1) give the oracle's
+    result; with a small cell side the refinement and the failures go through
+    it too."""
+    D = gen()
+    N = D.shape[0]
+    _say(f"[heavy] {name} N={N} K={K} heavy_min={heavy_min}")
+    ids, dists, st = _join(knn, D, K, heavy_min=heavy_min, w_factor=0.6, tail_pairs=-1)
+    _check_rows(D, ids, dists, K, np.arange(N), oracle_mod)
+    assert st["levels"] >= 2
