@@ -112,9 +112,14 @@ typedef struct knn_join_opts {
                              repeat the recorded counts; per-level times are 0 [0] */
   double tail_pairs;      /* brute-force tail once (remaining queries) x N <= this
                              [1.5e9]; < 0 disables the tail (Sec. 5.3.8 remedy) */
-  int64_t heavy_min;      /* persistent schedule: queries with at least this many
+  int64_t heavy_min;      /* queries with at least this many
                              candidates get a workgroup each; 0 = automatic
                              (those that would outlast the level), < 0 = never */
+  int32_t queue_grain;    /* persistent schedule: work items claimed per queue pop;
+                             0 = automatic [about 4 pops per wavefront] */
+  int32_t item_order;     /* persistent schedule: 0 = densest class first inside
+                             each XCD's contiguous chunk (Sec. 4.5 ordering);
+                             1 = cell order [0] */
   knn_join_stats* stats;  /* optional statistics output */
 } knn_join_opts;
 

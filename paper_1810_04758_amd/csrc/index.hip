@@ -265,12 +265,12 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
 // on average (measured on MI355X over t in 2..64 and 2-6 dims): the power of
 // two nearest cand^0.6 / 4, raised until the level has enough lanes to fill
 // the GPU (A * t >= 2^18) and the per-wave LDS buffers stay within 16 KiB.
-static int lanes_for(double cand, int64_t A, int cap) {
+static int lanes_for(int dims, double cand, int64_t A, int cap) {
   const double want = std::pow(std::max(cand, 1.0), 0.6) / 4.0;
   int T = 2;
   while (T < 64 && (double)T * 1.41421356 < want) T *= 2;
   while (T < 64 && (double)A * T < (double)(1 << 18)) T *= 2;
-  while (T < 64 && search_lds_per_wave(T, cap) > 16384) T *= 2;
+  while (T < 64 && search_lds_per_wave(dims, T, cap) > 16384) T *= 2;
   return T;
 }
 
@@ -320,7 +320,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   double diag2 = 0;
   for (int j = 0; j < idx.n; ++j) diag2 += (idx.hi[j] - idx.lo[j]) * (idx.hi[j] - idx.lo[j]);
 
-  c.iscal.reserve(16);  // [0..7] XCD queue heads, [8] failures, [9] refinement rounds
+  c.iscal.reserve(kCounterInts);  // queue heads, failures, refinement rounds, heavy queries
   c.scal.reserve(4);
   c.active.reserve(N);
   c.fail_list.reserve(N);
@@ -406,18 +406,21 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       cand = (double)tot[0] / (double)std::max<int64_t>(A, 1);
       cand_max = tot[1];
       c.M = M;
-      if (T == 0) T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(cand, A, cap);
+      if (T == 0) T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(idx.n, cand, A, cap);
     }
+    // the per-wave buffers of small T grow with 3^(n-1) segment lists: raise
+    // T until one wavefront's LDS fits
+    while (T < 64 && search_lds_per_wave(idx.n, T, cap) > 65536) T *= 2;
     const int G = 64 / T;
-    const int waves = search_waves_per_block(T, cap);
+    const int waves = search_waves_per_block(idx.n, T, cap);
     // Heavy queries: a query on one wavefront costs about C/T lane steps, the
     // level about A*cand/(64*W) (W resident wavefronts); a query above half of
     // that (and above 4096 candidates) would outlast the level, so it gets a
-    // workgroup of its own (persistent schedule only).
+    // workgroup of its own.
     uint32_t heavy_min = 0;
     if (rp) {
       heavy_min = rp->heavy_min;
-    } else if (o.schedule == 0 && o.heavy_min >= 0) {
+    } else if (o.heavy_min >= 0) {
       double hm;
       if (o.heavy_min > 0) {
         hm = (double)o.heavy_min;
@@ -430,7 +433,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     // work items, densest first (Sec. 4.5 work estimate; persistent schedule)
     const int64_t n_items = ceil_div(A, G);
     const int32_t* order = nullptr;
-    if (o.schedule == 0 && n_items > 1) {
+    if (o.schedule == 0 && o.item_order == 0 && n_items > 1) {
       c.ikeys.reserve(n_items);
       c.ikeys2.reserve(n_items);
       c.ivals.reserve(n_items);
@@ -443,7 +446,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       }
       order = c.ivals.p;
     }
-    launch_zero(c.iscal.p, 16 * sizeof(int32_t), s);
+    launch_zero(c.iscal.p, kCounterInts * sizeof(int32_t), s);
     ev.rec(1, s);
 
     SearchArgs a{};
@@ -452,6 +455,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.perm = c.perm.p;
     a.cell_of = c.cell_of.p;
     a.ranges = c.ranges.p;
+    a.rslot = c.rslot.p;
     a.nrng = c.nrng.p;
     a.cand = c.cand_count.p;
     a.active = active;
@@ -475,17 +479,17 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.out_ids = d_ids;
     a.out_d = d_dists;
     a.fail_list = c.fail_list.p;
-    a.fail_count = c.iscal.p + 8;
-    a.refine_count = c.iscal.p + 9;
+    a.fail_count = c.iscal.p + kFailSlot;
+    a.refine_count = c.iscal.p + kRefineSlot;
     lp.heavy_min = heavy_min;
     if (heavy_min > 0) {
       // heavy queries first, one workgroup each (count stays on the device)
       c.heavy.reserve(N);
       a.heavy_min = heavy_min;
       a.heavy = c.heavy.p;
-      a.n_heavy = c.iscal.p + 10;
+      a.n_heavy = c.iscal.p + kHeavySlot;
       launch_heavy_list(active, A, c.cell_of.p, c.cand_count.p, heavy_min, c.heavy.p,
-                        c.iscal.p + 10, s);
+                        c.iscal.p + kHeavySlot, s);
       launch_search_heavy(a, idx.n, ncu, s);
     }
     if (o.schedule == 0) {
@@ -500,7 +504,9 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
         // about four pops per wavefront and queue: few atomics, fine enough
         // granularity for the dense-first balance at the end of each queue
         const int64_t total_waves = (int64_t)blocks * waves;
-        a.grain = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, n_items / (total_waves * 4)));
+        a.grain = o.queue_grain > 0
+                      ? o.queue_grain
+                      : (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, n_items / (total_waves * 4)));
       }
       lp.blocks = blocks;
       lp.grain = a.grain;
@@ -521,7 +527,10 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       sc[0] = rp->fails;
       sc[1] = rp->refine;
     } else {
-      KNN_HIP(hipMemcpyAsync(sc, c.iscal.p + 8, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipMemcpyAsync(&sc[0], c.iscal.p + kFailSlot, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipMemcpyAsync(&sc[1], c.iscal.p + kRefineSlot, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));
     }
     const int32_t fails = sc[0];
@@ -556,7 +565,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     // failures are re-queued on a grid with a larger cell side (Alg. 1):
     // linear growth by eps_step * w0 first, then geometric growth
     launch_zero(c.failed.p, (size_t)N, s);
-    launch_mark_failed(c.fail_list.p, c.iscal.p + 8, fails, c.failed.p, s);
+    launch_mark_failed(c.fail_list.p, c.iscal.p + kFailSlot, fails, c.failed.p, s);
     A = fails;
     w = (1.0 / c.gg.inv_w);
     if (level < linear)
@@ -577,7 +586,8 @@ bool GraphPlan::matches(int32_t K_, const knn_join_opts& o, int32_t* ids_, doubl
          opts.schedule == o.schedule && opts.batch_queries == o.batch_queries &&
          opts.eps_step == o.eps_step && opts.linear_levels == o.linear_levels &&
          opts.growth == o.growth && opts.tail_pairs == o.tail_pairs &&
-         opts.heavy_min == o.heavy_min;
+         opts.heavy_min == o.heavy_min && opts.queue_grain == o.queue_grain &&
+         opts.item_order == o.item_order;
 }
 
 GraphPlan::~GraphPlan() {

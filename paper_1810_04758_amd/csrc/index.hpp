@@ -55,7 +55,7 @@ struct JoinContext {
   DevBuf<int32_t> vals2;
   DevBuf<uint32_t> flags, tmp;
   DevBuf<uint32_t> scal;  // [0] = M, [1] = active count
-  DevBuf<int32_t> iscal;  // [0] = head, [1] = fail count, [2] = refine rounds
+  DevBuf<int32_t> iscal;  // level counters (kCounterInts, one 128-byte line each)
   DevBuf<int32_t> active, fail_list;
   DevBuf<uint8_t> failed;
   DevBuf<uint64_t> ikeys, ikeys2;

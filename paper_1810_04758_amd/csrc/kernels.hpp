@@ -8,6 +8,15 @@ namespace knn {
 constexpr int kMaxDims = KNN_MAX_DIMS;
 constexpr int kXcds = 8;  // accelerator complex dies of an MI355X, each with its own L2
 
+// Device counters of a search level, each on a 128-byte line of its own:
+// device-scope atomics on one line serialize, and the queue heads of the
+// eight XCDs are hit concurrently.
+constexpr int kLineInts = 32;
+constexpr int kFailSlot = kXcds * kLineInts;       // failed queries
+constexpr int kRefineSlot = kFailSlot + kLineInts;   // refinement rounds (diagnostics)
+constexpr int kHeavySlot = kRefineSlot + kLineInts;  // heavy queries
+constexpr int kCounterInts = kHeavySlot + kLineInts;
+
 // Geometry of one grid level (Sec. 3.1): cell side 1/inv_w, origin lo.
 struct GridGeom {
   int32_t dims;
@@ -114,6 +123,7 @@ struct SearchArgs {
   const int32_t* perm;     // sorted position -> point id
   const uint32_t* cell_of; // sorted position -> cell
   const uint32_t* ranges;  // cell*R*2 compacted non-empty row-segment ranges
+  const uint8_t* rslot;    // cell*R: segment index of each compacted range
   const uint32_t* nrng;    // non-empty segments per cell
   const uint32_t* cand;    // candidates per cell
   const int32_t* active;   // active sorted positions (nullptr: identity)
@@ -121,7 +131,7 @@ struct SearchArgs {
   const int32_t* order;    // item order (nullptr: identity)
   int64_t n_items;
   int64_t item_base;       // first item of this launch (schedule 1)
-  int32_t* head;           // persistent work-queue heads, one per XCD (device)
+  int32_t* head;           // persistent work-queue heads: XCD x at head[x * kLineInts]
   int64_t qbeg[kXcds + 1]; // queue x = order positions [qbeg[x], qbeg[x+1])
   int32_t grain;           // items claimed per queue pop
   int32_t persistent;
@@ -149,8 +159,8 @@ void launch_search(const SearchArgs& a, int dims, int lanes_per_query, int grid_
 constexpr int kHeavyThreads = 1024;
 void launch_search_heavy(const SearchArgs& a, int dims, int blocks, hipStream_t s);
 // Dynamic LDS bytes per wave for a given (lanes_per_query, cap).
-size_t search_lds_per_wave(int lanes_per_query, int cap);
-int search_waves_per_block(int lanes_per_query, int cap);
+size_t search_lds_per_wave(int dims, int lanes_per_query, int cap);
+int search_waves_per_block(int dims, int lanes_per_query, int cap);
 // Resident blocks per CU of the search kernel (occupancy API).
 int search_blocks_per_cu(int dims, int lanes_per_query, int cap);
 

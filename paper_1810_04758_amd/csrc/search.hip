@@ -37,6 +37,10 @@
 // computed d^2 > r^2 and cannot precede a survivor.
 #pragma clang fp contract(off)
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "kernels.hpp"
 
 namespace knn {
@@ -47,7 +51,12 @@ constexpr int NB = 64;         // count-pass bins: 8 octaves of d^2
 constexpr int kBinShift = 49;  // exponent + 3 mantissa bits: 8 bins per octave
 constexpr int NB2 = 32;        // bins of one exact-bisection round
 constexpr int kLog2NB2 = 5;
-constexpr int kUnroll = 4;     // candidates per lane in flight in the count/collect walks
+// candidates per lane in flight in the count/collect walks (fewer in 5-6
+// dimensions, whose coordinates take more registers)
+template <int DIM>
+struct Unroll {
+  static constexpr int v = DIM <= 4 ? 4 : 2;
+};
 constexpr int kFailBuf = 64;   // failed ids buffered per wavefront before one global append
 
 template <int D>
@@ -60,12 +69,12 @@ struct Pow3<0> {
 };
 
 template <int DIM>
-__device__ __forceinline__ double sq_dist(const double* __restrict__ Xs, int64_t N, int64_t p,
+__device__ __forceinline__ double sq_dist(const double* __restrict__ const (&Xd)[DIM], uint32_t p,
                                           const double (&q)[DIM]) {
   double s = 0.0;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    double t = __dsub_rn(Xs[(int64_t)j * N + p], q[j]);
+    double t = __dsub_rn(Xd[j][p], q[j]);
     s = __dadd_rn(s, __dmul_rn(t, t));
   }
   return s;
@@ -74,11 +83,20 @@ __device__ __forceinline__ double sq_dist(const double* __restrict__ Xs, int64_t
 // Monotone bin of a squared distance: 0..NB-1 for d2 <= thr, NB above it.
 // top = (bit pattern of the reference top) >> kBinShift; the bit pattern of a
 // non-negative double is monotone in its value, so the bin is monotone in d2.
-__device__ __forceinline__ int bin_of(double d2, double thr, int64_t top) {
-  const int64_t k =
-      (int64_t)((uint64_t)__double_as_longlong(d2) >> kBinShift) - top + (NB - 1);
-  const int b = k < 0 ? 0 : (k > NB - 1 ? NB - 1 : (int)k);
+// Only the high word is needed (kBinShift >= 32).
+__device__ __forceinline__ int bin_of(double d2, double thr, int top) {
+  const int k = (int)((uint32_t)__double2hiint(d2) >> (kBinShift - 32)) - top + (NB - 1);
+  const int b = min(max(k, 0), NB - 1);
   return d2 > thr ? NB : b;
+}
+
+// Upper limit of the squared distances in bins 0..b (for pruning the passes
+// that only need those bins): below the next bin edge, and never above thr.
+__device__ __forceinline__ double bins_limit(int b, double thr, int top) {
+  const int e = top - (NB - 1) + b + 1;  // bit pattern >> kBinShift of the next edge
+  if (b >= NB - 1 || e <= 0 || e >= (0x7FF0 >> (kBinShift - 48))) return thr;
+  const double edge = __longlong_as_double((long long)((uint64_t)e << kBinShift));
+  return fmin(edge, thr);
 }
 
 __device__ __forceinline__ void wave_fence() {
@@ -125,28 +143,105 @@ __device__ __forceinline__ int bitlen128(unsigned __int128 v) {
   return hi ? 128 - __builtin_clzll(hi) : (lo ? 64 - __builtin_clzll(lo) : 0);
 }
 
-// Flattened walk over a cell's non-empty row segments: virtual candidate v
-// (non-decreasing from call to call, below the cell's candidate count) ->
-// sorted position.
-struct Cands {
-  const uint32_t* rg;
-  uint32_t vs, ve, st;
+// Per-query candidate list in LDS: the non-empty row segments that a pass
+// needs, compacted, as (start position, running end in virtual candidate
+// numbering).  A segment is left out when a conservative lower bound of the
+// squared distance from the query to any of its points exceeds the pass's
+// limit (all its candidates would be beyond it).  The bound uses the query's
+// distances to its own cell's faces in the first n-1 dimensions (the segment
+// spans three cells along the last): a neighbour at offset +1 in dimension j
+// is at least (1 - fr_j - mg) w away, at offset -1 at least (fr_j - mg) w,
+// where fr_j is the query's exact fractional cell coordinate and mg bounds
+// the rounding of both cell coordinates in cell units; the final factor
+// (1 - 2^-40) covers the rounding of the bound and of the computed d2.
+constexpr double kBoundShrink = 1.0 - 0x1p-40;
+
+template <int DIM>
+__device__ __forceinline__ double seg_bound(int slot, const double (&flo)[DIM],
+                                            const double (&fhi)[DIM]) {
+  double s = 0.0;
+  int rr = slot;
+#pragma unroll
+  for (int j = DIM - 2; j >= 0; --j) {
+    const int o = rr % 3;
+    rr /= 3;
+    const double d = o == 0 ? flo[j] : (o == 2 ? fhi[j] : 0.0);
+    s += d * d;
+  }
+  return s;
+}
+
+// Builds the list of one query (its T lanes call it together; nr_w is the
+// wavefront's maximum segment count, so every lane takes the same trips and
+// the group exchanges stay converged).  Returns the list's candidate count.
+template <int DIM, int T>
+__device__ __forceinline__ uint32_t build_list(const uint32_t* __restrict__ rg,
+                                               const uint8_t* __restrict__ rs, int nr, int nr_w,
+                                               bool prune, double lim, const double (&qx)[DIM],
+                                               const SearchArgs& a, int l, uint32_t* seg_st,
+                                               uint32_t* seg_ve) {
+  // face distances (recomputed here rather than kept live through the passes)
+  double flo[DIM], fhi[DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    const double u = __dmul_rn(__dsub_rn(qx[j], a.lo[j]), a.inv_w);
+    const double fr = u - floor(u);  // exact
+    flo[j] = fmax(fr - a.margin, 0.0) * a.w;
+    fhi[j] = fmax((1.0 - fr) - a.margin, 0.0) * a.w;
+  }
+  uint32_t total = 0, cnt = 0;
+  for (int i0 = 0; i0 < nr_w; i0 += T) {
+    const int i = i0 + l;
+    uint32_t st = 0, len = 0;
+    if (i < nr) {
+      st = rg[2 * i];
+      len = rg[2 * i + 1] - st;
+      if (prune && seg_bound<DIM>(rs[i], flo, fhi) * kBoundShrink > lim) len = 0;
+    }
+    const uint32_t keep = len > 0 ? 1u : 0u;
+    uint32_t ik = keep, il = len;
+#pragma unroll
+    for (int o = 1; o < T; o <<= 1) {
+      const uint32_t uk = __shfl_up(ik, o, T);
+      const uint32_t ul = __shfl_up(il, o, T);
+      if (l >= o) {
+        ik += uk;
+        il += ul;
+      }
+    }
+    if (keep) {
+      seg_st[cnt + ik - 1] = st;
+      seg_ve[cnt + ik - 1] = total + il;
+    }
+    cnt += __shfl(ik, T - 1, T);
+    total += __shfl(il, T - 1, T);
+  }
+  return total;
+}
+
+// Walk over a list: virtual candidate v (non-decreasing from call to call,
+// below the list's count) -> sorted position.
+struct LWalk {
+  const uint32_t* st;
+  const uint32_t* ve;
   int r;
-  __device__ __forceinline__ void init(const uint32_t* rg_, int nr) {
-    rg = rg_;
+  uint32_t vs, vend, s0;
+  __device__ __forceinline__ void init(const uint32_t* st_, const uint32_t* ve_, uint32_t C) {
+    st = st_;
+    ve = ve_;
     r = 0;
     vs = 0;
-    st = nr > 0 ? rg[0] : 0u;
-    ve = nr > 0 ? rg[1] - st : 0u;
+    vend = C > 0 ? ve[0] : 0u;
+    s0 = C > 0 ? st[0] : 0u;
   }
   __device__ __forceinline__ uint32_t pos(uint32_t v) {
-    while (v >= ve) {
+    while (v >= vend) {
       ++r;
-      vs = ve;
-      st = rg[2 * r];
-      ve = vs + (rg[2 * r + 1] - st);
+      vs = vend;
+      vend = ve[r];
+      s0 = st[r];
     }
-    return st + (v - vs);
+    return s0 + (v - vs);
   }
 };
 
@@ -161,10 +256,11 @@ __device__ __forceinline__ void flush_failures(const SearchArgs& a, const int32_
 }
 
 template <int DIM, int T>
-__global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_search(const SearchArgs a) {
   constexpr int G = 64 / T;  // queries per wave
   constexpr int R = Pow3<DIM - 1>::v;
   constexpr int P = NB / T;  // count bins owned by each lane of a group
+  constexpr int kUnroll = Unroll<DIM>::v;
   extern __shared__ double smem[];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -174,21 +270,27 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
   const int cap = a.cap;
   const int K = a.K;
   const int64_t N = a.N;
-  const double* __restrict__ Xs = a.Xs;
   const int32_t* __restrict__ perm = a.perm;
+  // per-dimension coordinate arrays (uniform base pointers)
+  const double* __restrict__ Xd[DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) Xd[j] = a.Xs + (int64_t)j * N;
 
   // per-wave LDS: survivors d2 [cap][G], survivor ids [cap][G], histogram
-  // [NB][G]; the refinement histogram [NB2][G] reuses the d2 area (it is free
-  // before the collect, and cap >= NB2/2 + 1).
-  // Layout: [d2 of all waves][ids of all waves][histograms][failure buffers].
+  // [NB][G], failure buffer, candidate lists [G][R] (starts, ends); the
+  // refinement histogram [NB2][G] reuses the d2 area (it is free before the
+  // collect, and cap >= NB2/2 + 1).
   int32_t* bi_base = reinterpret_cast<int32_t*>(smem + (size_t)nwaves * cap * G);
   uint32_t* hist_base = reinterpret_cast<uint32_t*>(bi_base + (size_t)nwaves * cap * G);
   int32_t* fbuf_base = reinterpret_cast<int32_t*>(hist_base + (size_t)nwaves * NB * G);
+  uint32_t* seg_base = reinterpret_cast<uint32_t*>(fbuf_base + (size_t)nwaves * kFailBuf);
   double* bd = smem + (size_t)wave * cap * G;
   int32_t* bi = bi_base + (size_t)wave * cap * G;
   uint32_t* hist = hist_base + (size_t)wave * NB * G;
   uint32_t* hist2 = reinterpret_cast<uint32_t*>(bd);
   int32_t* fbuf = fbuf_base + (size_t)wave * kFailBuf;
+  uint32_t* seg_st = seg_base + (size_t)wave * 2 * R * G + (size_t)g * R;
+  uint32_t* seg_ve = seg_st + (size_t)R * G;
 
   const uint64_t lane_lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
@@ -213,8 +315,9 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
         int v = 0;
         if (lane == 0) {
           // a plain load first: drained queues cost no atomic
-          v = __hip_atomic_load(&a.head[qx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (a.qbeg[qx] + v < a.qbeg[qx + 1]) v = atomicAdd(&a.head[qx], a.grain);
+          int32_t* hp = a.head + qx * kLineInts;
+          v = __hip_atomic_load(hp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (a.qbeg[qx] + v < a.qbeg[qx + 1]) v = atomicAdd(hp, a.grain);
         }
         v = __shfl(v, 0, 64);
         const int64_t b = a.qbeg[qx] + v;
@@ -238,18 +341,19 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
     const int64_t slot = it * G + g;
     const bool in = slot < a.n_active;
     const int64_t q = in ? (a.active ? (int64_t)a.active[slot] : slot) : 0;
+    const uint32_t q32 = (uint32_t)q;
 
-    // ---- query point, covered radius ---------------------------------------
+    // ---- query point, covered radius, face distances ------------------------
     double qx[DIM];
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) qx[j] = Xs[(int64_t)j * N + q];
+    for (int j = 0; j < DIM; ++j) qx[j] = Xd[j][q];
     const uint32_t cell = a.cell_of[q];
     const uint32_t* rg = a.ranges + (size_t)cell * R * 2;
+    const uint8_t* rs = a.rslot + (size_t)cell * R;
     const uint32_t Cq = in ? a.cand[cell] : 0u;
     // heavy queries are handled by k_search_heavy
     const bool valid = in && (a.heavy_min == 0 || Cq < a.heavy_min);
     const int nr = valid ? (int)a.nrng[cell] : 0;
-    const uint32_t C = valid ? Cq : 0u;
     double mfrac = 0.5;
     bool full = true;
 #pragma unroll
@@ -273,32 +377,33 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
       thr = r * r;
       ref = thr;
     }
-    const int64_t top = (int64_t)((uint64_t)__double_as_longlong(ref) >> kBinShift);
+    const int top = (int)((uint64_t)__double_as_longlong(ref) >> kBinShift);
+    int nr_w = nr;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) nr_w = max(nr_w, __shfl_xor(nr_w, o, 64));
 
-    // ---- count pass ----------------------------------------------------------
+    // ---- count pass over the segments that can hold a point within thr -----
+    uint32_t C = build_list<DIM, T>(rg, rs, nr, nr_w, !full, thr, qx, a, l, seg_st, seg_ve);
     for (int b = l; b < NB; b += T) hist[b * G + g] = 0;
     wave_fence();
     {
-      Cands cs;
-      cs.init(rg, nr);
+      LWalk cs;
+      cs.init(seg_st, seg_ve, C);
       for (uint32_t v = l; v < C; v += T * kUnroll) {
         // positions first, then all coordinate loads in flight together
         uint32_t p[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t vv = v + (uint32_t)(u * T);
-          p[u] = vv < C ? cs.pos(vv) : 0xFFFFFFFFu;
+          p[u] = vv < C ? cs.pos(vv) : q32;
         }
         double d2[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-          d2[u] = sq_dist<DIM>(Xs, N, p[u] != 0xFFFFFFFFu ? p[u] : 0u, qx);
+        for (int u = 0; u < kUnroll; ++u) d2[u] = sq_dist<DIM>(Xd, p[u], qx);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          if (p[u] != 0xFFFFFFFFu && (int64_t)p[u] != q) {
-            const int b = bin_of(d2[u], thr, top);
-            if (b < NB) atomicAdd(&hist[b * G + g], 1u);
-          }
+          const int b = bin_of(d2[u], thr, top);
+          if (p[u] != q32 && b < NB) atomicAdd(&hist[b * G + g], 1u);
         }
       }
     }
@@ -350,6 +455,11 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
       }
     }
 
+    // ---- list for the remaining passes: only bins up to the selected one ----
+    const double lim2 = ok ? bins_limit(bsel, thr, top) : 0.0;
+    C = build_list<DIM, T>(rg, rs, ok ? nr : 0, nr_w, true, lim2, qx, a, l, seg_st, seg_ve);
+    wave_fence();
+
     // ---- exact refinement when the selected bin overflows the buffer -------
     // Keys are (d2 bits, id) as 96-bit integers; [A, B] is an inclusive key
     // interval with c_lo keys below A and c_hi keys up to B, c_lo < K <= c_hi.
@@ -363,13 +473,13 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
       // exact value bounds of the selected bin
       double dmin = INFINITY, dmax = -INFINITY;
       {
-        Cands cs;
-        cs.init(rg, nr);
+        LWalk cs;
+        cs.init(seg_st, seg_ve, C);
         const uint32_t Cr = refine ? C : 0u;
         for (uint32_t v = l; v < Cr; v += T) {
           const uint32_t p = cs.pos(v);
-          if ((int64_t)p != q) {
-            const double d2 = sq_dist<DIM>(Xs, N, p, qx);
+          if (p != q32) {
+            const double d2 = sq_dist<DIM>(Xd, p, qx);
             if (bin_of(d2, thr, top) == bsel) {
               dmin = fmin(dmin, d2);
               dmax = fmax(dmax, d2);
@@ -393,13 +503,13 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
         wave_fence();
         {
           const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
-          Cands cs;
-          cs.init(rg, nr);
+          LWalk cs;
+          cs.init(seg_st, seg_ve, C);
           const uint32_t Cr = refine ? C : 0u;
           for (uint32_t v = l; v < Cr; v += T) {
             const uint32_t p = cs.pos(v);
-            if ((int64_t)p != q) {
-              const double d2 = sq_dist<DIM>(Xs, N, p, qx);
+            if (p != q32) {
+              const double d2 = sq_dist<DIM>(Xd, p, qx);
               const uint64_t kh = (uint64_t)__double_as_longlong(d2);
               if (kh >= ahi && kh <= bhi) {
                 const unsigned __int128 k = ((unsigned __int128)kh << 32) | (uint32_t)perm[p];
@@ -436,24 +546,21 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
     // ---- collect pass: survivors bucketed by bin (counting sort) --------------
     wave_fence();
     {
-      Cands cs;
-      cs.init(rg, nr);
-      const uint32_t Cc = ok ? C : 0u;
-      for (uint32_t v = l; v < Cc; v += T * kUnroll) {
+      LWalk cs;
+      cs.init(seg_st, seg_ve, C);
+      for (uint32_t v = l; v < C; v += T * kUnroll) {
         uint32_t pp[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t vv = v + (uint32_t)(u * T);
-          pp[u] = vv < Cc ? cs.pos(vv) : 0xFFFFFFFFu;
+          pp[u] = vv < C ? cs.pos(vv) : q32;
         }
         double dd[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-          dd[u] = sq_dist<DIM>(Xs, N, pp[u] != 0xFFFFFFFFu ? pp[u] : 0u, qx);
+        for (int u = 0; u < kUnroll; ++u) dd[u] = sq_dist<DIM>(Xd, pp[u], qx);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t p = pp[u];
-          if (p == 0xFFFFFFFFu || (int64_t)p == q) continue;
           const double d2 = dd[u];
           const int b = bin_of(d2, thr, top);
           bool acc;
@@ -461,7 +568,7 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
             acc = d2 < th_d || (d2 == th_d && (th_id == 0xFFFFFFFFu || (uint32_t)perm[p] <= th_id));
           else
             acc = b <= bsel;
-          if (acc) {
+          if (p != q32 && acc) {
             const uint32_t s = atomicAdd(&hist[b * G + g], 1u);
             if ((int)s < cap) {
               bd[s * G + g] = d2;
@@ -506,42 +613,48 @@ __global__ void __launch_bounds__(256) k_search(const SearchArgs a) {
   if (nfail > 0) flush_failures(a, fbuf, nfail, lane);
 }
 
-
 // The same search for one query per workgroup of kHeavyThreads lanes: the
 // queries of a level whose candidate count is far above the level's mean
 // (next to dense regions after the cell side has grown), which would keep a
 // single wavefront busy long after the rest of the level is done.  Same bins,
-// selection, refinement and ranking as k_search, with workgroup barriers in
-// place of the group's lane exchanges.
+// lists, selection, refinement and ranking as k_search, with workgroup
+// barriers in place of the group's lane exchanges (the lists are built by the
+// first wavefront).
 template <int DIM>
 __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs a) {
   constexpr int R = Pow3<DIM - 1>::v;
   constexpr int NT = kHeavyThreads;
+  constexpr int kUnroll = Unroll<DIM>::v;
   extern __shared__ double smem[];
   __shared__ uint32_t hist[NB];
   __shared__ uint32_t hist2[NB2];
+  __shared__ uint32_t seg_st[R], seg_ve[R];
   __shared__ int s_bsel, s_clo, s_chi, s_refine;
+  __shared__ uint32_t s_C;
   __shared__ unsigned long long s_dmin, s_dmax;
   __shared__ unsigned __int128 s_A, s_B;
   const int tid = threadIdx.x;
   const int cap = a.cap;
   const int K = a.K;
   const int64_t N = a.N;
-  const double* __restrict__ Xs = a.Xs;
   const int32_t* __restrict__ perm = a.perm;
+  const double* __restrict__ Xd[DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) Xd[j] = a.Xs + (int64_t)j * N;
   double* bd = smem;
   int32_t* bi = reinterpret_cast<int32_t*>(smem + cap);
   const int nh = *a.n_heavy;
 
   for (int hq = blockIdx.x; hq < nh; hq += gridDim.x) {
     const int64_t q = a.heavy[hq];
+    const uint32_t q32 = (uint32_t)q;
     double qx[DIM];
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) qx[j] = Xs[(int64_t)j * N + q];
+    for (int j = 0; j < DIM; ++j) qx[j] = Xd[j][q];
     const uint32_t cell = a.cell_of[q];
     const uint32_t* rg = a.ranges + (size_t)cell * R * 2;
+    const uint8_t* rs = a.rslot + (size_t)cell * R;
     const int nr = (int)a.nrng[cell];
-    const uint32_t C = a.cand[cell];
     double mfrac = 0.5;
     bool full = true;
 #pragma unroll
@@ -563,31 +676,34 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
       thr = r * r;
       ref = thr;
     }
-    const int64_t top = (int64_t)((uint64_t)__double_as_longlong(ref) >> kBinShift);
+    const int top = (int)((uint64_t)__double_as_longlong(ref) >> kBinShift);
 
     // ---- count pass
-    for (int b = tid; b < NB; b += NT) hist[b] = 0;
+    if (tid < 64) {
+      const uint32_t C0 =
+          build_list<DIM, 64>(rg, rs, nr, nr, !full, thr, qx, a, tid, seg_st, seg_ve);
+      if (tid == 0) s_C = C0;
+      hist[tid] = 0;  // NB == 64
+    }
     __syncthreads();
+    uint32_t C = s_C;
     {
-      Cands cs;
-      cs.init(rg, nr);
+      LWalk cs;
+      cs.init(seg_st, seg_ve, C);
       for (uint32_t v = tid; v < C; v += NT * kUnroll) {
         uint32_t p[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t vv = v + (uint32_t)(u * NT);
-          p[u] = vv < C ? cs.pos(vv) : 0xFFFFFFFFu;
+          p[u] = vv < C ? cs.pos(vv) : q32;
         }
         double d2[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-          d2[u] = sq_dist<DIM>(Xs, N, p[u] != 0xFFFFFFFFu ? p[u] : 0u, qx);
+        for (int u = 0; u < kUnroll; ++u) d2[u] = sq_dist<DIM>(Xd, p[u], qx);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          if (p[u] != 0xFFFFFFFFu && (int64_t)p[u] != q) {
-            const int b = bin_of(d2[u], thr, top);
-            if (b < NB) atomicAdd(&hist[b], 1u);
-          }
+          const int b = bin_of(d2[u], thr, top);
+          if (p[u] != q32 && b < NB) atomicAdd(&hist[b], 1u);
         }
       }
     }
@@ -617,17 +733,26 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
     const int bsel = s_bsel;
     if (bsel == NB) continue;  // failed: re-queued for a larger cell side
 
+    // ---- list of the remaining passes
+    if (tid < 64) {
+      const uint32_t C1 = build_list<DIM, 64>(rg, rs, nr, nr, true, bins_limit(bsel, thr, top),
+                                              qx, a, tid, seg_st, seg_ve);
+      if (tid == 0) s_C = C1;
+    }
+    __syncthreads();
+    C = s_C;
+
     // ---- exact refinement when the selected bin overflows the buffer
     const bool refined = s_chi > cap;
     if (refined) {
       {
         unsigned long long mn = ~0ull, mx = 0ull;
-        Cands cs;
-        cs.init(rg, nr);
+        LWalk cs;
+        cs.init(seg_st, seg_ve, C);
         for (uint32_t v = tid; v < C; v += NT) {
           const uint32_t p = cs.pos(v);
-          if ((int64_t)p != q) {
-            const double d2 = sq_dist<DIM>(Xs, N, p, qx);
+          if (p != q32) {
+            const double d2 = sq_dist<DIM>(Xd, p, qx);
             if (bin_of(d2, thr, top) == bsel) {
               const unsigned long long kb = (unsigned long long)__double_as_longlong(d2);
               mn = min(mn, kb);
@@ -655,12 +780,12 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         __syncthreads();
         {
           const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
-          Cands cs;
-          cs.init(rg, nr);
+          LWalk cs;
+          cs.init(seg_st, seg_ve, C);
           for (uint32_t v = tid; v < C; v += NT) {
             const uint32_t p = cs.pos(v);
-            if ((int64_t)p != q) {
-              const double d2 = sq_dist<DIM>(Xs, N, p, qx);
+            if (p != q32) {
+              const double d2 = sq_dist<DIM>(Xd, p, qx);
               const uint64_t kh = (uint64_t)__double_as_longlong(d2);
               if (kh >= ahi && kh <= bhi) {
                 const unsigned __int128 k = ((unsigned __int128)kh << 32) | (uint32_t)perm[p];
@@ -697,23 +822,21 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
 
     // ---- collect pass
     {
-      Cands cs;
-      cs.init(rg, nr);
+      LWalk cs;
+      cs.init(seg_st, seg_ve, C);
       for (uint32_t v = tid; v < C; v += NT * kUnroll) {
         uint32_t pp[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t vv = v + (uint32_t)(u * NT);
-          pp[u] = vv < C ? cs.pos(vv) : 0xFFFFFFFFu;
+          pp[u] = vv < C ? cs.pos(vv) : q32;
         }
         double dd[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-          dd[u] = sq_dist<DIM>(Xs, N, pp[u] != 0xFFFFFFFFu ? pp[u] : 0u, qx);
+        for (int u = 0; u < kUnroll; ++u) dd[u] = sq_dist<DIM>(Xd, pp[u], qx);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t p = pp[u];
-          if (p == 0xFFFFFFFFu || (int64_t)p == q) continue;
           const double d2 = dd[u];
           const int b = bin_of(d2, thr, top);
           bool acc;
@@ -721,7 +844,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
             acc = d2 < th_d || (d2 == th_d && (th_id == 0xFFFFFFFFu || (uint32_t)perm[p] <= th_id));
           else
             acc = b <= bsel;
-          if (acc) {
+          if (p != q32 && acc) {
             const uint32_t sidx = atomicAdd(&hist[b], 1u);
             if ((int)sidx < cap) {
               bd[sidx] = d2;
@@ -795,14 +918,16 @@ void launch_dim(const SearchArgs& a, int T, int blocks, int threads, size_t lds,
 
 }  // namespace
 
-size_t search_lds_per_wave(int T, int cap) {
+size_t search_lds_per_wave(int dims, int T, int cap) {
   const int G = 64 / T;
+  size_t R = 1;
+  for (int j = 0; j < dims - 1; ++j) R *= 3;
   return (size_t)cap * G * (sizeof(double) + sizeof(int32_t)) + (size_t)NB * G * sizeof(uint32_t) +
-         (size_t)kFailBuf * sizeof(int32_t);
+         (size_t)kFailBuf * sizeof(int32_t) + 2 * R * G * sizeof(uint32_t);
 }
 
-int search_waves_per_block(int T, int cap) {
-  size_t per = search_lds_per_wave(T, cap);
+int search_waves_per_block(int dims, int T, int cap) {
+  size_t per = search_lds_per_wave(dims, T, cap);
   int w = (int)(65536 / per);
   if (w > 4) w = 4;
   if (w < 1) w = 1;
@@ -810,8 +935,19 @@ int search_waves_per_block(int T, int cap) {
 }
 
 int search_blocks_per_cu(int dims, int T, int cap) {
-  const int waves = search_waves_per_block(T, cap);
-  const size_t lds = search_lds_per_wave(T, cap) * waves;
+  // the occupancy query costs host time on every call; levels ask it often
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, int, int>, int> cache;
+  int dev = 0;
+  KNN_HIP(hipGetDevice(&dev));
+  const auto key = std::make_tuple(dev, dims, T, cap);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  const int waves = search_waves_per_block(dims, T, cap);
+  const size_t lds = search_lds_per_wave(dims, T, cap) * waves;
   int n = 1;
   switch (dims) {
     case 2: n = occupancy_dim<2>(T, waves * 64, lds); break;
@@ -821,7 +957,10 @@ int search_blocks_per_cu(int dims, int T, int cap) {
     case 6: n = occupancy_dim<6>(T, waves * 64, lds); break;
     default: break;
   }
-  return n > 0 ? n : 1;
+  n = n > 0 ? n : 1;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = n;
+  return n;
 }
 
 void launch_search_heavy(const SearchArgs& a, int dims, int blocks, hipStream_t s) {
@@ -841,9 +980,10 @@ void launch_search_heavy(const SearchArgs& a, int dims, int blocks, hipStream_t 
 
 void launch_search(const SearchArgs& a, int dims, int T, int grid_blocks, hipStream_t s) {
   KNN_CHECK(a.cap >= NB2 / 2 + 1, KNN_EINTERNAL, "per-query buffer too small");
-  const int waves = search_waves_per_block(T, a.cap);
-  const size_t lds = search_lds_per_wave(T, a.cap) * waves;
-  KNN_CHECK(lds <= 65536, KNN_EINVAL, "K too large for the per-query buffers");
+  const int waves = search_waves_per_block(dims, T, a.cap);
+  const size_t lds = search_lds_per_wave(dims, T, a.cap) * waves;
+  KNN_CHECK(lds <= 65536, KNN_EINVAL,
+            "per-query buffers exceed the LDS (raise lanes_per_query or lower K)");
   const int threads = waves * 64;
   switch (dims) {
     case 2: launch_dim<2>(a, T, grid_blocks, threads, lds, s); break;
