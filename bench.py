@@ -307,6 +307,7 @@ def main():
                 r = idx.autotune(K, stream=stream)
                 tuned.append(dict(dataset=name, K=K, w_factor=round(r["w_factor"], 3),
                                   growth=round(r["growth"], 4),
+                                  linear_levels=int(r["linear_levels"]), trials=int(r["trials"]),
                                   ms_default=round(r["ms_default"], 3),
                                   ms_tuned=round(r["ms_best"], 3)))
             idx.close()

@@ -207,11 +207,13 @@ typedef struct knn_autotune_result {
   double ms_best;     /* best join time measured (ms) */
   double ms_default;  /* join time of the untuned default (ms) */
   int32_t trials;     /* settings measured */
+  int32_t linear_levels; /* chosen linear growths before the geometric ones
+                            (0 or 1; -1 in the cache means none) */
 } knn_autotune_result;
 /* Runs on `stream` (device scratch allocated internally); blocks. */
 int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* out);
 /* Save / load the cache as text ("dims kbucket nbucket w_factor growth
- * lanes" per line); path NULL = $KNN_AUTOTUNE_CACHE. */
+ * lanes linear" per line); path NULL = $KNN_AUTOTUNE_CACHE. */
 int knn_autotune_save(const char* path);
 int knn_autotune_load(const char* path);
 

@@ -35,10 +35,10 @@ void load_file_locked(const char* p) {
   if (!p || !*p) return;
   FILE* f = std::fopen(p, "r");
   if (!f) return;
-  int d, kb, nb, lanes;
+  int d, kb, nb, lanes, lin;
   double wf, gr;
-  while (std::fscanf(f, "%d %d %d %lf %lf %d", &d, &kb, &nb, &wf, &gr, &lanes) == 6)
-    g_cache[Class(d, kb, nb)] = TuneEntry{wf, gr, lanes};
+  while (std::fscanf(f, "%d %d %d %lf %lf %d %d", &d, &kb, &nb, &wf, &gr, &lanes, &lin) == 7)
+    g_cache[Class(d, kb, nb)] = TuneEntry{wf, gr, lanes, lin};
   std::fclose(f);
 }
 
@@ -66,6 +66,8 @@ double autotune_w_factor(int dims, int K, int64_t N) {
 
 double autotune_growth(int dims, int K, int64_t N) { return autotune_get(dims, K, N).growth; }
 
+int autotune_linear(int dims, int K, int64_t N) { return autotune_get(dims, K, N).linear; }
+
 void autotune_store(int dims, int K, int64_t N, const TuneEntry& e) {
   std::lock_guard<std::mutex> lk(g_mu);
   ensure_loaded_locked();
@@ -91,8 +93,9 @@ int autotune_save(const char* path) {
   FILE* f = std::fopen(p, "w");
   if (!f) return -1;
   for (auto& kv : g_cache)
-    std::fprintf(f, "%d %d %d %.17g %.17g %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
-                 std::get<2>(kv.first), kv.second.w_factor, kv.second.growth, kv.second.lanes);
+    std::fprintf(f, "%d %d %d %.17g %.17g %d %d\n", std::get<0>(kv.first),
+                 std::get<1>(kv.first), std::get<2>(kv.first), kv.second.w_factor,
+                 kv.second.growth, kv.second.lanes, kv.second.linear);
   std::fclose(f);
   return 0;
 }

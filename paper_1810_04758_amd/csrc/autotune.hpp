@@ -13,6 +13,7 @@ struct TuneEntry {
   double w_factor;  // 0 = no measurement
   double growth;    // 0 = no measurement
   int lanes;        // 0 = chosen per level from the candidate counts
+  int linear = 0;   // linear growths: 0 = not measured (default), 1, or -1 (none)
 };
 
 // Cached entry for the class of (dims, K, N), or all zeros.
@@ -22,6 +23,8 @@ TuneEntry autotune_get(int dims, int K, int64_t N);
 int autotune_lanes(int dims, int K, int64_t N);
 double autotune_w_factor(int dims, int K, int64_t N);
 double autotune_growth(int dims, int K, int64_t N);
+// Linear growths before the geometric ones (0 if none cached: the default).
+int autotune_linear(int dims, int K, int64_t N);
 // Records a measured best setting for the class of (dims, K, N).
 void autotune_store(int dims, int K, int64_t N, const TuneEntry& e);
 // Loads / saves the cache file (path from KNN_AUTOTUNE_CACHE when path is NULL).

@@ -303,7 +303,11 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   // `linear` re-indexes, then geometric growth whose default multiplies the
   // scanned volume by 16 per level (the non-linear expansion Sec. 5.3.8
   // proposes for the GPU-Only tail)
-  const int linear = o.linear_levels > 0 ? o.linear_levels : (o.linear_levels < 0 ? 0 : 1);
+  int linear = o.linear_levels > 0 ? o.linear_levels : (o.linear_levels < 0 ? 0 : 1);
+  if (o.linear_levels == 0) {
+    const int tl = autotune_linear(idx.n, K, idx.N);
+    if (tl != 0) linear = tl > 0 ? tl : 0;
+  }
   const double tuned_growth = o.growth > 1.0 ? 0.0 : autotune_growth(idx.n, K, idx.N);
   const double growth = o.growth > 1.0 ? o.growth
                         : tuned_growth > 1.0 ? tuned_growth
@@ -964,12 +968,13 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
     const size_t NK = (size_t)idx->N * K;
     c.out_ids.reserve(NK);
     c.out_d.reserve(NK);
-    auto time_join = [&](double wf, double gr) {
+    auto time_join = [&](double wf, double gr, int lin) {
       double best = 1e300;
       for (int rep = 0; rep < 2; ++rep) {
         knn_join_opts o{};
         o.w_factor = wf;
         o.growth = gr;
+        o.linear_levels = lin;
         KNN_HIP(hipStreamSynchronize(s));
         auto t0 = std::chrono::steady_clock::now();
         self_join(*idx, c, K, c.out_ids.p, c.out_d.p, o, s);
@@ -979,26 +984,41 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
       }
       return best;
     };
+    // Staged search: the level-0 cell side first (default growth, the
+    // paper's linear first step), then growth x linear step for the best
+    // side, then the side again around the best at that growth.
     const double n = (double)idx->n;
-    const double wfs[] = {0.7, 1.0, 1.4, 2.0};
-    const double grs[] = {std::pow(4.0, 1.0 / n), std::pow(16.0, 1.0 / n), std::pow(64.0, 1.0 / n)};
+    const double g16 = std::pow(16.0, 1.0 / n);
     std::memset(out, 0, sizeof(*out));
-    out->ms_default = time_join(1.0, std::pow(16.0, 1.0 / n));
+    out->ms_default = time_join(1.0, g16, 1);
     out->ms_best = out->ms_default;
     out->w_factor = 1.0;
-    out->growth = std::pow(16.0, 1.0 / n);
+    out->growth = g16;
+    out->linear_levels = 1;
     out->trials = 1;
-    for (double wf : wfs)
-      for (double gr : grs) {
-        const double ms = time_join(wf, gr);
-        ++out->trials;
-        if (ms < out->ms_best) {
-          out->ms_best = ms;
-          out->w_factor = wf;
-          out->growth = gr;
-        }
+    auto consider = [&](double wf, double gr, int lin) {
+      const double ms = time_join(wf, gr, lin);
+      ++out->trials;
+      if (ms < out->ms_best) {
+        out->ms_best = ms;
+        out->w_factor = wf;
+        out->growth = gr;
+        out->linear_levels = lin;
       }
-    autotune_store(idx->n, K, idx->N, TuneEntry{out->w_factor, out->growth, 0});
+    };
+    for (double wf : {0.25, 0.5, 0.7, 1.4, 2.0}) consider(wf, g16, 1);
+    const double wf1 = out->w_factor;
+    for (double gb : {4.0, 16.0, 64.0})
+      for (int lin : {1, -1}) {
+        const double gr = std::pow(gb, 1.0 / n);
+        if (gb == 16.0 && lin == 1) continue;  // measured in the first stage
+        consider(wf1, gr, lin);
+      }
+    const double gr2 = out->growth;
+    const int lin2 = out->linear_levels;
+    for (double f : {0.8, 1.25}) consider(wf1 * f, gr2, lin2);
+    autotune_store(idx->n, K, idx->N,
+                   TuneEntry{out->w_factor, out->growth, 0, out->linear_levels > 0 ? 1 : -1});
   });
 }
 

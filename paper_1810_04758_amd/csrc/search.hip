@@ -6,12 +6,14 @@
 // For each query:
 //   1. Candidates are the points of the 3^n adjacent cells, stored as the
 //      non-empty ones of 3^(n-1) contiguous row segments of the cell-sorted
-//      SoA coordinates.  The T lanes walk them as one flattened array, so lane
+//      SoA coordinates.  Each pass copies the segments it needs into an LDS
+//      list (segments provably beyond the pass's distance limit are left
+//      out), and the T lanes walk the list as one flattened array, so lane
 //      utilisation does not depend on the segment lengths.
 //   2. Count pass: every candidate's squared distance (summed left to right,
 //      every operation rounded) goes through a monotone bin function into a
-//      per-query LDS histogram of NB log-spaced bins (8 per octave of d^2,
-//      read off the exponent and three mantissa bits) ending at r^2, where r
+//      per-query LDS histogram of NB log-spaced bins (read off the exponent
+//      and the top mantissa bits of d^2) ending at r^2, where r
 //      is the radius that the scanned cells provably cover.  Fewer than K
 //      candidates within r^2 means the K nearest cannot be proven from these
 //      cells: the query fails and is re-queued for a larger cell side (Alg. 1,
@@ -47,8 +49,19 @@ namespace knn {
 
 namespace {
 
-constexpr int NB = 64;         // count-pass bins: 8 octaves of d^2
-constexpr int kBinShift = 49;  // exponent + 3 mantissa bits: 8 bins per octave
+// Count-pass bins: NB log-spaced bins of d^2 below the covered radius.  The
+// range has to reach the K-th distance of dense cells, which lies far below
+// the covered radius; the resolution has to keep the selected bin within the
+// per-query buffer (an overflow is resolved exactly by refinement rounds, but
+// costs passes).  Around the K-th neighbour a bin's population grows like
+// (bin ratio)^(n/2), while a density contrast c moves the K-th distance by
+// c^(1/n): so 2-3 dimensions get 4 bins per octave over 16 octaves
+// (exponent + 2 mantissa bits), 4-6 dimensions 8 per octave over 8.
+constexpr int NB = 64;
+template <int DIM>
+struct BinShift {
+  static constexpr int v = DIM <= 3 ? 50 : 49;
+};
 constexpr int NB2 = 32;        // bins of one exact-bisection round
 constexpr int kLog2NB2 = 5;
 // candidates per lane in flight in the count/collect walks (fewer in 5-6
@@ -84,7 +97,9 @@ __device__ __forceinline__ double sq_dist(const double* __restrict__ const (&Xd)
 // top = (bit pattern of the reference top) >> kBinShift; the bit pattern of a
 // non-negative double is monotone in its value, so the bin is monotone in d2.
 // Only the high word is needed (kBinShift >= 32).
+template <int DIM>
 __device__ __forceinline__ int bin_of(double d2, double thr, int top) {
+  constexpr int kBinShift = BinShift<DIM>::v;
   const int k = (int)((uint32_t)__double2hiint(d2) >> (kBinShift - 32)) - top + (NB - 1);
   const int b = min(max(k, 0), NB - 1);
   return d2 > thr ? NB : b;
@@ -92,7 +107,9 @@ __device__ __forceinline__ int bin_of(double d2, double thr, int top) {
 
 // Upper limit of the squared distances in bins 0..b (for pruning the passes
 // that only need those bins): below the next bin edge, and never above thr.
+template <int DIM>
 __device__ __forceinline__ double bins_limit(int b, double thr, int top) {
+  constexpr int kBinShift = BinShift<DIM>::v;
   const int e = top - (NB - 1) + b + 1;  // bit pattern >> kBinShift of the next edge
   if (b >= NB - 1 || e <= 0 || e >= (0x7FF0 >> (kBinShift - 48))) return thr;
   const double edge = __longlong_as_double((long long)((uint64_t)e << kBinShift));
@@ -377,7 +394,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       thr = r * r;
       ref = thr;
     }
-    const int top = (int)((uint64_t)__double_as_longlong(ref) >> kBinShift);
+    const int top = (int)((uint64_t)__double_as_longlong(ref) >> BinShift<DIM>::v);
     int nr_w = nr;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) nr_w = max(nr_w, __shfl_xor(nr_w, o, 64));
@@ -402,7 +419,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         for (int u = 0; u < kUnroll; ++u) d2[u] = sq_dist<DIM>(Xd, p[u], qx);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const int b = bin_of(d2[u], thr, top);
+          const int b = bin_of<DIM>(d2[u], thr, top);
           if (p[u] != q32 && b < NB) atomicAdd(&hist[b * G + g], 1u);
         }
       }
@@ -456,7 +473,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     }
 
     // ---- list for the remaining passes: only bins up to the selected one ----
-    const double lim2 = ok ? bins_limit(bsel, thr, top) : 0.0;
+    const double lim2 = ok ? bins_limit<DIM>(bsel, thr, top) : 0.0;
     C = build_list<DIM, T>(rg, rs, ok ? nr : 0, nr_w, true, lim2, qx, a, l, seg_st, seg_ve);
     wave_fence();
 
@@ -480,7 +497,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
           const uint32_t p = cs.pos(v);
           if (p != q32) {
             const double d2 = sq_dist<DIM>(Xd, p, qx);
-            if (bin_of(d2, thr, top) == bsel) {
+            if (bin_of<DIM>(d2, thr, top) == bsel) {
               dmin = fmin(dmin, d2);
               dmax = fmax(dmax, d2);
             }
@@ -562,7 +579,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t p = pp[u];
           const double d2 = dd[u];
-          const int b = bin_of(d2, thr, top);
+          const int b = bin_of<DIM>(d2, thr, top);
           bool acc;
           if (refined)
             acc = d2 < th_d || (d2 == th_d && (th_id == 0xFFFFFFFFu || (uint32_t)perm[p] <= th_id));
@@ -591,7 +608,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       if (ai < c) {
         const double da = bd[ai * G + g];
         const int32_t ia = bi[ai * G + g];
-        const int b = bin_of(da, thr, top);
+        const int b = bin_of<DIM>(da, thr, top);
         const int start = b > 0 ? (int)hist[(b - 1) * G + g] : 0;
         if (start < K) {
           const int end = min((int)hist[b * G + g], cap);
@@ -676,7 +693,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
       thr = r * r;
       ref = thr;
     }
-    const int top = (int)((uint64_t)__double_as_longlong(ref) >> kBinShift);
+    const int top = (int)((uint64_t)__double_as_longlong(ref) >> BinShift<DIM>::v);
 
     // ---- count pass
     if (tid < 64) {
@@ -702,7 +719,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         for (int u = 0; u < kUnroll; ++u) d2[u] = sq_dist<DIM>(Xd, p[u], qx);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const int b = bin_of(d2[u], thr, top);
+          const int b = bin_of<DIM>(d2[u], thr, top);
           if (p[u] != q32 && b < NB) atomicAdd(&hist[b], 1u);
         }
       }
@@ -735,7 +752,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
 
     // ---- list of the remaining passes
     if (tid < 64) {
-      const uint32_t C1 = build_list<DIM, 64>(rg, rs, nr, nr, true, bins_limit(bsel, thr, top),
+      const uint32_t C1 = build_list<DIM, 64>(rg, rs, nr, nr, true, bins_limit<DIM>(bsel, thr, top),
                                               qx, a, tid, seg_st, seg_ve);
       if (tid == 0) s_C = C1;
     }
@@ -753,7 +770,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
           const uint32_t p = cs.pos(v);
           if (p != q32) {
             const double d2 = sq_dist<DIM>(Xd, p, qx);
-            if (bin_of(d2, thr, top) == bsel) {
+            if (bin_of<DIM>(d2, thr, top) == bsel) {
               const unsigned long long kb = (unsigned long long)__double_as_longlong(d2);
               mn = min(mn, kb);
               mx = max(mx, kb);
@@ -838,7 +855,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t p = pp[u];
           const double d2 = dd[u];
-          const int b = bin_of(d2, thr, top);
+          const int b = bin_of<DIM>(d2, thr, top);
           bool acc;
           if (refined)
             acc = d2 < th_d || (d2 == th_d && (th_id == 0xFFFFFFFFu || (uint32_t)perm[p] <= th_id));
@@ -862,7 +879,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
     for (int ai = tid; ai < c; ai += NT) {
       const double da = bd[ai];
       const int32_t ia = bi[ai];
-      const int b = bin_of(da, thr, top);
+      const int b = bin_of<DIM>(da, thr, top);
       const int start = b > 0 ? (int)hist[b - 1] : 0;
       if (start < K) {
         const int end = min((int)hist[b], cap);
