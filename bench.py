@@ -37,21 +37,25 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
 def alg_bytes(stats, n, K):
-    """Algorithmic HBM bytes of the search kernel over one join: per attempted
-    query its own coordinates (8n) and cell/row metadata (8), plus the output
-    row (12K: int32 id + fp64 distance per neighbour) when it succeeds or its
-    id (4) when it fails."""
+    """Algorithmic HBM bytes of the search kernel (k_search) over one join:
+    per query it searched, its own coordinates (8n) and cell/row metadata (8),
+    plus the output row (12K: int32 id + fp64 distance per neighbour) when it
+    succeeds or its id (4) when it fails.  Queries handed to the heavy-query
+    kernel are not k_search's."""
     total = 0
-    for a, f in zip(stats["attempted"], stats["failed"]):
+    for L, (a, f) in enumerate(zip(stats["attempted"], stats["failed"])):
+        h, hf = stats["heavy_queries"][L], stats["heavy_failed"][L]
+        a, f = a - h, f - hf
         total += a * (8 * n + 8) + (a - f) * 12 * K + f * 4
     return total
 
 
 def alg_ops(stats, n):
-    """Algorithmic FP64 operations of the search kernel over one join: per
-    scanned candidate n subtractions, n multiplications, n-1 additions and one
-    comparison (3n), for the candidates of every attempted query."""
-    return sum(a * c * 3 * n for a, c in zip(stats["attempted"], stats["cand_per_query"]))
+    """Algorithmic FP64 operations of k_search over one join: per candidate of
+    the 3^n cells of every query it searched, n subtractions, n
+    multiplications, n-1 additions and one comparison (3n)."""
+    return sum((a * c - hc) * 3 * n for a, c, hc in
+               zip(stats["attempted"], stats["cand_per_query"], stats["heavy_cand"]))
 
 
 def kernel_source_hash():
@@ -166,11 +170,12 @@ def serving_leg(api, seconds, rate=200.0, budget_gib=96, inflight=4):
 
 
 def schedule_comparison(api, dev, plan, outs, stream, reps=3):
-    """The persistent, density-ordered schedule against the plain one: one
-    launch per level over every unsolved query in cell order, one work item
-    per wavefront, no work queue (same cell sides and lanes per query, so the
+    """The persistent schedule (device work queues per XCD, density-ordered
+    items, heavy queries on workgroups of their own) against the plain one:
+    one launch per level over every unsolved query in cell order, one work
+    item per wavefront, no queue (same cell sides and lanes per query, so the
     same candidates are scanned).  Untimed by the step clock; best of `reps`
-    joins each, search-kernel time from the join's HIP events."""
+    joins each; search time (both search kernels) from the join's HIP events."""
     res = []
     tot = {0: [0.0, 0.0], 1: [0.0, 0.0]}
     for name, Ks in plan:
@@ -180,10 +185,12 @@ def schedule_comparison(api, dev, plan, outs, stream, reps=3):
             row = dict(dataset=name, K=K)
             for sched in (0, 1):
                 best_s = best_t = float("inf")
+                # plain: no queue, no density order, no heavy-query workgroups
+                extra = dict(schedule=1, heavy_min=-1) if sched else {}
                 for _ in range(reps):
                     _, _, st = idx.self_join(K, ids=ids, dists=dists, stream=stream,
-                                             with_stats=True, schedule=sched)
-                    best_s = min(best_s, sum(st["ms_search"]))
+                                             with_stats=True, **extra)
+                    best_s = min(best_s, sum(st["ms_search"]) + sum(st["ms_heavy"]))
                     best_t = min(best_t, st["ms_total"])
                 key = "persistent" if sched == 0 else "plain"
                 row[f"ms_search_{key}"] = round(best_s, 3)
@@ -354,7 +361,10 @@ def main():
         bytes_total += alg_bytes(st, n, K)
         ops_total += alg_ops(st, n)
         c = per_case.setdefault((name, K), dict(dataset=name, K=K, ms_total=[], levels=[],
-                                                fail_fraction=[], ms_search=[], ms_build=[]))
+                                                fail_fraction=[], ms_search=[], ms_build=[],
+                                                ms_heavy=[], ms_tail=[]))
+        c["ms_heavy"].append(sum(st["ms_heavy"]))
+        c["ms_tail"].append(st["ms_tail"])
         c["ms_total"].append(st["ms_total"])
         c["levels"].append(st["levels"])
         c["fail_fraction"].append(st["total_failed"] / max(1, st["total_attempted"]))
@@ -384,6 +394,8 @@ def main():
                           levels=int(np.median(c["levels"])),
                           fail_fraction=round(float(np.median(c["fail_fraction"])), 4),
                           ms_search=round(float(np.median(c["ms_search"])), 3),
+                          ms_heavy=round(float(np.median(c["ms_heavy"])), 3),
+                          ms_tail=round(float(np.median(c["ms_tail"])), 3),
                           ms_level_builds=round(float(np.median(c["ms_build"])), 3)))
 
     out = {

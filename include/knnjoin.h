@@ -78,7 +78,7 @@ typedef struct knn_join_stats {
   int64_t failed[KNN_MAX_LEVELS];      /* of which failed (re-queued) */
   int64_t cells[KNN_MAX_LEVELS];       /* non-empty cells of each level */
   double ms_build[KNN_MAX_LEVELS];     /* index construction time per level */
-  double ms_search[KNN_MAX_LEVELS];    /* search kernel time per level */
+  double ms_search[KNN_MAX_LEVELS];    /* search kernel (k_search) time per level */
   double ms_total;            /* wall time of the whole join */
   int64_t total_attempted;    /* sum of attempted */
   int64_t total_failed;       /* sum of failed: fraction = failed/attempted */
@@ -89,6 +89,10 @@ typedef struct knn_join_stats {
   int64_t tail_queries;       /* queries finished by the brute-force tail */
   int32_t tail_rounds;        /* its exact-bisection rounds */
   double ms_tail;             /* its time */
+  double ms_heavy[KNN_MAX_LEVELS];        /* heavy-query kernel time per level */
+  int64_t heavy_queries[KNN_MAX_LEVELS];  /* queries it took (one workgroup each) */
+  int64_t heavy_failed[KNN_MAX_LEVELS];   /* of which failed */
+  double heavy_cand[KNN_MAX_LEVELS];      /* their candidates in total */
 } knn_join_stats;
 
 /* Options of the join calls.  Zero fields take the defaults in brackets. */

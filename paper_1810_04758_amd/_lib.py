@@ -42,7 +42,9 @@ class JoinStats(ctypes.Structure):
                 ("lanes_per_query", c_i32), ("lanes", c_i32 * KNN_MAX_LEVELS),
                 ("cand_per_query", c_f64 * KNN_MAX_LEVELS),
                 ("refine_rounds", c_i64 * KNN_MAX_LEVELS),
-                ("tail_queries", c_i64), ("tail_rounds", c_i32), ("ms_tail", c_f64)]
+                ("tail_queries", c_i64), ("tail_rounds", c_i32), ("ms_tail", c_f64),
+                ("ms_heavy", c_f64 * KNN_MAX_LEVELS), ("heavy_queries", c_i64 * KNN_MAX_LEVELS),
+                ("heavy_failed", c_i64 * KNN_MAX_LEVELS), ("heavy_cand", c_f64 * KNN_MAX_LEVELS)]
 
     def as_dict(self):
         L = self.levels
@@ -55,7 +57,10 @@ class JoinStats(ctypes.Structure):
                     cand_per_query=list(self.cand_per_query[:L]),
                     refine_rounds=list(self.refine_rounds[:L]),
                     tail_queries=self.tail_queries, tail_rounds=self.tail_rounds,
-                    ms_tail=self.ms_tail)
+                    ms_tail=self.ms_tail, ms_heavy=list(self.ms_heavy[:L]),
+                    heavy_queries=list(self.heavy_queries[:L]),
+                    heavy_failed=list(self.heavy_failed[:L]),
+                    heavy_cand=list(self.heavy_cand[:L]))
 
 
 class JoinOpts(ctypes.Structure):

@@ -533,7 +533,8 @@ __global__ void k_active_cand_sum(const int32_t* __restrict__ active, int64_t n_
 __global__ void k_heavy_list(const int32_t* __restrict__ active, int64_t n_active,
                              const uint32_t* __restrict__ cell_of,
                              const uint32_t* __restrict__ cand_count, uint32_t heavy_min,
-                             int32_t* __restrict__ list, int32_t* count) {
+                             int32_t* __restrict__ list, int32_t* count,
+                             unsigned long long* cand_sum) {
   const int lane = threadIdx.x & 63;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < n_active;
@@ -541,14 +542,22 @@ __global__ void k_heavy_list(const int32_t* __restrict__ active, int64_t n_activ
     const int64_t i = base + lane;
     int32_t q = 0;
     bool h = false;
+    unsigned long long cs = 0;
     if (i < n_active) {
       q = active ? active[i] : (int32_t)i;
-      h = cand_count[cell_of[q]] >= heavy_min;
+      const uint32_t cq = cand_count[cell_of[q]];
+      h = cq >= heavy_min;
+      cs = h ? cq : 0ull;
     }
     const uint64_t m = __ballot(h);
     if (m) {
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) cs += __shfl_xor(cs, o, 64);
       int b = 0;
-      if (lane == 0) b = atomicAdd(count, (int)__popcll(m));
+      if (lane == 0) {
+        b = atomicAdd(count, (int)__popcll(m));
+        atomicAdd(cand_sum, cs);
+      }
       b = __shfl(b, 0, 64);
       const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
       if (h) list[b + (int)__popcll(m & lt)] = q;
@@ -748,10 +757,9 @@ void launch_active_cand_sum(const int32_t* active, int64_t n_active, const uint3
 
 void launch_heavy_list(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
                        const uint32_t* cand_count, uint32_t heavy_min, int32_t* list,
-                       int32_t* count, hipStream_t s) {
-  launch_zero(count, sizeof(int32_t), s);
+                       int32_t* count, unsigned long long* cand_sum, hipStream_t s) {
   k_heavy_list<<<grid_for(n_active, 2048), kBlock, 0, s>>>(active, n_active, cell_of, cand_count,
-                                                            heavy_min, list, count);
+                                                            heavy_min, list, count, cand_sum);
   KNN_LAUNCHED();
 }
 

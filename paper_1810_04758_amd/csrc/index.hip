@@ -492,10 +492,13 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       a.heavy_min = heavy_min;
       a.heavy = c.heavy.p;
       a.n_heavy = c.iscal.p + kHeavySlot;
+      a.heavy_fail = c.iscal.p + kHeavyFailSlot;
       launch_heavy_list(active, A, c.cell_of.p, c.cand_count.p, heavy_min, c.heavy.p,
-                        c.iscal.p + kHeavySlot, s);
+                        c.iscal.p + kHeavySlot,
+                        reinterpret_cast<unsigned long long*>(c.iscal.p + kHeavyCandSlot), s);
       launch_search_heavy(a, idx.n, ncu, s);
     }
+    ev.rec(3, s);
     if (o.schedule == 0) {
       int blocks;
       if (rp) {
@@ -527,15 +530,25 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     }
     ev.rec(2, s);
     int32_t sc[2] = {0, 0};
+    int64_t hq = 0, hf = 0;
+    double hc = 0;
     if (rp) {
       sc[0] = rp->fails;
       sc[1] = rp->refine;
+      hq = rp->heavy;
+      hf = rp->heavy_failed;
+      hc = rp->heavy_cand;
     } else {
-      KNN_HIP(hipMemcpyAsync(&sc[0], c.iscal.p + kFailSlot, sizeof(int32_t),
-                             hipMemcpyDeviceToHost, s));
-      KNN_HIP(hipMemcpyAsync(&sc[1], c.iscal.p + kRefineSlot, sizeof(int32_t),
-                             hipMemcpyDeviceToHost, s));
+      int32_t cnt[kCounterInts];
+      KNN_HIP(hipMemcpyAsync(cnt, c.iscal.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));
+      sc[0] = cnt[kFailSlot];
+      sc[1] = cnt[kRefineSlot];
+      hq = cnt[kHeavySlot];
+      hf = cnt[kHeavyFailSlot];
+      uint64_t hcu = 0;
+      std::memcpy(&hcu, &cnt[kHeavyCandSlot], sizeof(hcu));
+      hc = (double)hcu;
     }
     const int32_t fails = sc[0];
     if (record) {
@@ -545,6 +558,9 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       lp.cand = cand;
       lp.fails = fails;
       lp.refine = sc[1];
+      lp.heavy = hq;
+      lp.heavy_failed = hf;
+      lp.heavy_cand = hc;
       lp.M = c.M;
       lp.cell_w = 1.0 / c.gg.inv_w;
       record->push_back(lp);
@@ -560,7 +576,11 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       st->failed[level] = fails;
       st->cells[level] = c.M;
       st->ms_build[level] = elapsed_ms(ev.e[0], ev.e[1]);
-      st->ms_search[level] = elapsed_ms(ev.e[1], ev.e[2]);
+      st->ms_heavy[level] = elapsed_ms(ev.e[1], ev.e[3]);
+      st->ms_search[level] = elapsed_ms(ev.e[3], ev.e[2]);
+      st->heavy_queries[level] = hq;
+      st->heavy_failed[level] = hf;
+      st->heavy_cand[level] = hc;
       st->total_attempted += A;
       st->total_failed += fails;
     }
@@ -618,6 +638,9 @@ void stats_from_plan(const GraphPlan& gp, knn_join_stats* st) {
     st->lanes[L] = lp.T;
     st->cand_per_query[L] = lp.cand;
     st->refine_rounds[L] = lp.refine;
+    st->heavy_queries[L] = lp.heavy;
+    st->heavy_failed[L] = lp.heavy_failed;
+    st->heavy_cand[L] = lp.heavy_cand;
     st->cell_width[L] = lp.cell_w;
     st->attempted[L] = lp.A;
     st->failed[L] = lp.fails;

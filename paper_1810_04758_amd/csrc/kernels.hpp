@@ -15,7 +15,9 @@ constexpr int kLineInts = 32;
 constexpr int kFailSlot = kXcds * kLineInts;       // failed queries
 constexpr int kRefineSlot = kFailSlot + kLineInts;   // refinement rounds (diagnostics)
 constexpr int kHeavySlot = kRefineSlot + kLineInts;  // heavy queries
-constexpr int kCounterInts = kHeavySlot + kLineInts;
+constexpr int kHeavyFailSlot = kHeavySlot + kLineInts;      // of which failed (diagnostics)
+constexpr int kHeavyCandSlot = kHeavyFailSlot + kLineInts;  // their candidates (uint64)
+constexpr int kCounterInts = kHeavyCandSlot + kLineInts;
 
 // Geometry of one grid level (Sec. 3.1): cell side 1/inv_w, origin lo.
 struct GridGeom {
@@ -93,10 +95,11 @@ void launch_active_cand_sum(const int32_t* active /*nullable*/, int64_t n_active
                             const uint32_t* cell_of, const uint32_t* cand_count, uint64_t* sum,
                             hipStream_t s);
 // list[0 .. *count) = the active sorted positions whose cell has at least
-// heavy_min candidates (order unspecified); *count is zeroed first.
+// heavy_min candidates (order unspecified); *cand_sum += their candidates.
 void launch_heavy_list(const int32_t* active /*nullable*/, int64_t n_active,
                        const uint32_t* cell_of, const uint32_t* cand_count, uint32_t heavy_min,
-                       int32_t* list, int32_t* count, hipStream_t s);
+                       int32_t* list, int32_t* count, unsigned long long* cand_sum,
+                       hipStream_t s);
 // flags[p] = failed[perm[p]] for the next level's active list.
 void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count,
                         int64_t max_fail, uint8_t* failed, hipStream_t s);
@@ -150,6 +153,7 @@ struct SearchArgs {
   uint32_t heavy_min;      // > 0: k_search leaves queries with this many candidates or more
   const int32_t* heavy;    // to k_search_heavy: their sorted positions
   const int32_t* n_heavy;  // and their number (device)
+  int32_t* heavy_fail;     // failures among them (diagnostics)
 };
 // Returns the number of waves per block used.
 void launch_search(const SearchArgs& a, int dims, int lanes_per_query, int grid_blocks,

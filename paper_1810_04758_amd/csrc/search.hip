@@ -744,7 +744,10 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
       s_chi = chi;
       s_dmin = ~0ull;
       s_dmax = 0ull;
-      if (bsel == NB) a.fail_list[atomicAdd(a.fail_count, 1)] = perm[q];
+      if (bsel == NB) {
+        a.fail_list[atomicAdd(a.fail_count, 1)] = perm[q];
+        if (a.heavy_fail) atomicAdd(a.heavy_fail, 1);
+      }
     }
     __syncthreads();
     const int bsel = s_bsel;

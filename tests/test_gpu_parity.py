@@ -333,3 +333,8 @@ def test_heavy_queries(knn, oracle_mod, name, gen, K, heavy_min):
     ids, dists, st = _join(knn, D, K, heavy_min=heavy_min, w_factor=0.6, tail_pairs=-1)
     _check_rows(D, ids, dists, K, np.arange(N), oracle_mod)
     assert st["levels"] >= 2
+    if heavy_min == 1:  # every query of every level went to the workgroup kernel
+        assert st["heavy_queries"] == st["attempted"]
+        assert st["heavy_failed"] == st["failed"]
+    if heavy_min == -1:
+        assert not any(st["heavy_queries"])
