@@ -359,7 +359,7 @@ __device__ inline void range_of(int r, const int64_t (&cc)[DIM],
                                 const uint32_t* __restrict__ cell_start,
                                 const uint64_t* __restrict__ cell_key, uint32_t M,
                                 const uint32_t* __restrict__ dense, const struct GeomDev& gd,
-                                uint32_t& start, uint32_t& end);
+                                uint32_t& start, uint32_t& mid0, uint32_t& mid1, uint32_t& end);
 
 // A group of S lanes per cell (S = the power of two >= 3^(n-1), at most 64):
 // lane l computes row segments r = l, l+S, ...; the non-empty ones are written
@@ -391,15 +391,14 @@ __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
     uint32_t count = 0, cand = 0;
     for (int rb = 0; rb < R; rb += S) {
       const int r = rb + l;
-      uint32_t start = 0, end = 0;
-      if (r < R) range_of<DIM>(r, cc, cell_start, cell_key, M, dense, gd, start, end);
+      uint32_t start = 0, mid0 = 0, mid1 = 0, end = 0;
+      if (r < R) range_of<DIM>(r, cc, cell_start, cell_key, M, dense, gd, start, mid0, mid1, end);
       const bool ne = end > start;
       const uint64_t m = (S == 64 ? __ballot(ne) : (__ballot(ne) >> (sub * S))) &
                          (S == 64 ? ~0ull : ((1ull << S) - 1ull));
       if (ne) {
         const uint32_t pos = count + (uint32_t)__popcll(m & lt);
-        ranges[((int64_t)c * R + pos) * 2] = start;
-        ranges[((int64_t)c * R + pos) * 2 + 1] = end;
+        reinterpret_cast<uint4*>(ranges)[(int64_t)c * R + pos] = make_uint4(start, mid0, mid1, end);
         rslot[(int64_t)c * R + pos] = (uint8_t)r;
         cand += end - start;
       }
@@ -416,13 +415,15 @@ __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
 
 // Point range [start, end) of row segment r of the cell with coordinates cc
 // (offsets o_0..o_{DIM-2} in {-1,0,1}, o_0 slowest; last coordinate within
-// one of the cell's).  Empty: start == end == 0.
+// one of the cell's), split at mid0 and mid1: [start, mid0) holds the points
+// whose last cell coordinate is below the cell's, [mid0, mid1) those equal to
+// it, [mid1, end) those above.  Empty: all four 0.
 template <int DIM>
 __device__ inline void range_of(int r, const int64_t (&cc)[DIM],
                                 const uint32_t* __restrict__ cell_start,
                                 const uint64_t* __restrict__ cell_key, uint32_t M,
                                 const uint32_t* __restrict__ dense, const GeomDev& gd,
-                                uint32_t& start, uint32_t& end) {
+                                uint32_t& start, uint32_t& mid0, uint32_t& mid1, uint32_t& end) {
   {
     bool inside = true;
     uint64_t prefix = 0;
@@ -437,34 +438,46 @@ __device__ inline void range_of(int r, const int64_t (&cc)[DIM],
     }
     start = 0;
     end = 0;
+    mid0 = 0;
+    mid1 = 0;
     if (inside) {
 #pragma unroll
       for (int j = 0; j < DIM - 1; ++j) prefix += (uint64_t)nb[j] * gd.stride[j];
       const int64_t last = cc[DIM - 1];
       const int64_t a = last > 0 ? last - 1 : 0;
       const int64_t b = last + 1 < gd.g[DIM - 1] ? last + 1 : gd.g[DIM - 1] - 1;
+      // the segment's cells are consecutive in sorted order; the first one
+      // with t >= last starts the middle part, the first with t > last the
+      // upper part
+      uint32_t c_lo = 0xFFFFFFFFu, c_hi = 0xFFFFFFFFu;  // first / last cell of the segment
+      uint32_t c_mid = 0xFFFFFFFFu, c_up = 0xFFFFFFFFu;
       if (dense) {
-        uint32_t first = 0xFFFFFFFFu, lastc = 0xFFFFFFFFu;
         for (int64_t t = a; t <= b; ++t) {
           uint32_t ci = dense[prefix + (uint64_t)t];
           if (ci != 0xFFFFFFFFu) {
-            if (first == 0xFFFFFFFFu) first = ci;
-            lastc = ci;
+            if (c_lo == 0xFFFFFFFFu) c_lo = ci;
+            c_hi = ci;
+            if (t >= last && c_mid == 0xFFFFFFFFu) c_mid = ci;
+            if (t > last && c_up == 0xFFFFFFFFu) c_up = ci;
           }
-        }
-        if (first != 0xFFFFFFFFu) {
-          start = cell_start[first];
-          end = cell_start[lastc + 1];
         }
       } else {
         const uint64_t klo = prefix + (uint64_t)a, khi = prefix + (uint64_t)b;
+        const uint64_t kmid = prefix + (uint64_t)last;
         uint32_t f = lower_bound_key(cell_key, M, klo);
-        uint32_t l = f;
-        while (l < M && cell_key[l] <= khi) ++l;
-        if (l > f) {
-          start = cell_start[f];
-          end = cell_start[l];
+        for (uint32_t l = f; l < M && cell_key[l] <= khi; ++l) {
+          const uint64_t k = cell_key[l];
+          if (c_lo == 0xFFFFFFFFu) c_lo = l;
+          c_hi = l;
+          if (k >= kmid && c_mid == 0xFFFFFFFFu) c_mid = l;
+          if (k > kmid && c_up == 0xFFFFFFFFu) c_up = l;
         }
+      }
+      if (c_lo != 0xFFFFFFFFu) {
+        start = cell_start[c_lo];
+        end = cell_start[c_hi + 1];
+        mid0 = c_mid != 0xFFFFFFFFu ? cell_start[c_mid] : end;
+        mid1 = c_up != 0xFFFFFFFFu ? cell_start[c_up] : end;
       }
     }
   }

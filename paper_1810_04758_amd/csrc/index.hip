@@ -232,7 +232,7 @@ int64_t build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t 
       Mcap = std::max<int64_t>(M, 1);
     }
   }
-  c.ranges.reserve((size_t)Mcap * R * 2);
+  c.ranges.reserve((size_t)Mcap * R * 4);
   c.rslot.reserve((size_t)Mcap * R);
   c.nrng.reserve(N);
   launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, dense, c.gg,
@@ -249,7 +249,7 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   uint64_t b = 0;
   b += 8 * n * N;                      // Xs
   b += (4 + 4 + 8 + 4 + 4 + 4) * N;    // perm, cell_of, cell_key, cell_start, nrng, cand_count
-  b += 9 * R * N;                      // ranges + rslot
+  b += 17 * R * N;                     // ranges (4 x u32) + rslot
   if (idx.n > 2) b += std::max<uint64_t>(64 * N, 16ull << 20);  // dense key table
   b += (16 + 4 + 4) * N;               // keys, keys2, vals2, flags
   b += (uint64_t)radix_tmp_elems((int64_t)N) * 4;
@@ -1096,10 +1096,10 @@ int knn_grid_export(knn_index* idx, double cell_width, uint64_t* sorted_keys, in
       std::vector<uint32_t> hr, hn;
       std::vector<uint8_t> hs;
       if (ranges) {
-        hr.resize((size_t)M * R * 2);
+        hr.resize((size_t)M * R * 4);
         hs.resize((size_t)M * R);
         hn.resize((size_t)M);
-        KNN_HIP(hipMemcpyAsync(hr.data(), c.ranges.p, M * R * 2 * 4, hipMemcpyDeviceToHost, s));
+        KNN_HIP(hipMemcpyAsync(hr.data(), c.ranges.p, M * R * 4 * 4, hipMemcpyDeviceToHost, s));
         KNN_HIP(hipMemcpyAsync(hs.data(), c.rslot.p, M * R, hipMemcpyDeviceToHost, s));
         KNN_HIP(hipMemcpyAsync(hn.data(), c.nrng.p, M * 4, hipMemcpyDeviceToHost, s));
       }
@@ -1110,8 +1110,8 @@ int knn_grid_export(knn_index* idx, double cell_width, uint64_t* sorted_keys, in
         for (int64_t cc = 0; cc < M; ++cc)
           for (uint32_t i = 0; i < hn[cc]; ++i) {
             const int64_t r = hs[cc * R + i];
-            ranges[(cc * R + r) * 2] = hr[(cc * R + i) * 2];
-            ranges[(cc * R + r) * 2 + 1] = hr[(cc * R + i) * 2 + 1];
+            ranges[(cc * R + r) * 2] = hr[(cc * R + i) * 4];
+            ranges[(cc * R + r) * 2 + 1] = hr[(cc * R + i) * 4 + 3];
           }
       }
       if (grid_dims)

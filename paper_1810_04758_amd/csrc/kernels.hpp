@@ -72,8 +72,10 @@ void launch_gather_soa(const double* XA, const int32_t* perm, int64_t N, int n, 
 void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N,
                         uint32_t* table, int64_t table_size, hipStream_t s);
 // Row-segment neighbour ranges of every cell: the non-empty ones of the
-// 3^(n-1) segments, compacted in segment order into ranges[(c*R + i)*2 + {0,1}]
-// (start, end) with their segment index in rslot[c*R + i], their number in
+// 3^(n-1) segments, compacted in segment order into
+// ranges[(c*R + i)*4 + {0..3}] = (start, mid0, mid1, end): the segment's
+// points, split where the last cell coordinate reaches the cell's and where
+// it passes it; their segment index in rslot[c*R + i], their number in
 // nrng[c], and the candidate count (sum of lengths) in cand_count[c].
 void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_start,
                             const uint64_t* cell_key, const uint32_t* d_M,
@@ -125,7 +127,7 @@ struct SearchArgs {
   int64_t N;
   const int32_t* perm;     // sorted position -> point id
   const uint32_t* cell_of; // sorted position -> cell
-  const uint32_t* ranges;  // cell*R*2 compacted non-empty row-segment ranges
+  const uint32_t* ranges;  // cell*R*4 compacted non-empty row segments (start, mid0, mid1, end)
   const uint8_t* rslot;    // cell*R: segment index of each compacted range
   const uint32_t* nrng;    // non-empty segments per cell
   const uint32_t* cand;    // candidates per cell

@@ -162,11 +162,11 @@ __device__ __forceinline__ int bitlen128(unsigned __int128 v) {
 
 // Per-query candidate list in LDS: the non-empty row segments that a pass
 // needs, compacted, as (start position, running end in virtual candidate
-// numbering).  A segment is left out when a conservative lower bound of the
-// squared distance from the query to any of its points exceeds the pass's
-// limit (all its candidates would be beyond it).  The bound uses the query's
-// distances to its own cell's faces in the first n-1 dimensions (the segment
-// spans three cells along the last): a neighbour at offset +1 in dimension j
+// numbering).  A segment (or its first or last cell along the last
+// dimension) is left out when a conservative lower bound of the squared
+// distance from the query to any of its points exceeds the pass's limit (all
+// its candidates would be beyond it).  The bound uses the query's distances
+// to its own cell's faces: a neighbour at offset +1 in dimension j
 // is at least (1 - fr_j - mg) w away, at offset -1 at least (fr_j - mg) w,
 // where fr_j is the query's exact fractional cell coordinate and mg bounds
 // the rounding of both cell coordinates in cell units; the final factor
@@ -206,14 +206,27 @@ __device__ __forceinline__ uint32_t build_list(const uint32_t* __restrict__ rg,
     flo[j] = fmax(fr - a.margin, 0.0) * a.w;
     fhi[j] = fmax((1.0 - fr) - a.margin, 0.0) * a.w;
   }
+  // the last dimension: the segment's lower / upper cells are a face away
+  const double dlo = flo[DIM - 1] * flo[DIM - 1], dhi = fhi[DIM - 1] * fhi[DIM - 1];
   uint32_t total = 0, cnt = 0;
   for (int i0 = 0; i0 < nr_w; i0 += T) {
     const int i = i0 + l;
     uint32_t st = 0, len = 0;
     if (i < nr) {
-      st = rg[2 * i];
-      len = rg[2 * i + 1] - st;
-      if (prune && seg_bound<DIM>(rs[i], flo, fhi) * kBoundShrink > lim) len = 0;
+      const uint4 r4 = reinterpret_cast<const uint4*>(rg)[i];  // start, mid0, mid1, end
+      if (!prune) {
+        st = r4.x;
+        len = r4.w - r4.x;
+      } else {
+        // the middle cells are never farther than the outer ones, so the
+        // kept part of a segment is contiguous
+        const double b0 = seg_bound<DIM>(rs[i], flo, fhi);
+        if (b0 * kBoundShrink <= lim) {
+          st = (b0 + dlo) * kBoundShrink <= lim ? r4.x : r4.y;
+          const uint32_t en = (b0 + dhi) * kBoundShrink <= lim ? r4.w : r4.z;
+          len = en - st;
+        }
+      }
     }
     const uint32_t keep = len > 0 ? 1u : 0u;
     uint32_t ik = keep, il = len;
@@ -365,7 +378,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
     for (int j = 0; j < DIM; ++j) qx[j] = Xd[j][q];
     const uint32_t cell = a.cell_of[q];
-    const uint32_t* rg = a.ranges + (size_t)cell * R * 2;
+    const uint32_t* rg = a.ranges + (size_t)cell * R * 4;
     const uint8_t* rs = a.rslot + (size_t)cell * R;
     const uint32_t Cq = in ? a.cand[cell] : 0u;
     // heavy queries are handled by k_search_heavy
@@ -669,7 +682,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
 #pragma unroll
     for (int j = 0; j < DIM; ++j) qx[j] = Xd[j][q];
     const uint32_t cell = a.cell_of[q];
-    const uint32_t* rg = a.ranges + (size_t)cell * R * 2;
+    const uint32_t* rg = a.ranges + (size_t)cell * R * 4;
     const uint8_t* rs = a.rslot + (size_t)cell * R;
     const int nr = (int)a.nrng[cell];
     double mfrac = 0.5;
