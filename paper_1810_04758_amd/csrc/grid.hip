@@ -370,7 +370,8 @@ template <int DIM>
 __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
                                   const uint32_t* __restrict__ cell_start,
                                   const uint64_t* __restrict__ cell_key, const uint32_t* d_M,
-                                  const uint32_t* __restrict__ dense, GeomDev gd,
+                                  const uint32_t* __restrict__ dense,
+                                  const uint8_t* __restrict__ cell_active, GeomDev gd,
                                   uint32_t* __restrict__ ranges, uint8_t* __restrict__ rslot,
                                   uint32_t* __restrict__ nrng,
                                   uint32_t* __restrict__ cand_count) {
@@ -384,6 +385,7 @@ __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
   const int64_t groups = (int64_t)gridDim.x * (blockDim.x / S);
   for (int64_t c = (int64_t)blockIdx.x * (blockDim.x / S) + threadIdx.x / S; c < (int64_t)M;
        c += groups) {
+    if (cell_active && !cell_active[c]) continue;
     const uint32_t p0 = cell_start[c];
     int64_t cc[DIM];
 #pragma unroll
@@ -736,17 +738,18 @@ void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N
 
 void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_start,
                             const uint64_t* cell_key, const uint32_t* d_M,
-                            const uint32_t* dense, const GridGeom& gg, uint32_t* ranges,
-                            uint8_t* rslot, uint32_t* nrng, uint32_t* cand_count, hipStream_t s) {
+                            const uint32_t* dense, const uint8_t* cell_active,
+                            const GridGeom& gg, uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
+                            uint32_t* cand_count, hipStream_t s) {
   GeomDev gd = to_dev(gg);
   const int S = gg.dims == 2 ? 4 : gg.dims == 3 ? 16 : gg.dims == 4 ? 32 : 64;
   const int nb = grid_for(N * S, 65536);
   switch (gg.dims) {
-    case 2: k_neighbor_ranges<2><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, rslot, nrng, cand_count); break;
-    case 3: k_neighbor_ranges<3><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, rslot, nrng, cand_count); break;
-    case 4: k_neighbor_ranges<4><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, rslot, nrng, cand_count); break;
-    case 5: k_neighbor_ranges<5><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, rslot, nrng, cand_count); break;
-    case 6: k_neighbor_ranges<6><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, gd, ranges, rslot, nrng, cand_count); break;
+    case 2: k_neighbor_ranges<2><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, cell_active, gd, ranges, rslot, nrng, cand_count); break;
+    case 3: k_neighbor_ranges<3><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, cell_active, gd, ranges, rslot, nrng, cand_count); break;
+    case 4: k_neighbor_ranges<4><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, cell_active, gd, ranges, rslot, nrng, cand_count); break;
+    case 5: k_neighbor_ranges<5><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, cell_active, gd, ranges, rslot, nrng, cand_count); break;
+    case 6: k_neighbor_ranges<6><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, cell_active, gd, ranges, rslot, nrng, cand_count); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
   KNN_LAUNCHED();
@@ -785,6 +788,20 @@ void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count, i
 void launch_failed_flags(const uint8_t* failed, const int32_t* perm, int64_t N, uint32_t* flags,
                          hipStream_t s) {
   k_failed_flags<<<grid_for(N), kBlock, 0, s>>>(failed, perm, N, flags);
+  KNN_LAUNCHED();
+}
+
+__global__ void k_mark_cells_of(const int32_t* __restrict__ active, int64_t n_active,
+                                const uint32_t* __restrict__ cell_of, uint8_t* __restrict__ flags) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_active;
+       i += (int64_t)gridDim.x * blockDim.x)
+    flags[cell_of[active[i]]] = 1;
+}
+
+void launch_mark_cells_of(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
+                          uint8_t* flags, hipStream_t s) {
+  if (n_active <= 0) return;
+  k_mark_cells_of<<<grid_for(n_active), kBlock, 0, s>>>(active, n_active, cell_of, flags);
   KNN_LAUNCHED();
 }
 

@@ -158,7 +158,7 @@ int64_t JoinContext::device_bytes() const {
                    scal.bytes() + iscal.bytes() + active.bytes() + fail_list.bytes() +
                    failed.bytes() + ikeys.bytes() + ikeys2.bytes() + ivals.bytes() +
                    ivals2.bytes() + out_ids.bytes() + out_d.bytes() + tail_scratch.bytes() +
-                   cand_sum.bytes() + heavy.bytes());
+                   cand_sum.bytes() + heavy.bytes() + cell_active.bytes());
 }
 
 double eps_min_of(const knn_index& idx, int32_t K) {
@@ -180,8 +180,7 @@ void validate_join(const knn_index* idx, int32_t K) {
   KNN_CHECK(K <= KNN_MAX_K, KNN_EINVAL, "K above KNN_MAX_K");
 }
 
-int64_t build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s,
-                    int64_t Mcap_known) {
+void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s) {
   const int64_t N = idx.N;
   const int n = idx.n;
   c.gg = make_geom(idx, w);
@@ -218,6 +217,13 @@ int64_t build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t 
     launch_dense_table(c.cell_key.p, c.scal.p, N, c.dense.p, (int64_t)cells, s);
     dense = c.dense.p;
   }
+  c.dense_used = dense;
+}
+
+int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_t Mcap_known,
+                     const uint8_t* cell_active) {
+  const int64_t N = idx.N;
+  const int n = idx.n;
   const int64_t R = pow3(n - 1);
   int64_t Mcap = N;
   if (R >= 81) {
@@ -235,9 +241,15 @@ int64_t build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t 
   c.ranges.reserve((size_t)Mcap * R * 4);
   c.rslot.reserve((size_t)Mcap * R);
   c.nrng.reserve(N);
-  launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, dense, c.gg,
-                         c.ranges.p, c.rslot.p, c.nrng.p, c.cand_count.p, s);
+  launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, c.dense_used,
+                         cell_active, c.gg, c.ranges.p, c.rslot.p, c.nrng.p, c.cand_count.p, s);
   return Mcap;
+}
+
+int64_t build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s,
+                    int64_t Mcap_known) {
+  build_grid(idx, c, w, s);
+  return build_ranges(idx, c, s, Mcap_known, nullptr);
 }
 
 uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
@@ -380,9 +392,10 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       break;
     }
     ev.rec(0, s);
-    lp.Mcap = build_level(idx, c, w, s, rp ? rp->Mcap : 0);
+    build_grid(idx, c, w, s);
     // active list of this level (cell order): level 0 = every point
     const int32_t* active = nullptr;
+    const uint8_t* cell_active = nullptr;
     if (level > 0) {
       // keys2 (scratch of the level's sort) holds the exclusive scan
       uint32_t* ex = reinterpret_cast<uint32_t*>(c.keys2.p);
@@ -390,7 +403,13 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       launch_exclusive_scan(c.flags.p, ex, N, c.scal.p + 1, c.tmp.p, s);
       launch_compact_positions(c.flags.p, ex, N, c.active.p, s);
       active = c.active.p;
+      // neighbour ranges only for the cells that hold an active query
+      c.cell_active.reserve(N);
+      launch_zero(c.cell_active.p, (size_t)N, s);
+      launch_mark_cells_of(active, A, c.cell_of.p, c.cell_active.p, s);
+      cell_active = c.cell_active.p;
     }
+    lp.Mcap = build_ranges(idx, c, s, rp ? rp->Mcap : 0, cell_active);
     // lanes per query from the level's mean candidate count (the paper's t,
     // Sec. 4.7, chosen per level: the tail levels see far more candidates)
     double cand = 0;

@@ -65,6 +65,8 @@ struct JoinContext {
   DevBuf<char> tail_scratch;
   DevBuf<uint64_t> cand_sum;  // [0] candidates of the active queries, [1] their maximum
   DevBuf<int32_t> heavy;      // heavy queries of the level
+  DevBuf<uint8_t> cell_active;  // cells holding an active query (levels > 0)
+  const uint32_t* dense_used = nullptr;  // the level's dense key table, if any
 
   int64_t device_bytes() const;
 };
@@ -116,6 +118,12 @@ struct JoinParams {
   knn_join_opts opts;
 };
 
+// The grid of cell side w (keys, sort, cell table, sorted coordinates, dense
+// key table) into ctx, then the neighbour ranges of every cell (cell_active
+// NULL) or of the flagged cells only.
+void build_grid(const knn_index& idx, JoinContext& ctx, double w, hipStream_t s);
+int64_t build_ranges(const knn_index& idx, JoinContext& ctx, hipStream_t s, int64_t Mcap_known,
+                     const uint8_t* cell_active);
 // Builds the grid level of cell side w into ctx (Sec. 3.1 / 4.6).
 // Mcap_known > 0: the cell count that sizes the 5-6 dimension range arrays
 // (no round trip); else it is read back when needed.  Returns the Mcap used.

@@ -77,11 +77,17 @@ void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N
 // points, split where the last cell coordinate reaches the cell's and where
 // it passes it; their segment index in rslot[c*R + i], their number in
 // nrng[c], and the candidate count (sum of lengths) in cand_count[c].
+// cell_active (nullable): only the flagged cells get ranges (the others'
+// entries are left as they were).
 void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_start,
                             const uint64_t* cell_key, const uint32_t* d_M,
-                            const uint32_t* dense /*nullable*/, const GridGeom& gg,
+                            const uint32_t* dense /*nullable*/,
+                            const uint8_t* cell_active /*nullable*/, const GridGeom& gg,
                             uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
                             uint32_t* cand_count, hipStream_t s);
+// flags[cell_of[active[i]]] = 1 for every active query.
+void launch_mark_cells_of(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
+                          uint8_t* flags, hipStream_t s);
 
 // ---- work items (grid.hip) ----
 // Work item i = G consecutive active slots.  Its estimate is the sum of the
