@@ -115,7 +115,8 @@ typedef struct knn_join_opts {
                              (another key replaces it).  Statistics of a replay
                              repeat the recorded counts; per-level times are 0 [0] */
   double tail_pairs;      /* brute-force tail once (remaining queries) x N <= this
-                             [1.5e9]; < 0 disables the tail (Sec. 5.3.8 remedy) */
+                             [autotuned or 2.5e8]; < 0 disables the tail (the
+                             remedy Sec. 5.3.8 proposes) */
   int64_t heavy_min;      /* queries with at least this many
                              candidates get a workgroup each; 0 = automatic
                              (those that would outlast the level), < 0 = never */
@@ -213,11 +214,12 @@ typedef struct knn_autotune_result {
   int32_t trials;     /* settings measured */
   int32_t linear_levels; /* chosen linear growths before the geometric ones
                             (0 or 1; -1 in the cache means none) */
+  double tail_pairs;     /* chosen brute-force tail budget (pairs) */
 } knn_autotune_result;
 /* Runs on `stream` (device scratch allocated internally); blocks. */
 int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* out);
 /* Save / load the cache as text ("dims kbucket nbucket w_factor growth
- * lanes linear" per line); path NULL = $KNN_AUTOTUNE_CACHE. */
+ * lanes linear tail_pairs" per line); path NULL = $KNN_AUTOTUNE_CACHE. */
 int knn_autotune_save(const char* path);
 int knn_autotune_load(const char* path);
 

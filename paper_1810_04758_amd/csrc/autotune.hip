@@ -36,9 +36,10 @@ void load_file_locked(const char* p) {
   FILE* f = std::fopen(p, "r");
   if (!f) return;
   int d, kb, nb, lanes, lin;
-  double wf, gr;
-  while (std::fscanf(f, "%d %d %d %lf %lf %d %d", &d, &kb, &nb, &wf, &gr, &lanes, &lin) == 7)
-    g_cache[Class(d, kb, nb)] = TuneEntry{wf, gr, lanes, lin};
+  double wf, gr, tp;
+  while (std::fscanf(f, "%d %d %d %lf %lf %d %d %lf", &d, &kb, &nb, &wf, &gr, &lanes, &lin, &tp) ==
+         8)
+    g_cache[Class(d, kb, nb)] = TuneEntry{wf, gr, lanes, lin, tp};
   std::fclose(f);
 }
 
@@ -68,6 +69,10 @@ double autotune_growth(int dims, int K, int64_t N) { return autotune_get(dims, K
 
 int autotune_linear(int dims, int K, int64_t N) { return autotune_get(dims, K, N).linear; }
 
+double autotune_tail_pairs(int dims, int K, int64_t N) {
+  return autotune_get(dims, K, N).tail_pairs;
+}
+
 void autotune_store(int dims, int K, int64_t N, const TuneEntry& e) {
   std::lock_guard<std::mutex> lk(g_mu);
   ensure_loaded_locked();
@@ -93,9 +98,9 @@ int autotune_save(const char* path) {
   FILE* f = std::fopen(p, "w");
   if (!f) return -1;
   for (auto& kv : g_cache)
-    std::fprintf(f, "%d %d %d %.17g %.17g %d %d\n", std::get<0>(kv.first),
+    std::fprintf(f, "%d %d %d %.17g %.17g %d %d %.17g\n", std::get<0>(kv.first),
                  std::get<1>(kv.first), std::get<2>(kv.first), kv.second.w_factor,
-                 kv.second.growth, kv.second.lanes, kv.second.linear);
+                 kv.second.growth, kv.second.lanes, kv.second.linear, kv.second.tail_pairs);
   std::fclose(f);
   return 0;
 }

@@ -14,6 +14,7 @@ struct TuneEntry {
   double growth;    // 0 = no measurement
   int lanes;        // 0 = chosen per level from the candidate counts
   int linear = 0;   // linear growths: 0 = not measured (default), 1, or -1 (none)
+  double tail_pairs = 0;  // brute-force tail budget, 0 = not measured
 };
 
 // Cached entry for the class of (dims, K, N), or all zeros.
@@ -25,6 +26,8 @@ double autotune_w_factor(int dims, int K, int64_t N);
 double autotune_growth(int dims, int K, int64_t N);
 // Linear growths before the geometric ones (0 if none cached: the default).
 int autotune_linear(int dims, int K, int64_t N);
+// Brute-force tail budget (0 if none cached).
+double autotune_tail_pairs(int dims, int K, int64_t N);
 // Records a measured best setting for the class of (dims, K, N).
 void autotune_store(int dims, int K, int64_t N, const TuneEntry& e);
 // Loads / saves the cache file (path from KNN_AUTOTUNE_CACHE when path is NULL).

@@ -341,9 +341,8 @@ __global__ void k_dense_scatter(const uint64_t* __restrict__ cell_key, const uin
 }
 
 // Index of the first cell whose key is >= key (binary search in cell_key[0..M)).
-__device__ inline uint32_t lower_bound_key(const uint64_t* __restrict__ cell_key, uint32_t M,
-                                           uint64_t key) {
-  uint32_t lo = 0, hi = M;
+__device__ inline uint32_t lower_bound_key(const uint64_t* __restrict__ cell_key, uint32_t lo,
+                                           uint32_t hi, uint64_t key) {
   while (lo < hi) {
     uint32_t mid = lo + ((hi - lo) >> 1);
     if (cell_key[mid] < key)
@@ -358,7 +357,8 @@ template <int DIM>
 __device__ inline void range_of(int r, const int64_t (&cc)[DIM],
                                 const uint32_t* __restrict__ cell_start,
                                 const uint64_t* __restrict__ cell_key, uint32_t M,
-                                const uint32_t* __restrict__ dense, const struct GeomDev& gd,
+                                const uint32_t* __restrict__ dense,
+                                const uint2* __restrict__ rowtab, const struct GeomDev& gd,
                                 uint32_t& start, uint32_t& mid0, uint32_t& mid1, uint32_t& end);
 
 // A group of S lanes per cell (S = the power of two >= 3^(n-1), at most 64):
@@ -371,6 +371,7 @@ __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
                                   const uint32_t* __restrict__ cell_start,
                                   const uint64_t* __restrict__ cell_key, const uint32_t* d_M,
                                   const uint32_t* __restrict__ dense,
+                                  const uint2* __restrict__ rowtab,
                                   const uint8_t* __restrict__ cell_active, GeomDev gd,
                                   uint32_t* __restrict__ ranges, uint8_t* __restrict__ rslot,
                                   uint32_t* __restrict__ nrng,
@@ -394,7 +395,8 @@ __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
     for (int rb = 0; rb < R; rb += S) {
       const int r = rb + l;
       uint32_t start = 0, mid0 = 0, mid1 = 0, end = 0;
-      if (r < R) range_of<DIM>(r, cc, cell_start, cell_key, M, dense, gd, start, mid0, mid1, end);
+      if (r < R)
+        range_of<DIM>(r, cc, cell_start, cell_key, M, dense, rowtab, gd, start, mid0, mid1, end);
       const bool ne = end > start;
       const uint64_t m = (S == 64 ? __ballot(ne) : (__ballot(ne) >> (sub * S))) &
                          (S == 64 ? ~0ull : ((1ull << S) - 1ull));
@@ -424,7 +426,8 @@ template <int DIM>
 __device__ inline void range_of(int r, const int64_t (&cc)[DIM],
                                 const uint32_t* __restrict__ cell_start,
                                 const uint64_t* __restrict__ cell_key, uint32_t M,
-                                const uint32_t* __restrict__ dense, const GeomDev& gd,
+                                const uint32_t* __restrict__ dense,
+                                const uint2* __restrict__ rowtab, const GeomDev& gd,
                                 uint32_t& start, uint32_t& mid0, uint32_t& mid1, uint32_t& end) {
   {
     bool inside = true;
@@ -466,8 +469,15 @@ __device__ inline void range_of(int r, const int64_t (&cc)[DIM],
       } else {
         const uint64_t klo = prefix + (uint64_t)a, khi = prefix + (uint64_t)b;
         const uint64_t kmid = prefix + (uint64_t)last;
-        uint32_t f = lower_bound_key(cell_key, M, klo);
-        for (uint32_t l = f; l < M && cell_key[l] <= khi; ++l) {
+        // cells of the row (a CSR row table when there is one, else all)
+        uint32_t rs = 0, re = M;
+        if (rowtab) {
+          const uint2 rr2 = rowtab[prefix / (uint64_t)gd.g[DIM - 1]];
+          rs = rr2.x;
+          re = rr2.y;
+        }
+        uint32_t f = lower_bound_key(cell_key, rs, re, klo);
+        for (uint32_t l = f; l < re && cell_key[l] <= khi; ++l) {
           const uint64_t k = cell_key[l];
           if (c_lo == 0xFFFFFFFFu) c_lo = l;
           c_hi = l;
@@ -728,6 +738,24 @@ void launch_gather_soa(const double* X, const int32_t* perm, int64_t N, int n, d
   KNN_LAUNCHED();
 }
 
+__global__ void k_row_table(const uint64_t* __restrict__ cell_key, const uint32_t* d_M,
+                            uint64_t g_last, uint2* __restrict__ rowtab) {
+  const uint32_t M = *d_M;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < (int64_t)M;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t row = cell_key[c] / g_last;
+    if (c == 0 || cell_key[c - 1] / g_last != row) rowtab[row].x = (uint32_t)c;
+    if (c == (int64_t)M - 1 || cell_key[c + 1] / g_last != row) rowtab[row].y = (uint32_t)(c + 1);
+  }
+}
+
+void launch_row_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N, uint64_t g_last,
+                      uint2* rowtab, int64_t rows, hipStream_t s) {
+  launch_zero(rowtab, (size_t)rows * sizeof(uint2), s);
+  k_row_table<<<grid_for(N), kBlock, 0, s>>>(cell_key, d_M, g_last, rowtab);
+  KNN_LAUNCHED();
+}
+
 void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N,
                         uint32_t* table, int64_t table_size, hipStream_t s) {
   k_dense_fill<<<grid_for(table_size), kBlock, 0, s>>>(table, table_size);
@@ -738,18 +766,18 @@ void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N
 
 void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_start,
                             const uint64_t* cell_key, const uint32_t* d_M,
-                            const uint32_t* dense, const uint8_t* cell_active,
+                            const uint32_t* dense, const uint2* rowtab, const uint8_t* cell_active,
                             const GridGeom& gg, uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
                             uint32_t* cand_count, hipStream_t s) {
   GeomDev gd = to_dev(gg);
   const int S = gg.dims == 2 ? 4 : gg.dims == 3 ? 16 : gg.dims == 4 ? 32 : 64;
   const int nb = grid_for(N * S, 65536);
   switch (gg.dims) {
-    case 2: k_neighbor_ranges<2><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, cell_active, gd, ranges, rslot, nrng, cand_count); break;
-    case 3: k_neighbor_ranges<3><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, cell_active, gd, ranges, rslot, nrng, cand_count); break;
-    case 4: k_neighbor_ranges<4><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, cell_active, gd, ranges, rslot, nrng, cand_count); break;
-    case 5: k_neighbor_ranges<5><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, cell_active, gd, ranges, rslot, nrng, cand_count); break;
-    case 6: k_neighbor_ranges<6><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, cell_active, gd, ranges, rslot, nrng, cand_count); break;
+    case 2: k_neighbor_ranges<2><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, gd, ranges, rslot, nrng, cand_count); break;
+    case 3: k_neighbor_ranges<3><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, gd, ranges, rslot, nrng, cand_count); break;
+    case 4: k_neighbor_ranges<4><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, gd, ranges, rslot, nrng, cand_count); break;
+    case 5: k_neighbor_ranges<5><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, gd, ranges, rslot, nrng, cand_count); break;
+    case 6: k_neighbor_ranges<6><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, gd, ranges, rslot, nrng, cand_count); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
   KNN_LAUNCHED();

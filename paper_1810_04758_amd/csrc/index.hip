@@ -158,7 +158,7 @@ int64_t JoinContext::device_bytes() const {
                    scal.bytes() + iscal.bytes() + active.bytes() + fail_list.bytes() +
                    failed.bytes() + ikeys.bytes() + ikeys2.bytes() + ivals.bytes() +
                    ivals2.bytes() + out_ids.bytes() + out_d.bytes() + tail_scratch.bytes() +
-                   cand_sum.bytes() + heavy.bytes() + cell_active.bytes());
+                   cand_sum.bytes() + heavy.bytes() + cell_active.bytes() + rowtab.bytes());
 }
 
 double eps_min_of(const knn_index& idx, int32_t K) {
@@ -218,6 +218,18 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s) {
     dense = c.dense.p;
   }
   c.dense_used = dense;
+  // otherwise a row table, when the rows (cells sharing coordinates 0..n-2)
+  // are few enough: a range lookup is then a short search within one row
+  c.rowtab_used = nullptr;
+  if (!dense) {
+    const long double rows = cells / (long double)c.gg.g[n - 1];
+    if (rows <= (long double)std::max<int64_t>(32 * N, 1 << 22)) {
+      c.rowtab.reserve((size_t)rows);
+      launch_row_table(c.cell_key.p, c.scal.p, N, (uint64_t)c.gg.g[n - 1], c.rowtab.p,
+                       (int64_t)rows, s);
+      c.rowtab_used = c.rowtab.p;
+    }
+  }
 }
 
 int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_t Mcap_known,
@@ -242,7 +254,8 @@ int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_
   c.rslot.reserve((size_t)Mcap * R);
   c.nrng.reserve(N);
   launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, c.dense_used,
-                         cell_active, c.gg, c.ranges.p, c.rslot.p, c.nrng.p, c.cand_count.p, s);
+                         c.rowtab_used, cell_active, c.gg, c.ranges.p, c.rslot.p, c.nrng.p,
+                         c.cand_count.p, s);
   return Mcap;
 }
 
@@ -262,10 +275,10 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   b += 8 * n * N;                      // Xs
   b += (4 + 4 + 8 + 4 + 4 + 4) * N;    // perm, cell_of, cell_key, cell_start, nrng, cand_count
   b += 17 * R * N;                     // ranges (4 x u32) + rslot
-  if (idx.n > 2) b += std::max<uint64_t>(64 * N, 16ull << 20);  // dense key table
+  b += std::max<uint64_t>(256 * N, 32ull << 20);  // dense key table or row table
   b += (16 + 4 + 4) * N;               // keys, keys2, vals2, flags
   b += (uint64_t)radix_tmp_elems((int64_t)N) * 4;
-  b += (4 + 4 + 1) * N;                // active, fail_list, failed
+  b += (4 + 4 + 1 + 1 + 4) * N;        // active, fail_list, failed, cell_active, heavy
   b += 24 * N;                         // work-item keys and order (at most one item per query)
   b += std::min<uint64_t>(N, 65535) * (512 + cap * 12);  // brute-force tail scratch
   b += 4096;                           // scalars
@@ -332,7 +345,13 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   const int pad = std::max(16, K / 2);
   const int cap = K + pad;
   if (st) st->eps_min = eps_min;
-  const double tail_budget = o.tail_pairs > 0 ? o.tail_pairs : (o.tail_pairs < 0 ? -1.0 : 1.5e9);
+  // brute-force tail budget: with levels this cheap the tail only pays off for
+  // a few hundred queries (it scans all N points per query)
+  const double tuned_tail = o.tail_pairs == 0 ? autotune_tail_pairs(idx.n, K, idx.N) : 0.0;
+  const double tail_budget = o.tail_pairs > 0 ? o.tail_pairs
+                             : o.tail_pairs < 0 ? -1.0
+                             : tuned_tail > 0  ? tuned_tail
+                                               : 2.5e8;
   double diag2 = 0;
   for (int j = 0; j < idx.n; ++j) diag2 += (idx.hi[j] - idx.lo[j]) * (idx.hi[j] - idx.lo[j]);
 
@@ -1010,13 +1029,14 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
     const size_t NK = (size_t)idx->N * K;
     c.out_ids.reserve(NK);
     c.out_d.reserve(NK);
-    auto time_join = [&](double wf, double gr, int lin) {
+    auto time_join = [&](double wf, double gr, int lin, double tp) {
       double best = 1e300;
       for (int rep = 0; rep < 2; ++rep) {
         knn_join_opts o{};
         o.w_factor = wf;
         o.growth = gr;
         o.linear_levels = lin;
+        o.tail_pairs = tp;
         KNN_HIP(hipStreamSynchronize(s));
         auto t0 = std::chrono::steady_clock::now();
         self_join(*idx, c, K, c.out_ids.p, c.out_d.p, o, s);
@@ -1028,39 +1048,46 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
     };
     // Staged search: the level-0 cell side first (default growth, the
     // paper's linear first step), then growth x linear step for the best
-    // side, then the side again around the best at that growth.
+    // side, then the side again around the best at that growth, then the
+    // brute-force tail budget.
     const double n = (double)idx->n;
     const double g16 = std::pow(16.0, 1.0 / n);
+    const double tp0 = 2.5e8;
     std::memset(out, 0, sizeof(*out));
-    out->ms_default = time_join(1.0, g16, 1);
+    out->ms_default = time_join(1.0, g16, 1, tp0);
     out->ms_best = out->ms_default;
     out->w_factor = 1.0;
     out->growth = g16;
     out->linear_levels = 1;
+    out->tail_pairs = tp0;
     out->trials = 1;
-    auto consider = [&](double wf, double gr, int lin) {
-      const double ms = time_join(wf, gr, lin);
+    auto consider = [&](double wf, double gr, int lin, double tp) {
+      const double ms = time_join(wf, gr, lin, tp);
       ++out->trials;
       if (ms < out->ms_best) {
         out->ms_best = ms;
         out->w_factor = wf;
         out->growth = gr;
         out->linear_levels = lin;
+        out->tail_pairs = tp;
       }
     };
-    for (double wf : {0.25, 0.5, 0.7, 1.4, 2.0}) consider(wf, g16, 1);
+    for (double wf : {0.25, 0.5, 0.7, 1.4, 2.0}) consider(wf, g16, 1, tp0);
     const double wf1 = out->w_factor;
     for (double gb : {4.0, 16.0, 64.0})
       for (int lin : {1, -1}) {
         const double gr = std::pow(gb, 1.0 / n);
         if (gb == 16.0 && lin == 1) continue;  // measured in the first stage
-        consider(wf1, gr, lin);
+        consider(wf1, gr, lin, tp0);
       }
     const double gr2 = out->growth;
     const int lin2 = out->linear_levels;
-    for (double f : {0.8, 1.25}) consider(wf1 * f, gr2, lin2);
+    for (double f : {0.8, 1.25}) consider(wf1 * f, gr2, lin2, tp0);
+    const double wf3 = out->w_factor;
+    for (double tp : {6e7, 1e9}) consider(wf3, gr2, lin2, tp);
     autotune_store(idx->n, K, idx->N,
-                   TuneEntry{out->w_factor, out->growth, 0, out->linear_levels > 0 ? 1 : -1});
+                   TuneEntry{out->w_factor, out->growth, 0, out->linear_levels > 0 ? 1 : -1,
+                             out->tail_pairs});
   });
 }
 

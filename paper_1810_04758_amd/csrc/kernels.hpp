@@ -68,6 +68,11 @@ void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags,
 // Xs[j*N + p] = XA[perm[p]*n + j] (XA row-major N x n)
 void launch_gather_soa(const double* XA, const int32_t* perm, int64_t N, int n, double* Xs,
                        hipStream_t s);
+// Row table: for every row of the grid (the cells sharing coordinates
+// 0..n-2, row = key / g_last), [rowtab[row].x, rowtab[row].y) = its
+// non-empty cells (empty rows: 0, 0).  rows entries.
+void launch_row_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N, uint64_t g_last,
+                      uint2* rowtab, int64_t rows, hipStream_t s);
 // Dense key -> cell lookup table (table_size entries, set to ~0 where empty).
 void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N,
                         uint32_t* table, int64_t table_size, hipStream_t s);
@@ -81,7 +86,7 @@ void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N
 // entries are left as they were).
 void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_start,
                             const uint64_t* cell_key, const uint32_t* d_M,
-                            const uint32_t* dense /*nullable*/,
+                            const uint32_t* dense /*nullable*/, const uint2* rowtab /*nullable*/,
                             const uint8_t* cell_active /*nullable*/, const GridGeom& gg,
                             uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
                             uint32_t* cand_count, hipStream_t s);
