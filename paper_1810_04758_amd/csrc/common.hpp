@@ -75,4 +75,26 @@ struct DevBuf {
   size_t bytes() const { return n * sizeof(T); }
 };
 
+// Pinned host memory (for the small per-level read-backs: a copy into
+// pinned memory avoids the staging of pageable destinations).
+template <class T>
+struct HostBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  ~HostBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  void reserve(size_t count) {
+    if (p && count <= n) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    KNN_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), count * sizeof(T), hipHostMallocDefault));
+    n = count;
+  }
+};
+
 }  // namespace knn

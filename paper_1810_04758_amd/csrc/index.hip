@@ -244,10 +244,10 @@ int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_
     if (Mcap_known > 0) {
       Mcap = Mcap_known;
     } else {
-      uint32_t M = 0;
-      KNN_HIP(hipMemcpyAsync(&M, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      c.pinned.reserve(kCounterInts + 16);
+      KNN_HIP(hipMemcpyAsync(c.pinned.p, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));
-      Mcap = std::max<int64_t>(M, 1);
+      Mcap = std::max<int64_t>((uint32_t)c.pinned.p[0], 1);
     }
   }
   c.ranges.reserve((size_t)Mcap * R * 4);
@@ -440,11 +440,14 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       T = rp->T;
     } else {
       launch_active_cand_sum(active, A, c.cell_of.p, c.cand_count.p, c.cand_sum.p, s);
-      uint64_t tot[2] = {0, 0};
-      uint32_t M = 0;
-      KNN_HIP(hipMemcpyAsync(tot, c.cand_sum.p, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-      KNN_HIP(hipMemcpyAsync(&M, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      c.pinned.reserve(kCounterInts + 16);
+      int32_t* hp = c.pinned.p;
+      KNN_HIP(hipMemcpyAsync(hp, c.cand_sum.p, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipMemcpyAsync(hp + 4, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));  // the level's one round trip before the search
+      uint64_t tot[2];
+      std::memcpy(tot, hp, sizeof(tot));
+      const uint32_t M = (uint32_t)hp[4];
       cand = (double)tot[0] / (double)std::max<int64_t>(A, 1);
       cand_max = tot[1];
       c.M = M;
@@ -577,8 +580,10 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       hf = rp->heavy_failed;
       hc = rp->heavy_cand;
     } else {
-      int32_t cnt[kCounterInts];
-      KNN_HIP(hipMemcpyAsync(cnt, c.iscal.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
+      c.pinned.reserve(kCounterInts + 16);
+      int32_t* cnt = c.pinned.p;
+      KNN_HIP(hipMemcpyAsync(cnt, c.iscal.p, kCounterInts * sizeof(int32_t), hipMemcpyDeviceToHost,
+                             s));
       KNN_HIP(hipStreamSynchronize(s));
       sc[0] = cnt[kFailSlot];
       sc[1] = cnt[kRefineSlot];

@@ -68,6 +68,7 @@ struct JoinContext {
   DevBuf<uint8_t> cell_active;  // cells holding an active query (levels > 0)
   const uint32_t* dense_used = nullptr;  // the level's dense key table, if any
   DevBuf<uint2> rowtab;                  // row table (cells of each grid row)
+  HostBuf<int32_t> pinned;               // read-backs of the level loop
   const uint2* rowtab_used = nullptr;
 
   int64_t device_bytes() const;
