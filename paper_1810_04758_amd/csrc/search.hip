@@ -81,13 +81,49 @@ struct Pow3<0> {
   static constexpr int v = 1;
 };
 
-template <int DIM>
+// Coordinates of several candidates, loaded before any is used: a compiler
+// barrier between the loads and the arithmetic keeps them all in flight
+// (left alone, the scheduler waits on the first candidate's loads one by one).
+template <int DIM, bool OFF32, int U>
+__device__ __forceinline__ void sq_dist_batch(const double* __restrict__ const (&Xd)[DIM],
+                                              const uint32_t (&p)[U], const double (&q)[DIM],
+                                              double (&d2)[U]) {
+  double x[U][DIM];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t off = p[u] << 3;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+      x[u][j] = OFF32 ? *reinterpret_cast<const double*>(reinterpret_cast<const char*>(Xd[j]) + off)
+                      : Xd[j][p[u]];
+  }
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      const double t = __dsub_rn(x[u][j], q[j]);
+      s = __dadd_rn(s, __dmul_rn(t, t));
+    }
+    d2[u] = s;
+  }
+}
+
+// OFF32 (8 N < 2^32): the byte offset of a candidate fits 32 bits, so the
+// loads take the form scalar base + 32-bit vector offset (one shift per
+// candidate instead of a 64-bit address per coordinate).
+template <int DIM, bool OFF32>
 __device__ __forceinline__ double sq_dist(const double* __restrict__ const (&Xd)[DIM], uint32_t p,
                                           const double (&q)[DIM]) {
   double s = 0.0;
+  const uint32_t off = p << 3;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    double t = __dsub_rn(Xd[j][p], q[j]);
+    const double x = OFF32 ? *reinterpret_cast<const double*>(
+                                 reinterpret_cast<const char*>(Xd[j]) + off)
+                           : Xd[j][p];
+    double t = __dsub_rn(x, q[j]);
     s = __dadd_rn(s, __dmul_rn(t, t));
   }
   return s;
@@ -285,8 +321,9 @@ __device__ __forceinline__ void flush_failures(const SearchArgs& a, const int32_
   wave_fence();
 }
 
-template <int DIM, int T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_search(const SearchArgs a) {
+template <int DIM, int T, bool OFF32>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_search(const SearchArgs a) {
   constexpr int G = 64 / T;  // queries per wave
   constexpr int R = Pow3<DIM - 1>::v;
   constexpr int P = NB / T;  // count bins owned by each lane of a group
@@ -428,8 +465,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
           p[u] = vv < C ? cs.pos(vv) : q32;
         }
         double d2[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) d2[u] = sq_dist<DIM>(Xd, p[u], qx);
+        sq_dist_batch<DIM, OFF32, kUnroll>(Xd, p, qx, d2);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int b = bin_of<DIM>(d2[u], thr, top);
@@ -509,7 +545,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         for (uint32_t v = l; v < Cr; v += T) {
           const uint32_t p = cs.pos(v);
           if (p != q32) {
-            const double d2 = sq_dist<DIM>(Xd, p, qx);
+            const double d2 = sq_dist<DIM, OFF32>(Xd, p, qx);
             if (bin_of<DIM>(d2, thr, top) == bsel) {
               dmin = fmin(dmin, d2);
               dmax = fmax(dmax, d2);
@@ -539,7 +575,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
           for (uint32_t v = l; v < Cr; v += T) {
             const uint32_t p = cs.pos(v);
             if (p != q32) {
-              const double d2 = sq_dist<DIM>(Xd, p, qx);
+              const double d2 = sq_dist<DIM, OFF32>(Xd, p, qx);
               const uint64_t kh = (uint64_t)__double_as_longlong(d2);
               if (kh >= ahi && kh <= bhi) {
                 const unsigned __int128 k = ((unsigned __int128)kh << 32) | (uint32_t)perm[p];
@@ -586,8 +622,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
           pp[u] = vv < C ? cs.pos(vv) : q32;
         }
         double dd[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) dd[u] = sq_dist<DIM>(Xd, pp[u], qx);
+        sq_dist_batch<DIM, OFF32, kUnroll>(Xd, pp, qx, dd);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t p = pp[u];
@@ -729,7 +764,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         }
         double d2[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) d2[u] = sq_dist<DIM>(Xd, p[u], qx);
+        for (int u = 0; u < kUnroll; ++u) d2[u] = sq_dist<DIM, false>(Xd, p[u], qx);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const int b = bin_of<DIM>(d2[u], thr, top);
@@ -785,7 +820,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         for (uint32_t v = tid; v < C; v += NT) {
           const uint32_t p = cs.pos(v);
           if (p != q32) {
-            const double d2 = sq_dist<DIM>(Xd, p, qx);
+            const double d2 = sq_dist<DIM, false>(Xd, p, qx);
             if (bin_of<DIM>(d2, thr, top) == bsel) {
               const unsigned long long kb = (unsigned long long)__double_as_longlong(d2);
               mn = min(mn, kb);
@@ -818,7 +853,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
           for (uint32_t v = tid; v < C; v += NT) {
             const uint32_t p = cs.pos(v);
             if (p != q32) {
-              const double d2 = sq_dist<DIM>(Xd, p, qx);
+              const double d2 = sq_dist<DIM, false>(Xd, p, qx);
               const uint64_t kh = (uint64_t)__double_as_longlong(d2);
               if (kh >= ahi && kh <= bhi) {
                 const unsigned __int128 k = ((unsigned __int128)kh << 32) | (uint32_t)perm[p];
@@ -866,7 +901,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         }
         double dd[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) dd[u] = sq_dist<DIM>(Xd, pp[u], qx);
+        for (int u = 0; u < kUnroll; ++u) dd[u] = sq_dist<DIM, false>(Xd, pp[u], qx);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t p = pp[u];
@@ -918,7 +953,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
 template <int DIM, int T>
 int occupancy_of(int threads, size_t lds) {
   int n = 0;
-  KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<DIM, T>, threads, lds));
+  KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<DIM, T, true>, threads, lds));
   return n;
 }
 
@@ -935,18 +970,27 @@ int occupancy_dim(int T, int threads, size_t lds) {
   }
 }
 
-template <int DIM>
-void launch_dim(const SearchArgs& a, int T, int blocks, int threads, size_t lds, hipStream_t s) {
+template <int DIM, bool OFF32>
+void launch_dim_off(const SearchArgs& a, int T, int blocks, int threads, size_t lds,
+                    hipStream_t s) {
   switch (T) {
-    case 1: k_search<DIM, 1><<<blocks, threads, lds, s>>>(a); break;
-    case 2: k_search<DIM, 2><<<blocks, threads, lds, s>>>(a); break;
-    case 4: k_search<DIM, 4><<<blocks, threads, lds, s>>>(a); break;
-    case 8: k_search<DIM, 8><<<blocks, threads, lds, s>>>(a); break;
-    case 16: k_search<DIM, 16><<<blocks, threads, lds, s>>>(a); break;
-    case 32: k_search<DIM, 32><<<blocks, threads, lds, s>>>(a); break;
-    case 64: k_search<DIM, 64><<<blocks, threads, lds, s>>>(a); break;
+    case 1: k_search<DIM, 1, OFF32><<<blocks, threads, lds, s>>>(a); break;
+    case 2: k_search<DIM, 2, OFF32><<<blocks, threads, lds, s>>>(a); break;
+    case 4: k_search<DIM, 4, OFF32><<<blocks, threads, lds, s>>>(a); break;
+    case 8: k_search<DIM, 8, OFF32><<<blocks, threads, lds, s>>>(a); break;
+    case 16: k_search<DIM, 16, OFF32><<<blocks, threads, lds, s>>>(a); break;
+    case 32: k_search<DIM, 32, OFF32><<<blocks, threads, lds, s>>>(a); break;
+    case 64: k_search<DIM, 64, OFF32><<<blocks, threads, lds, s>>>(a); break;
     default: throw Error(KNN_EINVAL, "lanes_per_query must be a power of two in [1, 64]");
   }
+}
+
+template <int DIM>
+void launch_dim(const SearchArgs& a, int T, int blocks, int threads, size_t lds, hipStream_t s) {
+  if (a.N < ((int64_t)1 << 29))
+    launch_dim_off<DIM, true>(a, T, blocks, threads, lds, s);
+  else
+    launch_dim_off<DIM, false>(a, T, blocks, threads, lds, s);
 }
 
 }  // namespace
