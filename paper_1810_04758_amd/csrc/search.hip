@@ -64,10 +64,16 @@ struct BinShift {
 };
 constexpr int NB2 = 32;        // bins of one exact-bisection round
 constexpr int kLog2NB2 = 5;
-// candidates per lane in flight in the count/collect walks (fewer in 5-6
-// dimensions, whose coordinates take more registers)
+// Candidates per lane in flight in the count/collect walks and the waves per
+// SIMD the register budget is set for (measured on MI355X: 2-4 dimensions are
+// best at 4 in flight with 4 waves per SIMD, 5-6 dimensions, whose L2 hit
+// rate is low, at 4 in flight with 2 waves and the registers that frees).
 template <int DIM>
 struct Unroll {
+  static constexpr int v = 4;
+};
+template <int DIM>
+struct WavesPerEu {
   static constexpr int v = DIM <= 4 ? 4 : 2;
 };
 constexpr int kFailBuf = 64;   // failed ids buffered per wavefront before one global append
@@ -322,7 +328,7 @@ __device__ __forceinline__ void flush_failures(const SearchArgs& a, const int32_
 }
 
 template <int DIM, int T, bool OFF32>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEu<DIM>::v)))
 k_search(const SearchArgs a) {
   constexpr int G = 64 / T;  // queries per wave
   constexpr int R = Pow3<DIM - 1>::v;
