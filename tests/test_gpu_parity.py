@@ -154,7 +154,8 @@ def test_figures_through_gpu(knn, oracle_mod):
             assert ids[0, :kk].tolist() == p["knn_ids_of_query"]
 
 
-@pytest.mark.parametrize("case", ["dups", "all_same", "n2", "lattice", "kmax", "line"])
+@pytest.mark.parametrize("case", ["dups", "all_same", "n2", "lattice", "kmax", "line",
+                                  "outliers3d", "outliers4d", "outliers2d"])
 def test_edge_cases(knn, oracle_mod, case):
     if case == "dups":
         base = datagen.uniform(300, 2, seed=40)
@@ -172,6 +173,15 @@ def test_edge_cases(knn, oracle_mod, case):
     elif case == "kmax":
         D = datagen.uniform(300, 2, seed=41)
         K = 299
+    elif case.startswith("outliers"):
+        # a small dense cube and a few points 1e4 away: the grid has far more
+        # rows than points (and cells than the key space allows at first), so
+        # neighbour ranges come from binary search over the cell keys rather
+        # than a dense or row table
+        n = int(case[-2])
+        D = datagen.uniform(3000, n, seed=44) / 100.0
+        D = np.concatenate([D, np.full((3, n), 1e4) + np.arange(3)[:, None]])
+        K = 5
     else:  # all points on a line (zero extent in one dimension)
         D = np.zeros((1000, 2))
         D[:, 0] = np.linspace(0, 1, 1000) ** 2
