@@ -42,33 +42,56 @@ constexpr int kWave = 64;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Device buffer owned by RAII.
+// Device memory cache, per device.  A released block goes back to the cache
+// and is handed out again to a request of at least half its size.  Every
+// user releases memory only after the device work that used it has finished
+// (the library's calls return after their work; an asynchronous graph replay
+// is waited for before its scratch is released), so a reused block needs no
+// stream ordering.  At most KNN_DEVICE_CACHE_BYTES (default 32 GiB) per device
+// is kept; the cache is emptied and the allocation retried when hipMalloc
+// runs out of memory.
+void* device_acquire(size_t bytes, int* device, size_t* capacity);
+void device_release(void* p, int device, size_t capacity);
+
+// Device buffer owned by RAII (memory from the device cache).
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  int dev = -1;
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), dev(o.dev) {
+    o.p = nullptr;
+    o.n = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      dev = o.dev;
+      o.p = nullptr;
+      o.n = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t count) {
     release();
     if (count == 0) count = 1;
-    KNN_HIP(hipMalloc(&p, count * sizeof(T)));
-    n = count;
+    size_t cap = 0;
+    p = static_cast<T*>(device_acquire(count * sizeof(T), &dev, &cap));
+    n = cap / sizeof(T);
   }
   // Grow to at least `count` elements (contents not preserved).
   void reserve(size_t count) {
     if (count > n || p == nullptr) alloc(count);
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) device_release(p, dev, n * sizeof(T));
     p = nullptr;
     n = 0;
   }

@@ -1,0 +1,86 @@
+// pool.hip -- the device memory cache behind DevBuf (see common.hpp).
+#include <cstdlib>
+#include <map>
+#include <mutex>
+
+#include "common.hpp"
+
+namespace knn {
+
+namespace {
+
+struct Pool {
+  std::multimap<size_t, void*> free;  // capacity -> block
+  size_t cached = 0;
+};
+
+std::mutex g_mu;
+std::map<int, Pool> g_pools;
+
+size_t cache_limit() {
+  static const size_t lim = [] {
+    const char* e = std::getenv("KNN_DEVICE_CACHE_BYTES");
+    return e ? (size_t)std::strtoull(e, nullptr, 10) : (size_t)32 << 30;
+  }();
+  return lim;
+}
+
+// Requests are rounded so that sizes that differ a little share blocks.
+size_t round_up(size_t b) {
+  const size_t g = b < ((size_t)1 << 20) ? 256 : ((size_t)1 << 20);
+  return (b + g - 1) / g * g;
+}
+
+void drain_locked(Pool& pl) {
+  for (auto& kv : pl.free) (void)hipFree(kv.second);
+  pl.free.clear();
+  pl.cached = 0;
+}
+
+}  // namespace
+
+void* device_acquire(size_t bytes, int* device, size_t* capacity) {
+  const size_t want = round_up(bytes == 0 ? 1 : bytes);
+  int dev = 0;
+  KNN_HIP(hipGetDevice(&dev));
+  *device = dev;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Pool& pl = g_pools[dev];
+    auto it = pl.free.lower_bound(want);
+    if (it != pl.free.end() && it->first <= 2 * want) {
+      void* p = it->second;
+      *capacity = it->first;
+      pl.cached -= it->first;
+      pl.free.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      drain_locked(g_pools[dev]);
+    }
+    e = hipMalloc(&p, want);
+  }
+  KNN_HIP(e);
+  *capacity = want;
+  return p;
+}
+
+void device_release(void* p, int device, size_t capacity) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Pool& pl = g_pools[device];
+  if (pl.cached + capacity > cache_limit()) {
+    (void)hipFree(p);
+    return;
+  }
+  pl.free.emplace(capacity, p);
+  pl.cached += capacity;
+}
+
+}  // namespace knn
