@@ -125,6 +125,11 @@ typedef struct knn_join_opts {
   int32_t item_order;     /* persistent schedule: 0 = densest class first inside
                              each XCD's contiguous chunk (Sec. 4.5 ordering);
                              1 = cell order [0] */
+  int32_t share_lists;    /* 1: the queries of a wavefront that share a cell walk
+                             one candidate list (the union of their pruned
+                             lists), so every load serves all of them; -1: each
+                             query walks its own; 0 = automatic [1 in 5-6
+                             dimensions, whose search is bound by the L2] */
   knn_join_stats* stats;  /* optional statistics output */
 } knn_join_opts;
 

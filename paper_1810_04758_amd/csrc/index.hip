@@ -512,6 +512,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     for (int x = 0; x <= kXcds; ++x)  // queue x: items of chunk x (ceil(x * n_items / 8) onwards)
       a.qbeg[x] = (x * n_items + kXcds - 1) / kXcds;
     a.persistent = o.schedule == 0 ? 1 : 0;
+    a.share_lists = o.share_lists > 0 ? 1 : (o.share_lists < 0 ? 0 : (idx.n >= 5 ? 1 : 0));
     for (int j = 0; j < kMaxDims; ++j) {
       a.lo[j] = c.gg.lo[j];
       a.g[j] = c.gg.g[j];
@@ -526,6 +527,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.fail_list = c.fail_list.p;
     a.fail_count = c.iscal.p + kFailSlot;
     a.refine_count = c.iscal.p + kRefineSlot;
+    a.walk_error = c.iscal.p + kWalkErrSlot;
     lp.heavy_min = heavy_min;
     if (heavy_min > 0) {
       // heavy queries first, one workgroup each (count stays on the device)
@@ -585,6 +587,8 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       KNN_HIP(hipMemcpyAsync(cnt, c.iscal.p, kCounterInts * sizeof(int32_t), hipMemcpyDeviceToHost,
                              s));
       KNN_HIP(hipStreamSynchronize(s));
+      KNN_CHECK(cnt[kWalkErrSlot] == 0, KNN_EINTERNAL,
+                "search: a candidate list was inconsistent with its count");
       sc[0] = cnt[kFailSlot];
       sc[1] = cnt[kRefineSlot];
       hq = cnt[kHeavySlot];
@@ -654,7 +658,7 @@ bool GraphPlan::matches(int32_t K_, const knn_join_opts& o, int32_t* ids_, doubl
          opts.eps_step == o.eps_step && opts.linear_levels == o.linear_levels &&
          opts.growth == o.growth && opts.tail_pairs == o.tail_pairs &&
          opts.heavy_min == o.heavy_min && opts.queue_grain == o.queue_grain &&
-         opts.item_order == o.item_order;
+         opts.item_order == o.item_order && opts.share_lists == o.share_lists;
 }
 
 GraphPlan::~GraphPlan() {

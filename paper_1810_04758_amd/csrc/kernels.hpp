@@ -17,7 +17,8 @@ constexpr int kRefineSlot = kFailSlot + kLineInts;   // refinement rounds (diagn
 constexpr int kHeavySlot = kRefineSlot + kLineInts;  // heavy queries
 constexpr int kHeavyFailSlot = kHeavySlot + kLineInts;      // of which failed (diagnostics)
 constexpr int kHeavyCandSlot = kHeavyFailSlot + kLineInts;  // their candidates (uint64)
-constexpr int kCounterInts = kHeavyCandSlot + kLineInts;
+constexpr int kWalkErrSlot = kHeavyCandSlot + kLineInts;    // candidate-list overruns
+constexpr int kCounterInts = kWalkErrSlot + kLineInts;
 
 // Geometry of one grid level (Sec. 3.1): cell side 1/inv_w, origin lo.
 struct GridGeom {
@@ -151,6 +152,7 @@ struct SearchArgs {
   int64_t qbeg[kXcds + 1]; // queue x = order positions [qbeg[x], qbeg[x+1])
   int32_t grain;           // items claimed per queue pop
   int32_t persistent;
+  int32_t share_lists;     // wavefronts whose queries share a cell walk one list
   double lo[kMaxDims];
   double inv_w;
   double w;                // fl(1 / inv_w)
@@ -167,6 +169,7 @@ struct SearchArgs {
   const int32_t* heavy;    // to k_search_heavy: their sorted positions
   const int32_t* n_heavy;  // and their number (device)
   int32_t* heavy_fail;     // failures among them (diagnostics)
+  int32_t* walk_error;     // candidate-list walks that ran past their list (must stay 0)
 };
 // Returns the number of waves per block used.
 void launch_search(const SearchArgs& a, int dims, int lanes_per_query, int grid_blocks,

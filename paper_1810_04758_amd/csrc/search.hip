@@ -238,7 +238,7 @@ __device__ __forceinline__ uint32_t build_list(const uint32_t* __restrict__ rg,
                                                const uint8_t* __restrict__ rs, int nr, int nr_w,
                                                bool prune, double lim, const double (&qx)[DIM],
                                                const SearchArgs& a, int l, uint32_t* seg_st,
-                                               uint32_t* seg_ve) {
+                                               uint32_t* seg_ve, bool shared, uint32_t& nent) {
   // face distances (recomputed here rather than kept live through the passes)
   double flo[DIM], fhi[DIM];
 #pragma unroll
@@ -270,6 +270,18 @@ __device__ __forceinline__ uint32_t build_list(const uint32_t* __restrict__ rg,
         }
       }
     }
+    if (shared) {
+      // every group of the wavefront has the same cell: keep the union of
+      // their ranges, so all groups walk one list and each load serves them all
+      uint32_t lo = len ? st : 0xFFFFFFFFu, hi = len ? st + len : 0u;
+#pragma unroll
+      for (int o = T; o < 64; o <<= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+      }
+      st = lo;
+      len = hi > lo ? hi - lo : 0u;
+    }
     const uint32_t keep = len > 0 ? 1u : 0u;
     uint32_t ik = keep, il = len;
 #pragma unroll
@@ -288,26 +300,38 @@ __device__ __forceinline__ uint32_t build_list(const uint32_t* __restrict__ rg,
     cnt += __shfl(ik, T - 1, T);
     total += __shfl(il, T - 1, T);
   }
+  nent = cnt;
   return total;
 }
 
-// Walk over a list: virtual candidate v (non-decreasing from call to call,
-// below the list's count) -> sorted position.
+// Walk over a list of n entries: virtual candidate v (non-decreasing from
+// call to call, below the list's count) -> sorted position.  A walk that
+// would run past the last entry (a list inconsistent with its count) stops
+// there, flags `bad` and returns an in-bounds position; the kernel reports
+// it and the join fails with an error.
 struct LWalk {
   const uint32_t* st;
   const uint32_t* ve;
-  int r;
+  int r, n;
   uint32_t vs, vend, s0;
-  __device__ __forceinline__ void init(const uint32_t* st_, const uint32_t* ve_, uint32_t C) {
+  bool bad;
+  __device__ __forceinline__ void init(const uint32_t* st_, const uint32_t* ve_, uint32_t C,
+                                       uint32_t nent) {
     st = st_;
     ve = ve_;
     r = 0;
+    n = (int)nent;
     vs = 0;
-    vend = C > 0 ? ve[0] : 0u;
-    s0 = C > 0 ? st[0] : 0u;
+    bad = false;
+    vend = (C > 0 && nent > 0) ? ve[0] : 0u;
+    s0 = (C > 0 && nent > 0) ? st[0] : 0u;
   }
   __device__ __forceinline__ uint32_t pos(uint32_t v) {
     while (v >= vend) {
+      if (r + 1 >= n) {
+        bad = true;
+        return s0;
+      }
       ++r;
       vs = vend;
       vend = ve[r];
@@ -316,6 +340,11 @@ struct LWalk {
     return s0 + (v - vs);
   }
 };
+
+// A walk that ran past its list: counted on the device, the join then fails.
+__device__ __forceinline__ void report_walk(const SearchArgs& a, const LWalk& cs) {
+  if (cs.bad) atomicAdd(a.walk_error, 1);
+}
 
 // Appends the wavefront's buffered failed ids to the global failure list.
 __device__ __forceinline__ void flush_failures(const SearchArgs& a, const int32_t* fbuf, int nfail,
@@ -454,14 +483,28 @@ k_search(const SearchArgs a) {
     int nr_w = nr;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) nr_w = max(nr_w, __shfl_xor(nr_w, o, 64));
+    // one candidate list for the whole wavefront when all its queries share a
+    // cell (lists of queries of one cell differ only by pruning)
+    bool shared = false;
+    if (a.share_lists && G > 1) {
+      uint32_t cmin = valid ? cell : 0xFFFFFFFFu, cmax = valid ? cell : 0u;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        cmin = min(cmin, (uint32_t)__shfl_xor((int)cmin, o, 64));
+        cmax = max(cmax, (uint32_t)__shfl_xor((int)cmax, o, 64));
+      }
+      shared = cmin == cmax;
+    }
 
     // ---- count pass over the segments that can hold a point within thr -----
-    uint32_t C = build_list<DIM, T>(rg, rs, nr, nr_w, !full, thr, qx, a, l, seg_st, seg_ve);
+    uint32_t nent = 0;
+    uint32_t C = build_list<DIM, T>(rg, rs, nr, nr_w, !full, thr, qx, a, l, seg_st, seg_ve,
+                                    shared, nent);
     for (int b = l; b < NB; b += T) hist[b * G + g] = 0;
     wave_fence();
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, C);
+      cs.init(seg_st, seg_ve, C, nent);
       for (uint32_t v = l; v < C; v += T * kUnroll) {
         // positions first, then all coordinate loads in flight together
         uint32_t p[kUnroll];
@@ -478,6 +521,7 @@ k_search(const SearchArgs a) {
           if (p[u] != q32 && b < NB) atomicAdd(&hist[b * G + g], 1u);
         }
       }
+      report_walk(a, cs);
     }
     wave_fence();
 
@@ -529,7 +573,8 @@ k_search(const SearchArgs a) {
 
     // ---- list for the remaining passes: only bins up to the selected one ----
     const double lim2 = ok ? bins_limit<DIM>(bsel, thr, top) : 0.0;
-    C = build_list<DIM, T>(rg, rs, ok ? nr : 0, nr_w, true, lim2, qx, a, l, seg_st, seg_ve);
+    C = build_list<DIM, T>(rg, rs, ok ? nr : 0, nr_w, true, lim2, qx, a, l, seg_st, seg_ve,
+                           shared, nent);
     wave_fence();
 
     // ---- exact refinement when the selected bin overflows the buffer -------
@@ -546,7 +591,7 @@ k_search(const SearchArgs a) {
       double dmin = INFINITY, dmax = -INFINITY;
       {
         LWalk cs;
-        cs.init(seg_st, seg_ve, C);
+        cs.init(seg_st, seg_ve, C, nent);
         const uint32_t Cr = refine ? C : 0u;
         for (uint32_t v = l; v < Cr; v += T) {
           const uint32_t p = cs.pos(v);
@@ -558,6 +603,7 @@ k_search(const SearchArgs a) {
             }
           }
         }
+        report_walk(a, cs);
       }
       dmin = group_min<T>(dmin);
       dmax = group_max<T>(dmax);
@@ -576,7 +622,7 @@ k_search(const SearchArgs a) {
         {
           const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
           LWalk cs;
-          cs.init(seg_st, seg_ve, C);
+          cs.init(seg_st, seg_ve, C, nent);
           const uint32_t Cr = refine ? C : 0u;
           for (uint32_t v = l; v < Cr; v += T) {
             const uint32_t p = cs.pos(v);
@@ -589,10 +635,12 @@ k_search(const SearchArgs a) {
               }
             }
           }
+          report_walk(a, cs);
         }
         wave_fence();
         if (refine) {
           int cum = c_lo;
+          bool found = false;
           for (int b = 0; b < NB2; ++b) {
             const int h = (int)hist2[b * G + g];
             if (cum + h >= K) {
@@ -602,11 +650,20 @@ k_search(const SearchArgs a) {
               B = nB < B ? nB : B;
               c_lo = cum;
               c_hi = cum + h;
+              found = true;
               break;
             }
             cum += h;
           }
-          if (c_hi <= cap) refine = false;
+          // The counts of [A, B] always reach K, and a single-key interval
+          // holds at most one candidate (so c_hi <= K there); otherwise the
+          // passes disagreed: stop and report instead of looping.
+          if (c_hi <= cap) {
+            refine = false;
+          } else if (!found || A == B) {
+            refine = false;
+            if (l == 0) atomicAdd(a.walk_error, 1);
+          }
         }
         wave_fence();
       }
@@ -619,7 +676,7 @@ k_search(const SearchArgs a) {
     wave_fence();
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, C);
+      cs.init(seg_st, seg_ve, C, nent);
       for (uint32_t v = l; v < C; v += T * kUnroll) {
         uint32_t pp[kUnroll];
 #pragma unroll
@@ -639,7 +696,9 @@ k_search(const SearchArgs a) {
             acc = d2 < th_d || (d2 == th_d && (th_id == 0xFFFFFFFFu || (uint32_t)perm[p] <= th_id));
           else
             acc = b <= bsel;
-          if (p != q32 && acc) {
+          // only queries that selected a bin collect: a failed or empty slot
+          // walking a shared list has bsel == NB, and bin NB is not a bucket
+          if (ok && p != q32 && acc) {
             const uint32_t s = atomicAdd(&hist[b * G + g], 1u);
             if ((int)s < cap) {
               bd[s * G + g] = d2;
@@ -648,6 +707,7 @@ k_search(const SearchArgs a) {
           }
         }
       }
+      report_walk(a, cs);
     }
     wave_fence();
 
@@ -701,7 +761,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
   __shared__ uint32_t hist2[NB2];
   __shared__ uint32_t seg_st[R], seg_ve[R];
   __shared__ int s_bsel, s_clo, s_chi, s_refine;
-  __shared__ uint32_t s_C;
+  __shared__ uint32_t s_C, s_nent;
   __shared__ unsigned long long s_dmin, s_dmax;
   __shared__ unsigned __int128 s_A, s_B;
   const int tid = threadIdx.x;
@@ -751,16 +811,21 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
 
     // ---- count pass
     if (tid < 64) {
-      const uint32_t C0 =
-          build_list<DIM, 64>(rg, rs, nr, nr, !full, thr, qx, a, tid, seg_st, seg_ve);
-      if (tid == 0) s_C = C0;
+      uint32_t ne = 0;
+      const uint32_t C0 = build_list<DIM, 64>(rg, rs, nr, nr, !full, thr, qx, a, tid, seg_st,
+                                              seg_ve, false, ne);
+      if (tid == 0) {
+        s_C = C0;
+        s_nent = ne;
+      }
       hist[tid] = 0;  // NB == 64
     }
     __syncthreads();
     uint32_t C = s_C;
+    uint32_t nent = s_nent;
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, C);
+      cs.init(seg_st, seg_ve, C, nent);
       for (uint32_t v = tid; v < C; v += NT * kUnroll) {
         uint32_t p[kUnroll];
 #pragma unroll
@@ -777,6 +842,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
           if (p[u] != q32 && b < NB) atomicAdd(&hist[b], 1u);
         }
       }
+      report_walk(a, cs);
     }
     __syncthreads();
 
@@ -809,12 +875,17 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
 
     // ---- list of the remaining passes
     if (tid < 64) {
+      uint32_t ne = 0;
       const uint32_t C1 = build_list<DIM, 64>(rg, rs, nr, nr, true, bins_limit<DIM>(bsel, thr, top),
-                                              qx, a, tid, seg_st, seg_ve);
-      if (tid == 0) s_C = C1;
+                                              qx, a, tid, seg_st, seg_ve, false, ne);
+      if (tid == 0) {
+        s_C = C1;
+        s_nent = ne;
+      }
     }
     __syncthreads();
     C = s_C;
+    nent = s_nent;
 
     // ---- exact refinement when the selected bin overflows the buffer
     const bool refined = s_chi > cap;
@@ -822,7 +893,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
       {
         unsigned long long mn = ~0ull, mx = 0ull;
         LWalk cs;
-        cs.init(seg_st, seg_ve, C);
+        cs.init(seg_st, seg_ve, C, nent);
         for (uint32_t v = tid; v < C; v += NT) {
           const uint32_t p = cs.pos(v);
           if (p != q32) {
@@ -836,6 +907,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         }
         if (mn != ~0ull) atomicMin(&s_dmin, mn);
         if (mx != 0ull) atomicMax(&s_dmax, mx);
+        report_walk(a, cs);
       }
       __syncthreads();
       if (tid == 0) {
@@ -855,7 +927,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         {
           const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
           LWalk cs;
-          cs.init(seg_st, seg_ve, C);
+          cs.init(seg_st, seg_ve, C, nent);
           for (uint32_t v = tid; v < C; v += NT) {
             const uint32_t p = cs.pos(v);
             if (p != q32) {
@@ -867,10 +939,12 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
               }
             }
           }
+          report_walk(a, cs);
         }
         __syncthreads();
         if (tid == 0) {
           int cum = s_clo;
+          bool found = false;
           for (int b = 0; b < NB2; ++b) {
             const int h = (int)hist2[b];
             if (cum + h >= K) {
@@ -880,11 +954,17 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
               s_B = nB < B ? nB : B;
               s_clo = cum;
               s_chi = cum + h;
+              found = true;
               break;
             }
             cum += h;
           }
-          if (s_chi <= cap) s_refine = 0;
+          if (s_chi <= cap) {
+            s_refine = 0;
+          } else if (!found || s_A == s_B) {
+            s_refine = 0;
+            atomicAdd(a.walk_error, 1);
+          }
         }
         __syncthreads();
       }
@@ -897,7 +977,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
     // ---- collect pass
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, C);
+      cs.init(seg_st, seg_ve, C, nent);
       for (uint32_t v = tid; v < C; v += NT * kUnroll) {
         uint32_t pp[kUnroll];
 #pragma unroll
@@ -927,6 +1007,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
           }
         }
       }
+      report_walk(a, cs);
     }
     __syncthreads();
 

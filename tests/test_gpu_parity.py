@@ -348,3 +348,18 @@ def test_heavy_queries(knn, oracle_mod, name, gen, K, heavy_min):
         assert st["heavy_failed"] == st["failed"]
     if heavy_min == -1:
         assert not any(st["heavy_queries"])
+
+
+@pytest.mark.parametrize("share", [1, -1])
+@pytest.mark.parametrize("name,gen,K,lanes", [
+    ("unif6d_t4", lambda: datagen.uniform(6000, 6, seed=51), 12, 4),
+    ("expo4d_t8", lambda: datagen.exponential(9000, 4, seed=52), 20, 8),
+    ("clus2d_t2", lambda: datagen.clustered(8000, seed=53), 9, 2),
+], ids=["unif6d_t4", "expo4d_t8", "clus2d_t2"])
+def test_shared_lists(knn, oracle_mod, share, name, gen, K, lanes):
+    """Wavefronts whose queries share a cell walking one (union) list, or each
+    query its own: the oracle's result either way."""
+    D = gen()
+    _say(f"[share] {name} share={share} lanes={lanes}")
+    ids, dists, st = _join(knn, D, K, share_lists=share, lanes_per_query=lanes)
+    _check_rows(D, ids, dists, K, np.arange(D.shape[0]), oracle_mod)
