@@ -315,7 +315,7 @@ def main():
                 tuned.append(dict(dataset=name, K=K, w_factor=round(r["w_factor"], 3),
                                   growth=round(r["growth"], 4),
                                   linear_levels=int(r["linear_levels"]), trials=int(r["trials"]),
-                                  tail_pairs=r["tail_pairs"],
+                                  tail_pairs=r["tail_pairs"], lanes_shift=int(r["lanes_shift"]),
                                   ms_default=round(r["ms_default"], 3),
                                   ms_tuned=round(r["ms_best"], 3)))
             idx.close()

@@ -125,6 +125,8 @@ typedef struct knn_join_opts {
   int32_t item_order;     /* persistent schedule: 0 = densest class first inside
                              each XCD's contiguous chunk (Sec. 4.5 ordering);
                              1 = cell order [0] */
+  int32_t lanes_shift;    /* automatic lanes per query times 2^lanes_shift (-2..2)
+                             [autotuned or 0] */
   int32_t share_lists;    /* 1: the queries of a wavefront that share a cell walk
                              one candidate list (the union of their pruned
                              lists), so every load serves all of them; -1: each
@@ -220,11 +222,13 @@ typedef struct knn_autotune_result {
   int32_t linear_levels; /* chosen linear growths before the geometric ones
                             (0 or 1; -1 in the cache means none) */
   double tail_pairs;     /* chosen brute-force tail budget (pairs) */
+  int32_t lanes_shift;   /* chosen shift of the lanes-per-query rule (x 2^shift) */
 } knn_autotune_result;
 /* Runs on `stream` (device scratch allocated internally); blocks. */
 int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* out);
 /* Save / load the cache as text ("dims kbucket nbucket w_factor growth
- * lanes linear tail_pairs" per line); path NULL = $KNN_AUTOTUNE_CACHE. */
+ * lanes linear tail_pairs lanes_shift" per line); path NULL =
+ * $KNN_AUTOTUNE_CACHE. */
 int knn_autotune_save(const char* path);
 int knn_autotune_load(const char* path);
 

@@ -68,7 +68,8 @@ class JoinOpts(ctypes.Structure):
                 ("schedule", c_i32), ("batch_queries", c_i32), ("eps_step", c_f64),
                 ("linear_levels", c_i32), ("growth", c_f64), ("use_graph", c_i32),
                 ("tail_pairs", c_f64), ("heavy_min", ctypes.c_int64),
-                ("queue_grain", c_i32), ("item_order", c_i32), ("share_lists", c_i32),
+                ("queue_grain", c_i32), ("item_order", c_i32), ("lanes_shift", c_i32),
+                ("share_lists", c_i32),
                 ("stats", ctypes.POINTER(JoinStats))]
 
 
@@ -82,7 +83,7 @@ class IndexInfo(ctypes.Structure):
 class AutotuneResult(ctypes.Structure):
     _fields_ = [("w_factor", c_f64), ("growth", c_f64), ("ms_best", c_f64),
                 ("ms_default", c_f64), ("trials", c_i32), ("linear_levels", c_i32),
-                ("tail_pairs", c_f64)]
+                ("tail_pairs", c_f64), ("lanes_shift", c_i32)]
 
 
 class ServerOpts(ctypes.Structure):

@@ -35,11 +35,11 @@ void load_file_locked(const char* p) {
   if (!p || !*p) return;
   FILE* f = std::fopen(p, "r");
   if (!f) return;
-  int d, kb, nb, lanes, lin;
+  int d, kb, nb, lanes, lin, ls;
   double wf, gr, tp;
-  while (std::fscanf(f, "%d %d %d %lf %lf %d %d %lf", &d, &kb, &nb, &wf, &gr, &lanes, &lin, &tp) ==
-         8)
-    g_cache[Class(d, kb, nb)] = TuneEntry{wf, gr, lanes, lin, tp};
+  while (std::fscanf(f, "%d %d %d %lf %lf %d %d %lf %d", &d, &kb, &nb, &wf, &gr, &lanes, &lin, &tp,
+                     &ls) == 9)
+    g_cache[Class(d, kb, nb)] = TuneEntry{wf, gr, lanes, lin, tp, ls};
   std::fclose(f);
 }
 
@@ -73,6 +73,10 @@ double autotune_tail_pairs(int dims, int K, int64_t N) {
   return autotune_get(dims, K, N).tail_pairs;
 }
 
+int autotune_lanes_shift(int dims, int K, int64_t N) {
+  return autotune_get(dims, K, N).lanes_shift;
+}
+
 void autotune_store(int dims, int K, int64_t N, const TuneEntry& e) {
   std::lock_guard<std::mutex> lk(g_mu);
   ensure_loaded_locked();
@@ -98,9 +102,10 @@ int autotune_save(const char* path) {
   FILE* f = std::fopen(p, "w");
   if (!f) return -1;
   for (auto& kv : g_cache)
-    std::fprintf(f, "%d %d %d %.17g %.17g %d %d %.17g\n", std::get<0>(kv.first),
+    std::fprintf(f, "%d %d %d %.17g %.17g %d %d %.17g %d\n", std::get<0>(kv.first),
                  std::get<1>(kv.first), std::get<2>(kv.first), kv.second.w_factor,
-                 kv.second.growth, kv.second.lanes, kv.second.linear, kv.second.tail_pairs);
+                 kv.second.growth, kv.second.lanes, kv.second.linear, kv.second.tail_pairs,
+                 kv.second.lanes_shift);
   std::fclose(f);
   return 0;
 }

@@ -15,6 +15,7 @@ struct TuneEntry {
   int lanes;        // 0 = chosen per level from the candidate counts
   int linear = 0;   // linear growths: 0 = not measured (default), 1, or -1 (none)
   double tail_pairs = 0;  // brute-force tail budget, 0 = not measured
+  int lanes_shift = 0;    // the per-level lanes-per-query rule times 2^shift
 };
 
 // Cached entry for the class of (dims, K, N), or all zeros.
@@ -28,6 +29,8 @@ double autotune_growth(int dims, int K, int64_t N);
 int autotune_linear(int dims, int K, int64_t N);
 // Brute-force tail budget (0 if none cached).
 double autotune_tail_pairs(int dims, int K, int64_t N);
+// Shift of the per-level lanes-per-query rule (0 if none cached).
+int autotune_lanes_shift(int dims, int K, int64_t N);
 // Records a measured best setting for the class of (dims, K, N).
 void autotune_store(int dims, int K, int64_t N, const TuneEntry& e);
 // Loads / saves the cache file (path from KNN_AUTOTUNE_CACHE when path is NULL).

@@ -342,6 +342,9 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   KNN_CHECK(T_fixed == 0 || (T_fixed >= 1 && T_fixed <= 64 && (T_fixed & (T_fixed - 1)) == 0),
             KNN_EINVAL, "lanes_per_query must be a power of two in [1, 64]");
   const int T_tuned = T_fixed > 0 ? 0 : autotune_lanes(idx.n, K, idx.N);
+  const int lanes_shift = std::max(-2, std::min(2, o.lanes_shift != 0
+                                                       ? o.lanes_shift
+                                                       : autotune_lanes_shift(idx.n, K, idx.N)));
   const int pad = std::max(16, K / 2);
   const int cap = K + pad;
   if (st) st->eps_min = eps_min;
@@ -451,7 +454,11 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       cand = (double)tot[0] / (double)std::max<int64_t>(A, 1);
       cand_max = tot[1];
       c.M = M;
-      if (T == 0) T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(idx.n, cand, A, cap);
+      if (T == 0) {
+        T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(idx.n, cand, A, cap);
+        for (int sft = lanes_shift; sft > 0 && T < 64; --sft) T *= 2;
+        for (int sft = lanes_shift; sft < 0 && T > 1; ++sft) T /= 2;
+      }
     }
     // the per-wave buffers of small T grow with 3^(n-1) segment lists: raise
     // T until one wavefront's LDS fits
@@ -658,7 +665,8 @@ bool GraphPlan::matches(int32_t K_, const knn_join_opts& o, int32_t* ids_, doubl
          opts.eps_step == o.eps_step && opts.linear_levels == o.linear_levels &&
          opts.growth == o.growth && opts.tail_pairs == o.tail_pairs &&
          opts.heavy_min == o.heavy_min && opts.queue_grain == o.queue_grain &&
-         opts.item_order == o.item_order && opts.share_lists == o.share_lists;
+         opts.item_order == o.item_order && opts.share_lists == o.share_lists &&
+         opts.lanes_shift == o.lanes_shift;
 }
 
 GraphPlan::~GraphPlan() {
@@ -1038,6 +1046,7 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
     const size_t NK = (size_t)idx->N * K;
     c.out_ids.reserve(NK);
     c.out_d.reserve(NK);
+    int ls_cur = 0;  // lanes shift of the trials (stage 5)
     auto time_join = [&](double wf, double gr, int lin, double tp) {
       double best = 1e300;
       for (int rep = 0; rep < 2; ++rep) {
@@ -1046,6 +1055,7 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
         o.growth = gr;
         o.linear_levels = lin;
         o.tail_pairs = tp;
+        o.lanes_shift = ls_cur;
         KNN_HIP(hipStreamSynchronize(s));
         auto t0 = std::chrono::steady_clock::now();
         self_join(*idx, c, K, c.out_ids.p, c.out_d.p, o, s);
@@ -1094,9 +1104,19 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
     for (double f : {0.8, 1.25}) consider(wf1 * f, gr2, lin2, tp0);
     const double wf3 = out->w_factor;
     for (double tp : {6e7, 1e9}) consider(wf3, gr2, lin2, tp);
+    // the lanes-per-query rule, halved or doubled at every level
+    const double tp4 = out->tail_pairs;
+    out->lanes_shift = 0;
+    for (int ls : {-1, 1}) {
+      ls_cur = ls;
+      const double before = out->ms_best;
+      consider(wf3, gr2, lin2, tp4);
+      if (out->ms_best < before) out->lanes_shift = ls;
+    }
+    ls_cur = 0;
     autotune_store(idx->n, K, idx->N,
                    TuneEntry{out->w_factor, out->growth, 0, out->linear_levels > 0 ? 1 : -1,
-                             out->tail_pairs});
+                             out->tail_pairs, out->lanes_shift});
   });
 }
 

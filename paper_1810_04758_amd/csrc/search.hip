@@ -238,7 +238,7 @@ __device__ __forceinline__ uint32_t build_list(const uint32_t* __restrict__ rg,
                                                const uint8_t* __restrict__ rs, int nr, int nr_w,
                                                bool prune, double lim, const double (&qx)[DIM],
                                                const SearchArgs& a, int l, uint32_t* seg_st,
-                                               uint32_t* seg_ve, bool shared, uint32_t& nent) {
+                                               uint32_t* seg_ve, bool shared) {
   // face distances (recomputed here rather than kept live through the passes)
   double flo[DIM], fhi[DIM];
 #pragma unroll
@@ -300,51 +300,43 @@ __device__ __forceinline__ uint32_t build_list(const uint32_t* __restrict__ rg,
     cnt += __shfl(ik, T - 1, T);
     total += __shfl(il, T - 1, T);
   }
-  nent = cnt;
+  if (l == 0) {  // sentinel: ends every walk (its start is never used in a valid list)
+    seg_st[cnt] = 0;
+    seg_ve[cnt] = 0xFFFFFFFFu;
+  }
   return total;
 }
 
-// Walk over a list of n entries: virtual candidate v (non-decreasing from
-// call to call, below the list's count) -> sorted position.  A walk that
-// would run past the last entry (a list inconsistent with its count) stops
-// there, flags `bad` and returns an in-bounds position; the kernel reports
-// it and the join fails with an error.
+// Walk over a list: virtual candidate v (non-decreasing from call to call,
+// below the list's count) -> sorted position.  Every list ends with a
+// sentinel entry whose end is 0xFFFFFFFF, so a walk can never go past it,
+// and positions are clamped below N: a list inconsistent with its count
+// cannot make the walk loop or read out of bounds (the refinement rounds
+// detect the inconsistent counts and report them).
 struct LWalk {
   const uint32_t* st;
   const uint32_t* ve;
-  int r, n;
-  uint32_t vs, vend, s0;
-  bool bad;
-  __device__ __forceinline__ void init(const uint32_t* st_, const uint32_t* ve_, uint32_t C,
-                                       uint32_t nent) {
+  int r;
+  uint32_t vs, vend, s0, last;
+  __device__ __forceinline__ void init(const uint32_t* st_, const uint32_t* ve_, uint32_t nlast) {
     st = st_;
     ve = ve_;
     r = 0;
-    n = (int)nent;
     vs = 0;
-    bad = false;
-    vend = (C > 0 && nent > 0) ? ve[0] : 0u;
-    s0 = (C > 0 && nent > 0) ? st[0] : 0u;
+    vend = ve[0];
+    s0 = st[0];
+    last = nlast;
   }
   __device__ __forceinline__ uint32_t pos(uint32_t v) {
     while (v >= vend) {
-      if (r + 1 >= n) {
-        bad = true;
-        return s0;
-      }
       ++r;
       vs = vend;
       vend = ve[r];
       s0 = st[r];
     }
-    return s0 + (v - vs);
+    return min(s0 + (v - vs), last);
   }
 };
-
-// A walk that ran past its list: counted on the device, the join then fails.
-__device__ __forceinline__ void report_walk(const SearchArgs& a, const LWalk& cs) {
-  if (cs.bad) atomicAdd(a.walk_error, 1);
-}
 
 // Appends the wavefront's buffered failed ids to the global failure list.
 __device__ __forceinline__ void flush_failures(const SearchArgs& a, const int32_t* fbuf, int nfail,
@@ -372,6 +364,7 @@ k_search(const SearchArgs a) {
   const int cap = a.cap;
   const int K = a.K;
   const int64_t N = a.N;
+  const uint32_t nlast = (uint32_t)(N - 1);
   const int32_t* __restrict__ perm = a.perm;
   // per-dimension coordinate arrays (uniform base pointers)
   const double* __restrict__ Xd[DIM];
@@ -391,8 +384,8 @@ k_search(const SearchArgs a) {
   uint32_t* hist = hist_base + (size_t)wave * NB * G;
   uint32_t* hist2 = reinterpret_cast<uint32_t*>(bd);
   int32_t* fbuf = fbuf_base + (size_t)wave * kFailBuf;
-  uint32_t* seg_st = seg_base + (size_t)wave * 2 * R * G + (size_t)g * R;
-  uint32_t* seg_ve = seg_st + (size_t)R * G;
+  uint32_t* seg_st = seg_base + (size_t)wave * 2 * (R + 1) * G + (size_t)g * (R + 1);
+  uint32_t* seg_ve = seg_st + (size_t)(R + 1) * G;
 
   const uint64_t lane_lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
@@ -497,14 +490,13 @@ k_search(const SearchArgs a) {
     }
 
     // ---- count pass over the segments that can hold a point within thr -----
-    uint32_t nent = 0;
-    uint32_t C = build_list<DIM, T>(rg, rs, nr, nr_w, !full, thr, qx, a, l, seg_st, seg_ve,
-                                    shared, nent);
+    uint32_t C =
+        build_list<DIM, T>(rg, rs, nr, nr_w, !full, thr, qx, a, l, seg_st, seg_ve, shared);
     for (int b = l; b < NB; b += T) hist[b * G + g] = 0;
     wave_fence();
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, C, nent);
+      cs.init(seg_st, seg_ve, nlast);
       for (uint32_t v = l; v < C; v += T * kUnroll) {
         // positions first, then all coordinate loads in flight together
         uint32_t p[kUnroll];
@@ -521,7 +513,6 @@ k_search(const SearchArgs a) {
           if (p[u] != q32 && b < NB) atomicAdd(&hist[b * G + g], 1u);
         }
       }
-      report_walk(a, cs);
     }
     wave_fence();
 
@@ -574,7 +565,7 @@ k_search(const SearchArgs a) {
     // ---- list for the remaining passes: only bins up to the selected one ----
     const double lim2 = ok ? bins_limit<DIM>(bsel, thr, top) : 0.0;
     C = build_list<DIM, T>(rg, rs, ok ? nr : 0, nr_w, true, lim2, qx, a, l, seg_st, seg_ve,
-                           shared, nent);
+                           shared);
     wave_fence();
 
     // ---- exact refinement when the selected bin overflows the buffer -------
@@ -591,7 +582,7 @@ k_search(const SearchArgs a) {
       double dmin = INFINITY, dmax = -INFINITY;
       {
         LWalk cs;
-        cs.init(seg_st, seg_ve, C, nent);
+        cs.init(seg_st, seg_ve, nlast);
         const uint32_t Cr = refine ? C : 0u;
         for (uint32_t v = l; v < Cr; v += T) {
           const uint32_t p = cs.pos(v);
@@ -603,8 +594,7 @@ k_search(const SearchArgs a) {
             }
           }
         }
-        report_walk(a, cs);
-      }
+        }
       dmin = group_min<T>(dmin);
       dmax = group_max<T>(dmax);
       unsigned __int128 A = 0;
@@ -622,7 +612,7 @@ k_search(const SearchArgs a) {
         {
           const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
           LWalk cs;
-          cs.init(seg_st, seg_ve, C, nent);
+          cs.init(seg_st, seg_ve, nlast);
           const uint32_t Cr = refine ? C : 0u;
           for (uint32_t v = l; v < Cr; v += T) {
             const uint32_t p = cs.pos(v);
@@ -635,8 +625,7 @@ k_search(const SearchArgs a) {
               }
             }
           }
-          report_walk(a, cs);
-        }
+            }
         wave_fence();
         if (refine) {
           int cum = c_lo;
@@ -676,7 +665,7 @@ k_search(const SearchArgs a) {
     wave_fence();
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, C, nent);
+      cs.init(seg_st, seg_ve, nlast);
       for (uint32_t v = l; v < C; v += T * kUnroll) {
         uint32_t pp[kUnroll];
 #pragma unroll
@@ -707,7 +696,6 @@ k_search(const SearchArgs a) {
           }
         }
       }
-      report_walk(a, cs);
     }
     wave_fence();
 
@@ -759,15 +747,16 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
   extern __shared__ double smem[];
   __shared__ uint32_t hist[NB];
   __shared__ uint32_t hist2[NB2];
-  __shared__ uint32_t seg_st[R], seg_ve[R];
+  __shared__ uint32_t seg_st[R + 1], seg_ve[R + 1];
   __shared__ int s_bsel, s_clo, s_chi, s_refine;
-  __shared__ uint32_t s_C, s_nent;
+  __shared__ uint32_t s_C;
   __shared__ unsigned long long s_dmin, s_dmax;
   __shared__ unsigned __int128 s_A, s_B;
   const int tid = threadIdx.x;
   const int cap = a.cap;
   const int K = a.K;
   const int64_t N = a.N;
+  const uint32_t nlast = (uint32_t)(N - 1);
   const int32_t* __restrict__ perm = a.perm;
   const double* __restrict__ Xd[DIM];
 #pragma unroll
@@ -811,21 +800,16 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
 
     // ---- count pass
     if (tid < 64) {
-      uint32_t ne = 0;
-      const uint32_t C0 = build_list<DIM, 64>(rg, rs, nr, nr, !full, thr, qx, a, tid, seg_st,
-                                              seg_ve, false, ne);
-      if (tid == 0) {
-        s_C = C0;
-        s_nent = ne;
-      }
+      const uint32_t C0 =
+          build_list<DIM, 64>(rg, rs, nr, nr, !full, thr, qx, a, tid, seg_st, seg_ve, false);
+      if (tid == 0) s_C = C0;
       hist[tid] = 0;  // NB == 64
     }
     __syncthreads();
     uint32_t C = s_C;
-    uint32_t nent = s_nent;
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, C, nent);
+      cs.init(seg_st, seg_ve, nlast);
       for (uint32_t v = tid; v < C; v += NT * kUnroll) {
         uint32_t p[kUnroll];
 #pragma unroll
@@ -842,7 +826,6 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
           if (p[u] != q32 && b < NB) atomicAdd(&hist[b], 1u);
         }
       }
-      report_walk(a, cs);
     }
     __syncthreads();
 
@@ -875,17 +858,12 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
 
     // ---- list of the remaining passes
     if (tid < 64) {
-      uint32_t ne = 0;
       const uint32_t C1 = build_list<DIM, 64>(rg, rs, nr, nr, true, bins_limit<DIM>(bsel, thr, top),
-                                              qx, a, tid, seg_st, seg_ve, false, ne);
-      if (tid == 0) {
-        s_C = C1;
-        s_nent = ne;
-      }
+                                              qx, a, tid, seg_st, seg_ve, false);
+      if (tid == 0) s_C = C1;
     }
     __syncthreads();
     C = s_C;
-    nent = s_nent;
 
     // ---- exact refinement when the selected bin overflows the buffer
     const bool refined = s_chi > cap;
@@ -893,7 +871,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
       {
         unsigned long long mn = ~0ull, mx = 0ull;
         LWalk cs;
-        cs.init(seg_st, seg_ve, C, nent);
+        cs.init(seg_st, seg_ve, nlast);
         for (uint32_t v = tid; v < C; v += NT) {
           const uint32_t p = cs.pos(v);
           if (p != q32) {
@@ -907,8 +885,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         }
         if (mn != ~0ull) atomicMin(&s_dmin, mn);
         if (mx != 0ull) atomicMax(&s_dmax, mx);
-        report_walk(a, cs);
-      }
+        }
       __syncthreads();
       if (tid == 0) {
         s_A = (unsigned __int128)(uint64_t)s_dmin << 32;
@@ -927,7 +904,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         {
           const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
           LWalk cs;
-          cs.init(seg_st, seg_ve, C, nent);
+          cs.init(seg_st, seg_ve, nlast);
           for (uint32_t v = tid; v < C; v += NT) {
             const uint32_t p = cs.pos(v);
             if (p != q32) {
@@ -939,8 +916,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
               }
             }
           }
-          report_walk(a, cs);
-        }
+            }
         __syncthreads();
         if (tid == 0) {
           int cum = s_clo;
@@ -977,7 +953,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
     // ---- collect pass
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, C, nent);
+      cs.init(seg_st, seg_ve, nlast);
       for (uint32_t v = tid; v < C; v += NT * kUnroll) {
         uint32_t pp[kUnroll];
 #pragma unroll
@@ -1007,7 +983,6 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
           }
         }
       }
-      report_walk(a, cs);
     }
     __syncthreads();
 
@@ -1087,7 +1062,7 @@ size_t search_lds_per_wave(int dims, int T, int cap) {
   size_t R = 1;
   for (int j = 0; j < dims - 1; ++j) R *= 3;
   return (size_t)cap * G * (sizeof(double) + sizeof(int32_t)) + (size_t)NB * G * sizeof(uint32_t) +
-         (size_t)kFailBuf * sizeof(int32_t) + 2 * R * G * sizeof(uint32_t);
+         (size_t)kFailBuf * sizeof(int32_t) + 2 * (R + 1) * G * sizeof(uint32_t);
 }
 
 int search_waves_per_block(int dims, int T, int cap) {
