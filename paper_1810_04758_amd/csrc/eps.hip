@@ -48,14 +48,26 @@ __global__ void k_pair_sums(const double* __restrict__ X, int64_t N, int n,
 constexpr int kSampleChunk = 256;
 constexpr int kMaxBins = 4096;
 
+// Bin of a distance, floor(sqrt(d2) * inv_bw) with the correctly rounded
+// square root.  The hardware square root (not correctly rounded, but within
+// far less than 2^-20 relative) decides the bin unless the scaled value lies
+// within 2^-20 of a bin edge; only then is the exact square root taken.
+__device__ __forceinline__ double dist_bin(double d2, double inv_bw) {
+  const double t = __builtin_amdgcn_sqrt(d2) * inv_bw;
+  const double r = rint(t);
+  if (fabs(t - r) > t * 0x1p-20 + 0x1p-1000) return floor(t);
+  return floor(sqrt(d2) * inv_bw);
+}
+
 // Each thread takes points j; the sample points of a chunk sit in LDS.  The
 // per-block histogram is accumulated in LDS (uint32) and added to the global
 // uint64 counts at the end.
-__global__ void k_dist_histogram(const double* __restrict__ X, int64_t N, int n,
+template <int DIM>
+__global__ void k_dist_histogram(const double* __restrict__ X, int64_t N,
                                  const int64_t* __restrict__ sample, int64_t ns, double inv_bw,
                                  int n_bins, double skip_d2, uint64_t* __restrict__ counts) {
   __shared__ uint32_t h[kMaxBins];
-  __shared__ double sx[kMaxDims][kSampleChunk];
+  __shared__ double sx[DIM][kSampleChunk];
   __shared__ int64_t sid[kSampleChunk];
   for (int b = threadIdx.x; b < n_bins; b += blockDim.x) h[b] = 0;
   for (int64_t c0 = 0; c0 < ns; c0 += kSampleChunk) {
@@ -64,21 +76,24 @@ __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N, int n,
     for (int i = threadIdx.x; i < cn; i += blockDim.x) {
       int64_t id = sample[c0 + i];
       sid[i] = id;
-      for (int j = 0; j < n; ++j) sx[j][i] = X[(int64_t)j * N + id];
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) sx[j][i] = X[(int64_t)j * N + id];
     }
     __syncthreads();
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
          p += (int64_t)gridDim.x * blockDim.x) {
-      double x[kMaxDims];
-      for (int j = 0; j < n; ++j) x[j] = X[(int64_t)j * N + p];
+      double x[DIM];
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) x[j] = X[(int64_t)j * N + p];
       for (int i = 0; i < cn; ++i) {
         double s = 0.0;
-        for (int j = 0; j < n; ++j) {
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
           double t = __dsub_rn(x[j], sx[j][i]);
           s = __dadd_rn(s, __dmul_rn(t, t));
         }
         if (s > skip_d2 || p == sid[i]) continue;  // certainly beyond the last bin, or self
-        double t = floor(sqrt(s) * inv_bw);
+        const double t = dist_bin(s, inv_bw);
         if (t < (double)n_bins) atomicAdd(&h[(int)t], 1u);
       }
     }
@@ -103,14 +118,21 @@ void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sam
                            int64_t ns, double inv_bw, int n_bins, uint64_t* counts,
                            hipStream_t s) {
   KNN_CHECK(n_bins >= 1 && n_bins <= kMaxBins, KNN_EINVAL, "n_bins must be in [1, 4096]");
-  KNN_HIP(hipMemsetAsync(counts, 0, n_bins * sizeof(uint64_t), s));
+  launch_zero(counts, n_bins * sizeof(uint64_t), s);
   if (ns <= 0 || N <= 0) return;
   // distances whose bin is certainly >= n_bins skip the square root
   double lim = (double)n_bins / inv_bw;
   double skip_d2 = lim * lim * 1.0001 + 1e-300;
   int64_t want = ceil_div(N, kBlock);
   int nb = (int)(want < 2048 ? want : 2048);
-  k_dist_histogram<<<nb, kBlock, 0, s>>>(X, N, n, sample, ns, inv_bw, n_bins, skip_d2, counts);
+  switch (n) {
+    case 2: k_dist_histogram<2><<<nb, kBlock, 0, s>>>(X, N, sample, ns, inv_bw, n_bins, skip_d2, counts); break;
+    case 3: k_dist_histogram<3><<<nb, kBlock, 0, s>>>(X, N, sample, ns, inv_bw, n_bins, skip_d2, counts); break;
+    case 4: k_dist_histogram<4><<<nb, kBlock, 0, s>>>(X, N, sample, ns, inv_bw, n_bins, skip_d2, counts); break;
+    case 5: k_dist_histogram<5><<<nb, kBlock, 0, s>>>(X, N, sample, ns, inv_bw, n_bins, skip_d2, counts); break;
+    case 6: k_dist_histogram<6><<<nb, kBlock, 0, s>>>(X, N, sample, ns, inv_bw, n_bins, skip_d2, counts); break;
+    default: throw Error(KNN_EINVAL, "dims out of range");
+  }
   KNN_LAUNCHED();
 }
 
