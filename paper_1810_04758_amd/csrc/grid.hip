@@ -315,14 +315,20 @@ __global__ void k_emit_cells(const uint64_t* __restrict__ keys, const uint32_t* 
   }
 }
 
-// Xs[j*N + p] = XA[perm[p]*n + j]: the source point's coordinates are
-// adjacent in the row-major copy, so each random gather touches one line.
-__global__ void k_gather_soa(const double* __restrict__ XA, const int32_t* __restrict__ perm,
-                             int64_t N, int n, double* __restrict__ Xs) {
+// Point-major sorted coordinates: point p (sorted position) takes the row
+// perm[p] of the row-major copy, padded to an even count with 0.
+__global__ void k_gather_points(const double* __restrict__ XA, const int32_t* __restrict__ perm,
+                                int64_t N, int n, double* __restrict__ Xs) {
+  const int S = point_stride(n);
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
        p += (int64_t)gridDim.x * blockDim.x) {
     const int64_t src = perm[p];
-    for (int j = 0; j < n; ++j) Xs[(int64_t)j * N + p] = XA[src * n + j];
+    const double* in = XA + src * n;
+    double2* out = reinterpret_cast<double2*>(Xs + p * S);
+    for (int h = 0; h < S / 2; ++h) {
+      const int j = 2 * h;
+      out[h] = make_double2(in[j], j + 1 < n ? in[j + 1] : 0.0);
+    }
   }
 }
 
@@ -390,7 +396,8 @@ __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
     const uint32_t p0 = cell_start[c];
     int64_t cc[DIM];
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) cc[j] = cell_coord(Xs[(int64_t)j * N + p0], gd.lo[j], gd.inv_w);
+    for (int j = 0; j < DIM; ++j)
+      cc[j] = cell_coord(Xs[(int64_t)p0 * point_stride(DIM) + j], gd.lo[j], gd.inv_w);
     uint32_t count = 0, cand = 0;
     for (int rb = 0; rb < R; rb += S) {
       const int r = rb + l;
@@ -732,9 +739,9 @@ void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags, u
   KNN_LAUNCHED();
 }
 
-void launch_gather_soa(const double* X, const int32_t* perm, int64_t N, int n, double* Xs,
-                       hipStream_t s) {
-  k_gather_soa<<<grid_for(N), kBlock, 0, s>>>(X, perm, N, n, Xs);
+void launch_gather_points(const double* X, const int32_t* perm, int64_t N, int n, double* Xs,
+                          hipStream_t s) {
+  k_gather_points<<<grid_for(N), kBlock, 0, s>>>(X, perm, N, n, Xs);
   KNN_LAUNCHED();
 }
 

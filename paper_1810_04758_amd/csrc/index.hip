@@ -184,7 +184,7 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s) {
   const int64_t N = idx.N;
   const int n = idx.n;
   c.gg = make_geom(idx, w);
-  c.Xs.reserve((size_t)N * n);
+  c.Xs.reserve((size_t)N * point_stride(n));
   c.perm.reserve(N);
   c.cell_of.reserve(N);
   c.cell_key.reserve(N);
@@ -203,7 +203,7 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s) {
   }
   build_cell_table(c.keys.p, N, c.flags.p, c.cell_of.p, c.cell_key.p, c.cell_start.p, c.scal.p,
                    c.tmp.p, s);
-  launch_gather_soa(idx.XA.p, c.perm.p, N, n, c.Xs.p, s);
+  launch_gather_points(idx.XA.p, c.perm.p, N, n, c.Xs.p, s);
   // The number of cells M stays on the device (kernels read it there), so the
   // level is built without a host round trip; per-cell arrays are sized for
   // the worst case M = N.
@@ -272,7 +272,7 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   const uint64_t R = (uint64_t)pow3(idx.n - 1);
   const uint64_t cap = (uint64_t)K + std::max<uint64_t>(16, (uint64_t)K / 2);
   uint64_t b = 0;
-  b += 8 * n * N;                      // Xs
+  b += 8 * (uint64_t)point_stride(idx.n) * N;  // Xs
   b += (4 + 4 + 8 + 4 + 4 + 4) * N;    // perm, cell_of, cell_key, cell_start, nrng, cand_count
   b += 17 * R * N;                     // ranges (4 x u32) + rslot
   b += std::max<uint64_t>(256 * N, 32ull << 20);  // dense key table or row table

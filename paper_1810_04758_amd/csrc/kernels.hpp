@@ -66,9 +66,13 @@ void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* 
 void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags,
                       uint32_t* cell_of, uint64_t* cell_key, uint32_t* cell_start,
                       uint32_t* d_M, uint32_t* tmp, hipStream_t s);
-// Xs[j*N + p] = XA[perm[p]*n + j] (XA row-major N x n)
-void launch_gather_soa(const double* XA, const int32_t* perm, int64_t N, int n, double* Xs,
-                       hipStream_t s);
+// Doubles per point in the sorted coordinate array: n rounded up to even, so
+// a point is whole 16-byte pairs (a padding coordinate is 0).
+inline constexpr int point_stride(int n) { return (n + 1) & ~1; }
+// Xs[p*S + j] = XA[perm[p]*n + j] for j < n, Xs[p*S + n] = 0 when n is odd
+// (S = point_stride(n); XA row-major N x n)
+void launch_gather_points(const double* XA, const int32_t* perm, int64_t N, int n, double* Xs,
+                          hipStream_t s);
 // Row table: for every row of the grid (the cells sharing coordinates
 // 0..n-2, row = key / g_last), [rowtab[row].x, rowtab[row].y) = its
 // non-empty cells (empty rows: 0, 0).  rows entries.
@@ -135,7 +139,7 @@ void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sam
 
 // ---- search (search.hip) ----
 struct SearchArgs {
-  const double* Xs;        // SoA sorted coordinates, Xs[j*N + p]
+  const double* Xs;        // sorted coordinates, point-major: Xs[p*point_stride(n) + j]
   int64_t N;
   const int32_t* perm;     // sorted position -> point id
   const uint32_t* cell_of; // sorted position -> cell

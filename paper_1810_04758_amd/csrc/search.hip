@@ -87,22 +87,36 @@ struct Pow3<0> {
   static constexpr int v = 1;
 };
 
+// Coordinates of point p of the point-major sorted array: S = point_stride
+// doubles per point, read as S/2 16-byte loads (one address for them all).
+// OFF32 (8 S N < 2^32): the byte offset fits 32 bits, so the loads take the
+// form scalar base + 32-bit vector offset.
+template <int DIM, bool OFF32>
+__device__ __forceinline__ void load_point(const double* __restrict__ Xs, uint32_t p,
+                                           double (&x)[DIM]) {
+  constexpr int S = point_stride(DIM);
+  const double2* src =
+      OFF32 ? reinterpret_cast<const double2*>(reinterpret_cast<const char*>(Xs) +
+                                               p * (uint32_t)(S * sizeof(double)))
+            : reinterpret_cast<const double2*>(Xs + (size_t)p * S);
+#pragma unroll
+  for (int h = 0; h < S / 2; ++h) {
+    const double2 t = src[h];
+    x[2 * h] = t.x;
+    if (2 * h + 1 < DIM) x[2 * h + 1] = t.y;
+  }
+}
+
 // Coordinates of several candidates, loaded before any is used: a compiler
 // barrier between the loads and the arithmetic keeps them all in flight
 // (left alone, the scheduler waits on the first candidate's loads one by one).
 template <int DIM, bool OFF32, int U>
-__device__ __forceinline__ void sq_dist_batch(const double* __restrict__ const (&Xd)[DIM],
+__device__ __forceinline__ void sq_dist_batch(const double* __restrict__ Xs,
                                               const uint32_t (&p)[U], const double (&q)[DIM],
                                               double (&d2)[U]) {
   double x[U][DIM];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const uint32_t off = p[u] << 3;
-#pragma unroll
-    for (int j = 0; j < DIM; ++j)
-      x[u][j] = OFF32 ? *reinterpret_cast<const double*>(reinterpret_cast<const char*>(Xd[j]) + off)
-                      : Xd[j][p[u]];
-  }
+  for (int u = 0; u < U; ++u) load_point<DIM, OFF32>(Xs, p[u], x[u]);
   asm volatile("" ::: "memory");
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -116,43 +130,54 @@ __device__ __forceinline__ void sq_dist_batch(const double* __restrict__ const (
   }
 }
 
-// OFF32 (8 N < 2^32): the byte offset of a candidate fits 32 bits, so the
-// loads take the form scalar base + 32-bit vector offset (one shift per
-// candidate instead of a 64-bit address per coordinate).
 template <int DIM, bool OFF32>
-__device__ __forceinline__ double sq_dist(const double* __restrict__ const (&Xd)[DIM], uint32_t p,
+__device__ __forceinline__ double sq_dist(const double* __restrict__ Xs, uint32_t p,
                                           const double (&q)[DIM]) {
+  double x[DIM];
+  load_point<DIM, OFF32>(Xs, p, x);
   double s = 0.0;
-  const uint32_t off = p << 3;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
-    const double x = OFF32 ? *reinterpret_cast<const double*>(
-                                 reinterpret_cast<const char*>(Xd[j]) + off)
-                           : Xd[j][p];
-    double t = __dsub_rn(x, q[j]);
+    double t = __dsub_rn(x[j], q[j]);
     s = __dadd_rn(s, __dmul_rn(t, t));
   }
   return s;
 }
 
 // Monotone bin of a squared distance: 0..NB-1 for d2 <= thr, NB above it.
-// top = (bit pattern of the reference top) >> kBinShift; the bit pattern of a
-// non-negative double is monotone in its value, so the bin is monotone in d2.
-// Only the high word is needed (kBinShift >= 32).
+// top = (bit pattern of the reference top) >> kBinShift, top0 = top - (NB-1);
+// the bit pattern of a non-negative double is monotone in its value, so the
+// bin is monotone in d2.  Only the high word is needed (kBinShift >= 32).
 template <int DIM>
-__device__ __forceinline__ int bin_of(double d2, double thr, int top) {
+__device__ __forceinline__ int bin_clamped(double d2, int top0) {
   constexpr int kBinShift = BinShift<DIM>::v;
-  const int k = (int)((uint32_t)__double2hiint(d2) >> (kBinShift - 32)) - top + (NB - 1);
-  const int b = min(max(k, 0), NB - 1);
-  return d2 > thr ? NB : b;
+  const int k = (int)((uint32_t)__double2hiint(d2) >> (kBinShift - 32)) - top0;
+  // clamp to [0, NB - 1] in one instruction (the compiler splits min(max())
+  // into three here)
+  int b;
+  asm("v_med3_i32 %0, %1, 0, %2" : "=v"(b) : "v"(k), "i"(NB - 1));
+  return b;
+}
+template <int DIM>
+__device__ __forceinline__ int bin_of(double d2, double thr, int top0) {
+  return d2 > thr ? NB : bin_clamped<DIM>(d2, top0);
+}
+
+// top0 of a reference squared distance, opaque to the optimizer (which would
+// otherwise fold the subtraction back into every bin computation)
+template <int DIM>
+__device__ __forceinline__ int bin_top0(double ref) {
+  int t = (int)((uint64_t)__double_as_longlong(ref) >> BinShift<DIM>::v) - (NB - 1);
+  asm("" : "+v"(t));
+  return t;
 }
 
 // Upper limit of the squared distances in bins 0..b (for pruning the passes
 // that only need those bins): below the next bin edge, and never above thr.
 template <int DIM>
-__device__ __forceinline__ double bins_limit(int b, double thr, int top) {
+__device__ __forceinline__ double bins_limit(int b, double thr, int top0) {
   constexpr int kBinShift = BinShift<DIM>::v;
-  const int e = top - (NB - 1) + b + 1;  // bit pattern >> kBinShift of the next edge
+  const int e = top0 + b + 1;  // bit pattern >> kBinShift of the next edge
   if (b >= NB - 1 || e <= 0 || e >= (0x7FF0 >> (kBinShift - 48))) return thr;
   const double edge = __longlong_as_double((long long)((uint64_t)e << kBinShift));
   return fmin(edge, thr);
@@ -203,8 +228,8 @@ __device__ __forceinline__ int bitlen128(unsigned __int128 v) {
 }
 
 // Per-query candidate list in LDS: the non-empty row segments that a pass
-// needs, compacted, as (start position, running end in virtual candidate
-// numbering).  A segment (or its first or last cell along the last
+// needs, compacted, as (sorted position minus virtual position, running end in
+// virtual candidate numbering).  A segment (or its first or last cell along the last
 // dimension) is left out when a conservative lower bound of the squared
 // distance from the query to any of its points exceeds the pass's limit (all
 // its candidates would be beyond it).  The bound uses the query's distances
@@ -237,7 +262,7 @@ template <int DIM, int T>
 __device__ __forceinline__ uint32_t build_list(const uint32_t* __restrict__ rg,
                                                const uint8_t* __restrict__ rs, int nr, int nr_w,
                                                bool prune, double lim, const double (&qx)[DIM],
-                                               const SearchArgs& a, int l, uint32_t* seg_st,
+                                               const SearchArgs& a, int l, uint32_t* seg_of,
                                                uint32_t* seg_ve, bool shared) {
   // face distances (recomputed here rather than kept live through the passes)
   double flo[DIM], fhi[DIM];
@@ -294,14 +319,16 @@ __device__ __forceinline__ uint32_t build_list(const uint32_t* __restrict__ rg,
       }
     }
     if (keep) {
-      seg_st[cnt + ik - 1] = st;
+      // offset from virtual to sorted position (mod 2^32): the segment's
+      // virtual start is total + il - len
+      seg_of[cnt + ik - 1] = st - (total + il - len);
       seg_ve[cnt + ik - 1] = total + il;
     }
     cnt += __shfl(ik, T - 1, T);
     total += __shfl(il, T - 1, T);
   }
-  if (l == 0) {  // sentinel: ends every walk (its start is never used in a valid list)
-    seg_st[cnt] = 0;
+  if (l == 0) {  // sentinel: ends every walk (its offset is never used in a valid list)
+    seg_of[cnt] = 0;
     seg_ve[cnt] = 0xFFFFFFFFu;
   }
   return total;
@@ -314,29 +341,40 @@ __device__ __forceinline__ uint32_t build_list(const uint32_t* __restrict__ rg,
 // cannot make the walk loop or read out of bounds (the refinement rounds
 // detect the inconsistent counts and report them).
 struct LWalk {
-  const uint32_t* st;
+  const uint32_t* of;
   const uint32_t* ve;
   int r;
-  uint32_t vs, vend, s0, last;
-  __device__ __forceinline__ void init(const uint32_t* st_, const uint32_t* ve_, uint32_t nlast) {
-    st = st_;
+  uint32_t vend, off, last;
+  __device__ __forceinline__ void init(const uint32_t* of_, const uint32_t* ve_, uint32_t nlast) {
+    of = of_;
     ve = ve_;
     r = 0;
-    vs = 0;
     vend = ve[0];
-    s0 = st[0];
+    off = of[0];
     last = nlast;
   }
   __device__ __forceinline__ uint32_t pos(uint32_t v) {
     while (v >= vend) {
       ++r;
-      vs = vend;
       vend = ve[r];
-      s0 = st[r];
+      off = of[r];
     }
-    return min(s0 + (v - vs), last);
+    return min(off + v, last);
   }
 };
+
+// Positions of the batch of virtual candidates v, v + T, ..., v + (U-1) T of
+// a walk; slots at or past the list's count C get `pad`.  kWhole: the caller
+// knows that the whole batch lies inside the list.
+template <int T, int U, bool kWhole>
+__device__ __forceinline__ void batch_pos(LWalk& cs, uint32_t v, uint32_t C, uint32_t pad,
+                                          uint32_t (&p)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t vv = v + (uint32_t)(u * T);
+    p[u] = (kWhole || vv < C) ? cs.pos(vv) : pad;
+  }
+}
 
 // Appends the wavefront's buffered failed ids to the global failure list.
 __device__ __forceinline__ void flush_failures(const SearchArgs& a, const int32_t* fbuf, int nfail,
@@ -366,10 +404,7 @@ k_search(const SearchArgs a) {
   const int64_t N = a.N;
   const uint32_t nlast = (uint32_t)(N - 1);
   const int32_t* __restrict__ perm = a.perm;
-  // per-dimension coordinate arrays (uniform base pointers)
-  const double* __restrict__ Xd[DIM];
-#pragma unroll
-  for (int j = 0; j < DIM; ++j) Xd[j] = a.Xs + (int64_t)j * N;
+  const double* __restrict__ Xs = a.Xs;  // point-major sorted coordinates
 
   // per-wave LDS: survivors d2 [cap][G], survivor ids [cap][G], histogram
   // [NB][G], failure buffer, candidate lists [G][R] (starts, ends); the
@@ -384,8 +419,8 @@ k_search(const SearchArgs a) {
   uint32_t* hist = hist_base + (size_t)wave * NB * G;
   uint32_t* hist2 = reinterpret_cast<uint32_t*>(bd);
   int32_t* fbuf = fbuf_base + (size_t)wave * kFailBuf;
-  uint32_t* seg_st = seg_base + (size_t)wave * 2 * (R + 1) * G + (size_t)g * (R + 1);
-  uint32_t* seg_ve = seg_st + (size_t)(R + 1) * G;
+  uint32_t* seg_of = seg_base + (size_t)wave * 2 * (R + 1) * G + (size_t)g * (R + 1);
+  uint32_t* seg_ve = seg_of + (size_t)(R + 1) * G;
 
   const uint64_t lane_lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
@@ -440,8 +475,7 @@ k_search(const SearchArgs a) {
 
     // ---- query point, covered radius, face distances ------------------------
     double qx[DIM];
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) qx[j] = Xd[j][q];
+    load_point<DIM, false>(Xs, (uint32_t)q, qx);
     const uint32_t cell = a.cell_of[q];
     const uint32_t* rg = a.ranges + (size_t)cell * R * 4;
     const uint8_t* rs = a.rslot + (size_t)cell * R;
@@ -472,7 +506,7 @@ k_search(const SearchArgs a) {
       thr = r * r;
       ref = thr;
     }
-    const int top = (int)((uint64_t)__double_as_longlong(ref) >> BinShift<DIM>::v);
+    const int top0 = bin_top0<DIM>(ref);
     int nr_w = nr;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) nr_w = max(nr_w, __shfl_xor(nr_w, o, 64));
@@ -491,28 +525,42 @@ k_search(const SearchArgs a) {
 
     // ---- count pass over the segments that can hold a point within thr -----
     uint32_t C =
-        build_list<DIM, T>(rg, rs, nr, nr_w, !full, thr, qx, a, l, seg_st, seg_ve, shared);
+        build_list<DIM, T>(rg, rs, nr, nr_w, !full, thr, qx, a, l, seg_of, seg_ve, shared);
     for (int b = l; b < NB; b += T) hist[b * G + g] = 0;
     wave_fence();
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, nlast);
-      for (uint32_t v = l; v < C; v += T * kUnroll) {
-        // positions first, then all coordinate loads in flight together
-        uint32_t p[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const uint32_t vv = v + (uint32_t)(u * T);
-          p[u] = vv < C ? cs.pos(vv) : q32;
-        }
+      cs.init(seg_of, seg_ve, nlast);
+      // positions first, then all coordinate loads in flight together
+      auto count = [&](const uint32_t (&p)[kUnroll]) {
         double d2[kUnroll];
-        sq_dist_batch<DIM, OFF32, kUnroll>(Xd, p, qx, d2);
+        sq_dist_batch<DIM, OFF32, kUnroll>(Xs, p, qx, d2);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const int b = bin_of<DIM>(d2[u], thr, top);
-          if (p[u] != q32 && b < NB) atomicAdd(&hist[b * G + g], 1u);
+          if (!(d2[u] > thr)) atomicAdd(&hist[bin_clamped<DIM>(d2[u], top0) * G + g], 1u);
         }
+      };
+      uint32_t v = l;
+      for (; v + (kUnroll - 1) * T < C; v += T * kUnroll) {
+        uint32_t p[kUnroll];
+        batch_pos<T, kUnroll, true>(cs, v, C, q32, p);
+        count(p);
       }
+      if (v < C) {
+        uint32_t p[kUnroll];
+        batch_pos<T, kUnroll, false>(cs, v, C, q32, p);
+        count(p);
+      }
+    }
+    // The walk counted the query itself (its own cell is always in the list)
+    // and every slot past the list's end (given the query's position): all at
+    // distance 0, in bin bin_of(0).  Each lane takes back its own padding
+    // slots, lane 0 also the query.
+    if (valid) {
+      const uint32_t it = l < (int)C ? (C - (uint32_t)l + T * kUnroll - 1) / (T * kUnroll) : 0u;
+      const uint32_t real = l < (int)C ? (C - (uint32_t)l + T - 1) / T : 0u;
+      const uint32_t back = it * kUnroll - real + (l == 0 ? 1u : 0u);
+      if (back) atomicSub(&hist[bin_of<DIM>(0.0, thr, top0) * G + g], back);
     }
     wave_fence();
 
@@ -563,8 +611,8 @@ k_search(const SearchArgs a) {
     }
 
     // ---- list for the remaining passes: only bins up to the selected one ----
-    const double lim2 = ok ? bins_limit<DIM>(bsel, thr, top) : 0.0;
-    C = build_list<DIM, T>(rg, rs, ok ? nr : 0, nr_w, true, lim2, qx, a, l, seg_st, seg_ve,
+    const double lim2 = ok ? bins_limit<DIM>(bsel, thr, top0) : 0.0;
+    C = build_list<DIM, T>(rg, rs, ok ? nr : 0, nr_w, true, lim2, qx, a, l, seg_of, seg_ve,
                            shared);
     wave_fence();
 
@@ -582,13 +630,13 @@ k_search(const SearchArgs a) {
       double dmin = INFINITY, dmax = -INFINITY;
       {
         LWalk cs;
-        cs.init(seg_st, seg_ve, nlast);
+        cs.init(seg_of, seg_ve, nlast);
         const uint32_t Cr = refine ? C : 0u;
         for (uint32_t v = l; v < Cr; v += T) {
           const uint32_t p = cs.pos(v);
           if (p != q32) {
-            const double d2 = sq_dist<DIM, OFF32>(Xd, p, qx);
-            if (bin_of<DIM>(d2, thr, top) == bsel) {
+            const double d2 = sq_dist<DIM, OFF32>(Xs, p, qx);
+            if (bin_of<DIM>(d2, thr, top0) == bsel) {
               dmin = fmin(dmin, d2);
               dmax = fmax(dmax, d2);
             }
@@ -612,12 +660,12 @@ k_search(const SearchArgs a) {
         {
           const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
           LWalk cs;
-          cs.init(seg_st, seg_ve, nlast);
+          cs.init(seg_of, seg_ve, nlast);
           const uint32_t Cr = refine ? C : 0u;
           for (uint32_t v = l; v < Cr; v += T) {
             const uint32_t p = cs.pos(v);
             if (p != q32) {
-              const double d2 = sq_dist<DIM, OFF32>(Xd, p, qx);
+              const double d2 = sq_dist<DIM, OFF32>(Xs, p, qx);
               const uint64_t kh = (uint64_t)__double_as_longlong(d2);
               if (kh >= ahi && kh <= bhi) {
                 const unsigned __int128 k = ((unsigned __int128)kh << 32) | (uint32_t)perm[p];
@@ -665,21 +713,15 @@ k_search(const SearchArgs a) {
     wave_fence();
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, nlast);
-      for (uint32_t v = l; v < C; v += T * kUnroll) {
-        uint32_t pp[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const uint32_t vv = v + (uint32_t)(u * T);
-          pp[u] = vv < C ? cs.pos(vv) : q32;
-        }
+      cs.init(seg_of, seg_ve, nlast);
+      auto collect = [&](const uint32_t (&pp)[kUnroll]) {
         double dd[kUnroll];
-        sq_dist_batch<DIM, OFF32, kUnroll>(Xd, pp, qx, dd);
+        sq_dist_batch<DIM, OFF32, kUnroll>(Xs, pp, qx, dd);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t p = pp[u];
           const double d2 = dd[u];
-          const int b = bin_of<DIM>(d2, thr, top);
+          const int b = bin_of<DIM>(d2, thr, top0);
           bool acc;
           if (refined)
             acc = d2 < th_d || (d2 == th_d && (th_id == 0xFFFFFFFFu || (uint32_t)perm[p] <= th_id));
@@ -695,6 +737,17 @@ k_search(const SearchArgs a) {
             }
           }
         }
+      };
+      uint32_t v = l;
+      for (; v + (kUnroll - 1) * T < C; v += T * kUnroll) {
+        uint32_t pp[kUnroll];
+        batch_pos<T, kUnroll, true>(cs, v, C, q32, pp);
+        collect(pp);
+      }
+      if (v < C) {
+        uint32_t pp[kUnroll];
+        batch_pos<T, kUnroll, false>(cs, v, C, q32, pp);
+        collect(pp);
       }
     }
     wave_fence();
@@ -710,7 +763,7 @@ k_search(const SearchArgs a) {
       if (ai < c) {
         const double da = bd[ai * G + g];
         const int32_t ia = bi[ai * G + g];
-        const int b = bin_of<DIM>(da, thr, top);
+        const int b = bin_of<DIM>(da, thr, top0);
         const int start = b > 0 ? (int)hist[(b - 1) * G + g] : 0;
         if (start < K) {
           const int end = min((int)hist[b * G + g], cap);
@@ -747,7 +800,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
   extern __shared__ double smem[];
   __shared__ uint32_t hist[NB];
   __shared__ uint32_t hist2[NB2];
-  __shared__ uint32_t seg_st[R + 1], seg_ve[R + 1];
+  __shared__ uint32_t seg_of[R + 1], seg_ve[R + 1];
   __shared__ int s_bsel, s_clo, s_chi, s_refine;
   __shared__ uint32_t s_C;
   __shared__ unsigned long long s_dmin, s_dmax;
@@ -758,9 +811,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
   const int64_t N = a.N;
   const uint32_t nlast = (uint32_t)(N - 1);
   const int32_t* __restrict__ perm = a.perm;
-  const double* __restrict__ Xd[DIM];
-#pragma unroll
-  for (int j = 0; j < DIM; ++j) Xd[j] = a.Xs + (int64_t)j * N;
+  const double* __restrict__ Xs = a.Xs;
   double* bd = smem;
   int32_t* bi = reinterpret_cast<int32_t*>(smem + cap);
   const int nh = *a.n_heavy;
@@ -769,8 +820,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
     const int64_t q = a.heavy[hq];
     const uint32_t q32 = (uint32_t)q;
     double qx[DIM];
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) qx[j] = Xd[j][q];
+    load_point<DIM, false>(Xs, (uint32_t)q, qx);
     const uint32_t cell = a.cell_of[q];
     const uint32_t* rg = a.ranges + (size_t)cell * R * 4;
     const uint8_t* rs = a.rslot + (size_t)cell * R;
@@ -796,12 +846,12 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
       thr = r * r;
       ref = thr;
     }
-    const int top = (int)((uint64_t)__double_as_longlong(ref) >> BinShift<DIM>::v);
+    const int top0 = bin_top0<DIM>(ref);
 
     // ---- count pass
     if (tid < 64) {
       const uint32_t C0 =
-          build_list<DIM, 64>(rg, rs, nr, nr, !full, thr, qx, a, tid, seg_st, seg_ve, false);
+          build_list<DIM, 64>(rg, rs, nr, nr, !full, thr, qx, a, tid, seg_of, seg_ve, false);
       if (tid == 0) s_C = C0;
       hist[tid] = 0;  // NB == 64
     }
@@ -809,7 +859,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
     uint32_t C = s_C;
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, nlast);
+      cs.init(seg_of, seg_ve, nlast);
       for (uint32_t v = tid; v < C; v += NT * kUnroll) {
         uint32_t p[kUnroll];
 #pragma unroll
@@ -819,10 +869,10 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         }
         double d2[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) d2[u] = sq_dist<DIM, false>(Xd, p[u], qx);
+        for (int u = 0; u < kUnroll; ++u) d2[u] = sq_dist<DIM, false>(Xs, p[u], qx);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-          const int b = bin_of<DIM>(d2[u], thr, top);
+          const int b = bin_of<DIM>(d2[u], thr, top0);
           if (p[u] != q32 && b < NB) atomicAdd(&hist[b], 1u);
         }
       }
@@ -858,8 +908,8 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
 
     // ---- list of the remaining passes
     if (tid < 64) {
-      const uint32_t C1 = build_list<DIM, 64>(rg, rs, nr, nr, true, bins_limit<DIM>(bsel, thr, top),
-                                              qx, a, tid, seg_st, seg_ve, false);
+      const uint32_t C1 = build_list<DIM, 64>(rg, rs, nr, nr, true, bins_limit<DIM>(bsel, thr, top0),
+                                              qx, a, tid, seg_of, seg_ve, false);
       if (tid == 0) s_C = C1;
     }
     __syncthreads();
@@ -871,12 +921,12 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
       {
         unsigned long long mn = ~0ull, mx = 0ull;
         LWalk cs;
-        cs.init(seg_st, seg_ve, nlast);
+        cs.init(seg_of, seg_ve, nlast);
         for (uint32_t v = tid; v < C; v += NT) {
           const uint32_t p = cs.pos(v);
           if (p != q32) {
-            const double d2 = sq_dist<DIM, false>(Xd, p, qx);
-            if (bin_of<DIM>(d2, thr, top) == bsel) {
+            const double d2 = sq_dist<DIM, false>(Xs, p, qx);
+            if (bin_of<DIM>(d2, thr, top0) == bsel) {
               const unsigned long long kb = (unsigned long long)__double_as_longlong(d2);
               mn = min(mn, kb);
               mx = max(mx, kb);
@@ -904,11 +954,11 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         {
           const uint64_t ahi = (uint64_t)(A >> 32), bhi = (uint64_t)(B >> 32);
           LWalk cs;
-          cs.init(seg_st, seg_ve, nlast);
+          cs.init(seg_of, seg_ve, nlast);
           for (uint32_t v = tid; v < C; v += NT) {
             const uint32_t p = cs.pos(v);
             if (p != q32) {
-              const double d2 = sq_dist<DIM, false>(Xd, p, qx);
+              const double d2 = sq_dist<DIM, false>(Xs, p, qx);
               const uint64_t kh = (uint64_t)__double_as_longlong(d2);
               if (kh >= ahi && kh <= bhi) {
                 const unsigned __int128 k = ((unsigned __int128)kh << 32) | (uint32_t)perm[p];
@@ -953,7 +1003,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
     // ---- collect pass
     {
       LWalk cs;
-      cs.init(seg_st, seg_ve, nlast);
+      cs.init(seg_of, seg_ve, nlast);
       for (uint32_t v = tid; v < C; v += NT * kUnroll) {
         uint32_t pp[kUnroll];
 #pragma unroll
@@ -963,12 +1013,12 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
         }
         double dd[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) dd[u] = sq_dist<DIM, false>(Xd, pp[u], qx);
+        for (int u = 0; u < kUnroll; ++u) dd[u] = sq_dist<DIM, false>(Xs, pp[u], qx);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const uint32_t p = pp[u];
           const double d2 = dd[u];
-          const int b = bin_of<DIM>(d2, thr, top);
+          const int b = bin_of<DIM>(d2, thr, top0);
           bool acc;
           if (refined)
             acc = d2 < th_d || (d2 == th_d && (th_id == 0xFFFFFFFFu || (uint32_t)perm[p] <= th_id));
@@ -992,7 +1042,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
     for (int ai = tid; ai < c; ai += NT) {
       const double da = bd[ai];
       const int32_t ia = bi[ai];
-      const int b = bin_of<DIM>(da, thr, top);
+      const int b = bin_of<DIM>(da, thr, top0);
       const int start = b > 0 ? (int)hist[b - 1] : 0;
       if (start < K) {
         const int end = min((int)hist[b], cap);
@@ -1049,7 +1099,7 @@ void launch_dim_off(const SearchArgs& a, int T, int blocks, int threads, size_t 
 
 template <int DIM>
 void launch_dim(const SearchArgs& a, int T, int blocks, int threads, size_t lds, hipStream_t s) {
-  if (a.N < ((int64_t)1 << 29))
+  if (a.N * point_stride(DIM) * (int64_t)sizeof(double) < ((int64_t)1 << 32))
     launch_dim_off<DIM, true>(a, T, blocks, threads, lds, s);
   else
     launch_dim_off<DIM, false>(a, T, blocks, threads, lds, s);
