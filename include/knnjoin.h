@@ -93,6 +93,8 @@ typedef struct knn_join_stats {
   int64_t heavy_queries[KNN_MAX_LEVELS];  /* queries it took (one workgroup each) */
   int64_t heavy_failed[KNN_MAX_LEVELS];   /* of which failed */
   double heavy_cand[KNN_MAX_LEVELS];      /* their candidates in total */
+  int64_t spec_queries[KNN_MAX_LEVELS];   /* queries whose speculation held (no
+                                             collect pass) */
 } knn_join_stats;
 
 /* Options of the join calls.  Zero fields take the defaults in brackets. */
@@ -132,6 +134,10 @@ typedef struct knn_join_opts {
                              lists), so every load serves all of them; -1: each
                              query walks its own; 0 = automatic [1 in 5-6
                              dimensions, whose search is bound by the L2] */
+  int32_t speculate;      /* 0: the count pass keeps the candidates within a
+                             K-th distance predicted from the local density and,
+                             when they hold the K nearest, the collect pass is
+                             skipped for that query; -1: never [0] */
   knn_join_stats* stats;  /* optional statistics output */
 } knn_join_opts;
 

@@ -44,7 +44,8 @@ class JoinStats(ctypes.Structure):
                 ("refine_rounds", c_i64 * KNN_MAX_LEVELS),
                 ("tail_queries", c_i64), ("tail_rounds", c_i32), ("ms_tail", c_f64),
                 ("ms_heavy", c_f64 * KNN_MAX_LEVELS), ("heavy_queries", c_i64 * KNN_MAX_LEVELS),
-                ("heavy_failed", c_i64 * KNN_MAX_LEVELS), ("heavy_cand", c_f64 * KNN_MAX_LEVELS)]
+                ("heavy_failed", c_i64 * KNN_MAX_LEVELS), ("heavy_cand", c_f64 * KNN_MAX_LEVELS),
+                ("spec_queries", c_i64 * KNN_MAX_LEVELS)]
 
     def as_dict(self):
         L = self.levels
@@ -60,7 +61,8 @@ class JoinStats(ctypes.Structure):
                     ms_tail=self.ms_tail, ms_heavy=list(self.ms_heavy[:L]),
                     heavy_queries=list(self.heavy_queries[:L]),
                     heavy_failed=list(self.heavy_failed[:L]),
-                    heavy_cand=list(self.heavy_cand[:L]))
+                    heavy_cand=list(self.heavy_cand[:L]),
+                    spec_queries=list(self.spec_queries[:L]))
 
 
 class JoinOpts(ctypes.Structure):
@@ -70,6 +72,7 @@ class JoinOpts(ctypes.Structure):
                 ("tail_pairs", c_f64), ("heavy_min", ctypes.c_int64),
                 ("queue_grain", c_i32), ("item_order", c_i32), ("lanes_shift", c_i32),
                 ("share_lists", c_i32),
+                ("speculate", c_i32),
                 ("stats", ctypes.POINTER(JoinStats))]
 
 

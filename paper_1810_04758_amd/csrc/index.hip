@@ -529,12 +529,15 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.margin = (8.0 * (double)c.gg.g_max + 4.0 * idx.n + 32.0) * std::ldexp(1.0, -53);
     a.K = K;
     a.cap = cap;
+    a.spec_slots = o.speculate < 0 ? 0 : search_spec_slots(idx.n, T, cap);
+    a.spec_coef = search_spec_coef(idx.n, K, a.w);
     a.out_ids = d_ids;
     a.out_d = d_dists;
     a.fail_list = c.fail_list.p;
     a.fail_count = c.iscal.p + kFailSlot;
     a.refine_count = c.iscal.p + kRefineSlot;
     a.walk_error = c.iscal.p + kWalkErrSlot;
+    a.spec_count = c.iscal.p + kSpecSlot;
     lp.heavy_min = heavy_min;
     if (heavy_min > 0) {
       // heavy queries first, one workgroup each (count stays on the device)
@@ -580,11 +583,13 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     }
     ev.rec(2, s);
     int32_t sc[2] = {0, 0};
+    int32_t spec_held = 0;
     int64_t hq = 0, hf = 0;
     double hc = 0;
     if (rp) {
       sc[0] = rp->fails;
       sc[1] = rp->refine;
+      spec_held = rp->spec;
       hq = rp->heavy;
       hf = rp->heavy_failed;
       hc = rp->heavy_cand;
@@ -598,6 +603,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
                 "search: a candidate list was inconsistent with its count");
       sc[0] = cnt[kFailSlot];
       sc[1] = cnt[kRefineSlot];
+      spec_held = cnt[kSpecSlot];
       hq = cnt[kHeavySlot];
       hf = cnt[kHeavyFailSlot];
       uint64_t hcu = 0;
@@ -612,6 +618,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       lp.cand = cand;
       lp.fails = fails;
       lp.refine = sc[1];
+      lp.spec = spec_held;
       lp.heavy = hq;
       lp.heavy_failed = hf;
       lp.heavy_cand = hc;
@@ -624,6 +631,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       st->lanes[level] = T;
       st->cand_per_query[level] = cand;
       st->refine_rounds[level] = sc[1];
+      st->spec_queries[level] = spec_held;
       st->levels = level + 1;
       st->cell_width[level] = 1.0 / c.gg.inv_w;
       st->attempted[level] = A;
@@ -666,7 +674,7 @@ bool GraphPlan::matches(int32_t K_, const knn_join_opts& o, int32_t* ids_, doubl
          opts.growth == o.growth && opts.tail_pairs == o.tail_pairs &&
          opts.heavy_min == o.heavy_min && opts.queue_grain == o.queue_grain &&
          opts.item_order == o.item_order && opts.share_lists == o.share_lists &&
-         opts.lanes_shift == o.lanes_shift;
+         opts.lanes_shift == o.lanes_shift && opts.speculate == o.speculate;
 }
 
 GraphPlan::~GraphPlan() {
@@ -693,6 +701,7 @@ void stats_from_plan(const GraphPlan& gp, knn_join_stats* st) {
     st->lanes[L] = lp.T;
     st->cand_per_query[L] = lp.cand;
     st->refine_rounds[L] = lp.refine;
+    st->spec_queries[L] = lp.spec;
     st->heavy_queries[L] = lp.heavy;
     st->heavy_failed[L] = lp.heavy_failed;
     st->heavy_cand[L] = lp.heavy_cand;

@@ -92,6 +92,7 @@ struct LevelPlan {
   double cand = 0;
   int32_t fails = 0;
   int32_t refine = 0;
+  int32_t spec = 0;
   int64_t heavy = 0;
   int64_t heavy_failed = 0;
   double heavy_cand = 0;

@@ -18,7 +18,8 @@ constexpr int kHeavySlot = kRefineSlot + kLineInts;  // heavy queries
 constexpr int kHeavyFailSlot = kHeavySlot + kLineInts;      // of which failed (diagnostics)
 constexpr int kHeavyCandSlot = kHeavyFailSlot + kLineInts;  // their candidates (uint64)
 constexpr int kWalkErrSlot = kHeavyCandSlot + kLineInts;    // candidate-list overruns
-constexpr int kCounterInts = kWalkErrSlot + kLineInts;
+constexpr int kSpecSlot = kWalkErrSlot + kLineInts;          // speculations that held
+constexpr int kCounterInts = kSpecSlot + kLineInts;
 
 // Geometry of one grid level (Sec. 3.1): cell side 1/inv_w, origin lo.
 struct GridGeom {
@@ -174,6 +175,9 @@ struct SearchArgs {
   const int32_t* n_heavy;  // and their number (device)
   int32_t* heavy_fail;     // failures among them (diagnostics)
   int32_t* walk_error;     // candidate-list walks that ran past their list (must stay 0)
+  int32_t spec_slots;      // speculative survivor slots per query (0: off)
+  int32_t* spec_count;     // diagnostics: queries whose speculation held
+  double spec_coef;        // predicted K-th d2 = spec_coef * C^(-2/n), C = candidates of the cell
 };
 // Returns the number of waves per block used.
 void launch_search(const SearchArgs& a, int dims, int lanes_per_query, int grid_blocks,
@@ -184,6 +188,10 @@ constexpr int kHeavyThreads = 1024;
 void launch_search_heavy(const SearchArgs& a, int dims, int blocks, hipStream_t s);
 // Dynamic LDS bytes per wave for a given (lanes_per_query, cap).
 size_t search_lds_per_wave(int dims, int lanes_per_query, int cap);
+// Speculative survivor slots per query for a given (lanes_per_query, cap), and
+// the coefficient of the predicted K-th squared distance at cell side w.
+int search_spec_slots(int dims, int lanes_per_query, int cap);
+double search_spec_coef(int dims, int K, double w);
 int search_waves_per_block(int dims, int lanes_per_query, int cap);
 // Resident blocks per CU of the search kernel (occupancy API).
 int search_blocks_per_cu(int dims, int lanes_per_query, int cap);

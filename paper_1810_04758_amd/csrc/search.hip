@@ -198,6 +198,12 @@ __device__ __forceinline__ int group_incl_scan(int v, int l) {
   return v;
 }
 template <int T>
+__device__ __forceinline__ int group_sum_int(int v) {
+#pragma unroll
+  for (int o = 1; o < T; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <int T>
 __device__ __forceinline__ int group_min_int(int v) {
 #pragma unroll
   for (int o = 1; o < T; o <<= 1) v = min(v, __shfl_xor(v, o, 64));
@@ -412,15 +418,28 @@ k_search(const SearchArgs a) {
   // collect, and cap >= NB2/2 + 1).
   int32_t* bi_base = reinterpret_cast<int32_t*>(smem + (size_t)nwaves * cap * G);
   uint32_t* hist_base = reinterpret_cast<uint32_t*>(bi_base + (size_t)nwaves * cap * G);
-  int32_t* fbuf_base = reinterpret_cast<int32_t*>(hist_base + (size_t)nwaves * NB * G);
+  int32_t* fbuf_base = reinterpret_cast<int32_t*>(hist_base + (size_t)nwaves * (NB + 1) * G);
   uint32_t* seg_base = reinterpret_cast<uint32_t*>(fbuf_base + (size_t)nwaves * kFailBuf);
   double* bd = smem + (size_t)wave * cap * G;
   int32_t* bi = bi_base + (size_t)wave * cap * G;
-  uint32_t* hist = hist_base + (size_t)wave * NB * G;
+  uint32_t* hist = hist_base + (size_t)wave * (NB + 1) * G;
   uint32_t* hist2 = reinterpret_cast<uint32_t*>(bd);
   int32_t* fbuf = fbuf_base + (size_t)wave * kFailBuf;
   uint32_t* seg_of = seg_base + (size_t)wave * 2 * (R + 1) * G + (size_t)g * (R + 1);
   uint32_t* seg_ve = seg_of + (size_t)(R + 1) * G;
+  // speculative survivors of group g: slot k at spos[k * G + g] (SC slots),
+  // their count in hist[NB * G + g]
+  const int SC = a.spec_slots;
+  uint32_t* spos = seg_base + (size_t)nwaves * 2 * (R + 1) * G + (size_t)wave * SC * G;
+  // Speculation: the K-th squared distance of a query is predicted from the
+  // point density of its cell's 3^n block (C points in (3w)^n): a ball
+  // holding K points there has d^n = K (3w)^n / (C V_n), so
+  // d^2 = spec_coef * C^(-2/n), spec_coef including a safety factor.  The
+  // count pass keeps the positions of the candidates within that limit; if
+  // they turn out to hold at least K candidates (so all K nearest) without
+  // overflowing, the survivors are bucketed from them and the collect pass
+  // over the whole list is skipped.
+  int spec_held = 0;  // wavefront total (lane 0), added to a.spec_count at the end
 
   const uint64_t lane_lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
@@ -482,6 +501,8 @@ k_search(const SearchArgs a) {
     const uint32_t Cq = in ? a.cand[cell] : 0u;
     // heavy queries are handled by k_search_heavy
     const bool valid = in && (a.heavy_min == 0 || Cq < a.heavy_min);
+    const double dpred =
+        SC > 0 && Cq > 0 ? a.spec_coef * (double)powf((float)Cq, -2.0f / DIM) : -1.0;
     const int nr = valid ? (int)a.nrng[cell] : 0;
     double mfrac = 0.5;
     bool full = true;
@@ -526,7 +547,7 @@ k_search(const SearchArgs a) {
     // ---- count pass over the segments that can hold a point within thr -----
     uint32_t C =
         build_list<DIM, T>(rg, rs, nr, nr_w, !full, thr, qx, a, l, seg_of, seg_ve, shared);
-    for (int b = l; b < NB; b += T) hist[b * G + g] = 0;
+    for (int b = l; b <= NB; b += T) hist[b * G + g] = 0;
     wave_fence();
     {
       LWalk cs;
@@ -538,6 +559,10 @@ k_search(const SearchArgs a) {
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           if (!(d2[u] > thr)) atomicAdd(&hist[bin_clamped<DIM>(d2[u], top0) * G + g], 1u);
+          if (d2[u] <= dpred && p[u] != q32) {
+            const uint32_t k = atomicAdd(&hist[NB * G + g], 1u);
+            if ((int)k < SC) spos[k * G + g] = p[u];
+          }
         }
       };
       uint32_t v = l;
@@ -610,10 +635,22 @@ k_search(const SearchArgs a) {
       }
     }
 
+    // ---- speculation outcome ------------------------------------------------
+    // The kept candidates (d2 <= dpred) number sn.  sn >= K puts the K-th
+    // smallest d2 at or below dpred, so they include every candidate of the
+    // bins below bsel and every candidate of bin bsel that can rank below K
+    // (any other has d2 > dpred, so K candidates precede it).
+    const int sn = (int)hist[NB * G + g];
+    const bool spec = ok && c_hi <= cap && sn >= K && sn <= SC;
+    {
+      const int held = (int)__popcll(__ballot(spec && l == 0));
+      if (lane == 0) spec_held += held;
+    }
+
     // ---- list for the remaining passes: only bins up to the selected one ----
     const double lim2 = ok ? bins_limit<DIM>(bsel, thr, top0) : 0.0;
-    C = build_list<DIM, T>(rg, rs, ok ? nr : 0, nr_w, true, lim2, qx, a, l, seg_of, seg_ve,
-                           shared);
+    C = build_list<DIM, T>(rg, rs, ok && !spec ? nr : 0, nr_w, true, lim2, qx, a, l, seg_of,
+                           seg_ve, shared);
     wave_fence();
 
     // ---- exact refinement when the selected bin overflows the buffer -------
@@ -729,7 +766,8 @@ k_search(const SearchArgs a) {
             acc = b <= bsel;
           // only queries that selected a bin collect: a failed or empty slot
           // walking a shared list has bsel == NB, and bin NB is not a bucket
-          if (ok && p != q32 && acc) {
+          // (a speculating query collects from its kept candidates below)
+          if (ok && !spec && p != q32 && acc) {
             const uint32_t s = atomicAdd(&hist[b * G + g], 1u);
             if ((int)s < cap) {
               bd[s * G + g] = d2;
@@ -748,6 +786,21 @@ k_search(const SearchArgs a) {
         uint32_t pp[kUnroll];
         batch_pos<T, kUnroll, false>(cs, v, C, q32, pp);
         collect(pp);
+      }
+    }
+    if (spec) {
+      // the kept candidates of bins up to bsel, into their buckets
+      for (int k = l; k < sn; k += T) {
+        const uint32_t p = spos[k * G + g];
+        const double d2 = sq_dist<DIM, OFF32>(Xs, p, qx);
+        const int b = bin_of<DIM>(d2, thr, top0);
+        if (b <= bsel) {
+          const uint32_t s = atomicAdd(&hist[b * G + g], 1u);
+          if ((int)s < cap) {
+            bd[s * G + g] = d2;
+            bi[s * G + g] = perm[p];
+          }
+        }
       }
     }
     wave_fence();
@@ -783,6 +836,7 @@ k_search(const SearchArgs a) {
     wave_fence();
   }
   if (nfail > 0) flush_failures(a, fbuf, nfail, lane);
+  if (lane == 0 && spec_held > 0 && a.spec_count) atomicAdd(a.spec_count, spec_held);
 }
 
 // The same search for one query per workgroup of kHeavyThreads lanes: the
@@ -1107,12 +1161,41 @@ void launch_dim(const SearchArgs& a, int T, int blocks, int threads, size_t lds,
 
 }  // namespace
 
-size_t search_lds_per_wave(int dims, int T, int cap) {
+static size_t lds_base_per_wave(int dims, int T, int cap) {
   const int G = 64 / T;
   size_t R = 1;
   for (int j = 0; j < dims - 1; ++j) R *= 3;
-  return (size_t)cap * G * (sizeof(double) + sizeof(int32_t)) + (size_t)NB * G * sizeof(uint32_t) +
-         (size_t)kFailBuf * sizeof(int32_t) + 2 * (R + 1) * G * sizeof(uint32_t);
+  return (size_t)cap * G * (sizeof(double) + sizeof(int32_t)) +
+         (size_t)(NB + 1) * G * sizeof(uint32_t) + (size_t)kFailBuf * sizeof(int32_t) +
+         2 * (R + 1) * G * sizeof(uint32_t);
+}
+
+// Speculative slots per query: twice the survivor buffer, but only what the
+// per-wave budget of 16 KiB leaves beside the other buffers; none when that
+// is below cap (a speculation needs room for more than K).
+int search_spec_slots(int dims, int T, int cap) {
+  const int G = 64 / T;
+  const size_t base = lds_base_per_wave(dims, T, cap);
+  const int room = base < 16384 ? (int)((16384 - base) / (G * sizeof(uint32_t))) : 0;
+  const int sc = std::min(2 * cap, room);
+  return sc >= cap ? sc : 0;
+}
+
+// Coefficient of the predicted K-th squared distance, spec_coef * C^(-2/n)
+// for C points in the 3^n block of cells of side w: f w^2 (K 3^n / V_n)^(2/n)
+// with V_n the volume of the unit n-ball and f = 1.7^(2/n), which lets the
+// kept set hold 1.7 K points when the density is uniform (the prediction
+// then misses only for queries whose K-th distance is well above the local
+// mean).
+double search_spec_coef(int dims, int K, double w) {
+  const double n = dims;
+  const double vn = std::pow(M_PI, n / 2) / std::tgamma(n / 2 + 1);
+  return std::pow(1.7, 2.0 / n) * w * w * std::pow(K * std::pow(3.0, n) / vn, 2.0 / n);
+}
+
+size_t search_lds_per_wave(int dims, int T, int cap) {
+  return lds_base_per_wave(dims, T, cap) +
+         (size_t)(64 / T) * search_spec_slots(dims, T, cap) * sizeof(uint32_t);
 }
 
 int search_waves_per_block(int dims, int T, int cap) {

@@ -351,6 +351,27 @@ def test_heavy_queries(knn, oracle_mod, name, gen, K, heavy_min):
         assert not any(st["heavy_queries"])
 
 
+@pytest.mark.parametrize("speculate", [0, -1])
+@pytest.mark.parametrize("name,gen,K,lanes", [
+    ("expo4d_k24", lambda: datagen.exponential(9000, 4, seed=61), 24, 8),
+    ("unif6d_k16", lambda: datagen.uniform(7000, 6, seed=62), 16, 16),
+    ("expo2d_k40", lambda: datagen.exponential(8000, 2, seed=63), 40, 8),
+    ("unif3d_k7", lambda: datagen.uniform(6000, 3, seed=64), 7, 4),
+], ids=["expo4d_k24", "unif6d_k16", "expo2d_k40", "unif3d_k7"])
+def test_speculation(knn, oracle_mod, speculate, name, gen, K, lanes):
+    """Survivors kept during the count pass (collect pass skipped when they
+    hold the K nearest) or always collected: the oracle's result either way,
+    and with speculation on, some queries of the first level speculate."""
+    D = gen()
+    _say(f"[spec] {name} speculate={speculate} lanes={lanes}")
+    ids, dists, st = _join(knn, D, K, speculate=speculate, lanes_per_query=lanes, tail_pairs=-1)
+    _check_rows(D, ids, dists, K, np.arange(D.shape[0]), oracle_mod)
+    if speculate < 0:
+        assert not any(st["spec_queries"])
+    else:
+        assert 0 < st["spec_queries"][0] <= st["attempted"][0] - st["failed"][0]
+
+
 @pytest.mark.parametrize("share", [1, -1])
 @pytest.mark.parametrize("name,gen,K,lanes", [
     ("unif6d_t4", lambda: datagen.uniform(6000, 6, seed=51), 12, 4),
