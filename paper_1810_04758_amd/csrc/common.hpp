@@ -86,9 +86,14 @@ struct DevBuf {
     p = static_cast<T*>(device_acquire(count * sizeof(T), &dev, &cap));
     n = cap / sizeof(T);
   }
-  // Grow to at least `count` elements (contents not preserved).
-  void reserve(size_t count) {
-    if (count > n || p == nullptr) alloc(count);
+  // Grow to at least `count` elements (contents not preserved); true when
+  // the buffer was (re)allocated.
+  bool reserve(size_t count) {
+    if (count > n || p == nullptr) {
+      alloc(count);
+      return true;
+    }
+    return false;
   }
   void release() {
     if (p) device_release(p, dev, n * sizeof(T));

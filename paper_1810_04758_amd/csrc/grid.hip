@@ -92,10 +92,8 @@ __global__ void k_bounds_final(const double* __restrict__ part, int nparts, int 
 }
 
 // --------------------------------------------------------------------------
-// exclusive scan of uint32 (reduce, scan partials, apply)
+// exclusive scan of uint32
 // --------------------------------------------------------------------------
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kBlock * kScanItems;
 
 __device__ inline uint32_t wave_incl_scan(uint32_t v) {
   const int lane = threadIdx.x & 63;
@@ -126,53 +124,163 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
   return base + inc - v;
 }
 
-__global__ void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
-                              uint32_t* __restrict__ part) {
-  int64_t base = (int64_t)blockIdx.x * kScanTile;
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
-    if (i < n) s += in[i];
-  }
-  uint32_t tot;
-  block_excl_scan(s, &tot);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
+// Single-pass exclusive scan with decoupled look-back.  Tiles are taken in
+// ticket order (an atomic counter), so every tile a block waits for belongs to
+// a block that is already running.  A block publishes its tile's sum at once;
+// then its first wavefront reads the words of the 64 preceding tiles at a
+// time, adds the sums up to the nearest inclusive prefix (or all 64, and goes
+// on further back), and the block publishes its own inclusive prefix.
+// Status word per tile: flag (bit 63 inclusive prefix, bit 62 tile sum),
+// epoch (bits 32..61), value (bits 0..31).  The epoch advances once per scan
+// (the block with the last ticket moves it on and resets the ticket; the
+// next scan on the stream starts after this one ends), so the words of
+// earlier scans never need clearing.  A look-back that waits more
+// than kScanSpinLimit rounds counts an error in state[2] and stops.
+constexpr uint64_t kFlagInc = 1ull << 63;
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint32_t kEpochMask = (1u << 30) - 1;
+constexpr uint32_t kScanSpinLimit = 1u << 20;
+constexpr int kOneItems = 32;
+constexpr int kLookWords = 4;
+constexpr int kOneTile = kBlock * kOneItems;
 
-// Single-block exclusive scan of the partials in place; total to *total.
-__global__ void k_scan_partials(uint32_t* part, int64_t np, uint32_t* total) {
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < np; base += kBlock) {
-    int64_t i = base + threadIdx.x;
-    uint32_t v = i < np ? part[i] : 0;
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(v, &tot);
-    if (i < np) part[i] = carry + ex;
-    carry += tot;
+template <bool VEC>
+__global__ void __launch_bounds__(kBlock)
+k_scan_onepass(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t n, int64_t nb,
+               uint32_t* __restrict__ state, uint32_t* __restrict__ total) {
+  __shared__ uint32_t s_tile, s_epoch, s_excl;
+  // state[0..1]: one 64-bit word, ticket (low half) and epoch (high half), so
+  // a block takes both in one atomic; the status words carry their values,
+  // so every access here is a relaxed device-scope atomic (no cache
+  // write-back or invalidation)
+  unsigned long long* te = reinterpret_cast<unsigned long long*>(state);
+  unsigned long long* status = reinterpret_cast<unsigned long long*>(state + 4);
+  if (threadIdx.x == 0) {
+    const unsigned long long old =
+        __hip_atomic_fetch_add(te, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t t = (uint32_t)old;
+    const uint32_t e = (uint32_t)(old >> 32) & kEpochMask;
+    if ((int64_t)t == nb - 1)  // every ticket is taken: reset it, next epoch
+      __hip_atomic_store(te, (unsigned long long)((e + 1) & kEpochMask) << 32, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    s_tile = t;
+    s_epoch = e;
   }
-  if (threadIdx.x == 0 && total) *total = carry;
-}
-
-__global__ void k_scan_apply(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                             int64_t n, const uint32_t* __restrict__ part) {
-  // thread t owns kScanItems consecutive elements of the tile
-  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t s = 0;
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const uint32_t ep = s_epoch;
+  const uint64_t etag = (uint64_t)ep << 32;
+  // thread t owns kOneItems consecutive elements of the tile
+  const int64_t base = tile * kOneTile + (int64_t)threadIdx.x * kOneItems;
+  const bool whole = VEC && base + kOneItems <= n;
+  uint32_t v[kOneItems];
+  if (whole) {
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    int64_t i = base + k;
-    v[k] = i < n ? in[i] : 0;
-    s += v[k];
+    for (int k = 0; k < kOneItems / 4; ++k) {
+      const uint4 q = reinterpret_cast<const uint4*>(in + base)[k];
+      v[4 * k] = q.x;
+      v[4 * k + 1] = q.y;
+      v[4 * k + 2] = q.z;
+      v[4 * k + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kOneItems; ++k) v[k] = base + k < n ? in[base + k] : 0u;
   }
-  uint32_t tot;
-  uint32_t ex = block_excl_scan(s, &tot) + part[blockIdx.x];
+  uint32_t sum = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    int64_t i = base + k;
-    if (i < n) out[i] = ex;
-    ex += v[k];
+  for (int k = 0; k < kOneItems; ++k) sum += v[k];
+  uint32_t agg;
+  uint32_t ex = block_excl_scan(sum, &agg);
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&status[tile], (tile == 0 ? kFlagInc : kFlagAgg) | etag | agg,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < 64 && tile > 0) {
+    // a window of kLookWords x 64 predecessors per round, all loads in flight
+    // together: predecessor j - (lane + 64 k) is word k of lane `lane`
+    const int lane = threadIdx.x;
+    uint32_t excl = 0;
+    uint32_t spins = 0;
+    int64_t j = tile - 1;
+    for (;;) {
+      unsigned long long w[kLookWords];
+#pragma unroll
+      for (int k = 0; k < kLookWords; ++k) {
+        const int64_t idx = j - lane - 64 * k;
+        // before tile 0: an inclusive prefix of 0
+        w[k] = idx >= 0 ? __hip_atomic_load(&status[idx], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)
+                        : (kFlagInc | etag);
+      }
+      // nearest inclusive prefix: word kp, lane lp (kp = kLookWords: none)
+      int kp = kLookWords, lp = 63;
+      bool ready = true;
+#pragma unroll
+      for (int k = 0; k < kLookWords; ++k) {
+        if (kp < kLookWords) break;
+        const bool valid = (w[k] & (kFlagInc | kFlagAgg)) != 0 &&
+                           (uint32_t)((w[k] >> 32) & kEpochMask) == ep;
+        const uint64_t pm = __ballot(valid && (w[k] & kFlagInc) != 0);
+        const uint64_t vm = __ballot(valid);
+        const int last = pm ? __builtin_ctzll(pm) : 63;
+        const uint64_t need = last == 63 ? ~0ull : ((2ull << last) - 1ull);
+        if ((vm & need) != need) {
+          ready = false;
+          break;
+        }
+        if (pm) {
+          kp = k;
+          lp = last;
+        }
+      }
+      if (!ready) {
+        if (++spins > kScanSpinLimit) {
+          if (lane == 0) atomicAdd(state + 2, 1u);
+          break;
+        }
+        continue;
+      }
+      uint32_t part = 0;
+#pragma unroll
+      for (int k = 0; k < kLookWords; ++k)
+        if (k < kp || (k == kp && lane <= lp)) part += (uint32_t)w[k];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+      excl += part;
+      if (kp < kLookWords) break;
+      j -= 64 * kLookWords;
+    }
+    if (lane == 0) {
+      __hip_atomic_store(&status[tile], kFlagInc | etag | (uint32_t)(excl + agg),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = excl;
+    }
+  } else if (threadIdx.x == 0) {
+    s_excl = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && tile == nb - 1 && total) *total = s_excl + agg;
+  ex += s_excl;
+  if (whole) {
+#pragma unroll
+    for (int k = 0; k < kOneItems / 4; ++k) {
+      uint4 q;
+      q.x = ex;
+      ex += v[4 * k];
+      q.y = ex;
+      ex += v[4 * k + 1];
+      q.z = ex;
+      ex += v[4 * k + 2];
+      q.w = ex;
+      ex += v[4 * k + 3];
+      reinterpret_cast<uint4*>(out + base)[k] = q;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kOneItems; ++k) {
+      if (base + k < n) out[base + k] = ex;
+      ex += v[k];
+    }
   }
 }
 
@@ -654,31 +762,36 @@ void launch_bounds(const double* X, int64_t N, int n, double* part, double* lo, 
   KNN_LAUNCHED();
 }
 
-size_t scan_tmp_elems(int64_t n) { return (size_t)ceil_div(n, kScanTile) + 1; }
+size_t scan_state_elems(int64_t n) {
+  // scans of up to n elements, or of a radix histogram of n keys
+  const int64_t m = std::max<int64_t>(n, ((int64_t)1 << kMaxDigitBits) * ceil_div(n, kRadixTile));
+  return 4 + 2 * (size_t)(ceil_div(m, kOneTile) + 1);
+}
 
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
-                           uint32_t* tmp, hipStream_t s) {
+                           uint32_t* state, int64_t state_elems, hipStream_t s) {
   if (n <= 0) {
     if (total) launch_zero(total, sizeof(uint32_t), s);
     return;
   }
-  int64_t nb = ceil_div(n, kScanTile);
-  k_scan_reduce<<<(unsigned)nb, kBlock, 0, s>>>(in, n, tmp);
-  KNN_LAUNCHED();
-  k_scan_partials<<<1, kBlock, 0, s>>>(tmp, nb, total);
-  KNN_LAUNCHED();
-  k_scan_apply<<<(unsigned)nb, kBlock, 0, s>>>(in, out, n, tmp);
+  const int64_t nb = ceil_div(n, kOneTile);
+  KNN_CHECK(4 + 2 * nb <= state_elems, KNN_EINTERNAL, "scan state too small");
+  const bool vec = ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0);
+  if (vec)
+    k_scan_onepass<true><<<(unsigned)nb, kBlock, 0, s>>>(in, out, n, nb, state, total);
+  else
+    k_scan_onepass<false><<<(unsigned)nb, kBlock, 0, s>>>(in, out, n, nb, state, total);
   KNN_LAUNCHED();
 }
 
 size_t radix_tmp_elems(int64_t n) {
   int64_t nb = ceil_div(n, kRadixTile);
-  const int64_t cnt = ((int64_t)1 << kMaxDigitBits) * nb;
-  return (size_t)cnt + scan_tmp_elems(cnt);
+  return (size_t)(((int64_t)1 << kMaxDigitBits) * nb);
 }
 
 bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
-                      int64_t n, int bits, uint32_t* tmp, hipStream_t s) {
+                      int64_t n, int bits, uint32_t* tmp, uint32_t* state, int64_t state_elems,
+                      hipStream_t s) {
   if (n <= 1 || bits <= 0) return false;
   int64_t nb = ceil_div(n, kRadixTile);
   // 11-bit digits when they save a pass, else 8-bit (smaller LDS tables)
@@ -686,7 +799,6 @@ bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* v
   const int passes = (bits + DB - 1) / DB;
   const int64_t cnt = ((int64_t)1 << DB) * nb;
   uint32_t* hist = tmp;
-  uint32_t* stmp = tmp + cnt;
   uint64_t* src_k = keys;
   int32_t* src_v = vals;
   uint64_t* dst_k = keys2;
@@ -698,7 +810,7 @@ bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* v
     else
       k_radix_hist<8><<<(unsigned)nb, kBlock, 0, s>>>(src_k, n, shift, hist, nb);
     KNN_LAUNCHED();
-    launch_exclusive_scan(hist, hist, cnt, nullptr, stmp, s);
+    launch_exclusive_scan(hist, hist, cnt, nullptr, state, state_elems, s);
     if (DB == 11)
       k_radix_scatter<11><<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb,
                                                           dst_k, dst_v);
@@ -728,12 +840,12 @@ void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* 
 }
 
 void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags, uint32_t* cell_of,
-                      uint64_t* cell_key, uint32_t* cell_start, uint32_t* d_M, uint32_t* tmp,
-                      hipStream_t s) {
+                      uint64_t* cell_key, uint32_t* cell_start, uint32_t* d_M, uint32_t* state,
+                      int64_t state_elems, hipStream_t s) {
   int nb = grid_for(N);
   k_mark_cells<<<nb, kBlock, 0, s>>>(sorted_keys, N, flags);
   KNN_LAUNCHED();
-  launch_exclusive_scan(flags, cell_of, N, d_M, tmp, s);
+  launch_exclusive_scan(flags, cell_of, N, d_M, state, state_elems, s);
   k_emit_cells<<<nb, kBlock, 0, s>>>(sorted_keys, flags, cell_of, N, cell_of, cell_key,
                                      cell_start);
   KNN_LAUNCHED();

@@ -194,15 +194,19 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s) {
   c.keys2.reserve(N);
   c.vals2.reserve(N);
   c.flags.reserve(N);
-  c.tmp.reserve(std::max(radix_tmp_elems(N), scan_tmp_elems(N)));
+  c.tmp.reserve(radix_tmp_elems(N));
+  // scan state: zero-filled once per allocation (it carries the scans' epoch)
+  if (c.scan_state.reserve(scan_state_elems(N)))
+    launch_zero(c.scan_state.p, c.scan_state.bytes(), s);
   c.scal.reserve(4);
   launch_cell_keys(idx.X.p, N, c.gg, c.keys.p, c.perm.p, s);
-  if (radix_sort_pairs(c.keys.p, c.perm.p, c.keys2.p, c.vals2.p, N, c.gg.key_bits, c.tmp.p, s)) {
+  if (radix_sort_pairs(c.keys.p, c.perm.p, c.keys2.p, c.vals2.p, N, c.gg.key_bits, c.tmp.p,
+                       c.scan_state.p, (int64_t)c.scan_state.n, s)) {
     std::swap(c.keys, c.keys2);  // sorted output is in the scratch pair
     std::swap(c.perm, c.vals2);
   }
   build_cell_table(c.keys.p, N, c.flags.p, c.cell_of.p, c.cell_key.p, c.cell_start.p, c.scal.p,
-                   c.tmp.p, s);
+                   c.scan_state.p, (int64_t)c.scan_state.n, s);
   launch_gather_points(idx.XA.p, c.perm.p, N, n, c.Xs.p, s);
   // The number of cells M stays on the device (kernels read it there), so the
   // level is built without a host round trip; per-cell arrays are sized for
@@ -278,6 +282,7 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   b += std::max<uint64_t>(256 * N, 32ull << 20);  // dense key table or row table
   b += (16 + 4 + 4) * N;               // keys, keys2, vals2, flags
   b += (uint64_t)radix_tmp_elems((int64_t)N) * 4;
+  b += (uint64_t)scan_state_elems((int64_t)N) * 4;
   b += (4 + 4 + 1 + 1 + 4) * N;        // active, fail_list, failed, cell_active, heavy
   b += 24 * N;                         // work-item keys and order (at most one item per query)
   b += std::min<uint64_t>(N, 65535) * (512 + cap * 12);  // brute-force tail scratch
@@ -422,7 +427,8 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       // keys2 (scratch of the level's sort) holds the exclusive scan
       uint32_t* ex = reinterpret_cast<uint32_t*>(c.keys2.p);
       launch_failed_flags(c.failed.p, c.perm.p, N, c.flags.p, s);
-      launch_exclusive_scan(c.flags.p, ex, N, c.scal.p + 1, c.tmp.p, s);
+      launch_exclusive_scan(c.flags.p, ex, N, c.scal.p + 1, c.scan_state.p,
+                            (int64_t)c.scan_state.n, s);
       launch_compact_positions(c.flags.p, ex, N, c.active.p, s);
       active = c.active.p;
       // neighbour ranges only for the cells that hold an active query
@@ -492,7 +498,8 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       c.ivals2.reserve(n_items);
       launch_item_keys(active, A, G, c.cell_of.p, c.cand_count.p, c.ikeys.p, c.ivals.p, n_items,
                        s);
-      if (radix_sort_pairs(c.ikeys.p, c.ivals.p, c.ikeys2.p, c.ivals2.p, n_items, 9, c.tmp.p, s)) {
+      if (radix_sort_pairs(c.ikeys.p, c.ivals.p, c.ikeys2.p, c.ivals2.p, n_items, 9, c.tmp.p,
+                           c.scan_state.p, (int64_t)c.scan_state.n, s)) {
         std::swap(c.ikeys, c.ikeys2);
         std::swap(c.ivals, c.ivals2);
       }
@@ -598,9 +605,12 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       int32_t* cnt = c.pinned.p;
       KNN_HIP(hipMemcpyAsync(cnt, c.iscal.p, kCounterInts * sizeof(int32_t), hipMemcpyDeviceToHost,
                              s));
+      KNN_HIP(hipMemcpyAsync(cnt + kCounterInts, c.scan_state.p + 2, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));
       KNN_CHECK(cnt[kWalkErrSlot] == 0, KNN_EINTERNAL,
                 "search: a candidate list was inconsistent with its count");
+      KNN_CHECK(cnt[kCounterInts] == 0, KNN_EINTERNAL, "scan: a look-back found no prefix");
       sc[0] = cnt[kFailSlot];
       sc[1] = cnt[kRefineSlot];
       spec_held = cnt[kSpecSlot];

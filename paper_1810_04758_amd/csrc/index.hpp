@@ -54,6 +54,7 @@ struct JoinContext {
   DevBuf<uint64_t> keys, keys2;
   DevBuf<int32_t> vals2;
   DevBuf<uint32_t> flags, tmp;
+  DevBuf<uint32_t> scan_state;  // single-pass scan epoch, ticket, tile words
   DevBuf<uint32_t> scal;  // [0] = M, [1] = active count
   DevBuf<int32_t> iscal;  // level counters (kCounterInts, one 128-byte line each)
   DevBuf<int32_t> active, fail_list;

@@ -43,30 +43,35 @@ void launch_bounds(const double* X, int64_t N, int n, double* part, double* lo, 
                    hipStream_t s);
 
 // ---- scan (grid.hip) ----
-// Exclusive scan of n uint32 values (out may equal in).  If total != nullptr the
-// sum of all values is written there (device).  tmp: scan_tmp_elems(n) uint32.
-size_t scan_tmp_elems(int64_t n);
+// Exclusive scan of n uint32 values (out may equal in) in one pass.  If
+// total != nullptr the sum of all values is written there (device).  state:
+// state_elems >= scan_state_elems(n) uint32 owned by one stream's work,
+// zero-filled once when allocated and kept between scans (it carries the
+// scans' epoch and ticket); state[2] counts look-back errors (must stay 0).
+size_t scan_state_elems(int64_t n);
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
-                           uint32_t* tmp, hipStream_t s);
+                           uint32_t* state, int64_t state_elems, hipStream_t s);
 
 // ---- radix sort (grid.hip) ----
 // Stable LSD sort of (key, val) pairs by the low `bits` bits of the keys.
 // keys/vals hold the input; keys2/vals2 are same-size scratch; tmp:
-// radix_tmp_elems(n) uint32.  Returns true when the sorted output ended up in
-// keys2/vals2 (odd number of passes), false when it is in keys/vals.
+// radix_tmp_elems(n) uint32; state: scan state (launch_exclusive_scan).
+// Returns true when the sorted output ended up in keys2/vals2 (odd number of
+// passes), false when it is in keys/vals.
 size_t radix_tmp_elems(int64_t n);
 bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
-                      int64_t n, int bits, uint32_t* tmp, hipStream_t s);
+                      int64_t n, int bits, uint32_t* tmp, uint32_t* state, int64_t state_elems,
+                      hipStream_t s);
 
 // ---- grid level construction (grid.hip) ----
 // keys[i] = cell key of point i (original order, SoA X); vals[i] = i.
 void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* keys,
                       int32_t* vals, hipStream_t s);
 // From sorted keys: flags -> scan -> cell table.  cell_of (N), cell_key (N),
-// cell_start (N+1), d_M (device scalar) written.  tmp: scan tmp.
+// cell_start (N+1), d_M (device scalar) written.  state: scan state.
 void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags,
                       uint32_t* cell_of, uint64_t* cell_key, uint32_t* cell_start,
-                      uint32_t* d_M, uint32_t* tmp, hipStream_t s);
+                      uint32_t* d_M, uint32_t* state, int64_t state_elems, hipStream_t s);
 // Doubles per point in the sorted coordinate array: n rounded up to even, so
 // a point is whole 16-byte pairs (a padding coordinate is 0).
 inline constexpr int point_stride(int n) { return (n + 1) & ~1; }
