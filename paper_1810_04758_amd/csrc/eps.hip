@@ -49,14 +49,15 @@ constexpr int kSampleChunk = 256;
 constexpr int kMaxBins = 4096;
 
 // Bin of a distance, floor(sqrt(d2) * inv_bw) with the correctly rounded
-// square root.  The hardware square root (not correctly rounded, but within
-// far less than 2^-20 relative) decides the bin unless the scaled value lies
-// within 2^-20 of a bin edge; only then is the exact square root taken.
-__device__ __forceinline__ double dist_bin(double d2, double inv_bw) {
-  const double t = __builtin_amdgcn_sqrt(d2) * inv_bw;
-  const double r = rint(t);
-  if (fabs(t - r) > t * 0x1p-20 + 0x1p-1000) return floor(t);
-  return floor(sqrt(d2) * inv_bw);
+// square root.  A single-precision estimate (relative error below 2^-21:
+// the conversion of d2, the hardware square root and two products) decides
+// the bin unless it lies within 2^-18 (relative) of an integer; only then is
+// the double-precision value taken.
+__device__ __forceinline__ int dist_bin(double d2, double inv_bw, float inv_bw_f) {
+  const float t = __builtin_amdgcn_sqrtf((float)d2) * inv_bw_f;
+  const float r = rintf(t);
+  if (fabsf(t - r) > t * 0x1p-18f) return (int)floorf(t);
+  return (int)floor(sqrt(d2) * inv_bw);
 }
 
 // Each thread takes points j; the sample points of a chunk sit in LDS.  The
@@ -67,6 +68,7 @@ __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N,
                                  const int64_t* __restrict__ sample, int64_t ns, double inv_bw,
                                  int n_bins, double skip_d2, uint64_t* __restrict__ counts) {
   __shared__ uint32_t h[kMaxBins];
+  const float inv_bw_f = (float)inv_bw;
   __shared__ double sx[DIM][kSampleChunk];
   __shared__ int64_t sid[kSampleChunk];
   for (int b = threadIdx.x; b < n_bins; b += blockDim.x) h[b] = 0;
@@ -93,8 +95,8 @@ __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N,
           s = __dadd_rn(s, __dmul_rn(t, t));
         }
         if (s > skip_d2 || p == sid[i]) continue;  // certainly beyond the last bin, or self
-        const double t = dist_bin(s, inv_bw);
-        if (t < (double)n_bins) atomicAdd(&h[(int)t], 1u);
+        const int b = dist_bin(s, inv_bw, inv_bw_f);
+        if (b < n_bins) atomicAdd(&h[b], 1u);
       }
     }
   }
