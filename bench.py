@@ -41,11 +41,13 @@ def alg_bytes(stats, n, K):
     per query it searched, its own coordinates (8n) and cell/row metadata (8),
     plus the output row (12K: int32 id + fp64 distance per neighbour) when it
     succeeds or its id (4) when it fails.  Queries handed to the heavy-query
-    kernel are not k_search's."""
+    kernel, and queries deferred to the next level before the search, are not
+    k_search's."""
     total = 0
     for L, (a, f) in enumerate(zip(stats["attempted"], stats["failed"])):
         h, hf = stats["heavy_queries"][L], stats["heavy_failed"][L]
-        a, f = a - h, f - hf
+        d = stats["deferred"][L]
+        a, f = a - h - d, f - hf - d
         total += a * (8 * n + 8) + (a - f) * 12 * K + f * 4
     return total
 
@@ -53,9 +55,11 @@ def alg_bytes(stats, n, K):
 def alg_ops(stats, n):
     """Algorithmic FP64 operations of k_search over one join: per candidate of
     the 3^n cells of every query it searched, n subtractions, n
-    multiplications, n-1 additions and one comparison (3n)."""
-    return sum((a * c - hc) * 3 * n for a, c, hc in
-               zip(stats["attempted"], stats["cand_per_query"], stats["heavy_cand"]))
+    multiplications, n-1 additions and one comparison (3n).  The mean
+    candidate count is over the queries searched (not deferred)."""
+    return sum(((a - d) * c - hc) * 3 * n for a, d, c, hc in
+               zip(stats["attempted"], stats["deferred"], stats["cand_per_query"],
+                   stats["heavy_cand"]))
 
 
 def kernel_source_hash():

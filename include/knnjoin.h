@@ -84,7 +84,8 @@ typedef struct knn_join_stats {
   int64_t total_failed;       /* sum of failed: fraction = failed/attempted */
   int32_t lanes_per_query;    /* t of level 0 */
   int32_t lanes[KNN_MAX_LEVELS];          /* t used at each level */
-  double cand_per_query[KNN_MAX_LEVELS];  /* mean candidates per active query */
+  double cand_per_query[KNN_MAX_LEVELS];  /* mean candidates per searched query
+                                             (active and not deferred) */
   int64_t refine_rounds[KNN_MAX_LEVELS];  /* exact-bisection rounds (crowded bins) */
   int64_t tail_queries;       /* queries finished by the brute-force tail */
   int32_t tail_rounds;        /* its exact-bisection rounds */
@@ -95,6 +96,8 @@ typedef struct knn_join_stats {
   double heavy_cand[KNN_MAX_LEVELS];      /* their candidates in total */
   int64_t spec_queries[KNN_MAX_LEVELS];   /* queries whose speculation held (no
                                              collect pass) */
+  int64_t deferred[KNN_MAX_LEVELS];       /* queries deferred to the next level
+                                             without a count pass (in failed) */
 } knn_join_stats;
 
 /* Options of the join calls.  Zero fields take the defaults in brackets. */
@@ -138,6 +141,10 @@ typedef struct knn_join_opts {
                              K-th distance predicted from the local density and,
                              when they hold the K nearest, the collect pass is
                              skipped for that query; -1: never [0] */
+  int32_t predict_fail;   /* 0: a query whose K-th distance, predicted from the
+                             local density, exceeds its covered radius by a
+                             margin goes to the next level without searching
+                             this one (results are unchanged); -1: never [0] */
   knn_join_stats* stats;  /* optional statistics output */
 } knn_join_opts;
 

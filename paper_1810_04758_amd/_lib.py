@@ -45,7 +45,8 @@ class JoinStats(ctypes.Structure):
                 ("tail_queries", c_i64), ("tail_rounds", c_i32), ("ms_tail", c_f64),
                 ("ms_heavy", c_f64 * KNN_MAX_LEVELS), ("heavy_queries", c_i64 * KNN_MAX_LEVELS),
                 ("heavy_failed", c_i64 * KNN_MAX_LEVELS), ("heavy_cand", c_f64 * KNN_MAX_LEVELS),
-                ("spec_queries", c_i64 * KNN_MAX_LEVELS)]
+                ("spec_queries", c_i64 * KNN_MAX_LEVELS),
+                ("deferred", c_i64 * KNN_MAX_LEVELS)]
 
     def as_dict(self):
         L = self.levels
@@ -62,7 +63,8 @@ class JoinStats(ctypes.Structure):
                     heavy_queries=list(self.heavy_queries[:L]),
                     heavy_failed=list(self.heavy_failed[:L]),
                     heavy_cand=list(self.heavy_cand[:L]),
-                    spec_queries=list(self.spec_queries[:L]))
+                    spec_queries=list(self.spec_queries[:L]),
+                    deferred=list(self.deferred[:L]))
 
 
 class JoinOpts(ctypes.Structure):
@@ -73,6 +75,7 @@ class JoinOpts(ctypes.Structure):
                 ("queue_grain", c_i32), ("item_order", c_i32), ("lanes_shift", c_i32),
                 ("share_lists", c_i32),
                 ("speculate", c_i32),
+                ("predict_fail", c_i32),
                 ("stats", ctypes.POINTER(JoinStats))]
 
 

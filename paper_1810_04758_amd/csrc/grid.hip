@@ -6,6 +6,7 @@
 #pragma clang fp contract(off)
 
 #include "kernels.hpp"
+#include "lookback.hpp"
 
 namespace knn {
 
@@ -95,83 +96,19 @@ __global__ void k_bounds_final(const double* __restrict__ part, int nparts, int 
 // exclusive scan of uint32
 // --------------------------------------------------------------------------
 
-__device__ inline uint32_t wave_incl_scan(uint32_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t o = __shfl_up(v, d, 64);
-    if (lane >= d) v += o;
-  }
-  return v;
-}
-
-// Exclusive block scan of one value per thread (blockDim == kBlock); returns
-// the exclusive prefix and writes the block total to *total.
-__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
-  __shared__ uint32_t wsum[kBlock / 64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t inc = wave_incl_scan(v);
-  if (lane == 63) wsum[w] = inc;
-  __syncthreads();
-  uint32_t base = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < kBlock / 64; ++i) {
-    if (i < w) base += wsum[i];
-    tot += wsum[i];
-  }
-  __syncthreads();
-  *total = tot;
-  return base + inc - v;
-}
-
-// Single-pass exclusive scan with decoupled look-back.  Tiles are taken in
-// ticket order (an atomic counter), so every tile a block waits for belongs to
-// a block that is already running.  A block publishes its tile's sum at once;
-// then its first wavefront reads the words of the 64 preceding tiles at a
-// time, adds the sums up to the nearest inclusive prefix (or all 64, and goes
-// on further back), and the block publishes its own inclusive prefix.
-// Status word per tile: flag (bit 63 inclusive prefix, bit 62 tile sum),
-// epoch (bits 32..61), value (bits 0..31).  The epoch advances once per scan
-// (the block with the last ticket moves it on and resets the ticket; the
-// next scan on the stream starts after this one ends), so the words of
-// earlier scans never need clearing.  A look-back that waits more
-// than kScanSpinLimit rounds counts an error in state[2] and stops.
-constexpr uint64_t kFlagInc = 1ull << 63;
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint32_t kEpochMask = (1u << 30) - 1;
-constexpr uint32_t kScanSpinLimit = 1u << 20;
 constexpr int kOneItems = 32;
-constexpr int kLookWords = 4;
 constexpr int kOneTile = kBlock * kOneItems;
+static_assert(kOneTile >= kLbMinTile, "scan state sized for larger tiles");
 
+// Single-pass exclusive scan (look-back over tile words, lookback.hpp).
 template <bool VEC>
 __global__ void __launch_bounds__(kBlock)
 k_scan_onepass(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t n, int64_t nb,
                uint32_t* __restrict__ state, uint32_t* __restrict__ total) {
-  __shared__ uint32_t s_tile, s_epoch, s_excl;
-  // state[0..1]: one 64-bit word, ticket (low half) and epoch (high half), so
-  // a block takes both in one atomic; the status words carry their values,
-  // so every access here is a relaxed device-scope atomic (no cache
-  // write-back or invalidation)
-  unsigned long long* te = reinterpret_cast<unsigned long long*>(state);
-  unsigned long long* status = reinterpret_cast<unsigned long long*>(state + 4);
-  if (threadIdx.x == 0) {
-    const unsigned long long old =
-        __hip_atomic_fetch_add(te, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t t = (uint32_t)old;
-    const uint32_t e = (uint32_t)(old >> 32) & kEpochMask;
-    if ((int64_t)t == nb - 1)  // every ticket is taken: reset it, next epoch
-      __hip_atomic_store(te, (unsigned long long)((e + 1) & kEpochMask) << 32, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    s_tile = t;
-    s_epoch = e;
-  }
-  __syncthreads();
-  const int64_t tile = s_tile;
-  const uint32_t ep = s_epoch;
-  const uint64_t etag = (uint64_t)ep << 32;
+  __shared__ uint32_t s_excl;
+  const LbTile lt = lb_take_tile(state, nb);
   // thread t owns kOneItems consecutive elements of the tile
-  const int64_t base = tile * kOneTile + (int64_t)threadIdx.x * kOneItems;
+  const int64_t base = lt.tile * kOneTile + (int64_t)threadIdx.x * kOneItems;
   const bool whole = VEC && base + kOneItems <= n;
   uint32_t v[kOneItems];
   if (whole) {
@@ -191,76 +128,10 @@ k_scan_onepass(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int6
 #pragma unroll
   for (int k = 0; k < kOneItems; ++k) sum += v[k];
   uint32_t agg;
-  uint32_t ex = block_excl_scan(sum, &agg);
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&status[tile], (tile == 0 ? kFlagInc : kFlagAgg) | etag | agg,
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (threadIdx.x < 64 && tile > 0) {
-    // a window of kLookWords x 64 predecessors per round, all loads in flight
-    // together: predecessor j - (lane + 64 k) is word k of lane `lane`
-    const int lane = threadIdx.x;
-    uint32_t excl = 0;
-    uint32_t spins = 0;
-    int64_t j = tile - 1;
-    for (;;) {
-      unsigned long long w[kLookWords];
-#pragma unroll
-      for (int k = 0; k < kLookWords; ++k) {
-        const int64_t idx = j - lane - 64 * k;
-        // before tile 0: an inclusive prefix of 0
-        w[k] = idx >= 0 ? __hip_atomic_load(&status[idx], __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT)
-                        : (kFlagInc | etag);
-      }
-      // nearest inclusive prefix: word kp, lane lp (kp = kLookWords: none)
-      int kp = kLookWords, lp = 63;
-      bool ready = true;
-#pragma unroll
-      for (int k = 0; k < kLookWords; ++k) {
-        if (kp < kLookWords) break;
-        const bool valid = (w[k] & (kFlagInc | kFlagAgg)) != 0 &&
-                           (uint32_t)((w[k] >> 32) & kEpochMask) == ep;
-        const uint64_t pm = __ballot(valid && (w[k] & kFlagInc) != 0);
-        const uint64_t vm = __ballot(valid);
-        const int last = pm ? __builtin_ctzll(pm) : 63;
-        const uint64_t need = last == 63 ? ~0ull : ((2ull << last) - 1ull);
-        if ((vm & need) != need) {
-          ready = false;
-          break;
-        }
-        if (pm) {
-          kp = k;
-          lp = last;
-        }
-      }
-      if (!ready) {
-        if (++spins > kScanSpinLimit) {
-          if (lane == 0) atomicAdd(state + 2, 1u);
-          break;
-        }
-        continue;
-      }
-      uint32_t part = 0;
-#pragma unroll
-      for (int k = 0; k < kLookWords; ++k)
-        if (k < kp || (k == kp && lane <= lp)) part += (uint32_t)w[k];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-      excl += part;
-      if (kp < kLookWords) break;
-      j -= 64 * kLookWords;
-    }
-    if (lane == 0) {
-      __hip_atomic_store(&status[tile], kFlagInc | etag | (uint32_t)(excl + agg),
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_excl = excl;
-    }
-  } else if (threadIdx.x == 0) {
-    s_excl = 0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && tile == nb - 1 && total) *total = s_excl + agg;
-  ex += s_excl;
+  uint32_t ex = block_excl_scan<kBlock>(sum, &agg);
+  const uint32_t excl = lb_tile_prefix(state, lt, agg, &s_excl);
+  if (threadIdx.x == 0 && lt.tile == nb - 1 && total) *total = excl + agg;
+  ex += excl;
   if (whole) {
 #pragma unroll
     for (int k = 0; k < kOneItems / 4; ++k) {
@@ -765,7 +636,7 @@ void launch_bounds(const double* X, int64_t N, int n, double* part, double* lo, 
 size_t scan_state_elems(int64_t n) {
   // scans of up to n elements, or of a radix histogram of n keys
   const int64_t m = std::max<int64_t>(n, ((int64_t)1 << kMaxDigitBits) * ceil_div(n, kRadixTile));
-  return 4 + 2 * (size_t)(ceil_div(m, kOneTile) + 1);
+  return 4 + 2 * (size_t)(ceil_div(m, kLbMinTile) + 1);
 }
 
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,

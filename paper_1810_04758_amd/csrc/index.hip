@@ -283,7 +283,7 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   b += (16 + 4 + 4) * N;               // keys, keys2, vals2, flags
   b += (uint64_t)radix_tmp_elems((int64_t)N) * 4;
   b += (uint64_t)scan_state_elems((int64_t)N) * 4;
-  b += (4 + 4 + 1 + 1 + 4) * N;        // active, fail_list, failed, cell_active, heavy
+  b += (4 + 4 + 4 + 1 + 1 + 4) * N;    // active, active2, fail_list, failed, cell_active, heavy
   b += 24 * N;                         // work-item keys and order (at most one item per query)
   b += std::min<uint64_t>(N, 65535) * (512 + cap * 12);  // brute-force tail scratch
   b += 4096;                           // scalars
@@ -438,6 +438,38 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       cell_active = c.cell_active.p;
     }
     lp.Mcap = build_ranges(idx, c, s, rp ? rp->Mcap : 0, cell_active);
+    // the level's counters start here: the deferral filter appends to the
+    // failure list
+    const int64_t A_in = A;
+    launch_zero(c.iscal.p, kCounterInts * sizeof(int32_t), s);
+    const bool filt = o.predict_fail >= 0;
+    if (filt) {
+      c.active2.reserve(N);
+      DeferArgs da{};
+      da.Xs = c.Xs.p;
+      da.perm = c.perm.p;
+      da.cell_of = c.cell_of.p;
+      da.cand = c.cand_count.p;
+      da.active = active;
+      da.n_active = A;
+      for (int j = 0; j < kMaxDims; ++j) {
+        da.lo[j] = c.gg.lo[j];
+        da.g[j] = c.gg.g[j];
+      }
+      da.inv_w = c.gg.inv_w;
+      da.w = 1.0 / c.gg.inv_w;
+      da.margin = (8.0 * (double)c.gg.g_max + 4.0 * idx.n + 32.0) * std::ldexp(1.0, -53);
+      da.defer_coef = search_density_coef(idx.n, K, da.w) / 1.3;
+      da.out_active = c.active2.p;
+      da.out_count = c.scal.p + 2;
+      da.fail_list = c.fail_list.p;
+      da.fail_count = c.iscal.p + kFailSlot;
+      da.cand_sum = reinterpret_cast<unsigned long long*>(c.cand_sum.p);
+      da.state = c.scan_state.p;
+      da.state_elems = (int64_t)c.scan_state.n;
+      launch_defer_filter(da, idx.n, s);
+      active = c.active2.p;
+    }
     // lanes per query from the level's mean candidate count (the paper's t,
     // Sec. 4.7, chosen per level: the tail levels see far more candidates)
     double cand = 0;
@@ -447,16 +479,18 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       cand = rp->cand;
       c.M = rp->M;
       T = rp->T;
+      if (filt) A = rp->A_kept;
     } else {
-      launch_active_cand_sum(active, A, c.cell_of.p, c.cand_count.p, c.cand_sum.p, s);
+      if (!filt) launch_active_cand_sum(active, A, c.cell_of.p, c.cand_count.p, c.cand_sum.p, s);
       c.pinned.reserve(kCounterInts + 16);
       int32_t* hp = c.pinned.p;
       KNN_HIP(hipMemcpyAsync(hp, c.cand_sum.p, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-      KNN_HIP(hipMemcpyAsync(hp + 4, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipMemcpyAsync(hp + 4, c.scal.p, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));  // the level's one round trip before the search
       uint64_t tot[2];
       std::memcpy(tot, hp, sizeof(tot));
       const uint32_t M = (uint32_t)hp[4];
+      if (filt) A = (int64_t)(uint32_t)hp[6];
       cand = (double)tot[0] / (double)std::max<int64_t>(A, 1);
       cand_max = tot[1];
       c.M = M;
@@ -505,7 +539,6 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       }
       order = c.ivals.p;
     }
-    launch_zero(c.iscal.p, kCounterInts * sizeof(int32_t), s);
     ev.rec(1, s);
 
     SearchArgs a{};
@@ -537,7 +570,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.K = K;
     a.cap = cap;
     a.spec_slots = o.speculate < 0 ? 0 : search_spec_slots(idx.n, T, cap);
-    a.spec_coef = search_spec_coef(idx.n, K, a.w);
+    a.spec_coef = std::pow(1.7, 2.0 / idx.n) * search_density_coef(idx.n, K, a.w);
     a.out_ids = d_ids;
     a.out_d = d_dists;
     a.fail_list = c.fail_list.p;
@@ -546,7 +579,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.walk_error = c.iscal.p + kWalkErrSlot;
     a.spec_count = c.iscal.p + kSpecSlot;
     lp.heavy_min = heavy_min;
-    if (heavy_min > 0) {
+    if (heavy_min > 0 && A > 0) {
       // heavy queries first, one workgroup each (count stays on the device)
       c.heavy.reserve(N);
       a.heavy_min = heavy_min;
@@ -559,7 +592,9 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       launch_search_heavy(a, idx.n, ncu, s);
     }
     ev.rec(3, s);
-    if (o.schedule == 0) {
+    if (A == 0) {
+      // every query of the level was deferred
+    } else if (o.schedule == 0) {
       int blocks;
       if (rp) {
         blocks = rp->blocks;
@@ -590,13 +625,14 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     }
     ev.rec(2, s);
     int32_t sc[2] = {0, 0};
-    int32_t spec_held = 0;
+    int32_t spec_held = 0, deferred = 0;
     int64_t hq = 0, hf = 0;
     double hc = 0;
     if (rp) {
       sc[0] = rp->fails;
       sc[1] = rp->refine;
       spec_held = rp->spec;
+      deferred = rp->deferred;
       hq = rp->heavy;
       hf = rp->heavy_failed;
       hc = rp->heavy_cand;
@@ -614,6 +650,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       sc[0] = cnt[kFailSlot];
       sc[1] = cnt[kRefineSlot];
       spec_held = cnt[kSpecSlot];
+      deferred = (int32_t)(A_in - A);
       hq = cnt[kHeavySlot];
       hf = cnt[kHeavyFailSlot];
       uint64_t hcu = 0;
@@ -622,13 +659,15 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     }
     const int32_t fails = sc[0];
     if (record) {
-      lp.A = A;
+      lp.A = A_in;
+      lp.A_kept = A;
       lp.T = T;
       lp.n_items = n_items;
       lp.cand = cand;
       lp.fails = fails;
       lp.refine = sc[1];
       lp.spec = spec_held;
+      lp.deferred = deferred;
       lp.heavy = hq;
       lp.heavy_failed = hf;
       lp.heavy_cand = hc;
@@ -642,9 +681,10 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       st->cand_per_query[level] = cand;
       st->refine_rounds[level] = sc[1];
       st->spec_queries[level] = spec_held;
+      st->deferred[level] = deferred;
       st->levels = level + 1;
       st->cell_width[level] = 1.0 / c.gg.inv_w;
-      st->attempted[level] = A;
+      st->attempted[level] = A_in;
       st->failed[level] = fails;
       st->cells[level] = c.M;
       st->ms_build[level] = elapsed_ms(ev.e[0], ev.e[1]);
@@ -653,11 +693,11 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       st->heavy_queries[level] = hq;
       st->heavy_failed[level] = hf;
       st->heavy_cand[level] = hc;
-      st->total_attempted += A;
+      st->total_attempted += A_in;
       st->total_failed += fails;
     }
     if (fails == 0) break;
-    KNN_CHECK(fails <= A, KNN_EINTERNAL, "more failures than attempted queries");
+    KNN_CHECK(fails <= A_in, KNN_EINTERNAL, "more failures than attempted queries");
     // failures are re-queued on a grid with a larger cell side (Alg. 1):
     // linear growth by eps_step * w0 first, then geometric growth
     launch_zero(c.failed.p, (size_t)N, s);
@@ -684,7 +724,8 @@ bool GraphPlan::matches(int32_t K_, const knn_join_opts& o, int32_t* ids_, doubl
          opts.growth == o.growth && opts.tail_pairs == o.tail_pairs &&
          opts.heavy_min == o.heavy_min && opts.queue_grain == o.queue_grain &&
          opts.item_order == o.item_order && opts.share_lists == o.share_lists &&
-         opts.lanes_shift == o.lanes_shift && opts.speculate == o.speculate;
+         opts.lanes_shift == o.lanes_shift && opts.speculate == o.speculate &&
+         opts.predict_fail == o.predict_fail;
 }
 
 GraphPlan::~GraphPlan() {
@@ -712,6 +753,7 @@ void stats_from_plan(const GraphPlan& gp, knn_join_stats* st) {
     st->cand_per_query[L] = lp.cand;
     st->refine_rounds[L] = lp.refine;
     st->spec_queries[L] = lp.spec;
+    st->deferred[L] = lp.deferred;
     st->heavy_queries[L] = lp.heavy;
     st->heavy_failed[L] = lp.heavy_failed;
     st->heavy_cand[L] = lp.heavy_cand;

@@ -58,6 +58,7 @@ struct JoinContext {
   DevBuf<uint32_t> scal;  // [0] = M, [1] = active count
   DevBuf<int32_t> iscal;  // level counters (kCounterInts, one 128-byte line each)
   DevBuf<int32_t> active, fail_list;
+  DevBuf<int32_t> active2;  // the level's active list after the deferral filter
   DevBuf<uint8_t> failed;
   DevBuf<uint64_t> ikeys, ikeys2;
   DevBuf<int32_t> ivals, ivals2;
@@ -94,6 +95,8 @@ struct LevelPlan {
   int32_t fails = 0;
   int32_t refine = 0;
   int32_t spec = 0;
+  int32_t deferred = 0;
+  int64_t A_kept = 0;  // active queries after the deferral filter
   int64_t heavy = 0;
   int64_t heavy_failed = 0;
   double heavy_cand = 0;

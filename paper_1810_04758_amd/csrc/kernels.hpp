@@ -48,6 +48,8 @@ void launch_bounds(const double* X, int64_t N, int n, double* part, double* lo, 
 // state_elems >= scan_state_elems(n) uint32 owned by one stream's work,
 // zero-filled once when allocated and kept between scans (it carries the
 // scans' epoch and ticket); state[2] counts look-back errors (must stay 0).
+// Users of the state take tiles of at least kLbMinTile elements.
+constexpr int kLbMinTile = 2048;
 size_t scan_state_elems(int64_t n);
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                            uint32_t* state, int64_t state_elems, hipStream_t s);
@@ -182,8 +184,35 @@ struct SearchArgs {
   int32_t* walk_error;     // candidate-list walks that ran past their list (must stay 0)
   int32_t spec_slots;      // speculative survivor slots per query (0: off)
   int32_t* spec_count;     // diagnostics: queries whose speculation held
-  double spec_coef;        // predicted K-th d2 = spec_coef * C^(-2/n), C = candidates of the cell
+  double spec_coef;        // speculation limit = spec_coef * C^(-2/n), C = candidates of the cell
 };
+// Deferral filter of a level's active queries: a query whose K-th squared
+// distance, predicted from its 3^n block's density, exceeds its covered
+// radius^2 by the defer margin goes straight to the failure list; the others
+// form the level's new active list (cell order kept).
+struct DeferArgs {
+  const double* Xs;
+  const int32_t* perm;
+  const uint32_t* cell_of;
+  const uint32_t* cand;       // candidates per cell
+  const int32_t* active;      // active sorted positions (nullptr: identity)
+  int64_t n_active;
+  double lo[kMaxDims];
+  double inv_w;
+  double w;
+  int64_t g[kMaxDims];
+  double margin;
+  double defer_coef;          // deferred when defer_coef * C^(-2/n) > thr
+  int32_t* out_active;        // kept positions
+  uint32_t* out_count;        // their number (device)
+  int32_t* fail_list;         // deferred ids appended here
+  int32_t* fail_count;
+  unsigned long long* cand_sum;  // [0] += candidates of kept queries, [1] = max (pre-zeroed)
+  uint32_t* state;            // single-pass scan state (launch_exclusive_scan)
+  int64_t state_elems;
+};
+void launch_defer_filter(const DeferArgs& a, int dims, hipStream_t s);
+
 // Returns the number of waves per block used.
 void launch_search(const SearchArgs& a, int dims, int lanes_per_query, int grid_blocks,
                    hipStream_t s);
@@ -196,7 +225,7 @@ size_t search_lds_per_wave(int dims, int lanes_per_query, int cap);
 // Speculative survivor slots per query for a given (lanes_per_query, cap), and
 // the coefficient of the predicted K-th squared distance at cell side w.
 int search_spec_slots(int dims, int lanes_per_query, int cap);
-double search_spec_coef(int dims, int K, double w);
+double search_density_coef(int dims, int K, double w);
 int search_waves_per_block(int dims, int lanes_per_query, int cap);
 // Resident blocks per CU of the search kernel (occupancy API).
 int search_blocks_per_cu(int dims, int lanes_per_query, int cap);

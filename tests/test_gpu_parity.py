@@ -344,9 +344,10 @@ def test_heavy_queries(knn, oracle_mod, name, gen, K, heavy_min):
     ids, dists, st = _join(knn, D, K, heavy_min=heavy_min, w_factor=0.6, tail_pairs=-1)
     _check_rows(D, ids, dists, K, np.arange(N), oracle_mod)
     assert st["levels"] >= 2
-    if heavy_min == 1:  # every query of every level went to the workgroup kernel
-        assert st["heavy_queries"] == st["attempted"]
-        assert st["heavy_failed"] == st["failed"]
+    if heavy_min == 1:  # every searched query of every level went to the workgroup kernel
+        L = st["levels"]
+        assert st["heavy_queries"] == [st["attempted"][i] - st["deferred"][i] for i in range(L)]
+        assert st["heavy_failed"] == [st["failed"][i] - st["deferred"][i] for i in range(L)]
     if heavy_min == -1:
         assert not any(st["heavy_queries"])
 
@@ -370,6 +371,28 @@ def test_speculation(knn, oracle_mod, speculate, name, gen, K, lanes):
         assert not any(st["spec_queries"])
     else:
         assert 0 < st["spec_queries"][0] <= st["attempted"][0] - st["failed"][0]
+
+
+@pytest.mark.parametrize("predict_fail", [0, -1])
+@pytest.mark.parametrize("name,gen,K", [
+    ("expo4d_k24", lambda: datagen.exponential(12000, 4, seed=71), 24),
+    ("expo2d_k6", lambda: datagen.exponential(12000, 2, seed=72), 6),
+    ("unif5d_k10", lambda: datagen.uniform(8000, 5, seed=73), 10),
+], ids=["expo4d_k24", "expo2d_k6", "unif5d_k10"])
+def test_predicted_failures(knn, oracle_mod, predict_fail, name, gen, K):
+    """Queries whose predicted K-th distance is well beyond their covered
+    radius deferred to the next level without a count pass, or all searched:
+    the oracle's result either way; deferred queries count as failed."""
+    D = gen()
+    _say(f"[defer] {name} predict_fail={predict_fail}")
+    ids, dists, st = _join(knn, D, K, predict_fail=predict_fail, w_factor=0.7, tail_pairs=-1)
+    _check_rows(D, ids, dists, K, np.arange(D.shape[0]), oracle_mod)
+    for L in range(st["levels"]):
+        assert st["deferred"][L] <= st["failed"][L]
+    if predict_fail < 0:
+        assert not any(st["deferred"])
+    else:
+        assert st["deferred"][0] > 0
 
 
 @pytest.mark.parametrize("share", [1, -1])
