@@ -74,7 +74,8 @@ typedef struct knn_join_stats {
   int32_t levels;             /* grid levels searched (1 + re-indexes) */
   double eps_min;             /* eps_min(K) from the histogram */
   double cell_width[KNN_MAX_LEVELS];   /* cell side of each level */
-  int64_t attempted[KNN_MAX_LEVELS];   /* queries searched at each level */
+  int64_t attempted[KNN_MAX_LEVELS];   /* active queries at each level (deferred
+                                          ones included) */
   int64_t failed[KNN_MAX_LEVELS];      /* of which failed (re-queued) */
   int64_t cells[KNN_MAX_LEVELS];       /* non-empty cells of each level */
   double ms_build[KNN_MAX_LEVELS];     /* index construction time per level */
