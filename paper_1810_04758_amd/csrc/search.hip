@@ -66,12 +66,12 @@ struct BinShift {
 constexpr int NB2 = 32;        // bins of one exact-bisection round
 constexpr int kLog2NB2 = 5;
 // Candidates per lane in flight in the count/collect walks and the waves per
-// SIMD the register budget is set for (measured on MI355X: 2-4 dimensions are
-// best at 4 in flight with 4 waves per SIMD, 5-6 dimensions, whose L2 hit
-// rate is low, at 4 in flight with 2 waves and the registers that frees).
+// SIMD the register budget is set for (measured on MI355X with point-major
+// coordinates: 2-4 dimensions are best at 4 in flight with 4 waves per SIMD;
+// 5-6 dimensions at 2 in flight, 8 % faster than 4, with 2-4 waves alike).
 template <int DIM>
 struct Unroll {
-  static constexpr int v = 4;
+  static constexpr int v = DIM <= 4 ? 4 : 2;
 };
 template <int DIM>
 struct WavesPerEu {
