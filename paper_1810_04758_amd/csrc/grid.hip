@@ -270,6 +270,47 @@ __global__ void k_cell_keys(const double* __restrict__ X, int64_t N, GeomDev gd,
   }
 }
 
+// Keys of the previous level's sorted points (point-major), their positions
+// as values: a level sorted from there reads and writes far more coherently
+// than from the original order.
+template <int DIM>
+__global__ void k_cell_keys_points(const double* __restrict__ Xs, int64_t N, GeomDev gd,
+                                   uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+  constexpr int S = point_stride(DIM);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double2* src = reinterpret_cast<const double2*>(Xs + i * S);
+    double x[S];
+#pragma unroll
+    for (int h = 0; h < S / 2; ++h) {
+      const double2 t = src[h];
+      x[2 * h] = t.x;
+      x[2 * h + 1] = t.y;
+    }
+    uint64_t key = 0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+      key += (uint64_t)cell_coord(x[j], gd.lo[j], gd.inv_w) * gd.stride[j];
+    keys[i] = key;
+    vals[i] = (int32_t)i;
+  }
+}
+
+// New sorted order from previous positions: point p' takes the previous
+// point pos[p'] (coordinates and id).
+__global__ void k_gather_prev(const double* __restrict__ Xs_prev, const int32_t* __restrict__ perm_prev,
+                              const int32_t* __restrict__ pos, int64_t N, int S,
+                              double* __restrict__ Xs, int32_t* __restrict__ perm) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t src = pos[p];
+    perm[p] = perm_prev[src];
+    const double2* in = reinterpret_cast<const double2*>(Xs_prev + src * S);
+    double2* out = reinterpret_cast<double2*>(Xs + p * S);
+    for (int h = 0; h < S / 2; ++h) out[h] = in[h];
+  }
+}
+
 __global__ void k_mark_cells(const uint64_t* __restrict__ keys, int64_t N,
                              uint32_t* __restrict__ flags) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
@@ -707,6 +748,28 @@ void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* 
     case 6: k_cell_keys<6><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
+  KNN_LAUNCHED();
+}
+
+void launch_cell_keys_points(const double* Xs, int64_t N, const GridGeom& gg, uint64_t* keys,
+                             int32_t* vals, hipStream_t s) {
+  GeomDev gd = to_dev(gg);
+  int nb = grid_for(N);
+  switch (gg.dims) {
+    case 2: k_cell_keys_points<2><<<nb, kBlock, 0, s>>>(Xs, N, gd, keys, vals); break;
+    case 3: k_cell_keys_points<3><<<nb, kBlock, 0, s>>>(Xs, N, gd, keys, vals); break;
+    case 4: k_cell_keys_points<4><<<nb, kBlock, 0, s>>>(Xs, N, gd, keys, vals); break;
+    case 5: k_cell_keys_points<5><<<nb, kBlock, 0, s>>>(Xs, N, gd, keys, vals); break;
+    case 6: k_cell_keys_points<6><<<nb, kBlock, 0, s>>>(Xs, N, gd, keys, vals); break;
+    default: throw Error(KNN_EINVAL, "dims out of range");
+  }
+  KNN_LAUNCHED();
+}
+
+void launch_gather_prev(const double* Xs_prev, const int32_t* perm_prev, const int32_t* pos,
+                        int64_t N, int n, double* Xs, int32_t* perm, hipStream_t s) {
+  k_gather_prev<<<grid_for(N), kBlock, 0, s>>>(Xs_prev, perm_prev, pos, N, point_stride(n), Xs,
+                                               perm);
   KNN_LAUNCHED();
 }
 

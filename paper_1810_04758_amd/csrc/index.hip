@@ -158,7 +158,9 @@ int64_t JoinContext::device_bytes() const {
                    scal.bytes() + iscal.bytes() + active.bytes() + fail_list.bytes() +
                    failed.bytes() + ikeys.bytes() + ikeys2.bytes() + ivals.bytes() +
                    ivals2.bytes() + out_ids.bytes() + out_d.bytes() + tail_scratch.bytes() +
-                   cand_sum.bytes() + heavy.bytes() + cell_active.bytes() + rowtab.bytes());
+                   cand_sum.bytes() + heavy.bytes() + cell_active.bytes() + rowtab.bytes() +
+                   Xs2.bytes() + perm2.bytes() + pos.bytes() + active2.bytes() +
+                   scan_state.bytes());
 }
 
 double eps_min_of(const knn_index& idx, int32_t K) {
@@ -180,7 +182,7 @@ void validate_join(const knn_index* idx, int32_t K) {
   KNN_CHECK(K <= KNN_MAX_K, KNN_EINVAL, "K above KNN_MAX_K");
 }
 
-void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s) {
+void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s, bool from_prev) {
   const int64_t N = idx.N;
   const int n = idx.n;
   c.gg = make_geom(idx, w);
@@ -199,15 +201,33 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s) {
   if (c.scan_state.reserve(scan_state_elems(N)))
     launch_zero(c.scan_state.p, c.scan_state.bytes(), s);
   c.scal.reserve(4);
-  launch_cell_keys(idx.X.p, N, c.gg, c.keys.p, c.perm.p, s);
-  if (radix_sort_pairs(c.keys.p, c.perm.p, c.keys2.p, c.vals2.p, N, c.gg.key_bits, c.tmp.p,
-                       c.scan_state.p, (int64_t)c.scan_state.n, s)) {
-    std::swap(c.keys, c.keys2);  // sorted output is in the scratch pair
-    std::swap(c.perm, c.vals2);
+  if (from_prev) {
+    // sort the previous level's order (spatially coherent: each new cell's
+    // points come from a few runs of it) by the new keys, then carry the
+    // coordinates and ids over
+    c.pos.reserve(N);
+    c.Xs2.reserve((size_t)N * point_stride(n));
+    c.perm2.reserve(N);
+    launch_cell_keys_points(c.Xs.p, N, c.gg, c.keys.p, c.pos.p, s);
+    if (radix_sort_pairs(c.keys.p, c.pos.p, c.keys2.p, c.vals2.p, N, c.gg.key_bits, c.tmp.p,
+                         c.scan_state.p, (int64_t)c.scan_state.n, s)) {
+      std::swap(c.keys, c.keys2);
+      std::swap(c.pos, c.vals2);
+    }
+    launch_gather_prev(c.Xs.p, c.perm.p, c.pos.p, N, n, c.Xs2.p, c.perm2.p, s);
+    std::swap(c.Xs, c.Xs2);
+    std::swap(c.perm, c.perm2);
+  } else {
+    launch_cell_keys(idx.X.p, N, c.gg, c.keys.p, c.perm.p, s);
+    if (radix_sort_pairs(c.keys.p, c.perm.p, c.keys2.p, c.vals2.p, N, c.gg.key_bits, c.tmp.p,
+                         c.scan_state.p, (int64_t)c.scan_state.n, s)) {
+      std::swap(c.keys, c.keys2);  // sorted output is in the scratch pair
+      std::swap(c.perm, c.vals2);
+    }
   }
   build_cell_table(c.keys.p, N, c.flags.p, c.cell_of.p, c.cell_key.p, c.cell_start.p, c.scal.p,
                    c.scan_state.p, (int64_t)c.scan_state.n, s);
-  launch_gather_points(idx.XA.p, c.perm.p, N, n, c.Xs.p, s);
+  if (!from_prev) launch_gather_points(idx.XA.p, c.perm.p, N, n, c.Xs.p, s);
   // The number of cells M stays on the device (kernels read it there), so the
   // level is built without a host round trip; per-cell arrays are sized for
   // the worst case M = N.
@@ -276,7 +296,8 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   const uint64_t R = (uint64_t)pow3(idx.n - 1);
   const uint64_t cap = (uint64_t)K + std::max<uint64_t>(16, (uint64_t)K / 2);
   uint64_t b = 0;
-  b += 8 * (uint64_t)point_stride(idx.n) * N;  // Xs
+  b += 16 * (uint64_t)point_stride(idx.n) * N;  // Xs and the previous level's
+  b += 8 * N;                                    // perm2, pos
   b += (4 + 4 + 8 + 4 + 4 + 4) * N;    // perm, cell_of, cell_key, cell_start, nrng, cand_count
   b += 17 * R * N;                     // ranges (4 x u32) + rslot
   b += std::max<uint64_t>(256 * N, 32ull << 20);  // dense key table or row table
@@ -419,7 +440,9 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       break;
     }
     ev.rec(0, s);
-    build_grid(idx, c, w, s);
+    // level 0 sorts the points from their original order, later levels from
+    // the previous level's order
+    build_grid(idx, c, w, s, level > 0);
     // active list of this level (cell order): level 0 = every point
     const int32_t* active = nullptr;
     const uint8_t* cell_active = nullptr;

@@ -40,8 +40,9 @@ struct JoinContext {
   // level arrays
   GridGeom gg{};
   int64_t M = 0;
-  DevBuf<double> Xs;
-  DevBuf<int32_t> perm;
+  DevBuf<double> Xs, Xs2;      // sorted points (Xs2: the other of a level pair)
+  DevBuf<int32_t> perm, perm2;  // sorted position -> id
+  DevBuf<int32_t> pos;          // sort values of a level sorted from the previous one
   DevBuf<uint32_t> cell_of;
   DevBuf<uint64_t> cell_key;
   DevBuf<uint32_t> cell_start;
@@ -129,7 +130,10 @@ struct JoinParams {
 // The grid of cell side w (keys, sort, cell table, sorted coordinates, dense
 // key table) into ctx, then the neighbour ranges of every cell (cell_active
 // NULL) or of the flagged cells only.
-void build_grid(const knn_index& idx, JoinContext& ctx, double w, hipStream_t s);
+// from_prev: sort from the sorted order the context holds (a previous level
+// of the same join, same points) instead of from the original order.
+void build_grid(const knn_index& idx, JoinContext& ctx, double w, hipStream_t s,
+                bool from_prev = false);
 int64_t build_ranges(const knn_index& idx, JoinContext& ctx, hipStream_t s, int64_t Mcap_known,
                      const uint8_t* cell_active);
 // Builds the grid level of cell side w into ctx (Sec. 3.1 / 4.6).

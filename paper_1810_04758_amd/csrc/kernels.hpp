@@ -74,6 +74,13 @@ void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* 
 void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags,
                       uint32_t* cell_of, uint64_t* cell_key, uint32_t* cell_start,
                       uint32_t* d_M, uint32_t* state, int64_t state_elems, hipStream_t s);
+// keys[p] = cell key of the point at sorted position p of the previous level
+// (point-major Xs), vals[p] = p.
+void launch_cell_keys_points(const double* Xs, int64_t N, const GridGeom& gg, uint64_t* keys,
+                             int32_t* vals, hipStream_t s);
+// perm[p] = perm_prev[pos[p]], point p of Xs = point pos[p] of Xs_prev.
+void launch_gather_prev(const double* Xs_prev, const int32_t* perm_prev, const int32_t* pos,
+                        int64_t N, int n, double* Xs, int32_t* perm, hipStream_t s);
 // Doubles per point in the sorted coordinate array: n rounded up to even, so
 // a point is whole 16-byte pairs (a padding coordinate is 0).
 inline constexpr int point_stride(int n) { return (n + 1) & ~1; }
