@@ -161,7 +161,7 @@ k_scan_onepass(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int6
 // ballots (lanes with the same digit) plus the counts of earlier waves and
 // earlier chunks of the tile, so equal digits keep their input order.
 // --------------------------------------------------------------------------
-constexpr int kRadixItems = 8;
+constexpr int kRadixItems = 16;
 constexpr int kRadixTile = kBlock * kRadixItems;
 constexpr int kMaxDigitBits = 11;
 
@@ -182,6 +182,12 @@ __global__ void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int s
   for (int d = threadIdx.x; d < RB; d += kBlock) hist[(int64_t)d * nb + blockIdx.x] = h[d];
 }
 
+// Stable scatter of one tile: rounds of kBlock keys in input order; in a
+// round, a key's rank among the wave's keys of its digit comes from DB
+// ballots, and the wave's count per digit goes to wcnt[w][d] (written by the
+// digit's first lane), so the keys of earlier waves precede it.  Only the
+// entries a round touched are updated afterwards (run[d] advanced, wcnt
+// cleared), not all RB digits.
 template <int DB>
 __global__ void k_radix_scatter(const uint64_t* __restrict__ keys,
                                 const int32_t* __restrict__ vals, int64_t n, int shift,
@@ -212,8 +218,10 @@ __global__ void k_radix_scatter(const uint64_t* __restrict__ keys,
       uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
     }
-    uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    const bool leader = valid && rank == 0;
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    if (leader) wcnt[w][d] = cnt;
     __syncthreads();
     if (valid) {
       uint32_t pos = run[d] + rank;
@@ -222,14 +230,9 @@ __global__ void k_radix_scatter(const uint64_t* __restrict__ keys,
       ovals[pos] = val;
     }
     __syncthreads();
-    for (int dd = t; dd < RB; dd += kBlock) {
-      uint32_t add = 0;
-#pragma unroll
-      for (int i2 = 0; i2 < kBlock / 64; ++i2) {
-        add += wcnt[i2][dd];
-        wcnt[i2][dd] = 0;
-      }
-      run[dd] += add;
+    if (leader) {
+      atomicAdd(&run[d], cnt);
+      wcnt[w][d] = 0;
     }
     __syncthreads();
   }
