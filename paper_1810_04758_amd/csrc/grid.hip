@@ -245,6 +245,7 @@ struct GeomDev {
   double lo[kMaxDims];
   double inv_w;
   uint64_t stride[kMaxDims];
+  uint64_t rstride[kMaxDims];  // row index stride (stride / g_last) of the first n-1 dims
   int64_t g[kMaxDims];
 };
 
@@ -253,6 +254,8 @@ GeomDev to_dev(const GridGeom& gg) {
   for (int j = 0; j < kMaxDims; ++j) {
     d.lo[j] = gg.lo[j];
     d.stride[j] = gg.stride[j];
+    d.rstride[j] = (j < gg.dims - 1 && gg.g[gg.dims - 1] > 0)
+                       ? gg.stride[j] / (uint64_t)gg.g[gg.dims - 1] : 0;
     d.g[j] = gg.g[j];
   }
   d.inv_w = gg.inv_w;
@@ -372,6 +375,13 @@ __global__ void k_dense_scatter(const uint64_t* __restrict__ cell_key, const uin
 // Index of the first cell whose key is >= key (binary search in cell_key[0..M)).
 __device__ inline uint32_t lower_bound_key(const uint64_t* __restrict__ cell_key, uint32_t lo,
                                            uint32_t hi, uint64_t key) {
+  // short ranges (most grid rows): a linear probe, the loads independent
+  if (hi - lo <= 4) {
+    uint32_t f = hi;
+    for (uint32_t i = hi; i > lo; --i)
+      if (cell_key[i - 1] >= key) f = i - 1;
+    return f;
+  }
   while (lo < hi) {
     uint32_t mid = lo + ((hi - lo) >> 1);
     if (cell_key[mid] < key)
@@ -461,7 +471,7 @@ __device__ inline void range_of(int r, const int64_t (&cc)[DIM],
                                 uint32_t& start, uint32_t& mid0, uint32_t& mid1, uint32_t& end) {
   {
     bool inside = true;
-    uint64_t prefix = 0;
+    uint64_t prefix = 0, row = 0;
     int rr = r;
     int64_t nb[DIM];
 #pragma unroll
@@ -477,7 +487,10 @@ __device__ inline void range_of(int r, const int64_t (&cc)[DIM],
     mid1 = 0;
     if (inside) {
 #pragma unroll
-      for (int j = 0; j < DIM - 1; ++j) prefix += (uint64_t)nb[j] * gd.stride[j];
+      for (int j = 0; j < DIM - 1; ++j) {
+        prefix += (uint64_t)nb[j] * gd.stride[j];
+        row += (uint64_t)nb[j] * gd.rstride[j];  // prefix / g_last without a division
+      }
       const int64_t last = cc[DIM - 1];
       const int64_t a = last > 0 ? last - 1 : 0;
       const int64_t b = last + 1 < gd.g[DIM - 1] ? last + 1 : gd.g[DIM - 1] - 1;
@@ -502,7 +515,7 @@ __device__ inline void range_of(int r, const int64_t (&cc)[DIM],
         // cells of the row (a CSR row table when there is one, else all)
         uint32_t rs = 0, re = M;
         if (rowtab) {
-          const uint2 rr2 = rowtab[prefix / (uint64_t)gd.g[DIM - 1]];
+          const uint2 rr2 = rowtab[row];
           rs = rr2.x;
           re = rr2.y;
         }
