@@ -317,28 +317,102 @@ __global__ void k_gather_prev(const double* __restrict__ Xs_prev, const int32_t*
   }
 }
 
-__global__ void k_mark_cells(const uint64_t* __restrict__ keys, int64_t N,
-                             uint32_t* __restrict__ flags) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * blockDim.x)
-    flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+// Cell table in one pass: a cell starts where the sorted key changes.  A tile
+// is kCtRounds rounds of 64 consecutive positions per wavefront (coalesced);
+// the start flags of a round are one ballot, kept for the second sweep; the
+// wavefront counts go through a block scan and the look-back over earlier
+// tiles, and every start emits its cell's key and first position.  The last
+// position writes M and cell_start[M].
+constexpr int kCtRounds = 16;
+constexpr int kCtTile = kBlock * kCtRounds;
+static_assert(kCtTile >= kLbMinTile, "scan state sized for larger tiles");
+
+// Offsets of a tile's wavefronts: the exclusive prefix of this wavefront's
+// count over the block and the earlier tiles.
+__device__ inline uint32_t tile_wave_offset(uint32_t* state, LbTile lt, uint32_t wcount,
+                                            uint32_t* total_out) {
+  __shared__ uint32_t s_w[kBlock / 64];
+  __shared__ uint32_t s_excl;
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) s_w[w] = wcount;
+  __syncthreads();
+  uint32_t before = 0, agg = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) {
+    if (i < w) before += s_w[i];
+    agg += s_w[i];
+  }
+  const uint32_t excl = lb_tile_prefix(state, lt, agg, &s_excl);
+  if (total_out) *total_out = excl + agg;
+  return excl + before;
 }
 
-// ex: exclusive scan of flags (may alias cell_of).
-__global__ void k_emit_cells(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ flags,
-                             const uint32_t* ex, int64_t N, uint32_t* cell_of,
-                             uint64_t* __restrict__ cell_key, uint32_t* __restrict__ cell_start) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t f = flags[i];
-    uint32_t c = ex[i] + f - 1u;
-    if (f) {
-      cell_key[c] = keys[i];
-      cell_start[c] = (uint32_t)i;
-    }
-    cell_of[i] = c;
-    if (i == N - 1) cell_start[c + 1] = (uint32_t)N;
+__global__ void __launch_bounds__(kBlock)
+k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int64_t nb, uint32_t* __restrict__ cell_of,
+             uint64_t* __restrict__ cell_key, uint32_t* __restrict__ cell_start,
+             uint32_t* __restrict__ d_M, uint32_t* __restrict__ state) {
+  const LbTile lt = lb_take_tile(state, nb);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t wbase = lt.tile * kCtTile + (int64_t)w * 64 * kCtRounds;
+  uint64_t key[kCtRounds], m[kCtRounds];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int r = 0; r < kCtRounds; ++r) {
+    const int64_t i = wbase + r * 64 + lane;
+    key[r] = i < N ? keys[i] : 0;
+    const uint64_t up = __shfl_up(key[r], 1, 64);
+    const uint64_t prev = lane > 0 ? up : (i > 0 && i < N ? keys[i - 1] : 0);
+    m[r] = __ballot(i < N && (i == 0 || key[r] != prev));
+    cnt += (uint32_t)__popcll(m[r]);
   }
+  uint32_t c = tile_wave_offset(state, lt, cnt, nullptr);  // cells started before
+#pragma unroll
+  for (int r = 0; r < kCtRounds; ++r) {
+    const int64_t i = wbase + r * 64 + lane;
+    const bool f = (m[r] >> lane) & 1ull;
+    const uint32_t ci = c + (uint32_t)__popcll(m[r] & lt_mask);  // this start's cell
+    if (i < N) {
+      if (f) {
+        cell_key[ci] = key[r];
+        cell_start[ci] = (uint32_t)i;
+      }
+      cell_of[i] = f ? ci : ci - 1u;
+      if (i == N - 1) {
+        const uint32_t M = ci + (f ? 1u : 0u);
+        cell_start[M] = (uint32_t)N;
+        *d_M = M;
+      }
+    }
+    c += (uint32_t)__popcll(m[r]);
+  }
+}
+
+// Active list in one pass: the sorted positions whose point failed, in order.
+__global__ void __launch_bounds__(kBlock)
+k_active_list(const uint8_t* __restrict__ failed, const int32_t* __restrict__ perm, int64_t N,
+              int64_t nb, int32_t* __restrict__ out, uint32_t* __restrict__ count,
+              uint32_t* __restrict__ state) {
+  const LbTile lt = lb_take_tile(state, nb);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t wbase = lt.tile * kCtTile + (int64_t)w * 64 * kCtRounds;
+  uint64_t m[kCtRounds];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int r = 0; r < kCtRounds; ++r) {
+    const int64_t p = wbase + r * 64 + lane;
+    m[r] = __ballot(p < N && failed[perm[p]]);
+    cnt += (uint32_t)__popcll(m[r]);
+  }
+  uint32_t total;
+  uint32_t o = tile_wave_offset(state, lt, cnt, &total);
+#pragma unroll
+  for (int r = 0; r < kCtRounds; ++r) {
+    if ((m[r] >> lane) & 1ull) out[o + (uint32_t)__popcll(m[r] & lt_mask)] = (int32_t)(wbase + r * 64 + lane);
+    o += (uint32_t)__popcll(m[r]);
+  }
+  if (threadIdx.x == 0 && lt.tile == nb - 1) *count = total;
 }
 
 // Point-major sorted coordinates: point p (sorted position) takes the row
@@ -641,20 +715,6 @@ __global__ void k_mark_failed(const int32_t* __restrict__ fail_list, const int32
     failed[fail_list[i]] = 1;
 }
 
-__global__ void k_failed_flags(const uint8_t* __restrict__ failed, const int32_t* __restrict__ perm,
-                               int64_t N, uint32_t* __restrict__ flags) {
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
-       p += (int64_t)gridDim.x * blockDim.x)
-    flags[p] = failed[perm[p]] ? 1u : 0u;
-}
-
-__global__ void k_compact(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ ex,
-                          int64_t N, int32_t* __restrict__ out) {
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
-       p += (int64_t)gridDim.x * blockDim.x)
-    if (flags[p]) out[ex[p]] = (int32_t)p;
-}
-
 // Zero fill: `words` 32-bit words, then `tail` (< 4) trailing bytes.  A kernel
 // rather than a memset node, so the join's launch sequence can be captured in
 // a graph and replayed.
@@ -792,12 +852,27 @@ void launch_gather_prev(const double* Xs_prev, const int32_t* perm_prev, const i
 void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags, uint32_t* cell_of,
                       uint64_t* cell_key, uint32_t* cell_start, uint32_t* d_M, uint32_t* state,
                       int64_t state_elems, hipStream_t s) {
-  int nb = grid_for(N);
-  k_mark_cells<<<nb, kBlock, 0, s>>>(sorted_keys, N, flags);
+  (void)flags;
+  if (N <= 0) {
+    launch_zero(d_M, sizeof(uint32_t), s);
+    return;
+  }
+  const int64_t nb = ceil_div(N, kCtTile);
+  KNN_CHECK(4 + 2 * nb <= state_elems, KNN_EINTERNAL, "scan state too small");
+  k_cell_table<<<(unsigned)nb, kBlock, 0, s>>>(sorted_keys, N, nb, cell_of, cell_key, cell_start,
+                                               d_M, state);
   KNN_LAUNCHED();
-  launch_exclusive_scan(flags, cell_of, N, d_M, state, state_elems, s);
-  k_emit_cells<<<nb, kBlock, 0, s>>>(sorted_keys, flags, cell_of, N, cell_of, cell_key,
-                                     cell_start);
+}
+
+void launch_active_list(const uint8_t* failed, const int32_t* perm, int64_t N, int32_t* out,
+                        uint32_t* count, uint32_t* state, int64_t state_elems, hipStream_t s) {
+  if (N <= 0) {
+    launch_zero(count, sizeof(uint32_t), s);
+    return;
+  }
+  const int64_t nb = ceil_div(N, kCtTile);
+  KNN_CHECK(4 + 2 * nb <= state_elems, KNN_EINTERNAL, "scan state too small");
+  k_active_list<<<(unsigned)nb, kBlock, 0, s>>>(failed, perm, N, nb, out, count, state);
   KNN_LAUNCHED();
 }
 
@@ -882,12 +957,6 @@ void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count, i
   KNN_LAUNCHED();
 }
 
-void launch_failed_flags(const uint8_t* failed, const int32_t* perm, int64_t N, uint32_t* flags,
-                         hipStream_t s) {
-  k_failed_flags<<<grid_for(N), kBlock, 0, s>>>(failed, perm, N, flags);
-  KNN_LAUNCHED();
-}
-
 __global__ void k_mark_cells_of(const int32_t* __restrict__ active, int64_t n_active,
                                 const uint32_t* __restrict__ cell_of, uint8_t* __restrict__ flags) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_active;
@@ -899,12 +968,6 @@ void launch_mark_cells_of(const int32_t* active, int64_t n_active, const uint32_
                           uint8_t* flags, hipStream_t s) {
   if (n_active <= 0) return;
   k_mark_cells_of<<<grid_for(n_active), kBlock, 0, s>>>(active, n_active, cell_of, flags);
-  KNN_LAUNCHED();
-}
-
-void launch_compact_positions(const uint32_t* flags, const uint32_t* ex, int64_t N, int32_t* out,
-                              hipStream_t s) {
-  k_compact<<<grid_for(N), kBlock, 0, s>>>(flags, ex, N, out);
   KNN_LAUNCHED();
 }
 

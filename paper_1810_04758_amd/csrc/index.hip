@@ -447,12 +447,8 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     const int32_t* active = nullptr;
     const uint8_t* cell_active = nullptr;
     if (level > 0) {
-      // keys2 (scratch of the level's sort) holds the exclusive scan
-      uint32_t* ex = reinterpret_cast<uint32_t*>(c.keys2.p);
-      launch_failed_flags(c.failed.p, c.perm.p, N, c.flags.p, s);
-      launch_exclusive_scan(c.flags.p, ex, N, c.scal.p + 1, c.scan_state.p,
-                            (int64_t)c.scan_state.n, s);
-      launch_compact_positions(c.flags.p, ex, N, c.active.p, s);
+      launch_active_list(c.failed.p, c.perm.p, N, c.active.p, c.scal.p + 1, c.scan_state.p,
+                         (int64_t)c.scan_state.n, s);
       active = c.active.p;
       // neighbour ranges only for the cells that hold an active query
       c.cell_active.reserve(N);

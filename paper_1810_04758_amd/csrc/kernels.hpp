@@ -69,8 +69,9 @@ bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* v
 // keys[i] = cell key of point i (original order, SoA X); vals[i] = i.
 void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* keys,
                       int32_t* vals, hipStream_t s);
-// From sorted keys: flags -> scan -> cell table.  cell_of (N), cell_key (N),
-// cell_start (N+1), d_M (device scalar) written.  state: scan state.
+// From sorted keys, in one pass (cell starts counted, scanned by look-back):
+// the cell table.  cell_of (N), cell_key (N),
+// cell_start (N+1), d_M (device scalar) written.  state: scan state (flags unused).
 void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags,
                       uint32_t* cell_of, uint64_t* cell_key, uint32_t* cell_start,
                       uint32_t* d_M, uint32_t* state, int64_t state_elems, hipStream_t s);
@@ -133,13 +134,13 @@ void launch_heavy_list(const int32_t* active /*nullable*/, int64_t n_active,
                        const uint32_t* cell_of, const uint32_t* cand_count, uint32_t heavy_min,
                        int32_t* list, int32_t* count, unsigned long long* cand_sum,
                        hipStream_t s);
-// flags[p] = failed[perm[p]] for the next level's active list.
+// failed[id] = 1 for the ids of the failure list (next level's active list).
 void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count,
                         int64_t max_fail, uint8_t* failed, hipStream_t s);
-void launch_failed_flags(const uint8_t* failed, const int32_t* perm, int64_t N,
-                         uint32_t* flags, hipStream_t s);
-void launch_compact_positions(const uint32_t* flags, const uint32_t* ex, int64_t N,
-                              int32_t* out, hipStream_t s);
+// out = the sorted positions p with failed[perm[p]] != 0, in order; their
+// number to *count (device).  One pass (scan state as launch_exclusive_scan).
+void launch_active_list(const uint8_t* failed, const int32_t* perm, int64_t N, int32_t* out,
+                        uint32_t* count, uint32_t* state, int64_t state_elems, hipStream_t s);
 // Zeroes `bytes` bytes at p (4-byte aligned) with a kernel, not a memset node.
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
