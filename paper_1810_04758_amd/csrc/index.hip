@@ -1172,6 +1172,9 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
       }
     };
     for (double wf : {0.25, 0.5, 0.7, 1.4, 2.0}) consider(wf, g16, 1, tp0);
+    // the best side at the edge of the range: two more beyond it
+    if (out->w_factor >= 2.0)
+      for (double wf : {2.8, 4.0}) consider(wf, g16, 1, tp0);
     const double wf1 = out->w_factor;
     for (double gb : {4.0, 16.0, 64.0})
       for (int lin : {1, -1}) {
@@ -1179,6 +1182,9 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
         if (gb == 16.0 && lin == 1) continue;  // measured in the first stage
         consider(wf1, gr, lin, tp0);
       }
+    // the fastest growth best: one faster
+    if (out->growth >= std::pow(64.0, 1.0 / n) * 0.999)
+      consider(wf1, std::pow(256.0, 1.0 / n), out->linear_levels, tp0);
     const double gr2 = out->growth;
     const int lin2 = out->linear_levels;
     for (double f : {0.8, 1.25}) consider(wf1 * f, gr2, lin2, tp0);

@@ -197,7 +197,7 @@ def test_autotune_keeps_results_and_roundtrips(knn, oracle_mod, tmp_path):
     _say("[autotune]")
     idx = knn.build_index(torch.from_numpy(D).cuda())
     r = idx.autotune(10)
-    assert r["trials"] == 17 and r["ms_best"] <= r["ms_default"] and r["tail_pairs"] > 0
+    assert 17 <= r["trials"] <= 20 and r["ms_best"] <= r["ms_default"] and r["tail_pairs"] > 0
     assert r["lanes_shift"] in (-1, 0, 1)
     assert r["w_factor"] > 0 and r["growth"] > 1 and r["linear_levels"] in (1, -1)
     ids, dists = idx.self_join(10)  # uses the cached setting
