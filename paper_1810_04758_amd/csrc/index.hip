@@ -1182,9 +1182,11 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
         if (gb == 16.0 && lin == 1) continue;  // measured in the first stage
         consider(wf1, gr, lin, tp0);
       }
-    // the fastest growth best: one faster
+    // the fastest (slowest) growth best: one faster (slower)
     if (out->growth >= std::pow(64.0, 1.0 / n) * 0.999)
       consider(wf1, std::pow(256.0, 1.0 / n), out->linear_levels, tp0);
+    else if (out->growth <= std::pow(4.0, 1.0 / n) * 1.001)
+      consider(wf1, std::pow(2.0, 1.0 / n), out->linear_levels, tp0);
     const double gr2 = out->growth;
     const int lin2 = out->linear_levels;
     for (double f : {0.8, 1.25}) consider(wf1 * f, gr2, lin2, tp0);
