@@ -841,71 +841,88 @@ k_search(const SearchArgs a) {
   if (lane == 0 && spec_held > 0 && a.spec_count) atomicAdd(a.spec_count, spec_held);
 }
 
-// Deferral filter: kDeferItems consecutive active slots per thread, kept
-// slots compacted in order through the single-pass scan's look-back.
-constexpr int kDeferItems = 8;
-constexpr int kDeferTile = 256 * kDeferItems;
+// Deferral filter: a tile is kDeferRounds rounds of 64 consecutive active
+// slots per wavefront (coalesced); keep / defer decisions are ballots, kept
+// slots are compacted in order through the single-pass scan's look-back,
+// deferred ids appended after one atomic per block.
+constexpr int kDeferRounds = 8;
+constexpr int kDeferTile = 256 * kDeferRounds;
 static_assert(kDeferTile >= kLbMinTile, "scan state sized for larger tiles");
 
 template <int DIM>
 __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t nb) {
   __shared__ uint32_t s_excl, s_fbase;
+  __shared__ uint32_t s_wk[4], s_wd[4];
   __shared__ unsigned long long s_sum[4], s_max[4];
   const LbTile lt = lb_take_tile(a.state, nb);
-  const int64_t base = lt.tile * kDeferTile + (int64_t)threadIdx.x * kDeferItems;
-  uint32_t keepm = 0;  // bit k: slot base + k is kept
-  uint32_t nkeep = 0, ndef = 0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t wbase = lt.tile * kDeferTile + (int64_t)w * 64 * kDeferRounds;
+  uint64_t mk[kDeferRounds], md[kDeferRounds];
+  int32_t qk[kDeferRounds];
+  uint32_t nk = 0, nd = 0;
   unsigned long long csum = 0, cmax = 0;
-  int32_t qk[kDeferItems];
 #pragma unroll
-  for (int k = 0; k < kDeferItems; ++k) {
-    qk[k] = 0;
-    const int64_t i = base + k;
-    if (i >= a.n_active) continue;
-    const int32_t q = a.active ? a.active[i] : (int32_t)i;
+  for (int k = 0; k < kDeferRounds; ++k) {
+    const int64_t i = wbase + k * 64 + lane;
+    const bool in = i < a.n_active;
+    const int32_t q = in ? (a.active ? a.active[i] : (int32_t)i) : 0;
     qk[k] = q;
-    double qx[DIM];
-    load_point<DIM, false>(a.Xs, (uint32_t)q, qx);
-    const uint32_t Cq = a.cand[a.cell_of[q]];
-    // the covered radius of the search kernel
-    double mfrac = 0.5;
-    bool full = true;
+    bool defer = false;
+    uint32_t Cq = 0;
+    if (in) {
+      double qx[DIM];
+      load_point<DIM, false>(a.Xs, (uint32_t)q, qx);
+      Cq = a.cand[a.cell_of[q]];
+      // the covered radius of the search kernel
+      double mfrac = 0.5;
+      bool full = true;
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) {
-      const double u = __dmul_rn(__dsub_rn(qx[j], a.lo[j]), a.inv_w);
-      const double fl = floor(u);
-      const double fr = u - fl;
-      mfrac = fmin(mfrac, fmin(fr, 1.0 - fr));
-      const int64_t c = (int64_t)fl;
-      if (c > 1 || c < a.g[j] - 2) full = false;
+      for (int j = 0; j < DIM; ++j) {
+        const double u = __dmul_rn(__dsub_rn(qx[j], a.lo[j]), a.inv_w);
+        const double fl = floor(u);
+        const double fr = u - fl;
+        mfrac = fmin(mfrac, fmin(fr, 1.0 - fr));
+        const int64_t c = (int64_t)fl;
+        if (c > 1 || c < a.g[j] - 2) full = false;
+      }
+      const double r = (1.0 + mfrac) * a.w * (1.0 - a.margin);
+      defer = !full && Cq > 0 && a.defer_coef * (double)powf((float)Cq, -2.0f / DIM) > r * r;
     }
-    const double r = (1.0 + mfrac) * a.w * (1.0 - a.margin);
-    const bool defer = !full && Cq > 0 &&
-                       a.defer_coef * (double)powf((float)Cq, -2.0f / DIM) > r * r;
-    if (defer) {
-      ++ndef;
-    } else {
-      keepm |= 1u << k;
-      ++nkeep;
+    mk[k] = __ballot(in && !defer);
+    md[k] = __ballot(in && defer);
+    nk += (uint32_t)__popcll(mk[k]);
+    nd += (uint32_t)__popcll(md[k]);
+    if (in && !defer) {
       csum += Cq;
       cmax = cmax > Cq ? cmax : (unsigned long long)Cq;
     }
   }
-  // kept: block scan + look-back; deferred: one atomic per block
-  uint32_t agg, dagg;
-  uint32_t ex = block_excl_scan<256>(nkeep, &agg);
-  const uint32_t dex = block_excl_scan<256>(ndef, &dagg);
-  if (threadIdx.x == 0) s_fbase = dagg ? (uint32_t)atomicAdd(a.fail_count, (int32_t)dagg) : 0u;
-  const uint32_t excl = lb_tile_prefix(a.state, lt, agg, &s_excl);
-  if (threadIdx.x == 0 && lt.tile == nb - 1) *a.out_count = excl + agg;
-  uint32_t o = excl + ex, f = s_fbase + dex;
+  if (lane == 0) {
+    s_wk[w] = nk;
+    s_wd[w] = nd;
+  }
+  __syncthreads();
+  uint32_t bk = 0, bd = 0, agg = 0, dagg = 0;
 #pragma unroll
-  for (int k = 0; k < kDeferItems; ++k) {
-    if (base + k >= a.n_active) break;
-    if (keepm >> k & 1u)
-      a.out_active[o++] = qk[k];
-    else
-      a.fail_list[f++] = a.perm[qk[k]];
+  for (int i = 0; i < 4; ++i) {
+    if (i < w) {
+      bk += s_wk[i];
+      bd += s_wd[i];
+    }
+    agg += s_wk[i];
+    dagg += s_wd[i];
+  }
+  if (threadIdx.x == 0) s_fbase = dagg ? (uint32_t)atomicAdd(a.fail_count, (int32_t)dagg) : 0u;
+  const uint32_t excl = lb_tile_prefix(a.state, lt, agg, &s_excl);  // (a barrier)
+  if (threadIdx.x == 0 && lt.tile == nb - 1) *a.out_count = excl + agg;
+  uint32_t o = excl + bk, f = s_fbase + bd;
+#pragma unroll
+  for (int k = 0; k < kDeferRounds; ++k) {
+    if ((mk[k] >> lane) & 1ull) a.out_active[o + (uint32_t)__popcll(mk[k] & lt_mask)] = qk[k];
+    if ((md[k] >> lane) & 1ull) a.fail_list[f + (uint32_t)__popcll(md[k] & lt_mask)] = a.perm[qk[k]];
+    o += (uint32_t)__popcll(mk[k]);
+    f += (uint32_t)__popcll(md[k]);
   }
   // candidate sum and maximum of the kept queries
 #pragma unroll
@@ -914,16 +931,16 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
     const unsigned long long m2 = __shfl_xor(cmax, off, 64);
     cmax = cmax > m2 ? cmax : m2;
   }
-  if ((threadIdx.x & 63) == 0) {
-    s_sum[threadIdx.x >> 6] = csum;
-    s_max[threadIdx.x >> 6] = cmax;
+  if (lane == 0) {
+    s_sum[w] = csum;
+    s_max[w] = cmax;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long ts = 0, tm = 0;
-    for (int w = 0; w < 4; ++w) {
-      ts += s_sum[w];
-      tm = tm > s_max[w] ? tm : s_max[w];
+    for (int i = 0; i < 4; ++i) {
+      ts += s_sum[i];
+      tm = tm > s_max[i] ? tm : s_max[i];
     }
     if (ts) atomicAdd(&a.cand_sum[0], ts);
     if (tm) atomicMax(&a.cand_sum[1], tm);
