@@ -390,8 +390,8 @@ k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int64_t nb, uint32_t*
 
 // Active list in one pass: the sorted positions whose point failed, in order.
 __global__ void __launch_bounds__(kBlock)
-k_active_list(const uint8_t* __restrict__ failed, const int32_t* __restrict__ perm, int64_t N,
-              int64_t nb, int32_t* __restrict__ out, uint32_t* __restrict__ count,
+k_active_list(const uint8_t* __restrict__ failed, uint8_t tag, const int32_t* __restrict__ perm,
+              int64_t N, int64_t nb, int32_t* __restrict__ out, uint32_t* __restrict__ count,
               uint32_t* __restrict__ state) {
   const LbTile lt = lb_take_tile(state, nb);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -402,7 +402,7 @@ k_active_list(const uint8_t* __restrict__ failed, const int32_t* __restrict__ pe
 #pragma unroll
   for (int r = 0; r < kCtRounds; ++r) {
     const int64_t p = wbase + r * 64 + lane;
-    m[r] = __ballot(p < N && failed[perm[p]]);
+    m[r] = __ballot(p < N && failed[perm[p]] == tag);
     cnt += (uint32_t)__popcll(m[r]);
   }
   uint32_t total;
@@ -485,8 +485,9 @@ __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
                                   const uint64_t* __restrict__ cell_key, const uint32_t* d_M,
                                   const uint32_t* __restrict__ dense,
                                   const uint2* __restrict__ rowtab,
-                                  const uint8_t* __restrict__ cell_active, GeomDev gd,
-                                  uint32_t* __restrict__ ranges, uint8_t* __restrict__ rslot,
+                                  const uint8_t* __restrict__ cell_active, uint8_t active_tag,
+                                  GeomDev gd, uint32_t* __restrict__ ranges,
+                                  uint8_t* __restrict__ rslot,
                                   uint32_t* __restrict__ nrng,
                                   uint32_t* __restrict__ cand_count) {
   constexpr int R = DIM == 2 ? 3 : DIM == 3 ? 9 : DIM == 4 ? 27 : DIM == 5 ? 81 : 243;
@@ -499,7 +500,7 @@ __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
   const int64_t groups = (int64_t)gridDim.x * (blockDim.x / S);
   for (int64_t c = (int64_t)blockIdx.x * (blockDim.x / S) + threadIdx.x / S; c < (int64_t)M;
        c += groups) {
-    if (cell_active && !cell_active[c]) continue;
+    if (cell_active && cell_active[c] != active_tag) continue;
     const uint32_t p0 = cell_start[c];
     int64_t cc[DIM];
 #pragma unroll
@@ -708,11 +709,11 @@ __global__ void k_heavy_list(const int32_t* __restrict__ active, int64_t n_activ
 }
 
 __global__ void k_mark_failed(const int32_t* __restrict__ fail_list, const int32_t* d_count,
-                              uint8_t* __restrict__ failed) {
+                              uint8_t* __restrict__ failed, uint8_t tag) {
   const int64_t cnt = *d_count;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
        i += (int64_t)gridDim.x * blockDim.x)
-    failed[fail_list[i]] = 1;
+    failed[fail_list[i]] = tag;
 }
 
 // Zero fill: `words` 32-bit words, then `tail` (< 4) trailing bytes.  A kernel
@@ -864,15 +865,16 @@ void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags, u
   KNN_LAUNCHED();
 }
 
-void launch_active_list(const uint8_t* failed, const int32_t* perm, int64_t N, int32_t* out,
-                        uint32_t* count, uint32_t* state, int64_t state_elems, hipStream_t s) {
+void launch_active_list(const uint8_t* failed, uint8_t tag, const int32_t* perm, int64_t N,
+                        int32_t* out, uint32_t* count, uint32_t* state, int64_t state_elems,
+                        hipStream_t s) {
   if (N <= 0) {
     launch_zero(count, sizeof(uint32_t), s);
     return;
   }
   const int64_t nb = ceil_div(N, kCtTile);
   KNN_CHECK(4 + 2 * nb <= state_elems, KNN_EINTERNAL, "scan state too small");
-  k_active_list<<<(unsigned)nb, kBlock, 0, s>>>(failed, perm, N, nb, out, count, state);
+  k_active_list<<<(unsigned)nb, kBlock, 0, s>>>(failed, tag, perm, N, nb, out, count, state);
   KNN_LAUNCHED();
 }
 
@@ -911,17 +913,17 @@ void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N
 void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_start,
                             const uint64_t* cell_key, const uint32_t* d_M,
                             const uint32_t* dense, const uint2* rowtab, const uint8_t* cell_active,
-                            const GridGeom& gg, uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
-                            uint32_t* cand_count, hipStream_t s) {
+                            uint8_t active_tag, const GridGeom& gg, uint32_t* ranges,
+                            uint8_t* rslot, uint32_t* nrng, uint32_t* cand_count, hipStream_t s) {
   GeomDev gd = to_dev(gg);
   const int S = gg.dims == 2 ? 4 : gg.dims == 3 ? 16 : gg.dims == 4 ? 32 : 64;
   const int nb = grid_for(N * S, 65536);
   switch (gg.dims) {
-    case 2: k_neighbor_ranges<2><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, gd, ranges, rslot, nrng, cand_count); break;
-    case 3: k_neighbor_ranges<3><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, gd, ranges, rslot, nrng, cand_count); break;
-    case 4: k_neighbor_ranges<4><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, gd, ranges, rslot, nrng, cand_count); break;
-    case 5: k_neighbor_ranges<5><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, gd, ranges, rslot, nrng, cand_count); break;
-    case 6: k_neighbor_ranges<6><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, gd, ranges, rslot, nrng, cand_count); break;
+    case 2: k_neighbor_ranges<2><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
+    case 3: k_neighbor_ranges<3><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
+    case 4: k_neighbor_ranges<4><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
+    case 5: k_neighbor_ranges<5><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
+    case 6: k_neighbor_ranges<6><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
   KNN_LAUNCHED();
@@ -952,22 +954,23 @@ void launch_heavy_list(const int32_t* active, int64_t n_active, const uint32_t* 
 }
 
 void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count, int64_t max_fail,
-                        uint8_t* failed, hipStream_t s) {
-  k_mark_failed<<<grid_for(max_fail), kBlock, 0, s>>>(fail_list, d_fail_count, failed);
+                        uint8_t* failed, uint8_t tag, hipStream_t s) {
+  k_mark_failed<<<grid_for(max_fail), kBlock, 0, s>>>(fail_list, d_fail_count, failed, tag);
   KNN_LAUNCHED();
 }
 
 __global__ void k_mark_cells_of(const int32_t* __restrict__ active, int64_t n_active,
-                                const uint32_t* __restrict__ cell_of, uint8_t* __restrict__ flags) {
+                                const uint32_t* __restrict__ cell_of, uint8_t* __restrict__ flags,
+                                uint8_t tag) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_active;
        i += (int64_t)gridDim.x * blockDim.x)
-    flags[cell_of[active[i]]] = 1;
+    flags[cell_of[active[i]]] = tag;
 }
 
 void launch_mark_cells_of(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
-                          uint8_t* flags, hipStream_t s) {
+                          uint8_t* flags, uint8_t tag, hipStream_t s) {
   if (n_active <= 0) return;
-  k_mark_cells_of<<<grid_for(n_active), kBlock, 0, s>>>(active, n_active, cell_of, flags);
+  k_mark_cells_of<<<grid_for(n_active), kBlock, 0, s>>>(active, n_active, cell_of, flags, tag);
   KNN_LAUNCHED();
 }
 

@@ -126,6 +126,9 @@ GridGeom make_geom(const knn_index& idx, double& w) {
   throw Error(KNN_EINTERNAL, "could not choose a grid geometry");
 }
 
+// Flag value of a level (> 0) in the failure and active-cell arrays: 1..255.
+uint8_t level_tag(int level) { return (uint8_t)(1 + (level - 1) % 255); }
+
 double elapsed_ms(hipEvent_t a, hipEvent_t b) {
   float ms = 0;
   KNN_HIP(hipEventElapsedTime(&ms, a, b));
@@ -257,7 +260,7 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s, b
 }
 
 int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_t Mcap_known,
-                     const uint8_t* cell_active) {
+                     const uint8_t* cell_active, uint8_t active_tag) {
   const int64_t N = idx.N;
   const int n = idx.n;
   const int64_t R = pow3(n - 1);
@@ -278,15 +281,15 @@ int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_
   c.rslot.reserve((size_t)Mcap * R);
   c.nrng.reserve(N);
   launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, c.dense_used,
-                         c.rowtab_used, cell_active, c.gg, c.ranges.p, c.rslot.p, c.nrng.p,
-                         c.cand_count.p, s);
+                         c.rowtab_used, cell_active, active_tag, c.gg, c.ranges.p, c.rslot.p,
+                         c.nrng.p, c.cand_count.p, s);
   return Mcap;
 }
 
 int64_t build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s,
                     int64_t Mcap_known) {
   build_grid(idx, c, w, s);
-  return build_ranges(idx, c, s, Mcap_known, nullptr);
+  return build_ranges(idx, c, s, Mcap_known, nullptr, 0);
 }
 
 uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
@@ -389,7 +392,10 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   c.active.reserve(N);
   c.fail_list.reserve(N);
   c.failed.reserve(N);
+  c.cell_active.reserve(N);
   c.cand_sum.reserve(2);
+  // Failure and active-cell flags carry the level's tag (level_tag), so they
+  // are cleared only when the tags start over (before level 1's marks).
   const int ncu = cu_count(c.device);
 
   Events ev(st != nullptr);
@@ -447,16 +453,14 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     const int32_t* active = nullptr;
     const uint8_t* cell_active = nullptr;
     if (level > 0) {
-      launch_active_list(c.failed.p, c.perm.p, N, c.active.p, c.scal.p + 1, c.scan_state.p,
-                         (int64_t)c.scan_state.n, s);
+      launch_active_list(c.failed.p, level_tag(level), c.perm.p, N, c.active.p, c.scal.p + 1,
+                         c.scan_state.p, (int64_t)c.scan_state.n, s);
       active = c.active.p;
       // neighbour ranges only for the cells that hold an active query
-      c.cell_active.reserve(N);
-      launch_zero(c.cell_active.p, (size_t)N, s);
-      launch_mark_cells_of(active, A, c.cell_of.p, c.cell_active.p, s);
+      launch_mark_cells_of(active, A, c.cell_of.p, c.cell_active.p, level_tag(level), s);
       cell_active = c.cell_active.p;
     }
-    lp.Mcap = build_ranges(idx, c, s, rp ? rp->Mcap : 0, cell_active);
+    lp.Mcap = build_ranges(idx, c, s, rp ? rp->Mcap : 0, cell_active, level_tag(level));
     // the level's counters start here: the deferral filter appends to the
     // failure list
     const int64_t A_in = A;
@@ -719,8 +723,12 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     KNN_CHECK(fails <= A_in, KNN_EINTERNAL, "more failures than attempted queries");
     // failures are re-queued on a grid with a larger cell side (Alg. 1):
     // linear growth by eps_step * w0 first, then geometric growth
-    launch_zero(c.failed.p, (size_t)N, s);
-    launch_mark_failed(c.fail_list.p, c.iscal.p + kFailSlot, fails, c.failed.p, s);
+    if (level_tag(level + 1) == 1) {  // tags wrapped: clear the stale ones
+      launch_zero(c.failed.p, (size_t)N, s);
+      launch_zero(c.cell_active.p, (size_t)N, s);
+    }
+    launch_mark_failed(c.fail_list.p, c.iscal.p + kFailSlot, fails, c.failed.p,
+                       level_tag(level + 1), s);
     A = fails;
     w = (1.0 / c.gg.inv_w);
     if (level < linear)

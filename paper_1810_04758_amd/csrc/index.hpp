@@ -135,7 +135,7 @@ struct JoinParams {
 void build_grid(const knn_index& idx, JoinContext& ctx, double w, hipStream_t s,
                 bool from_prev = false);
 int64_t build_ranges(const knn_index& idx, JoinContext& ctx, hipStream_t s, int64_t Mcap_known,
-                     const uint8_t* cell_active);
+                     const uint8_t* cell_active, uint8_t active_tag);
 // Builds the grid level of cell side w into ctx (Sec. 3.1 / 4.6).
 // Mcap_known > 0: the cell count that sizes the 5-6 dimension range arrays
 // (no round trip); else it is read back when needed.  Returns the Mcap used.

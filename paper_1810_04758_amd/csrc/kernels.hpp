@@ -103,17 +103,17 @@ void launch_dense_table(const uint64_t* cell_key, const uint32_t* d_M, int64_t N
 // points, split where the last cell coordinate reaches the cell's and where
 // it passes it; their segment index in rslot[c*R + i], their number in
 // nrng[c], and the candidate count (sum of lengths) in cand_count[c].
-// cell_active (nullable): only the flagged cells get ranges (the others'
-// entries are left as they were).
+// cell_active (nullable): only the cells flagged with active_tag get ranges
+// (the others' entries are left as they were).
 void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_start,
                             const uint64_t* cell_key, const uint32_t* d_M,
                             const uint32_t* dense /*nullable*/, const uint2* rowtab /*nullable*/,
-                            const uint8_t* cell_active /*nullable*/, const GridGeom& gg,
-                            uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
-                            uint32_t* cand_count, hipStream_t s);
-// flags[cell_of[active[i]]] = 1 for every active query.
+                            const uint8_t* cell_active /*nullable*/, uint8_t active_tag,
+                            const GridGeom& gg, uint32_t* ranges, uint8_t* rslot,
+                            uint32_t* nrng, uint32_t* cand_count, hipStream_t s);
+// flags[cell_of[active[i]]] = tag for every active query.
 void launch_mark_cells_of(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
-                          uint8_t* flags, hipStream_t s);
+                          uint8_t* flags, uint8_t tag, hipStream_t s);
 
 // ---- work items (grid.hip) ----
 // Work item i = G consecutive active slots.  Its estimate is the sum of the
@@ -134,13 +134,15 @@ void launch_heavy_list(const int32_t* active /*nullable*/, int64_t n_active,
                        const uint32_t* cell_of, const uint32_t* cand_count, uint32_t heavy_min,
                        int32_t* list, int32_t* count, unsigned long long* cand_sum,
                        hipStream_t s);
-// failed[id] = 1 for the ids of the failure list (next level's active list).
+// failed[id] = tag for the ids of the failure list (the next level's active
+// queries carry that level's tag).
 void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count,
-                        int64_t max_fail, uint8_t* failed, hipStream_t s);
-// out = the sorted positions p with failed[perm[p]] != 0, in order; their
+                        int64_t max_fail, uint8_t* failed, uint8_t tag, hipStream_t s);
+// out = the sorted positions p with failed[perm[p]] == tag, in order; their
 // number to *count (device).  One pass (scan state as launch_exclusive_scan).
-void launch_active_list(const uint8_t* failed, const int32_t* perm, int64_t N, int32_t* out,
-                        uint32_t* count, uint32_t* state, int64_t state_elems, hipStream_t s);
+void launch_active_list(const uint8_t* failed, uint8_t tag, const int32_t* perm, int64_t N,
+                        int32_t* out, uint32_t* count, uint32_t* state, int64_t state_elems,
+                        hipStream_t s);
 // Zeroes `bytes` bytes at p (4-byte aligned) with a kernel, not a memset node.
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
