@@ -161,7 +161,7 @@ int64_t JoinContext::device_bytes() const {
                    scal.bytes() + iscal.bytes() + active.bytes() + fail_list.bytes() +
                    failed.bytes() + ikeys.bytes() + ikeys2.bytes() + ivals.bytes() +
                    ivals2.bytes() + out_ids.bytes() + out_d.bytes() + tail_scratch.bytes() +
-                   cand_sum.bytes() + heavy.bytes() + cell_active.bytes() + rowtab.bytes() +
+                   heavy.bytes() + cell_active.bytes() + rowtab.bytes() +
                    Xs2.bytes() + perm2.bytes() + pos.bytes() + active2.bytes() +
                    scan_state.bytes());
 }
@@ -393,7 +393,6 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   c.fail_list.reserve(N);
   c.failed.reserve(N);
   c.cell_active.reserve(N);
-  c.cand_sum.reserve(2);
   // Failure and active-cell flags carry the level's tag (level_tag), so they
   // are cleared only when the tags start over (before level 1's marks).
   const int ncu = cu_count(c.device);
@@ -487,7 +486,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       da.out_count = c.scal.p + 2;
       da.fail_list = c.fail_list.p;
       da.fail_count = c.iscal.p + kFailSlot;
-      da.cand_sum = reinterpret_cast<unsigned long long*>(c.cand_sum.p);
+      da.cand_sum = reinterpret_cast<unsigned long long*>(c.iscal.p + kCandSumSlot);
       da.state = c.scan_state.p;
       da.state_elems = (int64_t)c.scan_state.n;
       launch_defer_filter(da, idx.n, s);
@@ -504,10 +503,11 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       T = rp->T;
       if (filt) A = rp->A_kept;
     } else {
-      if (!filt) launch_active_cand_sum(active, A, c.cell_of.p, c.cand_count.p, c.cand_sum.p, s);
+      uint64_t* csum = reinterpret_cast<uint64_t*>(c.iscal.p + kCandSumSlot);
+      if (!filt) launch_active_cand_sum(active, A, c.cell_of.p, c.cand_count.p, csum, s);
       c.pinned.reserve(kCounterInts + 16);
       int32_t* hp = c.pinned.p;
-      KNN_HIP(hipMemcpyAsync(hp, c.cand_sum.p, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipMemcpyAsync(hp, csum, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipMemcpyAsync(hp + 4, c.scal.p, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));  // the level's one round trip before the search
       uint64_t tot[2];

@@ -66,7 +66,7 @@ struct JoinContext {
   DevBuf<int32_t> out_ids;  // staging for host-destination joins
   DevBuf<double> out_d;
   DevBuf<char> tail_scratch;
-  DevBuf<uint64_t> cand_sum;  // [0] candidates of the active queries, [1] their maximum
+  // [0] candidates of the active queries, [1] their maximum
   DevBuf<int32_t> heavy;      // heavy queries of the level
   DevBuf<uint8_t> cell_active;  // cells holding an active query (levels > 0)
   const uint32_t* dense_used = nullptr;  // the level's dense key table, if any

@@ -19,7 +19,8 @@ constexpr int kHeavyFailSlot = kHeavySlot + kLineInts;      // of which failed (
 constexpr int kHeavyCandSlot = kHeavyFailSlot + kLineInts;  // their candidates (uint64)
 constexpr int kWalkErrSlot = kHeavyCandSlot + kLineInts;    // candidate-list overruns
 constexpr int kSpecSlot = kWalkErrSlot + kLineInts;          // speculations that held
-constexpr int kCounterInts = kSpecSlot + kLineInts;
+constexpr int kCandSumSlot = kSpecSlot + kLineInts;          // candidate sum, max (2 x u64)
+constexpr int kCounterInts = kCandSumSlot + kLineInts;
 
 // Geometry of one grid level (Sec. 3.1): cell side 1/inv_w, origin lo.
 struct GridGeom {

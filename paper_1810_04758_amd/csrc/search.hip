@@ -1270,7 +1270,6 @@ void launch_dim(const SearchArgs& a, int T, int blocks, int threads, size_t lds,
 }  // namespace
 
 void launch_defer_filter(const DeferArgs& a, int dims, hipStream_t s) {
-  launch_zero(a.cand_sum, 2 * sizeof(unsigned long long), s);
   if (a.n_active <= 0) {
     launch_zero(a.out_count, sizeof(uint32_t), s);
     return;
