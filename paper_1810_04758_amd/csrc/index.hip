@@ -664,12 +664,9 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       int32_t* cnt = c.pinned.p;
       KNN_HIP(hipMemcpyAsync(cnt, c.iscal.p, kCounterInts * sizeof(int32_t), hipMemcpyDeviceToHost,
                              s));
-      KNN_HIP(hipMemcpyAsync(cnt + kCounterInts, c.scan_state.p + 2, sizeof(int32_t),
-                             hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));
       KNN_CHECK(cnt[kWalkErrSlot] == 0, KNN_EINTERNAL,
                 "search: a candidate list was inconsistent with its count");
-      KNN_CHECK(cnt[kCounterInts] == 0, KNN_EINTERNAL, "scan: a look-back found no prefix");
       sc[0] = cnt[kFailSlot];
       sc[1] = cnt[kRefineSlot];
       spec_held = cnt[kSpecSlot];
@@ -735,6 +732,14 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       w = w + step;
     else
       w = w * growth;
+  }
+  if (!replay) {
+    // the single-pass scans' look-back error count (must stay 0), once a join
+    c.pinned.reserve(kCounterInts + 16);
+    KNN_HIP(hipMemcpyAsync(c.pinned.p, c.scan_state.p + 2, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           s));
+    KNN_HIP(hipStreamSynchronize(s));
+    KNN_CHECK(c.pinned.p[0] == 0, KNN_EINTERNAL, "scan: a look-back found no prefix");
   }
   if (st) {
     st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
