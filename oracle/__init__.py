@@ -38,6 +38,8 @@ def lib():
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         L.oracle_knn.argtypes = [P, i64, i32, i32, P, i64, P, P, i32]
         L.oracle_knn.restype = ctypes.c_int
+        L.oracle_knn_kdtree.argtypes = [P, i64, i32, i32, P, i64, P, P, i32]
+        L.oracle_knn_kdtree.restype = ctypes.c_int
         L.oracle_sq_dist.argtypes = [P, i32, i64, i64]
         L.oracle_sq_dist.restype = f64
         L.oracle_bounds.argtypes = [P, i64, i32, P, P]
@@ -86,6 +88,27 @@ def knn(D, K, rows=None, threads=0):
     rc = lib().oracle_knn(_p(D), N, n, K, rp, nrows, _p(ids), _p(dists), threads)
     if rc != 0:
         raise ValueError("oracle_knn: invalid arguments")
+    return ids, dists
+
+
+def knn_kdtree(D, K, rows=None, threads=0):
+    """The same result as knn() (Sec. 2.1 definition) through an exact kd-tree
+    search, for sizes where brute force is too slow.  Pinned to knn() by the
+    tests; same arguments and outputs."""
+    D = _f64(D)
+    N, n = D.shape
+    if rows is None:
+        nrows = N
+        rp = None
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        nrows = rows.shape[0]
+        rp = _p(rows)
+    ids = np.empty((nrows, K), dtype=np.int32)
+    dists = np.empty((nrows, K), dtype=np.float64)
+    rc = lib().oracle_knn_kdtree(_p(D), N, n, K, rp, nrows, _p(ids), _p(dists), threads)
+    if rc != 0:
+        raise ValueError("oracle_knn_kdtree: invalid arguments")
     return ids, dists
 
 

@@ -35,6 +35,10 @@
 //     cumulative histogram count is compared with K per sample point
 //     (count >= K * n_sample); self pairs are skipped.
 //
+// Two searches give the definition's result: plain brute force (the
+// definition written out), and an exact kd-tree search for inputs too large
+// for brute force, pinned to the first on many inputs.
+//
 // Parity pins (see tests/test_oracle_*.py): brute force in exact rational
 // arithmetic on tiny dyadic inputs, the paper's figure examples, integer
 // lattice closed forms, invariants and metamorphic relations.  The eps_min
@@ -114,6 +118,209 @@ int oracle_knn(const double* D, int64_t N, int32_t n, int32_t K,
       for (int32_t k = 0; k < K; ++k) {
         out_ids[r * K + k] = (int32_t)cand[k].second;
         out_dists[r * K + k] = std::sqrt(cand[k].first);
+      }
+    }
+  }
+  return bad ? -1 : 0;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The same result (Sec. 2.1 definition) through an exact kd-tree search, for
+// inputs too large for brute force.  This is a second oracle, not the
+// definition itself: the tests pin it to oracle_knn above on many inputs.
+//
+// Tree: the points are split recursively at the median of the dimension with
+// the largest extent (std::nth_element) until a node holds at most 16 points;
+// every node keeps the exact minimum and maximum of its points' coordinates
+// (any split gives the same result; the choice only affects speed).
+// Search: depth first, nearer child first, keeping the K smallest pairs
+// (d^2, id) of the points seen (ids other than the query's own) in a max-heap.
+// A node is skipped only when its box distance b^2 = sum_j gap_j^2 (gap_j the
+// distance from the query to the box along dimension j) exceeds the current
+// K-th d^2 by the factor (1 + 2^-40).  Why that is exact: for a point p in
+// the box the true d^2(q, p) is at least the true box distance; the computed
+// values carry relative errors below (n + 2) 2^-53 each, so the computed
+// d^2(q, p) then exceeds the K-th d^2 strictly: p could neither enter the K
+// smallest nor tie with the K-th.  (This assumes that no nonzero coordinate
+// difference is so small that its square underflows, |x - y| > 2^-500.)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct KdNode {
+  int64_t begin, end;   // points [begin, end) of the tree's point order
+  int64_t left, right;  // children (-1: leaf)
+  double lo[8], hi[8];  // exact bounds of the node's points
+};
+
+struct KdTree {
+  int n = 0;
+  std::vector<int64_t> order;  // tree order -> point id
+  std::vector<double> pts;     // coordinates in tree order, row-major
+  std::vector<KdNode> nodes;
+};
+
+// The tree's shape depends only on N: node [begin, end) with more than 16
+// points has the children [begin, mid) and [mid, end), mid = begin +
+// (end - begin) / 2.  Nodes are numbered breadth first, so those of one depth
+// are contiguous; a depth's nodes are independent (their point sets are fixed
+// once every ancestor has been split) and are processed in parallel.
+void kd_build(KdTree& t, const double* D, int64_t N) {
+  const int n = t.n;
+  t.order.resize((size_t)N);
+  for (int64_t i = 0; i < N; ++i) t.order[i] = i;
+  std::vector<int64_t> depth_start;
+  KdNode root;
+  root.begin = 0;
+  root.end = N;
+  root.left = root.right = -1;
+  t.nodes.push_back(root);
+  int64_t level_begin = 0;
+  while (level_begin < (int64_t)t.nodes.size()) {
+    int64_t level_end = (int64_t)t.nodes.size();
+    depth_start.push_back(level_begin);
+    for (int64_t v = level_begin; v < level_end; ++v) {
+      int64_t b = t.nodes[v].begin, e = t.nodes[v].end;
+      if (e - b <= 16) continue;
+      int64_t mid = b + (e - b) / 2;
+      KdNode c;
+      c.left = c.right = -1;
+      c.begin = b;
+      c.end = mid;
+      t.nodes[v].left = (int64_t)t.nodes.size();
+      t.nodes.push_back(c);
+      c.begin = mid;
+      c.end = e;
+      t.nodes[v].right = (int64_t)t.nodes.size();
+      t.nodes.push_back(c);
+    }
+    level_begin = level_end;
+  }
+  depth_start.push_back((int64_t)t.nodes.size());
+  for (size_t d = 0; d + 1 < depth_start.size(); ++d) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t v = depth_start[d]; v < depth_start[d + 1]; ++v) {
+      KdNode& nd = t.nodes[v];
+      for (int j = 0; j < n; ++j) {
+        nd.lo[j] = D[t.order[nd.begin] * n + j];
+        nd.hi[j] = nd.lo[j];
+      }
+      for (int64_t k = nd.begin; k < nd.end; ++k)
+        for (int j = 0; j < n; ++j) {
+          double x = D[t.order[k] * n + j];
+          if (x < nd.lo[j]) nd.lo[j] = x;
+          if (x > nd.hi[j]) nd.hi[j] = x;
+        }
+      if (nd.left < 0) continue;
+      // split at the median of the dimension with the largest extent
+      int split = 0;
+      for (int j = 1; j < n; ++j)
+        if (nd.hi[j] - nd.lo[j] > nd.hi[split] - nd.lo[split]) split = j;
+      int64_t mid = nd.begin + (nd.end - nd.begin) / 2;
+      std::nth_element(t.order.begin() + nd.begin, t.order.begin() + mid,
+                       t.order.begin() + nd.end, [&](int64_t a, int64_t b) {
+                         return D[a * n + split] < D[b * n + split];
+                       });
+    }
+  }
+}
+
+double kd_box_d2(const KdNode& nd, const double* q, int n) {
+  double s = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double gap = 0.0;
+    if (q[j] < nd.lo[j]) gap = nd.lo[j] - q[j];
+    if (q[j] > nd.hi[j]) gap = q[j] - nd.hi[j];
+    s = s + gap * gap;
+  }
+  return s;
+}
+
+// The K smallest (d^2, id) pairs seen so far, as a max-heap (front = largest).
+struct KBest {
+  int32_t K;
+  std::vector<std::pair<double, int64_t>> heap;
+  void offer(double d2, int64_t id) {
+    std::pair<double, int64_t> c(d2, id);
+    if ((int32_t)heap.size() < K) {
+      heap.push_back(c);
+      std::push_heap(heap.begin(), heap.end());
+    } else if (c < heap.front()) {
+      std::pop_heap(heap.begin(), heap.end());
+      heap.back() = c;
+      std::push_heap(heap.begin(), heap.end());
+    }
+  }
+  bool full() const { return (int32_t)heap.size() == K; }
+  double worst() const { return heap.front().first; }
+};
+
+void kd_search(const KdTree& t, int64_t node, const double* q, int64_t self, KBest& best) {
+  const int n = t.n;
+  const KdNode& nd = t.nodes[node];
+  if (best.full() && kd_box_d2(nd, q, n) > best.worst() * (1.0 + std::ldexp(1.0, -40))) return;
+  if (nd.left < 0) {
+    for (int64_t k = nd.begin; k < nd.end; ++k) {
+      int64_t j = t.order[k];
+      if (j == self) continue;  // exclude the point itself (by id)
+      best.offer(sq_dist(q, &t.pts[k * n], n), j);
+    }
+    return;
+  }
+  double dl = kd_box_d2(t.nodes[nd.left], q, n);
+  double dr = kd_box_d2(t.nodes[nd.right], q, n);
+  if (dl <= dr) {
+    kd_search(t, nd.left, q, self, best);
+    kd_search(t, nd.right, q, self, best);
+  } else {
+    kd_search(t, nd.right, q, self, best);
+    kd_search(t, nd.left, q, self, best);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Same contract as oracle_knn (rows, outputs, return value), answered with
+// the kd-tree search above.
+int oracle_knn_kdtree(const double* D, int64_t N, int32_t n, int32_t K, const int64_t* rows,
+                      int64_t nrows, int32_t* out_ids, double* out_dists, int32_t nthreads) {
+  if (!D || !out_ids || !out_dists || n < 1 || n > 8 || K < 1 || K > N - 1) return -1;
+  if (!rows) nrows = N;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  KdTree t;
+  t.n = n;
+  kd_build(t, D, N);
+  t.pts.resize((size_t)N * n);
+#pragma omp parallel for
+  for (int64_t k = 0; k < N; ++k)
+    for (int j = 0; j < n; ++j) t.pts[k * n + j] = D[t.order[k] * n + j];
+  int bad = 0;
+#pragma omp parallel
+  {
+    KBest best;
+    best.K = K;
+    best.heap.reserve((size_t)K);
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t s = 0; s < nrows; ++s) {
+      // all rows: visited in tree order (neighbouring queries walk the same
+      // nodes), each written to its own output row
+      int64_t r = rows ? s : t.order[s];
+      int64_t i = rows ? rows[r] : r;
+      if (i < 0 || i >= N) {
+        bad = 1;
+        continue;
+      }
+      best.heap.clear();
+      kd_search(t, 0, D + i * n, i, best);
+      std::sort_heap(best.heap.begin(), best.heap.end());  // ascending (d^2, id)
+      for (int32_t k = 0; k < K; ++k) {
+        out_ids[r * K + k] = (int32_t)best.heap[k].second;
+        out_dists[r * K + k] = std::sqrt(best.heap[k].first);
       }
     }
   }
