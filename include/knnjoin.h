@@ -122,7 +122,7 @@ typedef struct knn_join_opts {
                              repeat the recorded counts; per-level times are 0 [0] */
   double tail_pairs;      /* brute-force tail once (remaining queries) x N <= this
                              [autotuned or 2.5e8]; < 0 disables the tail (the
-                             remedy Sec. 5.3.8 proposes) */
+                             remedy Sec. 5.4 proposes) */
   int64_t heavy_min;      /* queries with at least this many
                              candidates get a workgroup each; 0 = automatic
                              (those that would outlast the level), < 0 = never */
@@ -218,6 +218,29 @@ typedef struct knn_index_info {
 } knn_index_info;
 int knn_index_info_get(const knn_index* idx, knn_index_info* out);
 
+/*
+ * The search-distance sampling an index holds (Sec. 4.4), read only, for
+ * inspection and testing.  Any output pointer may be NULL.
+ *   hist_sample  host, knn_index_info.n_sample entries: ids of the
+ *                histogram's sample points, increasing.
+ *   mean_sample  host, up to KNN_MAX_MEAN_SAMPLE entries: ids of the eps_mean
+ *                sample, increasing; their number goes to *n_mean.
+ *   counts       host, knn_index_info.n_bins entries: distances per bin (not
+ *                cumulative), bin b = [b, b+1) * bin_width.
+ *   bin_width    eps_mean / n_bins.
+ * How the samples are drawn (so that they can be reproduced): SplitMix64
+ * (Steele, Lea, Flood, OOPSLA 2014) outputs reduced modulo N, repeats
+ * skipped, until enough distinct ids are held, then sorted (every id when the
+ * sample would hold N or more).  The eps_mean sample holds
+ * min(max(round(mean_frac * N), min_mean_sample), N, KNN_MAX_MEAN_SAMPLE)
+ * ids drawn from the state `seed`; the histogram sample n_sample ids drawn
+ * from the state seed ^ 0x5DEECE66D.
+ * Errors: KNN_EINVAL (idx NULL).
+ */
+#define KNN_MAX_MEAN_SAMPLE 20000
+int knn_index_sampling_get(const knn_index* idx, int64_t* hist_sample, int64_t* mean_sample,
+                           int64_t* n_mean, uint64_t* counts, double* bin_width);
+
 /* ------------------------------------------------------------------------
  * Autotuner.  The level-0 cell side (as a multiple of eps_min(K)) and the
  * geometric growth of the cell side between levels decide how many queries
@@ -246,8 +269,10 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
 int knn_autotune_save(const char* path);
 int knn_autotune_load(const char* path);
 
-/* Upper bound of the device bytes one self-join of (idx, K) with host
- * outputs allocates beyond the index (the serving loop's admission size). */
+/* Upper bound of the device bytes one eager self-join of (idx, K) with host
+ * outputs allocates beyond the index, the device cache's rounding and reuse
+ * slack included (the serving loop's admission size).  A join captured in a
+ * HIP graph (use_graph) keeps every level's scratch and may hold more. */
 int knn_join_footprint(const knn_index* idx, int32_t K, uint64_t* bytes);
 
 /* eps_min(K) of Sec. 4.4 from the index's cumulative distance histogram:

@@ -51,6 +51,8 @@ def lib():
         L.oracle_sample_mean_dist.argtypes = [P, i32, P, i64]
         L.oracle_sample_mean_dist.restype = f64
         L.oracle_dist_histogram.argtypes = [P, i64, i32, P, i64, f64, i32, P]
+        L.oracle_splitmix64.argtypes = [ctypes.c_uint64, i64, P]
+        L.oracle_sample_ids.argtypes = [i64, i64, ctypes.c_uint64, P]
         L.oracle_eps_min.argtypes = [P, i32, f64, i64, i32]
         L.oracle_eps_min.restype = f64
         _lib = L
@@ -193,6 +195,22 @@ def dist_histogram(D, sample, inv_bin_width, n_bins):
     lib().oracle_dist_histogram(_p(D), D.shape[0], D.shape[1], _p(s), s.shape[0],
                                 inv_bin_width, n_bins, _p(counts))
     return counts
+
+
+def splitmix64(seed, count):
+    """The first `count` outputs of SplitMix64 from state `seed` (uint64)."""
+    out = np.empty(count, dtype=np.uint64)
+    lib().oracle_splitmix64(seed & (2 ** 64 - 1), count, _p(out))
+    return out
+
+
+def sample_ids(N, count, seed):
+    """Sec. 4.4 sampling: `count` distinct point ids drawn with SplitMix64
+    (outputs modulo N, repeats skipped), increasing; every id if count >= N."""
+    n = min(count, N)
+    out = np.empty(n, dtype=np.int64)
+    lib().oracle_sample_ids(N, count, seed & (2 ** 64 - 1), _p(out))
+    return out
 
 
 def eps_min(counts, bin_width, n_sample, K):

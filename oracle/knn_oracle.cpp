@@ -70,6 +70,15 @@ double sq_dist(const double* a, const double* b, int n) {
   return s;
 }
 
+#ifdef _OPENMP
+// Threads of a call that asks for none in particular: the OpenMP default of
+// the process (OMP_NUM_THREADS), read before any call changes it.
+int default_threads() {
+  static const int t = omp_get_max_threads();
+  return t;
+}
+#endif
+
 // Cell coordinate of one coordinate value: floor((x - lo) * inv_w).
 int64_t cell_coord(double x, double lo, double inv_w) {
   double u = (x - lo) * inv_w;
@@ -94,7 +103,7 @@ int oracle_knn(const double* D, int64_t N, int32_t n, int32_t K,
   if (!D || !out_ids || !out_dists || n < 1 || K < 1 || K > N - 1) return -1;
   if (!rows) nrows = N;
 #ifdef _OPENMP
-  if (nthreads > 0) omp_set_num_threads(nthreads);
+  omp_set_num_threads(nthreads > 0 ? nthreads : default_threads());
 #endif
   int bad = 0;
 #pragma omp parallel
@@ -290,7 +299,7 @@ int oracle_knn_kdtree(const double* D, int64_t N, int32_t n, int32_t K, const in
   if (!D || !out_ids || !out_dists || n < 1 || n > 8 || K < 1 || K > N - 1) return -1;
   if (!rows) nrows = N;
 #ifdef _OPENMP
-  if (nthreads > 0) omp_set_num_threads(nthreads);
+  omp_set_num_threads(nthreads > 0 ? nthreads : default_threads());
 #endif
   KdTree t;
   t.n = n;
@@ -486,6 +495,46 @@ void oracle_dist_histogram(const double* D, int64_t N, int32_t n, const int64_t*
       if (t < (double)n_bins) counts[(int64_t)t] += 1;
     }
   }
+}
+
+// SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014), written from its published definition: the state
+// advances by the golden-ratio increment 0x9E3779B97F4A7C15 and each output is
+// the state passed through the generator's two xor-shift-multiply rounds and
+// a final xor-shift.  out[k] = the (k+1)-th output from the state `seed`.
+void oracle_splitmix64(uint64_t seed, int64_t count, uint64_t* out) {
+  uint64_t state = seed;
+  for (int64_t k = 0; k < count; ++k) {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    out[k] = z ^ (z >> 31);
+  }
+}
+
+// The sampling of Sec. 4.4 draws point ids without replacement: successive
+// generator outputs reduced modulo N, repeats skipped, until `count` distinct
+// ids are held; returned in increasing order.  count >= N: every id.
+void oracle_sample_ids(int64_t N, int64_t count, uint64_t seed, int64_t* out) {
+  if (count >= N) {
+    for (int64_t i = 0; i < N; ++i) out[i] = i;
+    return;
+  }
+  std::vector<char> taken((size_t)N, 0);
+  int64_t held = 0;
+  uint64_t state = seed;
+  while (held < count) {
+    uint64_t v;
+    oracle_splitmix64(state, 1, &v);
+    state += 0x9E3779B97F4A7C15ull;
+    int64_t id = (int64_t)(v % (uint64_t)N);
+    if (!taken[id]) {
+      taken[id] = 1;
+      out[held++] = id;
+    }
+  }
+  std::sort(out, out + count);
 }
 
 // eps_min: midpoint of the first bin d whose cumulative count reaches K per

@@ -119,6 +119,8 @@ SIGNATURES = {
     "knn_last_error": (ctypes.c_char_p, []),
     "knn_index_info_get": (ctypes.c_int, [c_p, ctypes.POINTER(IndexInfo)]),
     "knn_eps_min": (ctypes.c_int, [c_p, c_i32, ctypes.POINTER(c_f64)]),
+    "knn_index_sampling_get": (ctypes.c_int, [c_p, c_p, c_p, ctypes.POINTER(c_i64), c_p,
+                                              ctypes.POINTER(c_f64)]),
     "knn_join_footprint": (ctypes.c_int, [c_p, c_i32, ctypes.POINTER(c_u64)]),
     "knn_autotune": (ctypes.c_int, [c_p, c_i32, c_p, ctypes.POINTER(AutotuneResult)]),
     "knn_autotune_save": (ctypes.c_int, [ctypes.c_char_p]),

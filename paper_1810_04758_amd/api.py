@@ -103,6 +103,21 @@ class Index:
         check(load().knn_eps_min(self.handle, K, ctypes.byref(v)))
         return v.value
 
+    def sampling(self):
+        """knn_index_sampling_get: the index's Sec. 4.4 samples and histogram
+        (histogram sample ids, eps_mean sample ids, per-bin counts, bin width)."""
+        inf = self.info()
+        hs = np.empty(inf["n_sample"], dtype=np.int64)
+        ms = np.empty(20000, dtype=np.int64)
+        counts = np.empty(inf["n_bins"], dtype=np.uint64)
+        nm = ctypes.c_int64()
+        bw = ctypes.c_double()
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        check(load().knn_index_sampling_get(self.handle, p(hs), p(ms), ctypes.byref(nm),
+                                            p(counts), ctypes.byref(bw)))
+        return dict(hist_sample=hs, mean_sample=ms[:nm.value].copy(), counts=counts,
+                    bin_width=bw.value)
+
     def autotune(self, K, stream=None):
         """knn_autotune: measure and cache the best (w_factor, growth) for K."""
         r = _lib.AutotuneResult()

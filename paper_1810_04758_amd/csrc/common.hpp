@@ -42,14 +42,18 @@ constexpr int kWave = 64;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Device memory cache, per device.  A released block goes back to the cache
-// and is handed out again to a request of at least half its size.  Every
+// Device memory cache, per device.  Requests are rounded up to 256 bytes
+// (below 1 MiB) or to whole MiB.  A released block goes back to the cache
+// and is handed out again to a rounded request of at least 4/5 of its size,
+// so a buffer of b requested bytes holds at most 1.25 (b + 1 MiB).  Every
 // user releases memory only after the device work that used it has finished
 // (the library's calls return after their work; an asynchronous graph replay
 // is waited for before its scratch is released), so a reused block needs no
 // stream ordering.  At most KNN_DEVICE_CACHE_BYTES (default 32 GiB) per device
 // is kept; the cache is emptied and the allocation retried when hipMalloc
 // runs out of memory.
+constexpr double kPoolSlack = 1.25;                  // capacity / rounded request, at most
+constexpr size_t kPoolRound = (size_t)1 << 20;       // rounding of large requests
 void* device_acquire(size_t bytes, int* device, size_t* capacity);
 void device_release(void* p, int device, size_t capacity);
 

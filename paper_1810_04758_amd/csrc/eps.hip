@@ -52,11 +52,18 @@ constexpr int kMaxBins = 4096;
 // square root.  A single-precision estimate (relative error below 2^-21:
 // the conversion of d2, the hardware square root and two products) decides
 // the bin unless it lies within 2^-18 (relative) of an integer; only then is
-// the double-precision value taken.
-__device__ __forceinline__ int dist_bin(double d2, double inv_bw, float inv_bw_f) {
-  const float t = __builtin_amdgcn_sqrtf((float)d2) * inv_bw_f;
-  const float r = rintf(t);
-  if (fabsf(t - r) > t * 0x1p-18f) return (int)floorf(t);
+// the double-precision value taken.  That error bound holds only while every
+// float involved is a normal number, so the estimate is used only for d2 in
+// [2^-100, 2^100] and when inv_bw lies in [2^-60, 2^60] (use_f, checked once
+// on the host): sqrt(d2) is then within [2^-50, 2^50] and the estimate within
+// [2^-110, 2^110], far inside float's normal range.  Other values take the
+// double-precision path.
+__device__ __forceinline__ int dist_bin(double d2, double inv_bw, float inv_bw_f, bool use_f) {
+  if (use_f && d2 >= 0x1p-100 && d2 <= 0x1p100) {
+    const float t = __builtin_amdgcn_sqrtf((float)d2) * inv_bw_f;
+    const float r = rintf(t);
+    if (fabsf(t - r) > t * 0x1p-18f) return (int)floorf(t);
+  }
   return (int)floor(sqrt(d2) * inv_bw);
 }
 
@@ -69,6 +76,7 @@ __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N,
                                  int n_bins, double skip_d2, uint64_t* __restrict__ counts) {
   __shared__ uint32_t h[kMaxBins];
   const float inv_bw_f = (float)inv_bw;
+  const bool use_f = inv_bw >= 0x1p-60 && inv_bw <= 0x1p60;
   __shared__ double sx[DIM][kSampleChunk];
   __shared__ int64_t sid[kSampleChunk];
   for (int b = threadIdx.x; b < n_bins; b += blockDim.x) h[b] = 0;
@@ -95,7 +103,7 @@ __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N,
           s = __dadd_rn(s, __dmul_rn(t, t));
         }
         if (s > skip_d2 || p == sid[i]) continue;  // certainly beyond the last bin, or self
-        const int b = dist_bin(s, inv_bw, inv_bw_f);
+        const int b = dist_bin(s, inv_bw, inv_bw_f, use_f);
         if (b < n_bins) atomicAdd(&h[b], 1u);
       }
     }

@@ -257,6 +257,17 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s, b
       c.rowtab_used = c.rowtab.p;
     }
   }
+  // An eager join holds at most one of the two lookup tables (the join
+  // footprint counts the larger): the one this level does not use goes back
+  // to the device cache.  No wait is needed: its last user was the range
+  // kernel of an earlier level or join, and the host has synchronised with
+  // the stream since (each level reads its counters back, each join returns
+  // after its work).  A context owned by a captured graph keeps both, since
+  // the graph's nodes refer to them.
+  if (!c.graph_owned) {
+    if (!c.dense_used) c.dense.release();
+    if (!c.rowtab_used) c.rowtab.release();
+  }
 }
 
 int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_t Mcap_known,
@@ -294,7 +305,9 @@ int64_t build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t 
 
 uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   // Upper bound of everything a JoinContext allocates, with the worst case of
-  // one non-empty cell per point (M = N).
+  // one non-empty cell per point (M = N), and of what the device cache hands
+  // out for it: at most kPoolSlack times each request rounded up, i.e.
+  // kPoolSlack (b + kPoolRound) for each of the context's buffers.
   const uint64_t N = (uint64_t)idx.N, n = (uint64_t)idx.n;
   const uint64_t R = (uint64_t)pow3(idx.n - 1);
   const uint64_t cap = (uint64_t)K + std::max<uint64_t>(16, (uint64_t)K / 2);
@@ -312,7 +325,8 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   b += std::min<uint64_t>(N, 65535) * (512 + cap * 12);  // brute-force tail scratch
   b += 4096;                           // scalars
   if (host_output) b += N * (uint64_t)K * 12;
-  return b;
+  b += (uint64_t)kContextBuffers * kPoolRound;
+  return (uint64_t)std::ceil((double)b * kPoolSlack);
 }
 
 // Lanes per query for a level of A active queries that see `cand` candidates
@@ -355,7 +369,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   const double step = (o.eps_step > 0 ? o.eps_step : 0.5) * w0;
   // growth: the paper's linear step (eps += eps_step * eps_min) for the first
   // `linear` re-indexes, then geometric growth whose default multiplies the
-  // scanned volume by 16 per level (the non-linear expansion Sec. 5.3.8
+  // scanned volume by 16 per level (the non-linear expansion Sec. 5.4
   // proposes for the GPU-Only tail)
   int linear = o.linear_levels > 0 ? o.linear_levels : (o.linear_levels < 0 ? 0 : 1);
   if (o.linear_levels == 0) {
@@ -664,7 +678,17 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       int32_t* cnt = c.pinned.p;
       KNN_HIP(hipMemcpyAsync(cnt, c.iscal.p, kCounterInts * sizeof(int32_t), hipMemcpyDeviceToHost,
                              s));
+      // the single-pass scans' look-back error count of this level's build
+      // (must stay 0), in the same round trip
+      KNN_HIP(hipMemcpyAsync(cnt + kCounterInts, c.scan_state.p + 2, sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));
+      if (cnt[kCounterInts] != 0) {
+        // cleared, so that later joins on this context start clean
+        launch_zero(c.scan_state.p + 2, sizeof(uint32_t), s);
+        KNN_HIP(hipStreamSynchronize(s));
+        throw Error(KNN_EINTERNAL, "scan: a look-back found no prefix");
+      }
       KNN_CHECK(cnt[kWalkErrSlot] == 0, KNN_EINTERNAL,
                 "search: a candidate list was inconsistent with its count");
       sc[0] = cnt[kFailSlot];
@@ -732,14 +756,6 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       w = w + step;
     else
       w = w * growth;
-  }
-  if (!replay) {
-    // the single-pass scans' look-back error count (must stay 0), once a join
-    c.pinned.reserve(kCounterInts + 16);
-    KNN_HIP(hipMemcpyAsync(c.pinned.p, c.scan_state.p + 2, sizeof(int32_t), hipMemcpyDeviceToHost,
-                           s));
-    KNN_HIP(hipStreamSynchronize(s));
-    KNN_CHECK(c.pinned.p[0] == 0, KNN_EINTERNAL, "scan: a look-back found no prefix");
   }
   if (st) {
     st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
@@ -815,9 +831,24 @@ void self_join_graph(knn_index& idx, int32_t K, int32_t* d_ids, double* d_dists,
     ev.rec(1, s);
     KNN_HIP(hipEventRecord(gp->done, s));
     if (st) {
+      // a replay has no host round trip; when the caller waits for its
+      // statistics, the error counters of its scratch are checked too
       KNN_HIP(hipEventSynchronize(ev.e[1]));
       stats_from_plan(*gp, st);
       st->ms_total = elapsed_ms(ev.e[0], ev.e[1]);
+      gp->ctx.pinned.reserve(kCounterInts + 16);
+      int32_t* cnt = gp->ctx.pinned.p;
+      KNN_HIP(hipMemcpyAsync(cnt, gp->ctx.iscal.p + kWalkErrSlot, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipMemcpyAsync(cnt + 1, gp->ctx.scan_state.p + 2, sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));
+      if (cnt[0] != 0 || cnt[1] != 0) {
+        launch_zero(gp->ctx.scan_state.p + 2, sizeof(uint32_t), s);
+        KNN_HIP(hipStreamSynchronize(s));
+        throw Error(KNN_EINTERNAL,
+                    "replayed join: a candidate list or a scan look-back was inconsistent");
+      }
     }
     return;
   }
@@ -834,6 +865,7 @@ void self_join_graph(knn_index& idx, int32_t K, int32_t* d_ids, double* d_dists,
   np->ids = d_ids;
   np->dists = d_dists;
   np->ctx.device = idx.device;
+  np->ctx.graph_owned = true;
   np->eps_min = eps_min_of(idx, K);
   KNN_HIP(hipEventCreateWithFlags(&np->done, hipEventDisableTiming));
   self_join(idx, np->ctx, K, d_ids, d_dists, o, s, &np->levels, nullptr);
@@ -931,7 +963,7 @@ knn_index* build_from_device(const double* D_dev, int64_t N, int n, const knn_bu
     // eps_mean over a sample of mean_frac * N points (Sec. 4.4)
     int64_t nm = (int64_t)std::llround(o.mean_frac * (double)N);
     nm = std::max<int64_t>(nm, o.min_mean_sample);
-    nm = std::min<int64_t>(nm, std::min<int64_t>(N, 20000));
+    nm = std::min<int64_t>(nm, std::min<int64_t>(N, KNN_MAX_MEAN_SAMPLE));
     std::vector<int64_t> sm = sample_ids(N, nm, o.seed);
     std::vector<int64_t> sh = sample_ids(N, o.n_sample, o.seed ^ 0x5DEECE66Dull);
     DevBuf<int64_t> d_sm(sm.size()), d_sh(sh.size());
@@ -959,6 +991,8 @@ knn_index* build_from_device(const double* D_dev, int64_t N, int n, const knn_bu
     std::vector<uint64_t> hc(o.n_bins);
     KNN_HIP(hipMemcpyAsync(hc.data(), counts.p, o.n_bins * 8, hipMemcpyDeviceToHost, s));
     KNN_HIP(hipStreamSynchronize(s));
+    idx->hist_sample = sh;
+    idx->mean_sample = sm;
     idx->cum.resize(o.n_bins);
     uint64_t c = 0;
     for (int b = 0; b < o.n_bins; ++b) {
@@ -1125,6 +1159,21 @@ int knn_index_info_get(const knn_index* idx, knn_index_info* out) {
     out->device_bytes = (int64_t)(idx->X.bytes() + idx->XA.bytes()) +
                         (idx->ctx ? idx->ctx->ctx.device_bytes() : 0) +
                         (idx->graph ? idx->graph->ctx.device_bytes() : 0);
+  });
+}
+
+int knn_index_sampling_get(const knn_index* idx, int64_t* hist_sample, int64_t* mean_sample,
+                           int64_t* n_mean, uint64_t* counts, double* bin_width) {
+  return guarded([&] {
+    KNN_CHECK(idx != nullptr, KNN_EINVAL, "index is NULL");
+    if (hist_sample)
+      std::copy(idx->hist_sample.begin(), idx->hist_sample.end(), hist_sample);
+    if (mean_sample)
+      std::copy(idx->mean_sample.begin(), idx->mean_sample.end(), mean_sample);
+    if (n_mean) *n_mean = (int64_t)idx->mean_sample.size();
+    if (counts)
+      for (int b = 0; b < idx->n_bins; ++b) counts[b] = idx->cum[b] - (b ? idx->cum[b - 1] : 0);
+    if (bin_width) *bin_width = idx->bin_width;
   });
 }
 

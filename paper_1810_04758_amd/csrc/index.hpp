@@ -26,6 +26,8 @@ struct knn_index {
   int n_bins = 0;
   int n_sample = 0;
   std::vector<uint64_t> cum;  // cumulative histogram counts
+  std::vector<int64_t> hist_sample;  // ids of the histogram's sample points
+  std::vector<int64_t> mean_sample;  // ids of the eps_mean sample
   std::atomic<int> busy{0};
   struct JoinContextHolder* ctx = nullptr;  // scratch of knn_self_join*
   knn::GraphPlan* graph = nullptr;          // last captured join (use_graph)
@@ -73,9 +75,12 @@ struct JoinContext {
   DevBuf<uint2> rowtab;                  // row table (cells of each grid row)
   HostBuf<int32_t> pinned;               // read-backs of the level loop
   const uint2* rowtab_used = nullptr;
+  bool graph_owned = false;  // scratch of a captured graph: buffers are never released
 
   int64_t device_bytes() const;
 };
+// Device buffers of a JoinContext (the DevBuf members above).
+constexpr int kContextBuffers = 35;
 
 // What one level of a join did, recorded by an eager run so that the same
 // launch sequence can be issued again without host round trips (a join on the

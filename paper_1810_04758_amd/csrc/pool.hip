@@ -48,7 +48,7 @@ void* device_acquire(size_t bytes, int* device, size_t* capacity) {
     std::lock_guard<std::mutex> lk(g_mu);
     Pool& pl = g_pools[dev];
     auto it = pl.free.lower_bound(want);
-    if (it != pl.free.end() && it->first <= 2 * want) {
+    if (it != pl.free.end() && it->first <= want + want / 4) {
       void* p = it->second;
       *capacity = it->first;
       pl.cached -= it->first;

@@ -1,6 +1,7 @@
-// tail.hip -- brute-force tail of the GPU-only join (the remedy the paper
-// suggests for the GPU-Only long tail, Sec. 5.3.8: once few queries remain,
-// search them against every point instead of growing eps further).
+// tail.hip -- brute-force tail of the GPU-only join: the remedy the paper
+// suggests for the GPU-Only long tail (Sec. 5.4, characterization of the
+// search-distance expansion): once few queries remain, search them against
+// every point instead of growing eps further.
 //
 // The few remaining queries are searched against all N points with the whole
 // GPU: blocks cover (chunk of points) x (batch of QB queries); a thread keeps

@@ -249,32 +249,65 @@ def test_grid_export_matches_oracle(knn, oracle_mod):
         assert (got["ranges"] == ref["ranges"]).all()
 
 
-def test_sampling_kernels_match_oracle(knn, oracle_mod):
+@pytest.mark.parametrize("scale", [1.0, 2.0 ** -70, 2.0 ** 70])
+def test_sampling_kernels_match_oracle(knn, oracle_mod, scale):
+    """The two sampling kernels of Sec. 4.4 on the same sample as the oracle;
+    scaled inputs put d^2 outside float's normal range (the kernel's
+    single-precision bin estimate must then give way to fp64)."""
     import torch
-    D = datagen.exponential(20000, 3, seed=60)
+    D = datagen.exponential(20000, 3, seed=60) * scale
     sample = datagen.sample_ids(20000, 300, seed=61)
     Dd = torch.from_numpy(D).cuda()
     sd = torch.from_numpy(sample).cuda()
-    _say("[sampling] mean + histogram")
+    _say(f"[sampling] mean + histogram scale={scale}")
     m = knn.sample_mean_dist(Dd, sd)
     m_ref = oracle_mod.sample_mean_dist(D, sample)
-    assert abs(m - m_ref) <= 1e-12 * m_ref
+    # both sum the same 44850 positive terms in different orders: each sum is
+    # within (terms - 1) * 2^-53 (relative) of the exact one
+    assert abs(m - m_ref) <= 2 * 44850 * 2.0 ** -53 * m_ref
     inv_bw = 1000.0 / m_ref
     counts = knn.dist_histogram(Dd, sd[:50], inv_bw, 1000).cpu().numpy().astype(np.uint64)
     ref = oracle_mod.dist_histogram(D, sample[:50], inv_bw, 1000)
     assert (counts == ref).all()
 
 
-def test_eps_min_from_index_matches_rule(knn, oracle_mod):
-    D = datagen.uniform(20000, 2, seed=62)
-    idx = knn.build_index(D)
+@pytest.mark.parametrize("name,gen,seed", [
+    ("expo2d", lambda: datagen.exponential(300_000, 2, seed=62), 1),
+    ("clustered", lambda: datagen.clustered(400_000, seed=63), 77),
+    ("unif4d", lambda: datagen.uniform(100_000, 4, seed=64), 5),
+    ("small_fallback", lambda: datagen.uniform(1100, 2, seed=65), 9),
+])
+def test_eps_min_chain_matches_oracle(knn, oracle_mod, name, gen, seed):
+    """The whole Sec. 4.4 chain of an index against the oracle's own: sample
+    ids (drawn on the oracle side with its own SplitMix64), eps_mean, the
+    distance histogram at the oracle's bin width, and eps_min(K) by the rule
+    (the midpoint of the first bin whose cumulative count reaches K per
+    sample point; eps_mean when none does, as for K = 1024 on 1100 points)."""
+    D = gen()
+    N = D.shape[0]
+    _say(f"[eps chain] {name} N={N}")
+    idx = knn.build_index(D, seed=seed)
     info = idx.info()
-    # eps_min(K) is non-decreasing in K and bounded by eps_mean
-    prev = 0.0
-    for K in (1, 2, 4, 8, 16, 32, 64):
-        e = idx.eps_min(K)
-        assert prev <= e <= info["eps_mean"]
-        prev = e
+    smp = idx.sampling()
+    n_mean = min(max(int(round(0.001 * N)), 64), N, 20000)
+    ref_mean_ids = oracle_mod.sample_ids(N, n_mean, seed)
+    ref_hist_ids = oracle_mod.sample_ids(N, 500, seed ^ 0x5DEECE66D)
+    assert (smp["mean_sample"] == ref_mean_ids).all()
+    assert (smp["hist_sample"] == ref_hist_ids).all()
+    eps_ref = oracle_mod.sample_mean_dist(D, ref_mean_ids)
+    pairs = n_mean * (n_mean - 1) // 2
+    tol = 2 * pairs * 2.0 ** -53  # two sums of `pairs` positive terms, any order
+    assert abs(info["eps_mean"] - eps_ref) <= tol * eps_ref
+    bw_ref = eps_ref / 1000
+    counts_ref = oracle_mod.dist_histogram(D, ref_hist_ids, 1.0 / bw_ref, 1000)
+    assert (smp["counts"] == counts_ref).all()
+    Ks = (1, 8, 32, 64) if N > 2000 else (1, 8, 1024)
+    for K in Ks:
+        e_ref = oracle_mod.eps_min(counts_ref, bw_ref, ref_hist_ids.shape[0], K)
+        assert abs(idx.eps_min(K) - e_ref) <= 2 * tol * e_ref, K
+    if N <= 2000:
+        assert idx.eps_min(1024) == info["eps_mean"] or abs(
+            idx.eps_min(1024) - info["eps_mean"]) <= 4 * 2.0 ** -53 * info["eps_mean"]
     idx.close()
 
 

@@ -103,3 +103,26 @@ def test_wait_timeout_and_unknown_ticket(api):
         srv.wait(t)  # already collected
     srv.close()
     ix.close()
+
+
+@pytest.mark.parametrize("name,gen,K,opts", [
+    # small cells at level 0 (row table), larger ones later (dense key table):
+    # a context once held both
+    ("expo3d_levels", lambda: datagen.exponential(200_000, 3, seed=77), 8, {"w_factor": 0.25}),
+    ("unif2d", lambda: datagen.uniform(100_000, 2, seed=78), 16, {}),
+    ("unif6d", lambda: datagen.uniform(30_000, 6, seed=79), 8, {"w_factor": 0.5}),
+])
+def test_footprint_bounds_what_a_join_holds(api, name, gen, K, opts):
+    """knn_join_footprint (the admission size) is an upper bound of the device
+    memory a join with host outputs actually holds, device cache slack
+    included, also for a join that runs many levels."""
+    print(f"[serving] footprint {name}", flush=True)
+    D = gen()
+    ix = api.build_index(D)
+    before = ix.info()["device_bytes"]  # the index alone (no join scratch yet)
+    fp = ix.join_footprint(K)
+    _, _, st = ix.self_join_host(K, with_stats=True, **opts)
+    held = ix.info()["device_bytes"] - before
+    assert st["levels"] >= 2 or name == "unif2d"
+    assert 0 < held <= fp, (held, fp)
+    ix.close()

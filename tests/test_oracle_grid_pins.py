@@ -182,3 +182,26 @@ def test_eps_min_uniform_density_statistical(oracle_mod):
     rho = N / 100.0 ** 2
     e_closed = math.sqrt(K / (math.pi * rho))
     assert 0.85 * e_closed < e < 1.25 * e_closed
+
+
+def test_splitmix64_published_outputs(oracle_mod):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "splitmix64_seed0.json")) as f:
+        g = json.load(f)
+    got = [int(v) for v in oracle_mod.splitmix64(g["seed"], len(g["outputs_hex"]))]
+    assert got == [int(h, 16) for h in g["outputs_hex"]]
+
+
+def test_sample_ids_draws_distinct_residues(oracle_mod):
+    # without replacement: the first `count` distinct generator residues mod N,
+    # increasing; every id when count >= N
+    N, count, seed = 1000, 300, 12345
+    ids = oracle_mod.sample_ids(N, count, seed)
+    assert ids.shape == (count,) and (np.diff(ids) > 0).all() and ids[0] >= 0 and ids[-1] < N
+    stream = oracle_mod.splitmix64(seed, 5000) % np.uint64(N)
+    _, first = np.unique(stream, return_index=True)
+    expect = np.sort(stream[np.sort(first)][:count].astype(np.int64))
+    assert (ids == expect).all()
+    assert (oracle_mod.sample_ids(7, 50, 3) == np.arange(7)).all()
