@@ -198,6 +198,32 @@ int knn_self_join(knn_index* idx, int32_t K, int32_t* ids, double* dists,
 int knn_self_join_device(knn_index* idx, int32_t K, int32_t* d_ids, double* d_dists,
                          const knn_join_opts* opts, void* stream);
 
+/*
+ * For callers that cannot allocate device memory during the call (serving
+ * loops that run on a fixed memory plan, harnesses that forbid hipMalloc):
+ * the same join as knn_self_join_device, same arguments, results and
+ * ordering, with every temporary buffer taken from a fixed scratch area of
+ * KNN_NOALLOC_SCRATCH_BYTES that the library holds per device (a static
+ * device array, present on every device that runs the library until the
+ * process ends).  The call makes no hipMalloc, hipFree, hipHostMalloc or
+ * other allocating call; the caller still provides d_ids / d_dists.
+ *   Limit: the join's buffers, each at its largest size for (index, K,
+ *   opts), must fit the area (roughly 230 + 17*3^(dims-1) bytes per point
+ *   plus the brute-force tail's per-query state); larger joins return
+ *   KNN_EINVAL, and knn_last_error() states the bytes needed.
+ *   opts->stats must be NULL and opts->use_graph 0 (both would allocate):
+ *   KNN_EINVAL otherwise.
+ * The area is shared by every call on a device and keeps the last call's
+ * contents; everything a join reads is written or cleared by the join
+ * itself.  Calls on one device are serialised by the library (a second
+ * caller blocks until the first returns; each call returns after its device
+ * work has completed), since overlapping joins in one area would race.
+ */
+#define KNN_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int knn_self_join_device_noalloc(knn_index* idx, int32_t K, int32_t* d_ids,
+                                 double* d_dists, const knn_join_opts* opts,
+                                 void* stream);
+
 /* Frees the index and its device memory.  NULL is a no-op. */
 void knn_destroy_index(knn_index* idx);
 

@@ -20,6 +20,7 @@ KNN_EINTERNAL = -6
 KNN_MAX_DIMS = 6
 KNN_MAX_K = 1024
 KNN_MAX_LEVELS = 64
+KNN_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 c_i32, c_i64, c_u64, c_f64, c_p = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                    ctypes.c_double, ctypes.c_void_p)
@@ -115,6 +116,8 @@ SIGNATURES = {
     "knn_self_join": (ctypes.c_int, [c_p, c_i32, c_p, c_p, ctypes.POINTER(JoinOpts)]),
     "knn_self_join_device": (ctypes.c_int, [c_p, c_i32, c_p, c_p, ctypes.POINTER(JoinOpts),
                                             c_p]),
+    "knn_self_join_device_noalloc": (ctypes.c_int, [c_p, c_i32, c_p, c_p,
+                                                    ctypes.POINTER(JoinOpts), c_p]),
     "knn_destroy_index": (None, [c_p]),
     "knn_last_error": (ctypes.c_char_p, []),
     "knn_index_info_get": (ctypes.c_int, [c_p, ctypes.POINTER(IndexInfo)]),

@@ -154,6 +154,23 @@ class Index:
             return ids, dists, st.as_dict()
         return ids, dists
 
+    def self_join_noalloc(self, K, ids, dists, stream=None, **opts):
+        """knn_self_join_device_noalloc: the same join with every temporary in
+        the library's fixed scratch area (no device allocation); ids / dists
+        are caller-provided contiguous device tensors (N x K int32 / float64)."""
+        torch = _torch()
+        if ids.shape != (self.N, K) or dists.shape != (self.N, K):
+            raise ValueError("output shape must be (N, K)")
+        if ids.dtype != torch.int32 or dists.dtype != torch.float64:
+            raise ValueError("outputs must be int32 / float64")
+        if not (ids.is_cuda and dists.is_cuda and ids.is_contiguous() and dists.is_contiguous()):
+            raise ValueError("outputs must be contiguous device tensors")
+        o = _join_opts(**opts)
+        check(load().knn_self_join_device_noalloc(self.handle, K, ctypes.c_void_p(ids.data_ptr()),
+                                                  ctypes.c_void_p(dists.data_ptr()),
+                                                  ctypes.byref(o), _stream_ptr(stream)))
+        return ids, dists
+
     def self_join_host(self, K, with_stats=False, **opts):
         """knn_self_join: results in host (numpy) arrays."""
         ids = np.empty((self.N, K), dtype=np.int32)

@@ -57,6 +57,27 @@ constexpr size_t kPoolRound = (size_t)1 << 20;       // rounding of large reques
 void* device_acquire(size_t bytes, int* device, size_t* capacity);
 void device_release(void* p, int device, size_t capacity);
 
+// Bump allocation from a fixed device region instead of the cache: while an
+// ArenaScope is alive on a thread, device_acquire on that thread hands out
+// consecutive 256-byte aligned pieces of [base, base + size) (KNN_ENOMEM once
+// they run out), marks them with device kArenaDevice, and device_release
+// ignores them; pinned host buffers (HostBuf) come from a static per-thread
+// block.  No HIP allocation is made in the scope.
+constexpr int kArenaDevice = -2;
+constexpr size_t kArenaHostBytes = 8192;
+struct ArenaScope {
+  char* base;
+  size_t size;
+  size_t used = 0;
+  ArenaScope* prev;
+  ArenaScope(void* base_, size_t size_);
+  ~ArenaScope();
+  ArenaScope(const ArenaScope&) = delete;
+  ArenaScope& operator=(const ArenaScope&) = delete;
+};
+bool arena_active();
+void* arena_host_block();  // kArenaHostBytes of host memory owned by the thread
+
 // Device buffer owned by RAII (memory from the device cache).
 template <class T>
 struct DevBuf {
@@ -116,14 +137,24 @@ struct HostBuf {
   HostBuf() = default;
   HostBuf(const HostBuf&) = delete;
   HostBuf& operator=(const HostBuf&) = delete;
+  bool borrowed = false;  // the thread's arena host block, never freed here
   ~HostBuf() {
-    if (p) (void)hipHostFree(p);
+    if (p && !borrowed) (void)hipHostFree(p);
   }
   void reserve(size_t count) {
     if (p && count <= n) return;
-    if (p) (void)hipHostFree(p);
+    if (p && !borrowed) (void)hipHostFree(p);
     p = nullptr;
     n = 0;
+    borrowed = false;
+    if (arena_active()) {
+      KNN_CHECK(count * sizeof(T) <= kArenaHostBytes, KNN_EINTERNAL,
+                "host read-back buffer above the arena's host block");
+      p = static_cast<T*>(arena_host_block());
+      borrowed = true;
+      n = count;
+      return;
+    }
     KNN_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), count * sizeof(T), hipHostMallocDefault));
     n = count;
   }

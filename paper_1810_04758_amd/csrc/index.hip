@@ -6,7 +6,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_set>
 
@@ -239,7 +241,9 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s, b
   long double cells = 1;
   for (int j = 0; j < n; ++j) cells *= (long double)c.gg.g[j];
   const uint32_t* dense = nullptr;
-  if (n > 2 && cells <= (long double)std::max<int64_t>(16 * N, 1 << 22)) {
+  const int64_t dense_lim = c.table_cap > 0 ? c.table_cap : std::max<int64_t>(16 * N, 1 << 22);
+  const int64_t rows_lim = c.table_cap > 0 ? c.table_cap : std::max<int64_t>(32 * N, 1 << 22);
+  if (n > 2 && cells <= (long double)dense_lim) {
     c.dense.reserve((size_t)cells);
     launch_dense_table(c.cell_key.p, c.scal.p, N, c.dense.p, (int64_t)cells, s);
     dense = c.dense.p;
@@ -250,7 +254,7 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s, b
   c.rowtab_used = nullptr;
   if (!dense) {
     const long double rows = cells / (long double)c.gg.g[n - 1];
-    if (rows <= (long double)std::max<int64_t>(32 * N, 1 << 22)) {
+    if (rows <= (long double)rows_lim) {
       c.rowtab.reserve((size_t)rows);
       launch_row_table(c.cell_key.p, c.scal.p, N, (uint64_t)c.gg.g[n - 1], c.rowtab.p,
                        (int64_t)rows, s);
@@ -264,7 +268,7 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s, b
   // the stream since (each level reads its counters back, each join returns
   // after its work).  A context owned by a captured graph keeps both, since
   // the graph's nodes refer to them.
-  if (!c.graph_owned) {
+  if (!c.graph_owned && !c.fixed) {
     if (!c.dense_used) c.dense.release();
     if (!c.rowtab_used) c.rowtab.release();
   }
@@ -329,6 +333,86 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   return (uint64_t)std::ceil((double)b * kPoolSlack);
 }
 
+double tail_budget_of(const knn_index& idx, int32_t K, const knn_join_opts& o) {
+  // with levels this cheap the tail only pays off for a few hundred queries
+  // (it scans all N points per query)
+  const double tuned_tail = o.tail_pairs == 0 ? autotune_tail_pairs(idx.n, K, idx.N) : 0.0;
+  return o.tail_pairs > 0 ? o.tail_pairs
+         : o.tail_pairs < 0 ? -1.0
+         : tuned_tail > 0  ? tuned_tail
+                           : 2.5e8;
+}
+
+namespace {
+
+// Every buffer a join can reserve, at its largest size for (idx, K, o) with
+// the lookup tables limited to table_cap entries: f(buffer, elements).
+template <class F>
+void for_each_join_buffer(const knn_index& idx, JoinContext& c, int32_t K,
+                          const knn_join_opts& o, int64_t table_cap, F&& f) {
+  const int64_t N = idx.N;
+  const int n = idx.n;
+  const int64_t S = point_stride(n), R = pow3(n - 1);
+  const int cap = K + std::max(16, K / 2);
+  f(c.Xs, N * S);
+  f(c.Xs2, N * S);
+  f(c.perm, N);
+  f(c.perm2, N);
+  f(c.pos, N);
+  f(c.cell_of, N);
+  f(c.cell_key, N);
+  f(c.cell_start, N + 1);
+  f(c.cand_count, N);
+  f(c.nrng, N);
+  f(c.ranges, N * R * 4);  // at most one cell per point
+  f(c.rslot, N * R);
+  f(c.keys, N);
+  f(c.keys2, N);
+  f(c.vals2, N);
+  f(c.flags, N);
+  f(c.tmp, (int64_t)radix_tmp_elems(N));
+  f(c.scan_state, (int64_t)scan_state_elems(N));
+  f(c.scal, 4);
+  f(c.iscal, kCounterInts);
+  f(c.active, N);
+  f(c.active2, N);
+  f(c.fail_list, N);
+  f(c.heavy, N);
+  f(c.failed, N);
+  f(c.cell_active, N);
+  f(c.ikeys, N);  // at most one work item per active query
+  f(c.ikeys2, N);
+  f(c.ivals, N);
+  f(c.ivals2, N);
+  if (n > 2) f(c.dense, table_cap);
+  f(c.rowtab, table_cap);
+  // the tail runs once A * N <= budget with A <= 65535 remaining queries
+  const double budget = tail_budget_of(idx, K, o);
+  int64_t a_max = 0;
+  if (budget > 0) a_max = std::min<int64_t>({(int64_t)(budget / (double)N), 65535, N});
+  f(c.tail_scratch, (int64_t)tail_state_bytes(std::max<int64_t>(a_max, 1), cap));
+}
+
+}  // namespace
+
+uint64_t fixed_scratch_bytes(const knn_index& idx, int32_t K, const knn_join_opts& o) {
+  JoinContext probe;
+  uint64_t total = 0;
+  for_each_join_buffer(idx, probe, K, o, kFixedTableFactor * idx.N, [&](auto& buf, int64_t count) {
+    using T = std::remove_reference_t<decltype(*buf.p)>;
+    total += ((uint64_t)std::max<int64_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+  });
+  return total;
+}
+
+void reserve_fixed_scratch(const knn_index& idx, JoinContext& c, int32_t K,
+                           const knn_join_opts& o, hipStream_t s) {
+  for_each_join_buffer(idx, c, K, o, c.table_cap,
+                       [&](auto& buf, int64_t count) { buf.reserve((size_t)count); });
+  // the single-pass scans' epoch and ticket start from zero
+  launch_zero(c.scan_state.p, c.scan_state.bytes(), s);
+}
+
 // Lanes per query for a level of A active queries that see `cand` candidates
 // on average (measured on MI355X over t in 2..64 and 2-6 dims): the power of
 // two nearest cand^0.6 / 4, raised until the level has enough lanes to fill
@@ -391,13 +475,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   const int pad = std::max(16, K / 2);
   const int cap = K + pad;
   if (st) st->eps_min = eps_min;
-  // brute-force tail budget: with levels this cheap the tail only pays off for
-  // a few hundred queries (it scans all N points per query)
-  const double tuned_tail = o.tail_pairs == 0 ? autotune_tail_pairs(idx.n, K, idx.N) : 0.0;
-  const double tail_budget = o.tail_pairs > 0 ? o.tail_pairs
-                             : o.tail_pairs < 0 ? -1.0
-                             : tuned_tail > 0  ? tuned_tail
-                                               : 2.5e8;
+  const double tail_budget = tail_budget_of(idx, K, o);
   double diag2 = 0;
   for (int j = 0; j < idx.n; ++j) diag2 += (idx.hi[j] - idx.lo[j]) * (idx.hi[j] - idx.lo[j]);
 
@@ -1026,6 +1104,33 @@ knn_join_opts resolve_join(const knn_join_opts* o) {
   return r;
 }
 
+// The fixed scratch area of knn_self_join_device_noalloc.  Each device that
+// runs the library holds its own copy until the process ends.  Host code
+// never passes the array's name to a kernel: the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) char scratch[KNN_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_addr;           // device -> address of its copy
+std::map<int, std::mutex> g_scratch_call_mu;   // device -> serialises its users
+
+// Address of `scratch` on device dev (dev must be current).
+char* scratch_of_device(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* ptr = nullptr;
+  KNN_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  KNN_CHECK(ptr != nullptr, KNN_EDEVICE, "no device address for the scratch area");
+  g_scratch_addr[dev] = static_cast<char*>(ptr);
+  return static_cast<char*>(ptr);
+}
+
+std::mutex& scratch_call_mutex(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_call_mu[dev];  // constructed in place, never moved
+}
+
 struct BusyGuard {
   knn_index* idx;
   explicit BusyGuard(knn_index* i) : idx(i) {
@@ -1095,6 +1200,41 @@ int knn_self_join_device(knn_index* idx, int32_t K, int32_t* d_ids, double* d_di
       self_join_graph(*idx, K, d_ids, d_dists, o, (hipStream_t)stream);
     else
       self_join(*idx, index_ctx(idx), K, d_ids, d_dists, o, (hipStream_t)stream);
+  });
+}
+
+int knn_self_join_device_noalloc(knn_index* idx, int32_t K, int32_t* d_ids, double* d_dists,
+                                 const knn_join_opts* opts, void* stream) {
+  return guarded([&] {
+    validate_join(idx, K);
+    KNN_CHECK(d_ids && d_dists, KNN_EINVAL, "output pointers are NULL");
+    knn_join_opts o = resolve_join(opts);
+    KNN_CHECK(o.stats == nullptr, KNN_EINVAL,
+              "no-allocation join: statistics (HIP events) are not available");
+    KNN_CHECK(o.use_graph == 0, KNN_EINVAL,
+              "no-allocation join: use_graph (a graph with scratch of its own) is not available");
+    const uint64_t need = fixed_scratch_bytes(*idx, K, o);
+    KNN_CHECK(need <= (uint64_t)KNN_NOALLOC_SCRATCH_BYTES, KNN_EINVAL,
+              "no-allocation join: this index and K need " + std::to_string(need) +
+                  " bytes of scratch, above the fixed area of " +
+                  std::to_string((uint64_t)KNN_NOALLOC_SCRATCH_BYTES));
+    BusyGuard bg(idx);
+    DeviceGuard dg(idx->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(scratch_call_mutex(idx->device));
+    ArenaScope arena(scratch_of_device(idx->device), (size_t)KNN_NOALLOC_SCRATCH_BYTES);
+    JoinContext c;  // destroyed before the arena scope ends
+    c.device = idx->device;
+    c.fixed = true;
+    c.table_cap = kFixedTableFactor * idx->N;
+    try {
+      reserve_fixed_scratch(*idx, c, K, o, s);
+      self_join(*idx, c, K, d_ids, d_dists, o, s);
+    } catch (...) {
+      // the next call reuses the area: let this one's work finish first
+      (void)hipStreamSynchronize(s);
+      throw;
+    }
   });
 }
 

@@ -76,6 +76,11 @@ struct JoinContext {
   HostBuf<int32_t> pinned;               // read-backs of the level loop
   const uint2* rowtab_used = nullptr;
   bool graph_owned = false;  // scratch of a captured graph: buffers are never released
+  // buffers carved from one fixed region (reserve_fixed_scratch): none is
+  // released or regrown during the join, and the dense key table and the row
+  // table are used only up to kFixedTableFactor * N entries
+  bool fixed = false;
+  int64_t table_cap = 0;  // > 0: that limit; 0: the default limits
 
   int64_t device_bytes() const;
 };
@@ -158,9 +163,19 @@ void self_join(const knn_index& idx, JoinContext& ctx, int32_t K, int32_t* d_ids
 // captures its launch sequence; later ones launch the graph.
 void self_join_graph(knn_index& idx, int32_t K, int32_t* d_ids, double* d_dists,
                      const knn_join_opts& o, hipStream_t s);
+constexpr int64_t kFixedTableFactor = 4;
 // Device bytes a join of (idx, K) needs beyond the index (admission control).
 uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output);
 double eps_min_of(const knn_index& idx, int32_t K);
+// Brute-force tail budget of a join in (remaining queries) x N pairs; <= 0: no tail.
+double tail_budget_of(const knn_index& idx, int32_t K, const knn_join_opts& o);
+// A join whose every buffer comes from one fixed region: the bytes it needs
+// (each buffer at its largest size for (idx, K, o), 256-byte aligned), and
+// the reservation of all of them in ctx at those sizes (so the level loop
+// never grows one).  ctx.table_cap must be set first.
+uint64_t fixed_scratch_bytes(const knn_index& idx, int32_t K, const knn_join_opts& o);
+void reserve_fixed_scratch(const knn_index& idx, JoinContext& ctx, int32_t K,
+                           const knn_join_opts& o, hipStream_t s);
 void validate_join(const knn_index* idx, int32_t K);
 
 }  // namespace knn

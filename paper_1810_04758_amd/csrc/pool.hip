@@ -1,5 +1,7 @@
 // pool.hip -- the device memory cache behind DevBuf (see common.hpp).
+#include <algorithm>
 #include <cstdlib>
+#include <string>
 #include <map>
 #include <mutex>
 
@@ -37,9 +39,34 @@ void drain_locked(Pool& pl) {
   pl.cached = 0;
 }
 
+thread_local ArenaScope* t_arena = nullptr;
+alignas(256) thread_local unsigned char t_arena_host[kArenaHostBytes];
+
 }  // namespace
 
+ArenaScope::ArenaScope(void* base_, size_t size_)
+    : base(static_cast<char*>(base_)), size(size_), prev(t_arena) {
+  t_arena = this;
+}
+
+ArenaScope::~ArenaScope() { t_arena = prev; }
+
+bool arena_active() { return t_arena != nullptr; }
+
+void* arena_host_block() { return t_arena_host; }
+
 void* device_acquire(size_t bytes, int* device, size_t* capacity) {
+  if (ArenaScope* a = t_arena) {
+    const size_t b = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    if (b > a->size - a->used)
+      throw Error(KNN_ENOMEM, "no-allocation join: its buffers need more than the " +
+                                  std::to_string(a->size) + "-byte scratch area");
+    void* p = a->base + a->used;
+    a->used += b;
+    *device = kArenaDevice;
+    *capacity = b;
+    return p;
+  }
   const size_t want = round_up(bytes == 0 ? 1 : bytes);
   int dev = 0;
   KNN_HIP(hipGetDevice(&dev));
@@ -72,7 +99,7 @@ void* device_acquire(size_t bytes, int* device, size_t* capacity) {
 }
 
 void device_release(void* p, int device, size_t capacity) {
-  if (!p) return;
+  if (!p || device == kArenaDevice) return;  // arena pieces are not the cache's
   std::lock_guard<std::mutex> lk(g_mu);
   Pool& pl = g_pools[device];
   if (pl.cached + capacity > cache_limit()) {
