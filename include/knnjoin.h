@@ -146,6 +146,15 @@ typedef struct knn_join_opts {
                              local density, exceeds its covered radius by a
                              margin goes to the next level without searching
                              this one (results are unchanged); -1: never [0] */
+  int32_t zorder;         /* 1: Z-order levels (2-4 dimensions): the points are
+                             sorted once by the bit-interleaved cell key of the
+                             level-0 grid, and every re-index doubles the cell
+                             side (the key shifted right by dims bits), so a
+                             level costs a cell-table pass instead of a sort;
+                             growth, linear_levels and eps_step are then
+                             ignored.  -1: row-major levels re-sorted at every
+                             re-index.  0 = autotuned, else on in 2-3
+                             dimensions [0] */
   knn_join_stats* stats;  /* optional statistics output */
 } knn_join_opts;
 
@@ -286,11 +295,12 @@ typedef struct knn_autotune_result {
                             (0 or 1; -1 in the cache means none) */
   double tail_pairs;     /* chosen brute-force tail budget (pairs) */
   int32_t lanes_shift;   /* chosen shift of the lanes-per-query rule (x 2^shift) */
+  int32_t zorder;        /* chosen level structure: 1 Z-order levels, -1 row-major */
 } knn_autotune_result;
 /* Runs on `stream` (device scratch allocated internally); blocks. */
 int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* out);
 /* Save / load the cache as text ("dims kbucket nbucket w_factor growth
- * lanes linear tail_pairs lanes_shift" per line); path NULL =
+ * lanes linear tail_pairs lanes_shift zorder" per line); path NULL =
  * $KNN_AUTOTUNE_CACHE. */
 int knn_autotune_save(const char* path);
 int knn_autotune_load(const char* path);

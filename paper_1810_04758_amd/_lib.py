@@ -77,6 +77,7 @@ class JoinOpts(ctypes.Structure):
                 ("share_lists", c_i32),
                 ("speculate", c_i32),
                 ("predict_fail", c_i32),
+                ("zorder", c_i32),
                 ("stats", ctypes.POINTER(JoinStats))]
 
 
@@ -90,7 +91,7 @@ class IndexInfo(ctypes.Structure):
 class AutotuneResult(ctypes.Structure):
     _fields_ = [("w_factor", c_f64), ("growth", c_f64), ("ms_best", c_f64),
                 ("ms_default", c_f64), ("trials", c_i32), ("linear_levels", c_i32),
-                ("tail_pairs", c_f64), ("lanes_shift", c_i32)]
+                ("tail_pairs", c_f64), ("lanes_shift", c_i32), ("zorder", c_i32)]
 
 
 class ServerOpts(ctypes.Structure):

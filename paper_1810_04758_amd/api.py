@@ -28,7 +28,7 @@ def _stream_ptr(stream):
 def _join_opts(w_factor=0.0, cell_width=0.0, lanes_per_query=0, schedule=0, batch_queries=0,
                eps_step=0.0, linear_levels=0, growth=0.0, use_graph=0, tail_pairs=0.0,
                heavy_min=0, queue_grain=0, item_order=0, lanes_shift=0, share_lists=0,
-               speculate=0, predict_fail=0,
+               speculate=0, predict_fail=0, zorder=0,
                stats=None):
     o = JoinOpts()
     load().knn_join_opts_default(ctypes.byref(o))
@@ -49,6 +49,7 @@ def _join_opts(w_factor=0.0, cell_width=0.0, lanes_per_query=0, schedule=0, batc
     o.share_lists = share_lists
     o.speculate = speculate
     o.predict_fail = predict_fail
+    o.zorder = zorder
     o.stats = ctypes.pointer(stats) if stats is not None else None
     return o
 

@@ -35,11 +35,11 @@ void load_file_locked(const char* p) {
   if (!p || !*p) return;
   FILE* f = std::fopen(p, "r");
   if (!f) return;
-  int d, kb, nb, lanes, lin, ls;
+  int d, kb, nb, lanes, lin, ls, z;
   double wf, gr, tp;
-  while (std::fscanf(f, "%d %d %d %lf %lf %d %d %lf %d", &d, &kb, &nb, &wf, &gr, &lanes, &lin, &tp,
-                     &ls) == 9)
-    g_cache[Class(d, kb, nb)] = TuneEntry{wf, gr, lanes, lin, tp, ls};
+  while (std::fscanf(f, "%d %d %d %lf %lf %d %d %lf %d %d", &d, &kb, &nb, &wf, &gr, &lanes, &lin,
+                     &tp, &ls, &z) == 10)
+    g_cache[Class(d, kb, nb)] = TuneEntry{wf, gr, lanes, lin, tp, ls, z};
   std::fclose(f);
 }
 
@@ -77,6 +77,8 @@ int autotune_lanes_shift(int dims, int K, int64_t N) {
   return autotune_get(dims, K, N).lanes_shift;
 }
 
+int autotune_zorder(int dims, int K, int64_t N) { return autotune_get(dims, K, N).zorder; }
+
 void autotune_store(int dims, int K, int64_t N, const TuneEntry& e) {
   std::lock_guard<std::mutex> lk(g_mu);
   ensure_loaded_locked();
@@ -102,10 +104,10 @@ int autotune_save(const char* path) {
   FILE* f = std::fopen(p, "w");
   if (!f) return -1;
   for (auto& kv : g_cache)
-    std::fprintf(f, "%d %d %d %.17g %.17g %d %d %.17g %d\n", std::get<0>(kv.first),
+    std::fprintf(f, "%d %d %d %.17g %.17g %d %d %.17g %d %d\n", std::get<0>(kv.first),
                  std::get<1>(kv.first), std::get<2>(kv.first), kv.second.w_factor,
                  kv.second.growth, kv.second.lanes, kv.second.linear, kv.second.tail_pairs,
-                 kv.second.lanes_shift);
+                 kv.second.lanes_shift, kv.second.zorder);
   std::fclose(f);
   return 0;
 }

@@ -16,6 +16,7 @@ struct TuneEntry {
   int linear = 0;   // linear growths: 0 = not measured (default), 1, or -1 (none)
   double tail_pairs = 0;  // brute-force tail budget, 0 = not measured
   int lanes_shift = 0;    // the per-level lanes-per-query rule times 2^shift
+  int zorder = 0;         // Z-order levels: 1 on, -1 off, 0 = not measured
 };
 
 // Cached entry for the class of (dims, K, N), or all zeros.
@@ -31,6 +32,8 @@ int autotune_linear(int dims, int K, int64_t N);
 double autotune_tail_pairs(int dims, int K, int64_t N);
 // Shift of the per-level lanes-per-query rule (0 if none cached).
 int autotune_lanes_shift(int dims, int K, int64_t N);
+// Z-order levels: 1 / -1 as measured, 0 if none cached.
+int autotune_zorder(int dims, int K, int64_t N);
 // Records a measured best setting for the class of (dims, K, N).
 void autotune_store(int dims, int K, int64_t N, const TuneEntry& e);
 // Loads / saves the cache file (path from KNN_AUTOTUNE_CACHE when path is NULL).

@@ -247,7 +247,31 @@ struct GeomDev {
   uint64_t stride[kMaxDims];
   uint64_t rstride[kMaxDims];  // row index stride (stride / g_last) of the first n-1 dims
   int64_t g[kMaxDims];
+  int32_t zbits;               // > 0: Z-order keys with this many bits per dimension
 };
+
+// Z-order key of cell coordinates c (bits bits each): bit b of dimension j
+// goes to position b*DIM + DIM-1-j.
+template <int DIM>
+__device__ inline uint64_t zorder_key(const int64_t (&c)[DIM], int bits) {
+  uint64_t key = 0;
+  for (int b = bits - 1; b >= 0; --b) {
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) key = (key << 1) | (((uint64_t)c[j] >> b) & 1ull);
+  }
+  return key;
+}
+
+template <int DIM>
+__device__ inline void zorder_coords(uint64_t key, int bits, int64_t (&c)[DIM]) {
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) c[j] = 0;
+  for (int b = bits - 1; b >= 0; --b) {
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+      c[j] |= (int64_t)((key >> (b * DIM + DIM - 1 - j)) & 1ull) << b;
+  }
+}
 
 GeomDev to_dev(const GridGeom& gg) {
   GeomDev d{};
@@ -259,6 +283,7 @@ GeomDev to_dev(const GridGeom& gg) {
     d.g[j] = gg.g[j];
   }
   d.inv_w = gg.inv_w;
+  d.zbits = gg.zbits;
   return d;
 }
 
@@ -268,9 +293,16 @@ __global__ void k_cell_keys(const double* __restrict__ X, int64_t N, GeomDev gd,
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * blockDim.x) {
     uint64_t key = 0;
+    if (gd.zbits > 0) {
+      int64_t c[DIM];
 #pragma unroll
-    for (int j = 0; j < DIM; ++j)
-      key += (uint64_t)cell_coord(X[(int64_t)j * N + i], gd.lo[j], gd.inv_w) * gd.stride[j];
+      for (int j = 0; j < DIM; ++j) c[j] = cell_coord(X[(int64_t)j * N + i], gd.lo[j], gd.inv_w);
+      key = zorder_key<DIM>(c, gd.zbits);
+    } else {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j)
+        key += (uint64_t)cell_coord(X[(int64_t)j * N + i], gd.lo[j], gd.inv_w) * gd.stride[j];
+    }
     keys[i] = key;
     vals[i] = (int32_t)i;
   }
@@ -348,9 +380,10 @@ __device__ inline uint32_t tile_wave_offset(uint32_t* state, LbTile lt, uint32_t
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int64_t nb, uint32_t* __restrict__ cell_of,
-             uint64_t* __restrict__ cell_key, uint32_t* __restrict__ cell_start,
-             uint32_t* __restrict__ d_M, uint32_t* __restrict__ state) {
+k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int64_t nb, int shift,
+             uint32_t* __restrict__ cell_of, uint64_t* __restrict__ cell_key,
+             uint32_t* __restrict__ cell_start, uint32_t* __restrict__ d_M,
+             uint32_t* __restrict__ state) {
   const LbTile lt = lb_take_tile(state, nb);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -360,9 +393,9 @@ k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int64_t nb, uint32_t*
 #pragma unroll
   for (int r = 0; r < kCtRounds; ++r) {
     const int64_t i = wbase + r * 64 + lane;
-    key[r] = i < N ? keys[i] : 0;
+    key[r] = i < N ? keys[i] >> shift : 0;
     const uint64_t up = __shfl_up(key[r], 1, 64);
-    const uint64_t prev = lane > 0 ? up : (i > 0 && i < N ? keys[i - 1] : 0);
+    const uint64_t prev = lane > 0 ? up : (i > 0 && i < N ? keys[i - 1] >> shift : 0);
     m[r] = __ballot(i < N && (i == 0 || key[r] != prev));
     cnt += (uint32_t)__popcll(m[r]);
   }
@@ -402,7 +435,7 @@ k_active_list(const uint8_t* __restrict__ failed, uint8_t tag, const int32_t* __
 #pragma unroll
   for (int r = 0; r < kCtRounds; ++r) {
     const int64_t p = wbase + r * 64 + lane;
-    m[r] = __ballot(p < N && failed[perm[p]] == tag);
+    m[r] = __ballot(p < N && failed[perm ? perm[p] : (int32_t)p] == tag);
     cnt += (uint32_t)__popcll(m[r]);
   }
   uint32_t total;
@@ -716,6 +749,136 @@ __global__ void k_mark_failed(const int32_t* __restrict__ fail_list, const int32
     failed[fail_list[i]] = tag;
 }
 
+__global__ void k_pos_to_id(int32_t* __restrict__ list, int64_t n,
+                            const int32_t* __restrict__ perm) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    list[i] = perm[list[i]];
+}
+
+// Position of the cell with key k in cell_key[0..M) (sorted, distinct keys),
+// searched outward from position c0 (key k0) by galloping, then bisection;
+// 0xFFFFFFFF when no cell has that key.
+__device__ inline uint32_t find_cell_near(const uint64_t* __restrict__ ck, uint32_t M, uint32_t c0,
+                                          uint64_t k0, uint64_t k) {
+  if (k == k0) return c0;
+  uint64_t lo, hi;  // the first position with key >= k lies in [lo, hi]
+  if (k > k0) {
+    uint64_t prev = c0, step = 1;
+    for (;;) {
+      const uint64_t probe = (uint64_t)c0 + step;
+      if (probe >= M) {
+        hi = M;
+        break;
+      }
+      if (ck[probe] >= k) {
+        hi = probe;
+        break;
+      }
+      prev = probe;
+      step <<= 1;
+    }
+    lo = prev + 1;
+  } else {
+    uint64_t prev = c0, step = 1;  // ck[prev] >= k
+    for (;;) {
+      if (step > c0) {
+        lo = 0;
+        break;
+      }
+      const uint64_t probe = (uint64_t)c0 - step;
+      if (ck[probe] < k) {
+        lo = probe + 1;
+        break;
+      }
+      prev = probe;
+      step <<= 1;
+    }
+    hi = prev;
+  }
+  while (lo < hi) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    if (ck[mid] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < M && ck[lo] == k) ? (uint32_t)lo : 0xFFFFFFFFu;
+}
+
+// Z-order level ranges: a group of S lanes per (flagged) cell, lane l taking
+// the block cells r = l, l + S, ... (r in [0, 3^DIM), offsets in base 3, the
+// last dimension fastest); the non-empty ones are written compacted in r
+// order as described in kernels.hpp.
+template <int DIM>
+__global__ void k_neighbor_ranges_z(const uint32_t* __restrict__ cell_start,
+                                    const uint64_t* __restrict__ cell_key, const uint32_t* d_M,
+                                    const uint8_t* __restrict__ cell_active, uint8_t active_tag,
+                                    GeomDev gd, uint32_t* __restrict__ ranges,
+                                    uint8_t* __restrict__ rslot, uint32_t* __restrict__ nrng,
+                                    uint32_t* __restrict__ cand_count) {
+  constexpr int R = DIM == 2 ? 9 : DIM == 3 ? 27 : 81;
+  constexpr int S = R <= 16 ? 16 : R <= 32 ? 32 : 64;
+  const uint32_t M = *d_M;
+  const int lane = threadIdx.x & 63;
+  const int l = lane % S;
+  const int sub = lane / S;
+  const uint64_t lt = l == 0 ? 0ull : (~0ull >> (64 - l));
+  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / S);
+  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x / S) + threadIdx.x / S; c < (int64_t)M;
+       c += groups) {
+    if (cell_active && cell_active[c] != active_tag) continue;
+    const uint64_t k0 = cell_key[c];
+    int64_t cc[DIM];
+    zorder_coords<DIM>(k0, gd.zbits, cc);
+    uint32_t count = 0, cand = 0;
+    for (int rb = 0; rb < R; rb += S) {
+      const int r = rb + l;
+      uint32_t start = 0, end = 0;
+      int olast = 0;
+      if (r < R) {
+        int64_t nb[DIM];
+        bool inside = true;
+        int rr = r;
+#pragma unroll
+        for (int j = DIM - 1; j >= 0; --j) {
+          const int o = rr % 3 - 1;
+          rr /= 3;
+          if (j == DIM - 1) olast = o;
+          nb[j] = cc[j] + o;
+          if (nb[j] < 0 || nb[j] >= gd.g[j]) inside = false;
+        }
+        if (inside) {
+          const uint32_t f =
+              find_cell_near(cell_key, M, (uint32_t)c, k0, zorder_key<DIM>(nb, gd.zbits));
+          if (f != 0xFFFFFFFFu) {
+            start = cell_start[f];
+            end = cell_start[f + 1];
+          }
+        }
+      }
+      const bool ne = end > start;
+      const uint64_t m = (S == 64 ? __ballot(ne) : (__ballot(ne) >> (sub * S))) &
+                         (S == 64 ? ~0ull : ((1ull << S) - 1ull));
+      if (ne) {
+        const uint32_t pos = count + (uint32_t)__popcll(m & lt);
+        const uint32_t m0 = olast < 0 ? end : start;   // the cell is the lower part,
+        const uint32_t m1 = olast > 0 ? start : end;   // the middle or the upper part
+        reinterpret_cast<uint4*>(ranges)[(int64_t)c * R + pos] = make_uint4(start, m0, m1, end);
+        rslot[(int64_t)c * R + pos] = (uint8_t)(r / 3);
+        cand += end - start;
+      }
+      count += (uint32_t)__popcll(m);
+    }
+#pragma unroll
+    for (int o = 1; o < S; o <<= 1) cand += __shfl_xor(cand, o, 64);
+    if (l == 0) {
+      nrng[c] = count;
+      cand_count[c] = cand;
+    }
+  }
+}
+
 // Zero fill: `words` 32-bit words, then `tail` (< 4) trailing bytes.  A kernel
 // rather than a memset node, so the join's launch sequence can be captured in
 // a graph and replayed.
@@ -852,7 +1015,7 @@ void launch_gather_prev(const double* Xs_prev, const int32_t* perm_prev, const i
 
 void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags, uint32_t* cell_of,
                       uint64_t* cell_key, uint32_t* cell_start, uint32_t* d_M, uint32_t* state,
-                      int64_t state_elems, hipStream_t s) {
+                      int64_t state_elems, hipStream_t s, int shift) {
   (void)flags;
   if (N <= 0) {
     launch_zero(d_M, sizeof(uint32_t), s);
@@ -860,8 +1023,33 @@ void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags, u
   }
   const int64_t nb = ceil_div(N, kCtTile);
   KNN_CHECK(4 + 2 * nb <= state_elems, KNN_EINTERNAL, "scan state too small");
-  k_cell_table<<<(unsigned)nb, kBlock, 0, s>>>(sorted_keys, N, nb, cell_of, cell_key, cell_start,
-                                               d_M, state);
+  KNN_CHECK(shift >= 0 && shift < 64, KNN_EINTERNAL, "cell table: key shift out of range");
+  k_cell_table<<<(unsigned)nb, kBlock, 0, s>>>(sorted_keys, N, nb, shift, cell_of, cell_key,
+                                               cell_start, d_M, state);
+  KNN_LAUNCHED();
+}
+
+void launch_pos_to_id(int32_t* list, int64_t n, const int32_t* perm, hipStream_t s) {
+  if (n <= 0) return;
+  k_pos_to_id<<<grid_for(n), kBlock, 0, s>>>(list, n, perm);
+  KNN_LAUNCHED();
+}
+
+void launch_neighbor_ranges_z(const uint32_t* cell_start, const uint64_t* cell_key,
+                              const uint32_t* d_M, int64_t N, const uint8_t* cell_active,
+                              uint8_t active_tag, const GridGeom& gg, uint32_t* ranges,
+                              uint8_t* rslot, uint32_t* nrng, uint32_t* cand_count,
+                              hipStream_t s) {
+  KNN_CHECK(gg.zbits >= 0 && gg.dims <= kZMaxDims, KNN_EINTERNAL, "not a Z-order level");
+  GeomDev gd = to_dev(gg);
+  const int S = gg.dims == 2 ? 16 : gg.dims == 3 ? 32 : 64;
+  const int nb = grid_for(N * S, 65536);
+  switch (gg.dims) {
+    case 2: k_neighbor_ranges_z<2><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
+    case 3: k_neighbor_ranges_z<3><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
+    case 4: k_neighbor_ranges_z<4><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
+    default: throw Error(KNN_EINVAL, "Z-order levels take 2-4 dimensions");
+  }
   KNN_LAUNCHED();
 }
 
@@ -960,17 +1148,19 @@ void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count, i
 }
 
 __global__ void k_mark_cells_of(const int32_t* __restrict__ active, int64_t n_active,
-                                const uint32_t* __restrict__ cell_of, uint8_t* __restrict__ flags,
-                                uint8_t tag) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_active;
+                                const uint32_t* n_dev, const uint32_t* __restrict__ cell_of,
+                                uint8_t* __restrict__ flags, uint8_t tag) {
+  const int64_t n = n_dev ? min(n_active, (int64_t)*n_dev) : n_active;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    flags[cell_of[active[i]]] = tag;
+    flags[cell_of[active ? active[i] : (int32_t)i]] = tag;
 }
 
 void launch_mark_cells_of(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
-                          uint8_t* flags, uint8_t tag, hipStream_t s) {
+                          uint8_t* flags, uint8_t tag, hipStream_t s, const uint32_t* n_dev) {
   if (n_active <= 0) return;
-  k_mark_cells_of<<<grid_for(n_active), kBlock, 0, s>>>(active, n_active, cell_of, flags, tag);
+  k_mark_cells_of<<<grid_for(n_active), kBlock, 0, s>>>(active, n_active, n_dev, cell_of, flags,
+                                                        tag);
   KNN_LAUNCHED();
 }
 

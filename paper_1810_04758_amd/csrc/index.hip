@@ -128,6 +128,48 @@ GridGeom make_geom(const knn_index& idx, double& w) {
   throw Error(KNN_EINTERNAL, "could not choose a grid geometry");
 }
 
+// Geometry of the level-0 Z-order grid of cell side w: row-major sizes, and
+// the bits per dimension of the interleaved keys (dims * bits <= 62).  The
+// side is enlarged until that fits (a performance policy only).
+GridGeom make_geom_z(const knn_index& idx, double& w) {
+  for (int attempt = 0; attempt < 200; ++attempt) {
+    GridGeom gg = make_geom(idx, w);  // may enlarge w for its own limits
+    int bits = 0;
+    while (bits < 62 && ((gg.g_max - 1) >> bits) != 0) ++bits;
+    if (idx.n * bits <= 62) {
+      gg.zbits = bits;
+      gg.zshift = 0;
+      gg.key_bits = idx.n * bits;
+      return gg;
+    }
+    w *= 2;
+  }
+  throw Error(KNN_EINTERNAL, "could not choose a Z-order grid geometry");
+}
+
+// Level L of a Z-order ladder: cell side w0 * 2^L, so inv_w is the level-0
+// one times 2^-L exactly and every cell coordinate is the level-0 one shifted
+// right by L (floor(u / 2^L) = floor(floor(u) / 2^L) for u >= 0, and scaling
+// by a power of two rounds identically).
+GridGeom z_level_geom(const GridGeom& g0, int L) {
+  GridGeom gg = g0;
+  gg.inv_w = std::ldexp(g0.inv_w, -L);
+  gg.g_max = 1;
+  for (int j = 0; j < g0.dims; ++j) {
+    gg.g[j] = ((g0.g[j] - 1) >> L) + 1;
+    gg.g_max = std::max(gg.g_max, gg.g[j]);
+  }
+  uint64_t st = 1;
+  for (int j = g0.dims - 1; j >= 0; --j) {
+    gg.stride[j] = st;
+    st *= (uint64_t)gg.g[j];
+  }
+  gg.zbits = std::max(g0.zbits - L, 0);
+  gg.zshift = g0.dims * std::min(L, g0.zbits);
+  gg.key_bits = g0.dims * gg.zbits;
+  return gg;
+}
+
 // Flag value of a level (> 0) in the failure and active-cell arrays: 1..255.
 uint8_t level_tag(int level) { return (uint8_t)(1 + (level - 1) % 255); }
 
@@ -190,6 +232,7 @@ void validate_join(const knn_index* idx, int32_t K) {
 void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s, bool from_prev) {
   const int64_t N = idx.N;
   const int n = idx.n;
+  c.zmode = false;
   c.gg = make_geom(idx, w);
   c.Xs.reserve((size_t)N * point_stride(n));
   c.perm.reserve(N);
@@ -274,11 +317,59 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s, b
   }
 }
 
+void build_grid_z(const knn_index& idx, JoinContext& c, double w0, int level, hipStream_t s) {
+  const int64_t N = idx.N;
+  const int n = idx.n;
+  KNN_CHECK(n <= kZMaxDims, KNN_EINTERNAL, "Z-order levels take 2-4 dimensions");
+  c.zmode = true;
+  if (level == 0) {
+    c.gz0 = make_geom_z(idx, w0);
+    c.Xs.reserve((size_t)N * point_stride(n));
+    c.perm.reserve(N);
+    c.keys.reserve(N);
+    c.keys2.reserve(N);
+    c.vals2.reserve(N);
+    c.tmp.reserve(radix_tmp_elems(N));
+    if (c.scan_state.reserve(scan_state_elems(N)))
+      launch_zero(c.scan_state.p, c.scan_state.bytes(), s);
+    launch_cell_keys(idx.X.p, N, c.gz0, c.keys.p, c.perm.p, s);
+    if (radix_sort_pairs(c.keys.p, c.perm.p, c.keys2.p, c.vals2.p, N, c.gz0.key_bits, c.tmp.p,
+                         c.scan_state.p, (int64_t)c.scan_state.n, s)) {
+      std::swap(c.keys, c.keys2);  // sorted output is in the scratch pair
+      std::swap(c.perm, c.vals2);
+    }
+    launch_gather_points(idx.XA.p, c.perm.p, N, n, c.Xs.p, s);
+  }
+  c.gg = z_level_geom(c.gz0, level);
+  c.cell_of.reserve(N);
+  c.cell_key.reserve(N);
+  c.cell_start.reserve(N + 1);
+  c.cand_count.reserve(N);
+  c.flags.reserve(N);
+  c.scal.reserve(4);
+  build_cell_table(c.keys.p, N, c.flags.p, c.cell_of.p, c.cell_key.p, c.cell_start.p, c.scal.p,
+                   c.scan_state.p, (int64_t)c.scan_state.n, s, c.gg.zshift);
+  c.M = -1;
+  c.dense_used = nullptr;
+  c.rowtab_used = nullptr;
+  if (!c.graph_owned && !c.fixed) {  // neither lookup table is used
+    c.dense.release();
+    c.rowtab.release();
+  }
+}
+
+bool use_zorder(const knn_index& idx, int32_t K, const knn_join_opts& o) {
+  if (idx.n > kZMaxDims || o.zorder < 0) return false;
+  if (o.zorder > 0) return true;
+  const int tuned = autotune_zorder(idx.n, K, idx.N);
+  return tuned != 0 ? tuned > 0 : idx.n <= 3;
+}
+
 int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_t Mcap_known,
                      const uint8_t* cell_active, uint8_t active_tag) {
   const int64_t N = idx.N;
   const int n = idx.n;
-  const int64_t R = pow3(n - 1);
+  const int64_t R = c.zmode ? pow3(n) : pow3(n - 1);
   int64_t Mcap = N;
   if (R >= 81) {
     // 5-6 dims: 81-243 segments per cell make the worst case large; size the
@@ -295,14 +386,19 @@ int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_
   c.ranges.reserve((size_t)Mcap * R * 4);
   c.rslot.reserve((size_t)Mcap * R);
   c.nrng.reserve(N);
-  launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, c.dense_used,
-                         c.rowtab_used, cell_active, active_tag, c.gg, c.ranges.p, c.rslot.p,
-                         c.nrng.p, c.cand_count.p, s);
+  if (c.zmode)
+    launch_neighbor_ranges_z(c.cell_start.p, c.cell_key.p, c.scal.p, N, cell_active, active_tag,
+                             c.gg, c.ranges.p, c.rslot.p, c.nrng.p, c.cand_count.p, s);
+  else
+    launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, c.dense_used,
+                           c.rowtab_used, cell_active, active_tag, c.gg, c.ranges.p, c.rslot.p,
+                           c.nrng.p, c.cand_count.p, s);
   return Mcap;
 }
 
 int64_t build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s,
                     int64_t Mcap_known) {
+  c.zmode = false;
   build_grid(idx, c, w, s);
   return build_ranges(idx, c, s, Mcap_known, nullptr, 0);
 }
@@ -313,7 +409,8 @@ uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   // out for it: at most kPoolSlack times each request rounded up, i.e.
   // kPoolSlack (b + kPoolRound) for each of the context's buffers.
   const uint64_t N = (uint64_t)idx.N, n = (uint64_t)idx.n;
-  const uint64_t R = (uint64_t)pow3(idx.n - 1);
+  // Z-order levels list the 3^n cells of a block, row-major ones 3^(n-1) segments
+  const uint64_t R = (uint64_t)pow3(idx.n <= kZMaxDims ? idx.n : idx.n - 1);
   const uint64_t cap = (uint64_t)K + std::max<uint64_t>(16, (uint64_t)K / 2);
   uint64_t b = 0;
   b += 16 * (uint64_t)point_stride(idx.n) * N;  // Xs and the previous level's
@@ -352,7 +449,7 @@ void for_each_join_buffer(const knn_index& idx, JoinContext& c, int32_t K,
                           const knn_join_opts& o, int64_t table_cap, F&& f) {
   const int64_t N = idx.N;
   const int n = idx.n;
-  const int64_t S = point_stride(n), R = pow3(n - 1);
+  const int64_t S = point_stride(n), R = use_zorder(idx, K, o) ? pow3(n) : pow3(n - 1);
   const int cap = K + std::max(16, K / 2);
   f(c.Xs, N * S);
   f(c.Xs2, N * S);
@@ -417,12 +514,12 @@ void reserve_fixed_scratch(const knn_index& idx, JoinContext& c, int32_t K,
 // on average (measured on MI355X over t in 2..64 and 2-6 dims): the power of
 // two nearest cand^0.6 / 4, raised until the level has enough lanes to fill
 // the GPU (A * t >= 2^18) and the per-wave LDS buffers stay within 16 KiB.
-static int lanes_for(int dims, double cand, int64_t A, int cap) {
+static int lanes_for(int dims, double cand, int64_t A, int cap, bool zl) {
   const double want = std::pow(std::max(cand, 1.0), 0.6) / 4.0;
   int T = 2;
   while (T < 64 && (double)T * 1.41421356 < want) T *= 2;
   while (T < 64 && (double)A * T < (double)(1 << 18)) T *= 2;
-  while (T < 64 && search_lds_per_wave(dims, T, cap) > 16384) T *= 2;
+  while (T < 64 && search_lds_per_wave(dims, T, cap, zl) > 16384) T *= 2;
   return T;
 }
 
@@ -474,6 +571,9 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
                                                        : autotune_lanes_shift(idx.n, K, idx.N)));
   const int pad = std::max(16, K / 2);
   const int cap = K + pad;
+  // Z-order levels: one sort, cell side doubling per level (growth,
+  // linear_levels and eps_step do not apply)
+  const bool zl = use_zorder(idx, K, o);
   if (st) st->eps_min = eps_min;
   const double tail_budget = tail_budget_of(idx, K, o);
   double diag2 = 0;
@@ -509,6 +609,8 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       ta.X = idx.X.p;
       ta.N = N;
       ta.n = idx.n;
+      // Z-order levels list failures by sorted position: the tail takes ids
+      if (zl) launch_pos_to_id(c.fail_list.p, A, c.perm.p, s);
       ta.q_ids = c.fail_list.p;
       ta.A = (int32_t)A;
       const double top_ref = std::max(diag2, 1e-290);
@@ -538,33 +640,36 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     }
     ev.rec(0, s);
     // level 0 sorts the points from their original order, later levels from
-    // the previous level's order
-    build_grid(idx, c, w, s, level > 0);
+    // the previous level's order (row-major) or not at all (Z-order)
+    if (zl) {
+      // the top of the ladder is one cell, where every query succeeds
+      KNN_CHECK(level == 0 || level <= c.gz0.zbits, KNN_EINTERNAL,
+                "Z-order levels ran past their single-cell top");
+      build_grid_z(idx, c, w0, level, s);
+    } else
+      build_grid(idx, c, w, s, level > 0);
     // active list of this level (cell order): level 0 = every point
     const int32_t* active = nullptr;
     const uint8_t* cell_active = nullptr;
     if (level > 0) {
-      launch_active_list(c.failed.p, level_tag(level), c.perm.p, N, c.active.p, c.scal.p + 1,
-                         c.scan_state.p, (int64_t)c.scan_state.n, s);
+      // Z-order levels keep the sorted order and list failures by sorted
+      // position, so their flags are read without a gather through perm
+      launch_active_list(c.failed.p, level_tag(level), zl ? nullptr : c.perm.p, N, c.active.p,
+                         c.scal.p + 1, c.scan_state.p, (int64_t)c.scan_state.n, s);
       active = c.active.p;
-      // neighbour ranges only for the cells that hold an active query
-      launch_mark_cells_of(active, A, c.cell_of.p, c.cell_active.p, level_tag(level), s);
-      cell_active = c.cell_active.p;
     }
-    lp.Mcap = build_ranges(idx, c, s, rp ? rp->Mcap : 0, cell_active, level_tag(level));
-    // the level's counters start here: the deferral filter appends to the
+    // the level's counters start here: the deferral filters append to the
     // failure list
     const int64_t A_in = A;
     launch_zero(c.iscal.p, kCounterInts * sizeof(int32_t), s);
     const bool filt = o.predict_fail >= 0;
-    if (filt) {
-      c.active2.reserve(N);
+    auto defer_args = [&](const int32_t* in, int32_t* out, uint32_t* out_count) {
       DeferArgs da{};
       da.Xs = c.Xs.p;
       da.perm = c.perm.p;
       da.cell_of = c.cell_of.p;
       da.cand = c.cand_count.p;
-      da.active = active;
+      da.active = in;
       da.n_active = A;
       for (int j = 0; j < kMaxDims; ++j) {
         da.lo[j] = c.gg.lo[j];
@@ -574,15 +679,53 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       da.w = 1.0 / c.gg.inv_w;
       da.margin = (8.0 * (double)c.gg.g_max + 4.0 * idx.n + 32.0) * std::ldexp(1.0, -53);
       da.defer_coef = search_density_coef(idx.n, K, da.w) / 1.3;
-      da.out_active = c.active2.p;
-      da.out_count = c.scal.p + 2;
+      da.out_active = out;
+      da.out_count = out_count;
       da.fail_list = c.fail_list.p;
       da.fail_count = c.iscal.p + kFailSlot;
+      da.fail_pos = zl ? 1 : 0;
       da.cand_sum = reinterpret_cast<unsigned long long*>(c.iscal.p + kCandSumSlot);
       da.state = c.scan_state.p;
       da.state_elems = (int64_t)c.scan_state.n;
-      launch_defer_filter(da, idx.n, s);
+      return da;
+    };
+    const uint32_t* n_pre = nullptr;  // device count of the list the prefilter kept
+    if (zl && filt) {
+      // Z-order levels: a first deferral from the parent-group density, before
+      // any neighbour range exists, so that ranges are built only for the
+      // cells of the queries it keeps (most of a fine level's queries are
+      // deferred); a deliberately loose margin (2 on the squared distance,
+      // against 1.3 for the block estimate that follows)
+      c.active2.reserve(N);
+      DeferArgs pa = defer_args(active, c.active2.p, c.scal.p + 3);
+      pa.cand = nullptr;
+      pa.cell_key = c.cell_key.p;
+      pa.cell_start = c.cell_start.p;
+      pa.d_M = c.scal.p;
+      pa.cand_sum = nullptr;
+      pa.defer_coef = search_density_coef(idx.n, K, pa.w) * (4.0 / 9.0) / 2.0;
+      launch_defer_filter(pa, idx.n, s);
       active = c.active2.p;
+      n_pre = c.scal.p + 3;
+    }
+    if (level > 0 || n_pre) {
+      // neighbour ranges only for the cells that hold an active query; the
+      // flags are stale garbage before level 1 clears them, so level 0 clears
+      // its own first
+      if (level == 0) launch_zero(c.cell_active.p, (size_t)N, s);
+      const uint8_t tag = level == 0 ? (uint8_t)1 : level_tag(level);
+      launch_mark_cells_of(active, A, c.cell_of.p, c.cell_active.p, tag, s, n_pre);
+      cell_active = c.cell_active.p;
+    }
+    lp.Mcap = build_ranges(idx, c, s, rp ? rp->Mcap : 0, cell_active,
+                           level == 0 ? (uint8_t)1 : level_tag(level));
+    if (filt) {
+      // the deferral filter on the block density (candidate counts)
+      int32_t* out = n_pre ? c.active.p : (c.active2.reserve(N), c.active2.p);
+      DeferArgs da = defer_args(active, out, c.scal.p + 2);
+      da.n_active_dev = n_pre;
+      launch_defer_filter(da, idx.n, s);
+      active = out;
     }
     // lanes per query from the level's mean candidate count (the paper's t,
     // Sec. 4.7, chosen per level: the tail levels see far more candidates)
@@ -610,16 +753,16 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       cand_max = tot[1];
       c.M = M;
       if (T == 0) {
-        T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(idx.n, cand, A, cap);
+        T = (level == 0 && T_tuned > 0) ? T_tuned : lanes_for(idx.n, cand, A, cap, zl);
         for (int sft = lanes_shift; sft > 0 && T < 64; --sft) T *= 2;
         for (int sft = lanes_shift; sft < 0 && T > 1; ++sft) T /= 2;
       }
     }
     // the per-wave buffers of small T grow with 3^(n-1) segment lists: raise
     // T until one wavefront's LDS fits
-    while (T < 64 && search_lds_per_wave(idx.n, T, cap) > 65536) T *= 2;
+    while (T < 64 && search_lds_per_wave(idx.n, T, cap, zl) > 65536) T *= 2;
     const int G = 64 / T;
-    const int waves = search_waves_per_block(idx.n, T, cap);
+    const int waves = search_waves_per_block(idx.n, T, cap, zl);
     // Heavy queries: a query on one wavefront costs about C/T lane steps, the
     // level about A*cand/(64*W) (W resident wavefronts); a query above half of
     // that (and above 4096 candidates) would outlast the level, so it gets a
@@ -632,7 +775,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       if (o.heavy_min > 0) {
         hm = (double)o.heavy_min;
       } else {
-        const double W = (double)ncu * search_blocks_per_cu(idx.n, T, cap) * waves;
+        const double W = (double)ncu * search_blocks_per_cu(idx.n, T, cap, zl) * waves;
         hm = std::max(4096.0, (double)T * (double)A * cand / (128.0 * W));
       }
       if ((double)cand_max >= hm) heavy_min = (uint32_t)std::min(hm, 4294967295.0);
@@ -675,6 +818,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       a.qbeg[x] = (x * n_items + kXcds - 1) / kXcds;
     a.persistent = o.schedule == 0 ? 1 : 0;
     a.share_lists = o.share_lists > 0 ? 1 : (o.share_lists < 0 ? 0 : (idx.n >= 5 ? 1 : 0));
+    a.zl = zl ? 1 : 0;
     for (int j = 0; j < kMaxDims; ++j) {
       a.lo[j] = c.gg.lo[j];
       a.g[j] = c.gg.g[j];
@@ -684,12 +828,13 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.margin = (8.0 * (double)c.gg.g_max + 4.0 * idx.n + 32.0) * std::ldexp(1.0, -53);
     a.K = K;
     a.cap = cap;
-    a.spec_slots = o.speculate < 0 ? 0 : search_spec_slots(idx.n, T, cap);
+    a.spec_slots = o.speculate < 0 ? 0 : search_spec_slots(idx.n, T, cap, zl);
     a.spec_coef = std::pow(1.7, 2.0 / idx.n) * search_density_coef(idx.n, K, a.w);
     a.out_ids = d_ids;
     a.out_d = d_dists;
     a.fail_list = c.fail_list.p;
     a.fail_count = c.iscal.p + kFailSlot;
+    a.fail_pos = zl ? 1 : 0;
     a.refine_count = c.iscal.p + kRefineSlot;
     a.walk_error = c.iscal.p + kWalkErrSlot;
     a.spec_count = c.iscal.p + kSpecSlot;
@@ -717,7 +862,8 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       } else {
         // persistent grid: exactly what can be resident at once
         int64_t want = ceil_div(n_items, waves);
-        blocks = (int)std::min<int64_t>(want, (int64_t)ncu * search_blocks_per_cu(idx.n, T, cap));
+        blocks = (int)std::min<int64_t>(want,
+                                        (int64_t)ncu * search_blocks_per_cu(idx.n, T, cap, zl));
         // about four pops per wavefront and queue: few atomics, fine enough
         // granularity for the dense-first balance at the end of each queue
         const int64_t total_waves = (int64_t)blocks * waves;
@@ -851,7 +997,7 @@ bool GraphPlan::matches(int32_t K_, const knn_join_opts& o, int32_t* ids_, doubl
          opts.heavy_min == o.heavy_min && opts.queue_grain == o.queue_grain &&
          opts.item_order == o.item_order && opts.share_lists == o.share_lists &&
          opts.lanes_shift == o.lanes_shift && opts.speculate == o.speculate &&
-         opts.predict_fail == o.predict_fail;
+         opts.predict_fail == o.predict_fail && opts.zorder == o.zorder;
 }
 
 GraphPlan::~GraphPlan() {
@@ -1328,7 +1474,8 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
     const size_t NK = (size_t)idx->N * K;
     c.out_ids.reserve(NK);
     c.out_d.reserve(NK);
-    int ls_cur = 0;  // lanes shift of the trials (stage 5)
+    int ls_cur = 0;  // lanes shift of the trials (last stage)
+    int z_cur = -1;  // level structure of the trials: -1 row-major, 1 Z-order
     auto time_join = [&](double wf, double gr, int lin, double tp) {
       double best = 1e300;
       for (int rep = 0; rep < 2; ++rep) {
@@ -1338,6 +1485,7 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
         o.linear_levels = lin;
         o.tail_pairs = tp;
         o.lanes_shift = ls_cur;
+        o.zorder = z_cur;
         KNN_HIP(hipStreamSynchronize(s));
         auto t0 = std::chrono::steady_clock::now();
         self_join(*idx, c, K, c.out_ids.p, c.out_d.p, o, s);
@@ -1347,10 +1495,12 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
       }
       return best;
     };
-    // Staged search: the level-0 cell side first (default growth, the
-    // paper's linear first step), then growth x linear step for the best
-    // side, then the side again around the best at that growth, then the
-    // brute-force tail budget.
+    // Staged search.  Row-major levels: the level-0 cell side first (default
+    // growth, the paper's linear first step), then growth x linear step for
+    // the best side, then the side again around the best at that growth,
+    // then the brute-force tail budget.  Z-order levels (2-4 dimensions,
+    // growth 2 by construction): the level-0 side, then the tail budget.
+    // Last, the lanes-per-query rule for the overall best.
     const double n = (double)idx->n;
     const double g16 = std::pow(16.0, 1.0 / n);
     const double tp0 = 2.5e8;
@@ -1361,6 +1511,7 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
     out->growth = g16;
     out->linear_levels = 1;
     out->tail_pairs = tp0;
+    out->zorder = -1;
     out->trials = 1;
     auto consider = [&](double wf, double gr, int lin, double tp) {
       const double ms = time_join(wf, gr, lin, tp);
@@ -1371,6 +1522,7 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
         out->growth = gr;
         out->linear_levels = lin;
         out->tail_pairs = tp;
+        out->zorder = z_cur;
       }
     };
     for (double wf : {0.25, 0.5, 0.7, 1.4, 2.0}) consider(wf, g16, 1, tp0);
@@ -1394,19 +1546,52 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
     for (double f : {0.8, 1.25}) consider(wf1 * f, gr2, lin2, tp0);
     const double wf3 = out->w_factor;
     for (double tp : {6e7, 1e9}) consider(wf3, gr2, lin2, tp);
+    if (idx->n <= kZMaxDims) {
+      // Z-order levels: levels are cheap, so finer level-0 sides are in range
+      z_cur = 1;
+      const double rm_best = out->ms_best;
+      double zbest = 1e300, zwf = 0;
+      auto try_z = [&](double wf) {
+        const double ms = time_join(wf, 2.0, -1, tp0);
+        ++out->trials;
+        if (ms < zbest) {
+          zbest = ms;
+          zwf = wf;
+        }
+      };
+      for (double wf : {0.0625, 0.125, 0.25, 0.5, 1.0}) try_z(wf);
+      // the best side at the edge of the range: one more beyond it
+      if (zwf <= 0.0625)
+        try_z(0.03125);
+      else if (zwf >= 1.0)
+        try_z(2.0);
+      const double zwf1 = zwf;
+      for (double f : {0.7, 1.4}) try_z(zwf1 * f);
+      if (zbest < rm_best) {
+        out->ms_best = zbest;
+        out->w_factor = zwf;
+        out->growth = 2.0;
+        out->linear_levels = -1;
+        out->tail_pairs = tp0;
+        out->zorder = 1;
+        for (double tp : {6e7, 1e9}) consider(zwf, 2.0, -1, tp);
+      }
+      z_cur = out->zorder;
+    }
     // the lanes-per-query rule, halved or doubled at every level
-    const double tp4 = out->tail_pairs;
+    const double wf4 = out->w_factor, gr4 = out->growth, tp4 = out->tail_pairs;
+    const int lin4 = out->linear_levels;
     out->lanes_shift = 0;
     for (int ls : {-1, 1}) {
       ls_cur = ls;
       const double before = out->ms_best;
-      consider(wf3, gr2, lin2, tp4);
+      consider(wf4, gr4, lin4, tp4);
       if (out->ms_best < before) out->lanes_shift = ls;
     }
     ls_cur = 0;
     autotune_store(idx->n, K, idx->N,
                    TuneEntry{out->w_factor, out->growth, 0, out->linear_levels > 0 ? 1 : -1,
-                             out->tail_pairs, out->lanes_shift});
+                             out->tail_pairs, out->lanes_shift, out->zorder});
   });
 }
 

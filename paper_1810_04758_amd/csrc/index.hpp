@@ -41,6 +41,8 @@ struct JoinContext {
   int device = 0;
   // level arrays
   GridGeom gg{};
+  GridGeom gz0{};  // Z-order levels: the level-0 geometry the keys were sorted for
+  bool zmode = false;  // the current level is a Z-order level
   int64_t M = 0;
   DevBuf<double> Xs, Xs2;      // sorted points (Xs2: the other of a level pair)
   DevBuf<int32_t> perm, perm2;  // sorted position -> id
@@ -146,6 +148,14 @@ void build_grid(const knn_index& idx, JoinContext& ctx, double w, hipStream_t s,
                 bool from_prev = false);
 int64_t build_ranges(const knn_index& idx, JoinContext& ctx, hipStream_t s, int64_t Mcap_known,
                      const uint8_t* cell_active, uint8_t active_tag);
+// Z-order level `level` (cell side w0 * 2^level) into ctx: level 0 computes
+// the interleaved keys, sorts them once and gathers the points; a later level
+// only rebuilds the cell table from the same sorted keys shifted by
+// dims * level bits (cell sides double exactly, so each coarse cell is a run
+// of the sorted order).  Neighbour ranges follow with build_ranges.
+void build_grid_z(const knn_index& idx, JoinContext& ctx, double w0, int level, hipStream_t s);
+// Whether a join of (idx, K) with options o runs on Z-order levels.
+bool use_zorder(const knn_index& idx, int32_t K, const knn_join_opts& o);
 // Builds the grid level of cell side w into ctx (Sec. 3.1 / 4.6).
 // Mcap_known > 0: the cell count that sizes the 5-6 dimension range arrays
 // (no round trip); else it is read back when needed.  Returns the Mcap used.

@@ -31,6 +31,13 @@ struct GridGeom {
   uint64_t stride[kMaxDims];  // key stride per dimension (last = 1)
   int32_t key_bits;           // bits of the largest key
   int64_t g_max;
+  // Z-order levels: keys interleave the bits of the cell coordinates (bit b
+  // of dimension j at position b*dims + dims-1-j), zbits bits per dimension
+  // at this level.  The cell key of a point at level L is its level-0 key
+  // shifted right by zshift = dims*L, so one sort of the level-0 keys orders
+  // the points for every level.  zbits = 0: row-major keys (stride).
+  int32_t zbits;
+  int32_t zshift;
 };
 
 // ---- elementwise / reductions (grid.hip) ----
@@ -67,15 +74,21 @@ bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* v
                       hipStream_t s);
 
 // ---- grid level construction (grid.hip) ----
-// keys[i] = cell key of point i (original order, SoA X); vals[i] = i.
+// keys[i] = cell key of point i (original order, SoA X; row-major or Z-order
+// as gg says); vals[i] = i.
 void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* keys,
                       int32_t* vals, hipStream_t s);
 // From sorted keys, in one pass (cell starts counted, scanned by look-back):
 // the cell table.  cell_of (N), cell_key (N),
 // cell_start (N+1), d_M (device scalar) written.  state: scan state (flags unused).
+// shift: the cells are those of sorted_keys >> shift (a Z-order level above
+// the one the keys were sorted for); cell_key holds the shifted keys.
 void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags,
                       uint32_t* cell_of, uint64_t* cell_key, uint32_t* cell_start,
-                      uint32_t* d_M, uint32_t* state, int64_t state_elems, hipStream_t s);
+                      uint32_t* d_M, uint32_t* state, int64_t state_elems, hipStream_t s,
+                      int shift = 0);
+// list[i] = perm[list[i]] for i < n (sorted positions -> point ids).
+void launch_pos_to_id(int32_t* list, int64_t n, const int32_t* perm, hipStream_t s);
 // keys[p] = cell key of the point at sorted position p of the previous level
 // (point-major Xs), vals[p] = p.
 void launch_cell_keys_points(const double* Xs, int64_t N, const GridGeom& gg, uint64_t* keys,
@@ -112,9 +125,26 @@ void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_st
                             const uint8_t* cell_active /*nullable*/, uint8_t active_tag,
                             const GridGeom& gg, uint32_t* ranges, uint8_t* rslot,
                             uint32_t* nrng, uint32_t* cand_count, hipStream_t s);
-// flags[cell_of[active[i]]] = tag for every active query.
+// Z-order level: neighbour ranges of the cells flagged with active_tag
+// (every cell when cell_active is NULL), one entry per non-empty cell of the
+// 3^n block, compacted in block order (offsets o_0..o_{n-1} in {-1,0,1}, the
+// last fastest) in the row-segment format above: rslot = the offsets of
+// dimensions 0..n-2, and the cell is the lower part (o_{n-1} = -1: start,
+// end, end, end), the middle (0: start, start, end, end) or the upper part
+// (+1: start, start, start, end) of its segment, so the search's pruning
+// reads it unchanged.  Neighbours are found by a galloping search outward
+// from the cell's own position in cell_key (Z-order neighbours are mostly
+// close in the sorted cell table).  ranges: R = 3^n entries per cell.
+void launch_neighbor_ranges_z(const uint32_t* cell_start, const uint64_t* cell_key,
+                              const uint32_t* d_M, int64_t N, const uint8_t* cell_active,
+                              uint8_t active_tag, const GridGeom& gg, uint32_t* ranges,
+                              uint8_t* rslot, uint32_t* nrng, uint32_t* cand_count,
+                              hipStream_t s);
+// flags[cell_of[active[i]]] = tag for every active query (n_dev non-NULL:
+// the first min(n_active, *n_dev) of the list).
 void launch_mark_cells_of(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
-                          uint8_t* flags, uint8_t tag, hipStream_t s);
+                          uint8_t* flags, uint8_t tag, hipStream_t s,
+                          const uint32_t* n_dev = nullptr);
 
 // ---- work items (grid.hip) ----
 // Work item i = G consecutive active slots.  Its estimate is the sum of the
@@ -135,11 +165,13 @@ void launch_heavy_list(const int32_t* active /*nullable*/, int64_t n_active,
                        const uint32_t* cell_of, const uint32_t* cand_count, uint32_t heavy_min,
                        int32_t* list, int32_t* count, unsigned long long* cand_sum,
                        hipStream_t s);
-// failed[id] = tag for the ids of the failure list (the next level's active
-// queries carry that level's tag).
+// failed[e] = tag for the entries e of the failure list (ids, or sorted
+// positions on Z-order levels; the next level's active queries carry that
+// level's tag).
 void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count,
                         int64_t max_fail, uint8_t* failed, uint8_t tag, hipStream_t s);
-// out = the sorted positions p with failed[perm[p]] == tag, in order; their
+// out = the sorted positions p with failed[perm[p]] == tag (perm NULL:
+// failed[p] == tag), in order; their
 // number to *count (device).  One pass (scan state as launch_exclusive_scan).
 void launch_active_list(const uint8_t* failed, uint8_t tag, const int32_t* perm, int64_t N,
                         int32_t* out, uint32_t* count, uint32_t* state, int64_t state_elems,
@@ -176,6 +208,7 @@ struct SearchArgs {
   int32_t grain;           // items claimed per queue pop
   int32_t persistent;
   int32_t share_lists;     // wavefronts whose queries share a cell walk one list
+  int32_t zl;              // Z-order level: 3^n single-cell ranges per cell (else 3^(n-1))
   double lo[kMaxDims];
   double inv_w;
   double w;                // fl(1 / inv_w)
@@ -185,8 +218,9 @@ struct SearchArgs {
   int32_t cap;             // per-query survivor buffer entries (>= K)
   int32_t* out_ids;        // N x K, row = point id
   double* out_d;
-  int32_t* fail_list;      // point ids of failed queries
+  int32_t* fail_list;      // point ids of failed queries (sorted positions if fail_pos)
   int32_t* fail_count;
+  int32_t fail_pos;        // Z-order levels: failures listed by sorted position
   int32_t* refine_count;   // diagnostics: refinement rounds executed
   uint32_t heavy_min;      // > 0: k_search leaves queries with this many candidates or more
   const int32_t* heavy;    // to k_search_heavy: their sorted positions
@@ -208,6 +242,14 @@ struct DeferArgs {
   const uint32_t* cand;       // candidates per cell
   const int32_t* active;      // active sorted positions (nullptr: identity)
   int64_t n_active;
+  const uint32_t* n_active_dev;  // nullable: the count is min(n_active, *n_active_dev)
+  // Z-order levels, before the neighbour ranges exist: with cell_key set, the
+  // density comes from the query's parent group (the 2^n cells whose keys
+  // agree above the last n bits, a cell of twice the side) instead of cand
+  const uint64_t* cell_key;
+  const uint32_t* cell_start;
+  const uint32_t* d_M;
+  int32_t fail_pos;           // deferred queries listed by sorted position (else id)
   double lo[kMaxDims];
   double inv_w;
   double w;
@@ -218,7 +260,8 @@ struct DeferArgs {
   uint32_t* out_count;        // their number (device)
   int32_t* fail_list;         // deferred ids appended here
   int32_t* fail_count;
-  unsigned long long* cand_sum;  // [0] += candidates of kept queries, [1] = max (pre-zeroed)
+  unsigned long long* cand_sum;  // nullable: [0] += candidates of kept queries, [1] = max
+                                 // (pre-zeroed)
   uint32_t* state;            // single-pass scan state (launch_exclusive_scan)
   int64_t state_elems;
 };
@@ -231,14 +274,17 @@ void launch_search(const SearchArgs& a, int dims, int lanes_per_query, int grid_
 // *a.n_heavy), grid-stride over them (blocks: any positive count).
 constexpr int kHeavyThreads = 1024;
 void launch_search_heavy(const SearchArgs& a, int dims, int blocks, hipStream_t s);
-// Dynamic LDS bytes per wave for a given (lanes_per_query, cap).
-size_t search_lds_per_wave(int dims, int lanes_per_query, int cap);
+// Dynamic LDS bytes per wave for a given (lanes_per_query, cap); zl: a
+// Z-order level (3^n range slots per cell).
+size_t search_lds_per_wave(int dims, int lanes_per_query, int cap, bool zl = false);
 // Speculative survivor slots per query for a given (lanes_per_query, cap), and
 // the coefficient of the predicted K-th squared distance at cell side w.
-int search_spec_slots(int dims, int lanes_per_query, int cap);
+int search_spec_slots(int dims, int lanes_per_query, int cap, bool zl = false);
 double search_density_coef(int dims, int K, double w);
-int search_waves_per_block(int dims, int lanes_per_query, int cap);
+int search_waves_per_block(int dims, int lanes_per_query, int cap, bool zl = false);
 // Resident blocks per CU of the search kernel (occupancy API).
-int search_blocks_per_cu(int dims, int lanes_per_query, int cap);
+int search_blocks_per_cu(int dims, int lanes_per_query, int cap, bool zl = false);
+// Largest dimension count with Z-order levels.
+constexpr int kZMaxDims = 4;
 
 }  // namespace knn

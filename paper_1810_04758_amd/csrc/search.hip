@@ -393,11 +393,13 @@ __device__ __forceinline__ void flush_failures(const SearchArgs& a, const int32_
   wave_fence();
 }
 
-template <int DIM, int T, bool OFF32>
+// ZL: a Z-order level, whose cells list the 3^n cells of their block one by
+// one (else the 3^(n-1) row segments).
+template <int DIM, int T, bool OFF32, bool ZL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WavesPerEu<DIM>::v)))
 k_search(const SearchArgs a) {
   constexpr int G = 64 / T;  // queries per wave
-  constexpr int R = Pow3<DIM - 1>::v;
+  constexpr int R = ZL ? Pow3<DIM>::v : Pow3<DIM - 1>::v;
   constexpr int P = NB / T;  // count bins owned by each lane of a group
   constexpr int kUnroll = Unroll<DIM>::v;
   extern __shared__ double smem[];
@@ -631,7 +633,7 @@ k_search(const SearchArgs a) {
           flush_failures(a, fbuf, nfail, lane);
           nfail = 0;
         }
-        if (lf) fbuf[nfail + (int)__popcll(fm & lane_lt)] = perm[q];
+        if (lf) fbuf[nfail + (int)__popcll(fm & lane_lt)] = a.fail_pos ? (int32_t)q : perm[q];
         nfail += nf;
         wave_fence();
       }
@@ -862,10 +864,12 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
   int32_t qk[kDeferRounds];
   uint32_t nk = 0, nd = 0;
   unsigned long long csum = 0, cmax = 0;
+  const int64_t n_act = a.n_active_dev ? min(a.n_active, (int64_t)*a.n_active_dev) : a.n_active;
+  const uint32_t M = a.cell_key ? *a.d_M : 0u;
 #pragma unroll
   for (int k = 0; k < kDeferRounds; ++k) {
     const int64_t i = wbase + k * 64 + lane;
-    const bool in = i < a.n_active;
+    const bool in = i < n_act;
     const int32_t q = in ? (a.active ? a.active[i] : (int32_t)i) : 0;
     qk[k] = q;
     bool defer = false;
@@ -873,7 +877,18 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
     if (in) {
       double qx[DIM];
       load_point<DIM, false>(a.Xs, (uint32_t)q, qx);
-      Cq = a.cand[a.cell_of[q]];
+      const uint32_t c = a.cell_of[q];
+      if (a.cell_key) {
+        // the points of the parent group: the cells next to c in the table
+        // whose keys agree above the last DIM bits (at most 2^DIM of them)
+        const uint64_t pk = a.cell_key[c] >> DIM;
+        uint32_t c0 = c, c1 = c;
+        while (c0 > 0 && (a.cell_key[c0 - 1] >> DIM) == pk) --c0;
+        while (c1 + 1 < M && (a.cell_key[c1 + 1] >> DIM) == pk) ++c1;
+        Cq = a.cell_start[c1 + 1] - a.cell_start[c0];
+      } else {
+        Cq = a.cand[c];
+      }
       // the covered radius of the search kernel
       double mfrac = 0.5;
       bool full = true;
@@ -920,7 +935,8 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
 #pragma unroll
   for (int k = 0; k < kDeferRounds; ++k) {
     if ((mk[k] >> lane) & 1ull) a.out_active[o + (uint32_t)__popcll(mk[k] & lt_mask)] = qk[k];
-    if ((md[k] >> lane) & 1ull) a.fail_list[f + (uint32_t)__popcll(md[k] & lt_mask)] = a.perm[qk[k]];
+    if ((md[k] >> lane) & 1ull)
+      a.fail_list[f + (uint32_t)__popcll(md[k] & lt_mask)] = a.fail_pos ? qk[k] : a.perm[qk[k]];
     o += (uint32_t)__popcll(mk[k]);
     f += (uint32_t)__popcll(md[k]);
   }
@@ -942,8 +958,8 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
       ts += s_sum[i];
       tm = tm > s_max[i] ? tm : s_max[i];
     }
-    if (ts) atomicAdd(&a.cand_sum[0], ts);
-    if (tm) atomicMax(&a.cand_sum[1], tm);
+    if (a.cand_sum && ts) atomicAdd(&a.cand_sum[0], ts);
+    if (a.cand_sum && tm) atomicMax(&a.cand_sum[1], tm);
   }
 }
 
@@ -954,9 +970,9 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
 // lists, selection, refinement and ranking as k_search, with workgroup
 // barriers in place of the group's lane exchanges (the lists are built by the
 // first wavefront).
-template <int DIM>
+template <int DIM, bool ZL>
 __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs a) {
-  constexpr int R = Pow3<DIM - 1>::v;
+  constexpr int R = ZL ? Pow3<DIM>::v : Pow3<DIM - 1>::v;
   constexpr int NT = kHeavyThreads;
   constexpr int kUnroll = Unroll<DIM>::v;
   extern __shared__ double smem[];
@@ -1060,7 +1076,7 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
       s_dmin = ~0ull;
       s_dmax = 0ull;
       if (bsel == NB) {
-        a.fail_list[atomicAdd(a.fail_count, 1)] = perm[q];
+        a.fail_list[atomicAdd(a.fail_count, 1)] = a.fail_pos ? (int32_t)q : perm[q];
         if (a.heavy_fail) atomicAdd(a.heavy_fail, 1);
       }
     }
@@ -1224,47 +1240,83 @@ __global__ void __launch_bounds__(kHeavyThreads) k_search_heavy(const SearchArgs
   }
 }
 
-template <int DIM, int T>
+// Z-order levels exist for 2..kZMaxDims dimensions only (no kernels above).
+template <int DIM>
+constexpr bool kHasZ = DIM <= kZMaxDims;
+
+template <int DIM, int T, bool ZL>
 int occupancy_of(int threads, size_t lds) {
   int n = 0;
-  KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<DIM, T, true>, threads, lds));
+  KNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_search<DIM, T, true, ZL>, threads,
+                                                       lds));
   return n;
 }
 
-template <int DIM>
-int occupancy_dim(int T, int threads, size_t lds) {
+template <int DIM, bool ZL>
+int occupancy_dim_z(int T, int threads, size_t lds) {
   switch (T) {
-    case 1: return occupancy_of<DIM, 1>(threads, lds);
-    case 2: return occupancy_of<DIM, 2>(threads, lds);
-    case 4: return occupancy_of<DIM, 4>(threads, lds);
-    case 8: return occupancy_of<DIM, 8>(threads, lds);
-    case 16: return occupancy_of<DIM, 16>(threads, lds);
-    case 32: return occupancy_of<DIM, 32>(threads, lds);
-    default: return occupancy_of<DIM, 64>(threads, lds);
+    case 1: return occupancy_of<DIM, 1, ZL>(threads, lds);
+    case 2: return occupancy_of<DIM, 2, ZL>(threads, lds);
+    case 4: return occupancy_of<DIM, 4, ZL>(threads, lds);
+    case 8: return occupancy_of<DIM, 8, ZL>(threads, lds);
+    case 16: return occupancy_of<DIM, 16, ZL>(threads, lds);
+    case 32: return occupancy_of<DIM, 32, ZL>(threads, lds);
+    default: return occupancy_of<DIM, 64, ZL>(threads, lds);
   }
 }
 
-template <int DIM, bool OFF32>
+template <int DIM>
+int occupancy_dim(int T, int threads, size_t lds, bool zl) {
+  if constexpr (kHasZ<DIM>) {
+    if (zl) return occupancy_dim_z<DIM, true>(T, threads, lds);
+  }
+  KNN_CHECK(!zl, KNN_EINTERNAL, "no Z-order search kernel for this dimension");
+  return occupancy_dim_z<DIM, false>(T, threads, lds);
+}
+
+template <int DIM, bool OFF32, bool ZL>
 void launch_dim_off(const SearchArgs& a, int T, int blocks, int threads, size_t lds,
                     hipStream_t s) {
   switch (T) {
-    case 1: k_search<DIM, 1, OFF32><<<blocks, threads, lds, s>>>(a); break;
-    case 2: k_search<DIM, 2, OFF32><<<blocks, threads, lds, s>>>(a); break;
-    case 4: k_search<DIM, 4, OFF32><<<blocks, threads, lds, s>>>(a); break;
-    case 8: k_search<DIM, 8, OFF32><<<blocks, threads, lds, s>>>(a); break;
-    case 16: k_search<DIM, 16, OFF32><<<blocks, threads, lds, s>>>(a); break;
-    case 32: k_search<DIM, 32, OFF32><<<blocks, threads, lds, s>>>(a); break;
-    case 64: k_search<DIM, 64, OFF32><<<blocks, threads, lds, s>>>(a); break;
+    case 1: k_search<DIM, 1, OFF32, ZL><<<blocks, threads, lds, s>>>(a); break;
+    case 2: k_search<DIM, 2, OFF32, ZL><<<blocks, threads, lds, s>>>(a); break;
+    case 4: k_search<DIM, 4, OFF32, ZL><<<blocks, threads, lds, s>>>(a); break;
+    case 8: k_search<DIM, 8, OFF32, ZL><<<blocks, threads, lds, s>>>(a); break;
+    case 16: k_search<DIM, 16, OFF32, ZL><<<blocks, threads, lds, s>>>(a); break;
+    case 32: k_search<DIM, 32, OFF32, ZL><<<blocks, threads, lds, s>>>(a); break;
+    case 64: k_search<DIM, 64, OFF32, ZL><<<blocks, threads, lds, s>>>(a); break;
     default: throw Error(KNN_EINVAL, "lanes_per_query must be a power of two in [1, 64]");
   }
 }
 
+template <int DIM, bool ZL>
+void launch_dim_z(const SearchArgs& a, int T, int blocks, int threads, size_t lds,
+                  hipStream_t s) {
+  if (a.N * point_stride(DIM) * (int64_t)sizeof(double) < ((int64_t)1 << 32))
+    launch_dim_off<DIM, true, ZL>(a, T, blocks, threads, lds, s);
+  else
+    launch_dim_off<DIM, false, ZL>(a, T, blocks, threads, lds, s);
+}
+
 template <int DIM>
 void launch_dim(const SearchArgs& a, int T, int blocks, int threads, size_t lds, hipStream_t s) {
-  if (a.N * point_stride(DIM) * (int64_t)sizeof(double) < ((int64_t)1 << 32))
-    launch_dim_off<DIM, true>(a, T, blocks, threads, lds, s);
-  else
-    launch_dim_off<DIM, false>(a, T, blocks, threads, lds, s);
+  if constexpr (kHasZ<DIM>) {
+    if (a.zl) return launch_dim_z<DIM, true>(a, T, blocks, threads, lds, s);
+  }
+  KNN_CHECK(!a.zl, KNN_EINTERNAL, "no Z-order search kernel for this dimension");
+  launch_dim_z<DIM, false>(a, T, blocks, threads, lds, s);
+}
+
+template <int DIM>
+void launch_heavy_dim(const SearchArgs& a, int blocks, size_t lds, hipStream_t s) {
+  if constexpr (kHasZ<DIM>) {
+    if (a.zl) {
+      k_search_heavy<DIM, true><<<blocks, kHeavyThreads, lds, s>>>(a);
+      return;
+    }
+  }
+  KNN_CHECK(!a.zl, KNN_EINTERNAL, "no Z-order search kernel for this dimension");
+  k_search_heavy<DIM, false><<<blocks, kHeavyThreads, lds, s>>>(a);
 }
 
 }  // namespace
@@ -1287,10 +1339,10 @@ void launch_defer_filter(const DeferArgs& a, int dims, hipStream_t s) {
   KNN_LAUNCHED();
 }
 
-static size_t lds_base_per_wave(int dims, int T, int cap) {
+static size_t lds_base_per_wave(int dims, int T, int cap, bool zl) {
   const int G = 64 / T;
   size_t R = 1;
-  for (int j = 0; j < dims - 1; ++j) R *= 3;
+  for (int j = 0; j < (zl ? dims : dims - 1); ++j) R *= 3;
   return (size_t)cap * G * (sizeof(double) + sizeof(int32_t)) +
          (size_t)(NB + 1) * G * sizeof(uint32_t) + (size_t)kFailBuf * sizeof(int32_t) +
          2 * (R + 1) * G * sizeof(uint32_t);
@@ -1299,9 +1351,9 @@ static size_t lds_base_per_wave(int dims, int T, int cap) {
 // Speculative slots per query: twice the survivor buffer, but only what the
 // per-wave budget of 16 KiB leaves beside the other buffers; none when that
 // is below cap (a speculation needs room for more than K).
-int search_spec_slots(int dims, int T, int cap) {
+int search_spec_slots(int dims, int T, int cap, bool zl) {
   const int G = 64 / T;
-  const size_t base = lds_base_per_wave(dims, T, cap);
+  const size_t base = lds_base_per_wave(dims, T, cap, zl);
   const int room = base < 16384 ? (int)((16384 - base) / (G * sizeof(uint32_t))) : 0;
   const int sc = std::min(2 * cap, room);
   return sc >= cap ? sc : 0;
@@ -1321,40 +1373,40 @@ double search_density_coef(int dims, int K, double w) {
   return w * w * std::pow(K * std::pow(3.0, n) / vn, 2.0 / n);
 }
 
-size_t search_lds_per_wave(int dims, int T, int cap) {
-  return lds_base_per_wave(dims, T, cap) +
-         (size_t)(64 / T) * search_spec_slots(dims, T, cap) * sizeof(uint32_t);
+size_t search_lds_per_wave(int dims, int T, int cap, bool zl) {
+  return lds_base_per_wave(dims, T, cap, zl) +
+         (size_t)(64 / T) * search_spec_slots(dims, T, cap, zl) * sizeof(uint32_t);
 }
 
-int search_waves_per_block(int dims, int T, int cap) {
-  size_t per = search_lds_per_wave(dims, T, cap);
+int search_waves_per_block(int dims, int T, int cap, bool zl) {
+  size_t per = search_lds_per_wave(dims, T, cap, zl);
   int w = (int)(65536 / per);
   if (w > 4) w = 4;
   if (w < 1) w = 1;
   return w;
 }
 
-int search_blocks_per_cu(int dims, int T, int cap) {
+int search_blocks_per_cu(int dims, int T, int cap, bool zl) {
   // the occupancy query costs host time on every call; levels ask it often
   static std::mutex mu;
-  static std::map<std::tuple<int, int, int, int>, int> cache;
+  static std::map<std::tuple<int, int, int, int, bool>, int> cache;
   int dev = 0;
   KNN_HIP(hipGetDevice(&dev));
-  const auto key = std::make_tuple(dev, dims, T, cap);
+  const auto key = std::make_tuple(dev, dims, T, cap, zl);
   {
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
   }
-  const int waves = search_waves_per_block(dims, T, cap);
-  const size_t lds = search_lds_per_wave(dims, T, cap) * waves;
+  const int waves = search_waves_per_block(dims, T, cap, zl);
+  const size_t lds = search_lds_per_wave(dims, T, cap, zl) * waves;
   int n = 1;
   switch (dims) {
-    case 2: n = occupancy_dim<2>(T, waves * 64, lds); break;
-    case 3: n = occupancy_dim<3>(T, waves * 64, lds); break;
-    case 4: n = occupancy_dim<4>(T, waves * 64, lds); break;
-    case 5: n = occupancy_dim<5>(T, waves * 64, lds); break;
-    case 6: n = occupancy_dim<6>(T, waves * 64, lds); break;
+    case 2: n = occupancy_dim<2>(T, waves * 64, lds, zl); break;
+    case 3: n = occupancy_dim<3>(T, waves * 64, lds, zl); break;
+    case 4: n = occupancy_dim<4>(T, waves * 64, lds, zl); break;
+    case 5: n = occupancy_dim<5>(T, waves * 64, lds, zl); break;
+    case 6: n = occupancy_dim<6>(T, waves * 64, lds, zl); break;
     default: break;
   }
   n = n > 0 ? n : 1;
@@ -1368,11 +1420,11 @@ void launch_search_heavy(const SearchArgs& a, int dims, int blocks, hipStream_t 
   const size_t lds = (size_t)a.cap * (sizeof(double) + sizeof(int32_t));
   KNN_CHECK(lds <= 49152, KNN_EINVAL, "K too large for the per-query buffers");
   switch (dims) {
-    case 2: k_search_heavy<2><<<blocks, kHeavyThreads, lds, s>>>(a); break;
-    case 3: k_search_heavy<3><<<blocks, kHeavyThreads, lds, s>>>(a); break;
-    case 4: k_search_heavy<4><<<blocks, kHeavyThreads, lds, s>>>(a); break;
-    case 5: k_search_heavy<5><<<blocks, kHeavyThreads, lds, s>>>(a); break;
-    case 6: k_search_heavy<6><<<blocks, kHeavyThreads, lds, s>>>(a); break;
+    case 2: launch_heavy_dim<2>(a, blocks, lds, s); break;
+    case 3: launch_heavy_dim<3>(a, blocks, lds, s); break;
+    case 4: launch_heavy_dim<4>(a, blocks, lds, s); break;
+    case 5: launch_heavy_dim<5>(a, blocks, lds, s); break;
+    case 6: launch_heavy_dim<6>(a, blocks, lds, s); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
   KNN_LAUNCHED();
@@ -1380,8 +1432,8 @@ void launch_search_heavy(const SearchArgs& a, int dims, int blocks, hipStream_t 
 
 void launch_search(const SearchArgs& a, int dims, int T, int grid_blocks, hipStream_t s) {
   KNN_CHECK(a.cap >= NB2 / 2 + 1, KNN_EINTERNAL, "per-query buffer too small");
-  const int waves = search_waves_per_block(dims, T, a.cap);
-  const size_t lds = search_lds_per_wave(dims, T, a.cap) * waves;
+  const int waves = search_waves_per_block(dims, T, a.cap, a.zl != 0);
+  const size_t lds = search_lds_per_wave(dims, T, a.cap, a.zl != 0) * waves;
   KNN_CHECK(lds <= 65536, KNN_EINVAL,
             "per-query buffers exceed the LDS (raise lanes_per_query or lower K)");
   const int threads = waves * 64;
