@@ -4,7 +4,12 @@ A step is one pass of the whole hot path over the workload: for every dataset
 of the workload, knn_build_index_device (bounds, eps sampling) and, for every
 K, knn_self_join_device (grid levels, density-ordered persistent search,
 failure re-queue and re-index), with the coordinates already resident in
-device memory.  Prints one JSON line.
+device memory.  The default workload is the largest configuration, the
+clustered catalogue-shaped 2-D set (N = 2e7, K = 16).  The other
+configurations are reported beside it as extra cases (join time, queries/s
+and the search kernel's roofline each), with the persistent-vs-plain and
+graph-vs-eager comparisons, the serving workload at two request rates, and
+the CPU oracle timed on every configuration.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -23,13 +28,16 @@ sys.path.insert(0, ROOT)
 
 WORKLOADS = {
     # name: (description, [(dataset name, K list)])
+    "clustered2d_20m": ("clustered catalogue-shaped 2-D: 70% from 500 Gaussian clusters, 30% "
+                        "uniform background, N=2e7, K=16", [("clustered2d_20m", [16])]),
     "expo_2m": ("skewed density: exponential(rate 40) coordinates, N=2e6, 2-D and 4-D, "
                 "K in {1,8,32,64}", [("expo2d_2m", [1, 8, 32, 64]), ("expo4d_2m", [1, 8, 32, 64])]),
     "expo2d_2m_k32": ("exponential(rate 40) 2-D, N=2e6, K=32", [("expo2d_2m", [32])]),
     "unif2d_50k": ("uniform [0,100)^2, N=5e4, K=5", [("unif2d_50k", [5])]),
     "unif6d_5m": ("uniform [0,100)^6, N=5e6, K=32", [("unif6d_5m", [32])]),
-    "clustered2d_20m": ("clustered catalogue-shaped 2-D, N=2e7, K=16", [("clustered2d_20m", [16])]),
 }
+# the configurations reported beside the headline, as extra cases
+EXTRA_WORKLOADS = ["unif2d_50k", "expo_2m", "unif6d_5m", "clustered2d_20m"]
 
 HBM_PEAK_GBS = 8000.0
 # FP64 vector peak without FMA: 256 CUs x 64 lanes x 2.4 GHz (78.6 TFLOP/s counts an FMA as 2)
@@ -92,56 +100,87 @@ def measured_traffic(workload):
         return None
 
 
-def cpu_baseline(datasets, cases, budget_s=12.0):
-    """Time the CPU oracle (as it stands) on a bounded sample of the same
-    queries: a probe sizes the per-case sample so the whole leg takes about
-    budget_s seconds of wall time on all host cores."""
+def roofline_of(records):
+    """Roofline of the search kernel over the given joins [(n, K, stats)]:
+    algorithmic bytes and FP64 operations of all its launches over their total
+    duration (HIP events recorded around each launch on the join stream).  The
+    binding roof is the one with the larger time at peak; the other is
+    reported beside it."""
+    search_ms = sum(sum(st["ms_search"]) for _, _, st in records)
+    launches = sum(st["levels"] for _, _, st in records)
+    nbytes = sum(alg_bytes(st, n, K) for n, K, st in records)
+    ops = sum(alg_ops(st, n) for n, K, st in records)
+    achieved = nbytes / (search_ms * 1e-3) / 1e9 if search_ms > 0 else 0.0
+    achieved_ops = ops / (search_ms * 1e-3) / 1e12 if search_ms > 0 else 0.0
+    alu_bound = ops / (ALU_PEAK_TOPS * 1e12) > nbytes / (HBM_PEAK_GBS * 1e9)
+    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    alu = {"bound": "alu", "achieved": round(achieved_ops, 3), "peak": round(ALU_PEAK_TOPS, 2),
+           "unit": "TFLOP/s", "frac": round(achieved_ops / ALU_PEAK_TOPS, 4)}
+    roof = dict(alu if alu_bound else hbm)
+    roof.update({"kernel": "k_search",
+                 "alg_bytes_per_launch": round(nbytes / max(1, launches)),
+                 "alg_fp64_ops_per_launch": round(ops / max(1, launches)),
+                 "avg_launch_ms": round(search_ms / max(1, launches), 4),
+                 "launches": launches,
+                 "other_roof": hbm if alu_bound else alu})
+    return roof
+
+
+def oracle_rate(D, K, rows, threads):
+    """Queries per second of the brute-force oracle on the given rows."""
     import oracle
+    t0 = time.perf_counter()
+    oracle.knn(D, K, rows=rows, threads=threads)
+    return rows.shape[0] / (time.perf_counter() - t0), time.perf_counter() - t0
+
+
+def cpu_baseline(cases, budget_s=3.0, single_s=1.5):
+    """The CPU oracle (brute force by the definition, as it stands) timed on
+    the host cores on a bounded random sample of each configuration's queries:
+    all cores, then one core; a probe sizes each sample to about budget_s
+    (single_s on one core) of wall time.  cases: [(name, D, K)]."""
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     rng = np.random.default_rng(0)
-    name0, K0 = cases[0]
-    probe = rng.choice(datasets[name0].shape[0], size=threads, replace=False)
-    t0 = time.perf_counter()
-    oracle.knn(datasets[name0], K0, rows=probe, threads=threads)
-    per_query = (time.perf_counter() - t0) / threads
-    per_case = int(max(threads, min(20000, budget_s / len(cases) / max(per_query, 1e-9))))
-    per_case = (per_case // threads) * threads
-    done = 0
-    t_total = 0.0
-    sample_desc = []
-    for name, K in cases:
-        D = datasets[name]
-        rows = rng.choice(D.shape[0], size=min(per_case, D.shape[0]), replace=False)
-        t0 = time.perf_counter()
-        oracle.knn(D, K, rows=rows, threads=threads)
-        t_total += time.perf_counter() - t0
-        done += rows.shape[0]
-        sample_desc.append(f"{name}/K={K}:{rows.shape[0]}q")
-    return {"value": round(done / t_total, 2), "unit": "queries/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "brute-force oracle on random rows of the same inputs: " +
-                      ", ".join(sample_desc) + f" ({done} queries, {t_total:.1f} s wall)"}
+    out = []
+    for name, D, K in cases:
+        N = D.shape[0]
+        probe = rng.choice(N, size=min(N, threads), replace=False)
+        r, _ = oracle_rate(D, K, probe, threads)
+        n_all = int(min(N, max(threads, min(200_000, budget_s * r))))
+        rows = rng.choice(N, size=n_all, replace=False)
+        r_all, t_all = oracle_rate(D, K, rows, threads)
+        n_one = int(min(N, max(4, min(50_000, single_s * r_all / threads))))
+        rows1 = rng.choice(N, size=n_one, replace=False)
+        r_one, t_one = oracle_rate(D, K, rows1, 1)
+        out.append({"config": name, "K": K, "N": N,
+                    "all_cores": {"value": round(r_all, 2), "cores": threads,
+                                  "sample_queries": n_all, "wall_s": round(t_all, 2)},
+                    "single_core": {"value": round(r_one, 2), "cores": 1,
+                                    "sample_queries": n_one, "wall_s": round(t_one, 2)}})
+    return out
 
 
-def serving_leg(api, seconds, rate=200.0, budget_gib=96, inflight=4):
+def serving_leg(api, seconds, rate, pool=None, idxs=None, budget_gib=96, inflight=4,
+                max_queue=64):
     """The serving workload: a Poisson stream (mean `rate` requests/s for
     `seconds`) of self-join requests over 24 resident datasets (N log-uniform
     in [1e4, 1e7], dims in {2,3,4,6}, uniform or exponential coordinates, K in
-    {1,4,16,64}), admitted by device-memory footprint and run concurrently.
-    Latency is submit -> results ready; most requests are latency-only
-    (results discarded on the device), every 25th is copied back and compared
-    with a solo join of the same index and K."""
+    {1,4,16,64}), admitted by device-memory footprint and run concurrently.  A
+    request that finds max_queue requests already waiting is refused
+    (KNN_EBUSY) and counted.  Latency is submit -> results ready; most
+    requests are latency-only (results discarded on the device), every 25th is
+    copied back and compared with a solo join of the same index and K."""
+    from paper_1810_04758_amd._lib import KNN_EBUSY, KnnError
     from paper_1810_04758_amd import datagen
-    t_build = time.perf_counter()
-    pool = datagen.serving_pool()
-    idxs = [api.build_index(D) for D, _ in pool]
-    t_build = time.perf_counter() - t_build
     arrivals, ds, ks = datagen.serving_trace(seconds, rate, len(pool))
-    srv = api.Server(mem_budget_bytes=budget_gib << 30, max_inflight=inflight)
+    srv = api.Server(mem_budget_bytes=budget_gib << 30, max_inflight=inflight,
+                     max_queue=max_queue)
     for ix in idxs:
         srv.add_dataset(ix)
     checks = []
     tickets = []
+    refused = 0
     t0 = time.perf_counter()
     for i, (ta, d, k) in enumerate(zip(arrivals, ds, ks)):
         now = time.perf_counter() - t0
@@ -149,7 +188,13 @@ def serving_leg(api, seconds, rate=200.0, budget_gib=96, inflight=4):
             time.sleep(ta - now)
         N = pool[d][0].shape[0]
         keep = (i % 25 == 0) and N <= 1_000_000
-        tickets.append((srv.submit(int(d), int(k), N, discard=not keep), int(d), int(k), keep))
+        try:
+            tickets.append((srv.submit(int(d), int(k), N, discard=not keep), int(d), int(k),
+                            keep))
+        except KnnError as e:
+            if e.code != KNN_EBUSY:
+                raise
+            refused += 1
     for t, d, k, keep in tickets:
         ids, dists = srv.wait(t)
         if keep:
@@ -161,84 +206,148 @@ def serving_leg(api, seconds, rate=200.0, budget_gib=96, inflight=4):
     for d, k, ids, dists in checks:
         ref_i, ref_d = idxs[d].self_join_host(k)
         same = same and bool((ref_i == ids).all() and (ref_d == dists).all())
-    for ix in idxs:
-        ix.close()
-    return {"requests": int(st["completed"]), "trace_seconds": seconds, "rate_per_s": rate,
+    return {"offered": int(len(arrivals)), "refused_queue_full": refused,
+            "completed": int(st["completed"]), "trace_seconds": seconds, "rate_per_s": rate,
             "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
             "mean_ms": round(st["mean_ms"], 2), "queries_per_s": round(st["queries_per_s"], 1),
             "requests_per_s": round(st["requests_per_s"], 2), "wall_s": round(wall, 2),
             "peak_inflight": int(st["peak_inflight"]), "peak_bytes": int(st["peak_bytes"]),
-            "mix_equals_solo_checked": len(checks), "mix_equals_solo": same,
-            "index_build_s": round(t_build, 2),
-            "datasets": [desc for _, desc in pool]}
+            "max_queue": max_queue,
+            "mix_equals_solo_checked": len(checks), "mix_equals_solo": same}
 
 
-def schedule_comparison(api, dev, plan, outs, stream, reps=3):
+def serving(api, seconds_hi, seconds_lo, rate_lo):
+    """Both serving points over one resident pool: the configured 200
+    requests/s, and a rate the GPU sustains (served about equal to offered)."""
+    from paper_1810_04758_amd import datagen
+    t_build = time.perf_counter()
+    pool = datagen.serving_pool()
+    idxs = [api.build_index(D) for D, _ in pool]
+    t_build = time.perf_counter() - t_build
+    out = {"datasets": [desc for _, desc in pool], "index_build_s": round(t_build, 2)}
+    if seconds_lo > 0:
+        out["sustainable"] = serving_leg(api, seconds_lo, rate_lo, pool, idxs)
+    if seconds_hi > 0:
+        out["configured"] = serving_leg(api, seconds_hi, 200.0, pool, idxs)
+    for ix in idxs:
+        ix.close()
+    return out
+
+
+def schedule_row(idx, K, ids, dists, stream, reps=3):
     """The persistent schedule (device work queues per XCD, density-ordered
     items, heavy queries on workgroups of their own) against the plain one:
     one launch per level over every unsolved query in cell order, one work
     item per wavefront, no queue (same cell sides and lanes per query, so the
-    same candidates are scanned).  Untimed by the step clock; best of `reps`
-    joins each; search time (both search kernels) from the join's HIP events."""
-    res = []
-    tot = {0: [0.0, 0.0], 1: [0.0, 0.0]}
-    for name, Ks in plan:
-        idx = api.build_index(dev[name], stream=stream)
-        for K in Ks:
-            ids, dists = outs[(name, K)]
-            row = dict(dataset=name, K=K)
-            for sched in (0, 1):
-                best_s = best_t = float("inf")
-                # plain: no queue, no density order, no heavy-query workgroups
-                extra = dict(schedule=1, heavy_min=-1) if sched else {}
-                for _ in range(reps):
-                    _, _, st = idx.self_join(K, ids=ids, dists=dists, stream=stream,
-                                             with_stats=True, **extra)
-                    best_s = min(best_s, sum(st["ms_search"]) + sum(st["ms_heavy"]))
-                    best_t = min(best_t, st["ms_total"])
-                key = "persistent" if sched == 0 else "plain"
-                row[f"ms_search_{key}"] = round(best_s, 3)
-                row[f"ms_join_{key}"] = round(best_t, 3)
-                tot[sched][0] += best_s
-                tot[sched][1] += best_t
-            row["search_speedup"] = round(row["ms_search_plain"] / row["ms_search_persistent"], 3)
-            res.append(row)
-        idx.close()
-    return {"cases": res,
-            "search_speedup": round(tot[1][0] / tot[0][0], 3),
-            "join_speedup": round(tot[1][1] / tot[0][1], 3)}
+    same candidates are scanned).  Best of `reps` joins each; search time
+    (both search kernels) from the join's HIP events."""
+    row = {}
+    for sched in (0, 1):
+        best_s = best_t = float("inf")
+        extra = dict(schedule=1, heavy_min=-1) if sched else {}
+        for _ in range(reps):
+            _, _, st = idx.self_join(K, ids=ids, dists=dists, stream=stream, with_stats=True,
+                                     **extra)
+            best_s = min(best_s, sum(st["ms_search"]) + sum(st["ms_heavy"]))
+            best_t = min(best_t, st["ms_total"])
+        key = "persistent" if sched == 0 else "plain"
+        row[f"ms_search_{key}"] = round(best_s, 3)
+        row[f"ms_join_{key}"] = round(best_t, 3)
+    row["search_speedup"] = round(row["ms_search_plain"] / row["ms_search_persistent"], 3)
+    row["join_speedup"] = round(row["ms_join_plain"] / row["ms_join_persistent"], 3)
+    return row
 
 
-def graph_comparison(api, dev, plan, outs, stream, reps=3):
+def graph_row(idx, K, ids, dists, stream, reps=3):
     """Eager joins against replays of the join captured in a HIP graph
     (use_graph): same index, K and outputs; wall time from submit to the
     stream being drained, best of `reps` each."""
     import torch
-    res = []
-    tot_e = tot_g = 0.0
-    for name, Ks in plan:
-        idx = api.build_index(dev[name], stream=stream)
-        for K in Ks:
-            ids, dists = outs[(name, K)]
-            best = {}
-            for mode in (0, 1):
-                if mode:
-                    idx.self_join(K, ids=ids, dists=dists, stream=stream, use_graph=1)  # capture
-                b = float("inf")
+    best = {}
+    for mode in (0, 1):
+        if mode:
+            idx.self_join(K, ids=ids, dists=dists, stream=stream, use_graph=1)  # capture
+        b = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            idx.self_join(K, ids=ids, dists=dists, stream=stream, use_graph=mode)
+            torch.cuda.synchronize()
+            b = min(b, (time.perf_counter() - t0) * 1e3)
+        best[mode] = b
+    return dict(ms_eager=round(best[0], 3), ms_graph_replay=round(best[1], 3),
+                speedup=round(best[0] / best[1], 3))
+
+
+def tune_row(r):
+    return dict(w_factor=round(r["w_factor"], 4), growth=round(r["growth"], 4),
+                linear_levels=int(r["linear_levels"]), zorder=int(r["zorder"]),
+                trials=int(r["trials"]), tail_pairs=r["tail_pairs"],
+                lanes_shift=int(r["lanes_shift"]), ms_default=round(r["ms_default"], 3),
+                ms_tuned=round(r["ms_best"], 3))
+
+
+def case_summary(name, K, N, sts):
+    """Medians over the timed joins of one (dataset, K)."""
+    med = lambda key: float(np.median([key(st) for st in sts]))  # noqa: E731
+    ms = med(lambda st: st["ms_total"])
+    return dict(dataset=name, K=K, N=N, ms_join_median=round(ms, 3),
+                queries_per_s=round(N / (ms * 1e-3), 1),
+                levels=int(med(lambda st: st["levels"])),
+                fail_fraction=round(med(lambda st: st["total_failed"] /
+                                        max(1, st["total_attempted"])), 4),
+                ms_search=round(med(lambda st: sum(st["ms_search"])), 3),
+                ms_heavy=round(med(lambda st: sum(st["ms_heavy"])), 3),
+                ms_tail=round(med(lambda st: st["ms_tail"]), 3),
+                ms_level_builds=round(med(lambda st: sum(st["ms_build"])), 3))
+
+
+def extra_cases(api, stream, names, autotune, reps, sched_sets, graph_sets, host_keep):
+    """The other configurations: per (dataset, K) an untimed autotune pass and
+    a warm-up join, then `reps` timed joins (index built once, inputs and
+    outputs resident); the join median, queries/s and the search kernel's
+    roofline per configuration; persistent-vs-plain on sched_sets and
+    graph-vs-eager on graph_sets."""
+    import torch
+    from paper_1810_04758_amd import datagen
+    out, sched, graph = [], [], []
+    for wl in names:
+        desc, plan = WORKLOADS[wl]
+        recs = []
+        cases = []
+        for name, Ks in plan:
+            D, _, _ = datagen.config_points(name)
+            host_keep[name] = D
+            Dd = torch.from_numpy(D).cuda()
+            N, n = D.shape
+            idx = api.build_index(Dd, stream=stream)
+            for K in Ks:
+                ids = torch.empty((N, K), dtype=torch.int32, device="cuda")
+                dists = torch.empty((N, K), dtype=torch.float64, device="cuda")
+                tuned = tune_row(idx.autotune(K, stream=stream)) if autotune else None
+                idx.self_join(K, ids=ids, dists=dists, stream=stream)
+                sts = []
                 for _ in range(reps):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    idx.self_join(K, ids=ids, dists=dists, stream=stream, use_graph=mode)
-                    torch.cuda.synchronize()
-                    b = min(b, (time.perf_counter() - t0) * 1e3)
-                best[mode] = b
-            tot_e += best[0]
-            tot_g += best[1]
-            res.append(dict(dataset=name, K=K, ms_eager=round(best[0], 3),
-                            ms_graph_replay=round(best[1], 3),
-                            speedup=round(best[0] / best[1], 3)))
-        idx.close()
-    return {"cases": res, "speedup": round(tot_e / tot_g, 3)}
+                    _, _, st = idx.self_join(K, ids=ids, dists=dists, stream=stream,
+                                             with_stats=True)
+                    sts.append(st)
+                    recs.append((n, K, st))
+                c = case_summary(name, K, N, sts)
+                c["roofline"] = roofline_of([(n, K, st) for st in sts])
+                if tuned:
+                    c["autotune"] = tuned
+                cases.append(c)
+                if wl in sched_sets:
+                    sched.append(dict(dataset=name, K=K, **schedule_row(idx, K, ids, dists,
+                                                                        stream)))
+                if wl in graph_sets:
+                    graph.append(dict(dataset=name, K=K, **graph_row(idx, K, ids, dists, stream)))
+                del ids, dists
+            idx.close()
+            del Dd
+            torch.cuda.empty_cache()
+        out.append(dict(workload=wl, description=desc, cases=cases, roofline=roofline_of(recs)))
+    return out, sched, graph
 
 
 def main():
@@ -246,15 +355,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="expo_2m", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="clustered2d_20m", choices=sorted(WORKLOADS))
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--w-factor", type=float, default=0.0)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the (untimed) knn_autotune pass before the timed steps")
-    ap.add_argument("--serving-seconds", type=float, default=2.0,
-                    help="length of the serving trace (0 = skip the serving leg)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other configurations (extra cases)")
+    ap.add_argument("--extra-reps", type=int, default=5,
+                    help="timed joins per extra case")
+    ap.add_argument("--serving-seconds", type=float, default=60.0,
+                    help="length of the 200 requests/s serving trace (0 = skip)")
+    ap.add_argument("--serving-sustainable-seconds", type=float, default=20.0,
+                    help="length of the serving trace at the sustainable rate (0 = skip)")
+    ap.add_argument("--serving-sustainable-rate", type=float, default=8.0,
+                    help="requests/s of the sustainable serving point")
     ap.add_argument("--no-schedule-comparison", action="store_true",
                     help="skip the (untimed) persistent-vs-plain schedule comparison")
     ap.add_argument("--no-graph-comparison", action="store_true",
@@ -279,6 +396,7 @@ def main():
     torch.cuda.set_device(0)
     api.load()
     desc, plan = WORKLOADS[args.workload]
+    print(f"[bench] workload {args.workload}", file=sys.stderr, flush=True)
 
     # synthetic inputs, generated once and made resident in HBM
     host = {}
@@ -308,20 +426,15 @@ def main():
                     record.append((name, K, st))
             idx.close()
 
-    # autotuner (untimed, like a warmup): measures the level-0 cell side and
-    # the growth of the cell side per (dims, K, N) class and caches the best
+    # autotuner (untimed, like a warmup): measures the level-0 cell side, the
+    # level structure and the growth of the cell side per (dims, K, N) class
+    # and caches the best
     tuned = []
     if not args.no_autotune and not (args.lanes or args.w_factor):
         for name, Ks in plan:
             idx = api.build_index(dev[name], stream=stream)
             for K in Ks:
-                r = idx.autotune(K, stream=stream)
-                tuned.append(dict(dataset=name, K=K, w_factor=round(r["w_factor"], 3),
-                                  growth=round(r["growth"], 4),
-                                  linear_levels=int(r["linear_levels"]), trials=int(r["trials"]),
-                                  tail_pairs=r["tail_pairs"], lanes_shift=int(r["lanes_shift"]),
-                                  ms_default=round(r["ms_default"], 3),
-                                  ms_tuned=round(r["ms_best"], 3)))
+                tuned.append(dict(dataset=name, K=K, **tune_row(idx.autotune(K, stream=stream))))
             idx.close()
     if args.autotune_cache:
         if tuned:
@@ -339,6 +452,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1000.0 / args.steps
+    print(f"[bench] timed steps done: {ms_per_step:.3f} ms per step", file=sys.stderr, flush=True)
     calib = None
     if args.calibration_copy_mib > 0:
         x = torch.ones(args.calibration_copy_mib << 17, dtype=torch.float64, device="cuda")
@@ -354,54 +468,13 @@ def main():
 
     # roofline of the search kernel (dominant kernel), from HIP events recorded
     # around its launches on the join stream
-    search_ms = 0.0
-    search_launches = 0
-    bytes_total = 0
-    ops_total = 0.0
+    roof = roofline_of([(host[name].shape[1], K, st) for name, K, st in records])
+    roof["traffic"] = measured_traffic(args.workload)
     per_case = {}
     for name, K, st in records:
-        n = host[name].shape[1]
-        search_ms += sum(st["ms_search"])
-        search_launches += st["levels"]
-        bytes_total += alg_bytes(st, n, K)
-        ops_total += alg_ops(st, n)
-        c = per_case.setdefault((name, K), dict(dataset=name, K=K, ms_total=[], levels=[],
-                                                fail_fraction=[], ms_search=[], ms_build=[],
-                                                ms_heavy=[], ms_tail=[]))
-        c["ms_heavy"].append(sum(st["ms_heavy"]))
-        c["ms_tail"].append(st["ms_tail"])
-        c["ms_total"].append(st["ms_total"])
-        c["levels"].append(st["levels"])
-        c["fail_fraction"].append(st["total_failed"] / max(1, st["total_attempted"]))
-        c["ms_search"].append(sum(st["ms_search"]))
-        c["ms_build"].append(sum(st["ms_build"]))
-    achieved = bytes_total / (search_ms * 1e-3) / 1e9 if search_ms > 0 else 0.0
-    achieved_ops = ops_total / (search_ms * 1e-3) / 1e12 if search_ms > 0 else 0.0
-    # the binding roof is the one with the larger time at peak
-    alu_bound = ops_total / (ALU_PEAK_TOPS * 1e12) > bytes_total / (HBM_PEAK_GBS * 1e9)
-    hbm_roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    alu_roof = {"bound": "alu", "achieved": round(achieved_ops, 3), "peak": round(ALU_PEAK_TOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved_ops / ALU_PEAK_TOPS, 4)}
-    roof = dict(alu_roof if alu_bound else hbm_roof)
-    roof.update({"traffic": measured_traffic(args.workload), "kernel": "k_search",
-                 "alg_bytes_per_launch": round(bytes_total / max(1, search_launches)),
-                 "alg_fp64_ops_per_launch": round(ops_total / max(1, search_launches)),
-                 "avg_launch_ms": round(search_ms / max(1, search_launches), 4),
-                 "launches": search_launches,
-                 "other_roof": hbm_roof if alu_bound else alu_roof})
-    cases = []
-    for (name, K), c in per_case.items():
-        N = host[name].shape[0]
-        med = float(np.median(c["ms_total"]))
-        cases.append(dict(dataset=name, K=K, N=N, ms_join_median=round(med, 3),
-                          queries_per_s=round(N / (med * 1e-3), 1),
-                          levels=int(np.median(c["levels"])),
-                          fail_fraction=round(float(np.median(c["fail_fraction"])), 4),
-                          ms_search=round(float(np.median(c["ms_search"])), 3),
-                          ms_heavy=round(float(np.median(c["ms_heavy"])), 3),
-                          ms_tail=round(float(np.median(c["ms_tail"])), 3),
-                          ms_level_builds=round(float(np.median(c["ms_build"])), 3)))
+        per_case.setdefault((name, K), []).append(st)
+    cases = [case_summary(name, K, host[name].shape[0], sts) for (name, K), sts in
+             per_case.items()]
 
     out = {
         "metric": "KNN self-join queries/s (1 GPU)",
@@ -424,15 +497,70 @@ def main():
     }
     if calib:
         out["calibration_copy"] = calib
-    if args.schedule == 0 and not args.no_schedule_comparison:
-        out["persistent_vs_plain"] = schedule_comparison(api, dev, plan, outs, stream)
-    if not args.no_graph_comparison:
-        out["graph_vs_eager"] = graph_comparison(api, dev, plan, outs, stream)
-    if args.serving_seconds > 0:
-        out["serving"] = serving_leg(api, args.serving_seconds)
+    cmp_sched = args.schedule == 0 and not args.no_schedule_comparison
+    cmp_graph = not args.no_graph_comparison
+    sched_rows, graph_rows = [], []
+    if cmp_sched or cmp_graph:
+        for name, Ks in plan:
+            idx = api.build_index(dev[name], stream=stream)
+            for K in Ks:
+                ids, dists = outs[(name, K)]
+                if cmp_sched:
+                    sched_rows.append(dict(dataset=name, K=K,
+                                           **schedule_row(idx, K, ids, dists, stream)))
+                if cmp_graph and args.workload in ("clustered2d_20m", "unif6d_5m"):
+                    graph_rows.append(dict(dataset=name, K=K,
+                                           **graph_row(idx, K, ids, dists, stream)))
+            idx.close()
+    # the headline's device buffers are not needed past this point
+    del outs
+    dev.clear()
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        names = [w for w in EXTRA_WORKLOADS if w != args.workload]
+        print(f"[bench] extra cases {names}", file=sys.stderr, flush=True)
+        extra, s2, g2 = extra_cases(
+            api, stream, names, not args.no_autotune, args.extra_reps,
+            sched_sets={"expo_2m", "clustered2d_20m"} if cmp_sched else set(),
+            graph_sets={"unif6d_5m", "clustered2d_20m"} if cmp_graph else set(),
+            host_keep=host)
+        out["extra_cases"] = extra
+        sched_rows += s2
+        graph_rows += g2
+    if sched_rows:
+        tp = sum(r["ms_search_plain"] for r in sched_rows)
+        tq = sum(r["ms_search_persistent"] for r in sched_rows)
+        jp = sum(r["ms_join_plain"] for r in sched_rows)
+        jq = sum(r["ms_join_persistent"] for r in sched_rows)
+        out["persistent_vs_plain"] = {"cases": sched_rows, "search_speedup": round(tp / tq, 3),
+                                      "join_speedup": round(jp / jq, 3)}
+    if graph_rows:
+        te = sum(r["ms_eager"] for r in graph_rows)
+        tg = sum(r["ms_graph_replay"] for r in graph_rows)
+        out["graph_vs_eager"] = {"cases": graph_rows, "speedup": round(te / tg, 3)}
+    if args.serving_seconds > 0 or args.serving_sustainable_seconds > 0:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serving"] = serving(api, args.serving_seconds, args.serving_sustainable_seconds,
+                                 args.serving_sustainable_rate)
     if not args.no_cpu_baseline:
-        flat = [(name, K) for name, Ks in plan for K in Ks]
-        out["cpu_baseline"] = cpu_baseline(host, flat)
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        cfgs = [(name, host[name], K) for name, Ks in plan for K in Ks]
+        for wl in (EXTRA_WORKLOADS if not args.no_extra else []):
+            if wl == args.workload:
+                continue
+            for name, Ks in WORKLOADS[wl][1]:
+                cfgs += [(name, host[name], K) for K in Ks[:1]]
+        per = cpu_baseline(cfgs)
+        head = per[0]["all_cores"]
+        out["cpu_baseline"] = {
+            "value": head["value"], "unit": "queries/s", "cores": head["cores"],
+            "kind": "oracle",
+            "sample": (f"brute-force oracle (the definition, OpenMP over queries) on "
+                       f"{head['sample_queries']} random rows of {per[0]['config']} at "
+                       f"K={per[0]['K']} ({head['wall_s']} s wall); single core: "
+                       f"{per[0]['single_core']['value']} queries/s on "
+                       f"{per[0]['single_core']['sample_queries']} rows"),
+            "per_config": per}
     print(json.dumps(out), flush=True)
 
 
