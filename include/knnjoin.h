@@ -261,7 +261,12 @@ int knn_index_info_get(const knn_index* idx, knn_index_info* out);
  *   mean_sample  host, up to KNN_MAX_MEAN_SAMPLE entries: ids of the eps_mean
  *                sample, increasing; their number goes to *n_mean.
  *   counts       host, knn_index_info.n_bins entries: distances per bin (not
- *                cumulative), bin b = [b, b+1) * bin_width.
+ *                cumulative), bin b = [b, b+1) * bin_width.  eps_min(K) for
+ *                any K <= KNN_MAX_K reads only the bins up to the first one
+ *                whose cumulative count reaches KNN_MAX_K per sample point;
+ *                the counts are exact up to that bin (or a few bins beyond
+ *                it) and 0 after it (all bins are exact when no bin reaches
+ *                it).
  *   bin_width    eps_mean / n_bins.
  * How the samples are drawn (so that they can be reproduced): SplitMix64
  * (Steele, Lea, Flood, OOPSLA 2014) outputs reduced modulo N, repeats

@@ -67,13 +67,16 @@ __device__ __forceinline__ int dist_bin(double d2, double inv_bw, float inv_bw_f
   return (int)floor(sqrt(d2) * inv_bw);
 }
 
-// Each thread takes points j; the sample points of a chunk sit in LDS.  The
+// Each thread takes points p = i * pstride (every point when pstride = 1);
+// the sample points of a chunk sit in LDS.  Only bins below count_bins are
+// counted (pairs certainly beyond them skip the bin arithmetic).  The
 // per-block histogram is accumulated in LDS (uint32) and added to the global
 // uint64 counts at the end.
 template <int DIM>
-__global__ void k_dist_histogram(const double* __restrict__ X, int64_t N,
+__global__ void k_dist_histogram(const double* __restrict__ X, int64_t N, int64_t pstride,
                                  const int64_t* __restrict__ sample, int64_t ns, double inv_bw,
-                                 int n_bins, double skip_d2, uint64_t* __restrict__ counts) {
+                                 int count_bins, double skip_d2, uint64_t* __restrict__ counts) {
+  const int n_bins = count_bins;
   __shared__ uint32_t h[kMaxBins];
   const float inv_bw_f = (float)inv_bw;
   const bool use_f = inv_bw >= 0x1p-60 && inv_bw <= 0x1p60;
@@ -90,8 +93,8 @@ __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N,
       for (int j = 0; j < DIM; ++j) sx[j][i] = X[(int64_t)j * N + id];
     }
     __syncthreads();
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
-         p += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t p = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * pstride; p < N;
+         p += (int64_t)gridDim.x * blockDim.x * pstride) {
       double x[DIM];
 #pragma unroll
       for (int j = 0; j < DIM; ++j) x[j] = X[(int64_t)j * N + p];
@@ -126,21 +129,23 @@ int launch_sample_pair_sums(const double* X, int64_t N, int n, const int64_t* sa
 
 void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sample,
                            int64_t ns, double inv_bw, int n_bins, uint64_t* counts,
-                           hipStream_t s) {
+                           hipStream_t s, int count_bins, int64_t pstride) {
   KNN_CHECK(n_bins >= 1 && n_bins <= kMaxBins, KNN_EINVAL, "n_bins must be in [1, 4096]");
+  if (count_bins <= 0 || count_bins > n_bins) count_bins = n_bins;
+  KNN_CHECK(pstride >= 1, KNN_EINTERNAL, "histogram point stride must be >= 1");
   launch_zero(counts, n_bins * sizeof(uint64_t), s);
   if (ns <= 0 || N <= 0) return;
-  // distances whose bin is certainly >= n_bins skip the square root
-  double lim = (double)n_bins / inv_bw;
+  // distances whose bin is certainly >= count_bins skip the square root
+  double lim = (double)count_bins / inv_bw;
   double skip_d2 = lim * lim * 1.0001 + 1e-300;
-  int64_t want = ceil_div(N, kBlock);
+  int64_t want = ceil_div(ceil_div(N, pstride), kBlock);
   int nb = (int)(want < 2048 ? want : 2048);
   switch (n) {
-    case 2: k_dist_histogram<2><<<nb, kBlock, 0, s>>>(X, N, sample, ns, inv_bw, n_bins, skip_d2, counts); break;
-    case 3: k_dist_histogram<3><<<nb, kBlock, 0, s>>>(X, N, sample, ns, inv_bw, n_bins, skip_d2, counts); break;
-    case 4: k_dist_histogram<4><<<nb, kBlock, 0, s>>>(X, N, sample, ns, inv_bw, n_bins, skip_d2, counts); break;
-    case 5: k_dist_histogram<5><<<nb, kBlock, 0, s>>>(X, N, sample, ns, inv_bw, n_bins, skip_d2, counts); break;
-    case 6: k_dist_histogram<6><<<nb, kBlock, 0, s>>>(X, N, sample, ns, inv_bw, n_bins, skip_d2, counts); break;
+    case 2: k_dist_histogram<2><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, counts); break;
+    case 3: k_dist_histogram<3><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, counts); break;
+    case 4: k_dist_histogram<4><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, counts); break;
+    case 5: k_dist_histogram<5><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, counts); break;
+    case 6: k_dist_histogram<6><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, counts); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
   KNN_LAUNCHED();

@@ -1209,20 +1209,53 @@ knn_index* build_from_device(const double* D_dev, int64_t N, int n, const knn_bu
     idx->n_bins = o.n_bins;
     idx->n_sample = (int)sh.size();
     idx->bin_width = eps_mean / o.n_bins;
+    // eps_min(K) reads the cumulative histogram only up to the first bin
+    // where it reaches K per sample point, so for every K <= KNN_MAX_K only
+    // the bins up to where it reaches KNN_MAX_K per sample point matter.
+    // That bin is estimated on every pstride-th point (with a margin of 4),
+    // the bins below it are counted exactly over all points (the far pairs,
+    // most of them, skip the bin arithmetic), and all bins are counted when
+    // the estimate fell short.
+    const int64_t ns = (int64_t)sh.size();
+    const double inv_bw = 1.0 / idx->bin_width;
+    const uint64_t need = (uint64_t)KNN_MAX_K * (uint64_t)ns;
     DevBuf<uint64_t> counts(o.n_bins);
-    launch_dist_histogram(idx->X.p, N, n, d_sh.p, (int64_t)sh.size(), 1.0 / idx->bin_width,
-                          o.n_bins, counts.p, s);
     std::vector<uint64_t> hc(o.n_bins);
-    KNN_HIP(hipMemcpyAsync(hc.data(), counts.p, o.n_bins * 8, hipMemcpyDeviceToHost, s));
-    KNN_HIP(hipStreamSynchronize(s));
+    auto histogram = [&](int count_bins, int64_t pstride) {
+      launch_dist_histogram(idx->X.p, N, n, d_sh.p, ns, inv_bw, o.n_bins, counts.p, s,
+                            count_bins, pstride);
+      KNN_HIP(hipMemcpyAsync(hc.data(), counts.p, o.n_bins * 8, hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));
+    };
+    int count_bins = o.n_bins;
+    const int64_t pstride = N / (int64_t)262144;
+    if (pstride >= 8) {
+      histogram(o.n_bins, pstride);
+      uint64_t c = 0;
+      for (int b = 0; b < o.n_bins; ++b) {
+        c += hc[b] * (uint64_t)pstride;
+        if (c >= 4 * need) {
+          count_bins = b + 1;
+          break;
+        }
+      }
+    }
+    histogram(count_bins, 1);
+    auto cumulate = [&] {
+      idx->cum.assign(o.n_bins, 0);
+      uint64_t c = 0;
+      for (int b = 0; b < o.n_bins; ++b) {
+        c += hc[b];
+        idx->cum[b] = c;
+      }
+    };
+    cumulate();
+    if (count_bins < o.n_bins && idx->cum[count_bins - 1] < need) {
+      histogram(o.n_bins, 1);
+      cumulate();
+    }
     idx->hist_sample = sh;
     idx->mean_sample = sm;
-    idx->cum.resize(o.n_bins);
-    uint64_t c = 0;
-    for (int b = 0; b < o.n_bins; ++b) {
-      c += hc[b];
-      idx->cum[b] = c;
-    }
     return idx;
   } catch (...) {
     delete idx;

@@ -25,7 +25,9 @@ struct knn_index {
   double bin_width = 0;
   int n_bins = 0;
   int n_sample = 0;
-  std::vector<uint64_t> cum;  // cumulative histogram counts
+  // cumulative histogram counts, exact up to the first bin where they reach
+  // KNN_MAX_K per sample point (later bins are not counted)
+  std::vector<uint64_t> cum;
   std::vector<int64_t> hist_sample;  // ids of the histogram's sample points
   std::vector<int64_t> mean_sample;  // ids of the eps_mean sample
   std::atomic<int> busy{0};

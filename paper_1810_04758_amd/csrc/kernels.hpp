@@ -184,9 +184,13 @@ void launch_zero(void* p, size_t bytes, hipStream_t s);
 // rows; returns the number of partials written to part (host reads them).
 int launch_sample_pair_sums(const double* X, int64_t N, int n, const int64_t* sample,
                             int64_t ns, double* part, hipStream_t s);
+// Histogram of the distances from the sample points to the points p =
+// 0, pstride, 2 pstride, ... of X (all points when pstride = 1), bins of width
+// 1/inv_bw; only the first count_bins bins are counted (the rest stay 0;
+// count_bins <= 0: all n_bins).
 void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sample,
                            int64_t ns, double inv_bw, int n_bins, uint64_t* counts,
-                           hipStream_t s);
+                           hipStream_t s, int count_bins = 0, int64_t pstride = 1);
 
 // ---- search (search.hip) ----
 struct SearchArgs {

@@ -278,6 +278,9 @@ def test_sampling_kernels_match_oracle(knn, oracle_mod, scale):
     ("clustered", lambda: datagen.clustered(400_000, seed=63), 77),
     ("unif4d", lambda: datagen.uniform(100_000, 4, seed=64), 5),
     ("small_fallback", lambda: datagen.uniform(1100, 2, seed=65), 9),
+    # large enough for the histogram's estimate on a point subset: bins are
+    # counted only up to about where K = 1024 is reached
+    ("clustered_2m", lambda: datagen.clustered(2_200_000, seed=66), 3),
 ])
 def test_eps_min_chain_matches_oracle(knn, oracle_mod, name, gen, seed):
     """The whole Sec. 4.4 chain of an index against the oracle's own: sample
@@ -302,14 +305,55 @@ def test_eps_min_chain_matches_oracle(knn, oracle_mod, name, gen, seed):
     assert abs(info["eps_mean"] - eps_ref) <= tol * eps_ref
     bw_ref = eps_ref / 1000
     counts_ref = oracle_mod.dist_histogram(D, ref_hist_ids, 1.0 / bw_ref, 1000)
-    assert (smp["counts"] == counts_ref).all()
-    Ks = (1, 8, 32, 64) if N > 2000 else (1, 8, 1024)
+    # exact up to at least the first bin where the cumulative count reaches
+    # KNN_MAX_K = 1024 per sample point (all that any eps_min(K) reads), not
+    # counted (0) after the first difference
+    diff = np.nonzero(smp["counts"] != counts_ref)[0]
+    if diff.size:
+        first = diff[0]
+        assert (smp["counts"][first:] == 0).all()
+        assert first > 0 and np.cumsum(counts_ref)[first - 1] >= 1024 * ref_hist_ids.shape[0]
+    Ks = (1, 8, 32, 64, 1024) if N > 2000 else (1, 8, 1024)
     for K in Ks:
         e_ref = oracle_mod.eps_min(counts_ref, bw_ref, ref_hist_ids.shape[0], K)
         assert abs(idx.eps_min(K) - e_ref) <= 2 * tol * e_ref, K
     if N <= 2000:
         assert idx.eps_min(1024) == info["eps_mean"] or abs(
             idx.eps_min(1024) - info["eps_mean"]) <= 4 * 2.0 ** -53 * info["eps_mean"]
+    idx.close()
+
+
+def test_histogram_estimate_fallback(knn, oracle_mod):
+    """The index's histogram estimates, on every 8th point, the bin where the
+    cumulative count reaches KNN_MAX_K = 1024 per sample point and counts
+    exactly only up to it; when the exact counts then fall short, every bin
+    is counted.  Built to fall short: the 500 sample points (their ids are
+    known from the seed) and 520 more points, all at multiples of 8, sit in a
+    unit square, the rest of the 2.1e6 points some 1000 units away.  The
+    subset then sees 8 x its share of the close pairs (an estimate of about
+    2.3e6 >= 4 x 512000), the exact count is about 509500 < 512000, so the
+    whole histogram must come out, equal to the oracle's."""
+    N = 2_100_000
+    seed = 11
+    hist_ids = oracle_mod.sample_ids(N, 500, seed ^ 0x5DEECE66D)
+    rng = np.random.default_rng(12)
+    D = rng.uniform(1000.0, 2000.0, size=(N, 2))
+    near = np.setdiff1d(np.arange(0, N, 8), hist_ids)[:520]
+    close = np.concatenate([hist_ids, near])
+    D[close] = rng.uniform(0.0, 1.0, size=(close.shape[0], 2))
+    _say(f"[histogram fallback] N={N}")
+    idx = knn.build_index(D, seed=seed)
+    smp = idx.sampling()
+    info = idx.info()
+    assert (smp["hist_sample"] == hist_ids).all()
+    counts_ref = oracle_mod.dist_histogram(D, hist_ids, 1.0 / smp["bin_width"], 1000)
+    c = np.cumsum(counts_ref)
+    assert c[-1] < 1024 * 500 or (c >= 1024 * 500).argmax() > 2  # the estimate falls short
+    assert (smp["counts"] == counts_ref).all()
+    for K in (1, 64, 1024):
+        e_ref = oracle_mod.eps_min(counts_ref, smp["bin_width"], 500, K)
+        assert idx.eps_min(K) == e_ref, K
+    assert info["n_bins"] == 1000
     idx.close()
 
 
