@@ -423,9 +423,9 @@ k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int64_t nb, int shift
 
 // Active list in one pass: the sorted positions whose point failed, in order.
 __global__ void __launch_bounds__(kBlock)
-k_active_list(const uint8_t* __restrict__ failed, uint8_t tag, const int32_t* __restrict__ perm,
-              int64_t N, int64_t nb, int32_t* __restrict__ out, uint32_t* __restrict__ count,
-              uint32_t* __restrict__ state) {
+k_active_list(const uint8_t* __restrict__ failed, uint8_t tag, bool at_least,
+              const int32_t* __restrict__ perm, int64_t N, int64_t nb, int32_t* __restrict__ out,
+              uint32_t* __restrict__ count, uint32_t* __restrict__ state) {
   const LbTile lt = lb_take_tile(state, nb);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -435,7 +435,8 @@ k_active_list(const uint8_t* __restrict__ failed, uint8_t tag, const int32_t* __
 #pragma unroll
   for (int r = 0; r < kCtRounds; ++r) {
     const int64_t p = wbase + r * 64 + lane;
-    m[r] = __ballot(p < N && failed[perm ? perm[p] : (int32_t)p] == tag);
+    const uint8_t f = p < N ? failed[perm ? perm[p] : (int32_t)p] : (uint8_t)0;
+    m[r] = __ballot(p < N && (at_least ? (f >= tag) : (f == tag)));
     cnt += (uint32_t)__popcll(m[r]);
   }
   uint32_t total;
@@ -1055,14 +1056,15 @@ void launch_neighbor_ranges_z(const uint32_t* cell_start, const uint64_t* cell_k
 
 void launch_active_list(const uint8_t* failed, uint8_t tag, const int32_t* perm, int64_t N,
                         int32_t* out, uint32_t* count, uint32_t* state, int64_t state_elems,
-                        hipStream_t s) {
+                        hipStream_t s, bool at_least) {
   if (N <= 0) {
     launch_zero(count, sizeof(uint32_t), s);
     return;
   }
   const int64_t nb = ceil_div(N, kCtTile);
   KNN_CHECK(4 + 2 * nb <= state_elems, KNN_EINTERNAL, "scan state too small");
-  k_active_list<<<(unsigned)nb, kBlock, 0, s>>>(failed, tag, perm, N, nb, out, count, state);
+  k_active_list<<<(unsigned)nb, kBlock, 0, s>>>(failed, tag, at_least, perm, N, nb, out, count,
+                                                state);
   KNN_LAUNCHED();
 }
 

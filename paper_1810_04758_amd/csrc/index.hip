@@ -207,7 +207,7 @@ int64_t JoinContext::device_bytes() const {
                    ivals2.bytes() + out_ids.bytes() + out_d.bytes() + tail_scratch.bytes() +
                    heavy.bytes() + cell_active.bytes() + rowtab.bytes() +
                    Xs2.bytes() + perm2.bytes() + pos.bytes() + active2.bytes() +
-                   scan_state.bytes());
+                   scan_state.bytes() + pending.bytes());
 }
 
 double eps_min_of(const knn_index& idx, int32_t K) {
@@ -377,7 +377,7 @@ int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_
     if (Mcap_known > 0) {
       Mcap = Mcap_known;
     } else {
-      c.pinned.reserve(kCounterInts + 16);
+      c.pinned.reserve(kCounterInts + 16 + KNN_MAX_LEVELS);
       KNN_HIP(hipMemcpyAsync(c.pinned.p, c.scal.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));
       Mcap = std::max<int64_t>((uint32_t)c.pinned.p[0], 1);
@@ -471,6 +471,7 @@ void for_each_join_buffer(const knn_index& idx, JoinContext& c, int32_t K,
   f(c.scan_state, (int64_t)scan_state_elems(N));
   f(c.scal, 4);
   f(c.iscal, kCounterInts);
+  f(c.pending, KNN_MAX_LEVELS);
   f(c.active, N);
   f(c.active2, N);
   f(c.fail_list, N);
@@ -590,7 +591,8 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   const int ncu = cu_count(c.device);
 
   Events ev(st != nullptr);
-  int64_t A = N;  // active queries
+  int64_t A = N;          // active queries of the level
+  int64_t remaining = N;  // queries not solved yet
   for (int level = 0;; ++level) {
     if (level >= KNN_MAX_LEVELS - 1) w = std::max(w, 2.0 * ext + 1.0);  // everything in one block
     const LevelPlan* rp = nullptr;
@@ -600,18 +602,37 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     }
     LevelPlan lp;
     // brute-force tail once few queries remain (their ids are in fail_list)
+    // (remaining: the queries left, A of them active at this level; Z-order
+    // levels may hold more, deferred to later levels)
     const bool tail = rp ? rp->tail
-                         : (level > 0 && tail_budget > 0 && A <= 65535 &&
-                            (double)A * (double)N <= tail_budget);
+                         : (level > 0 && tail_budget > 0 && remaining <= 65535 &&
+                            (double)remaining * (double)N <= tail_budget);
     if (tail) {
       ev.rec(0, s);
       TailArgs ta{};
       ta.X = idx.X.p;
       ta.N = N;
       ta.n = idx.n;
-      // Z-order levels list failures by sorted position: the tail takes ids
-      if (zl) launch_pos_to_id(c.fail_list.p, A, c.perm.p, s);
-      ta.q_ids = c.fail_list.p;
+      if (rp) remaining = rp->A;
+      if (zl) {
+        // every query left is flagged with this level or a later one: list
+        // them (sorted positions) and take their ids
+        launch_active_list(c.failed.p, level_tag(level), nullptr, N, c.active.p, c.scal.p + 1,
+                           c.scan_state.p, (int64_t)c.scan_state.n, s, true);
+        if (!rp) {  // the flags must account for exactly the queries left
+          c.pinned.reserve(kCounterInts + 16 + KNN_MAX_LEVELS);
+          KNN_HIP(hipMemcpyAsync(c.pinned.p, c.scal.p + 1, sizeof(uint32_t),
+                                 hipMemcpyDeviceToHost, s));
+          KNN_HIP(hipStreamSynchronize(s));
+          KNN_CHECK((int64_t)(uint32_t)c.pinned.p[0] == remaining, KNN_EINTERNAL,
+                    "tail: the flagged queries differ from the count left");
+        }
+        launch_pos_to_id(c.active.p, remaining, c.perm.p, s);
+        ta.q_ids = c.active.p;
+      } else {
+        ta.q_ids = c.fail_list.p;
+      }
+      A = remaining;
       ta.A = (int32_t)A;
       const double top_ref = std::max(diag2, 1e-290);
       uint64_t tb;
@@ -658,6 +679,14 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
                          c.scal.p + 1, c.scan_state.p, (int64_t)c.scan_state.n, s);
       active = c.active.p;
     }
+    // Z-order levels: deferred queries are flagged straight for later levels,
+    // so the flags and the per-level pending counts start clean here
+    if (zl && level == 0) {
+      c.pending.reserve(KNN_MAX_LEVELS);
+      launch_zero(c.failed.p, (size_t)N, s);
+      launch_zero(c.cell_active.p, (size_t)N, s);
+      launch_zero(c.pending.p, KNN_MAX_LEVELS * sizeof(uint32_t), s);
+    }
     // the level's counters start here: the deferral filters append to the
     // failure list
     const int64_t A_in = A;
@@ -684,6 +713,12 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       da.fail_list = c.fail_list.p;
       da.fail_count = c.iscal.p + kFailSlot;
       da.fail_pos = zl ? 1 : 0;
+      if (zl) {  // skip ahead to the level the prediction asks for
+        da.failed = c.failed.p;
+        da.pending = c.pending.p;
+        da.level = level;
+        da.top_level = c.gz0.zbits;
+      }
       da.cand_sum = reinterpret_cast<unsigned long long*>(c.iscal.p + kCandSumSlot);
       da.state = c.scan_state.p;
       da.state_elems = (int64_t)c.scan_state.n;
@@ -709,16 +744,15 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       n_pre = c.scal.p + 3;
     }
     if (level > 0 || n_pre) {
-      // neighbour ranges only for the cells that hold an active query; the
-      // flags are stale garbage before level 1 clears them, so level 0 clears
-      // its own first
-      if (level == 0) launch_zero(c.cell_active.p, (size_t)N, s);
-      const uint8_t tag = level == 0 ? (uint8_t)1 : level_tag(level);
+      // neighbour ranges only for the cells that hold an active query (level
+      // 0 of Z-order levels, whose flag array was just cleared, marks with a
+      // tag no later level uses)
+      const uint8_t tag = level == 0 ? (uint8_t)0xFF : level_tag(level);
       launch_mark_cells_of(active, A, c.cell_of.p, c.cell_active.p, tag, s, n_pre);
       cell_active = c.cell_active.p;
     }
     lp.Mcap = build_ranges(idx, c, s, rp ? rp->Mcap : 0, cell_active,
-                           level == 0 ? (uint8_t)1 : level_tag(level));
+                           level == 0 ? (uint8_t)0xFF : level_tag(level));
     if (filt) {
       // the deferral filter on the block density (candidate counts)
       int32_t* out = n_pre ? c.active.p : (c.active2.reserve(N), c.active2.p);
@@ -740,7 +774,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     } else {
       uint64_t* csum = reinterpret_cast<uint64_t*>(c.iscal.p + kCandSumSlot);
       if (!filt) launch_active_cand_sum(active, A, c.cell_of.p, c.cand_count.p, csum, s);
-      c.pinned.reserve(kCounterInts + 16);
+      c.pinned.reserve(kCounterInts + 16 + KNN_MAX_LEVELS);
       int32_t* hp = c.pinned.p;
       KNN_HIP(hipMemcpyAsync(hp, csum, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipMemcpyAsync(hp + 4, c.scal.p, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -898,7 +932,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       hf = rp->heavy_failed;
       hc = rp->heavy_cand;
     } else {
-      c.pinned.reserve(kCounterInts + 16);
+      c.pinned.reserve(kCounterInts + 16 + KNN_MAX_LEVELS);
       int32_t* cnt = c.pinned.p;
       KNN_HIP(hipMemcpyAsync(cnt, c.iscal.p, kCounterInts * sizeof(int32_t), hipMemcpyDeviceToHost,
                              s));
@@ -906,6 +940,9 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       // (must stay 0), in the same round trip
       KNN_HIP(hipMemcpyAsync(cnt + kCounterInts, c.scan_state.p + 2, sizeof(uint32_t),
                              hipMemcpyDeviceToHost, s));
+      if (zl)  // queries flagged for each later level
+        KNN_HIP(hipMemcpyAsync(cnt + kCounterInts + 16, c.pending.p,
+                               KNN_MAX_LEVELS * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));
       if (cnt[kCounterInts] != 0) {
         // cleared, so that later joins on this context start clean
@@ -926,6 +963,21 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       hc = (double)hcu;
     }
     const int32_t fails = sc[0];
+    // the next level's active queries: this level's search failures and, on
+    // Z-order levels, the queries flagged for it by earlier deferrals; the
+    // queries left: those and every later level's
+    int64_t A_next = fails;
+    if (rp) {
+      remaining = rp->remaining;
+      if (level + 1 < (int)replay->size()) A_next = (*replay)[level + 1].A;
+    } else {
+      remaining = fails;
+      if (zl) {
+        const uint32_t* pend = reinterpret_cast<const uint32_t*>(c.pinned.p + kCounterInts + 16);
+        for (int L = level + 1; L < KNN_MAX_LEVELS; ++L) remaining += pend[L];
+        if (level + 1 < KNN_MAX_LEVELS) A_next += pend[level + 1];
+      }
+    }
     if (record) {
       lp.A = A_in;
       lp.A_kept = A;
@@ -941,6 +993,8 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       lp.heavy_cand = hc;
       lp.M = c.M;
       lp.cell_w = 1.0 / c.gg.inv_w;
+      lp.remaining = remaining;
+      lp.failed_stat = fails + (zl ? deferred : 0);
       record->push_back(lp);
     }
     if (st && level < KNN_MAX_LEVELS) {
@@ -953,7 +1007,9 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       st->levels = level + 1;
       st->cell_width[level] = 1.0 / c.gg.inv_w;
       st->attempted[level] = A_in;
-      st->failed[level] = fails;
+      // deferred queries count as failed (Z-order levels flag them without
+      // the failure list)
+      st->failed[level] = fails + (zl ? deferred : 0);
       st->cells[level] = c.M;
       st->ms_build[level] = elapsed_ms(ev.e[0], ev.e[1]);
       st->ms_heavy[level] = elapsed_ms(ev.e[1], ev.e[3]);
@@ -962,19 +1018,19 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       st->heavy_failed[level] = hf;
       st->heavy_cand[level] = hc;
       st->total_attempted += A_in;
-      st->total_failed += fails;
+      st->total_failed += fails + (zl ? deferred : 0);
     }
-    if (fails == 0) break;
+    if (remaining == 0) break;
     KNN_CHECK(fails <= A_in, KNN_EINTERNAL, "more failures than attempted queries");
     // failures are re-queued on a grid with a larger cell side (Alg. 1):
     // linear growth by eps_step * w0 first, then geometric growth
-    if (level_tag(level + 1) == 1) {  // tags wrapped: clear the stale ones
+    if (!zl && level_tag(level + 1) == 1) {  // tags wrapped: clear the stale ones
       launch_zero(c.failed.p, (size_t)N, s);
       launch_zero(c.cell_active.p, (size_t)N, s);
     }
     launch_mark_failed(c.fail_list.p, c.iscal.p + kFailSlot, fails, c.failed.p,
                        level_tag(level + 1), s);
-    A = fails;
+    A = A_next;
     w = (1.0 / c.gg.inv_w);
     if (level < linear)
       w = w + step;
@@ -1031,10 +1087,10 @@ void stats_from_plan(const GraphPlan& gp, knn_join_stats* st) {
     st->heavy_cand[L] = lp.heavy_cand;
     st->cell_width[L] = lp.cell_w;
     st->attempted[L] = lp.A;
-    st->failed[L] = lp.fails;
+    st->failed[L] = lp.failed_stat;
     st->cells[L] = lp.M;
     st->total_attempted += lp.A;
-    st->total_failed += lp.fails;
+    st->total_failed += lp.failed_stat;
     st->levels = ++L;
   }
 }

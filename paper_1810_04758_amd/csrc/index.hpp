@@ -49,6 +49,7 @@ struct JoinContext {
   DevBuf<double> Xs, Xs2;      // sorted points (Xs2: the other of a level pair)
   DevBuf<int32_t> perm, perm2;  // sorted position -> id
   DevBuf<int32_t> pos;          // sort values of a level sorted from the previous one
+  DevBuf<uint32_t> pending;     // Z-order levels: queries flagged for each later level
   DevBuf<uint32_t> cell_of;
   DevBuf<uint64_t> cell_key;
   DevBuf<uint32_t> cell_start;
@@ -89,7 +90,7 @@ struct JoinContext {
   int64_t device_bytes() const;
 };
 // Device buffers of a JoinContext (the DevBuf members above).
-constexpr int kContextBuffers = 35;
+constexpr int kContextBuffers = 36;
 
 // What one level of a join did, recorded by an eager run so that the same
 // launch sequence can be issued again without host round trips (a join on the
@@ -117,6 +118,8 @@ struct LevelPlan {
   double heavy_cand = 0;
   int64_t M = 0;
   double cell_w = 0;
+  int64_t remaining = 0;  // queries left after the level (its failures and the deferred)
+  int64_t failed_stat = 0;  // failed queries as the statistics count them (deferred included)
 };
 
 // A join captured in a HIP graph with the scratch it writes (its own context,

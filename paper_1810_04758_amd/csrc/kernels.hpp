@@ -171,11 +171,11 @@ void launch_heavy_list(const int32_t* active /*nullable*/, int64_t n_active,
 void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count,
                         int64_t max_fail, uint8_t* failed, uint8_t tag, hipStream_t s);
 // out = the sorted positions p with failed[perm[p]] == tag (perm NULL:
-// failed[p] == tag), in order; their
+// failed[p] == tag; at_least: >= tag instead of ==), in order; their
 // number to *count (device).  One pass (scan state as launch_exclusive_scan).
 void launch_active_list(const uint8_t* failed, uint8_t tag, const int32_t* perm, int64_t N,
                         int32_t* out, uint32_t* count, uint32_t* state, int64_t state_elems,
-                        hipStream_t s);
+                        hipStream_t s, bool at_least = false);
 // Zeroes `bytes` bytes at p (4-byte aligned) with a kernel, not a memset node.
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
@@ -254,6 +254,14 @@ struct DeferArgs {
   const uint32_t* cell_start;
   const uint32_t* d_M;
   int32_t fail_pos;           // deferred queries listed by sorted position (else id)
+  // Z-order levels: with failed set, a deferred query is not listed but
+  // flagged for the first level whose cell side could hold its predicted
+  // K-th distance (1.5 times the side at least covers that distance):
+  // failed[q] = that level (at most top_level) and pending[that level] += 1
+  uint8_t* failed;
+  uint32_t* pending;
+  int32_t level;
+  int32_t top_level;
   double lo[kMaxDims];
   double inv_w;
   double w;

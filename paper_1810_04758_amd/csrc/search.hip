@@ -856,6 +856,9 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
   __shared__ uint32_t s_excl, s_fbase;
   __shared__ uint32_t s_wk[4], s_wd[4];
   __shared__ unsigned long long s_sum[4], s_max[4];
+  __shared__ uint32_t s_pend[KNN_MAX_LEVELS];  // deferrals per target level (skip-ahead)
+  if (a.failed)
+    for (int i = threadIdx.x; i < KNN_MAX_LEVELS; i += blockDim.x) s_pend[i] = 0;
   const LbTile lt = lb_take_tile(a.state, nb);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -902,7 +905,18 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
         if (c > 1 || c < a.g[j] - 2) full = false;
       }
       const double r = (1.0 + mfrac) * a.w * (1.0 - a.margin);
-      defer = !full && Cq > 0 && a.defer_coef * (double)powf((float)Cq, -2.0f / DIM) > r * r;
+      const double pd = Cq > 0 ? a.defer_coef * (double)powf((float)Cq, -2.0f / DIM) : 0.0;
+      defer = !full && Cq > 0 && pd > r * r;
+      if (defer && a.failed) {
+        // skip ahead: the first level L' > level with 1.5 w 2^(L' - level)
+        // >= sqrt(pd), the smallest side at which the query could succeed
+        const float ratio = (float)(sqrt(pd) / (1.5 * a.w));
+        int jump = ratio > 2.0f ? (int)ceilf(log2f(ratio)) : 1;
+        jump = max(jump, 1);
+        const int target = min(a.level + jump, a.top_level);
+        a.failed[q] = (uint8_t)target;
+        atomicAdd(&s_pend[target], 1u);
+      }
     }
     mk[k] = __ballot(in && !defer);
     md[k] = __ballot(in && defer);
@@ -928,14 +942,15 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
     agg += s_wk[i];
     dagg += s_wd[i];
   }
-  if (threadIdx.x == 0) s_fbase = dagg ? (uint32_t)atomicAdd(a.fail_count, (int32_t)dagg) : 0u;
+  if (threadIdx.x == 0)
+    s_fbase = dagg && !a.failed ? (uint32_t)atomicAdd(a.fail_count, (int32_t)dagg) : 0u;
   const uint32_t excl = lb_tile_prefix(a.state, lt, agg, &s_excl);  // (a barrier)
   if (threadIdx.x == 0 && lt.tile == nb - 1) *a.out_count = excl + agg;
   uint32_t o = excl + bk, f = s_fbase + bd;
 #pragma unroll
   for (int k = 0; k < kDeferRounds; ++k) {
     if ((mk[k] >> lane) & 1ull) a.out_active[o + (uint32_t)__popcll(mk[k] & lt_mask)] = qk[k];
-    if ((md[k] >> lane) & 1ull)
+    if (((md[k] >> lane) & 1ull) && !a.failed)
       a.fail_list[f + (uint32_t)__popcll(md[k] & lt_mask)] = a.fail_pos ? qk[k] : a.perm[qk[k]];
     o += (uint32_t)__popcll(mk[k]);
     f += (uint32_t)__popcll(md[k]);
@@ -952,6 +967,9 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
     s_max[w] = cmax;
   }
   __syncthreads();
+  if (a.failed)
+    for (int i = threadIdx.x; i < KNN_MAX_LEVELS; i += blockDim.x)
+      if (s_pend[i]) atomicAdd(&a.pending[i], s_pend[i]);
   if (threadIdx.x == 0) {
     unsigned long long ts = 0, tm = 0;
     for (int i = 0; i < 4; ++i) {
