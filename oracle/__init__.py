@@ -40,6 +40,8 @@ def lib():
         L.oracle_knn.restype = ctypes.c_int
         L.oracle_knn_kdtree.argtypes = [P, i64, i32, i32, P, i64, P, P, i32]
         L.oracle_knn_kdtree.restype = ctypes.c_int
+        L.oracle_knn_rs.argtypes = [P, i64, P, i64, i32, i32, P, i64, P, P, i32]
+        L.oracle_knn_rs.restype = ctypes.c_int
         L.oracle_sq_dist.argtypes = [P, i32, i64, i64]
         L.oracle_sq_dist.restype = f64
         L.oracle_bounds.argtypes = [P, i64, i32, P, P]
@@ -111,6 +113,31 @@ def knn_kdtree(D, K, rows=None, threads=0):
     rc = lib().oracle_knn_kdtree(_p(D), N, n, K, rp, nrows, _p(ids), _p(dists), threads)
     if rc != 0:
         raise ValueError("oracle_knn_kdtree: invalid arguments")
+    return ids, dists
+
+
+def knn_rs(S, Q, K, rows=None, threads=0):
+    """KNN join of two sets (Sec. 2.1, R join S): for each row of Q (or the
+    given rows of Q) its K nearest points of S by (d^2, S id), nothing
+    excluded.  Returns (ids int32 [nrows, K] of S, dists float64)."""
+    S = _f64(S)
+    Q = _f64(Q)
+    if S.shape[1] != Q.shape[1]:
+        raise ValueError("S and Q must have the same dimension")
+    NQ, n = Q.shape
+    if rows is None:
+        nrows = NQ
+        rp = None
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        nrows = rows.shape[0]
+        rp = _p(rows)
+    ids = np.empty((nrows, K), dtype=np.int32)
+    dists = np.empty((nrows, K), dtype=np.float64)
+    rc = lib().oracle_knn_rs(_p(S), S.shape[0], _p(Q), NQ, n, K, rp, nrows, _p(ids), _p(dists),
+                             threads)
+    if rc != 0:
+        raise ValueError("oracle_knn_rs: invalid arguments")
     return ids, dists
 
 

@@ -133,6 +133,49 @@ int oracle_knn(const double* D, int64_t N, int32_t n, int32_t K,
   return bad ? -1 : 0;
 }
 
+// ---------------------------------------------------------------------------
+// KNN join R join_KNN S of two point sets (Sec. 2.1, last sentences of the
+// problem statement): for every point of R (here Q, row-major NQ x n) its K
+// nearest points of S (row-major NS x n), by the same definition with nothing
+// excluded (a query need not belong to S; where it coincides with a point of
+// S, that point is a neighbour at distance 0).  rows: the query rows to answer
+// (NULL = all NQ, in order).  Output row r: the K first pairs (d^2(q, j), j),
+// j over S, lexicographically; ids are S ids, distances sqrt(d^2).
+// Returns 0, or -1 on invalid arguments (K outside [1, NS], bad rows).
+// ---------------------------------------------------------------------------
+int oracle_knn_rs(const double* S, int64_t NS, const double* Q, int64_t NQ, int32_t n, int32_t K,
+                  const int64_t* rows, int64_t nrows, int32_t* out_ids, double* out_dists,
+                  int32_t nthreads) {
+  if (!S || !Q || !out_ids || !out_dists || n < 1 || K < 1 || K > NS) return -1;
+  if (!rows) nrows = NQ;
+#ifdef _OPENMP
+  omp_set_num_threads(nthreads > 0 ? nthreads : default_threads());
+#endif
+  int bad = 0;
+#pragma omp parallel
+  {
+    std::vector<std::pair<double, int64_t>> cand;
+    cand.reserve((size_t)NS);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t r = 0; r < nrows; ++r) {
+      const int64_t i = rows ? rows[r] : r;
+      if (i < 0 || i >= NQ) {
+        bad = 1;
+        continue;
+      }
+      cand.clear();
+      for (int64_t j = 0; j < NS; ++j)
+        cand.push_back(std::make_pair(sq_dist(Q + i * n, S + j * n, n), j));
+      std::partial_sort(cand.begin(), cand.begin() + K, cand.end());
+      for (int32_t k = 0; k < K; ++k) {
+        out_ids[r * K + k] = (int32_t)cand[k].second;
+        out_dists[r * K + k] = std::sqrt(cand[k].first);
+      }
+    }
+  }
+  return bad ? -1 : 0;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
