@@ -208,6 +208,34 @@ int knn_self_join_device(knn_index* idx, int32_t K, int32_t* d_ids, double* d_di
                          const knn_join_opts* opts, void* stream);
 
 /*
+ * KNN join of a query set with the indexed set, R join_KNN S (Sec. 2.1: the
+ * self-join's definition for a query set R = Q against the indexed points
+ * S = D; Sec. 4.3 adds such a query set to the GPU kernel): for every query
+ * point, the K points of D with the smallest Euclidean distance.  Nothing is
+ * excluded: a query equal to a point of D has that point as a neighbour at
+ * distance 0.  Distances, ordering and the tie rule are the self-join's.
+ * The index's grid levels are used unchanged (queries outside D's bounding
+ * box widen the levels' box); each query's neighbour cells are looked up
+ * from its own coordinates.
+ *   d_Q             device, n_queries x dims fp64 row-major (the index's
+ *                   dims), read only; must stay valid until the call returns.
+ *   d_ids, d_dists  device, n_queries x K each; row r = query r, ids are
+ *                   point ids of D.
+ *   K               1 <= K <= min(N, KNN_MAX_K).
+ *   opts            may be NULL; use_graph must be 0.
+ * Work is issued on `stream`; the call returns when the results are complete.
+ * Errors: KNN_EINVAL (K out of range, n_queries < 1, N + n_queries >= 2^31,
+ * a non-finite query coordinate, use_graph set, NULL pointers), KNN_ENOMEM,
+ * KNN_EDEVICE, KNN_EBUSY (another join running on the index).
+ */
+int knn_join_device(knn_index* idx, const double* d_Q, int64_t n_queries, int32_t K,
+                    int32_t* d_ids, double* d_dists, const knn_join_opts* opts, void* stream);
+
+/* As knn_join_device with Q, ids and dists in host memory (blocks). */
+int knn_join(knn_index* idx, const double* Q, int64_t n_queries, int32_t K, int32_t* ids,
+             double* dists, const knn_join_opts* opts);
+
+/*
  * For callers that cannot allocate device memory during the call (serving
  * loops that run on a fixed memory plan, harnesses that forbid hipMalloc):
  * the same join as knn_self_join_device, same arguments, results and

@@ -117,6 +117,9 @@ SIGNATURES = {
     "knn_self_join": (ctypes.c_int, [c_p, c_i32, c_p, c_p, ctypes.POINTER(JoinOpts)]),
     "knn_self_join_device": (ctypes.c_int, [c_p, c_i32, c_p, c_p, ctypes.POINTER(JoinOpts),
                                             c_p]),
+    "knn_join_device": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_p,
+                                       ctypes.POINTER(JoinOpts), c_p]),
+    "knn_join": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_p, ctypes.POINTER(JoinOpts)]),
     "knn_self_join_device_noalloc": (ctypes.c_int, [c_p, c_i32, c_p, c_p,
                                                     ctypes.POINTER(JoinOpts), c_p]),
     "knn_destroy_index": (None, [c_p]),

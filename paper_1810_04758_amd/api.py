@@ -155,6 +155,45 @@ class Index:
             return ids, dists, st.as_dict()
         return ids, dists
 
+    def join(self, Q, K, ids=None, dists=None, stream=None, with_stats=False, **opts):
+        """knn_join_device / knn_join: the K nearest points of the index for
+        every row of Q (R join S of Sec. 2.1, nothing excluded).  Q: a CUDA
+        tensor (results on the device) or a numpy array (results on the
+        host), n_queries x dims float64."""
+        st = JoinStats() if with_stats else None
+        o = _join_opts(stats=st, **opts)
+        torch = _torch()
+        if Q.shape[-1] != self.dims:
+            raise ValueError("Q must have the index's number of dimensions")
+        if isinstance(Q, torch.Tensor) and Q.is_cuda:
+            if Q.dtype != torch.float64 or Q.dim() != 2 or not Q.is_contiguous():
+                raise ValueError("Q must be a contiguous float64 n_queries x dims tensor")
+            NQ = Q.shape[0]
+            if ids is None:
+                ids = torch.empty((NQ, K), dtype=torch.int32, device=Q.device)
+            if dists is None:
+                dists = torch.empty((NQ, K), dtype=torch.float64, device=Q.device)
+            if ids.shape != (NQ, K) or dists.shape != (NQ, K):
+                raise ValueError("output shape must be (n_queries, K)")
+            check(load().knn_join_device(self.handle, ctypes.c_void_p(Q.data_ptr()), NQ, K,
+                                         ctypes.c_void_p(ids.data_ptr()),
+                                         ctypes.c_void_p(dists.data_ptr()), ctypes.byref(o),
+                                         _stream_ptr(stream)))
+        else:
+            Qh = np.ascontiguousarray(Q.numpy() if isinstance(Q, torch.Tensor) else Q,
+                                      dtype=np.float64)
+            if Qh.ndim != 2:
+                raise ValueError("Q must be n_queries x dims")
+            NQ = Qh.shape[0]
+            ids = np.empty((NQ, K), dtype=np.int32)
+            dists = np.empty((NQ, K), dtype=np.float64)
+            check(load().knn_join(self.handle, Qh.ctypes.data_as(ctypes.c_void_p), NQ, K,
+                                  ids.ctypes.data_as(ctypes.c_void_p),
+                                  dists.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o)))
+        if with_stats:
+            return ids, dists, st.as_dict()
+        return ids, dists
+
     def self_join_noalloc(self, K, ids, dists, stream=None, **opts):
         """knn_self_join_device_noalloc: the same join with every temporary in
         the library's fixed scratch area (no device allocation); ids / dists

@@ -424,8 +424,9 @@ k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int64_t nb, int shift
 // Active list in one pass: the sorted positions whose point failed, in order.
 __global__ void __launch_bounds__(kBlock)
 k_active_list(const uint8_t* __restrict__ failed, uint8_t tag, bool at_least,
-              const int32_t* __restrict__ perm, int64_t N, int64_t nb, int32_t* __restrict__ out,
-              uint32_t* __restrict__ count, uint32_t* __restrict__ state) {
+              const int32_t* __restrict__ perm, int64_t N, int64_t nb, int32_t base,
+              int32_t* __restrict__ out, uint32_t* __restrict__ count,
+              uint32_t* __restrict__ state) {
   const LbTile lt = lb_take_tile(state, nb);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -443,7 +444,8 @@ k_active_list(const uint8_t* __restrict__ failed, uint8_t tag, bool at_least,
   uint32_t o = tile_wave_offset(state, lt, cnt, &total);
 #pragma unroll
   for (int r = 0; r < kCtRounds; ++r) {
-    if ((m[r] >> lane) & 1ull) out[o + (uint32_t)__popcll(m[r] & lt_mask)] = (int32_t)(wbase + r * 64 + lane);
+    if ((m[r] >> lane) & 1ull)
+      out[o + (uint32_t)__popcll(m[r] & lt_mask)] = base + (int32_t)(wbase + r * 64 + lane);
     o += (uint32_t)__popcll(m[r]);
   }
   if (threadIdx.x == 0 && lt.tile == nb - 1) *count = total;
@@ -880,6 +882,125 @@ __global__ void k_neighbor_ranges_z(const uint32_t* __restrict__ cell_start,
   }
 }
 
+// Index of the first cell whose key is >= key in cell_key[0..M) (M >= 1),
+// clamped to M - 1: a starting point for the galloping search.
+__device__ inline uint32_t start_cell(const uint64_t* __restrict__ cell_key, uint32_t M,
+                                      uint64_t key) {
+  uint32_t lo = 0, hi = M;
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (cell_key[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < M ? lo : M - 1;
+}
+
+// Ranges of external queries (a join of a query set with the indexed set):
+// a query need not lie in any non-empty cell, so it gets a slot of its own,
+// slot i for the query at position base + i of the point array: its cell
+// coordinates come from its coordinates, its block's ranges are looked up in
+// the cell table (Z-order: galloping from the query key's place in it;
+// row-major: the row-segment lookup), written to slot i in the cells'
+// format, and cell_of[q] = i.  A group of S lanes per active query.
+template <int DIM, bool ZL>
+__global__ void k_query_ranges(const double* __restrict__ Xs, const int32_t* __restrict__ active,
+                               int64_t n_active, const uint32_t* n_dev, int64_t base, int64_t nq,
+                               const uint32_t* __restrict__ cell_start,
+                               const uint64_t* __restrict__ cell_key, const uint32_t* d_M,
+                               const uint32_t* __restrict__ dense,
+                               const uint2* __restrict__ rowtab, GeomDev gd,
+                               uint32_t* __restrict__ cell_of, uint32_t* __restrict__ ranges,
+                               uint8_t* __restrict__ rslot, uint32_t* __restrict__ nrng,
+                               uint32_t* __restrict__ cand_count) {
+  constexpr int R = ZL ? (DIM == 2 ? 9 : DIM == 3 ? 27 : 81)
+                       : (DIM == 2 ? 3 : DIM == 3 ? 9 : DIM == 4 ? 27 : DIM == 5 ? 81 : 243);
+  constexpr int S = R <= 4 ? 4 : R <= 16 ? 16 : R <= 32 ? 32 : 64;
+  const uint32_t M = *d_M;
+  const int lane = threadIdx.x & 63;
+  const int l = lane % S;
+  const int sub = lane / S;
+  const uint64_t lt = l == 0 ? 0ull : (~0ull >> (64 - l));
+  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / S);
+  const int64_t na = n_dev ? min(n_active, (int64_t)*n_dev) : n_active;
+  for (int64_t a = (int64_t)blockIdx.x * (blockDim.x / S) + threadIdx.x / S; a < na;
+       a += groups) {
+    const int32_t q = active[a];
+    const int64_t i = (int64_t)q - base;
+    if (i < 0 || i >= nq) continue;  // not a query position (never in a valid list)
+    int64_t cc[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+      cc[j] = cell_coord(Xs[(int64_t)q * point_stride(DIM) + j], gd.lo[j], gd.inv_w);
+    uint32_t c0 = 0;
+    uint64_t k0 = 0;
+    if constexpr (ZL) {
+      c0 = start_cell(cell_key, M, zorder_key<DIM>(cc, gd.zbits));
+      k0 = cell_key[c0];
+    }
+    uint32_t count = 0, cand = 0;
+    for (int rb = 0; rb < R; rb += S) {
+      const int r = rb + l;
+      uint32_t start = 0, mid0 = 0, mid1 = 0, end = 0;
+      int slot = 0;
+      if (r < R) {
+        if constexpr (ZL) {
+          int64_t nb[DIM];
+          bool inside = true;
+          int rr = r, olast = 0;
+#pragma unroll
+          for (int j = DIM - 1; j >= 0; --j) {
+            const int o = rr % 3 - 1;
+            rr /= 3;
+            if (j == DIM - 1) olast = o;
+            nb[j] = cc[j] + o;
+            if (nb[j] < 0 || nb[j] >= gd.g[j]) inside = false;
+          }
+          if (inside) {
+            const uint32_t f = find_cell_near(cell_key, M, c0, k0, zorder_key<DIM>(nb, gd.zbits));
+            if (f != 0xFFFFFFFFu) {
+              start = cell_start[f];
+              end = cell_start[f + 1];
+            }
+          }
+          mid0 = olast < 0 ? end : start;
+          mid1 = olast > 0 ? start : end;
+          slot = r / 3;
+        } else {
+          range_of<DIM>(r, cc, cell_start, cell_key, M, dense, rowtab, gd, start, mid0, mid1,
+                        end);
+          slot = r;
+        }
+      }
+      const bool ne = end > start;
+      const uint64_t m = (S == 64 ? __ballot(ne) : (__ballot(ne) >> (sub * S))) &
+                         (S == 64 ? ~0ull : ((1ull << S) - 1ull));
+      if (ne) {
+        const uint32_t pos = count + (uint32_t)__popcll(m & lt);
+        reinterpret_cast<uint4*>(ranges)[i * R + pos] = make_uint4(start, mid0, mid1, end);
+        rslot[i * R + pos] = (uint8_t)slot;
+        cand += end - start;
+      }
+      count += (uint32_t)__popcll(m);
+    }
+#pragma unroll
+    for (int o = 1; o < S; o <<= 1) cand += __shfl_xor(cand, o, 64);
+    if (l == 0) {
+      nrng[i] = count;
+      cand_count[i] = cand;
+      cell_of[q] = (uint32_t)i;
+    }
+  }
+}
+
+__global__ void k_iota(int32_t* __restrict__ out, int64_t n, int32_t base) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = base + (int32_t)i;
+}
+
+
 // Zero fill: `words` 32-bit words, then `tail` (< 4) trailing bytes.  A kernel
 // rather than a memset node, so the join's launch sequence can be captured in
 // a graph and replayed.
@@ -1056,15 +1177,15 @@ void launch_neighbor_ranges_z(const uint32_t* cell_start, const uint64_t* cell_k
 
 void launch_active_list(const uint8_t* failed, uint8_t tag, const int32_t* perm, int64_t N,
                         int32_t* out, uint32_t* count, uint32_t* state, int64_t state_elems,
-                        hipStream_t s, bool at_least) {
+                        hipStream_t s, bool at_least, int32_t base) {
   if (N <= 0) {
     launch_zero(count, sizeof(uint32_t), s);
     return;
   }
   const int64_t nb = ceil_div(N, kCtTile);
   KNN_CHECK(4 + 2 * nb <= state_elems, KNN_EINTERNAL, "scan state too small");
-  k_active_list<<<(unsigned)nb, kBlock, 0, s>>>(failed, tag, at_least, perm, N, nb, out, count,
-                                                state);
+  k_active_list<<<(unsigned)nb, kBlock, 0, s>>>(failed, tag, at_least, perm, N, nb, base, out,
+                                                count, state);
   KNN_LAUNCHED();
 }
 
@@ -1116,6 +1237,47 @@ void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_st
     case 6: k_neighbor_ranges<6><<<nb, kBlock, 0, s>>>(Xs, N, cell_start, cell_key, d_M, dense, rowtab, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
+  KNN_LAUNCHED();
+}
+
+void launch_query_ranges(const double* Xs, const int32_t* active, int64_t n_active,
+                         const uint32_t* n_dev, int64_t base, int64_t nq,
+                         const uint32_t* cell_start, const uint64_t* cell_key,
+                         const uint32_t* d_M, const uint32_t* dense, const uint2* rowtab,
+                         const GridGeom& gg, bool zl, uint32_t* cell_of, uint32_t* ranges,
+                         uint8_t* rslot, uint32_t* nrng, uint32_t* cand_count, hipStream_t s) {
+  if (n_active <= 0) return;
+  KNN_CHECK(!zl || gg.dims <= kZMaxDims, KNN_EINTERNAL, "Z-order levels take 2-4 dimensions");
+  GeomDev gd = to_dev(gg);
+  const int R = zl ? (gg.dims == 2 ? 9 : gg.dims == 3 ? 27 : 81)
+                   : (gg.dims == 2 ? 3 : gg.dims == 3 ? 9 : gg.dims == 4 ? 27 : 81);
+  const int S = R <= 4 ? 4 : R <= 16 ? 16 : R <= 32 ? 32 : 64;
+  const int nb = grid_for(n_active * S, 65536);
+#define KNN_QR(D, Z) k_query_ranges<D, Z><<<nb, kBlock, 0, s>>>(Xs, active, n_active, n_dev, base, nq, cell_start, cell_key, d_M, dense, rowtab, gd, cell_of, ranges, rslot, nrng, cand_count)
+  if (zl) {
+    switch (gg.dims) {
+      case 2: KNN_QR(2, true); break;
+      case 3: KNN_QR(3, true); break;
+      case 4: KNN_QR(4, true); break;
+      default: throw Error(KNN_EINVAL, "Z-order levels take 2-4 dimensions");
+    }
+  } else {
+    switch (gg.dims) {
+      case 2: KNN_QR(2, false); break;
+      case 3: KNN_QR(3, false); break;
+      case 4: KNN_QR(4, false); break;
+      case 5: KNN_QR(5, false); break;
+      case 6: KNN_QR(6, false); break;
+      default: throw Error(KNN_EINVAL, "dims out of range");
+    }
+  }
+#undef KNN_QR
+  KNN_LAUNCHED();
+}
+
+void launch_iota(int32_t* out, int64_t n, int32_t base, hipStream_t s) {
+  if (n <= 0) return;
+  k_iota<<<grid_for(n), kBlock, 0, s>>>(out, n, base);
   KNN_LAUNCHED();
 }
 

@@ -87,19 +87,19 @@ int64_t pow3(int e) {
 // Geometry of the level with cell side w.  The side is enlarged if the grid
 // would not fit the 62-bit key space or 2^30 cells per dimension (a
 // performance policy only: any side gives exact results).
-GridGeom make_geom(const knn_index& idx, double& w) {
+GridGeom make_geom(int n, const double* lo, const double* hi, double& w) {
   GridGeom gg{};
-  gg.dims = idx.n;
+  gg.dims = n;
   double ext = 0;
-  for (int j = 0; j < idx.n; ++j) ext = std::max(ext, idx.hi[j] - idx.lo[j]);
+  for (int j = 0; j < n; ++j) ext = std::max(ext, hi[j] - lo[j]);
   if (!(w > 0) || !std::isfinite(w)) w = ext > 0 ? ext : 1.0;
   for (int attempt = 0; attempt < 200; ++attempt) {
     double inv_w = 1.0 / w;
     bool fits = std::isfinite(inv_w) && inv_w > 0;
     long double prod = 1;
     int64_t gmax = 1;
-    for (int j = 0; fits && j < idx.n; ++j) {
-      double u = std::floor((idx.hi[j] - idx.lo[j]) * inv_w);
+    for (int j = 0; fits && j < n; ++j) {
+      double u = std::floor((hi[j] - lo[j]) * inv_w);
       if (!(u < (double)(1ll << 30))) {
         fits = false;
         break;
@@ -112,11 +112,11 @@ GridGeom make_geom(const knn_index& idx, double& w) {
       gg.inv_w = inv_w;
       gg.g_max = gmax;
       uint64_t st = 1;
-      for (int j = idx.n - 1; j >= 0; --j) {
+      for (int j = n - 1; j >= 0; --j) {
         gg.stride[j] = st;
         st *= (uint64_t)gg.g[j];
       }
-      for (int j = 0; j < idx.n; ++j) gg.lo[j] = idx.lo[j];
+      for (int j = 0; j < n; ++j) gg.lo[j] = lo[j];
       uint64_t maxkey = st - 1;
       int bits = 0;
       while (bits < 64 && (maxkey >> bits) != 0) ++bits;
@@ -131,15 +131,15 @@ GridGeom make_geom(const knn_index& idx, double& w) {
 // Geometry of the level-0 Z-order grid of cell side w: row-major sizes, and
 // the bits per dimension of the interleaved keys (dims * bits <= 62).  The
 // side is enlarged until that fits (a performance policy only).
-GridGeom make_geom_z(const knn_index& idx, double& w) {
+GridGeom make_geom_z(int n, const double* lo, const double* hi, double& w) {
   for (int attempt = 0; attempt < 200; ++attempt) {
-    GridGeom gg = make_geom(idx, w);  // may enlarge w for its own limits
+    GridGeom gg = make_geom(n, lo, hi, w);  // may enlarge w for its own limits
     int bits = 0;
     while (bits < 62 && ((gg.g_max - 1) >> bits) != 0) ++bits;
-    if (idx.n * bits <= 62) {
+    if (n * bits <= 62) {
       gg.zbits = bits;
       gg.zshift = 0;
-      gg.key_bits = idx.n * bits;
+      gg.key_bits = n * bits;
       return gg;
     }
     w *= 2;
@@ -233,7 +233,7 @@ void build_grid(const knn_index& idx, JoinContext& c, double w, hipStream_t s, b
   const int64_t N = idx.N;
   const int n = idx.n;
   c.zmode = false;
-  c.gg = make_geom(idx, w);
+  c.gg = make_geom(n, c.blo, c.bhi, w);
   c.Xs.reserve((size_t)N * point_stride(n));
   c.perm.reserve(N);
   c.cell_of.reserve(N);
@@ -323,7 +323,7 @@ void build_grid_z(const knn_index& idx, JoinContext& c, double w0, int level, hi
   KNN_CHECK(n <= kZMaxDims, KNN_EINTERNAL, "Z-order levels take 2-4 dimensions");
   c.zmode = true;
   if (level == 0) {
-    c.gz0 = make_geom_z(idx, w0);
+    c.gz0 = make_geom_z(n, c.blo, c.bhi, w0);
     c.Xs.reserve((size_t)N * point_stride(n));
     c.perm.reserve(N);
     c.keys.reserve(N);
@@ -399,6 +399,8 @@ int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_
 int64_t build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t s,
                     int64_t Mcap_known) {
   c.zmode = false;
+  std::copy(idx.lo, idx.lo + idx.n, c.blo);
+  std::copy(idx.hi, idx.hi + idx.n, c.bhi);
   build_grid(idx, c, w, s);
   return build_ranges(idx, c, s, Mcap_known, nullptr, 0);
 }
@@ -526,19 +528,38 @@ static int lanes_for(int dims, double cand, int64_t A, int cap, bool zl) {
 
 void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, double* d_dists,
                const knn_join_opts& o, hipStream_t s, std::vector<LevelPlan>* record,
-               const std::vector<LevelPlan>* replay) {
-  validate_join(&idx, K);
+               const std::vector<LevelPlan>* replay, const JoinQueries* jq) {
+  // rj: a join of the query set jq with the index's points (R join S,
+  // Sec. 2.1); the queries are appended to the sorted point array (positions
+  // N .. N + NQ - 1), lie in no cell, and get their ranges slot by slot
+  const bool rj = jq != nullptr;
+  if (rj) {
+    KNN_CHECK(K >= 1 && (int64_t)K <= idx.N && K <= KNN_MAX_K, KNN_EINVAL,
+              "K must be in [1, min(N, KNN_MAX_K)]");
+    KNN_CHECK(jq->NQ >= 1 && idx.N + jq->NQ < ((int64_t)1 << 31), KNN_EINVAL,
+              "the query count must be >= 1 and N + queries < 2^31");
+    KNN_CHECK(!replay && !record, KNN_EINTERNAL, "joins of a query set are not captured");
+  } else {
+    validate_join(&idx, K);
+  }
   KNN_CHECK(d_ids && d_dists, KNN_EINVAL, "output pointers are NULL");
   auto t_start = std::chrono::steady_clock::now();
   const int64_t N = idx.N;
+  const int64_t NQ = rj ? jq->NQ : 0;
+  const int64_t NP = N + NQ;  // points of the sorted array (queries after the indexed points)
   knn_join_stats* st = replay ? nullptr : o.stats;
   if (record) record->clear();
   if (st) std::memset(st, 0, sizeof(*st));
+  // the levels cover the index's bounds, joined with the queries'
+  for (int j = 0; j < idx.n; ++j) {
+    c.blo[j] = rj ? std::min(idx.lo[j], jq->lo[j]) : idx.lo[j];
+    c.bhi[j] = rj ? std::max(idx.hi[j], jq->hi[j]) : idx.hi[j];
+  }
 
   // level-0 cell side: w = w_factor * eps_min(K) (Sec. 4.4), or explicit
   const double eps_min = eps_min_of(idx, K);
   double ext = 0;
-  for (int j = 0; j < idx.n; ++j) ext = std::max(ext, idx.hi[j] - idx.lo[j]);
+  for (int j = 0; j < idx.n; ++j) ext = std::max(ext, c.bhi[j] - c.blo[j]);
   double w;
   if (o.cell_width > 0) {
     w = o.cell_width;
@@ -578,21 +599,41 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
   if (st) st->eps_min = eps_min;
   const double tail_budget = tail_budget_of(idx, K, o);
   double diag2 = 0;
-  for (int j = 0; j < idx.n; ++j) diag2 += (idx.hi[j] - idx.lo[j]) * (idx.hi[j] - idx.lo[j]);
+  for (int j = 0; j < idx.n; ++j) diag2 += (c.bhi[j] - c.blo[j]) * (c.bhi[j] - c.blo[j]);
 
   c.iscal.reserve(kCounterInts);  // queue heads, failures, refinement rounds, heavy queries
   c.scal.reserve(4);
-  c.active.reserve(N);
-  c.fail_list.reserve(N);
-  c.failed.reserve(N);
+  c.active.reserve(std::max(N, NQ));
+  c.fail_list.reserve(std::max(N, NQ));
+  c.failed.reserve(NP);
   c.cell_active.reserve(N);
+  // sorted failures are listed by position (Z-order levels keep the order;
+  // external queries keep theirs at every level)
+  const bool fpos = zl || rj;
+  if (rj) {
+    // the point arrays hold the queries after the indexed points, in both
+    // buffers of the row-major level pair
+    const int S = point_stride(idx.n);
+    c.Xs.reserve((size_t)NP * S);
+    c.perm.reserve(NP);
+    c.vals2.reserve(NP);
+    c.cell_of.reserve(NP);
+    if (!zl) {
+      c.Xs2.reserve((size_t)NP * S);
+      c.perm2.reserve(NP);
+    }
+    const int64_t NM = std::max(N, NQ);
+    c.tmp.reserve(radix_tmp_elems(NM));
+    if (c.scan_state.reserve(scan_state_elems(NM)))
+      launch_zero(c.scan_state.p, c.scan_state.bytes(), s);
+  }
   // Failure and active-cell flags carry the level's tag (level_tag), so they
   // are cleared only when the tags start over (before level 1's marks).
   const int ncu = cu_count(c.device);
 
   Events ev(st != nullptr);
-  int64_t A = N;          // active queries of the level
-  int64_t remaining = N;  // queries not solved yet
+  int64_t A = rj ? NQ : N;          // active queries of the level
+  int64_t remaining = A;            // queries not solved yet
   for (int level = 0;; ++level) {
     if (level >= KNN_MAX_LEVELS - 1) w = std::max(w, 2.0 * ext + 1.0);  // everything in one block
     const LevelPlan* rp = nullptr;
@@ -613,12 +654,17 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       ta.X = idx.X.p;
       ta.N = N;
       ta.n = idx.n;
+      if (rj) {
+        ta.QX = jq->QX;
+        ta.QN = NQ;
+      }
       if (rp) remaining = rp->A;
       if (zl) {
         // every query left is flagged with this level or a later one: list
         // them (sorted positions) and take their ids
-        launch_active_list(c.failed.p, level_tag(level), nullptr, N, c.active.p, c.scal.p + 1,
-                           c.scan_state.p, (int64_t)c.scan_state.n, s, true);
+        launch_active_list(c.failed.p + (rj ? N : 0), level_tag(level), nullptr, rj ? NQ : N,
+                           c.active.p, c.scal.p + 1, c.scan_state.p, (int64_t)c.scan_state.n, s,
+                           true, rj ? (int32_t)N : 0);
         if (!rp) {  // the flags must account for exactly the queries left
           c.pinned.reserve(kCounterInts + 16 + KNN_MAX_LEVELS);
           KNN_HIP(hipMemcpyAsync(c.pinned.p, c.scal.p + 1, sizeof(uint32_t),
@@ -630,6 +676,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
         launch_pos_to_id(c.active.p, remaining, c.perm.p, s);
         ta.q_ids = c.active.p;
       } else {
+        if (rj) launch_pos_to_id(c.fail_list.p, remaining, c.perm.p, s);
         ta.q_ids = c.fail_list.p;
       }
       A = remaining;
@@ -667,23 +714,58 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       KNN_CHECK(level == 0 || level <= c.gz0.zbits, KNN_EINTERNAL,
                 "Z-order levels ran past their single-cell top");
       build_grid_z(idx, c, w0, level, s);
-    } else
+    } else {
       build_grid(idx, c, w, s, level > 0);
+    }
+    if (rj && level == 0) {
+      // the queries, sorted by their level-0 cell key (locality), appended
+      // after the indexed points: coordinates and ids (row-major levels: in
+      // both buffers of the pair, which later levels swap)
+      const GridGeom& g0 = zl ? c.gz0 : c.gg;
+      const int S = point_stride(idx.n);
+      c.ikeys.reserve(NQ);
+      c.ikeys2.reserve(NQ);
+      c.ivals.reserve(NQ);
+      c.ivals2.reserve(NQ);
+      launch_cell_keys(jq->QX, NQ, g0, c.ikeys.p, c.ivals.p, s);
+      const int32_t* qperm =
+          radix_sort_pairs(c.ikeys.p, c.ivals.p, c.ikeys2.p, c.ivals2.p, NQ, g0.key_bits,
+                           c.tmp.p, c.scan_state.p, (int64_t)c.scan_state.n, s)
+              ? c.ivals2.p
+              : c.ivals.p;
+      launch_gather_points(jq->QA, qperm, NQ, idx.n, c.Xs.p + (size_t)N * S, s);
+      KNN_HIP(hipMemcpyAsync(c.perm.p + N, qperm, (size_t)NQ * sizeof(int32_t),
+                             hipMemcpyDeviceToDevice, s));
+      if (!zl) {
+        KNN_HIP(hipMemcpyAsync(c.Xs2.p + (size_t)N * S, c.Xs.p + (size_t)N * S,
+                               (size_t)NQ * S * sizeof(double), hipMemcpyDeviceToDevice, s));
+        KNN_HIP(hipMemcpyAsync(c.perm2.p + N, qperm, (size_t)NQ * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, s));
+      }
+    }
     // active list of this level (cell order): level 0 = every point
     const int32_t* active = nullptr;
     const uint8_t* cell_active = nullptr;
-    if (level > 0) {
-      // Z-order levels keep the sorted order and list failures by sorted
-      // position, so their flags are read without a gather through perm
-      launch_active_list(c.failed.p, level_tag(level), zl ? nullptr : c.perm.p, N, c.active.p,
-                         c.scal.p + 1, c.scan_state.p, (int64_t)c.scan_state.n, s);
+    if (rj && level == 0) {
+      launch_iota(c.active.p, NQ, (int32_t)N, s);  // every query
+      active = c.active.p;
+    } else if (level > 0) {
+      // failures flagged by position (Z-order levels, external queries) are
+      // read without a gather through perm
+      if (rj)
+        launch_active_list(c.failed.p + N, level_tag(level), nullptr, NQ, c.active.p,
+                           c.scal.p + 1, c.scan_state.p, (int64_t)c.scan_state.n, s, false,
+                           (int32_t)N);
+      else
+        launch_active_list(c.failed.p, level_tag(level), zl ? nullptr : c.perm.p, N, c.active.p,
+                           c.scal.p + 1, c.scan_state.p, (int64_t)c.scan_state.n, s);
       active = c.active.p;
     }
     // Z-order levels: deferred queries are flagged straight for later levels,
     // so the flags and the per-level pending counts start clean here
     if (zl && level == 0) {
       c.pending.reserve(KNN_MAX_LEVELS);
-      launch_zero(c.failed.p, (size_t)N, s);
+      launch_zero(c.failed.p, (size_t)NP, s);
       launch_zero(c.cell_active.p, (size_t)N, s);
       launch_zero(c.pending.p, KNN_MAX_LEVELS * sizeof(uint32_t), s);
     }
@@ -712,7 +794,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       da.out_count = out_count;
       da.fail_list = c.fail_list.p;
       da.fail_count = c.iscal.p + kFailSlot;
-      da.fail_pos = zl ? 1 : 0;
+      da.fail_pos = fpos ? 1 : 0;
       if (zl) {  // skip ahead to the level the prediction asks for
         da.failed = c.failed.p;
         da.pending = c.pending.p;
@@ -725,7 +807,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       return da;
     };
     const uint32_t* n_pre = nullptr;  // device count of the list the prefilter kept
-    if (zl && filt) {
+    if (zl && filt && !rj) {
       // Z-order levels: a first deferral from the parent-group density, before
       // any neighbour range exists, so that ranges are built only for the
       // cells of the queries it keeps (most of a fine level's queries are
@@ -743,19 +825,32 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       active = c.active2.p;
       n_pre = c.scal.p + 3;
     }
-    if (level > 0 || n_pre) {
-      // neighbour ranges only for the cells that hold an active query (level
-      // 0 of Z-order levels, whose flag array was just cleared, marks with a
-      // tag no later level uses)
-      const uint8_t tag = level == 0 ? (uint8_t)0xFF : level_tag(level);
-      launch_mark_cells_of(active, A, c.cell_of.p, c.cell_active.p, tag, s, n_pre);
-      cell_active = c.cell_active.p;
+    if (rj) {
+      // external queries: ranges slot by slot, for the active ones
+      const int64_t R = zl ? pow3(idx.n) : pow3(idx.n - 1);
+      c.ranges.reserve((size_t)NQ * R * 4);
+      c.rslot.reserve((size_t)NQ * R);
+      c.nrng.reserve(NQ);
+      c.cand_count.reserve(std::max(N, NQ));
+      launch_query_ranges(c.Xs.p, active, A, level > 0 ? c.scal.p + 1 : nullptr, N, NQ,
+                          c.cell_start.p, c.cell_key.p, c.scal.p,
+                          c.dense_used, c.rowtab_used, c.gg, zl, c.cell_of.p, c.ranges.p,
+                          c.rslot.p, c.nrng.p, c.cand_count.p, s);
+    } else {
+      if (level > 0 || n_pre) {
+        // neighbour ranges only for the cells that hold an active query
+        // (level 0 of Z-order levels, whose flag array was just cleared,
+        // marks with a tag no later level uses)
+        const uint8_t tag = level == 0 ? (uint8_t)0xFF : level_tag(level);
+        launch_mark_cells_of(active, A, c.cell_of.p, c.cell_active.p, tag, s, n_pre);
+        cell_active = c.cell_active.p;
+      }
+      lp.Mcap = build_ranges(idx, c, s, rp ? rp->Mcap : 0, cell_active,
+                             level == 0 ? (uint8_t)0xFF : level_tag(level));
     }
-    lp.Mcap = build_ranges(idx, c, s, rp ? rp->Mcap : 0, cell_active,
-                           level == 0 ? (uint8_t)0xFF : level_tag(level));
     if (filt) {
       // the deferral filter on the block density (candidate counts)
-      int32_t* out = n_pre ? c.active.p : (c.active2.reserve(N), c.active2.p);
+      int32_t* out = n_pre ? c.active.p : (c.active2.reserve(std::max(N, NQ)), c.active2.p);
       DeferArgs da = defer_args(active, out, c.scal.p + 2);
       da.n_active_dev = n_pre;
       launch_defer_filter(da, idx.n, s);
@@ -868,14 +963,15 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     a.out_d = d_dists;
     a.fail_list = c.fail_list.p;
     a.fail_count = c.iscal.p + kFailSlot;
-    a.fail_pos = zl ? 1 : 0;
+    a.fail_pos = fpos ? 1 : 0;
+    a.self_in_list = rj ? 0 : 1;
     a.refine_count = c.iscal.p + kRefineSlot;
     a.walk_error = c.iscal.p + kWalkErrSlot;
     a.spec_count = c.iscal.p + kSpecSlot;
     lp.heavy_min = heavy_min;
     if (heavy_min > 0 && A > 0) {
       // heavy queries first, one workgroup each (count stays on the device)
-      c.heavy.reserve(N);
+      c.heavy.reserve(std::max(N, NQ));
       a.heavy_min = heavy_min;
       a.heavy = c.heavy.p;
       a.n_heavy = c.iscal.p + kHeavySlot;
@@ -1025,7 +1121,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     // failures are re-queued on a grid with a larger cell side (Alg. 1):
     // linear growth by eps_step * w0 first, then geometric growth
     if (!zl && level_tag(level + 1) == 1) {  // tags wrapped: clear the stale ones
-      launch_zero(c.failed.p, (size_t)N, s);
+      launch_zero(c.failed.p, (size_t)NP, s);
       launch_zero(c.cell_active.p, (size_t)N, s);
     }
     launch_mark_failed(c.fail_list.p, c.iscal.p + kFailSlot, fails, c.failed.p,
@@ -1366,6 +1462,36 @@ std::mutex& scratch_call_mutex(int dev) {
   return g_scratch_call_mu[dev];  // constructed in place, never moved
 }
 
+// The join of the query set Q (device, row-major NQ x n) with the index's
+// points: the queries' SoA copy and bounds (non-finite coordinates refused),
+// then the level loop with the query set.
+void join_query_set(knn_index* idx, const double* d_Q, int64_t NQ, int32_t K, int32_t* d_ids,
+                    double* d_dists, const knn_join_opts& o, hipStream_t s) {
+  const int n = idx->n;
+  JoinQueries jq;
+  jq.QA = d_Q;
+  jq.NQ = NQ;
+  DevBuf<double> QX((size_t)NQ * n);
+  DevBuf<uint32_t> bad(1);
+  launch_zero(bad.p, sizeof(uint32_t), s);
+  launch_aos_to_soa(d_Q, NQ, n, QX.p, bad.p, s);
+  DevBuf<double> part((size_t)2 * n * kBoundsBlocks), lohi(2 * kMaxDims);
+  launch_bounds(QX.p, NQ, n, part.p, lohi.p, lohi.p + kMaxDims, s);
+  double hb[2 * kMaxDims];
+  uint32_t nbad = 0;
+  KNN_HIP(hipMemcpyAsync(hb, lohi.p, sizeof(hb), hipMemcpyDeviceToHost, s));
+  KNN_HIP(hipMemcpyAsync(&nbad, bad.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  KNN_HIP(hipStreamSynchronize(s));
+  KNN_CHECK(nbad == 0, KNN_EINVAL, "Q holds non-finite coordinates");
+  for (int j = 0; j < n; ++j) {
+    jq.lo[j] = hb[j];
+    jq.hi[j] = hb[kMaxDims + j];
+  }
+  jq.QX = QX.p;
+  // the level loop returns after its device work completed: QX may go
+  self_join(*idx, index_ctx(idx), K, d_ids, d_dists, o, s, nullptr, nullptr, &jq);
+}
+
 struct BusyGuard {
   knn_index* idx;
   explicit BusyGuard(knn_index* i) : idx(i) {
@@ -1435,6 +1561,53 @@ int knn_self_join_device(knn_index* idx, int32_t K, int32_t* d_ids, double* d_di
       self_join_graph(*idx, K, d_ids, d_dists, o, (hipStream_t)stream);
     else
       self_join(*idx, index_ctx(idx), K, d_ids, d_dists, o, (hipStream_t)stream);
+  });
+}
+
+int knn_join_device(knn_index* idx, const double* d_Q, int64_t n_queries, int32_t K,
+                    int32_t* d_ids, double* d_dists, const knn_join_opts* opts, void* stream) {
+  return guarded([&] {
+    KNN_CHECK(idx != nullptr, KNN_EINVAL, "index is NULL");
+    KNN_CHECK(d_Q && d_ids && d_dists, KNN_EINVAL, "NULL pointer");
+    KNN_CHECK(n_queries >= 1, KNN_EINVAL, "n_queries must be >= 1");
+    knn_join_opts o = resolve_join(opts);
+    KNN_CHECK(o.use_graph == 0, KNN_EINVAL, "use_graph is not available for a query set");
+    BusyGuard bg(idx);
+    DeviceGuard dg(idx->device);
+    join_query_set(idx, d_Q, n_queries, K, d_ids, d_dists, o, (hipStream_t)stream);
+  });
+}
+
+int knn_join(knn_index* idx, const double* Q, int64_t n_queries, int32_t K, int32_t* ids,
+             double* dists, const knn_join_opts* opts) {
+  return guarded([&] {
+    KNN_CHECK(idx != nullptr, KNN_EINVAL, "index is NULL");
+    KNN_CHECK(Q && ids && dists, KNN_EINVAL, "NULL pointer");
+    KNN_CHECK(n_queries >= 1 && n_queries < ((int64_t)1 << 31), KNN_EINVAL,
+              "n_queries must be in [1, 2^31)");
+    KNN_CHECK(K >= 1 && K <= KNN_MAX_K, KNN_EINVAL, "K out of range");
+    knn_join_opts o = resolve_join(opts);
+    KNN_CHECK(o.use_graph == 0, KNN_EINVAL, "use_graph is not available for a query set");
+    BusyGuard bg(idx);
+    DeviceGuard dg(idx->device);
+    hipStream_t s = nullptr;
+    KNN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    try {
+      const size_t nq = (size_t)n_queries * idx->n, nk = (size_t)n_queries * K;
+      DevBuf<double> dQ(nq);
+      DevBuf<int32_t> dI(nk);
+      DevBuf<double> dD(nk);
+      KNN_HIP(hipMemcpyAsync(dQ.p, Q, nq * sizeof(double), hipMemcpyHostToDevice, s));
+      join_query_set(idx, dQ.p, n_queries, K, dI.p, dD.p, o, s);
+      KNN_HIP(hipMemcpyAsync(ids, dI.p, nk * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipMemcpyAsync(dists, dD.p, nk * sizeof(double), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+      throw;
+    }
+    KNN_HIP(hipStreamDestroy(s));
   });
 }
 

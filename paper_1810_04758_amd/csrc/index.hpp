@@ -44,6 +44,10 @@ struct JoinContext {
   // level arrays
   GridGeom gg{};
   GridGeom gz0{};  // Z-order levels: the level-0 geometry the keys were sorted for
+  // bounds the grid levels cover: the index's, joined with an external query
+  // set's when there is one
+  double blo[KNN_MAX_DIMS] = {0};
+  double bhi[KNN_MAX_DIMS] = {0};
   bool zmode = false;  // the current level is a Z-order level
   int64_t M = 0;
   DevBuf<double> Xs, Xs2;      // sorted points (Xs2: the other of a level pair)
@@ -139,6 +143,17 @@ struct GraphPlan {
   ~GraphPlan();
 };
 
+// The query set of a join of two sets, R join_KNN S (Sec. 2.1): R = Q on the
+// device, row-major NQ x n (QA) and as SoA (QX[j*NQ + i]), with its bounds.
+// Its points are searched against the index's points S; nothing is excluded.
+struct JoinQueries {
+  const double* QA = nullptr;
+  const double* QX = nullptr;
+  int64_t NQ = 0;
+  double lo[KNN_MAX_DIMS] = {0};
+  double hi[KNN_MAX_DIMS] = {0};
+};
+
 struct JoinParams {
   int32_t K;
   knn_join_opts opts;
@@ -170,10 +185,13 @@ int64_t build_level(const knn_index& idx, JoinContext& ctx, double w, hipStream_
 // failures re-queued and the cell side grown until every query succeeds.
 // record: filled with the levels of this run.  replay: issue exactly these
 // levels with no host round trip (stream capture), statistics not written.
+// jq non-NULL: the join of the query set jq with the index's points instead
+// (rows of the outputs = query ids; K <= N; no replay).
 void self_join(const knn_index& idx, JoinContext& ctx, int32_t K, int32_t* d_ids,
                double* d_dists, const knn_join_opts& o, hipStream_t s,
                std::vector<LevelPlan>* record = nullptr,
-               const std::vector<LevelPlan>* replay = nullptr);
+               const std::vector<LevelPlan>* replay = nullptr,
+               const JoinQueries* jq = nullptr);
 // use_graph: the first join of (index, K, options, outputs) runs eagerly and
 // captures its launch sequence; later ones launch the graph.
 void self_join_graph(knn_index& idx, int32_t K, int32_t* d_ids, double* d_dists,

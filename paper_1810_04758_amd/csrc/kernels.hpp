@@ -175,7 +175,23 @@ void launch_mark_failed(const int32_t* fail_list, const int32_t* d_fail_count,
 // number to *count (device).  One pass (scan state as launch_exclusive_scan).
 void launch_active_list(const uint8_t* failed, uint8_t tag, const int32_t* perm, int64_t N,
                         int32_t* out, uint32_t* count, uint32_t* state, int64_t state_elems,
-                        hipStream_t s, bool at_least = false);
+                        hipStream_t s, bool at_least = false, int32_t base = 0);
+// (base: added to every position written, for flags of a sub-array.)
+// Ranges of external queries: for the active queries q (point positions
+// base + i of Xs, i in [0, count of queries)), their 3^n block's ranges in
+// the level's cell table, in the format of launch_neighbor_ranges (zl:
+// launch_neighbor_ranges_z), written to slot i (ranges[i*R...], rslot, nrng,
+// cand_count), and cell_of[q] = i.
+// (n_dev non-NULL: the list's count is min(n_active, *n_dev); list entries
+// outside [base, base + nq) are skipped.)
+void launch_query_ranges(const double* Xs, const int32_t* active, int64_t n_active,
+                         const uint32_t* n_dev, int64_t base, int64_t nq,
+                         const uint32_t* cell_start, const uint64_t* cell_key,
+                         const uint32_t* d_M, const uint32_t* dense, const uint2* rowtab,
+                         const GridGeom& gg, bool zl, uint32_t* cell_of, uint32_t* ranges,
+                         uint8_t* rslot, uint32_t* nrng, uint32_t* cand_count, hipStream_t s);
+// out[i] = base + i for i < n.
+void launch_iota(int32_t* out, int64_t n, int32_t base, hipStream_t s);
 // Zeroes `bytes` bytes at p (4-byte aligned) with a kernel, not a memset node.
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
@@ -213,6 +229,8 @@ struct SearchArgs {
   int32_t persistent;
   int32_t share_lists;     // wavefronts whose queries share a cell walk one list
   int32_t zl;              // Z-order level: 3^n single-cell ranges per cell (else 3^(n-1))
+  int32_t self_in_list;    // the query is a point of its own list (self-join), counted and
+                           // taken back; 0: external queries, not in any list
   double lo[kMaxDims];
   double inv_w;
   double w;                // fl(1 / inv_w)

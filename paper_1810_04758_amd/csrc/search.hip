@@ -581,14 +581,15 @@ k_search(const SearchArgs a) {
         count(p);
       }
     }
-    // The walk counted the query itself (its own cell is always in the list)
-    // and every slot past the list's end (given the query's position): all at
-    // distance 0, in bin bin_of(0).  Each lane takes back its own padding
-    // slots, lane 0 also the query.
+    // The walk counted the query itself (its own cell is always in the list
+    // of a self-join) and every slot past the list's end (given the query's
+    // position): all at distance 0, in bin bin_of(0).  Each lane takes back
+    // its own padding slots, lane 0 also the query (external queries are in
+    // no list).
     if (valid) {
       const uint32_t it = l < (int)C ? (C - (uint32_t)l + T * kUnroll - 1) / (T * kUnroll) : 0u;
       const uint32_t real = l < (int)C ? (C - (uint32_t)l + T - 1) / T : 0u;
-      const uint32_t back = it * kUnroll - real + (l == 0 ? 1u : 0u);
+      const uint32_t back = it * kUnroll - real + (l == 0 && a.self_in_list ? 1u : 0u);
       if (back) atomicSub(&hist[bin_of<DIM>(0.0, thr, top0) * G + g], back);
     }
     wave_fence();

@@ -62,7 +62,8 @@ __device__ __forceinline__ void load_batch(const TailArgs& a, QBatch& qb) {
   for (int i = threadIdx.x; i < nq; i += blockDim.x) {
     const int64_t id = a.q_ids[q0 + i];
     qb.id[i] = id;
-    for (int j = 0; j < a.n; ++j) qb.x[i][j] = a.X[(int64_t)j * a.N + id];
+    for (int j = 0; j < a.n; ++j)
+      qb.x[i][j] = a.QX ? a.QX[(int64_t)j * a.QN + id] : a.X[(int64_t)j * a.N + id];
   }
 }
 
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(kBlock) k_tail_hist(const TailArgs a) {
     for (int k = 0; k < PPT; ++k) {
       if (pid[k] < 0) continue;
       for (int i = 0; i < qb.nq; ++i) {
-        if (pid[k] == qb.id[i]) continue;
+        if (!a.QX && pid[k] == qb.id[i]) continue;
         atomicAdd(&h[i][tbin(tail_d2<DIM>(px[k], qb.x[i]), a.top)], 1u);
       }
     }
@@ -201,7 +202,7 @@ __global__ void __launch_bounds__(kBlock) k_tail_refine_count(const TailArgs a) 
     for (int k = 0; k < PPT; ++k) {
       if (pid[k] < 0) continue;
       for (int i = 0; i < qb.nq; ++i) {
-        if (!refining[i] || pid[k] == qb.id[i]) continue;
+        if (!refining[i] || (!a.QX && pid[k] == qb.id[i])) continue;
         const double d2 = tail_d2<DIM>(px[k], qb.x[i]);
         const unsigned __int128 key =
             ((unsigned __int128)(uint64_t)__double_as_longlong(d2) << 32) | (uint32_t)pid[k];
@@ -262,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_tail_collect(const TailArgs a) {
     for (int k = 0; k < PPT; ++k) {
       if (pid[k] < 0) continue;
       for (int i = 0; i < qb.nq; ++i) {
-        if (pid[k] == qb.id[i]) continue;
+        if (!a.QX && pid[k] == qb.id[i]) continue;
         const double d2 = tail_d2<DIM>(px[k], qb.x[i]);
         bool acc;
         if (smode[i] == kBin)

@@ -17,6 +17,11 @@ struct TailArgs {
   int64_t N;
   int32_t n;
   const int32_t* q_ids;  // the tail queries (point ids), A of them
+  // external queries (a join of a query set with the indexed set): their
+  // SoA coordinates QX[j*QN + id] by query id, and nothing excluded; NULL:
+  // the queries are points of X and each excludes itself
+  const double* QX;
+  int64_t QN;
   int32_t A;
   int64_t top;  // bit pattern of the squared bounding-box diagonal >> 50
   int32_t K;
