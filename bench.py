@@ -370,7 +370,7 @@ def main():
                     help="length of the 200 requests/s serving trace (0 = skip)")
     ap.add_argument("--serving-sustainable-seconds", type=float, default=20.0,
                     help="length of the serving trace at the sustainable rate (0 = skip)")
-    ap.add_argument("--serving-sustainable-rate", type=float, default=8.0,
+    ap.add_argument("--serving-sustainable-rate", type=float, default=10.0,
                     help="requests/s of the sustainable serving point")
     ap.add_argument("--no-schedule-comparison", action="store_true",
                     help="skip the (untimed) persistent-vs-plain schedule comparison")
