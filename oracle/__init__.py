@@ -42,6 +42,8 @@ def lib():
         L.oracle_knn_kdtree.restype = ctypes.c_int
         L.oracle_knn_rs.argtypes = [P, i64, P, i64, i32, i32, P, i64, P, P, i32]
         L.oracle_knn_rs.restype = ctypes.c_int
+        L.oracle_eps_join.argtypes = [P, i64, i32, f64, P, i64, P, P, P, P, i32]
+        L.oracle_eps_join.restype = ctypes.c_int
         L.oracle_sq_dist.argtypes = [P, i32, i64, i64]
         L.oracle_sq_dist.restype = f64
         L.oracle_bounds.argtypes = [P, i64, i32, P, P]
@@ -139,6 +141,35 @@ def knn_rs(S, Q, K, rows=None, threads=0):
     if rc != 0:
         raise ValueError("oracle_knn_rs: invalid arguments")
     return ids, dists
+
+
+def eps_join(D, eps, rows=None, threads=0):
+    """Distance similarity self-join (the range-query join the paper builds
+    on): every pair (i, j), j != i, with dist(i, j) <= eps, for every point
+    i (or the given rows), grouped by row in row order, j ascending.
+    Returns (q int32, j int32, dist float64, counts int64 per row)."""
+    D = _f64(D)
+    N, n = D.shape
+    if rows is None:
+        nrows = N
+        rp = None
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        nrows = rows.shape[0]
+        rp = _p(rows)
+    counts = np.empty(nrows, dtype=np.int64)
+    L = lib()
+    if L.oracle_eps_join(_p(D), N, n, float(eps), rp, nrows, _p(counts), None, None, None,
+                         threads) != 0:
+        raise ValueError("oracle_eps_join: invalid arguments")
+    tot = int(counts.sum())
+    q = np.empty(tot, dtype=np.int32)
+    j = np.empty(tot, dtype=np.int32)
+    d = np.empty(tot, dtype=np.float64)
+    if L.oracle_eps_join(_p(D), N, n, float(eps), rp, nrows, _p(counts), _p(q), _p(j), _p(d),
+                         threads) != 0:
+        raise ValueError("oracle_eps_join: invalid arguments")
+    return q, j, d, counts
 
 
 def sq_dist(D, a, b):

@@ -598,4 +598,54 @@ double oracle_eps_min(const uint64_t* counts, int32_t n_bins, double bin_width, 
   return (double)n_bins * bin_width;
 }
 
+// ---------------------------------------------------------------------------
+// Distance similarity self-join (the range-query join the paper builds on,
+// Sec. 1 and Sec. 3: every pair of points within a search distance eps).
+// For each query row r (point i = rows[r], all N when rows is NULL): every j
+// != i with dist(i, j) = sqrt(d^2(i, j)) <= eps, by the definition, in
+// ascending j.  Two calls: with out_* NULL it writes only counts[r]; then
+// with arrays of sum(counts) entries it writes the pairs grouped by row in
+// row order.  Returns 0, or -1 on invalid arguments.
+// ---------------------------------------------------------------------------
+int oracle_eps_join(const double* D, int64_t N, int32_t n, double eps, const int64_t* rows,
+                    int64_t nrows, int64_t* counts, int32_t* out_q, int32_t* out_j,
+                    double* out_d, int32_t nthreads) {
+  if (!D || !counts || n < 1 || !(eps >= 0)) return -1;
+  if (!rows) nrows = N;
+  for (int64_t r = 0; r < nrows; ++r)
+    if (rows && (rows[r] < 0 || rows[r] >= N)) return -1;
+#ifdef _OPENMP
+  omp_set_num_threads(nthreads > 0 ? nthreads : default_threads());
+#endif
+  if (!out_q) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrows; ++r) {
+      const int64_t i = rows ? rows[r] : r;
+      int64_t c = 0;
+      for (int64_t j = 0; j < N; ++j)
+        if (j != i && std::sqrt(sq_dist(D + i * n, D + j * n, n)) <= eps) ++c;
+      counts[r] = c;
+    }
+    return 0;
+  }
+  std::vector<int64_t> off((size_t)nrows + 1, 0);
+  for (int64_t r = 0; r < nrows; ++r) off[r + 1] = off[r] + counts[r];
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = rows ? rows[r] : r;
+    int64_t k = off[r];
+    for (int64_t j = 0; j < N; ++j) {
+      if (j == i) continue;
+      const double d = std::sqrt(sq_dist(D + i * n, D + j * n, n));
+      if (d <= eps && k < off[r + 1]) {
+        out_q[k] = (int32_t)i;
+        out_j[k] = (int32_t)j;
+        out_d[k] = d;
+        ++k;
+      }
+    }
+  }
+  return 0;
+}
+
 }  // extern "C"
