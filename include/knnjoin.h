@@ -51,6 +51,7 @@ extern "C" {
 #define KNN_EBUSY (-4)     /* object in use / queue full */
 #define KNN_ETIMEOUT (-5)  /* wait timed out */
 #define KNN_EINTERNAL (-6) /* internal invariant violated (a bug) */
+#define KNN_ECANCELED (-7) /* a caller's callback stopped the operation */
 
 #define KNN_MIN_DIMS 2
 #define KNN_MAX_DIMS 6
@@ -260,6 +261,92 @@ int knn_join(knn_index* idx, const double* Q, int64_t n_queries, int32_t K, int3
 int knn_self_join_device_noalloc(knn_index* idx, int32_t K, int32_t* d_ids,
                                  double* d_dists, const knn_join_opts* opts,
                                  void* stream);
+
+/* ------------------------------------------------------------------------
+ * Distance similarity self-join (Sec. 1 and Sec. 3: the range-query join
+ * whose GPU kernel the KNN join is built from).  Result: every ordered pair
+ * (i, j) of points of D with j != i and fl(sqrt(d2(i, j))) <= eps, d2 the
+ * KNN join's squared distance (left to right over the dimensions, every
+ * operation rounded, no fused multiply-add); each unordered pair appears
+ * twice, once per direction, and a duplicate point at distance 0 is a
+ * neighbour.  Pairs are key/value triples (query id, neighbour id, distance
+ * = the rounded square root), produced in batches that fit a result buffer
+ * (Sec. 3.2).
+ * Method: one grid level of cell side eps (Sec. 3.1; enlarged by 2^-16 so
+ * that rounding cannot move a neighbour out of the 3^n block, or further when
+ * the grid would be too fine); each query scans its block, skipping the
+ * parts of each row of cells that lie farther than eps.  The paper sizes its
+ * batches from an estimated result size; here a count pass gives each
+ * query's exact pair count first (kept for later calls with the same eps),
+ * so a batch can never overflow its buffer.
+ * The level and counts stay with the index until it is destroyed, a call
+ * with another eps replaces them, or knn_eps_join_release frees them.  These
+ * calls share the index's one-join-at-a-time rule (KNN_EBUSY).
+ * Errors of all of them: KNN_EINVAL (idx NULL, eps negative or not finite,
+ * the other arguments as stated), KNN_ENOMEM, KNN_EDEVICE, KNN_EBUSY.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Result size.  sample_stride 1: *n_pairs = the exact number of pairs; then
+ * d_counts, when not NULL (device, int32 x N), receives the pair count of
+ * each point id.  sample_stride s > 1: the estimate of Sec. 3.2 (a light
+ * pass over a sample): the pairs of every s-th query in the processing
+ * order (a sample spread evenly over the cells), scaled by N / (queries
+ * sampled), rounded; d_counts must then be NULL.
+ * Issues its work on `stream` and returns when the size is known.
+ */
+int knn_eps_join_size(knn_index* idx, double eps, int64_t sample_stride, uint64_t* n_pairs,
+                      int32_t* d_counts, void* stream);
+
+/*
+ * One batch into device memory.  The queries are taken in the index's
+ * processing order for this eps (cells in key order; a cursor is a position
+ * in it: 0 starts the join, n_points means done).  The batch holds the pairs
+ * of the queries at positions [cursor, *next_cursor): as many whole queries
+ * as fit `capacity` pairs, at least one (KNN_EINVAL, with the count in
+ * knn_last_error, if the query at `cursor` alone has more pairs; a cursor
+ * of n_points returns 0 pairs).
+ *   d_qids, d_nids  device, int32, capacity entries: query id, neighbour id.
+ *   d_dists         device, fp64, capacity entries.
+ *   *n_pairs        pairs written, at indices [0, *n_pairs).
+ * Order: a query's pairs are contiguous, queries in processing order; within
+ * a query the scan order (deterministic; not sorted by id or distance).
+ * The first call for an eps builds the level and counts (blocking); each
+ * call reads its batch bounds back, then issues the writes on `stream` and
+ * returns: the pairs are complete when the stream reaches that point.
+ */
+int knn_eps_join_device(knn_index* idx, double eps, int64_t cursor, uint64_t capacity,
+                        int32_t* d_qids, int32_t* d_nids, double* d_dists, uint64_t* n_pairs,
+                        int64_t* next_cursor, void* stream);
+
+/*
+ * The whole join to host memory, for results larger than device memory
+ * (Sec. 3.2's scheme): batches of at most batch_pairs pairs (0: 10^8, the
+ * paper's buffer size) are written on n_streams streams (0: 3, at most 8)
+ * in turn, each batch copied to pinned host buffers of its stream while the
+ * next batches are computed, and handed to `consume` on the calling thread,
+ * in batch order (the order of knn_eps_join_device's batches from cursor 0).
+ * The buffers passed to consume hold n_pairs entries and are valid until it
+ * returns.  consume returns 0 to go on; any other value stops the join
+ * (KNN_ECANCELED).  Device memory: about 16 * batch_pairs * n_streams bytes
+ * plus the level; pinned host memory the same.  Blocks until done.
+ * stats (may be NULL) receives the timings below.
+ */
+typedef int (*knn_eps_consumer)(const int32_t* qids, const int32_t* nids, const double* dists,
+                                uint64_t n_pairs, void* user);
+typedef struct knn_eps_join_stats {
+  uint64_t n_pairs;   /* pairs of the whole join */
+  int64_t n_batches;  /* batches handed to the consumer */
+  double ms_total;    /* wall time of the call */
+  double ms_count;    /* level and exact counts (part of ms_total) */
+  double ms_wait;     /* host time spent waiting for batches to arrive */
+  double ms_consume;  /* host time inside the consumer */
+} knn_eps_join_stats;
+int knn_eps_join(knn_index* idx, double eps, uint64_t batch_pairs, int32_t n_streams,
+                 knn_eps_consumer consume, void* user, knn_eps_join_stats* stats);
+
+/* Frees the level and counts of the distance similarity join. */
+int knn_eps_join_release(knn_index* idx);
 
 /* Frees the index and its device memory.  NULL is a no-op. */
 void knn_destroy_index(knn_index* idx);

@@ -17,6 +17,7 @@ KNN_EDEVICE = -3
 KNN_EBUSY = -4
 KNN_ETIMEOUT = -5
 KNN_EINTERNAL = -6
+KNN_ECANCELED = -7
 KNN_MAX_DIMS = 6
 KNN_MAX_K = 1024
 KNN_MAX_LEVELS = 64
@@ -106,6 +107,17 @@ class ServerStats(ctypes.Structure):
                 ("peak_inflight", c_i32)]
 
 
+class EpsJoinStats(ctypes.Structure):
+    _fields_ = [("n_pairs", c_u64), ("n_batches", c_i64), ("ms_total", c_f64),
+                ("ms_count", c_f64), ("ms_wait", c_f64), ("ms_consume", c_f64)]
+
+
+# int consume(const int32_t* qids, const int32_t* nids, const double* dists,
+#             uint64_t n_pairs, void* user)
+EpsConsumer = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
+                               ctypes.POINTER(c_f64), c_u64, c_p)
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "knn_build_opts_default": (None, [ctypes.POINTER(BuildOpts)]),
@@ -122,6 +134,12 @@ SIGNATURES = {
     "knn_join": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_p, ctypes.POINTER(JoinOpts)]),
     "knn_self_join_device_noalloc": (ctypes.c_int, [c_p, c_i32, c_p, c_p,
                                                     ctypes.POINTER(JoinOpts), c_p]),
+    "knn_eps_join_size": (ctypes.c_int, [c_p, c_f64, c_i64, ctypes.POINTER(c_u64), c_p, c_p]),
+    "knn_eps_join_device": (ctypes.c_int, [c_p, c_f64, c_i64, c_u64, c_p, c_p, c_p,
+                                           ctypes.POINTER(c_u64), ctypes.POINTER(c_i64), c_p]),
+    "knn_eps_join": (ctypes.c_int, [c_p, c_f64, c_u64, c_i32, EpsConsumer, c_p,
+                                    ctypes.POINTER(EpsJoinStats)]),
+    "knn_eps_join_release": (ctypes.c_int, [c_p]),
     "knn_destroy_index": (None, [c_p]),
     "knn_last_error": (ctypes.c_char_p, []),
     "knn_index_info_get": (ctypes.c_int, [c_p, ctypes.POINTER(IndexInfo)]),

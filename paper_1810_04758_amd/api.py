@@ -9,8 +9,8 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (BuildOpts, IndexInfo, JoinOpts, JoinStats, ServerOpts, ServerStats,
-                   check, load)
+from ._lib import (BuildOpts, EpsConsumer, EpsJoinStats, IndexInfo, JoinOpts, JoinStats,
+                   ServerOpts, ServerStats, check, load)
 
 
 def _torch():
@@ -222,6 +222,106 @@ class Index:
         if with_stats:
             return ids, dists, st.as_dict()
         return ids, dists
+
+    # ---- distance similarity self-join (every pair within eps) ----------------
+
+    def eps_join_size(self, eps, sample_stride=1, counts=False, stream=None):
+        """knn_eps_join_size: the exact number of pairs within eps
+        (sample_stride 1; with counts=True also the pairs of each point id, an
+        int32 device tensor of N entries), or the sampled estimate
+        (sample_stride > 1).  Returns n_pairs or (n_pairs, counts)."""
+        torch = _torch()
+        n = ctypes.c_uint64()
+        c = None
+        if counts:
+            c = torch.empty(self.N, dtype=torch.int32,
+                            device=torch.device("cuda", torch.cuda.current_device()))
+        check(load().knn_eps_join_size(self.handle, float(eps), int(sample_stride),
+                                       ctypes.byref(n),
+                                       ctypes.c_void_p(c.data_ptr() if c is not None else 0),
+                                       _stream_ptr(stream)))
+        return (n.value, c) if counts else n.value
+
+    def eps_join_batch(self, eps, cursor, qids, nids, dists, stream=None):
+        """knn_eps_join_device: the next batch from `cursor` into the device
+        tensors qids / nids (int32) and dists (float64), whose common length is
+        the capacity.  Returns (n_pairs, next_cursor)."""
+        torch = _torch()
+        cap = qids.numel()
+        if nids.numel() != cap or dists.numel() != cap:
+            raise ValueError("qids, nids and dists must have the same length")
+        if qids.dtype != torch.int32 or nids.dtype != torch.int32 or dists.dtype != torch.float64:
+            raise ValueError("qids / nids must be int32 and dists float64")
+        for t in (qids, nids, dists):
+            if not (t.is_cuda and t.is_contiguous()):
+                raise ValueError("outputs must be contiguous device tensors")
+        n = ctypes.c_uint64()
+        nxt = ctypes.c_int64()
+        check(load().knn_eps_join_device(self.handle, float(eps), int(cursor), cap,
+                                         ctypes.c_void_p(qids.data_ptr()),
+                                         ctypes.c_void_p(nids.data_ptr()),
+                                         ctypes.c_void_p(dists.data_ptr()), ctypes.byref(n),
+                                         ctypes.byref(nxt), _stream_ptr(stream)))
+        return n.value, nxt.value
+
+    def eps_join_device(self, eps, capacity=0, stream=None):
+        """Every pair within eps on the device, batch by batch (capacity pairs
+        per batch; 0: the exact total, one batch).  Returns (qids, nids, dists)
+        device tensors holding all pairs, in batch order."""
+        torch = _torch()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        total = self.eps_join_size(eps, stream=stream)
+        cap = capacity if capacity > 0 else max(total, 1)
+        q = torch.empty(total, dtype=torch.int32, device=dev)
+        j = torch.empty(total, dtype=torch.int32, device=dev)
+        d = torch.empty(total, dtype=torch.float64, device=dev)
+        bq = torch.empty(cap, dtype=torch.int32, device=dev)
+        bj = torch.empty(cap, dtype=torch.int32, device=dev)
+        bd = torch.empty(cap, dtype=torch.float64, device=dev)
+        cursor, at = 0, 0
+        while cursor < self.N:
+            n, cursor = self.eps_join_batch(eps, cursor, bq, bj, bd, stream=stream)
+            q[at:at + n].copy_(bq[:n])
+            j[at:at + n].copy_(bj[:n])
+            d[at:at + n].copy_(bd[:n])
+            at += n
+        if at != total:
+            raise RuntimeError(f"batches held {at} pairs, the count pass {total}")
+        return q, j, d
+
+    def eps_join(self, eps, consume=None, batch_pairs=0, n_streams=0):
+        """knn_eps_join: every pair within eps streamed to host memory in
+        batches.  consume(qids, nids, dists) gets numpy views valid during the
+        call (return True to stop); without it the pairs are gathered and
+        returned as (qids, nids, dists, stats)."""
+        parts = []
+
+        def _cb(q, j, d, n, _user):
+            n = int(n)
+            qa = np.ctypeslib.as_array(q, shape=(n,)) if n else np.empty(0, np.int32)
+            ja = np.ctypeslib.as_array(j, shape=(n,)) if n else np.empty(0, np.int32)
+            da = np.ctypeslib.as_array(d, shape=(n,)) if n else np.empty(0, np.float64)
+            if consume is None:
+                parts.append((qa.copy(), ja.copy(), da.copy()))
+                return 0
+            return 1 if consume(qa, ja, da) else 0
+
+        cb = EpsConsumer(_cb)
+        st = EpsJoinStats()
+        check(load().knn_eps_join(self.handle, float(eps), int(batch_pairs), int(n_streams), cb,
+                                  None, ctypes.byref(st)))
+        stats = {f: getattr(st, f) for f, _ in EpsJoinStats._fields_}
+        if consume is not None:
+            return stats
+        if parts:
+            q, j, d = (np.concatenate([p[i] for p in parts]) for i in range(3))
+        else:
+            q, j, d = (np.empty(0, np.int32), np.empty(0, np.int32), np.empty(0, np.float64))
+        return q, j, d, stats
+
+    def eps_join_release(self):
+        """knn_eps_join_release: frees the level and counts kept for the last eps."""
+        check(load().knn_eps_join_release(self.handle))
 
     def grid_export(self, cell_width):
         """knn_grid_export: the grid level of the given cell side, on the host."""

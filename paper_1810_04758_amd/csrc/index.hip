@@ -60,18 +60,6 @@ int current_device() {
   return d;
 }
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    KNN_HIP(hipGetDevice(&prev));
-    if (prev != dev) KNN_HIP(hipSetDevice(dev));
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
 int cu_count(int dev) {
   int v = 0;
   KNN_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev));
@@ -84,9 +72,8 @@ int64_t pow3(int e) {
   return r;
 }
 
-// Geometry of the level with cell side w.  The side is enlarged if the grid
-// would not fit the 62-bit key space or 2^30 cells per dimension (a
-// performance policy only: any side gives exact results).
+}  // namespace
+
 GridGeom make_geom(int n, const double* lo, const double* hi, double& w) {
   GridGeom gg{};
   gg.dims = n;
@@ -127,6 +114,8 @@ GridGeom make_geom(int n, const double* lo, const double* hi, double& w) {
   }
   throw Error(KNN_EINTERNAL, "could not choose a grid geometry");
 }
+
+namespace {
 
 // Geometry of the level-0 Z-order grid of cell side w: row-major sizes, and
 // the bits per dimension of the interleaved keys (dims * bits <= 62).  The
@@ -1275,27 +1264,6 @@ using namespace knn;
 
 namespace {
 
-template <class F>
-int guarded(F&& f) {
-  try {
-    f();
-    set_last_error("");
-    return KNN_OK;
-  } catch (const Error& e) {
-    set_last_error(e.what());
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    set_last_error("host allocation failed");
-    return KNN_ENOMEM;
-  } catch (const std::exception& e) {
-    set_last_error(e.what());
-    return KNN_EINTERNAL;
-  } catch (...) {
-    set_last_error("unknown error");
-    return KNN_EINTERNAL;
-  }
-}
-
 knn_build_opts resolve(const knn_build_opts* in) {
   knn_build_opts o{};
   if (in) o = *in;
@@ -1492,16 +1460,6 @@ void join_query_set(knn_index* idx, const double* d_Q, int64_t NQ, int32_t K, in
   self_join(*idx, index_ctx(idx), K, d_ids, d_dists, o, s, nullptr, nullptr, &jq);
 }
 
-struct BusyGuard {
-  knn_index* idx;
-  explicit BusyGuard(knn_index* i) : idx(i) {
-    int expect = 0;
-    KNN_CHECK(idx->busy.compare_exchange_strong(expect, 1), KNN_EBUSY,
-              "another join is running on this index");
-  }
-  ~BusyGuard() { idx->busy.store(0); }
-};
-
 }  // namespace
 
 extern "C" {
@@ -1685,6 +1643,8 @@ void knn_destroy_index(knn_index* idx) {
     idx->graph = nullptr;
     delete idx->ctx;
     idx->ctx = nullptr;
+    destroy_eps_state(idx->eps);
+    idx->eps = nullptr;
     delete idx;
   } catch (...) {
   }

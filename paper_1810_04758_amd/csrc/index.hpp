@@ -10,6 +10,7 @@
 
 namespace knn {
 struct GraphPlan;
+struct EpsJoinState;
 }
 
 struct knn_index {
@@ -33,6 +34,7 @@ struct knn_index {
   std::atomic<int> busy{0};
   struct JoinContextHolder* ctx = nullptr;  // scratch of knn_self_join*
   knn::GraphPlan* graph = nullptr;          // last captured join (use_graph)
+  knn::EpsJoinState* eps = nullptr;         // distance similarity join state
 };
 
 namespace knn {
@@ -210,6 +212,62 @@ uint64_t fixed_scratch_bytes(const knn_index& idx, int32_t K, const knn_join_opt
 void reserve_fixed_scratch(const knn_index& idx, JoinContext& ctx, int32_t K,
                            const knn_join_opts& o, hipStream_t s);
 void validate_join(const knn_index* idx, int32_t K);
+// Geometry of the level with cell side w.  The side is enlarged (w updated)
+// if the grid would not fit the 62-bit key space or 2^30 cells per dimension
+// (a performance policy only: any side gives exact results).
+GridGeom make_geom(int n, const double* lo, const double* hi, double& w);
+
+// The state of the distance similarity self-join an index keeps between
+// calls (epsjoin_rt.hip); freed with the index.
+struct EpsJoinState;
+void destroy_eps_state(EpsJoinState* st);
+
+// Makes `dev` current for a scope.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    KNN_HIP(hipGetDevice(&prev));
+    if (prev != dev) KNN_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// One join at a time per index (KNN_EBUSY otherwise).
+struct BusyGuard {
+  knn_index* idx;
+  explicit BusyGuard(knn_index* i) : idx(i) {
+    int expect = 0;
+    KNN_CHECK(idx->busy.compare_exchange_strong(expect, 1), KNN_EBUSY,
+              "another join is running on this index");
+  }
+  ~BusyGuard() { idx->busy.store(0); }
+};
+
+// Runs f at the C ABI edge: KNN_OK, or the code of the exception it threw
+// (its message to knn_last_error).
+template <class F>
+int guarded(F&& f) {
+  try {
+    f();
+    set_last_error("");
+    return KNN_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return KNN_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return KNN_EINTERNAL;
+  } catch (...) {
+    set_last_error("unknown error");
+    return KNN_EINTERNAL;
+  }
+}
 
 }  // namespace knn
 

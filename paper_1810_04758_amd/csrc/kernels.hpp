@@ -208,6 +208,52 @@ void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sam
                            int64_t ns, double inv_bw, int n_bins, uint64_t* counts,
                            hipStream_t s, int count_bins = 0, int64_t pstride = 1);
 
+// ---- distance similarity self-join (epsjoin.hip) ----
+// One row-major grid level (ranges / rslot / nrng, R segments per cell) whose
+// cell side w covers the search distance, and the squared-distance limit t
+// (the largest d^2 whose correctly rounded square root is <= eps).
+// Count pass: counts[slot] = the points j != p of position p = slot * stride
+// with d^2(p, j) <= t.  Write pass (counts of every position, off = their
+// exclusive prefix, N + 1 entries): the pairs of the positions [first, last)
+// at out + off[p] - off[first], as (id of p, id of j, sqrt(d^2)).
+struct EpsPassArgs {
+  const double* Xs;        // sorted coordinates, point-major: Xs[p*point_stride(n) + j]
+  int64_t N;
+  const int32_t* perm;     // sorted position -> id
+  const uint32_t* cell_of;
+  const uint32_t* ranges;
+  const uint8_t* rslot;
+  const uint32_t* nrng;
+  int32_t R;
+  GridGeom gg;
+  double w;                // the level's cell side
+  double margin;           // rounding of a cell coordinate, in cells
+  double t;
+  int64_t stride = 1;      // count pass: every stride-th position
+  int64_t first = 0, last = 0;  // write pass: sorted positions
+  uint32_t* counts = nullptr;
+  const uint64_t* off = nullptr;
+  int32_t* out_q = nullptr;
+  int32_t* out_j = nullptr;
+  double* out_d = nullptr;
+};
+void launch_eps_count(const EpsPassArgs& a, hipStream_t s);
+void launch_eps_write(const EpsPassArgs& a, hipStream_t s);
+// Elements of the tile array launch_offsets needs for n counts.
+int64_t eps_scan_tiles(int64_t n);
+// off[0..n] = exclusive prefix of counts[0..n) (off[n] = the total).
+void launch_offsets(const uint32_t* counts, int64_t n, uint64_t* tiles, uint64_t* off,
+                    hipStream_t s);
+// Greedy batches of positions from `first` whose pairs fit cap: bounds[2b] =
+// end position of batch b, bounds[2b+1] = its end offset; status[0] = the
+// batches written (at most maxb; -1: one position alone exceeds cap, its
+// pair count in status[2]), status[1] = off[first].
+void launch_batch_bounds(const uint64_t* off, int64_t n, int64_t first, uint64_t cap,
+                         int64_t maxb, int64_t* bounds, int64_t* status, hipStream_t s);
+// out[perm[p]] = counts[p].
+void launch_counts_by_id(const uint32_t* counts, const int32_t* perm, int64_t n, int32_t* out,
+                         hipStream_t s);
+
 // ---- search (search.hip) ----
 struct SearchArgs {
   const double* Xs;        // sorted coordinates, point-major: Xs[p*point_stride(n) + j]

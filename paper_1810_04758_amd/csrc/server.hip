@@ -152,23 +152,6 @@ double percentile(std::vector<double> v, double p) {
   return v[i];
 }
 
-template <class F>
-int guarded(F&& f) {
-  try {
-    f();
-    return KNN_OK;
-  } catch (const Error& e) {
-    set_last_error(e.what());
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    set_last_error("host allocation failed");
-    return KNN_ENOMEM;
-  } catch (const std::exception& e) {
-    set_last_error(e.what());
-    return KNN_EINTERNAL;
-  }
-}
-
 }  // namespace
 }  // namespace knn
 
