@@ -263,6 +263,60 @@ int knn_self_join_device_noalloc(knn_index* idx, int32_t K, int32_t* d_ids,
                                  void* stream);
 
 /* ------------------------------------------------------------------------
+ * Hybrid CPU/GPU KNN self-join (Sec. 4.1-4.5, Alg. 1 with its CPU ranks):
+ * the same result as knn_self_join, with the queries split between the GPU
+ * and host threads through one work queue.  The queue holds the point ids
+ * ordered by the point count of their own cell at eps_min(K), densest first
+ * (Sec. 4.5).  The GPU takes batches from the dense end and searches each at
+ * one eps (cell side eps; first eps = eps_factor * eps_min(K)); the queries
+ * it cannot prove go back to the front of the queue, and eps grows by
+ * eps_min / 2 when more than a quarter of a batch failed (Alg. 1).  Host
+ * threads take batches from the sparse end and solve them exactly with a
+ * kd-tree over all points (built on first use, kept with the index).
+ * Batch schedule, all sizes fractions of N: a monolithic GPU batch of
+ * n_large, then after each round n_large' = min(n_large / 2, max(0, 1 -
+ * done_gpu - done_cpu - n_cwin)) (the window n_cwin stays reserved for the
+ * CPU), until it reaches 0; then GPU batches of n_small; CPU batches of
+ * n_cpu; both small sizes halve once 95 % of the queries are done.
+ * ------------------------------------------------------------------------ */
+typedef struct knn_hybrid_opts {
+  double n_large;     /* first monolithic GPU batch [0.4]; < 0: none */
+  double n_small;     /* GPU batch after the monolithic rounds [0.005] */
+  double n_cwin;      /* window reserved for the CPU [0.4]; < 0: none */
+  double n_cpu;       /* CPU batch [0.005] */
+  double eps_factor;  /* first eps = eps_factor * eps_min(K) [1] */
+  int32_t cpu_threads;/* host threads [hardware threads - 1]; < 0: none (the
+                         GPU takes every batch) */
+  int32_t zorder;     /* the GPU's level structure, as knn_join_opts.zorder */
+} knn_hybrid_opts;
+typedef struct knn_hybrid_stats {
+  double ms_total;        /* T: the whole call */
+  double ms_gpu;          /* T_GPU: when the GPU finished its last batch */
+  double ms_cpu;          /* T_CPU: when the last host thread finished */
+  double load_imbalance;  /* |T_CPU - T_GPU| / T (Sec. 5.5); 0 without threads */
+  double ms_queue;        /* building the work queue (part of T) */
+  double ms_cpu_index;    /* building the kd-tree in this call (0 if kept) */
+  double eps_min;         /* eps_min(K) */
+  double eps_final;       /* the GPU's eps at the end */
+  int64_t gpu_queries;    /* queries solved by the GPU */
+  int64_t cpu_queries;    /* queries solved by the host threads */
+  int64_t gpu_attempts;   /* queries given to the GPU, failures counted again */
+  int32_t gpu_batches;
+  int32_t monolithic_batches;
+  int32_t reindexes;      /* eps increases */
+  int32_t cpu_threads;
+} knn_hybrid_stats;
+/*
+ * ids / dists: host, N x K each (row i = point i, nearest first, the order
+ * and distances of knn_self_join).  1 <= K <= min(N - 1, KNN_MAX_K - 1).
+ * opts and stats may be NULL.  Blocks until done.
+ * Errors: KNN_EINVAL (K out of range, n_small or n_cpu negative, NULL
+ * outputs), KNN_ENOMEM, KNN_EDEVICE, KNN_EBUSY.
+ */
+int knn_self_join_hybrid(knn_index* idx, int32_t K, int32_t* ids, double* dists,
+                         const knn_hybrid_opts* opts, knn_hybrid_stats* stats);
+
+/* ------------------------------------------------------------------------
  * Distance similarity self-join (Sec. 1 and Sec. 3: the range-query join
  * whose GPU kernel the KNN join is built from).  Result: every ordered pair
  * (i, j) of points of D with j != i and fl(sqrt(d2(i, j))) <= eps, d2 the
@@ -329,7 +383,9 @@ int knn_eps_join_device(knn_index* idx, double eps, int64_t cursor, uint64_t cap
  * The buffers passed to consume hold n_pairs entries and are valid until it
  * returns.  consume returns 0 to go on; any other value stops the join
  * (KNN_ECANCELED).  Device memory: about 16 * batch_pairs * n_streams bytes
- * plus the level; pinned host memory the same.  Blocks until done.
+ * plus the level; pinned host memory the same (batch_pairs is capped at the
+ * result size).  The streams and both kinds of buffers stay with the index's
+ * state for later calls (freed as the level is).  Blocks until done.
  * stats (may be NULL) receives the timings below.
  */
 typedef int (*knn_eps_consumer)(const int32_t* qids, const int32_t* nids, const double* dists,

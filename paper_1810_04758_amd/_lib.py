@@ -107,6 +107,19 @@ class ServerStats(ctypes.Structure):
                 ("peak_inflight", c_i32)]
 
 
+class HybridOpts(ctypes.Structure):
+    _fields_ = [("n_large", c_f64), ("n_small", c_f64), ("n_cwin", c_f64), ("n_cpu", c_f64),
+                ("eps_factor", c_f64), ("cpu_threads", c_i32), ("zorder", c_i32)]
+
+
+class HybridStats(ctypes.Structure):
+    _fields_ = [("ms_total", c_f64), ("ms_gpu", c_f64), ("ms_cpu", c_f64),
+                ("load_imbalance", c_f64), ("ms_queue", c_f64), ("ms_cpu_index", c_f64),
+                ("eps_min", c_f64), ("eps_final", c_f64), ("gpu_queries", c_i64),
+                ("cpu_queries", c_i64), ("gpu_attempts", c_i64), ("gpu_batches", c_i32),
+                ("monolithic_batches", c_i32), ("reindexes", c_i32), ("cpu_threads", c_i32)]
+
+
 class EpsJoinStats(ctypes.Structure):
     _fields_ = [("n_pairs", c_u64), ("n_batches", c_i64), ("ms_total", c_f64),
                 ("ms_count", c_f64), ("ms_wait", c_f64), ("ms_consume", c_f64)]
@@ -134,6 +147,8 @@ SIGNATURES = {
     "knn_join": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_p, ctypes.POINTER(JoinOpts)]),
     "knn_self_join_device_noalloc": (ctypes.c_int, [c_p, c_i32, c_p, c_p,
                                                     ctypes.POINTER(JoinOpts), c_p]),
+    "knn_self_join_hybrid": (ctypes.c_int, [c_p, c_i32, c_p, c_p, ctypes.POINTER(HybridOpts),
+                                             ctypes.POINTER(HybridStats)]),
     "knn_eps_join_size": (ctypes.c_int, [c_p, c_f64, c_i64, ctypes.POINTER(c_u64), c_p, c_p]),
     "knn_eps_join_device": (ctypes.c_int, [c_p, c_f64, c_i64, c_u64, c_p, c_p, c_p,
                                            ctypes.POINTER(c_u64), ctypes.POINTER(c_i64), c_p]),

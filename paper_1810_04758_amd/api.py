@@ -9,8 +9,8 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (BuildOpts, EpsConsumer, EpsJoinStats, IndexInfo, JoinOpts, JoinStats,
-                   ServerOpts, ServerStats, check, load)
+from ._lib import (BuildOpts, EpsConsumer, EpsJoinStats, HybridOpts, HybridStats, IndexInfo,
+                   JoinOpts, JoinStats, ServerOpts, ServerStats, check, load)
 
 
 def _torch():
@@ -222,6 +222,21 @@ class Index:
         if with_stats:
             return ids, dists, st.as_dict()
         return ids, dists
+
+    def self_join_hybrid(self, K, n_large=0.0, n_small=0.0, n_cwin=0.0, n_cpu=0.0,
+                         eps_factor=0.0, cpu_threads=0, zorder=0):
+        """knn_self_join_hybrid: the KNN self-join split between the GPU (dense
+        end of the work queue) and host threads (sparse end).  Returns
+        (ids int32 [N,K], dists float64 [N,K], stats dict) in host memory."""
+        ids = np.empty((self.N, K), dtype=np.int32)
+        dists = np.empty((self.N, K), dtype=np.float64)
+        o = HybridOpts(n_large=n_large, n_small=n_small, n_cwin=n_cwin, n_cpu=n_cpu,
+                       eps_factor=eps_factor, cpu_threads=cpu_threads, zorder=zorder)
+        st = HybridStats()
+        check(load().knn_self_join_hybrid(self.handle, K, ids.ctypes.data_as(ctypes.c_void_p),
+                                          dists.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o),
+                                          ctypes.byref(st)))
+        return ids, dists, {f: getattr(st, f) for f, _ in HybridStats._fields_}
 
     # ---- distance similarity self-join (every pair within eps) ----------------
 

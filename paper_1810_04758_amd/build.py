@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libknnjoin.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["grid.hip", "search.hip", "eps.hip", "tail.hip", "index.hip", "autotune.hip", "server.hip",
-           "pool.hip", "epsjoin.hip", "epsjoin_rt.hip"]
+           "pool.hip", "epsjoin.hip", "epsjoin_rt.hip", "hybrid.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KNN_OFFLOAD_ARCH", "gfx950")

@@ -8,12 +8,59 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "index.hpp"
 
 namespace knn {
+
+// One stream of the host streaming path with its batch buffers (device and
+// pinned host), kept between calls.
+struct EpsSlot {
+  hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;
+  DevBuf<int32_t> dq, dj;
+  DevBuf<double> dd;
+  int32_t* hq = nullptr;
+  int32_t* hj = nullptr;
+  double* hd = nullptr;
+  size_t host_cap = 0;
+  EpsSlot() = default;
+  EpsSlot(const EpsSlot&) = delete;
+  EpsSlot& operator=(const EpsSlot&) = delete;
+  void free_host() {
+    if (hq) (void)hipHostFree(hq);
+    if (hj) (void)hipHostFree(hj);
+    if (hd) (void)hipHostFree(hd);
+    hq = hj = nullptr;
+    hd = nullptr;
+    host_cap = 0;
+  }
+  void ensure(size_t per) {
+    if (!s) {
+      KNN_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      KNN_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    }
+    dq.reserve(per);
+    dj.reserve(per);
+    dd.reserve(per);
+    if (host_cap < per) {
+      free_host();
+      KNN_HIP(hipHostMalloc((void**)&hq, per * sizeof(int32_t), hipHostMallocDefault));
+      KNN_HIP(hipHostMalloc((void**)&hj, per * sizeof(int32_t), hipHostMallocDefault));
+      KNN_HIP(hipHostMalloc((void**)&hd, per * sizeof(double), hipHostMallocDefault));
+      host_cap = per;
+    }
+  }
+  ~EpsSlot() {
+    if (s) (void)hipStreamSynchronize(s);
+    free_host();
+    if (done) (void)hipEventDestroy(done);
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
 
 // What an index keeps between calls for the eps it last joined with: the
 // grid level (sorted order = the processing order the cursors refer to) and,
@@ -30,6 +77,17 @@ struct EpsJoinState {
   DevBuf<uint64_t> off, tiles;
   DevBuf<int64_t> small;  // batch bounds read-back
   HostBuf<int64_t> pinned;
+  // host streaming: a control stream and the batch streams, created on
+  // first use (the buffers grow to the largest batch asked for)
+  hipStream_t control = nullptr;
+  std::vector<std::unique_ptr<EpsSlot>> slots;
+  ~EpsJoinState() {
+    slots.clear();
+    if (control) {
+      (void)hipStreamSynchronize(control);
+      (void)hipStreamDestroy(control);
+    }
+  }
 };
 
 void destroy_eps_state(EpsJoinState* st) { delete st; }
@@ -177,23 +235,6 @@ void write_batch(const knn_index& idx, EpsJoinState& st, int64_t first, int64_t 
   launch_eps_write(a, s);
 }
 
-struct Slot {
-  hipStream_t s = nullptr;
-  hipEvent_t done = nullptr;
-  DevBuf<int32_t> dq, dj;
-  DevBuf<double> dd;
-  int32_t* hq = nullptr;
-  int32_t* hj = nullptr;
-  double* hd = nullptr;
-  ~Slot() {
-    if (done) (void)hipEventDestroy(done);
-    if (s) (void)hipStreamDestroy(s);
-    if (hq) (void)hipHostFree(hq);
-    if (hj) (void)hipHostFree(hj);
-    if (hd) (void)hipHostFree(hd);
-  }
-};
-
 }  // namespace
 
 }  // namespace knn
@@ -285,47 +326,34 @@ int knn_eps_join(knn_index* idx, double eps, uint64_t batch_pairs, int32_t n_str
     DeviceGuard dg(idx->device);
     const double t0 = now_ms();
     knn_eps_join_stats sts{};
-    // one control stream (level, counts, batch bounds) and S batch streams
-    std::vector<Slot> slots(S + 1);
-    for (auto& sl : slots) {
-      KNN_HIP(hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking));
-      KNN_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
-    }
-    hipStream_t s0 = slots[S].s;
     EpsJoinState& st = state_of(idx);
+    if (!st.control) KNN_HIP(hipStreamCreateWithFlags(&st.control, hipStreamNonBlocking));
+    hipStream_t s0 = st.control;
+    ensure_level(*idx, st, eps, s0);
+    ensure_counts(*idx, st, s0);  // synchronises s0: the level and counts are done
+    sts.ms_count = now_ms() - t0;
+    sts.n_pairs = st.total;
+    // batch b runs on slot b % S: its kernel and its copy to the slot's host
+    // buffers are queued while earlier batches are still copied or consumed;
+    // a slot's buffers are reused only after the consumer has returned from
+    // the batch S before
+    const size_t per = (size_t)std::min<uint64_t>(cap, std::max<uint64_t>(st.total, 1));
+    while ((int)st.slots.size() < S) st.slots.emplace_back(new EpsSlot());
+    std::vector<uint64_t> count_of;  // pairs of the batches issued, by batch
+    int64_t issued = 0, consumed = 0;
+    auto finish = [&](int64_t b) {
+      EpsSlot& sl = *st.slots[b % S];
+      const double w0 = now_ms();
+      KNN_HIP(hipEventSynchronize(sl.done));
+      const double w1 = now_ms();
+      sts.ms_wait += w1 - w0;
+      const int rc = consume(sl.hq, sl.hj, sl.hd, count_of[b], user);
+      sts.ms_consume += now_ms() - w1;
+      KNN_CHECK(rc == 0, KNN_ECANCELED,
+                "the consumer stopped the join (returned " + std::to_string(rc) + ")");
+      ++consumed;
+    };
     try {
-      ensure_level(*idx, st, eps, s0);
-      ensure_counts(*idx, st, s0);  // synchronises s0: the level and counts are done
-      sts.ms_count = now_ms() - t0;
-      sts.n_pairs = st.total;
-      const size_t per = (size_t)std::min<uint64_t>(cap, std::max<uint64_t>(st.total, 1));
-      for (int i = 0; i < S; ++i) {
-        Slot& sl = slots[i];
-        sl.dq.reserve(per);
-        sl.dj.reserve(per);
-        sl.dd.reserve(per);
-        KNN_HIP(hipHostMalloc((void**)&sl.hq, per * sizeof(int32_t), hipHostMallocDefault));
-        KNN_HIP(hipHostMalloc((void**)&sl.hj, per * sizeof(int32_t), hipHostMallocDefault));
-        KNN_HIP(hipHostMalloc((void**)&sl.hd, per * sizeof(double), hipHostMallocDefault));
-      }
-      // batch b runs on slot b % S: its kernel and its copy to the slot's
-      // host buffers are queued while earlier batches are still copied or
-      // consumed; the slot's buffers are reused only after the consumer
-      // returned from the batch S before
-      std::vector<uint64_t> count_of;  // pairs of the batches issued, by batch
-      int64_t issued = 0, consumed = 0;
-      auto finish = [&](int64_t b) {
-        Slot& sl = slots[b % S];
-        const double w0 = now_ms();
-        KNN_HIP(hipEventSynchronize(sl.done));
-        const double w1 = now_ms();
-        sts.ms_wait += w1 - w0;
-        const int rc = consume(sl.hq, sl.hj, sl.hd, count_of[b], user);
-        sts.ms_consume += now_ms() - w1;
-        KNN_CHECK(rc == 0, KNN_ECANCELED,
-                  "the consumer stopped the join (returned " + std::to_string(rc) + ")");
-        ++consumed;
-      };
       int64_t cursor = 0;
       std::vector<int64_t> ends;
       while (cursor < idx->N) {
@@ -335,7 +363,8 @@ int knn_eps_join(knn_index* idx, double eps, uint64_t batch_pairs, int32_t n_str
         for (int64_t k = 0; k < nb; ++k) {
           const int64_t b = issued;
           if (b >= S) finish(b - S);
-          Slot& sl = slots[b % S];
+          EpsSlot& sl = *st.slots[b % S];
+          sl.ensure(per);  // no-op once sized (the slot's last batch is consumed)
           const int64_t last = ends[2 * k];
           const uint64_t np = (uint64_t)ends[2 * k + 1] - start;
           write_batch(*idx, st, cursor, last, sl.dq.p, sl.dj.p, sl.dd.p, sl.s);
@@ -354,10 +383,10 @@ int knn_eps_join(knn_index* idx, double eps, uint64_t batch_pairs, int32_t n_str
       while (consumed < issued) finish(consumed);
       sts.n_batches = issued;
     } catch (...) {
-      for (auto& sl : slots) (void)hipStreamSynchronize(sl.s);
+      for (auto& sl : st.slots)
+        if (sl->s) (void)hipStreamSynchronize(sl->s);
       throw;
     }
-    for (auto& sl : slots) KNN_HIP(hipStreamSynchronize(sl.s));
     sts.ms_total = now_ms() - t0;
     if (stats) *stats = sts;
   });

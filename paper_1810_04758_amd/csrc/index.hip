@@ -517,7 +517,7 @@ static int lanes_for(int dims, double cand, int64_t A, int cap, bool zl) {
 
 void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, double* d_dists,
                const knn_join_opts& o, hipStream_t s, std::vector<LevelPlan>* record,
-               const std::vector<LevelPlan>* replay, const JoinQueries* jq) {
+               const std::vector<LevelPlan>* replay, const JoinQueries* jq, JoinLimit* lim) {
   // rj: a join of the query set jq with the index's points (R join S,
   // Sec. 2.1); the queries are appended to the sorted point array (positions
   // N .. N + NQ - 1), lie in no cell, and get their ranges slot by slot
@@ -532,6 +532,11 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     validate_join(&idx, K);
   }
   KNN_CHECK(d_ids && d_dists, KNN_EINVAL, "output pointers are NULL");
+  KNN_CHECK(!lim || (rj && !replay && !record && (lim->max_levels <= 0 || lim->unsolved)),
+            KNN_EINTERNAL, "a level limit needs a query set and an unsolved list");
+  if (lim) lim->n_unsolved = 0;
+  const bool keep_l0 = lim && lim->reuse_level0;
+  if (!keep_l0) c.l0_cached = false;  // this join rebuilds the context's levels
   auto t_start = std::chrono::steady_clock::now();
   const int64_t N = idx.N;
   const int64_t NQ = rj ? jq->NQ : 0;
@@ -603,14 +608,16 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     // the point arrays hold the queries after the indexed points, in both
     // buffers of the row-major level pair
     const int S = point_stride(idx.n);
-    c.Xs.reserve((size_t)NP * S);
-    c.perm.reserve(NP);
+    // a kept level 0 lives in these buffers: growing one drops it
+    bool moved = c.Xs.reserve((size_t)NP * S);
+    moved |= c.perm.reserve(NP);
     c.vals2.reserve(NP);
-    c.cell_of.reserve(NP);
+    moved |= c.cell_of.reserve(NP);
     if (!zl) {
-      c.Xs2.reserve((size_t)NP * S);
-      c.perm2.reserve(NP);
+      moved |= c.Xs2.reserve((size_t)NP * S);
+      moved |= c.perm2.reserve(NP);
     }
+    if (moved) c.l0_cached = false;
     const int64_t NM = std::max(N, NQ);
     c.tmp.reserve(radix_tmp_elems(NM));
     if (c.scan_state.reserve(scan_state_elems(NM)))
@@ -631,6 +638,28 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       rp = &(*replay)[level];
     }
     LevelPlan lp;
+    if (lim && lim->max_levels > 0 && level == lim->max_levels) {
+      // cut short: list the queries left (as the tail below does) and hand
+      // their query indices back
+      int32_t* list = c.fail_list.p;
+      if (zl) {
+        launch_active_list(c.failed.p + N, level_tag(level), nullptr, NQ, c.active.p,
+                           c.scal.p + 1, c.scan_state.p, (int64_t)c.scan_state.n, s, true,
+                           (int32_t)N);
+        c.pinned.reserve(kCounterInts + 16 + KNN_MAX_LEVELS);
+        KNN_HIP(hipMemcpyAsync(c.pinned.p, c.scal.p + 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               s));
+        KNN_HIP(hipStreamSynchronize(s));
+        KNN_CHECK((int64_t)(uint32_t)c.pinned.p[0] == remaining, KNN_EINTERNAL,
+                  "cut: the flagged queries differ from the count left");
+        list = c.active.p;
+      }
+      launch_pos_to_id(list, remaining, c.perm.p, s);
+      KNN_HIP(hipMemcpyAsync(lim->unsolved, list, (size_t)remaining * sizeof(int32_t),
+                             hipMemcpyDeviceToDevice, s));
+      lim->n_unsolved = remaining;
+      break;
+    }
     // brute-force tail once few queries remain (their ids are in fail_list)
     // (remaining: the queries left, A of them active at this level; Z-order
     // levels may hold more, deferred to later levels)
@@ -698,13 +727,24 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     ev.rec(0, s);
     // level 0 sorts the points from their original order, later levels from
     // the previous level's order (row-major) or not at all (Z-order)
-    if (zl) {
+    const bool reuse = level == 0 && keep_l0 && c.l0_cached && c.l0_w == w && c.l0_zl == zl;
+    if (reuse) {
+      // level 0 of the previous query-set join with this cell side: the
+      // indexed points' grid is unchanged (only the appended queries differ)
+    } else if (zl) {
       // the top of the ladder is one cell, where every query succeeds
       KNN_CHECK(level == 0 || level <= c.gz0.zbits, KNN_EINTERNAL,
                 "Z-order levels ran past their single-cell top");
       build_grid_z(idx, c, w0, level, s);
     } else {
       build_grid(idx, c, w, s, level > 0);
+    }
+    if (level == 0 && keep_l0) {
+      c.l0_cached = true;
+      c.l0_w = w;
+      c.l0_zl = zl;
+    } else if (level > 0) {
+      c.l0_cached = false;
     }
     if (rj && level == 0) {
       // the queries, sorted by their level-0 cell key (locality), appended
@@ -1645,6 +1685,8 @@ void knn_destroy_index(knn_index* idx) {
     idx->ctx = nullptr;
     destroy_eps_state(idx->eps);
     idx->eps = nullptr;
+    destroy_hybrid_state(idx->hybrid);
+    idx->hybrid = nullptr;
     delete idx;
   } catch (...) {
   }

@@ -11,6 +11,7 @@
 namespace knn {
 struct GraphPlan;
 struct EpsJoinState;
+struct HybridState;
 }
 
 struct knn_index {
@@ -35,6 +36,7 @@ struct knn_index {
   struct JoinContextHolder* ctx = nullptr;  // scratch of knn_self_join*
   knn::GraphPlan* graph = nullptr;          // last captured join (use_graph)
   knn::EpsJoinState* eps = nullptr;         // distance similarity join state
+  knn::HybridState* hybrid = nullptr;       // the hybrid join's host index
 };
 
 namespace knn {
@@ -92,6 +94,10 @@ struct JoinContext {
   // table are used only up to kFixedTableFactor * N entries
   bool fixed = false;
   int64_t table_cap = 0;  // > 0: that limit; 0: the default limits
+  // level 0 of a query-set join kept for the next one (JoinLimit::reuse_level0)
+  bool l0_cached = false;
+  double l0_w = 0;
+  bool l0_zl = false;
 
   int64_t device_bytes() const;
 };
@@ -156,6 +162,20 @@ struct JoinQueries {
   double hi[KNN_MAX_DIMS] = {0};
 };
 
+// A query-set join cut short after max_levels levels (the GPU component of
+// the hybrid join, Alg. 1: each batch is searched at one eps and the queries
+// that fail go back to the work queue): the query indices left unsolved go
+// to `unsolved` (device, NQ entries; their output rows are not written) and
+// their number to n_unsolved.  reuse_level0: keep the level-0 grid in the
+// context and skip its build when the next such join asks for the same cell
+// side (the indexed points never change).
+struct JoinLimit {
+  int max_levels = 0;
+  int32_t* unsolved = nullptr;
+  int64_t n_unsolved = 0;
+  bool reuse_level0 = false;
+};
+
 struct JoinParams {
   int32_t K;
   knn_join_opts opts;
@@ -193,7 +213,7 @@ void self_join(const knn_index& idx, JoinContext& ctx, int32_t K, int32_t* d_ids
                double* d_dists, const knn_join_opts& o, hipStream_t s,
                std::vector<LevelPlan>* record = nullptr,
                const std::vector<LevelPlan>* replay = nullptr,
-               const JoinQueries* jq = nullptr);
+               const JoinQueries* jq = nullptr, JoinLimit* lim = nullptr);
 // use_graph: the first join of (index, K, options, outputs) runs eagerly and
 // captures its launch sequence; later ones launch the graph.
 void self_join_graph(knn_index& idx, int32_t K, int32_t* d_ids, double* d_dists,
@@ -221,6 +241,9 @@ GridGeom make_geom(int n, const double* lo, const double* hi, double& w);
 // calls (epsjoin_rt.hip); freed with the index.
 struct EpsJoinState;
 void destroy_eps_state(EpsJoinState* st);
+// The hybrid join's host-side index (hybrid.hip); freed with the index.
+struct HybridState;
+void destroy_hybrid_state(HybridState* h);
 
 // Makes `dev` current for a scope.
 struct DeviceGuard {

@@ -54,9 +54,10 @@ def test_struct_sizes_match_header():
 #include <stdio.h>
 #include "knnjoin.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(knn_build_opts), sizeof(knn_join_opts),
-         sizeof(knn_join_stats), sizeof(knn_index_info), sizeof(knn_server_opts),
-         sizeof(knn_server_stats), sizeof(knn_autotune_result), sizeof(knn_eps_join_stats));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(knn_build_opts),
+         sizeof(knn_join_opts), sizeof(knn_join_stats), sizeof(knn_index_info),
+         sizeof(knn_server_opts), sizeof(knn_server_stats), sizeof(knn_autotune_result),
+         sizeof(knn_eps_join_stats), sizeof(knn_hybrid_opts), sizeof(knn_hybrid_stats));
   return 0;
 }
 '''
@@ -69,4 +70,5 @@ int main(void) {
     assert sizes == [ctypes.sizeof(t) for t in (_lib.BuildOpts, _lib.JoinOpts, _lib.JoinStats,
                                                 _lib.IndexInfo, _lib.ServerOpts,
                                                 _lib.ServerStats, _lib.AutotuneResult,
-                                                _lib.EpsJoinStats)]
+                                                _lib.EpsJoinStats, _lib.HybridOpts,
+                                                _lib.HybridStats)]
