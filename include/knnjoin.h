@@ -296,6 +296,8 @@ typedef struct knn_hybrid_stats {
   double load_imbalance;  /* |T_CPU - T_GPU| / T (Sec. 5.5); 0 without threads */
   double ms_queue;        /* building the work queue (part of T) */
   double ms_cpu_index;    /* building the kd-tree in this call (0 if kept) */
+  double ms_merge;        /* copying the GPU's rows into the host outputs (part
+                             of T, after T_GPU and T_CPU) */
   double eps_min;         /* eps_min(K) */
   double eps_final;       /* the GPU's eps at the end */
   int64_t gpu_queries;    /* queries solved by the GPU */

@@ -115,7 +115,7 @@ class HybridOpts(ctypes.Structure):
 class HybridStats(ctypes.Structure):
     _fields_ = [("ms_total", c_f64), ("ms_gpu", c_f64), ("ms_cpu", c_f64),
                 ("load_imbalance", c_f64), ("ms_queue", c_f64), ("ms_cpu_index", c_f64),
-                ("eps_min", c_f64), ("eps_final", c_f64), ("gpu_queries", c_i64),
+                ("ms_merge", c_f64), ("eps_min", c_f64), ("eps_final", c_f64), ("gpu_queries", c_i64),
                 ("cpu_queries", c_i64), ("gpu_attempts", c_i64), ("gpu_batches", c_i32),
                 ("monolithic_batches", c_i32), ("reindexes", c_i32), ("cpu_threads", c_i32)]
 

@@ -228,23 +228,42 @@ __global__ void k_take_ids(const int32_t* __restrict__ rows, int64_t nr,
 // included, at distance 0) -> its K nearest j != ids[b]: the list without
 // that id, or its first K entries when the id is not in it (K+1 other
 // points at distance 0 with lower ids).  Rows flagged unsolved are skipped.
+// The rows go to out_ids / out_d row `self` (N x K, by id), and solved[self]
+// is set.
 __global__ void k_drop_self(const int32_t* __restrict__ ids1, const double* __restrict__ d1,
                             const int32_t* __restrict__ qid, const uint8_t* __restrict__ unsolved,
                             int64_t nb, int K, int32_t* __restrict__ out_ids,
-                            double* __restrict__ out_d) {
+                            double* __restrict__ out_d, uint8_t* __restrict__ solved) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
        b += (int64_t)gridDim.x * blockDim.x) {
     if (unsolved[b]) continue;
     const int32_t self = qid[b];
     const int32_t* ri = ids1 + b * (K + 1);
     const double* rd = d1 + b * (K + 1);
+    int32_t* oi = out_ids + (int64_t)self * K;
+    double* od = out_d + (int64_t)self * K;
     int o = 0;
     for (int k = 0; k <= K && o < K; ++k) {
       if (ri[k] == self) continue;
-      out_ids[b * K + o] = ri[k];
-      out_d[b * K + o] = rd[k];
+      oi[o] = ri[k];
+      od[o] = rd[k];
       ++o;
     }
+    solved[self] = 1;
+  }
+}
+
+// Rows list[r] of the N x K arrays into consecutive rows of the outputs.
+__global__ void k_gather_rows(const int32_t* __restrict__ list, int64_t nr, int K,
+                              const int32_t* __restrict__ ids, const double* __restrict__ d,
+                              int32_t* __restrict__ out_ids, double* __restrict__ out_d) {
+  const int64_t total = nr * K;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / K, k = e - r * K;
+    const int64_t src = (int64_t)list[r] * K + k;
+    out_ids[e] = ids[src];
+    out_d[e] = d[src];
   }
 }
 
@@ -450,12 +469,14 @@ int knn_self_join_hybrid(knn_index* idx, int32_t K, int32_t* ids, double* dists,
     JoinContext gc;
     gc.device = idx->device;
     DevBuf<double> QA, QX, d1;
-    DevBuf<int32_t> i1, unsolved, uids, rows_i;
-    DevBuf<double> rows_d;
+    DevBuf<int32_t> i1, unsolved, uids;
     DevBuf<uint8_t> flags;
-    HostBuf<int32_t> h_rows_i, h_uids;
-    HostBuf<double> h_rows_d;
-    HostBuf<uint8_t> h_flags;
+    HostBuf<int32_t> h_uids;
+    // the GPU's rows stay on the device (by id) until the end
+    DevBuf<int32_t> g_ids((size_t)N * K);
+    DevBuf<double> g_d((size_t)N * K);
+    DevBuf<uint8_t> g_solved(N);
+    launch_zero(g_solved.p, (size_t)N, s);
     double t_gpu_end = 0;
     try {
       for (;;) {
@@ -481,8 +502,6 @@ int knn_self_join_hybrid(knn_index* idx, int32_t K, int32_t* ids, double* dists,
         unsolved.reserve(nb);
         uids.reserve(nb);
         flags.reserve(nb);
-        rows_i.reserve((size_t)nb * K);
-        rows_d.reserve((size_t)nb * K);
         k_gather_queries<<<grid_of(nb), kBlock, 0, s>>>(idx->XA.p, n, bids, nb, QA.p, QX.p);
         KNN_LAUNCHED();
         JoinQueries jq;
@@ -510,16 +529,10 @@ int knn_self_join_hybrid(knn_index* idx, int32_t K, int32_t* ids, double* dists,
           k_take_ids<<<grid_of(nf), kBlock, 0, s>>>(unsolved.p, nf, bids, uids.p);
           KNN_LAUNCHED();
         }
-        k_drop_self<<<grid_of(nb), kBlock, 0, s>>>(i1.p, d1.p, bids, flags.p, nb, K, rows_i.p,
-                                                    rows_d.p);
+        k_drop_self<<<grid_of(nb), kBlock, 0, s>>>(i1.p, d1.p, bids, flags.p, nb, K, g_ids.p,
+                                                    g_d.p, g_solved.p);
         KNN_LAUNCHED();
-        h_rows_i.reserve((size_t)nb * K);
-        h_rows_d.reserve((size_t)nb * K);
-        h_flags.reserve(nb);
         h_uids.reserve(std::max<int64_t>(nf, 1));
-        KNN_HIP(hipMemcpyAsync(h_rows_i.p, rows_i.p, (size_t)nb * K * 4, hipMemcpyDeviceToHost, s));
-        KNN_HIP(hipMemcpyAsync(h_rows_d.p, rows_d.p, (size_t)nb * K * 8, hipMemcpyDeviceToHost, s));
-        KNN_HIP(hipMemcpyAsync(h_flags.p, flags.p, (size_t)nb, hipMemcpyDeviceToHost, s));
         if (nf > 0) {
           KNN_HIP(hipMemcpyAsync(h_uids.p, uids.p, (size_t)nf * 4, hipMemcpyDeviceToHost, s));
           // failures go back to the front of the queue: positions
@@ -528,13 +541,6 @@ int knn_self_join_hybrid(knn_index* idx, int32_t K, int32_t* ids, double* dists,
                                  hipMemcpyDeviceToDevice, s));
         }
         KNN_HIP(hipStreamSynchronize(s));
-        const std::vector<int32_t> bh(hqueue.begin() + f0, hqueue.begin() + f0 + nb);
-        for (int64_t b = 0; b < nb; ++b) {
-          if (h_flags.p[b]) continue;
-          const int32_t id = bh[b];
-          std::memcpy(ids + (size_t)id * K, h_rows_i.p + (size_t)b * K, (size_t)K * 4);
-          std::memcpy(dists + (size_t)id * K, h_rows_d.p + (size_t)b * K, (size_t)K * 8);
-        }
         hs.gpu_batches += 1;
         hs.gpu_attempts += nb;
         if (mono) hs.monolithic_batches += 1;
@@ -585,6 +591,76 @@ int knn_self_join_hybrid(knn_index* idx, int32_t K, int32_t* ids, double* dists,
     if (cpu_launcher.joinable()) cpu_launcher.join();
     KNN_CHECK(cpu_error.empty(), KNN_EINTERNAL, "CPU component failed: " + cpu_error);
     KNN_CHECK(done_g + done_c == N, KNN_EINTERNAL, "the work queue lost queries");
+    // the GPU's rows into the host outputs: their ids in increasing order
+    // (a list from the solved flags), gathered into consecutive rows and
+    // copied in chunks (two in flight: the next chunk's copy overlaps the host
+    // threads writing this one), so the host writes move through the outputs
+    // in order
+    if (done_g > 0) {
+      const auto tm = Clock::now();
+      DevBuf<int32_t> glist(N);
+      DevBuf<uint32_t> gcount(1);
+      launch_active_list(g_solved.p, 1, nullptr, N, glist.p, gcount.p, gc.scan_state.p,
+                         (int64_t)gc.scan_state.n, s);
+      const int64_t chunk =
+          std::min<int64_t>(done_g, std::max<int64_t>(1, (64ll << 20) / (12 * (int64_t)K)));
+      std::vector<int32_t> hlist(done_g);
+      KNN_HIP(hipMemcpyAsync(hlist.data(), glist.p, done_g * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      uint32_t listed = 0;
+      KNN_HIP(hipMemcpyAsync(&listed, gcount.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      KNN_HIP(hipStreamSynchronize(s));
+      KNN_CHECK((int64_t)listed == done_g, KNN_EINTERNAL, "GPU rows: flags and counts differ");
+      DevBuf<int32_t> ci[2];
+      DevBuf<double> cd[2];
+      HostBuf<int32_t> hi_[2];
+      HostBuf<double> hd_[2];
+      hipEvent_t ev[2] = {nullptr, nullptr};
+      struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() {
+          for (int i = 0; i < 2; ++i)
+            if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+      } eg{ev};
+      for (int i = 0; i < 2; ++i) {
+        ci[i].reserve((size_t)chunk * K);
+        cd[i].reserve((size_t)chunk * K);
+        hi_[i].reserve((size_t)chunk * K);
+        hd_[i].reserve((size_t)chunk * K);
+        KNN_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+      }
+      const int64_t nchunks = ceil_div(done_g, chunk);
+      auto issue = [&](int64_t c) {
+        const int i = (int)(c & 1);
+        const int64_t r0 = c * chunk, nr = std::min(chunk, done_g - r0);
+        k_gather_rows<<<grid_of(nr * K), kBlock, 0, s>>>(glist.p + r0, nr, K, g_ids.p, g_d.p,
+                                                         ci[i].p, cd[i].p);
+        KNN_LAUNCHED();
+        KNN_HIP(hipMemcpyAsync(hi_[i].p, ci[i].p, (size_t)nr * K * 4, hipMemcpyDeviceToHost, s));
+        KNN_HIP(hipMemcpyAsync(hd_[i].p, cd[i].p, (size_t)nr * K * 8, hipMemcpyDeviceToHost, s));
+        KNN_HIP(hipEventRecord(ev[i], s));
+      };
+      const int nt = std::max(1, std::min(sch.threads > 0 ? sch.threads : 8, 16));
+      issue(0);
+      for (int64_t c = 0; c < nchunks; ++c) {
+        const int i = (int)(c & 1);
+        KNN_HIP(hipEventSynchronize(ev[i]));
+        if (c + 1 < nchunks) issue(c + 1);
+        const int64_t r0 = c * chunk, nr = std::min(chunk, done_g - r0);
+        auto part = [&](int t) {
+          for (int64_t r = nr * t / nt; r < nr * (t + 1) / nt; ++r) {
+            const int32_t id = hlist[r0 + r];
+            std::memcpy(ids + (size_t)id * K, hi_[i].p + (size_t)r * K, (size_t)K * 4);
+            std::memcpy(dists + (size_t)id * K, hd_[i].p + (size_t)r * K, (size_t)K * 8);
+          }
+        };
+        std::vector<std::thread> th;
+        for (int t = 1; t < nt; ++t) th.emplace_back(part, t);
+        part(0);
+        for (auto& x : th) x.join();
+      }
+      hs.ms_merge = ms_since(tm);
+    }
     hs.ms_total = ms_since(t0);
     hs.ms_gpu = t_gpu_end;
     hs.ms_cpu = sch.threads > 0 ? t_cpu_end : 0;
