@@ -350,6 +350,139 @@ def extra_cases(api, stream, names, autotune, reps, sched_sets, graph_sets, host
     return out, sched, graph
 
 
+def _eps_for(idx, per_point, lo, hi, stride=64):
+    """eps holding about per_point pairs per point, by bisection on the
+    sampled result-size estimate (knn_eps_join_size with a stride)."""
+    for _ in range(40):
+        mid = (lo * hi) ** 0.5
+        if idx.eps_join_size(mid, sample_stride=stride) > per_point * idx.N:
+            hi = mid
+        else:
+            lo = mid
+        if hi / lo < 1.02:
+            break
+    return hi
+
+
+def eps_join_leg(api, huge=True):
+    """The distance similarity self-join (every pair within eps) on three
+    workloads, eps chosen for a fixed mean pair count per point: level and
+    exact counts, the device write of all pairs as one batch (the write
+    kernel's output rate against HBM), the sampled estimate's error, and the
+    host streaming rate on 3 streams.  With `huge`, the clustered set at the
+    KNN method's eps_min(16): a result far larger than HBM streamed to host."""
+    import torch
+    from paper_1810_04758_amd import datagen
+    rows = []
+    dev = torch.device("cuda", 0)
+    for name, per_point, lo, hi in [("expo2d_2m", 32, 1e-6, 1.0), ("unif6d_5m", 32, 0.1, 100.0),
+                                    ("clustered2d_20m", 16, 1e-5, 10.0)]:
+        D, _, _ = datagen.config_points(name)
+        Dd = torch.from_numpy(D).cuda()
+        idx = api.build_index(Dd)
+        eps = _eps_for(idx, per_point, lo, hi)
+        t0 = time.perf_counter()
+        total = idx.eps_join_size(eps)
+        ms_count = 1e3 * (time.perf_counter() - t0)
+        est = idx.eps_join_size(eps, sample_stride=64)
+        idx.eps_join_size(eps)  # exact counts again for the batches
+        q = torch.empty(total, dtype=torch.int32, device=dev)
+        j = torch.empty(total, dtype=torch.int32, device=dev)
+        d = torch.empty(total, dtype=torch.float64, device=dev)
+        best = None
+        for _ in range(3):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            n, nxt = idx.eps_join_batch(eps, 0, q, j, d)
+            b.record()
+            torch.cuda.synchronize()
+            assert n == total and nxt == idx.N
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        del q, j, d
+        torch.cuda.empty_cache()
+        st = idx.eps_join(eps, consume=lambda *_: False, batch_pairs=1 << 24, n_streams=3)
+        body = st["ms_total"] - st["ms_count"]
+        out_gb = total * 16 / 1e9
+        rows.append({
+            "dataset": name, "N": int(D.shape[0]), "eps": eps, "pairs": int(total),
+            "pairs_per_point": round(total / D.shape[0], 2),
+            "ms_level_and_counts": round(ms_count, 3),
+            "estimate_stride64_rel_err": round(est / total - 1.0, 5),
+            "ms_write_device": round(best, 3),
+            "pairs_per_s_device": round(total / (best / 1e3), 1),
+            "write_roofline": {"bound": "hbm", "achieved": round(out_gb / (best / 1e3), 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(out_gb / (best / 1e3) / HBM_PEAK_GBS, 4),
+                               "bytes": "16 B of output per pair (the written result only)"},
+            "host_stream_3x2^24": {"ms": round(body, 2), "GB_per_s": round(out_gb / (body / 1e3), 2),
+                                   "batches": st["n_batches"]}})
+        print(f"[bench] eps join {name}: {rows[-1]['pairs']} pairs, write "
+              f"{rows[-1]['ms_write_device']} ms", file=sys.stderr, flush=True)
+        if huge and name == "clustered2d_20m":
+            eh = idx.eps_min(16)
+            seen = [0]
+
+            def cons(qa, ja, da):
+                seen[0] += qa.size
+                return False
+            st = idx.eps_join(eh, consume=cons, batch_pairs=1 << 26, n_streams=3)
+            body = st["ms_total"] - st["ms_count"]
+            gb = st["n_pairs"] * 16 / 1e9
+            rows.append({"dataset": name, "N": int(D.shape[0]), "eps": eh,
+                         "eps_is": "eps_min(16) of the KNN method",
+                         "pairs": int(st["n_pairs"]), "result_GB": round(gb, 1),
+                         "hbm_GB": round(torch.cuda.get_device_properties(0).total_memory / 1e9, 1),
+                         "host_stream_3x2^26": {"ms_total": round(st["ms_total"], 1),
+                                                "ms_count": round(st["ms_count"], 1),
+                                                "GB_per_s": round(gb / (body / 1e3), 2),
+                                                "batches": st["n_batches"],
+                                                "pairs_consumed": int(seen[0])}})
+            print(f"[bench] eps join beyond HBM: {gb:.1f} GB in {st['ms_total']:.0f} ms",
+                  file=sys.stderr, flush=True)
+        idx.close()
+        del Dd
+        torch.cuda.empty_cache()
+    return rows
+
+
+def hybrid_leg(api):
+    """The hybrid CPU/GPU join (host outputs) beside the GPU-only join with
+    host outputs (knn_self_join) on the same workload: times, the split and
+    the load imbalance |T_CPU - T_GPU| / T; the hybrid's second call (its
+    kd-tree is built by the first and kept with the index)."""
+    import torch
+    from paper_1810_04758_amd import datagen
+    rows = []
+    for name, K in [("expo2d_2m", 32), ("clustered2d_20m", 16)]:
+        D, _, _ = datagen.config_points(name)
+        idx = api.build_index(torch.from_numpy(D).cuda())
+        gi, gd = idx.self_join_host(K)
+        t0 = time.perf_counter()
+        gi, gd = idx.self_join_host(K)
+        ms_gpu_only = 1e3 * (time.perf_counter() - t0)
+        _, _, st0 = idx.self_join_hybrid(K)
+        hi, hd, st = idx.self_join_hybrid(K)
+        same = bool(np.array_equal(hi, gi) and np.array_equal(hd, gd))
+        rows.append({"dataset": name, "K": K, "ms_gpu_only_host_out": round(ms_gpu_only, 2),
+                     "ms_hybrid": round(st["ms_total"], 2),
+                     "ms_T_gpu": round(st["ms_gpu"], 2), "ms_T_cpu": round(st["ms_cpu"], 2),
+                     "load_imbalance": round(st["load_imbalance"], 4),
+                     "ms_queue": round(st["ms_queue"], 2), "ms_merge": round(st["ms_merge"], 2),
+                     "ms_cpu_index_first_call": round(st0["ms_cpu_index"], 1),
+                     "gpu_queries": st["gpu_queries"], "cpu_queries": st["cpu_queries"],
+                     "gpu_batches": st["gpu_batches"],
+                     "monolithic_batches": st["monolithic_batches"],
+                     "reindexes": st["reindexes"], "cpu_threads": st["cpu_threads"],
+                     "same_rows_as_gpu_only": same})
+        print(f"[bench] hybrid {name}: {rows[-1]['ms_hybrid']} ms vs GPU-only "
+              f"{rows[-1]['ms_gpu_only_host_out']} ms", file=sys.stderr, flush=True)
+        idx.close()
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,6 +512,12 @@ def main():
     ap.add_argument("--autotune-cache", default="",
                     help="file of autotuner choices: written after the autotune pass, "
                          "read instead of tuning with --no-autotune")
+    ap.add_argument("--no-eps-join", action="store_true",
+                    help="skip the distance similarity self-join leg")
+    ap.add_argument("--no-eps-huge", action="store_true",
+                    help="skip the eps join whose result is larger than HBM (streamed to host)")
+    ap.add_argument("--no-hybrid", action="store_true",
+                    help="skip the hybrid CPU/GPU join leg")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain fp64 copy kernel (y = -x) over "
                          "this many MiB, the reference dispatch for scaling HBM counters")
@@ -538,6 +677,12 @@ def main():
         te = sum(r["ms_eager"] for r in graph_rows)
         tg = sum(r["ms_graph_replay"] for r in graph_rows)
         out["graph_vs_eager"] = {"cases": graph_rows, "speedup": round(te / tg, 3)}
+    if not args.no_eps_join:
+        print("[bench] eps join", file=sys.stderr, flush=True)
+        out["eps_join"] = eps_join_leg(api, huge=not args.no_eps_huge)
+    if not args.no_hybrid:
+        print("[bench] hybrid", file=sys.stderr, flush=True)
+        out["hybrid"] = hybrid_leg(api)
     if args.serving_seconds > 0 or args.serving_sustainable_seconds > 0:
         print("[bench] serving", file=sys.stderr, flush=True)
         out["serving"] = serving(api, args.serving_seconds, args.serving_sustainable_seconds,

@@ -10,6 +10,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_set>
 
 #include "autotune.hpp"
@@ -185,6 +186,43 @@ struct Events {
 };
 
 }  // namespace
+
+void copy_to_host(HostStage& st, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const size_t C = HostStage::kStageBytes;
+  if (bytes <= C / 4) {  // small: one direct copy
+    if (bytes) KNN_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  for (int i = 0; i < 2; ++i) {
+    st.buf[i].reserve(C);
+    if (!st.ev[i]) KNN_HIP(hipEventCreateWithFlags(&st.ev[i], hipEventDisableTiming));
+  }
+  const size_t n = (bytes + C - 1) / C;
+  auto issue = [&](size_t k) {
+    const size_t off = k * C, len = std::min(C, bytes - off);
+    KNN_HIP(hipMemcpyAsync(st.buf[k & 1].p, static_cast<const char*>(src) + off, len,
+                           hipMemcpyDeviceToHost, s));
+    KNN_HIP(hipEventRecord(st.ev[k & 1], s));
+  };
+  const int nt = (int)std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  issue(0);
+  for (size_t k = 0; k < n; ++k) {
+    KNN_HIP(hipEventSynchronize(st.ev[k & 1]));
+    if (k + 1 < n) issue(k + 1);
+    const size_t off = k * C, len = std::min(C, bytes - off);
+    const char* from = st.buf[k & 1].p;
+    char* to = static_cast<char*>(dst) + off;
+    auto part = [&](int t) {
+      const size_t a = len * t / nt, b = len * (t + 1) / nt;
+      std::memcpy(to + a, from + a, b - a);
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(part, t);
+    part(0);
+    for (auto& x : th) x.join();
+  }
+}
 
 int64_t JoinContext::device_bytes() const {
   return (int64_t)(Xs.bytes() + perm.bytes() + cell_of.bytes() + cell_key.bytes() +
@@ -1597,9 +1635,9 @@ int knn_join(knn_index* idx, const double* Q, int64_t n_queries, int32_t K, int3
       DevBuf<double> dD(nk);
       KNN_HIP(hipMemcpyAsync(dQ.p, Q, nq * sizeof(double), hipMemcpyHostToDevice, s));
       join_query_set(idx, dQ.p, n_queries, K, dI.p, dD.p, o, s);
-      KNN_HIP(hipMemcpyAsync(ids, dI.p, nk * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      KNN_HIP(hipMemcpyAsync(dists, dD.p, nk * sizeof(double), hipMemcpyDeviceToHost, s));
-      KNN_HIP(hipStreamSynchronize(s));
+      JoinContext& c = index_ctx(idx);
+      copy_to_host(c.stage, ids, dI.p, nk * sizeof(int32_t), s);
+      copy_to_host(c.stage, dists, dD.p, nk * sizeof(double), s);
     } catch (...) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);
@@ -1663,9 +1701,8 @@ int knn_self_join(knn_index* idx, int32_t K, int32_t* ids, double* dists,
         self_join_graph(*idx, K, c.out_ids.p, c.out_d.p, o, s);
       else
         self_join(*idx, c, K, c.out_ids.p, c.out_d.p, o, s);
-      KNN_HIP(hipMemcpyAsync(ids, c.out_ids.p, NK * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      KNN_HIP(hipMemcpyAsync(dists, c.out_d.p, NK * sizeof(double), hipMemcpyDeviceToHost, s));
-      KNN_HIP(hipStreamSynchronize(s));
+      copy_to_host(c.stage, ids, c.out_ids.p, NK * sizeof(int32_t), s);
+      copy_to_host(c.stage, dists, c.out_d.p, NK * sizeof(double), s);
     } catch (...) {
       (void)hipStreamSynchronize(s);
       (void)hipStreamDestroy(s);

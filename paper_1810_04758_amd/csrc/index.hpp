@@ -41,6 +41,26 @@ struct knn_index {
 
 namespace knn {
 
+// Copies of large results from device memory into caller (pageable) host
+// memory: chunks of kStageBytes through two pinned buffers, the copy of the
+// next chunk in flight while host threads move the current one, so the
+// transfer runs near the link's rate instead of the runtime's pageable path.
+// The buffers are kept for later copies.
+struct HostStage {
+  static constexpr size_t kStageBytes = (size_t)64 << 20;
+  HostBuf<char> buf[2];
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  HostStage() = default;
+  HostStage(const HostStage&) = delete;
+  HostStage& operator=(const HostStage&) = delete;
+  ~HostStage() {
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+// dst (host) <- src (device, bytes), on stream s; returns when done.
+void copy_to_host(HostStage& st, void* dst, const void* src, size_t bytes, hipStream_t s);
+
 // One grid level (Sec. 3.1) plus every temporary of the level loop.  A
 // context serves one join at a time; concurrent joins use separate contexts.
 struct JoinContext {
@@ -87,6 +107,7 @@ struct JoinContext {
   const uint32_t* dense_used = nullptr;  // the level's dense key table, if any
   DevBuf<uint2> rowtab;                  // row table (cells of each grid row)
   HostBuf<int32_t> pinned;               // read-backs of the level loop
+  HostStage stage;                       // host-destination result copies
   const uint2* rowtab_used = nullptr;
   bool graph_owned = false;  // scratch of a captured graph: buffers are never released
   // buffers carved from one fixed region (reserve_fixed_scratch): none is
@@ -101,6 +122,7 @@ struct JoinContext {
 
   int64_t device_bytes() const;
 };
+
 // Device buffers of a JoinContext (the DevBuf members above).
 constexpr int kContextBuffers = 36;
 

@@ -70,6 +70,7 @@ void worker_main(knn_server* srv) {
   }
   hipStream_t s = nullptr;
   (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  HostStage stage;  // pinned staging of this worker's host-destination results
   for (;;) {
     std::shared_ptr<Request> rq;
     {
@@ -106,10 +107,8 @@ void worker_main(knn_server* srv) {
       knn_join_opts o{};
       self_join(*idx, ctx, rq->K, ctx.out_ids.p, ctx.out_d.p, o, s);
       if (rq->ids) {  // NULL outputs: a latency-only request, results discarded
-        KNN_HIP(hipMemcpyAsync(rq->ids, ctx.out_ids.p, NK * sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
-        KNN_HIP(hipMemcpyAsync(rq->dists, ctx.out_d.p, NK * sizeof(double),
-                               hipMemcpyDeviceToHost, s));
+        copy_to_host(stage, rq->ids, ctx.out_ids.p, NK * sizeof(int32_t), s);
+        copy_to_host(stage, rq->dists, ctx.out_d.p, NK * sizeof(double), s);
       }
       KNN_HIP(hipStreamSynchronize(s));
     } catch (const Error& e) {

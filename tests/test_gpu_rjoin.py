@@ -168,3 +168,24 @@ def test_join_invalid(knn):
     ids, _ = idx.join(Q, 100)  # K = N: every point, ordered
     assert all(sorted(r) == list(range(100)) for r in ids.tolist())
     idx.close()
+
+
+def test_host_outputs_staged_copy(knn):
+    """Results above the staged-copy threshold (several 64 MiB chunks through
+    the pinned double buffer) arrive in host memory identical to the device
+    outputs, for the self-join and the query-set join."""
+    import torch
+    D = datagen.uniform(1_000_000, 2, seed=61)
+    Q = datagen.uniform(700_000, 2, seed=62)
+    K = 12
+    idx = knn.build_index(torch.from_numpy(D).cuda())
+    _say(f"[rjoin] staged host copy N={D.shape[0]} NQ={Q.shape[0]} K={K}")
+    hi, hd = idx.self_join_host(K)
+    di, dd = idx.self_join(K)
+    torch.cuda.synchronize()
+    assert np.array_equal(hi, di.cpu().numpy()) and np.array_equal(hd, dd.cpu().numpy())
+    qi, qd = idx.join(Q, K)
+    gi, gd = idx.join(torch.from_numpy(Q).cuda(), K)
+    torch.cuda.synchronize()
+    assert np.array_equal(qi, gi.cpu().numpy()) and np.array_equal(qd, gd.cpu().numpy())
+    idx.close()
