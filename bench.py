@@ -381,6 +381,8 @@ def eps_join_leg(api, huge=True):
         Dd = torch.from_numpy(D).cuda()
         idx = api.build_index(Dd)
         eps = _eps_for(idx, per_point, lo, hi)
+        idx.eps_join_release()  # time the level build and the counts from scratch
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         total = idx.eps_join_size(eps)
         ms_count = 1e3 * (time.perf_counter() - t0)
