@@ -283,7 +283,8 @@ def tune_row(r):
     return dict(w_factor=round(r["w_factor"], 4), growth=round(r["growth"], 4),
                 linear_levels=int(r["linear_levels"]), zorder=int(r["zorder"]),
                 trials=int(r["trials"]), tail_pairs=r["tail_pairs"],
-                lanes_shift=int(r["lanes_shift"]), ms_default=round(r["ms_default"], 3),
+                lanes_shift=int(r["lanes_shift"]), queue_pops=int(r["queue_pops"]),
+                ms_default=round(r["ms_default"], 3),
                 ms_tuned=round(r["ms_best"], 3))
 
 

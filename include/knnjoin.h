@@ -128,7 +128,9 @@ typedef struct knn_join_opts {
                              candidates get a workgroup each; 0 = automatic
                              (those that would outlast the level), < 0 = never */
   int32_t queue_grain;    /* persistent schedule: work items claimed per queue pop;
-                             0 = automatic [about 4 pops per wavefront] */
+                             0 = automatic (a level's items over (wavefronts x P),
+                             at most 64, P = pops per wavefront [autotuned or 4]);
+                             < 0: automatic with P = -queue_grain */
   int32_t item_order;     /* persistent schedule: 0 = densest class first inside
                              each XCD's contiguous chunk (Sec. 4.5 ordering);
                              1 = cell order [0] */
@@ -474,11 +476,14 @@ typedef struct knn_autotune_result {
   double tail_pairs;     /* chosen brute-force tail budget (pairs) */
   int32_t lanes_shift;   /* chosen shift of the lanes-per-query rule (x 2^shift) */
   int32_t zorder;        /* chosen level structure: 1 Z-order levels, -1 row-major */
+  int32_t queue_pops;    /* chosen pops per wavefront and queue of the persistent
+                            search (the automatic queue_grain rule) */
 } knn_autotune_result;
 /* Runs on `stream` (device scratch allocated internally); blocks. */
 int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* out);
 /* Save / load the cache as text ("dims kbucket nbucket w_factor growth
- * lanes linear tail_pairs lanes_shift zorder" per line); path NULL =
+ * lanes linear tail_pairs lanes_shift zorder pops" per line; lines of the
+ * older 10-field form load with pops 0); path NULL =
  * $KNN_AUTOTUNE_CACHE. */
 int knn_autotune_save(const char* path);
 int knn_autotune_load(const char* path);

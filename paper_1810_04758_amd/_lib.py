@@ -92,7 +92,8 @@ class IndexInfo(ctypes.Structure):
 class AutotuneResult(ctypes.Structure):
     _fields_ = [("w_factor", c_f64), ("growth", c_f64), ("ms_best", c_f64),
                 ("ms_default", c_f64), ("trials", c_i32), ("linear_levels", c_i32),
-                ("tail_pairs", c_f64), ("lanes_shift", c_i32), ("zorder", c_i32)]
+                ("tail_pairs", c_f64), ("lanes_shift", c_i32), ("zorder", c_i32),
+                ("queue_pops", c_i32)]
 
 
 class ServerOpts(ctypes.Structure):

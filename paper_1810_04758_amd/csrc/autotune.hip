@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -35,11 +36,18 @@ void load_file_locked(const char* p) {
   if (!p || !*p) return;
   FILE* f = std::fopen(p, "r");
   if (!f) return;
-  int d, kb, nb, lanes, lin, ls, z;
-  double wf, gr, tp;
-  while (std::fscanf(f, "%d %d %d %lf %lf %d %d %lf %d %d", &d, &kb, &nb, &wf, &gr, &lanes, &lin,
-                     &tp, &ls, &z) == 10)
-    g_cache[Class(d, kb, nb)] = TuneEntry{wf, gr, lanes, lin, tp, ls, z};
+  // one entry per line: 11 fields, or the 10 of files written before the
+  // queue granularity was measured
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    int d, kb, nb, lanes, lin, ls, z, pp = 0;
+    double wf, gr, tp;
+    const int got = std::sscanf(line, "%d %d %d %lf %lf %d %d %lf %d %d %d", &d, &kb, &nb, &wf, &gr,
+                                &lanes, &lin, &tp, &ls, &z, &pp);
+    if (got < 10) continue;
+    if (got == 10) pp = 0;
+    g_cache[Class(d, kb, nb)] = TuneEntry{wf, gr, lanes, lin, tp, ls, z, pp};
+  }
   std::fclose(f);
 }
 
@@ -78,6 +86,7 @@ int autotune_lanes_shift(int dims, int K, int64_t N) {
 }
 
 int autotune_zorder(int dims, int K, int64_t N) { return autotune_get(dims, K, N).zorder; }
+int autotune_pops(int dims, int K, int64_t N) { return autotune_get(dims, K, N).pops; }
 
 void autotune_store(int dims, int K, int64_t N, const TuneEntry& e) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -104,10 +113,10 @@ int autotune_save(const char* path) {
   FILE* f = std::fopen(p, "w");
   if (!f) return -1;
   for (auto& kv : g_cache)
-    std::fprintf(f, "%d %d %d %.17g %.17g %d %d %.17g %d %d\n", std::get<0>(kv.first),
+    std::fprintf(f, "%d %d %d %.17g %.17g %d %d %.17g %d %d %d\n", std::get<0>(kv.first),
                  std::get<1>(kv.first), std::get<2>(kv.first), kv.second.w_factor,
                  kv.second.growth, kv.second.lanes, kv.second.linear, kv.second.tail_pairs,
-                 kv.second.lanes_shift, kv.second.zorder);
+                 kv.second.lanes_shift, kv.second.zorder, kv.second.pops);
   std::fclose(f);
   return 0;
 }

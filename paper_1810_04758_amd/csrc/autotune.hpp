@@ -17,6 +17,7 @@ struct TuneEntry {
   double tail_pairs = 0;  // brute-force tail budget, 0 = not measured
   int lanes_shift = 0;    // the per-level lanes-per-query rule times 2^shift
   int zorder = 0;         // Z-order levels: 1 on, -1 off, 0 = not measured
+  int pops = 0;           // persistent queue: pops per wavefront, 0 = not measured
 };
 
 // Cached entry for the class of (dims, K, N), or all zeros.
@@ -34,6 +35,8 @@ double autotune_tail_pairs(int dims, int K, int64_t N);
 int autotune_lanes_shift(int dims, int K, int64_t N);
 // Z-order levels: 1 / -1 as measured, 0 if none cached.
 int autotune_zorder(int dims, int K, int64_t N);
+// Pops per wavefront and queue of the persistent search (0 if none cached).
+int autotune_pops(int dims, int K, int64_t N);
 // Records a measured best setting for the class of (dims, K, N).
 void autotune_store(int dims, int K, int64_t N, const TuneEntry& e);
 // Loads / saves the cache file (path from KNN_AUTOTUNE_CACHE when path is NULL).

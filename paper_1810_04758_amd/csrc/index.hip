@@ -1061,12 +1061,16 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
         int64_t want = ceil_div(n_items, waves);
         blocks = (int)std::min<int64_t>(want,
                                         (int64_t)ncu * search_blocks_per_cu(idx.n, T, cap, zl));
-        // about four pops per wavefront and queue: few atomics, fine enough
+        // a few pops per wavefront and queue: few atomics, fine enough
         // granularity for the dense-first balance at the end of each queue
         const int64_t total_waves = (int64_t)blocks * waves;
+        const int tuned_pops = o.queue_grain == 0 ? autotune_pops(idx.n, K, idx.N) : 0;
+        const int64_t pops = o.queue_grain < 0 ? -(int64_t)o.queue_grain
+                             : tuned_pops > 0  ? tuned_pops
+                                               : 4;
         a.grain = o.queue_grain > 0
                       ? o.queue_grain
-                      : (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, n_items / (total_waves * 4)));
+                      : (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, n_items / (total_waves * pops)));
       }
       lp.blocks = blocks;
       lp.grain = a.grain;
@@ -1775,7 +1779,8 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
     const size_t NK = (size_t)idx->N * K;
     c.out_ids.reserve(NK);
     c.out_d.reserve(NK);
-    int ls_cur = 0;  // lanes shift of the trials (last stage)
+    int ls_cur = 0;  // lanes shift of the trials (last stages)
+    int pops_cur = 4;  // pops per wavefront of the trials (last stage)
     int z_cur = -1;  // level structure of the trials: -1 row-major, 1 Z-order
     auto time_join = [&](double wf, double gr, int lin, double tp) {
       double best = 1e300;
@@ -1787,6 +1792,7 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
         o.tail_pairs = tp;
         o.lanes_shift = ls_cur;
         o.zorder = z_cur;
+        o.queue_grain = -pops_cur;
         KNN_HIP(hipStreamSynchronize(s));
         auto t0 = std::chrono::steady_clock::now();
         self_join(*idx, c, K, c.out_ids.p, c.out_d.p, o, s);
@@ -1889,10 +1895,22 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
       consider(wf4, gr4, lin4, tp4);
       if (out->ms_best < before) out->lanes_shift = ls;
     }
+    // the queue granularity of the persistent search: pops per wavefront and
+    // queue (few: fewer atomics on the queue heads; many: finer balance at the
+    // end of each queue when dense items cluster)
+    ls_cur = out->lanes_shift;
+    out->queue_pops = 4;
+    for (int pp : {8, 16, 32, 64}) {
+      pops_cur = pp;
+      const double before = out->ms_best;
+      consider(wf4, gr4, lin4, tp4);
+      if (out->ms_best < before) out->queue_pops = pp;
+    }
+    pops_cur = 4;
     ls_cur = 0;
     autotune_store(idx->n, K, idx->N,
                    TuneEntry{out->w_factor, out->growth, 0, out->linear_levels > 0 ? 1 : -1,
-                             out->tail_pairs, out->lanes_shift, out->zorder});
+                             out->tail_pairs, out->lanes_shift, out->zorder, out->queue_pops});
   });
 }
 
