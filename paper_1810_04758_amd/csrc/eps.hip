@@ -22,18 +22,28 @@ __device__ __forceinline__ double sq_dist_soa(const double* __restrict__ X, int6
   return s;
 }
 
+// SX[j * ns + i] = X[j * N + sample[i]]: the sample's coordinates, compact
+// (the pair loop then reads a few hundred KB instead of gathering from D).
+__global__ void k_gather_sample(const double* __restrict__ X, int64_t N, int n,
+                                const int64_t* __restrict__ sample, int64_t ns,
+                                double* __restrict__ SX) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t id = sample[i];
+    for (int j = 0; j < n; ++j) SX[(int64_t)j * ns + i] = X[(int64_t)j * N + id];
+  }
+}
+
 // Block `a` sums the distances of sample point a to the sample points after it.
-__global__ void k_pair_sums(const double* __restrict__ X, int64_t N, int n,
-                            const int64_t* __restrict__ sample, int64_t ns,
+__global__ void k_pair_sums(const double* __restrict__ SX, int n, int64_t ns,
                             double* __restrict__ part) {
   __shared__ double red[kBlock];
   for (int64_t a = blockIdx.x; a < ns; a += gridDim.x) {
     double qa[kMaxDims];
-    const int64_t ia = sample[a];
-    for (int j = 0; j < n; ++j) qa[j] = X[(int64_t)j * N + ia];
+    for (int j = 0; j < n; ++j) qa[j] = SX[(int64_t)j * ns + a];
     double s = 0.0;
     for (int64_t b = a + 1 + threadIdx.x; b < ns; b += blockDim.x)
-      s += sqrt(sq_dist_soa(X, N, n, sample[b], qa));
+      s += sqrt(sq_dist_soa(SX, ns, n, b, qa));
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -119,10 +129,13 @@ __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N, int64_
 }  // namespace
 
 int launch_sample_pair_sums(const double* X, int64_t N, int n, const int64_t* sample,
-                            int64_t ns, double* part, hipStream_t s) {
+                            int64_t ns, double* SX, double* part, hipStream_t s) {
   if (ns < 2) return 0;
+  k_gather_sample<<<(int)std::min<int64_t>(ceil_div(ns, kBlock), 1024), kBlock, 0, s>>>(
+      X, N, n, sample, ns, SX);
+  KNN_LAUNCHED();
   int nb = (int)(ns < 65535 ? ns : 65535);
-  k_pair_sums<<<nb, kBlock, 0, s>>>(X, N, n, sample, ns, part);
+  k_pair_sums<<<nb, kBlock, 0, s>>>(SX, n, ns, part);
   KNN_LAUNCHED();
   return (int)ns;
 }

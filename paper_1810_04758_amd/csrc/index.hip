@@ -1396,7 +1396,8 @@ knn_index* build_from_device(const double* D_dev, int64_t N, int n, const knn_bu
     KNN_HIP(hipMemcpyAsync(d_sm.p, sm.data(), sm.size() * 8, hipMemcpyHostToDevice, s));
     KNN_HIP(hipMemcpyAsync(d_sh.p, sh.data(), sh.size() * 8, hipMemcpyHostToDevice, s));
     DevBuf<double> psum(std::max<size_t>(sm.size(), 1));
-    int np = launch_sample_pair_sums(idx->X.p, N, n, d_sm.p, (int64_t)sm.size(), psum.p, s);
+    DevBuf<double> sx(std::max<size_t>(sm.size() * n, 1));
+    int np = launch_sample_pair_sums(idx->X.p, N, n, d_sm.p, (int64_t)sm.size(), sx.p, psum.p, s);
     std::vector<double> hp(np);
     if (np) KNN_HIP(hipMemcpyAsync(hp.data(), psum.p, np * 8, hipMemcpyDeviceToHost, s));
     KNN_HIP(hipStreamSynchronize(s));
@@ -2007,7 +2008,8 @@ int knn_sample_mean_dist(const double* d_D, int64_t n_points, int32_t dims,
     KNN_HIP(hipMemsetAsync(bad.p, 0, 4, s));
     launch_aos_to_soa(d_D, n_points, dims, X.p, bad.p, s);
     DevBuf<double> part(std::max<int64_t>(ns, 1));
-    int np = launch_sample_pair_sums(X.p, n_points, dims, d_sample, ns, part.p, s);
+    DevBuf<double> sx(std::max<int64_t>(ns * dims, 1));
+    int np = launch_sample_pair_sums(X.p, n_points, dims, d_sample, ns, sx.p, part.p, s);
     std::vector<double> hp(np);
     if (np) KNN_HIP(hipMemcpyAsync(hp.data(), part.p, np * 8, hipMemcpyDeviceToHost, s));
     KNN_HIP(hipStreamSynchronize(s));

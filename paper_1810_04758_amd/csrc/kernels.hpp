@@ -198,8 +198,9 @@ void launch_zero(void* p, size_t bytes, hipStream_t s);
 // ---- search-distance sampling (eps.hip) ----
 // Partial sums of pair distances inside the sample: one double per block of
 // rows; returns the number of partials written to part (host reads them).
+// SX: scratch of ns * n doubles (the sample's coordinates, gathered first).
 int launch_sample_pair_sums(const double* X, int64_t N, int n, const int64_t* sample,
-                            int64_t ns, double* part, hipStream_t s);
+                            int64_t ns, double* SX, double* part, hipStream_t s);
 // Histogram of the distances from the sample points to the points p =
 // 0, pstride, 2 pstride, ... of X (all points when pstride = 1), bins of width
 // 1/inv_bw; only the first count_bins bins are counted (the rest stay 0;
