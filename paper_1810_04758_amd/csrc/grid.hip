@@ -559,8 +559,16 @@ __global__ void k_neighbor_ranges(const double* __restrict__ Xs, int64_t N,
       }
       count += (uint32_t)__popcll(m);
     }
+    // the group's total into its lane 0 (S need not be a power of two)
+    if constexpr ((S & (S - 1)) == 0) {
 #pragma unroll
-    for (int o = 1; o < S; o <<= 1) cand += __shfl_xor(cand, o, 64);
+      for (int o = 1; o < S; o <<= 1) cand += __shfl_xor(cand, o, 64);
+    } else {
+      uint32_t tot = 0;
+#pragma unroll
+      for (int o = 0; o < S; ++o) tot += __shfl(cand, sub * S + o, 64);
+      cand = tot;
+    }
     if (l == 0) {
       nrng[c] = count;
       cand_count[c] = cand;
@@ -821,15 +829,21 @@ __global__ void k_neighbor_ranges_z(const uint32_t* __restrict__ cell_start,
                                     uint8_t* __restrict__ rslot, uint32_t* __restrict__ nrng,
                                     uint32_t* __restrict__ cand_count) {
   constexpr int R = DIM == 2 ? 9 : DIM == 3 ? 27 : 81;
-  constexpr int S = R <= 16 ? 16 : R <= 32 ? 32 : 64;
+  // lanes per cell: one per neighbour up to a wavefront (2-D: 7 cells of 9
+  // lanes per wavefront, the last lane idle)
+  constexpr int S = R <= 64 ? R : 64;
+  constexpr int GPW = 64 / S;  // cells per wavefront
   const uint32_t M = *d_M;
   const int lane = threadIdx.x & 63;
   const int l = lane % S;
   const int sub = lane / S;
   const uint64_t lt = l == 0 ? 0ull : (~0ull >> (64 - l));
-  const int64_t groups = (int64_t)gridDim.x * (blockDim.x / S);
-  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x / S) + threadIdx.x / S; c < (int64_t)M;
-       c += groups) {
+  const uint64_t gmask = S >= 64 ? ~0ull : ((1ull << (S & 63)) - 1ull);
+  const int64_t wpb = blockDim.x / 64;
+  const int64_t groups = (int64_t)gridDim.x * wpb * GPW;
+  const int64_t c0 = sub < GPW ? ((int64_t)blockIdx.x * wpb + threadIdx.x / 64) * GPW + sub
+                               : (int64_t)M;  // the idle lane takes no cell
+  for (int64_t c = c0; c < (int64_t)M; c += groups) {
     if (cell_active && cell_active[c] != active_tag) continue;
     const uint64_t k0 = cell_key[c];
     int64_t cc[DIM];
@@ -861,8 +875,7 @@ __global__ void k_neighbor_ranges_z(const uint32_t* __restrict__ cell_start,
         }
       }
       const bool ne = end > start;
-      const uint64_t m = (S == 64 ? __ballot(ne) : (__ballot(ne) >> (sub * S))) &
-                         (S == 64 ? ~0ull : ((1ull << S) - 1ull));
+      const uint64_t m = (S == 64 ? __ballot(ne) : (__ballot(ne) >> (sub * S))) & gmask;
       if (ne) {
         const uint32_t pos = count + (uint32_t)__popcll(m & lt);
         const uint32_t m0 = olast < 0 ? end : start;   // the cell is the lower part,
@@ -873,8 +886,16 @@ __global__ void k_neighbor_ranges_z(const uint32_t* __restrict__ cell_start,
       }
       count += (uint32_t)__popcll(m);
     }
+    // the group's total into its lane 0 (S need not be a power of two)
+    if constexpr ((S & (S - 1)) == 0) {
 #pragma unroll
-    for (int o = 1; o < S; o <<= 1) cand += __shfl_xor(cand, o, 64);
+      for (int o = 1; o < S; o <<= 1) cand += __shfl_xor(cand, o, 64);
+    } else {
+      uint32_t tot = 0;
+#pragma unroll
+      for (int o = 0; o < S; ++o) tot += __shfl(cand, sub * S + o, 64);
+      cand = tot;
+    }
     if (l == 0) {
       nrng[c] = count;
       cand_count[c] = cand;
@@ -1164,8 +1185,8 @@ void launch_neighbor_ranges_z(const uint32_t* cell_start, const uint64_t* cell_k
                               hipStream_t s) {
   KNN_CHECK(gg.zbits >= 0 && gg.dims <= kZMaxDims, KNN_EINTERNAL, "not a Z-order level");
   GeomDev gd = to_dev(gg);
-  const int S = gg.dims == 2 ? 16 : gg.dims == 3 ? 32 : 64;
-  const int nb = grid_for(N * S, 65536);
+  const int S = gg.dims == 2 ? 9 : gg.dims == 3 ? 27 : 64;
+  const int nb = grid_for(N * 64 / (64 / S), 65536);
   switch (gg.dims) {
     case 2: k_neighbor_ranges_z<2><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
     case 3: k_neighbor_ranges_z<3><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
