@@ -4,6 +4,8 @@
 // point of D, binned up to eps_mean.
 #pragma clang fp contract(off)
 
+#include <cmath>
+
 #include "kernels.hpp"
 
 namespace knn {
@@ -82,15 +84,20 @@ __device__ __forceinline__ int dist_bin(double d2, double inv_bw, float inv_bw_f
 // counted (pairs certainly beyond them skip the bin arithmetic).  The
 // per-block histogram is accumulated in LDS (uint32) and added to the global
 // uint64 counts at the end.
+// skip_f: a single-precision squared distance above it proves the pair's
+// double-precision d^2 above skip_d2 (see launch_dist_histogram), so most far
+// pairs are rejected at single-precision rate; +inf disables the test.
 template <int DIM>
 __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N, int64_t pstride,
                                  const int64_t* __restrict__ sample, int64_t ns, double inv_bw,
-                                 int count_bins, double skip_d2, uint64_t* __restrict__ counts) {
+                                 int count_bins, double skip_d2, float skip_f,
+                                 uint64_t* __restrict__ counts) {
   const int n_bins = count_bins;
   __shared__ uint32_t h[kMaxBins];
   const float inv_bw_f = (float)inv_bw;
   const bool use_f = inv_bw >= 0x1p-60 && inv_bw <= 0x1p60;
   __shared__ double sx[DIM][kSampleChunk];
+  __shared__ float sxf[DIM][kSampleChunk];
   __shared__ int64_t sid[kSampleChunk];
   for (int b = threadIdx.x; b < n_bins; b += blockDim.x) h[b] = 0;
   for (int64_t c0 = 0; c0 < ns; c0 += kSampleChunk) {
@@ -100,15 +107,29 @@ __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N, int64_
       int64_t id = sample[c0 + i];
       sid[i] = id;
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) sx[j][i] = X[(int64_t)j * N + id];
+      for (int j = 0; j < DIM; ++j) {
+        sx[j][i] = X[(int64_t)j * N + id];
+        sxf[j][i] = (float)sx[j][i];
+      }
     }
     __syncthreads();
     for (int64_t p = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * pstride; p < N;
          p += (int64_t)gridDim.x * blockDim.x * pstride) {
       double x[DIM];
+      float xf[DIM];
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) x[j] = X[(int64_t)j * N + p];
+      for (int j = 0; j < DIM; ++j) {
+        x[j] = X[(int64_t)j * N + p];
+        xf[j] = (float)x[j];
+      }
       for (int i = 0; i < cn; ++i) {
+        float sf = 0.0f;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+          const float t = __fsub_rn(xf[j], sxf[j][i]);
+          sf = __fadd_rn(sf, __fmul_rn(t, t));
+        }
+        if (sf > skip_f) continue;  // provably beyond skip_d2
         double s = 0.0;
 #pragma unroll
         for (int j = 0; j < DIM; ++j) {
@@ -142,7 +163,7 @@ int launch_sample_pair_sums(const double* X, int64_t N, int n, const int64_t* sa
 
 void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sample,
                            int64_t ns, double inv_bw, int n_bins, uint64_t* counts,
-                           hipStream_t s, int count_bins, int64_t pstride) {
+                           hipStream_t s, int count_bins, int64_t pstride, double max_abs) {
   KNN_CHECK(n_bins >= 1 && n_bins <= kMaxBins, KNN_EINVAL, "n_bins must be in [1, 4096]");
   if (count_bins <= 0 || count_bins > n_bins) count_bins = n_bins;
   KNN_CHECK(pstride >= 1, KNN_EINTERNAL, "histogram point stride must be >= 1");
@@ -151,14 +172,35 @@ void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sam
   // distances whose bin is certainly >= count_bins skip the square root
   double lim = (double)count_bins / inv_bw;
   double skip_d2 = lim * lim * 1.0001 + 1e-300;
+  // The single-precision test.  With A = max_abs (every |coordinate|), each
+  // coordinate's conversion to float errs by at most A 2^-24 (plus 2^-149
+  // below float's normal range), so a float difference df_j of the converted
+  // values satisfies |df_j| <= (|x_j - q_j| + e)(1 + 2^-24), e = 2 A 2^-24 +
+  // 2^-148; the float sum sf of the n rounded squares is at most
+  // sum df_j^2 (1 + 2^-20).  Hence d = ||x - q|| >= sqrt(sf / (1 + 2^-20)) /
+  // (1 + 2^-24) - sqrt(n) e, and sf > (L + sqrt(n) e)^2 (1 + 2^-18) gives
+  // d > L = sqrt(skip_d2 (1 + 2^-49)), so the double-precision d^2 (n + 1
+  // roundings of 2^-53 each) exceeds skip_d2: such a pair is never counted.
+  float skip_f = INFINITY;
+  if (max_abs >= 0 && max_abs < 1e30 && std::isfinite(skip_d2)) {
+    const double e = 2.0 * max_abs * 0x1p-24 + 0x1p-148;
+    const double L = std::sqrt(skip_d2 * (1.0 + 0x1p-49));
+    const double lim_f = L + std::sqrt((double)n) * e;
+    const double T = lim_f * lim_f * (1.0 + 0x1p-18);
+    if (T < 1e38) {
+      float tf = (float)T;
+      if ((double)tf < T) tf = std::nextafter(tf, INFINITY);
+      skip_f = tf;
+    }
+  }
   int64_t want = ceil_div(ceil_div(N, pstride), kBlock);
   int nb = (int)(want < 2048 ? want : 2048);
   switch (n) {
-    case 2: k_dist_histogram<2><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, counts); break;
-    case 3: k_dist_histogram<3><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, counts); break;
-    case 4: k_dist_histogram<4><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, counts); break;
-    case 5: k_dist_histogram<5><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, counts); break;
-    case 6: k_dist_histogram<6><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, counts); break;
+    case 2: k_dist_histogram<2><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, skip_f, counts); break;
+    case 3: k_dist_histogram<3><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, skip_f, counts); break;
+    case 4: k_dist_histogram<4><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, skip_f, counts); break;
+    case 5: k_dist_histogram<5><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, skip_f, counts); break;
+    case 6: k_dist_histogram<6><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, skip_f, counts); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
   KNN_LAUNCHED();

@@ -1424,9 +1424,12 @@ knn_index* build_from_device(const double* D_dev, int64_t N, int n, const knn_bu
     const uint64_t need = (uint64_t)KNN_MAX_K * (uint64_t)ns;
     DevBuf<uint64_t> counts(o.n_bins);
     std::vector<uint64_t> hc(o.n_bins);
+    double max_abs = 0;  // every |coordinate| is at most this
+    for (int j = 0; j < n; ++j)
+      max_abs = std::max(max_abs, std::max(std::fabs(idx->lo[j]), std::fabs(idx->hi[j])));
     auto histogram = [&](int count_bins, int64_t pstride) {
       launch_dist_histogram(idx->X.p, N, n, d_sh.p, ns, inv_bw, o.n_bins, counts.p, s,
-                            count_bins, pstride);
+                            count_bins, pstride, max_abs);
       KNN_HIP(hipMemcpyAsync(hc.data(), counts.p, o.n_bins * 8, hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));
     };

@@ -204,10 +204,13 @@ int launch_sample_pair_sums(const double* X, int64_t N, int n, const int64_t* sa
 // Histogram of the distances from the sample points to the points p =
 // 0, pstride, 2 pstride, ... of X (all points when pstride = 1), bins of width
 // 1/inv_bw; only the first count_bins bins are counted (the rest stay 0;
-// count_bins <= 0: all n_bins).
+// count_bins <= 0: all n_bins).  max_abs: a bound on every |coordinate|
+// (< 0: unknown), which lets far pairs be rejected in single precision first
+// (the counts are the same).
 void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sample,
                            int64_t ns, double inv_bw, int n_bins, uint64_t* counts,
-                           hipStream_t s, int count_bins = 0, int64_t pstride = 1);
+                           hipStream_t s, int count_bins = 0, int64_t pstride = 1,
+                           double max_abs = -1.0);
 
 // ---- distance similarity self-join (epsjoin.hip) ----
 // One row-major grid level (ranges / rslot / nrng, R segments per cell) whose
