@@ -181,13 +181,16 @@ void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sam
   // (1 + 2^-24) - sqrt(n) e, and sf > (L + sqrt(n) e)^2 (1 + 2^-18) gives
   // d > L = sqrt(skip_d2 (1 + 2^-49)), so the double-precision d^2 (n + 1
   // roundings of 2^-53 each) exceeds skip_d2: such a pair is never counted.
+  // The relative bounds need the float values in the normal range: the test
+  // is used only for thresholds in [2^-100, 1e38] (below, the 2^-149
+  // absolute rounding of subnormal squares is no longer negligible).
   float skip_f = INFINITY;
   if (max_abs >= 0 && max_abs < 1e30 && std::isfinite(skip_d2)) {
     const double e = 2.0 * max_abs * 0x1p-24 + 0x1p-148;
     const double L = std::sqrt(skip_d2 * (1.0 + 0x1p-49));
     const double lim_f = L + std::sqrt((double)n) * e;
     const double T = lim_f * lim_f * (1.0 + 0x1p-18);
-    if (T < 1e38) {
+    if (T < 1e38 && T >= 0x1p-100) {
       float tf = (float)T;
       if ((double)tf < T) tf = std::nextafter(tf, INFINITY);
       skip_f = tf;

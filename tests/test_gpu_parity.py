@@ -279,6 +279,11 @@ def test_sampling_kernels_match_oracle(knn, oracle_mod, scale):
     ("clustered", lambda: datagen.clustered(400_000, seed=63), 77),
     ("unif4d", lambda: datagen.uniform(100_000, 4, seed=64), 5),
     ("small_fallback", lambda: datagen.uniform(1100, 2, seed=65), 9),
+    # scaled far from 1: the single-precision rejection of far pairs is off
+    # below (squares near float's subnormal range) and checked above
+    ("unif2d_tiny", lambda: datagen.uniform(100_000, 2, seed=67) * 2.0 ** -70, 3),
+    ("expo3d_large", lambda: datagen.exponential(100_000, 3, seed=68) * 2.0 ** 40, 4),
+    ("clustered_offset", lambda: datagen.clustered(300_000, seed=69) + 3.0e6, 5),
     # large enough for the histogram's estimate on a point subset: bins are
     # counted only up to about where K = 1024 is reached
     ("clustered_2m", lambda: datagen.clustered(2_200_000, seed=66), 3),
