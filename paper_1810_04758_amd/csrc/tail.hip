@@ -12,8 +12,10 @@
 //      bins per octave, ending at the squared bounding-box diagonal; every
 //      point is a candidate, so every query succeeds);
 //   2. select: first bin whose cumulative count reaches K;
-//   3. if it would overflow the per-query buffer, exact bisection of the key
-//      (d^2, id) inside that bin, one counting pass per round;
+//   3. if it would overflow the per-query buffer, exact refinement of the key
+//      (d^2, id) inside that bin: each round counts the keys of the interval
+//      in 64 equal key sub-ranges (6 bits of the key per round) and keeps
+//      the first where the count reaches K, one counting pass per round;
 //   4. collect the survivors into the per-query buffer;
 //   5. one wavefront per query ranks its survivors and writes the output row.
 #pragma clang fp contract(off)
@@ -29,6 +31,13 @@ constexpr int kChunk = kBlock * 8;      // points per block
 constexpr int QB = 32;                   // queries per block
 constexpr int TNB = 64;
 constexpr int kTailShift = 50;
+constexpr int kTailSplit = 64;     // key sub-ranges per refinement round
+constexpr int kLog2TailSplit = 6;
+
+__device__ __forceinline__ int tbitlen128(unsigned __int128 v) {
+  const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
+  return hi ? 128 - __builtin_clzll(hi) : (lo ? 64 - __builtin_clzll(lo) : 0);
+}
 
 enum Mode : int { kBin = 0, kRefine = 1, kKey = 2 };
 
@@ -151,32 +160,25 @@ __global__ void k_tail_select(const TailArgs a) {
   }
 }
 
-// Per query in refinement: four thresholds splitting [A, B]; written to state.
+// Per query in refinement: the width 2^sh of the round's kTailSplit equal key
+// sub-ranges of [A, B] (the last one may be partial), and cleared counts.
 __global__ void k_tail_split(const TailArgs a) {
   const int qi = blockIdx.x * blockDim.x + threadIdx.x;
   if (qi >= a.A) return;
   TailState& st = a.state[qi];
   if (st.mode != kRefine) return;
-  const unsigned __int128 span = st.B - st.A + 1;
-  const unsigned __int128 step = span / 4;
-  for (int i = 0; i < 4; ++i) {
-    if (i == 3)
-      st.t[i] = st.B;
-    else if (step == 0)
-      st.t[i] = (st.A + (unsigned __int128)i < st.B) ? st.A + (unsigned __int128)i : st.B;
-    else
-      st.t[i] = st.A - 1 + step * (unsigned __int128)(i + 1);
-    a.cnt[qi * 4 + i] = 0;
-  }
+  const int sh = tbitlen128(st.B - st.A) - kLog2TailSplit;
+  st.sh = sh < 0 ? 0 : sh;
+  for (int i = 0; i < kTailSplit; ++i) a.cnt[(int64_t)qi * kTailSplit + i] = 0;
 }
 
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_tail_refine_count(const TailArgs a) {
   constexpr int PPT = ppt<DIM>();
   __shared__ QBatch qb;
-  __shared__ uint32_t c4[QB][4];
-  __shared__ int refining[QB];
-  __shared__ unsigned __int128 sA[QB], st4[QB][4];
+  __shared__ uint32_t cs[QB][kTailSplit];
+  __shared__ int refining[QB], ssh[QB];
+  __shared__ unsigned __int128 sA[QB], sB[QB];
   __shared__ int any;
   const int q0 = blockIdx.y * QB;
   if (threadIdx.x == 0) any = 0;
@@ -187,10 +189,11 @@ __global__ void __launch_bounds__(kBlock) k_tail_refine_count(const TailArgs a) 
     if (r) {
       any = 1;
       sA[i] = a.state[q0 + i].A;
-      for (int t = 0; t < 4; ++t) st4[i][t] = a.state[q0 + i].t[t];
+      sB[i] = a.state[q0 + i].B;
+      ssh[i] = a.state[q0 + i].sh;
     }
-    for (int t = 0; t < 4; ++t) c4[i][t] = 0;
   }
+  for (int e = threadIdx.x; e < QB * kTailSplit; e += blockDim.x) cs[e / kTailSplit][e % kTailSplit] = 0;
   load_batch(a, qb);
   __syncthreads();
   if (!any) return;
@@ -206,16 +209,16 @@ __global__ void __launch_bounds__(kBlock) k_tail_refine_count(const TailArgs a) 
         const double d2 = tail_d2<DIM>(px[k], qb.x[i]);
         const unsigned __int128 key =
             ((unsigned __int128)(uint64_t)__double_as_longlong(d2) << 32) | (uint32_t)pid[k];
-        if (key >= sA[i] && key <= st4[i][3]) {
-          for (int t = 0; t < 4; ++t)
-            if (key <= st4[i][t]) atomicAdd(&c4[i][t], 1u);
-        }
+        if (key >= sA[i] && key <= sB[i])  // (B - A) >> sh < kTailSplit
+          atomicAdd(&cs[i][(int)((key - sA[i]) >> ssh[i])], 1u);
       }
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < qb.nq * 4; e += blockDim.x)
-    if (c4[e / 4][e % 4]) atomicAdd(&a.cnt[(int64_t)(q0 + e / 4) * 4 + e % 4], c4[e / 4][e % 4]);
+  for (int e = threadIdx.x; e < qb.nq * kTailSplit; e += blockDim.x) {
+    const uint32_t v = cs[e / kTailSplit][e % kTailSplit];
+    if (v) atomicAdd(&a.cnt[(int64_t)(q0 + e / kTailSplit) * kTailSplit + e % kTailSplit], v);
+  }
 }
 
 __global__ void k_tail_refine_update(const TailArgs a) {
@@ -223,17 +226,29 @@ __global__ void k_tail_refine_update(const TailArgs a) {
   if (qi >= a.A) return;
   TailState& st = a.state[qi];
   if (st.mode != kRefine) return;
-  int i = 0;
-  while (i < 3 && st.c_lo + (int)a.cnt[qi * 4 + i] < a.K) ++i;
-  const int nchi = st.c_lo + (int)a.cnt[qi * 4 + i];
-  if (i > 0) {
-    const int nclo = st.c_lo + (int)a.cnt[qi * 4 + i - 1];
-    st.A = st.t[i - 1] + 1;
-    st.c_lo = nclo;
+  // the first sub-range where the count (c_lo below A) reaches K
+  const uint32_t* c = a.cnt + (int64_t)qi * kTailSplit;
+  int cum = st.c_lo;
+  int b = 0;
+  for (; b < kTailSplit; ++b) {
+    if (cum + (int)c[b] >= a.K) break;
+    cum += (int)c[b];
   }
-  st.B = st.t[i];
-  st.c_hi = nchi;
-  if (st.c_hi <= a.cap)
+  if (b == kTailSplit) {
+    // the counts of [A, B] always reach K; the passes disagreed: stop here
+    // and report (the query keeps its interval)
+    st.mode = kKey;
+    atomicAdd(&a.flag[1], 1);
+    return;
+  }
+  const unsigned __int128 nA = st.A + ((unsigned __int128)b << st.sh);
+  const unsigned __int128 nB = nA + (((unsigned __int128)1 << st.sh) - 1);
+  st.A = nA;
+  if (nB < st.B) st.B = nB;
+  st.c_hi = cum + (int)c[b];
+  st.c_lo = cum;
+  // a single-key interval holds at most one candidate, so this ends
+  if (st.c_hi <= a.cap || st.A == st.B)
     st.mode = kKey;
   else
     atomicAdd(&a.flag[0], 1);
@@ -313,7 +328,7 @@ __global__ void k_tail_finish(const TailArgs a) {
 }  // namespace
 
 size_t tail_state_bytes(int64_t A, int cap) {
-  return (size_t)A * (sizeof(TailState) + TNB * 4 + 16 + (size_t)cap * 12) + 6 * 256;
+  return (size_t)A * (sizeof(TailState) + TNB * 4 + kTailSplit * 4 + (size_t)cap * 12) + 6 * 256;
 }
 
 #define LAUNCH_DIM(kern, grid, args)                                           \
@@ -338,7 +353,7 @@ int tail_run(TailArgs a, char* scratch, hipStream_t s, int fixed_rounds) {
   };
   a.state = reinterpret_cast<TailState*>(take((size_t)a.A * sizeof(TailState)));
   a.hist = reinterpret_cast<uint32_t*>(take((size_t)a.A * TNB * 4));
-  a.cnt = reinterpret_cast<uint32_t*>(take((size_t)a.A * 16));
+  a.cnt = reinterpret_cast<uint32_t*>(take((size_t)a.A * kTailSplit * 4));
   a.flag = reinterpret_cast<int32_t*>(take(16));
   a.buf_d = reinterpret_cast<double*>(take((size_t)a.A * a.cap * 8));
   a.buf_i = reinterpret_cast<int32_t*>(take((size_t)a.A * a.cap * 4));
@@ -368,8 +383,11 @@ int tail_run(TailArgs a, char* scratch, hipStream_t s, int fixed_rounds) {
     k_tail_refine_update<<<sb, kBlock, 0, s>>>(a);
     KNN_LAUNCHED();
     if (!fixed) {
-      KNN_HIP(hipMemcpyAsync(&nref, a.flag, 4, hipMemcpyDeviceToHost, s));
+      int32_t fl[2] = {0, 0};
+      KNN_HIP(hipMemcpyAsync(fl, a.flag, 8, hipMemcpyDeviceToHost, s));
       KNN_HIP(hipStreamSynchronize(s));
+      nref = fl[0];
+      KNN_CHECK(fl[1] == 0, KNN_EINTERNAL, "tail refinement: the counting passes disagreed");
     }
     ++rounds;
     KNN_CHECK(rounds < 200, KNN_EINTERNAL, "tail refinement did not converge");

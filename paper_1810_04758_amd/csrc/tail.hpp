@@ -8,7 +8,7 @@ namespace knn {
 
 struct TailState {
   unsigned __int128 A, B;  // inclusive (d2 bits, id) key interval while refining
-  unsigned __int128 t[4];  // split points of the current round
+  int32_t sh;              // the current round's sub-range width: 2^sh keys
   int32_t bsel, c_lo, c_hi, mode, fill;
 };
 
@@ -31,7 +31,7 @@ struct TailArgs {
   // carved from the scratch by tail_run
   TailState* state;
   uint32_t* hist;
-  uint32_t* cnt;
+  uint32_t* cnt;  // refinement: kTailSplit counts per query
   int32_t* flag;
   double* buf_d;
   int32_t* buf_i;
