@@ -238,6 +238,81 @@ __global__ void k_radix_scatter(const uint64_t* __restrict__ keys,
   }
 }
 
+// Stable scatter through LDS (8-bit digits): the tile's keys are first placed
+// in LDS in digit order (the same ballot ranks as above, with tile-local
+// digit starts), then written out digit run by digit run, so consecutive
+// lanes write consecutive addresses of one run (about 16 keys per run for a
+// 4096-key tile) instead of 256 scattered 8-byte stores per round.  The tile's
+// count of digit d is the difference of consecutive entries of the scanned
+// (digit-major, tile-minor) offsets, the last one closing at n.
+__global__ void __launch_bounds__(kBlock)
+k_radix_scatter_lds(const uint64_t* __restrict__ keys, const int32_t* __restrict__ vals,
+                    int64_t n, int shift, const uint32_t* __restrict__ offs, int64_t nb,
+                    uint64_t* __restrict__ okeys, int32_t* __restrict__ ovals) {
+  constexpr int DB = 8;
+  constexpr int RB = 1 << DB;
+  static_assert(RB == kBlock, "one digit per thread in the tile scan");
+  __shared__ uint64_t sk[kRadixTile];
+  __shared__ int32_t sv[kRadixTile];
+  __shared__ uint32_t lfirst[RB], lrun[RB], gbase[RB];
+  __shared__ uint32_t wcnt[kBlock / 64][RB];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  {
+    const int64_t e = (int64_t)t * nb + blockIdx.x;
+    const uint32_t o = offs[e];
+    const uint32_t nx = e + 1 < (int64_t)RB * nb ? offs[e + 1] : (uint32_t)n;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<kBlock>(nx - o, &tot);
+    lfirst[t] = ex;
+    lrun[t] = ex;
+    gbase[t] = o;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) wcnt[i][t] = 0;
+  }
+  __syncthreads();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int k = 0; k < kRadixItems; ++k) {
+    const int64_t i = base + (int64_t)k * kBlock + t;
+    const bool valid = i < n;
+    const uint64_t key = valid ? keys[i] : 0;
+    const int32_t val = valid ? vals[i] : 0;
+    const uint32_t d = (uint32_t)(key >> shift) & (uint32_t)(RB - 1);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < DB; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    const bool leader = valid && rank == 0;
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    if (leader) wcnt[w][d] = cnt;
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = lrun[d] + rank;
+      for (int i2 = 0; i2 < w; ++i2) pos += wcnt[i2][d];
+      sk[pos] = key;
+      sv[pos] = val;
+    }
+    __syncthreads();
+    if (leader) {
+      atomicAdd(&lrun[d], cnt);  // one leader per digit and wavefront
+      wcnt[w][d] = 0;
+    }
+    __syncthreads();
+  }
+  const int64_t tn = n - base < (int64_t)kRadixTile ? n - base : (int64_t)kRadixTile;
+  for (int j = t; j < (int)tn; j += kBlock) {
+    const uint64_t key = sk[j];
+    const uint32_t d = (uint32_t)(key >> shift) & (uint32_t)(RB - 1);
+    const uint32_t pos = gbase[d] + ((uint32_t)j - lfirst[d]);
+    okeys[pos] = key;
+    ovals[pos] = sv[j];
+  }
+}
+
 // --------------------------------------------------------------------------
 // grid level
 // --------------------------------------------------------------------------
@@ -1089,8 +1164,10 @@ bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* v
                       hipStream_t s) {
   if (n <= 1 || bits <= 0) return false;
   int64_t nb = ceil_div(n, kRadixTile);
-  // 11-bit digits when they save a pass, else 8-bit (smaller LDS tables)
-  const int DB = (bits + 10) / 11 < (bits + 7) / 8 ? 11 : 8;
+  // 8-bit digits, scattered through LDS (coalesced digit runs); the direct
+  // 11-bit scatter (one pass fewer, scattered stores) only for small sorts
+  const bool lds = n >= 4 * kRadixTile;
+  const int DB = lds ? 8 : ((bits + 10) / 11 < (bits + 7) / 8 ? 11 : 8);
   const int passes = (bits + DB - 1) / DB;
   const int64_t cnt = ((int64_t)1 << DB) * nb;
   uint32_t* hist = tmp;
@@ -1106,7 +1183,10 @@ bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* v
       k_radix_hist<8><<<(unsigned)nb, kBlock, 0, s>>>(src_k, n, shift, hist, nb);
     KNN_LAUNCHED();
     launch_exclusive_scan(hist, hist, cnt, nullptr, state, state_elems, s);
-    if (DB == 11)
+    if (lds)
+      k_radix_scatter_lds<<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb, dst_k,
+                                                          dst_v);
+    else if (DB == 11)
       k_radix_scatter<11><<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb,
                                                           dst_k, dst_v);
     else
