@@ -1855,8 +1855,14 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
     const double gr2 = out->growth;
     const int lin2 = out->linear_levels;
     for (double f : {0.8, 1.25}) consider(wf1 * f, gr2, lin2, tp0);
+    // the best uses the linear first step: also start straight at that
+    // step's side (w + 0.5 w), without it (a level 0 that defers nearly every
+    // query costs its whole build for nothing)
+    if (out->linear_levels == 1) consider(out->w_factor * 1.5, out->growth, -1, tp0);
     const double wf3 = out->w_factor;
-    for (double tp : {6e7, 1e9}) consider(wf3, gr2, lin2, tp);
+    const double gr3 = out->growth;
+    const int lin3 = out->linear_levels;
+    for (double tp : {6e7, 1e9}) consider(wf3, gr3, lin3, tp);
     if (idx->n <= kZMaxDims) {
       // Z-order levels: levels are cheap, so finer level-0 sides are in range
       z_cur = 1;
