@@ -1884,6 +1884,9 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
         try_z(2.0);
       const double zwf1 = zwf;
       for (double f : {0.7, 1.4}) try_z(zwf1 * f);
+      // and once more, finer, around the best of those
+      const double zwf2 = zwf;
+      for (double f : {0.85, 1.18}) try_z(zwf2 * f);
       if (zbest < rm_best) {
         out->ms_best = zbest;
         out->w_factor = zwf;
@@ -1916,6 +1919,11 @@ int knn_autotune(knn_index* idx, int32_t K, void* stream, knn_autotune_result* o
       consider(wf4, gr4, lin4, tp4);
       if (out->ms_best < before) out->queue_pops = pp;
     }
+    // last, the level-0 side once more with the chosen lanes and queue
+    // granularity (the best side shifts with them)
+    pops_cur = out->queue_pops;
+    for (double f : {0.8, 1.25})
+      consider(out->w_factor * f, out->growth, out->linear_levels, out->tail_pairs);
     pops_cur = 4;
     ls_cur = 0;
     autotune_store(idx->n, K, idx->N,
