@@ -58,6 +58,7 @@ __global__ void k_pair_sums(const double* __restrict__ SX, int n, int64_t ns,
 }
 
 constexpr int kSampleChunk = 256;
+constexpr int kPts = 4;  // points per thread in the distance histogram
 constexpr int kMaxBins = 4096;
 
 // Bin of a distance, floor(sqrt(d2) * inv_bw) with the correctly rounded
@@ -113,32 +114,48 @@ __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N, int64_
       }
     }
     __syncthreads();
-    for (int64_t p = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * pstride; p < N;
-         p += (int64_t)gridDim.x * blockDim.x * pstride) {
-      double x[DIM];
-      float xf[DIM];
+    // each thread takes kPts points (the LDS read of a sample point serves
+    // all of them): point index t0 + u * blockDim (u < kPts), point p =
+    // index * pstride
+    const int64_t nP = (N + pstride - 1) / pstride;
+    for (int64_t t0 = blockIdx.x * (int64_t)blockDim.x * kPts + threadIdx.x; t0 < nP;
+         t0 += (int64_t)gridDim.x * blockDim.x * kPts) {
+      double x[kPts][DIM];
+      float xf[kPts][DIM];
+      int64_t pp[kPts];
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) {
-        x[j] = X[(int64_t)j * N + p];
-        xf[j] = (float)x[j];
+      for (int u = 0; u < kPts; ++u) {
+        const int64_t t = t0 + (int64_t)u * blockDim.x;
+        pp[u] = t < nP ? t * pstride : -1;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+          x[u][j] = pp[u] >= 0 ? X[(int64_t)j * N + pp[u]] : 0.0;
+          xf[u][j] = (float)x[u][j];
+        }
       }
       for (int i = 0; i < cn; ++i) {
-        float sf = 0.0f;
+        float sq[DIM];
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-          const float t = __fsub_rn(xf[j], sxf[j][i]);
-          sf = __fadd_rn(sf, __fmul_rn(t, t));
-        }
-        if (sf > skip_f) continue;  // provably beyond skip_d2
-        double s = 0.0;
+        for (int j = 0; j < DIM; ++j) sq[j] = sxf[j][i];
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-          double t = __dsub_rn(x[j], sx[j][i]);
-          s = __dadd_rn(s, __dmul_rn(t, t));
+        for (int u = 0; u < kPts; ++u) {
+          float sf = 0.0f;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) {
+            const float t = __fsub_rn(xf[u][j], sq[j]);
+            sf = __fadd_rn(sf, __fmul_rn(t, t));
+          }
+          if (sf > skip_f || pp[u] < 0) continue;  // provably beyond skip_d2
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) {
+            const double t = __dsub_rn(x[u][j], sx[j][i]);
+            s = __dadd_rn(s, __dmul_rn(t, t));
+          }
+          if (s > skip_d2 || pp[u] == sid[i]) continue;  // beyond the last bin, or self
+          const int b = dist_bin(s, inv_bw, inv_bw_f, use_f);
+          if (b < n_bins) atomicAdd(&h[b], 1u);
         }
-        if (s > skip_d2 || p == sid[i]) continue;  // certainly beyond the last bin, or self
-        const int b = dist_bin(s, inv_bw, inv_bw_f, use_f);
-        if (b < n_bins) atomicAdd(&h[b], 1u);
       }
     }
   }
@@ -196,7 +213,7 @@ void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sam
       skip_f = tf;
     }
   }
-  int64_t want = ceil_div(ceil_div(N, pstride), kBlock);
+  int64_t want = ceil_div(ceil_div(N, pstride), (int64_t)kBlock * kPts);
   int nb = (int)(want < 2048 ? want : 2048);
   switch (n) {
     case 2: k_dist_histogram<2><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, skip_f, counts); break;
