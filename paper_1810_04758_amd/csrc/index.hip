@@ -11,7 +11,6 @@
 #include <mutex>
 #include <string>
 #include <thread>
-#include <unordered_set>
 
 #include "autotune.hpp"
 #include "index.hpp"
@@ -45,13 +44,29 @@ std::vector<int64_t> sample_ids(int64_t N, int64_t count, uint64_t seed) {
     return out;
   }
   SplitMix64 g{seed};
-  std::unordered_set<int64_t> seen;
-  seen.reserve((size_t)count * 2);
+  // ids seen so far: open addressing, linear probing, at most a quarter full
+  size_t cap = 16;
+  while (cap < (size_t)count * 4) cap <<= 1;
+  std::vector<uint64_t> seen(cap, ~0ull);
+  out.reserve((size_t)count);
   while ((int64_t)out.size() < count) {
-    int64_t id = (int64_t)(g.next() % (uint64_t)N);
-    if (seen.insert(id).second) out.push_back(id);
+    const uint64_t id = g.next() % (uint64_t)N;
+    size_t h = (size_t)((id * 0x9E3779B97F4A7C15ull) >> 20) & (cap - 1);
+    while (seen[h] != ~0ull && seen[h] != id) h = (h + 1) & (cap - 1);
+    if (seen[h] == ~0ull) {
+      seen[h] = id;
+      out.push_back((int64_t)id);
+    }
   }
-  std::sort(out.begin(), out.end());
+  // ascending: LSD radix sort, 11 bits a pass (ids < N < 2^31)
+  std::vector<int64_t> tmp(out.size());
+  for (int sh = 0; sh < 33; sh += 11) {
+    size_t cnt[2049] = {};
+    for (int64_t v : out) ++cnt[((uint64_t)v >> sh & 2047) + 1];
+    for (int b = 0; b < 2048; ++b) cnt[b + 1] += cnt[b];
+    for (int64_t v : out) tmp[cnt[(uint64_t)v >> sh & 2047]++] = v;
+    out.swap(tmp);
+  }
   return out;
 }
 
@@ -1372,26 +1387,26 @@ knn_index* build_from_device(const double* D_dev, int64_t N, int n, const knn_bu
     DevBuf<uint32_t> bad(1);
     KNN_HIP(hipMemsetAsync(bad.p, 0, sizeof(uint32_t), s));
     launch_aos_to_soa(D_dev, N, n, idx->X.p, bad.p, s);
-    uint32_t nbad = 0;
-    KNN_HIP(hipMemcpyAsync(&nbad, bad.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    KNN_HIP(hipStreamSynchronize(s));
-    KNN_CHECK(nbad == 0, KNN_EINVAL, "D holds non-finite coordinates");
-    // bounds
+    // bounds (a non-finite coordinate is reported below, before they are used)
     DevBuf<double> part((size_t)2 * n * kBoundsBlocks), lohi(2 * kMaxDims);
     launch_bounds(idx->X.p, N, n, part.p, lohi.p, lohi.p + kMaxDims, s);
     double hb[2 * kMaxDims];
+    uint32_t nbad = 0;
+    KNN_HIP(hipMemcpyAsync(&nbad, bad.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     KNN_HIP(hipMemcpyAsync(hb, lohi.p, sizeof(hb), hipMemcpyDeviceToHost, s));
-    KNN_HIP(hipStreamSynchronize(s));
-    for (int j = 0; j < n; ++j) {
-      idx->lo[j] = hb[j];
-      idx->hi[j] = hb[kMaxDims + j];
-    }
-    // eps_mean over a sample of mean_frac * N points (Sec. 4.4)
+    // the samples of Sec. 4.4 are drawn on the host while the device works:
+    // eps_mean over mean_frac * N points, the histogram over n_sample points
     int64_t nm = (int64_t)std::llround(o.mean_frac * (double)N);
     nm = std::max<int64_t>(nm, o.min_mean_sample);
     nm = std::min<int64_t>(nm, std::min<int64_t>(N, KNN_MAX_MEAN_SAMPLE));
     std::vector<int64_t> sm = sample_ids(N, nm, o.seed);
     std::vector<int64_t> sh = sample_ids(N, o.n_sample, o.seed ^ 0x5DEECE66Dull);
+    KNN_HIP(hipStreamSynchronize(s));
+    KNN_CHECK(nbad == 0, KNN_EINVAL, "D holds non-finite coordinates");
+    for (int j = 0; j < n; ++j) {
+      idx->lo[j] = hb[j];
+      idx->hi[j] = hb[kMaxDims + j];
+    }
     DevBuf<int64_t> d_sm(sm.size()), d_sh(sh.size());
     KNN_HIP(hipMemcpyAsync(d_sm.p, sm.data(), sm.size() * 8, hipMemcpyHostToDevice, s));
     KNN_HIP(hipMemcpyAsync(d_sh.p, sh.data(), sh.size() * 8, hipMemcpyHostToDevice, s));
