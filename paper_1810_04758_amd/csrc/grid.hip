@@ -424,45 +424,45 @@ __global__ void k_gather_prev(const double* __restrict__ Xs_prev, const int32_t*
   }
 }
 
-// Cell table in one pass: a cell starts where the sorted key changes.  A tile
-// is kCtRounds rounds of 64 consecutive positions per wavefront (coalesced);
-// the start flags of a round are one ballot, kept for the second sweep; the
-// wavefront counts go through a block scan and the look-back over earlier
-// tiles, and every start emits its cell's key and first position.  The last
-// position writes M and cell_start[M].
+// Cell table: a cell starts where the sorted key changes.  A tile is
+// kCtRounds rounds of 64 consecutive positions per wavefront (coalesced); the
+// start flags of a round are one ballot.  Three launches: the tiles' start
+// counts, their exclusive scan, and a second sweep that emits every start's
+// cell key and first position and every position's cell (offsets: the tile's
+// scanned count plus the block's earlier wavefronts and the ballot prefix).
+// No block waits for another, and the tile counts are plain loads and stores.
+// The last position writes M and cell_start[M].
 constexpr int kCtRounds = 16;
 constexpr int kCtTile = kBlock * kCtRounds;
-static_assert(kCtTile >= kLbMinTile, "scan state sized for larger tiles");
 
-// Offsets of a tile's wavefronts: the exclusive prefix of this wavefront's
-// count over the block and the earlier tiles.
-__device__ inline uint32_t tile_wave_offset(uint32_t* state, LbTile lt, uint32_t wcount,
-                                            uint32_t* total_out) {
+// Exclusive prefix of this wavefront's count over the block's wavefronts
+// (all threads; one barrier); *agg = the block's total.
+__device__ inline uint32_t block_wave_prefix(uint32_t wcount, uint32_t* agg) {
   __shared__ uint32_t s_w[kBlock / 64];
-  __shared__ uint32_t s_excl;
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) s_w[w] = wcount;
   __syncthreads();
-  uint32_t before = 0, agg = 0;
+  uint32_t before = 0, tot = 0;
 #pragma unroll
   for (int i = 0; i < kBlock / 64; ++i) {
     if (i < w) before += s_w[i];
-    agg += s_w[i];
+    tot += s_w[i];
   }
-  const uint32_t excl = lb_tile_prefix(state, lt, agg, &s_excl);
-  if (total_out) *total_out = excl + agg;
-  return excl + before;
+  *agg = tot;
+  return before;
 }
 
+// WRITE = false: tile_words[tile] = the tile's cell starts; WRITE = true:
+// tile_words[tile] holds the starts of all earlier tiles.
+template <bool WRITE>
 __global__ void __launch_bounds__(kBlock)
-k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int64_t nb, int shift,
+k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int shift,
              uint32_t* __restrict__ cell_of, uint64_t* __restrict__ cell_key,
              uint32_t* __restrict__ cell_start, uint32_t* __restrict__ d_M,
-             uint32_t* __restrict__ state) {
-  const LbTile lt = lb_take_tile(state, nb);
+             uint32_t* __restrict__ tile_words) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int64_t wbase = lt.tile * kCtTile + (int64_t)w * 64 * kCtRounds;
+  const int64_t wbase = (int64_t)blockIdx.x * kCtTile + (int64_t)w * 64 * kCtRounds;
   uint64_t key[kCtRounds], m[kCtRounds];
   uint32_t cnt = 0;
 #pragma unroll
@@ -474,7 +474,13 @@ k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int64_t nb, int shift
     m[r] = __ballot(i < N && (i == 0 || key[r] != prev));
     cnt += (uint32_t)__popcll(m[r]);
   }
-  uint32_t c = tile_wave_offset(state, lt, cnt, nullptr);  // cells started before
+  uint32_t agg;
+  const uint32_t before = block_wave_prefix(cnt, &agg);
+  if (!WRITE) {
+    if (threadIdx.x == 0) tile_words[blockIdx.x] = agg;
+    return;
+  }
+  uint32_t c = tile_words[blockIdx.x] + before;  // cells started before this wavefront
 #pragma unroll
   for (int r = 0; r < kCtRounds; ++r) {
     const int64_t i = wbase + r * 64 + lane;
@@ -496,16 +502,16 @@ k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int64_t nb, int shift
   }
 }
 
-// Active list in one pass: the sorted positions whose point failed, in order.
+// Active list: the sorted positions whose point failed, in order; the same
+// three launches as the cell table (tile counts, scan, writes).
+template <bool WRITE>
 __global__ void __launch_bounds__(kBlock)
 k_active_list(const uint8_t* __restrict__ failed, uint8_t tag, bool at_least,
-              const int32_t* __restrict__ perm, int64_t N, int64_t nb, int32_t base,
-              int32_t* __restrict__ out, uint32_t* __restrict__ count,
-              uint32_t* __restrict__ state) {
-  const LbTile lt = lb_take_tile(state, nb);
+              const int32_t* __restrict__ perm, int64_t N, int32_t base,
+              int32_t* __restrict__ out, uint32_t* __restrict__ tile_words) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int64_t wbase = lt.tile * kCtTile + (int64_t)w * 64 * kCtRounds;
+  const int64_t wbase = (int64_t)blockIdx.x * kCtTile + (int64_t)w * 64 * kCtRounds;
   uint64_t m[kCtRounds];
   uint32_t cnt = 0;
 #pragma unroll
@@ -515,15 +521,19 @@ k_active_list(const uint8_t* __restrict__ failed, uint8_t tag, bool at_least,
     m[r] = __ballot(p < N && (at_least ? (f >= tag) : (f == tag)));
     cnt += (uint32_t)__popcll(m[r]);
   }
-  uint32_t total;
-  uint32_t o = tile_wave_offset(state, lt, cnt, &total);
+  uint32_t agg;
+  const uint32_t before = block_wave_prefix(cnt, &agg);
+  if (!WRITE) {
+    if (threadIdx.x == 0) tile_words[blockIdx.x] = agg;
+    return;
+  }
+  uint32_t o = tile_words[blockIdx.x] + before;
 #pragma unroll
   for (int r = 0; r < kCtRounds; ++r) {
     if ((m[r] >> lane) & 1ull)
       out[o + (uint32_t)__popcll(m[r] & lt_mask)] = base + (int32_t)(wbase + r * 64 + lane);
     o += (uint32_t)__popcll(m[r]);
   }
-  if (threadIdx.x == 0 && lt.tile == nb - 1) *count = total;
 }
 
 // Point-major sorted coordinates: point p (sorted position) takes the row
@@ -1132,10 +1142,25 @@ void launch_bounds(const double* X, int64_t N, int n, double* part, double* lo, 
   KNN_LAUNCHED();
 }
 
+static size_t tile_area_elems(int64_t n) {
+  // per tile of >= kLbMinTile elements: a count, and two 64-bit masks per
+  // 64 elements (the deferral filter's keep and defer ballots)
+  return (size_t)(ceil_div(n, kLbMinTile) + 1) * (2 + 4 * (kLbMinTile / 64)) + 16;
+}
+
 size_t scan_state_elems(int64_t n) {
-  // scans of up to n elements, or of a radix histogram of n keys
+  // scans of up to n elements, or of a radix histogram of n keys (the
+  // look-back words), then the tile area of compactions of up to n elements
   const int64_t m = std::max<int64_t>(n, ((int64_t)1 << kMaxDigitBits) * ceil_div(n, kRadixTile));
-  return 4 + 2 * (size_t)(ceil_div(m, kLbMinTile) + 1);
+  return 4 + 2 * (size_t)(ceil_div(m, kLbMinTile) + 1) + tile_area_elems(n);
+}
+
+uint32_t* scan_tile_area(uint32_t* state, int64_t state_elems, int64_t words) {
+  // the last `words` (at most tile_area_elems of the size the state was made
+  // for), 8-byte aligned: past every look-back word a scan of that size uses
+  const int64_t start = (state_elems - words) & ~(int64_t)1;
+  KNN_CHECK(words > 0 && start >= 64, KNN_EINTERNAL, "scan state too small for the tile area");
+  return state + start;
 }
 
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
@@ -1245,10 +1270,14 @@ void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags, u
     return;
   }
   const int64_t nb = ceil_div(N, kCtTile);
-  KNN_CHECK(4 + 2 * nb <= state_elems, KNN_EINTERNAL, "scan state too small");
   KNN_CHECK(shift >= 0 && shift < 64, KNN_EINTERNAL, "cell table: key shift out of range");
-  k_cell_table<<<(unsigned)nb, kBlock, 0, s>>>(sorted_keys, N, nb, shift, cell_of, cell_key,
-                                               cell_start, d_M, state);
+  uint32_t* tw = scan_tile_area(state, state_elems, nb + 2);
+  k_cell_table<false><<<(unsigned)nb, kBlock, 0, s>>>(sorted_keys, N, shift, cell_of, cell_key,
+                                                      cell_start, d_M, tw);
+  KNN_LAUNCHED();
+  launch_exclusive_scan(tw, tw, nb, nullptr, state, state_elems, s);
+  k_cell_table<true><<<(unsigned)nb, kBlock, 0, s>>>(sorted_keys, N, shift, cell_of, cell_key,
+                                                     cell_start, d_M, tw);
   KNN_LAUNCHED();
 }
 
@@ -1284,9 +1313,13 @@ void launch_active_list(const uint8_t* failed, uint8_t tag, const int32_t* perm,
     return;
   }
   const int64_t nb = ceil_div(N, kCtTile);
-  KNN_CHECK(4 + 2 * nb <= state_elems, KNN_EINTERNAL, "scan state too small");
-  k_active_list<<<(unsigned)nb, kBlock, 0, s>>>(failed, tag, at_least, perm, N, nb, base, out,
-                                                count, state);
+  uint32_t* tw = scan_tile_area(state, state_elems, nb + 2);
+  k_active_list<false><<<(unsigned)nb, kBlock, 0, s>>>(failed, tag, at_least, perm, N, base, out,
+                                                       tw);
+  KNN_LAUNCHED();
+  launch_exclusive_scan(tw, tw, nb, count, state, state_elems, s);
+  k_active_list<true><<<(unsigned)nb, kBlock, 0, s>>>(failed, tag, at_least, perm, N, base, out,
+                                                      tw);
   KNN_LAUNCHED();
 }
 

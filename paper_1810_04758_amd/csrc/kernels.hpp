@@ -56,9 +56,15 @@ void launch_bounds(const double* X, int64_t N, int n, double* part, double* lo, 
 // state_elems >= scan_state_elems(n) uint32 owned by one stream's work,
 // zero-filled once when allocated and kept between scans (it carries the
 // scans' epoch and ticket); state[2] counts look-back errors (must stay 0).
-// Users of the state take tiles of at least kLbMinTile elements.
+// Users of the state take tiles of at least kLbMinTile elements.  Beyond the
+// look-back words the state holds a tile area for compactions of up to n
+// elements (counts, then their scan, then the writes: tile counts and ballot
+// masks, rewritten by every compaction).
 constexpr int kLbMinTile = 2048;
 size_t scan_state_elems(int64_t n);
+// The tile area's first `words` uint32 (8-byte aligned) of a state of
+// state_elems words made by scan_state_elems for at least the compaction's n.
+uint32_t* scan_tile_area(uint32_t* state, int64_t state_elems, int64_t words);
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total,
                            uint32_t* state, int64_t state_elems, hipStream_t s);
 
@@ -342,8 +348,11 @@ struct DeferArgs {
   int32_t* fail_count;
   unsigned long long* cand_sum;  // nullable: [0] += candidates of kept queries, [1] = max
                                  // (pre-zeroed)
-  uint32_t* state;            // single-pass scan state (launch_exclusive_scan)
+  uint32_t* state;            // scan state (launch_exclusive_scan) and its tile area
   int64_t state_elems;
+  // set by launch_defer_filter (carved from the tile area)
+  uint32_t* tile_counts;
+  uint32_t* tile_masks;
 };
 void launch_defer_filter(const DeferArgs& a, int dims, hipStream_t s);
 

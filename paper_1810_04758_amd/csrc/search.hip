@@ -44,7 +44,6 @@
 #include <tuple>
 
 #include "kernels.hpp"
-#include "lookback.hpp"
 
 namespace knn {
 
@@ -845,28 +844,33 @@ k_search(const SearchArgs a) {
 }
 
 // Deferral filter: a tile is kDeferRounds rounds of 64 consecutive active
-// slots per wavefront (coalesced); keep / defer decisions are ballots, kept
-// slots are compacted in order through the single-pass scan's look-back,
-// deferred ids appended after one atomic per block.
+// slots per wavefront (coalesced); keep / defer decisions are ballots.  Three
+// launches: the decisions (with the skip-ahead flags, pending counts and
+// candidate sums) store their ballots and each tile's kept count, a scan of
+// the counts, and a pass that compacts the kept slots in order from the
+// ballots and appends deferred ids after one atomic per block.
 constexpr int kDeferRounds = 8;
 constexpr int kDeferTile = 256 * kDeferRounds;
-static_assert(kDeferTile >= kLbMinTile, "scan state sized for larger tiles");
+static_assert(kDeferTile >= kLbMinTile, "tile area sized for larger tiles");
+
+// ballots of wavefront w of a tile, round k: keep, then defer
+__device__ inline unsigned long long* defer_masks(const DeferArgs& a, int64_t tile, int w, int k) {
+  return reinterpret_cast<unsigned long long*>(a.tile_masks) +
+         2 * ((tile * 4 + w) * kDeferRounds + k);
+}
 
 template <int DIM>
-__global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t nb) {
-  __shared__ uint32_t s_excl, s_fbase;
-  __shared__ uint32_t s_wk[4], s_wd[4];
+__global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a) {
+  __shared__ uint32_t s_wk[4];
   __shared__ unsigned long long s_sum[4], s_max[4];
   __shared__ uint32_t s_pend[KNN_MAX_LEVELS];  // deferrals per target level (skip-ahead)
   if (a.failed)
     for (int i = threadIdx.x; i < KNN_MAX_LEVELS; i += blockDim.x) s_pend[i] = 0;
-  const LbTile lt = lb_take_tile(a.state, nb);
+  __syncthreads();
+  const int64_t tile = blockIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int64_t wbase = lt.tile * kDeferTile + (int64_t)w * 64 * kDeferRounds;
-  uint64_t mk[kDeferRounds], md[kDeferRounds];
-  int32_t qk[kDeferRounds];
-  uint32_t nk = 0, nd = 0;
+  const int64_t wbase = tile * kDeferTile + (int64_t)w * 64 * kDeferRounds;
+  uint32_t nk = 0;
   unsigned long long csum = 0, cmax = 0;
   const int64_t n_act = a.n_active_dev ? min(a.n_active, (int64_t)*a.n_active_dev) : a.n_active;
   const uint32_t M = a.cell_key ? *a.d_M : 0u;
@@ -875,7 +879,6 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
     const int64_t i = wbase + k * 64 + lane;
     const bool in = i < n_act;
     const int32_t q = in ? (a.active ? a.active[i] : (int32_t)i) : 0;
-    qk[k] = q;
     bool defer = false;
     uint32_t Cq = 0;
     if (in) {
@@ -919,42 +922,18 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
         atomicAdd(&s_pend[target], 1u);
       }
     }
-    mk[k] = __ballot(in && !defer);
-    md[k] = __ballot(in && defer);
-    nk += (uint32_t)__popcll(mk[k]);
-    nd += (uint32_t)__popcll(md[k]);
+    const unsigned long long mk = __ballot(in && !defer);
+    const unsigned long long md = __ballot(in && defer);
+    nk += (uint32_t)__popcll(mk);
+    if (lane == 0) {
+      unsigned long long* mm = defer_masks(a, tile, w, k);
+      mm[0] = mk;
+      mm[1] = md;
+    }
     if (in && !defer) {
       csum += Cq;
       cmax = cmax > Cq ? cmax : (unsigned long long)Cq;
     }
-  }
-  if (lane == 0) {
-    s_wk[w] = nk;
-    s_wd[w] = nd;
-  }
-  __syncthreads();
-  uint32_t bk = 0, bd = 0, agg = 0, dagg = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (i < w) {
-      bk += s_wk[i];
-      bd += s_wd[i];
-    }
-    agg += s_wk[i];
-    dagg += s_wd[i];
-  }
-  if (threadIdx.x == 0)
-    s_fbase = dagg && !a.failed ? (uint32_t)atomicAdd(a.fail_count, (int32_t)dagg) : 0u;
-  const uint32_t excl = lb_tile_prefix(a.state, lt, agg, &s_excl);  // (a barrier)
-  if (threadIdx.x == 0 && lt.tile == nb - 1) *a.out_count = excl + agg;
-  uint32_t o = excl + bk, f = s_fbase + bd;
-#pragma unroll
-  for (int k = 0; k < kDeferRounds; ++k) {
-    if ((mk[k] >> lane) & 1ull) a.out_active[o + (uint32_t)__popcll(mk[k] & lt_mask)] = qk[k];
-    if (((md[k] >> lane) & 1ull) && !a.failed)
-      a.fail_list[f + (uint32_t)__popcll(md[k] & lt_mask)] = a.fail_pos ? qk[k] : a.perm[qk[k]];
-    o += (uint32_t)__popcll(mk[k]);
-    f += (uint32_t)__popcll(md[k]);
   }
   // candidate sum and maximum of the kept queries
 #pragma unroll
@@ -964,6 +943,7 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
     cmax = cmax > m2 ? cmax : m2;
   }
   if (lane == 0) {
+    s_wk[w] = nk;
     s_sum[w] = csum;
     s_max[w] = cmax;
   }
@@ -973,12 +953,67 @@ __global__ void __launch_bounds__(256) k_defer_filter(const DeferArgs a, int64_t
       if (s_pend[i]) atomicAdd(&a.pending[i], s_pend[i]);
   if (threadIdx.x == 0) {
     unsigned long long ts = 0, tm = 0;
+    uint32_t agg = 0;
     for (int i = 0; i < 4; ++i) {
       ts += s_sum[i];
       tm = tm > s_max[i] ? tm : s_max[i];
+      agg += s_wk[i];
     }
+    a.tile_counts[tile] = agg;
     if (a.cand_sum && ts) atomicAdd(&a.cand_sum[0], ts);
     if (a.cand_sum && tm) atomicMax(&a.cand_sum[1], tm);
+  }
+}
+
+// The compaction of a tile's decisions: a.tile_counts holds the kept slots
+// of all earlier tiles.
+__global__ void __launch_bounds__(256) k_defer_write(const DeferArgs a) {
+  __shared__ uint32_t s_wk[4], s_wd[4];
+  __shared__ uint32_t s_fbase;
+  const int64_t tile = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t wbase = tile * kDeferTile + (int64_t)w * 64 * kDeferRounds;
+  unsigned long long mk[kDeferRounds], md[kDeferRounds];
+  uint32_t nk = 0, nd = 0;
+#pragma unroll
+  for (int k = 0; k < kDeferRounds; ++k) {
+    const unsigned long long* mm = defer_masks(a, tile, w, k);
+    mk[k] = mm[0];
+    md[k] = mm[1];
+    nk += (uint32_t)__popcll(mk[k]);
+    nd += (uint32_t)__popcll(md[k]);
+  }
+  if (lane == 0) {
+    s_wk[w] = nk;
+    s_wd[w] = nd;
+  }
+  __syncthreads();
+  uint32_t bk = 0, bd = 0, dagg = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (i < w) {
+      bk += s_wk[i];
+      bd += s_wd[i];
+    }
+    dagg += s_wd[i];
+  }
+  if (threadIdx.x == 0)
+    s_fbase = dagg && !a.failed ? (uint32_t)atomicAdd(a.fail_count, (int32_t)dagg) : 0u;
+  __syncthreads();
+  uint32_t o = a.tile_counts[tile] + bk, f = s_fbase + bd;
+#pragma unroll
+  for (int k = 0; k < kDeferRounds; ++k) {
+    const int64_t i = wbase + k * 64 + lane;
+    const bool keep = (mk[k] >> lane) & 1ull;
+    const bool dfr = ((md[k] >> lane) & 1ull) && !a.failed;
+    if (keep || dfr) {
+      const int32_t q = a.active ? a.active[i] : (int32_t)i;
+      if (keep) a.out_active[o + (uint32_t)__popcll(mk[k] & lt_mask)] = q;
+      if (dfr) a.fail_list[f + (uint32_t)__popcll(md[k] & lt_mask)] = a.fail_pos ? q : a.perm[q];
+    }
+    o += (uint32_t)__popcll(mk[k]);
+    f += (uint32_t)__popcll(md[k]);
   }
 }
 
@@ -1346,15 +1381,23 @@ void launch_defer_filter(const DeferArgs& a, int dims, hipStream_t s) {
     return;
   }
   const int64_t nb = ceil_div(a.n_active, kDeferTile);
-  KNN_CHECK(4 + 2 * nb <= a.state_elems, KNN_EINTERNAL, "scan state too small");
+  // the tile area: nb counts (padded to even), then 2 masks per 64 slots
+  const int64_t cwords = (nb + 2) & ~(int64_t)1;
+  const int64_t mwords = nb * 4 * kDeferRounds * 4;
+  DeferArgs b = a;
+  b.tile_counts = scan_tile_area(a.state, a.state_elems, cwords + mwords);
+  b.tile_masks = b.tile_counts + cwords;
   switch (dims) {
-    case 2: k_defer_filter<2><<<(unsigned)nb, 256, 0, s>>>(a, nb); break;
-    case 3: k_defer_filter<3><<<(unsigned)nb, 256, 0, s>>>(a, nb); break;
-    case 4: k_defer_filter<4><<<(unsigned)nb, 256, 0, s>>>(a, nb); break;
-    case 5: k_defer_filter<5><<<(unsigned)nb, 256, 0, s>>>(a, nb); break;
-    case 6: k_defer_filter<6><<<(unsigned)nb, 256, 0, s>>>(a, nb); break;
+    case 2: k_defer_filter<2><<<(unsigned)nb, 256, 0, s>>>(b); break;
+    case 3: k_defer_filter<3><<<(unsigned)nb, 256, 0, s>>>(b); break;
+    case 4: k_defer_filter<4><<<(unsigned)nb, 256, 0, s>>>(b); break;
+    case 5: k_defer_filter<5><<<(unsigned)nb, 256, 0, s>>>(b); break;
+    case 6: k_defer_filter<6><<<(unsigned)nb, 256, 0, s>>>(b); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
+  KNN_LAUNCHED();
+  launch_exclusive_scan(b.tile_counts, b.tile_counts, nb, a.out_count, a.state, a.state_elems, s);
+  k_defer_write<<<(unsigned)nb, 256, 0, s>>>(b);
   KNN_LAUNCHED();
 }
 
