@@ -567,6 +567,24 @@ __global__ void k_dense_scatter(const uint64_t* __restrict__ cell_key, const uin
     table[cell_key[c]] = (uint32_t)c;
 }
 
+// Z-order level: the row-major cell index (strides of the level) of each
+// cell, -> its position in the cell table.  The table is not cleared first:
+// a reader checks that an entry names a cell of the level with its key.
+template <int DIM>
+__global__ void k_dense_scatter_z(const uint64_t* __restrict__ cell_key, const uint32_t* d_M,
+                                  GeomDev gd, uint32_t* __restrict__ table) {
+  const uint32_t M = *d_M;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < M;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    int64_t cc[DIM];
+    zorder_coords<DIM>(cell_key[c], gd.zbits, cc);
+    uint64_t rk = 0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) rk += (uint64_t)cc[j] * gd.stride[j];
+    table[rk] = (uint32_t)c;
+  }
+}
+
 // Index of the first cell whose key is >= key (binary search in cell_key[0..M)).
 __device__ inline uint32_t lower_bound_key(const uint64_t* __restrict__ cell_key, uint32_t lo,
                                            uint32_t hi, uint64_t key) {
@@ -910,6 +928,7 @@ template <int DIM>
 __global__ void k_neighbor_ranges_z(const uint32_t* __restrict__ cell_start,
                                     const uint64_t* __restrict__ cell_key, const uint32_t* d_M,
                                     const uint8_t* __restrict__ cell_active, uint8_t active_tag,
+                                    const uint32_t* __restrict__ dense,
                                     GeomDev gd, uint32_t* __restrict__ ranges,
                                     uint8_t* __restrict__ rslot, uint32_t* __restrict__ nrng,
                                     uint32_t* __restrict__ cand_count) {
@@ -951,8 +970,20 @@ __global__ void k_neighbor_ranges_z(const uint32_t* __restrict__ cell_start,
           if (nb[j] < 0 || nb[j] >= gd.g[j]) inside = false;
         }
         if (inside) {
-          const uint32_t f =
-              find_cell_near(cell_key, M, (uint32_t)c, k0, zorder_key<DIM>(nb, gd.zbits));
+          const uint64_t nk = zorder_key<DIM>(nb, gd.zbits);
+          uint32_t f;
+          if (dense) {
+            // the level's cell at these coordinates, if the entry is this
+            // level's: entries are never cleared, so one is trusted only
+            // when it names a cell of the level with this key
+            uint64_t rk = 0;
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) rk += (uint64_t)nb[j] * gd.stride[j];
+            f = dense[rk];
+            if (f >= M || cell_key[f] != nk) f = 0xFFFFFFFFu;
+          } else {
+            f = find_cell_near(cell_key, M, (uint32_t)c, k0, nk);
+          }
           if (f != 0xFFFFFFFFu) {
             start = cell_start[f];
             end = cell_start[f + 1];
@@ -1289,17 +1320,30 @@ void launch_pos_to_id(int32_t* list, int64_t n, const int32_t* perm, hipStream_t
 
 void launch_neighbor_ranges_z(const uint32_t* cell_start, const uint64_t* cell_key,
                               const uint32_t* d_M, int64_t N, const uint8_t* cell_active,
-                              uint8_t active_tag, const GridGeom& gg, uint32_t* ranges,
-                              uint8_t* rslot, uint32_t* nrng, uint32_t* cand_count,
-                              hipStream_t s) {
+                              uint8_t active_tag, const GridGeom& gg, uint32_t* dense,
+                              int64_t dense_size, uint32_t* ranges, uint8_t* rslot,
+                              uint32_t* nrng, uint32_t* cand_count, hipStream_t s) {
   KNN_CHECK(gg.zbits >= 0 && gg.dims <= kZMaxDims, KNN_EINTERNAL, "not a Z-order level");
   GeomDev gd = to_dev(gg);
+  if (dense) {
+    long double cells = 1;
+    for (int j = 0; j < gg.dims; ++j) cells *= (long double)gg.g[j];
+    KNN_CHECK(cells <= (long double)dense_size, KNN_EINTERNAL, "dense cell table too small");
+    const int sb = grid_for(N);
+    switch (gg.dims) {
+      case 2: k_dense_scatter_z<2><<<sb, kBlock, 0, s>>>(cell_key, d_M, gd, dense); break;
+      case 3: k_dense_scatter_z<3><<<sb, kBlock, 0, s>>>(cell_key, d_M, gd, dense); break;
+      case 4: k_dense_scatter_z<4><<<sb, kBlock, 0, s>>>(cell_key, d_M, gd, dense); break;
+      default: throw Error(KNN_EINVAL, "Z-order levels take 2-4 dimensions");
+    }
+    KNN_LAUNCHED();
+  }
   const int S = gg.dims == 2 ? 9 : gg.dims == 3 ? 27 : 64;
   const int nb = grid_for(N * 64 / (64 / S), 65536);
   switch (gg.dims) {
-    case 2: k_neighbor_ranges_z<2><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
-    case 3: k_neighbor_ranges_z<3><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
-    case 4: k_neighbor_ranges_z<4><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, gd, ranges, rslot, nrng, cand_count); break;
+    case 2: k_neighbor_ranges_z<2><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, dense, gd, ranges, rslot, nrng, cand_count); break;
+    case 3: k_neighbor_ranges_z<3><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, dense, gd, ranges, rslot, nrng, cand_count); break;
+    case 4: k_neighbor_ranges_z<4><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, dense, gd, ranges, rslot, nrng, cand_count); break;
     default: throw Error(KNN_EINVAL, "Z-order levels take 2-4 dimensions");
   }
   KNN_LAUNCHED();

@@ -394,10 +394,7 @@ void build_grid_z(const knn_index& idx, JoinContext& c, double w0, int level, hi
   c.M = -1;
   c.dense_used = nullptr;
   c.rowtab_used = nullptr;
-  if (!c.graph_owned && !c.fixed) {  // neither lookup table is used
-    c.dense.release();
-    c.rowtab.release();
-  }
+  if (!c.graph_owned && !c.fixed) c.rowtab.release();  // the dense table serves the ranges
 }
 
 bool use_zorder(const knn_index& idx, int32_t K, const knn_join_opts& o) {
@@ -428,13 +425,25 @@ int64_t build_ranges(const knn_index& idx, JoinContext& c, hipStream_t s, int64_
   c.ranges.reserve((size_t)Mcap * R * 4);
   c.rslot.reserve((size_t)Mcap * R);
   c.nrng.reserve(N);
-  if (c.zmode)
+  if (c.zmode) {
+    // neighbours through a row-major table of the level's cells when it fits
+    // (never cleared: entries are checked against the cell keys)
+    long double cells = 1;
+    for (int j = 0; j < n; ++j) cells *= (long double)c.gg.g[j];
+    const int64_t lim = c.table_cap > 0 ? c.table_cap : std::max<int64_t>(64 * N, 1 << 22);
+    uint32_t* dense = nullptr;
+    if (cells <= (long double)lim && (!c.fixed || (long double)c.dense.n >= cells)) {
+      c.dense.reserve((size_t)cells);
+      dense = c.dense.p;
+    }
     launch_neighbor_ranges_z(c.cell_start.p, c.cell_key.p, c.scal.p, N, cell_active, active_tag,
-                             c.gg, c.ranges.p, c.rslot.p, c.nrng.p, c.cand_count.p, s);
-  else
+                             c.gg, dense, dense ? (int64_t)c.dense.n : 0, c.ranges.p, c.rslot.p,
+                             c.nrng.p, c.cand_count.p, s);
+  } else {
     launch_neighbor_ranges(c.Xs.p, N, c.cell_start.p, c.cell_key.p, c.scal.p, c.dense_used,
                            c.rowtab_used, cell_active, active_tag, c.gg, c.ranges.p, c.rslot.p,
                            c.nrng.p, c.cand_count.p, s);
+  }
   return Mcap;
 }
 
@@ -526,7 +535,7 @@ void for_each_join_buffer(const knn_index& idx, JoinContext& c, int32_t K,
   f(c.ikeys2, N);
   f(c.ivals, N);
   f(c.ivals2, N);
-  if (n > 2) f(c.dense, table_cap);
+  f(c.dense, table_cap);  // row-major levels of 3-6 dims, Z-order levels
   f(c.rowtab, table_cap);
   // the tail runs once A * N <= budget with A <= 65535 remaining queries
   const double budget = tail_budget_of(idx, K, o);

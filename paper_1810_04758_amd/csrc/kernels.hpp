@@ -141,11 +141,15 @@ void launch_neighbor_ranges(const double* Xs, int64_t N, const uint32_t* cell_st
 // reads it unchanged.  Neighbours are found by a galloping search outward
 // from the cell's own position in cell_key (Z-order neighbours are mostly
 // close in the sorted cell table).  ranges: R = 3^n entries per cell.
+// dense (nullable, dense_size >= the level's prod(g) entries, contents
+// arbitrary): first filled with each cell's position at its row-major index,
+// then neighbours are looked up there (one load and a key check) instead of
+// by the galloping search.
 void launch_neighbor_ranges_z(const uint32_t* cell_start, const uint64_t* cell_key,
                               const uint32_t* d_M, int64_t N, const uint8_t* cell_active,
-                              uint8_t active_tag, const GridGeom& gg, uint32_t* ranges,
-                              uint8_t* rslot, uint32_t* nrng, uint32_t* cand_count,
-                              hipStream_t s);
+                              uint8_t active_tag, const GridGeom& gg, uint32_t* dense,
+                              int64_t dense_size, uint32_t* ranges, uint8_t* rslot,
+                              uint32_t* nrng, uint32_t* cand_count, hipStream_t s);
 // flags[cell_of[active[i]]] = tag for every active query (n_dev non-NULL:
 // the first min(n_active, *n_dev) of the list).
 void launch_mark_cells_of(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
