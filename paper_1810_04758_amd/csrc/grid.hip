@@ -270,13 +270,24 @@ k_radix_scatter_lds(const uint64_t* __restrict__ keys, const int32_t* __restrict
 #pragma unroll
     for (int i = 0; i < kBlock / 64; ++i) wcnt[i][t] = 0;
   }
+  // the tile's keys and values, all loads in flight at once (the rounds
+  // below would otherwise wait for one load each)
+  uint64_t kk[kRadixItems];
+  int32_t vv[kRadixItems];
+#pragma unroll
+  for (int k = 0; k < kRadixItems; ++k) {
+    const int64_t i = base + (int64_t)k * kBlock + t;
+    kk[k] = i < n ? keys[i] : 0;
+    vv[k] = i < n ? vals[i] : 0;
+  }
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
   for (int k = 0; k < kRadixItems; ++k) {
     const int64_t i = base + (int64_t)k * kBlock + t;
     const bool valid = i < n;
-    const uint64_t key = valid ? keys[i] : 0;
-    const int32_t val = valid ? vals[i] : 0;
+    const uint64_t key = kk[k];
+    const int32_t val = vv[k];
     const uint32_t d = (uint32_t)(key >> shift) & (uint32_t)(RB - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
