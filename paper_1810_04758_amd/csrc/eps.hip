@@ -139,13 +139,15 @@ __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N, int64_
         for (int j = 0; j < DIM; ++j) sq[j] = sxf[j][i];
 #pragma unroll
         for (int u = 0; u < kPts; ++u) {
+          // each square added with one rounding (a fused multiply-add)
           float sf = 0.0f;
 #pragma unroll
           for (int j = 0; j < DIM; ++j) {
             const float t = __fsub_rn(xf[u][j], sq[j]);
-            sf = __fadd_rn(sf, __fmul_rn(t, t));
+            sf = __builtin_fmaf(t, t, sf);
           }
-          if (sf > skip_f || pp[u] < 0) continue;  // provably beyond skip_d2
+          if (sf > skip_f) continue;  // provably beyond skip_d2
+          if (pp[u] < 0) continue;
           double s = 0.0;
 #pragma unroll
           for (int j = 0; j < DIM; ++j) {
@@ -193,8 +195,10 @@ void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sam
   // coordinate's conversion to float errs by at most A 2^-24 (plus 2^-149
   // below float's normal range), so a float difference df_j of the converted
   // values satisfies |df_j| <= (|x_j - q_j| + e)(1 + 2^-24), e = 2 A 2^-24 +
-  // 2^-148; the float sum sf of the n rounded squares is at most
-  // sum df_j^2 (1 + 2^-20).  Hence d = ||x - q|| >= sqrt(sf / (1 + 2^-20)) /
+  // 2^-148; the float sum sf of the n squares, each added by a fused
+  // multiply-add (one rounding of 2^-24 per step), is at most
+  // sum df_j^2 (1 + 2^-24)^n <= sum df_j^2 (1 + 2^-20).  Hence
+  // d = ||x - q|| >= sqrt(sf / (1 + 2^-20)) /
   // (1 + 2^-24) - sqrt(n) e, and sf > (L + sqrt(n) e)^2 (1 + 2^-18) gives
   // d > L = sqrt(skip_d2 (1 + 2^-49)), so the double-precision d^2 (n + 1
   // roundings of 2^-53 each) exceeds skip_d2: such a pair is never counted.
