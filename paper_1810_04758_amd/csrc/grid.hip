@@ -1030,6 +1030,103 @@ __global__ void k_neighbor_ranges_z(const uint32_t* __restrict__ cell_start,
   }
 }
 
+// First position in keys[0..N) whose key is >= k (N if none).
+__device__ inline int64_t lower_bound_u64(const uint64_t* __restrict__ keys, int64_t N,
+                                          uint64_t k) {
+  int64_t lo = 0, hi = N;
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (keys[mid] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// A Z-order level with few active queries, without its cell table: slot i
+// holds the ranges of the 3^n block of the i-th active query (sorted
+// position q), each neighbour cell's points found in the sorted level-0
+// keys as the run whose keys shifted right by zshift equal the cell's key
+// (two binary searches), in the format of k_neighbor_ranges_z; cell_of[q] =
+// i, and *d_M = the number of slots.  A group of S lanes per query.
+template <int DIM>
+__global__ void k_sparse_ranges_z(const uint64_t* __restrict__ keys, int64_t N,
+                                  const int32_t* __restrict__ active, int64_t n_active,
+                                  const uint32_t* n_dev, int zshift, GeomDev gd,
+                                  uint32_t* __restrict__ ranges, uint8_t* __restrict__ rslot,
+                                  uint32_t* __restrict__ nrng, uint32_t* __restrict__ cand_count,
+                                  uint32_t* __restrict__ cell_of, uint32_t* __restrict__ d_M) {
+  constexpr int R = DIM == 2 ? 9 : DIM == 3 ? 27 : 81;
+  constexpr int S = R <= 64 ? R : 64;
+  constexpr int GPW = 64 / S;
+  const int64_t na = n_dev ? min(n_active, (int64_t)*n_dev) : n_active;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *d_M = (uint32_t)na;
+  const int lane = threadIdx.x & 63;
+  const int l = lane % S;
+  const int sub = lane / S;
+  const uint64_t lt = l == 0 ? 0ull : (~0ull >> (64 - l));
+  const uint64_t gmask = S >= 64 ? ~0ull : ((1ull << (S & 63)) - 1ull);
+  const int64_t wpb = blockDim.x / 64;
+  const int64_t groups = (int64_t)gridDim.x * wpb * GPW;
+  const int64_t i0 = sub < GPW ? ((int64_t)blockIdx.x * wpb + threadIdx.x / 64) * GPW + sub : na;
+  for (int64_t i = i0; i < na; i += groups) {
+    const int32_t q = active[i];
+    const uint64_t k0 = keys[q] >> zshift;
+    int64_t cc[DIM];
+    zorder_coords<DIM>(k0, gd.zbits, cc);
+    uint32_t count = 0, cand = 0;
+    for (int rb = 0; rb < R; rb += S) {
+      const int r = rb + l;
+      uint32_t start = 0, end = 0;
+      int olast = 0;
+      if (r < R) {
+        int64_t nb[DIM];
+        bool inside = true;
+        int rr = r;
+#pragma unroll
+        for (int j = DIM - 1; j >= 0; --j) {
+          const int o = rr % 3 - 1;
+          rr /= 3;
+          if (j == DIM - 1) olast = o;
+          nb[j] = cc[j] + o;
+          if (nb[j] < 0 || nb[j] >= gd.g[j]) inside = false;
+        }
+        if (inside) {
+          const uint64_t nk = zorder_key<DIM>(nb, gd.zbits);
+          start = (uint32_t)lower_bound_u64(keys, N, nk << zshift);
+          end = (uint32_t)lower_bound_u64(keys, N, (nk + 1) << zshift);
+        }
+      }
+      const bool ne = end > start;
+      const uint64_t m = (S == 64 ? __ballot(ne) : (__ballot(ne) >> (sub * S))) & gmask;
+      if (ne) {
+        const uint32_t pos = count + (uint32_t)__popcll(m & lt);
+        const uint32_t m0 = olast < 0 ? end : start;
+        const uint32_t m1 = olast > 0 ? start : end;
+        reinterpret_cast<uint4*>(ranges)[i * R + pos] = make_uint4(start, m0, m1, end);
+        rslot[i * R + pos] = (uint8_t)(r / 3);
+        cand += end - start;
+      }
+      count += (uint32_t)__popcll(m);
+    }
+    if constexpr ((S & (S - 1)) == 0) {
+#pragma unroll
+      for (int o = 1; o < S; o <<= 1) cand += __shfl_xor(cand, o, 64);
+    } else {
+      uint32_t tot = 0;
+#pragma unroll
+      for (int o = 0; o < S; ++o) tot += __shfl(cand, sub * S + o, 64);
+      cand = tot;
+    }
+    if (l == 0) {
+      nrng[i] = count;
+      cand_count[i] = cand;
+      cell_of[q] = (uint32_t)i;
+    }
+  }
+}
+
 // Index of the first cell whose key is >= key in cell_key[0..M) (M >= 1),
 // clamped to M - 1: a starting point for the galloping search.
 __device__ inline uint32_t start_cell(const uint64_t* __restrict__ cell_key, uint32_t M,
@@ -1355,6 +1452,30 @@ void launch_neighbor_ranges_z(const uint32_t* cell_start, const uint64_t* cell_k
     case 2: k_neighbor_ranges_z<2><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, dense, gd, ranges, rslot, nrng, cand_count); break;
     case 3: k_neighbor_ranges_z<3><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, dense, gd, ranges, rslot, nrng, cand_count); break;
     case 4: k_neighbor_ranges_z<4><<<nb, kBlock, 0, s>>>(cell_start, cell_key, d_M, cell_active, active_tag, dense, gd, ranges, rslot, nrng, cand_count); break;
+    default: throw Error(KNN_EINVAL, "Z-order levels take 2-4 dimensions");
+  }
+  KNN_LAUNCHED();
+}
+
+void launch_sparse_ranges_z(const uint64_t* sorted_keys, int64_t N, const int32_t* active,
+                            int64_t n_active, const uint32_t* n_dev, const GridGeom& gg,
+                            uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
+                            uint32_t* cand_count, uint32_t* cell_of, uint32_t* d_M,
+                            hipStream_t s) {
+  KNN_CHECK(gg.zbits >= 0 && gg.dims <= kZMaxDims, KNN_EINTERNAL, "not a Z-order level");
+  KNN_CHECK(gg.zshift >= 0 && gg.zshift + gg.dims * gg.zbits <= 62, KNN_EINTERNAL,
+            "Z-order level: key bits out of range");
+  if (n_active <= 0) {
+    launch_zero(d_M, sizeof(uint32_t), s);
+    return;
+  }
+  GeomDev gd = to_dev(gg);
+  const int S = gg.dims == 2 ? 9 : gg.dims == 3 ? 27 : 64;
+  const int nb = grid_for(ceil_div(n_active, 64 / S) * 64, 65536);
+  switch (gg.dims) {
+    case 2: k_sparse_ranges_z<2><<<nb, kBlock, 0, s>>>(sorted_keys, N, active, n_active, n_dev, gg.zshift, gd, ranges, rslot, nrng, cand_count, cell_of, d_M); break;
+    case 3: k_sparse_ranges_z<3><<<nb, kBlock, 0, s>>>(sorted_keys, N, active, n_active, n_dev, gg.zshift, gd, ranges, rslot, nrng, cand_count, cell_of, d_M); break;
+    case 4: k_sparse_ranges_z<4><<<nb, kBlock, 0, s>>>(sorted_keys, N, active, n_active, n_dev, gg.zshift, gd, ranges, rslot, nrng, cand_count, cell_of, d_M); break;
     default: throw Error(KNN_EINVAL, "Z-order levels take 2-4 dimensions");
   }
   KNN_LAUNCHED();

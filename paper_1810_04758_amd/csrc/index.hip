@@ -459,6 +459,12 @@ int64_t build_level(const knn_index& idx, JoinContext& c, double w, hipStream_t 
   return build_ranges(idx, c, s, Mcap_known, nullptr, 0);
 }
 
+// Z-order self-join levels after the first with at most this many active
+// queries build no cell table (launch_sparse_ranges_z): on 2e7 points the
+// table's two sweeps cost about 0.1 ms, the sparse lookups of 1.6e4 queries
+// (3^n blocks, two binary searches each) a few tens of microseconds.
+constexpr int64_t kSparseLevelQueries = 16384;
+
 uint64_t join_footprint(const knn_index& idx, int32_t K, bool host_output) {
   // Upper bound of everything a JoinContext allocates, with the worst case of
   // one non-empty cell per point (M = N), and of what the device cache hands
@@ -793,9 +799,21 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
     // level 0 sorts the points from their original order, later levels from
     // the previous level's order (row-major) or not at all (Z-order)
     const bool reuse = level == 0 && keep_l0 && c.l0_cached && c.l0_w == w && c.l0_zl == zl;
+    // a later Z-order level of a self-join with few active queries builds no
+    // cell table: each query's block is looked up in the sorted level-0 keys
+    // (the table over all N points would cost more than their searches)
+    const bool sparse = zl && !rj && level > 0 && A <= kSparseLevelQueries;
     if (reuse) {
       // level 0 of the previous query-set join with this cell side: the
       // indexed points' grid is unchanged (only the appended queries differ)
+    } else if (sparse) {
+      KNN_CHECK(level <= c.gz0.zbits, KNN_EINTERNAL,
+                "Z-order levels ran past their single-cell top");
+      c.zmode = true;
+      c.gg = z_level_geom(c.gz0, level);
+      c.M = -1;
+      c.dense_used = nullptr;
+      c.rowtab_used = nullptr;
     } else if (zl) {
       // the top of the ladder is one cell, where every query succeeds
       KNN_CHECK(level == 0 || level <= c.gz0.zbits, KNN_EINTERNAL,
@@ -901,7 +919,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       return da;
     };
     const uint32_t* n_pre = nullptr;  // device count of the list the prefilter kept
-    if (zl && filt && !rj) {
+    if (zl && filt && !rj && !sparse) {
       // Z-order levels: a first deferral from the parent-group density, before
       // any neighbour range exists, so that ranges are built only for the
       // cells of the queries it keeps (most of a fine level's queries are
@@ -930,6 +948,13 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
                           c.cell_start.p, c.cell_key.p, c.scal.p,
                           c.dense_used, c.rowtab_used, c.gg, zl, c.cell_of.p, c.ranges.p,
                           c.rslot.p, c.nrng.p, c.cand_count.p, s);
+    } else if (sparse) {
+      const int64_t R = pow3(idx.n);
+      c.ranges.reserve((size_t)A * R * 4);
+      c.rslot.reserve((size_t)A * R);
+      launch_sparse_ranges_z(c.keys.p, N, active, A, c.scal.p + 1, c.gg, c.ranges.p, c.rslot.p,
+                             c.nrng.p, c.cand_count.p, c.cell_of.p, c.scal.p, s);
+      lp.Mcap = A;
     } else {
       if (level > 0 || n_pre) {
         // neighbour ranges only for the cells that hold an active query
@@ -946,7 +971,7 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       // the deferral filter on the block density (candidate counts)
       int32_t* out = n_pre ? c.active.p : (c.active2.reserve(std::max(N, NQ)), c.active2.p);
       DeferArgs da = defer_args(active, out, c.scal.p + 2);
-      da.n_active_dev = n_pre;
+      da.n_active_dev = n_pre ? n_pre : sparse ? c.scal.p + 1 : nullptr;
       launch_defer_filter(da, idx.n, s);
       active = out;
     }

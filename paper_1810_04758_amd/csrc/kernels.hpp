@@ -150,6 +150,17 @@ void launch_neighbor_ranges_z(const uint32_t* cell_start, const uint64_t* cell_k
                               uint8_t active_tag, const GridGeom& gg, uint32_t* dense,
                               int64_t dense_size, uint32_t* ranges, uint8_t* rslot,
                               uint32_t* nrng, uint32_t* cand_count, hipStream_t s);
+// A Z-order level's ranges without its cell table, for few active queries:
+// slot i (the i-th active sorted position q, the first min(n_active,
+// *n_dev) of the list) gets the ranges of q's 3^n block in the format above,
+// each neighbour cell's points found by binary search in the sorted level-0
+// keys (keys >> gg.zshift == the cell's key); cell_of[q] = i, nrng and
+// cand_count by slot, and *d_M = the number of slots.
+void launch_sparse_ranges_z(const uint64_t* sorted_keys, int64_t N, const int32_t* active,
+                            int64_t n_active, const uint32_t* n_dev, const GridGeom& gg,
+                            uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
+                            uint32_t* cand_count, uint32_t* cell_of, uint32_t* d_M,
+                            hipStream_t s);
 // flags[cell_of[active[i]]] = tag for every active query (n_dev non-NULL:
 // the first min(n_active, *n_dev) of the list).
 void launch_mark_cells_of(const int32_t* active, int64_t n_active, const uint32_t* cell_of,
