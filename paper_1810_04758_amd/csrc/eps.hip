@@ -58,7 +58,11 @@ __global__ void k_pair_sums(const double* __restrict__ SX, int n, int64_t ns,
 }
 
 constexpr int kSampleChunk = 256;
-constexpr int kPts = 4;  // points per thread in the distance histogram
+// points per thread in the distance histogram: 4 on a pass over every point
+// (one LDS read of a sample point serves four pairs), 1 on a strided estimate
+// pass (four times the workgroups: a few hundred workgroups of four points
+// per thread left one wavefront per SIMD and no latency hidden)
+constexpr int kPtsAll = 4;
 constexpr int kMaxBins = 4096;
 
 // Bin of a distance, floor(sqrt(d2) * inv_bw) with the correctly rounded
@@ -88,7 +92,7 @@ __device__ __forceinline__ int dist_bin(double d2, double inv_bw, float inv_bw_f
 // skip_f: a single-precision squared distance above it proves the pair's
 // double-precision d^2 above skip_d2 (see launch_dist_histogram), so most far
 // pairs are rejected at single-precision rate; +inf disables the test.
-template <int DIM>
+template <int DIM, int kPts>
 __global__ void k_dist_histogram(const double* __restrict__ X, int64_t N, int64_t pstride,
                                  const int64_t* __restrict__ sample, int64_t ns, double inv_bw,
                                  int count_bins, double skip_d2, float skip_f,
@@ -217,16 +221,26 @@ void launch_dist_histogram(const double* X, int64_t N, int n, const int64_t* sam
       skip_f = tf;
     }
   }
-  int64_t want = ceil_div(ceil_div(N, pstride), (int64_t)kBlock * kPts);
+  const int pts = pstride > 1 ? 1 : kPtsAll;
+  int64_t want = ceil_div(ceil_div(N, pstride), (int64_t)kBlock * pts);
   int nb = (int)(want < 2048 ? want : 2048);
-  switch (n) {
-    case 2: k_dist_histogram<2><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, skip_f, counts); break;
-    case 3: k_dist_histogram<3><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, skip_f, counts); break;
-    case 4: k_dist_histogram<4><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, skip_f, counts); break;
-    case 5: k_dist_histogram<5><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, skip_f, counts); break;
-    case 6: k_dist_histogram<6><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, skip_d2, skip_f, counts); break;
+#define KNN_HIST(D, P) \
+  k_dist_histogram<D, P><<<nb, kBlock, 0, s>>>(X, N, pstride, sample, ns, inv_bw, count_bins, \
+                                               skip_d2, skip_f, counts)
+  switch (n * 8 + pts) {
+    case 2 * 8 + 1: KNN_HIST(2, 1); break;
+    case 3 * 8 + 1: KNN_HIST(3, 1); break;
+    case 4 * 8 + 1: KNN_HIST(4, 1); break;
+    case 5 * 8 + 1: KNN_HIST(5, 1); break;
+    case 6 * 8 + 1: KNN_HIST(6, 1); break;
+    case 2 * 8 + kPtsAll: KNN_HIST(2, kPtsAll); break;
+    case 3 * 8 + kPtsAll: KNN_HIST(3, kPtsAll); break;
+    case 4 * 8 + kPtsAll: KNN_HIST(4, kPtsAll); break;
+    case 5 * 8 + kPtsAll: KNN_HIST(5, kPtsAll); break;
+    case 6 * 8 + kPtsAll: KNN_HIST(6, kPtsAll); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
+#undef KNN_HIST
   KNN_LAUNCHED();
 }
 
