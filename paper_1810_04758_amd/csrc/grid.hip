@@ -165,8 +165,8 @@ constexpr int kRadixItems = 16;
 constexpr int kRadixTile = kBlock * kRadixItems;
 constexpr int kMaxDigitBits = 11;
 
-template <int DB>
-__global__ void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+template <int DB, class KeyT>
+__global__ void k_radix_hist(const KeyT* __restrict__ keys, int64_t n, int shift,
                              uint32_t* __restrict__ hist, int64_t nb) {
   constexpr int RB = 1 << DB;
   __shared__ uint32_t h[RB];
@@ -176,7 +176,7 @@ __global__ void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int s
 #pragma unroll
   for (int k = 0; k < kRadixItems; ++k) {
     int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (uint64_t)(RB - 1)], 1u);
+    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (uint32_t)(RB - 1)], 1u);
   }
   __syncthreads();
   for (int d = threadIdx.x; d < RB; d += kBlock) hist[(int64_t)d * nb + blockIdx.x] = h[d];
@@ -188,11 +188,11 @@ __global__ void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int s
 // digit's first lane), so the keys of earlier waves precede it.  Only the
 // entries a round touched are updated afterwards (run[d] advanced, wcnt
 // cleared), not all RB digits.
-template <int DB>
-__global__ void k_radix_scatter(const uint64_t* __restrict__ keys,
+template <int DB, class KeyT>
+__global__ void k_radix_scatter(const KeyT* __restrict__ keys,
                                 const int32_t* __restrict__ vals, int64_t n, int shift,
                                 const uint32_t* __restrict__ offs, int64_t nb,
-                                uint64_t* __restrict__ okeys, int32_t* __restrict__ ovals) {
+                                KeyT* __restrict__ okeys, int32_t* __restrict__ ovals) {
   constexpr int RB = 1 << DB;
   __shared__ uint32_t run[RB];
   __shared__ uint32_t wcnt[kBlock / 64][RB];
@@ -208,7 +208,7 @@ __global__ void k_radix_scatter(const uint64_t* __restrict__ keys,
   for (int k = 0; k < kRadixItems; ++k) {
     int64_t i = base + (int64_t)k * kBlock + t;
     bool valid = i < n;
-    uint64_t key = valid ? keys[i] : 0;
+    KeyT key = valid ? keys[i] : 0;
     int32_t val = valid ? vals[i] : 0;
     uint32_t d = (uint32_t)(key >> shift) & (uint32_t)(RB - 1);
     uint64_t peers = __ballot(valid);
@@ -245,14 +245,15 @@ __global__ void k_radix_scatter(const uint64_t* __restrict__ keys,
 // 4096-key tile) instead of 256 scattered 8-byte stores per round.  The tile's
 // count of digit d is the difference of consecutive entries of the scanned
 // (digit-major, tile-minor) offsets, the last one closing at n.
+template <class KeyT>
 __global__ void __launch_bounds__(kBlock)
-k_radix_scatter_lds(const uint64_t* __restrict__ keys, const int32_t* __restrict__ vals,
+k_radix_scatter_lds(const KeyT* __restrict__ keys, const int32_t* __restrict__ vals,
                     int64_t n, int shift, const uint32_t* __restrict__ offs, int64_t nb,
-                    uint64_t* __restrict__ okeys, int32_t* __restrict__ ovals) {
+                    KeyT* __restrict__ okeys, int32_t* __restrict__ ovals) {
   constexpr int DB = 8;
   constexpr int RB = 1 << DB;
   static_assert(RB == kBlock, "one digit per thread in the tile scan");
-  __shared__ uint64_t sk[kRadixTile];
+  __shared__ KeyT sk[kRadixTile];
   __shared__ int32_t sv[kRadixTile];
   __shared__ uint32_t lfirst[RB], lrun[RB], gbase[RB];
   __shared__ uint32_t wcnt[kBlock / 64][RB];
@@ -272,7 +273,7 @@ k_radix_scatter_lds(const uint64_t* __restrict__ keys, const int32_t* __restrict
   }
   // the tile's keys and values, all loads in flight at once (the rounds
   // below would otherwise wait for one load each)
-  uint64_t kk[kRadixItems];
+  KeyT kk[kRadixItems];
   int32_t vv[kRadixItems];
 #pragma unroll
   for (int k = 0; k < kRadixItems; ++k) {
@@ -286,7 +287,7 @@ k_radix_scatter_lds(const uint64_t* __restrict__ keys, const int32_t* __restrict
   for (int k = 0; k < kRadixItems; ++k) {
     const int64_t i = base + (int64_t)k * kBlock + t;
     const bool valid = i < n;
-    const uint64_t key = kk[k];
+    const KeyT key = kk[k];
     const int32_t val = vv[k];
     const uint32_t d = (uint32_t)(key >> shift) & (uint32_t)(RB - 1);
     uint64_t peers = __ballot(valid);
@@ -316,7 +317,7 @@ k_radix_scatter_lds(const uint64_t* __restrict__ keys, const int32_t* __restrict
   }
   const int64_t tn = n - base < (int64_t)kRadixTile ? n - base : (int64_t)kRadixTile;
   for (int j = t; j < (int)tn; j += kBlock) {
-    const uint64_t key = sk[j];
+    const KeyT key = sk[j];
     const uint32_t d = (uint32_t)(key >> shift) & (uint32_t)(RB - 1);
     const uint32_t pos = gbase[d] + ((uint32_t)j - lfirst[d]);
     okeys[pos] = key;
@@ -373,9 +374,9 @@ GeomDev to_dev(const GridGeom& gg) {
   return d;
 }
 
-template <int DIM>
+template <int DIM, class KeyT>
 __global__ void k_cell_keys(const double* __restrict__ X, int64_t N, GeomDev gd,
-                            uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+                            KeyT* __restrict__ keys, int32_t* __restrict__ vals) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * blockDim.x) {
     uint64_t key = 0;
@@ -389,7 +390,7 @@ __global__ void k_cell_keys(const double* __restrict__ X, int64_t N, GeomDev gd,
       for (int j = 0; j < DIM; ++j)
         key += (uint64_t)cell_coord(X[(int64_t)j * N + i], gd.lo[j], gd.inv_w) * gd.stride[j];
     }
-    keys[i] = key;
+    keys[i] = (KeyT)key;
     vals[i] = (int32_t)i;
   }
 }
@@ -465,9 +466,9 @@ __device__ inline uint32_t block_wave_prefix(uint32_t wcount, uint32_t* agg) {
 
 // WRITE = false: tile_words[tile] = the tile's cell starts; WRITE = true:
 // tile_words[tile] holds the starts of all earlier tiles.
-template <bool WRITE>
+template <bool WRITE, class KeyT>
 __global__ void __launch_bounds__(kBlock)
-k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int shift,
+k_cell_table(const KeyT* __restrict__ keys, int64_t N, int shift,
              uint32_t* __restrict__ cell_of, uint64_t* __restrict__ cell_key,
              uint32_t* __restrict__ cell_start, uint32_t* __restrict__ d_M,
              uint32_t* __restrict__ tile_words) {
@@ -479,9 +480,10 @@ k_cell_table(const uint64_t* __restrict__ keys, int64_t N, int shift,
 #pragma unroll
   for (int r = 0; r < kCtRounds; ++r) {
     const int64_t i = wbase + r * 64 + lane;
-    key[r] = i < N ? keys[i] >> shift : 0;
+    // widened before the shift (the shift may equal a 32-bit key's width)
+    key[r] = i < N ? (uint64_t)keys[i] >> shift : 0;
     const uint64_t up = __shfl_up(key[r], 1, 64);
-    const uint64_t prev = lane > 0 ? up : (i > 0 && i < N ? keys[i - 1] >> shift : 0);
+    const uint64_t prev = lane > 0 ? up : (i > 0 && i < N ? (uint64_t)keys[i - 1] >> shift : 0);
     m[r] = __ballot(i < N && (i == 0 || key[r] != prev));
     cnt += (uint32_t)__popcll(m[r]);
   }
@@ -1031,12 +1033,12 @@ __global__ void k_neighbor_ranges_z(const uint32_t* __restrict__ cell_start,
 }
 
 // First position in keys[0..N) whose key is >= k (N if none).
-__device__ inline int64_t lower_bound_u64(const uint64_t* __restrict__ keys, int64_t N,
-                                          uint64_t k) {
+template <class KeyT>
+__device__ inline int64_t lower_bound_key(const KeyT* __restrict__ keys, int64_t N, uint64_t k) {
   int64_t lo = 0, hi = N;
   while (lo < hi) {
     const int64_t mid = lo + ((hi - lo) >> 1);
-    if (keys[mid] < k)
+    if ((uint64_t)keys[mid] < k)
       lo = mid + 1;
     else
       hi = mid;
@@ -1050,8 +1052,8 @@ __device__ inline int64_t lower_bound_u64(const uint64_t* __restrict__ keys, int
 // keys as the run whose keys shifted right by zshift equal the cell's key
 // (two binary searches), in the format of k_neighbor_ranges_z; cell_of[q] =
 // i, and *d_M = the number of slots.  A group of S lanes per query.
-template <int DIM>
-__global__ void k_sparse_ranges_z(const uint64_t* __restrict__ keys, int64_t N,
+template <int DIM, class KeyT>
+__global__ void k_sparse_ranges_z(const KeyT* __restrict__ keys, int64_t N,
                                   const int32_t* __restrict__ active, int64_t n_active,
                                   const uint32_t* n_dev, int zshift, GeomDev gd,
                                   uint32_t* __restrict__ ranges, uint8_t* __restrict__ rslot,
@@ -1072,7 +1074,7 @@ __global__ void k_sparse_ranges_z(const uint64_t* __restrict__ keys, int64_t N,
   const int64_t i0 = sub < GPW ? ((int64_t)blockIdx.x * wpb + threadIdx.x / 64) * GPW + sub : na;
   for (int64_t i = i0; i < na; i += groups) {
     const int32_t q = active[i];
-    const uint64_t k0 = keys[q] >> zshift;
+    const uint64_t k0 = (uint64_t)keys[q] >> zshift;
     int64_t cc[DIM];
     zorder_coords<DIM>(k0, gd.zbits, cc);
     uint32_t count = 0, cand = 0;
@@ -1094,8 +1096,8 @@ __global__ void k_sparse_ranges_z(const uint64_t* __restrict__ keys, int64_t N,
         }
         if (inside) {
           const uint64_t nk = zorder_key<DIM>(nb, gd.zbits);
-          start = (uint32_t)lower_bound_u64(keys, N, nk << zshift);
-          end = (uint32_t)lower_bound_u64(keys, N, (nk + 1) << zshift);
+          start = (uint32_t)lower_bound_key(keys, N, nk << zshift);
+          end = (uint32_t)lower_bound_key(keys, N, (nk + 1) << zshift);
         }
       }
       const bool ne = end > start;
@@ -1323,10 +1325,12 @@ size_t radix_tmp_elems(int64_t n) {
   return (size_t)(((int64_t)1 << kMaxDigitBits) * nb);
 }
 
-bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
-                      int64_t n, int bits, uint32_t* tmp, uint32_t* state, int64_t state_elems,
-                      hipStream_t s) {
+template <class KeyT>
+static bool radix_sort_pairs_t(KeyT* keys, int32_t* vals, KeyT* keys2, int32_t* vals2,
+                               int64_t n, int bits, uint32_t* tmp, uint32_t* state,
+                               int64_t state_elems, hipStream_t s) {
   if (n <= 1 || bits <= 0) return false;
+  KNN_CHECK(bits <= (int)(8 * sizeof(KeyT)), KNN_EINTERNAL, "radix sort: more bits than the key");
   int64_t nb = ceil_div(n, kRadixTile);
   // 8-bit digits, scattered through LDS (coalesced digit runs); the direct
   // 11-bit scatter (one pass fewer, scattered stores) only for small sorts
@@ -1335,27 +1339,27 @@ bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* v
   const int passes = (bits + DB - 1) / DB;
   const int64_t cnt = ((int64_t)1 << DB) * nb;
   uint32_t* hist = tmp;
-  uint64_t* src_k = keys;
+  KeyT* src_k = keys;
   int32_t* src_v = vals;
-  uint64_t* dst_k = keys2;
+  KeyT* dst_k = keys2;
   int32_t* dst_v = vals2;
   for (int ps = 0; ps < passes; ++ps) {
     const int shift = DB * ps;
     if (DB == 11)
-      k_radix_hist<11><<<(unsigned)nb, kBlock, 0, s>>>(src_k, n, shift, hist, nb);
+      k_radix_hist<11, KeyT><<<(unsigned)nb, kBlock, 0, s>>>(src_k, n, shift, hist, nb);
     else
-      k_radix_hist<8><<<(unsigned)nb, kBlock, 0, s>>>(src_k, n, shift, hist, nb);
+      k_radix_hist<8, KeyT><<<(unsigned)nb, kBlock, 0, s>>>(src_k, n, shift, hist, nb);
     KNN_LAUNCHED();
     launch_exclusive_scan(hist, hist, cnt, nullptr, state, state_elems, s);
     if (lds)
-      k_radix_scatter_lds<<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb, dst_k,
-                                                          dst_v);
+      k_radix_scatter_lds<KeyT><<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb,
+                                                                dst_k, dst_v);
     else if (DB == 11)
-      k_radix_scatter<11><<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb,
-                                                          dst_k, dst_v);
+      k_radix_scatter<11, KeyT><<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb,
+                                                                dst_k, dst_v);
     else
-      k_radix_scatter<8><<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb,
-                                                         dst_k, dst_v);
+      k_radix_scatter<8, KeyT><<<(unsigned)nb, kBlock, 0, s>>>(src_k, src_v, n, shift, hist, nb,
+                                                               dst_k, dst_v);
     KNN_LAUNCHED();
     std::swap(src_k, dst_k);
     std::swap(src_v, dst_v);
@@ -1363,19 +1367,44 @@ bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* v
   return src_k != keys;
 }
 
-void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* keys,
-                      int32_t* vals, hipStream_t s) {
+bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
+                      int64_t n, int bits, uint32_t* tmp, uint32_t* state, int64_t state_elems,
+                      hipStream_t s) {
+  return radix_sort_pairs_t(keys, vals, keys2, vals2, n, bits, tmp, state, state_elems, s);
+}
+
+bool radix_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys2, int32_t* vals2,
+                      int64_t n, int bits, uint32_t* tmp, uint32_t* state, int64_t state_elems,
+                      hipStream_t s) {
+  return radix_sort_pairs_t(keys, vals, keys2, vals2, n, bits, tmp, state, state_elems, s);
+}
+
+template <class KeyT>
+static void launch_cell_keys_t(const double* X, int64_t N, const GridGeom& gg, KeyT* keys,
+                               int32_t* vals, hipStream_t s) {
+  KNN_CHECK(gg.key_bits <= (int)(8 * sizeof(KeyT)), KNN_EINTERNAL,
+            "cell keys: more bits than the key");
   GeomDev gd = to_dev(gg);
   int nb = grid_for(N);
   switch (gg.dims) {
-    case 2: k_cell_keys<2><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
-    case 3: k_cell_keys<3><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
-    case 4: k_cell_keys<4><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
-    case 5: k_cell_keys<5><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
-    case 6: k_cell_keys<6><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
+    case 2: k_cell_keys<2, KeyT><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
+    case 3: k_cell_keys<3, KeyT><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
+    case 4: k_cell_keys<4, KeyT><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
+    case 5: k_cell_keys<5, KeyT><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
+    case 6: k_cell_keys<6, KeyT><<<nb, kBlock, 0, s>>>(X, N, gd, keys, vals); break;
     default: throw Error(KNN_EINVAL, "dims out of range");
   }
   KNN_LAUNCHED();
+}
+
+void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* keys,
+                      int32_t* vals, hipStream_t s) {
+  launch_cell_keys_t(X, N, gg, keys, vals, s);
+}
+
+void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint32_t* keys,
+                      int32_t* vals, hipStream_t s) {
+  launch_cell_keys_t(X, N, gg, keys, vals, s);
 }
 
 void launch_cell_keys_points(const double* Xs, int64_t N, const GridGeom& gg, uint64_t* keys,
@@ -1400,10 +1429,10 @@ void launch_gather_prev(const double* Xs_prev, const int32_t* perm_prev, const i
   KNN_LAUNCHED();
 }
 
-void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags, uint32_t* cell_of,
-                      uint64_t* cell_key, uint32_t* cell_start, uint32_t* d_M, uint32_t* state,
-                      int64_t state_elems, hipStream_t s, int shift) {
-  (void)flags;
+template <class KeyT>
+static void build_cell_table_t(const KeyT* sorted_keys, int64_t N, uint32_t* cell_of,
+                               uint64_t* cell_key, uint32_t* cell_start, uint32_t* d_M,
+                               uint32_t* state, int64_t state_elems, hipStream_t s, int shift) {
   if (N <= 0) {
     launch_zero(d_M, sizeof(uint32_t), s);
     return;
@@ -1411,13 +1440,29 @@ void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags, u
   const int64_t nb = ceil_div(N, kCtTile);
   KNN_CHECK(shift >= 0 && shift < 64, KNN_EINTERNAL, "cell table: key shift out of range");
   uint32_t* tw = scan_tile_area(state, state_elems, nb + 2);
-  k_cell_table<false><<<(unsigned)nb, kBlock, 0, s>>>(sorted_keys, N, shift, cell_of, cell_key,
-                                                      cell_start, d_M, tw);
+  k_cell_table<false, KeyT><<<(unsigned)nb, kBlock, 0, s>>>(sorted_keys, N, shift, cell_of,
+                                                            cell_key, cell_start, d_M, tw);
   KNN_LAUNCHED();
   launch_exclusive_scan(tw, tw, nb, nullptr, state, state_elems, s);
-  k_cell_table<true><<<(unsigned)nb, kBlock, 0, s>>>(sorted_keys, N, shift, cell_of, cell_key,
-                                                     cell_start, d_M, tw);
+  k_cell_table<true, KeyT><<<(unsigned)nb, kBlock, 0, s>>>(sorted_keys, N, shift, cell_of,
+                                                           cell_key, cell_start, d_M, tw);
   KNN_LAUNCHED();
+}
+
+void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags, uint32_t* cell_of,
+                      uint64_t* cell_key, uint32_t* cell_start, uint32_t* d_M, uint32_t* state,
+                      int64_t state_elems, hipStream_t s, int shift) {
+  (void)flags;
+  build_cell_table_t(sorted_keys, N, cell_of, cell_key, cell_start, d_M, state, state_elems, s,
+                     shift);
+}
+
+void build_cell_table(const uint32_t* sorted_keys, int64_t N, uint32_t* flags, uint32_t* cell_of,
+                      uint64_t* cell_key, uint32_t* cell_start, uint32_t* d_M, uint32_t* state,
+                      int64_t state_elems, hipStream_t s, int shift) {
+  (void)flags;
+  build_cell_table_t(sorted_keys, N, cell_of, cell_key, cell_start, d_M, state, state_elems, s,
+                     shift);
 }
 
 void launch_pos_to_id(int32_t* list, int64_t n, const int32_t* perm, hipStream_t s) {
@@ -1457,11 +1502,12 @@ void launch_neighbor_ranges_z(const uint32_t* cell_start, const uint64_t* cell_k
   KNN_LAUNCHED();
 }
 
-void launch_sparse_ranges_z(const uint64_t* sorted_keys, int64_t N, const int32_t* active,
-                            int64_t n_active, const uint32_t* n_dev, const GridGeom& gg,
-                            uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
-                            uint32_t* cand_count, uint32_t* cell_of, uint32_t* d_M,
-                            hipStream_t s) {
+template <class KeyT>
+static void launch_sparse_ranges_z_t(const KeyT* sorted_keys, int64_t N, const int32_t* active,
+                                     int64_t n_active, const uint32_t* n_dev, const GridGeom& gg,
+                                     uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
+                                     uint32_t* cand_count, uint32_t* cell_of, uint32_t* d_M,
+                                     hipStream_t s) {
   KNN_CHECK(gg.zbits >= 0 && gg.dims <= kZMaxDims, KNN_EINTERNAL, "not a Z-order level");
   KNN_CHECK(gg.zshift >= 0 && gg.zshift + gg.dims * gg.zbits <= 62, KNN_EINTERNAL,
             "Z-order level: key bits out of range");
@@ -1473,12 +1519,30 @@ void launch_sparse_ranges_z(const uint64_t* sorted_keys, int64_t N, const int32_
   const int S = gg.dims == 2 ? 9 : gg.dims == 3 ? 27 : 64;
   const int nb = grid_for(ceil_div(n_active, 64 / S) * 64, 65536);
   switch (gg.dims) {
-    case 2: k_sparse_ranges_z<2><<<nb, kBlock, 0, s>>>(sorted_keys, N, active, n_active, n_dev, gg.zshift, gd, ranges, rslot, nrng, cand_count, cell_of, d_M); break;
-    case 3: k_sparse_ranges_z<3><<<nb, kBlock, 0, s>>>(sorted_keys, N, active, n_active, n_dev, gg.zshift, gd, ranges, rslot, nrng, cand_count, cell_of, d_M); break;
-    case 4: k_sparse_ranges_z<4><<<nb, kBlock, 0, s>>>(sorted_keys, N, active, n_active, n_dev, gg.zshift, gd, ranges, rslot, nrng, cand_count, cell_of, d_M); break;
+    case 2: k_sparse_ranges_z<2, KeyT><<<nb, kBlock, 0, s>>>(sorted_keys, N, active, n_active, n_dev, gg.zshift, gd, ranges, rslot, nrng, cand_count, cell_of, d_M); break;
+    case 3: k_sparse_ranges_z<3, KeyT><<<nb, kBlock, 0, s>>>(sorted_keys, N, active, n_active, n_dev, gg.zshift, gd, ranges, rslot, nrng, cand_count, cell_of, d_M); break;
+    case 4: k_sparse_ranges_z<4, KeyT><<<nb, kBlock, 0, s>>>(sorted_keys, N, active, n_active, n_dev, gg.zshift, gd, ranges, rslot, nrng, cand_count, cell_of, d_M); break;
     default: throw Error(KNN_EINVAL, "Z-order levels take 2-4 dimensions");
   }
   KNN_LAUNCHED();
+}
+
+void launch_sparse_ranges_z(const uint64_t* sorted_keys, int64_t N, const int32_t* active,
+                            int64_t n_active, const uint32_t* n_dev, const GridGeom& gg,
+                            uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
+                            uint32_t* cand_count, uint32_t* cell_of, uint32_t* d_M,
+                            hipStream_t s) {
+  launch_sparse_ranges_z_t(sorted_keys, N, active, n_active, n_dev, gg, ranges, rslot, nrng,
+                           cand_count, cell_of, d_M, s);
+}
+
+void launch_sparse_ranges_z(const uint32_t* sorted_keys, int64_t N, const int32_t* active,
+                            int64_t n_active, const uint32_t* n_dev, const GridGeom& gg,
+                            uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
+                            uint32_t* cand_count, uint32_t* cell_of, uint32_t* d_M,
+                            hipStream_t s) {
+  launch_sparse_ranges_z_t(sorted_keys, N, active, n_active, n_dev, gg, ranges, rslot, nrng,
+                           cand_count, cell_of, d_M, s);
 }
 
 void launch_active_list(const uint8_t* failed, uint8_t tag, const int32_t* perm, int64_t N,

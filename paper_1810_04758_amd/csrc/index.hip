@@ -374,9 +374,21 @@ void build_grid_z(const knn_index& idx, JoinContext& c, double w0, int level, hi
     c.tmp.reserve(radix_tmp_elems(N));
     if (c.scan_state.reserve(scan_state_elems(N)))
       launch_zero(c.scan_state.p, c.scan_state.bytes(), s);
-    launch_cell_keys(idx.X.p, N, c.gz0, c.keys.p, c.perm.p, s);
-    if (radix_sort_pairs(c.keys.p, c.perm.p, c.keys2.p, c.vals2.p, N, c.gz0.key_bits, c.tmp.p,
-                         c.scan_state.p, (int64_t)c.scan_state.n, s)) {
+    // keys of at most 32 bits are sorted as uint32 (in the same buffers)
+    c.zkeys32 = c.gz0.key_bits <= 32;
+    bool swapped;
+    if (c.zkeys32) {
+      uint32_t* k = reinterpret_cast<uint32_t*>(c.keys.p);
+      uint32_t* k2 = reinterpret_cast<uint32_t*>(c.keys2.p);
+      launch_cell_keys(idx.X.p, N, c.gz0, k, c.perm.p, s);
+      swapped = radix_sort_pairs(k, c.perm.p, k2, c.vals2.p, N, c.gz0.key_bits, c.tmp.p,
+                                 c.scan_state.p, (int64_t)c.scan_state.n, s);
+    } else {
+      launch_cell_keys(idx.X.p, N, c.gz0, c.keys.p, c.perm.p, s);
+      swapped = radix_sort_pairs(c.keys.p, c.perm.p, c.keys2.p, c.vals2.p, N, c.gz0.key_bits,
+                                 c.tmp.p, c.scan_state.p, (int64_t)c.scan_state.n, s);
+    }
+    if (swapped) {
       std::swap(c.keys, c.keys2);  // sorted output is in the scratch pair
       std::swap(c.perm, c.vals2);
     }
@@ -389,8 +401,13 @@ void build_grid_z(const knn_index& idx, JoinContext& c, double w0, int level, hi
   c.cand_count.reserve(N);
   c.flags.reserve(N);
   c.scal.reserve(4);
-  build_cell_table(c.keys.p, N, c.flags.p, c.cell_of.p, c.cell_key.p, c.cell_start.p, c.scal.p,
-                   c.scan_state.p, (int64_t)c.scan_state.n, s, c.gg.zshift);
+  if (c.zkeys32)
+    build_cell_table(reinterpret_cast<const uint32_t*>(c.keys.p), N, c.flags.p, c.cell_of.p,
+                     c.cell_key.p, c.cell_start.p, c.scal.p, c.scan_state.p,
+                     (int64_t)c.scan_state.n, s, c.gg.zshift);
+  else
+    build_cell_table(c.keys.p, N, c.flags.p, c.cell_of.p, c.cell_key.p, c.cell_start.p, c.scal.p,
+                     c.scan_state.p, (int64_t)c.scan_state.n, s, c.gg.zshift);
   c.M = -1;
   c.dense_used = nullptr;
   c.rowtab_used = nullptr;
@@ -952,8 +969,13 @@ void self_join(const knn_index& idx, JoinContext& c, int32_t K, int32_t* d_ids, 
       const int64_t R = pow3(idx.n);
       c.ranges.reserve((size_t)A * R * 4);
       c.rslot.reserve((size_t)A * R);
-      launch_sparse_ranges_z(c.keys.p, N, active, A, c.scal.p + 1, c.gg, c.ranges.p, c.rslot.p,
-                             c.nrng.p, c.cand_count.p, c.cell_of.p, c.scal.p, s);
+      if (c.zkeys32)
+        launch_sparse_ranges_z(reinterpret_cast<const uint32_t*>(c.keys.p), N, active, A,
+                               c.scal.p + 1, c.gg, c.ranges.p, c.rslot.p, c.nrng.p,
+                               c.cand_count.p, c.cell_of.p, c.scal.p, s);
+      else
+        launch_sparse_ranges_z(c.keys.p, N, active, A, c.scal.p + 1, c.gg, c.ranges.p, c.rslot.p,
+                               c.nrng.p, c.cand_count.p, c.cell_of.p, c.scal.p, s);
       lp.Mcap = A;
     } else {
       if (level > 0 || n_pre) {

@@ -73,6 +73,9 @@ struct JoinContext {
   double blo[KNN_MAX_DIMS] = {0};
   double bhi[KNN_MAX_DIMS] = {0};
   bool zmode = false;  // the current level is a Z-order level
+  // the Z-order levels' sorted keys are held as uint32 in keys / keys2
+  // (level-0 keys of at most 32 bits)
+  bool zkeys32 = false;
   int64_t M = 0;
   DevBuf<double> Xs, Xs2;      // sorted points (Xs2: the other of a level pair)
   DevBuf<int32_t> perm, perm2;  // sorted position -> id

@@ -78,18 +78,31 @@ size_t radix_tmp_elems(int64_t n);
 bool radix_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys2, int32_t* vals2,
                       int64_t n, int bits, uint32_t* tmp, uint32_t* state, int64_t state_elems,
                       hipStream_t s);
+// The same for keys of at most 32 bits held as uint32 (a third less traffic
+// per pass than 64-bit keys).
+bool radix_sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys2, int32_t* vals2,
+                      int64_t n, int bits, uint32_t* tmp, uint32_t* state, int64_t state_elems,
+                      hipStream_t s);
 
 // ---- grid level construction (grid.hip) ----
 // keys[i] = cell key of point i (original order, SoA X; row-major or Z-order
 // as gg says); vals[i] = i.
 void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint64_t* keys,
                       int32_t* vals, hipStream_t s);
-// From sorted keys, in one pass (cell starts counted, scanned by look-back):
-// the cell table.  cell_of (N), cell_key (N),
-// cell_start (N+1), d_M (device scalar) written.  state: scan state (flags unused).
-// shift: the cells are those of sorted_keys >> shift (a Z-order level above
-// the one the keys were sorted for); cell_key holds the shifted keys.
+// uint32 keys (gg.key_bits <= 32)
+void launch_cell_keys(const double* X, int64_t N, const GridGeom& gg, uint32_t* keys,
+                      int32_t* vals, hipStream_t s);
+// From sorted keys (cell starts counted per tile, the counts scanned, then
+// written): the cell table.  cell_of (N), cell_key (N),
+// cell_start (N+1), d_M (device scalar) written.  state: scan state and its
+// tile area (flags unused).  shift: the cells are those of sorted_keys >>
+// shift (a Z-order level above the one the keys were sorted for); cell_key
+// holds the shifted keys (64-bit whatever the width of sorted_keys).
 void build_cell_table(const uint64_t* sorted_keys, int64_t N, uint32_t* flags,
+                      uint32_t* cell_of, uint64_t* cell_key, uint32_t* cell_start,
+                      uint32_t* d_M, uint32_t* state, int64_t state_elems, hipStream_t s,
+                      int shift = 0);
+void build_cell_table(const uint32_t* sorted_keys, int64_t N, uint32_t* flags,
                       uint32_t* cell_of, uint64_t* cell_key, uint32_t* cell_start,
                       uint32_t* d_M, uint32_t* state, int64_t state_elems, hipStream_t s,
                       int shift = 0);
@@ -157,6 +170,11 @@ void launch_neighbor_ranges_z(const uint32_t* cell_start, const uint64_t* cell_k
 // keys (keys >> gg.zshift == the cell's key); cell_of[q] = i, nrng and
 // cand_count by slot, and *d_M = the number of slots.
 void launch_sparse_ranges_z(const uint64_t* sorted_keys, int64_t N, const int32_t* active,
+                            int64_t n_active, const uint32_t* n_dev, const GridGeom& gg,
+                            uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
+                            uint32_t* cand_count, uint32_t* cell_of, uint32_t* d_M,
+                            hipStream_t s);
+void launch_sparse_ranges_z(const uint32_t* sorted_keys, int64_t N, const int32_t* active,
                             int64_t n_active, const uint32_t* n_dev, const GridGeom& gg,
                             uint32_t* ranges, uint8_t* rslot, uint32_t* nrng,
                             uint32_t* cand_count, uint32_t* cell_of, uint32_t* d_M,
