@@ -159,4 +159,10 @@ def test_zorder_larger_sizes_sampled(knn, oracle_mod):
         ref_i, ref_d = oracle_mod.knn_kdtree(D, K)
         bad = np.nonzero((ids != ref_i).any(axis=1) | (dists != ref_d).any(axis=1))[0]
         assert bad.size == 0, f"{bad.size} rows differ, e.g. {bad[0]}"
-        _say(f"  levels={st['levels']} tail={st['tail_queries']}")
+        L = st["levels"]
+        att, cells = st["attempted"][:L], st["cells"][:L]
+        _say(f"  levels={L} tail={st['tail_queries']} attempted={att} cells={cells}")
+        if name == "clustered2d":
+            # a later level with few queries ran without a cell table (one
+            # ranges slot per query: as many "cells" as queries)
+            assert any(0 < att[l] <= 16384 and cells[l] == att[l] for l in range(1, L)), (att, cells)
