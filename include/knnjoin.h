@@ -248,9 +248,11 @@ int knn_join(knn_index* idx, const double* Q, int64_t n_queries, int32_t K, int3
  * process ends).  The call makes no hipMalloc, hipFree, hipHostMalloc or
  * other allocating call; the caller still provides d_ids / d_dists.
  *   Limit: the join's buffers, each at its largest size for (index, K,
- *   opts), must fit the area (roughly 230 + 17*3^(dims-1) bytes per point
- *   plus the brute-force tail's per-query state); larger joins return
- *   KNN_EINVAL, and knn_last_error() states the bytes needed.
+ *   opts), must fit the area (roughly 180-250 + 17*R bytes per point, R =
+ *   3^dims on Z-order levels and 3^(dims-1) on row-major ones, plus the
+ *   brute-force tail's per-query state: about 2e5 points in 2-D, 1.5e4 in
+ *   6-D); larger joins return KNN_EINVAL, and knn_last_error() states the
+ *   bytes needed.
  *   opts->stats must be NULL and opts->use_graph 0 (both would allocate):
  *   KNN_EINVAL otherwise.
  * The area is shared by every call on a device and keeps the last call's
